@@ -1,0 +1,482 @@
+"""Two-level nonlinear restricted additive Schwarz (RASPEN), FP64 oracle.
+
+Follows Section 2 of the paper:
+  * local corrections T_i(u) solving R_i F(u - P_i T_i(u)) = 0 (eq. 4) by an
+    inner Newton iteration on each overlapping subdomain;
+  * one-level residual F_1(u) = sum_i P~_i T_i(u) (eq. 5) with restricted
+    prolongations P~_i forming a partition of unity (eq. 8);
+  * coarse correction T_0(u) solving R_0 F(u - P_0 T_0(u)) = 0 (eq. 9) with
+    a GDSW coarse space (energy-minimising extension of interface indicator
+    functions) and R_0 = P_0^T;
+  * additive coupling F_a(u) = F_1(u) + P_0 T_0(u) (eq. 10);
+  * the exact tangents (eqs. 6, 7, 12) and the outer Newton iteration on the
+    tangent system (eq. 13), solved by restarted GMRES.
+
+Readings where the paper is silent (all are stated again where used):
+  * overlap: delta layers of elements added by node adjacency;
+  * V_i = nodes of the overlapping patch whose every element lies in the
+    patch; the other patch nodes (Gamma_i) carry the current global values;
+    Dirichlet nodes in V_i keep identity rows;
+  * P~_i: node g is owned by the largest subdomain id among its elements and
+    P~_i copies the owned entries only (a partition of unity, eq. 8);
+  * the coarse basis is extended with DF at the linearisation point u = 0;
+  * inner/coarse Newton start from T = 0 and stop when
+    ||r||_2 <= max(rtol * rho_0, eta * ||b||_inf * sqrt(n)) or the last step
+    was below 1e-14 of the iterate (rounding stagnation); at most 30 steps;
+  * the exact tangent uses DF at the converged local states;
+  * outer Newton: u <- u - du (eq. 13), full steps, stop when
+    ||F_x(u_k)|| <= rtol ||F_x(u_0)||; GMRES restarted every 50 iterations,
+    x_0 = 0, modified Gram-Schmidt, Givens rotations.
+
+Dense LU with partial pivoting (LAPACK getrf through SciPy) is the linear
+solver of every step; GDSW components are ordered by their smallest node
+index.  FP64 throughout.  Test infrastructure only.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from .p1 import P1Problem, p1_element
+
+
+class LocalFailure(RuntimeError):
+    """An inner (or coarse) Newton iteration did not meet its stopping rule."""
+
+
+def _stop_tol(rho0, b_inf, n, rtol, eta):
+    return max(rtol * rho0, eta * b_inf * np.sqrt(n))
+
+
+class Schwarz:
+    """RASPEN with optional GDSW coarse level for one P1Problem.
+
+    coupling: "one_level" (F_1, eq. 5) or "additive" (F_a, eq. 10).
+    """
+
+    def __init__(self, problem: P1Problem, coupling: str = "one_level",
+                 inner_rtol=1e-12, inner_eta=1e-10, inner_maxit=30,
+                 stagnation=1e-14):
+        if coupling not in ("one_level", "additive"):
+            raise ValueError(coupling)
+        self.P = problem
+        self.case = problem.case
+        self.coupling = coupling
+        self.inner_rtol = inner_rtol
+        self.inner_eta = inner_eta
+        self.inner_maxit = inner_maxit
+        self.stagnation = stagnation
+        self.b_inf = float(np.max(np.abs(problem.b))) if problem.N else 0.0
+        self._build_maps()
+        self.Phi = None
+        if coupling == "additive":
+            self._build_gdsw()
+        self.state = None
+
+    # ------------------------------------------------------------------ maps
+    def _build_maps(self):
+        """Overlapping subdomains and transfer operators (Section 2).
+
+        The paper builds an element-based overlap from the dual graph; here
+        the non-overlapping element set of each subdomain is grown by
+        `overlap` layers of elements sharing a node with the current set.
+        """
+        P = self.P
+        conn = P.conn
+        part = np.asarray(self.case["elem_part"], dtype=np.int64)
+        n_sub = int(self.case["n_sub"])
+        delta = int(self.case["overlap"])
+        N, E = P.N, P.E
+        self.part = part
+        self.n_sub = n_sub
+        inc = sp.csr_matrix((np.ones(3 * E), (conn.ravel(),
+                             np.repeat(np.arange(E), 3))), shape=(N, E))
+        self.inc = inc
+        deg = np.asarray(inc.sum(axis=1)).ravel()
+        owner = np.full(N, -1, dtype=np.int64)
+        np.maximum.at(owner, conn.ravel(), np.repeat(part, 3))
+        self.owner = owner
+        subs = []
+        for i in range(n_sub):
+            pe = (part == i).astype(np.float64)
+            if not pe.any():
+                raise ValueError(f"subdomain {i} is empty")
+            for _ in range(delta):
+                nodes = (inc @ pe) > 0
+                pe = ((inc.T @ nodes.astype(np.float64)) > 0).astype(np.float64)
+            cnt = inc @ pe
+            in_patch = cnt > 0
+            V = np.nonzero(in_patch & (cnt == deg))[0]
+            Gam = np.nonzero(in_patch & (cnt != deg))[0]
+            elems = np.nonzero(pe)[0]
+            loc = np.full(N, -1, dtype=np.int64)
+            loc[V] = np.arange(len(V))
+            loc[Gam] = len(V) + np.arange(len(Gam))
+            subs.append({"V": V, "Gam": Gam, "elems": elems,
+                         "lconn": loc[conn[elems]], "dirV": P.is_dir[V],
+                         "loc": loc})
+        self.subs = subs
+        # restricted prolongation P~_i: owned nodes and their positions in V_i
+        own_loc = np.empty(N, dtype=np.int64)
+        for i, s in enumerate(subs):
+            owned = np.nonzero(owner == i)[0]
+            li = s["loc"][owned]
+            if np.any(li < 0) or np.any(li >= len(s["V"])):
+                raise ValueError(f"subdomain {i}: owned nodes not in V_i "
+                                 "(overlap must be >= 1)")
+            own_loc[owned] = li
+            s["owned"] = owned
+            s["owned_loc"] = li
+        self.own_loc = own_loc
+
+    # ----------------------------------------------------------- local level
+    def local_residual(self, i, x, trace):
+        """r = R_i F(v) with v = u outside V_i and x on V_i (eq. 4).
+
+        Assembled from the patch elements only; exact because every element
+        touching a node of V_i lies in the patch.
+        """
+        s = self.subs[i]
+        P = self.P
+        v = np.concatenate([x, trace])
+        r_e, _ = p1_element(v[s["lconn"]], P.G[s["elems"]],
+                            P.kappa[s["elems"]], P.beta, P.load[s["elems"]])
+        R = np.zeros(len(v))
+        np.add.at(R, s["lconn"], r_e)
+        r = R[:len(x)]
+        d = s["dirV"]
+        r[d] = x[d] - P.dir_value[s["V"][d]]
+        return r
+
+    def local_jacobian(self, i, x, trace):
+        """J_ii = R_i DF(v) P_i and the coupling B_i = R_i DF(v) on Gamma_i."""
+        s = self.subs[i]
+        P = self.P
+        nV = len(x)
+        v = np.concatenate([x, trace])
+        _, K = p1_element(v[s["lconn"]], P.G[s["elems"]],
+                          P.kappa[s["elems"]], P.beta, P.load[s["elems"]])
+        lc = s["lconn"]
+        rows = np.broadcast_to(lc[:, :, None], K.shape).ravel()
+        cols = np.broadcast_to(lc[:, None, :], K.shape).ravel()
+        keep = rows < nV
+        Jf = np.zeros((nV, len(v)))
+        np.add.at(Jf, (rows[keep], cols[keep]), K.ravel()[keep])
+        d = np.nonzero(s["dirV"])[0]
+        Jf[d, :] = 0.0
+        Jf[d, d] = 1.0
+        return Jf[:, :nV].copy(), Jf[:, nV:].copy()
+
+    def local_solve(self, i, u, x0=None):
+        """T_i(u) by Newton's method on R_i F(u - P_i T_i(u)) = 0 (eq. 4).
+
+        Starts from x = R_i u (T_i = 0) unless x0 is given; the stopping rule
+        is measured against rho_plain = ||R_i F(u)||.  Returns the converged
+        local state, T_i(u) = R_i u - x*, and the LU of J_ii and B_i at x*
+        (the exact tangent, eq. 6, needs DF at u_i = u - P_i T_i(u)).
+        """
+        s = self.subs[i]
+        xu = u[s["V"]].copy()
+        tr = u[s["Gam"]].copy()
+        r = self.local_residual(i, xu, tr)
+        rho_plain = float(np.linalg.norm(r))
+        tol = _stop_tol(rho_plain, self.b_inf, len(xu), self.inner_rtol,
+                        self.inner_eta)
+        x = xu if x0 is None else np.array(x0, dtype=np.float64)
+        if x0 is not None:
+            r = self.local_residual(i, x, tr)
+        its = 0
+        dprev = None
+        hist = [float(np.linalg.norm(r))]
+        while True:
+            rn = float(np.linalg.norm(r))
+            if not np.isfinite(rn):
+                raise LocalFailure(f"subdomain {i}: non-finite residual")
+            if rn <= tol:
+                break
+            if dprev is not None and dprev <= self.stagnation * np.max(np.abs(x)):
+                break
+            if its == self.inner_maxit:
+                raise LocalFailure(f"subdomain {i}: no convergence in "
+                                   f"{its} Newton steps")
+            J, _ = self.local_jacobian(i, x, tr)
+            d = sla.lu_solve(sla.lu_factor(J, check_finite=False), r)
+            x = x - d
+            its += 1
+            dprev = float(np.max(np.abs(d)))
+            r = self.local_residual(i, x, tr)
+            hist.append(float(np.linalg.norm(r)))
+        J, B = self.local_jacobian(i, x, tr)
+        return {"x": x, "T": xu - x, "lu": sla.lu_factor(J, check_finite=False),
+                "B": B, "its": its, "rho_plain": rho_plain, "hist": hist}
+
+    def F1(self, u, sols=None):
+        """One-level RASPEN residual F_1(u)[g] = T_{o(g)}(u)[l(g)] (eqs. 5, 8)."""
+        if sols is None:
+            sols = [self.local_solve(i, u) for i in range(self.n_sub)]
+        Fx = np.empty(self.P.N)
+        for s, sol in zip(self.subs, sols):
+            Fx[s["owned"]] = sol["T"][s["owned_loc"]]
+        return Fx, sols
+
+    # ---------------------------------------------------------- coarse level
+    def _build_gdsw(self, u_lin=None):
+        """GDSW coarse basis Phi (N x n0) (Section 1 and 2).
+
+        Interface nodes (not Dirichlet, adjacent to elements of >= 2
+        subdomains) are grouped by the set of subdomains they touch and each
+        group is split into connected components (vertices: >= 3 subdomains,
+        edges: 2).  A scalar problem has one basis function per component,
+        equal to 1 on it and 0 on the rest of the interface; it is extended
+        into each subdomain interior by the discrete harmonic extension
+        Phi_I = -A_II^{-1} A_IG Phi_G with A = DF(u_lin), u_lin = 0.
+        """
+        P = self.P
+        N = P.N
+        conn = P.conn
+        part = self.part
+        NS = sp.csr_matrix((np.ones(3 * P.E), (conn.ravel(), np.repeat(part, 3))),
+                           shape=(N, self.n_sub))
+        NS.sort_indices()
+        nsub = np.diff(NS.indptr)
+        iface = (nsub >= 2) & ~P.is_dir
+        keys = {}
+        for g in np.nonzero(iface)[0]:
+            k = tuple(NS.indices[NS.indptr[g]:NS.indptr[g + 1]].tolist())
+            keys.setdefault(k, []).append(g)
+        # mesh edges for connectivity of a class
+        e = np.concatenate([conn[:, [0, 1]], conn[:, [1, 2]], conn[:, [2, 0]]])
+        adj = sp.csr_matrix((np.ones(len(e)), (e[:, 0], e[:, 1])), shape=(N, N))
+        adj = ((adj + adj.T) > 0).tocsr()
+        comps = []
+        for k, nodes in keys.items():
+            nodes = np.array(sorted(nodes))
+            sub = adj[nodes][:, nodes]
+            nc, lab = sp.csgraph.connected_components(sub, directed=False)
+            for c in range(nc):
+                comps.append((nodes[lab == c], len(k)))
+        comps.sort(key=lambda t: int(t[0].min()))
+        n0 = len(comps)
+        rows = np.concatenate([c[0] for c in comps]) if n0 else np.zeros(0, int)
+        cols = np.concatenate([np.full(len(c[0]), k) for k, c in enumerate(comps)]) \
+            if n0 else np.zeros(0, int)
+        PhiG = sp.csr_matrix((np.ones(len(rows)), (rows, cols)), shape=(N, n0))
+        self.components = comps
+        u0 = np.zeros(N) if u_lin is None else u_lin
+        A = P.jacobian(u0)
+        prow, pcol, pval = [rows], [cols], [np.ones(len(rows))]
+        interior = (nsub == 1) & ~P.is_dir
+        self.interior_blocks = []
+        for i in range(self.n_sub):
+            el = np.nonzero(part == i)[0]
+            clos = np.zeros(N, dtype=bool)
+            clos[conn[el].ravel()] = True
+            I = np.nonzero(clos & interior)[0]
+            bnd = np.nonzero(clos & ~(clos & interior))[0]
+            if len(I) == 0:
+                continue
+            AII = A[I][:, I].toarray()
+            rhs = -(A[I][:, bnd] @ PhiG[bnd]).toarray()
+            PhiI = sla.lu_solve(sla.lu_factor(AII, check_finite=False), rhs)
+            nzc = np.nonzero(np.any(PhiI != 0.0, axis=0))[0]
+            prow.append(np.repeat(I, len(nzc)))
+            pcol.append(np.tile(nzc, len(I)))
+            pval.append(PhiI[:, nzc].ravel())
+            self.interior_blocks.append((i, I, bnd))
+        self.Phi = sp.csr_matrix((np.concatenate(pval), (np.concatenate(prow),
+                                  np.concatenate(pcol))), shape=(N, n0))
+        self.Phi.eliminate_zeros()
+        self.PhiT = self.Phi.T.tocsr()
+        self.n0 = n0
+        self.phib_inf = float(np.max(np.abs(self.PhiT @ P.b))) if n0 else 0.0
+
+    def coarse_solve(self, u):
+        """T_0(u) by Newton on G(c) = Phi^T F(u - Phi c) = 0 (eq. 9, R_0 =
+        P_0^T = Phi^T), from c = 0:  c <- c + A0^{-1} G(c) with the Galerkin
+        matrix A0 = Phi^T DF(u - Phi c) Phi.  Keeps LU(A0) and DF at the
+        converged point u_0 = u - Phi c* for the tangent (eq. 12)."""
+        P = self.P
+        Phi, PhiT = self.Phi, self.PhiT
+        c = np.zeros(self.n0)
+        w = u.copy()
+        G = PhiT @ P.residual(w)
+        rho = float(np.linalg.norm(G))
+        tol = _stop_tol(rho, self.phib_inf, self.n0, self.inner_rtol,
+                        self.inner_eta)
+        its = 0
+        dprev = None
+        while True:
+            gn = float(np.linalg.norm(G))
+            if not np.isfinite(gn):
+                raise LocalFailure("coarse: non-finite residual")
+            if gn <= tol:
+                break
+            if dprev is not None and dprev <= self.stagnation * np.max(np.abs(c)):
+                break
+            if its == self.inner_maxit:
+                raise LocalFailure("coarse: no convergence")
+            A0 = (PhiT @ (P.jacobian(w) @ Phi)).toarray()
+            d = sla.lu_solve(sla.lu_factor(A0, check_finite=False), G)
+            c = c + d
+            its += 1
+            dprev = float(np.max(np.abs(d)))
+            w = u - Phi @ c
+            G = PhiT @ P.residual(w)
+        DF0 = P.jacobian(w)
+        A0 = (PhiT @ (DF0 @ Phi)).toarray()
+        return {"c": c, "lu": sla.lu_factor(A0, check_finite=False),
+                "DF0": DF0, "its": its, "A0": A0}
+
+    # --------------------------------------------------------- combinations
+    def evaluate(self, u):
+        """F_x(u) for the configured coupling; keeps the state for the tangent."""
+        Fx, sols = self.F1(u)
+        co = None
+        if self.coupling == "additive":
+            co = self.coarse_solve(u)
+            Fx = Fx + self.Phi @ co["c"]
+        self.state = {"u": u.copy(), "sols": sols, "coarse": co}
+        return Fx
+
+    def tangent(self, v):
+        """D F_x(u) v at the last evaluated u, using R_i DF(u_i) v =
+        J_ii R_i v + B_i v_Gamma and the partition of unity (eq. 8):
+        D F_a v = v + sum_i P~_i J_ii^{-1} B_i v_Gamma_i
+                    + Phi A0^{-1} Phi^T DF(u_0) v      (eqs. 6, 7, 12)."""
+        st = self.state
+        y = v.copy()
+        for s, sol in zip(self.subs, st["sols"]):
+            z = sla.lu_solve(sol["lu"], sol["B"] @ v[s["Gam"]])
+            y[s["owned"]] += z[s["owned_loc"]]
+        co = st["coarse"]
+        if co is not None:
+            y += self.Phi @ sla.lu_solve(co["lu"], self.PhiT @ (co["DF0"] @ v))
+        return y
+
+    def tangent_literal(self, v):
+        """The same tangent from its definition, sum_i P~_i (R_i DF(u_i) P_i)^-1
+        R_i DF(u_i) v + P_0 DT_0 v, with DF(u_i) assembled globally at
+        u_i = u - P_i T_i(u) (eqs. 6, 7)."""
+        st = self.state
+        P = self.P
+        y = np.zeros_like(v)
+        for s, sol in zip(self.subs, st["sols"]):
+            ui = st["u"].copy()
+            ui[s["V"]] = sol["x"]
+            w = (P.jacobian(ui) @ v)[s["V"]]
+            z = sla.lu_solve(sol["lu"], w)
+            y[s["owned"]] += z[s["owned_loc"]]
+        co = st["coarse"]
+        if co is not None:
+            y += self.Phi @ sla.lu_solve(co["lu"], self.PhiT @ (co["DF0"] @ v))
+        return y
+
+    def solve(self, u0=None, rtol=1e-8, maxit=50, gmres_rtol=1e-6,
+              gmres_restart=50, gmres_maxit=1000):
+        """Outer Newton on F_x(u) = 0: solve D F_x(u_k) du = F_x(u_k) (eq. 13)
+        by GMRES and set u_{k+1} = u_k - du."""
+        u = np.zeros(self.P.N) if u0 is None else np.array(u0, dtype=np.float64)
+        Fx = self.evaluate(u)
+        r0 = float(np.linalg.norm(Fx))
+        stats = {"outer": 0, "gmres": [], "inner": [], "coarse": [],
+                 "res": [r0], "converged": False}
+        stats["inner"].append(sum(s["its"] for s in self.state["sols"]))
+        if self.state["coarse"] is not None:
+            stats["coarse"].append(self.state["coarse"]["its"])
+        for _ in range(maxit):
+            if float(np.linalg.norm(Fx)) <= rtol * r0:
+                stats["converged"] = True
+                break
+            du, its = gmres_mgs(self.tangent, Fx, rtol=gmres_rtol,
+                                restart=gmres_restart, maxit=gmres_maxit)
+            stats["gmres"].append(its)
+            u = u - du
+            Fx = self.evaluate(u)
+            stats["outer"] += 1
+            stats["res"].append(float(np.linalg.norm(Fx)))
+            stats["inner"].append(sum(s["its"] for s in self.state["sols"]))
+            if self.state["coarse"] is not None:
+                stats["coarse"].append(self.state["coarse"]["its"])
+        else:
+            stats["converged"] = float(np.linalg.norm(Fx)) <= rtol * r0
+        return u, stats
+
+
+def gmres_mgs(apply, b, rtol=1e-6, restart=50, maxit=1000):
+    """Restarted GMRES(m) for apply(x) = b from x_0 = 0 (Saad-Schultz):
+    Arnoldi with modified Gram-Schmidt, Givens rotations, stop when the
+    residual estimate |g_{j+1}| <= rtol ||b||.  Returns (x, iterations)."""
+    n = len(b)
+    x = np.zeros(n)
+    bn = float(np.linalg.norm(b))
+    if bn == 0.0:
+        return x, 0
+    its = 0
+    r = b.copy()
+    while its < maxit:
+        beta = float(np.linalg.norm(r))
+        if beta <= rtol * bn:
+            break
+        m = restart
+        V = np.zeros((m + 1, n))
+        H = np.zeros((m + 1, m))
+        cs = np.zeros(m)
+        sn = np.zeros(m)
+        g = np.zeros(m + 1)
+        g[0] = beta
+        V[0] = r / beta
+        j = 0
+        done = False
+        while j < m and its < maxit:
+            w = apply(V[j])
+            its += 1
+            for i in range(j + 1):
+                H[i, j] = V[i] @ w
+                w = w - H[i, j] * V[i]
+            H[j + 1, j] = float(np.linalg.norm(w))
+            if H[j + 1, j] != 0.0:
+                V[j + 1] = w / H[j + 1, j]
+            for i in range(j):
+                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+                H[i + 1, j] = -sn[i] * H[i, j] + cs[i] * H[i + 1, j]
+                H[i, j] = t
+            den = np.hypot(H[j, j], H[j + 1, j])
+            cs[j] = H[j, j] / den
+            sn[j] = H[j + 1, j] / den
+            H[j, j] = den
+            H[j + 1, j] = 0.0
+            g[j + 1] = -sn[j] * g[j]
+            g[j] = cs[j] * g[j]
+            j += 1
+            if abs(g[j]) <= rtol * bn:
+                done = True
+                break
+        y = sla.solve_triangular(H[:j, :j], g[:j])
+        x = x + V[:j].T @ y
+        if done:
+            break
+        r = b - apply(x)
+    return x, its
+
+
+def global_newton(problem: P1Problem, u0=None, maxit=50, dense=False):
+    """Plain definition of the discrete solution u*: Newton's method on
+    F(u) = 0 (eq. 3) with a direct solve of DF(u) du = F(u), run until the
+    step is at the rounding level (|du|_inf <= 1e-13 |u|_inf) or F = 0."""
+    u = np.zeros(problem.N) if u0 is None else np.array(u0, dtype=np.float64)
+    its = 0
+    for its in range(1, maxit + 1):
+        F = problem.residual(u)
+        if not np.any(F):
+            break
+        A = problem.jacobian(u)
+        if dense:
+            d = sla.lu_solve(sla.lu_factor(A.toarray()), F)
+        else:
+            d = spla.spsolve(A.tocsc(), F)
+        u = u - d
+        if np.max(np.abs(d)) <= 1e-13 * max(np.max(np.abs(u)), 1e-300):
+            break
+    return u, its

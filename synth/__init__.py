@@ -1,0 +1,231 @@
+"""Seeded synthetic inputs for the two-level nonlinear Schwarz solver.
+
+This module produces *inputs only*: meshes, element partitions, boundary node
+lists, coefficient fields and load samples.  It holds none of the solver's
+arithmetic (no element integrals, no overlap construction, no Schwarz step),
+so that the FP64 CPU oracle and the HIP path can both consume it without
+sharing any of the method.
+
+Problem statements (the paper, Section 1):
+  * nonlinear diffusion  -div((u^2+1) grad u) = f on a rectangle, u = 0 on the
+    boundary (eq. 1; the paper takes f = 1 on the unit square);
+  * the mesh is a regular grid of squares, each split into two triangles
+    along the (i,j)-(i+1,j+1) diagonal, counter-clockwise vertex order;
+  * subdomains are boxes of whole grid cells (the paper partitions the dual
+    graph of the mesh, i.e. by elements; Section 2, last paragraph).
+
+Load data enter as samples of f at the three edge midpoints of every
+element, ordered (v0,v1), (v1,v2), (v2,v0); each consumer integrates them.
+The coefficient field enters as one value per element.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = [
+    "p1_grid", "even_cuts", "box_partition", "boundary_nodes",
+    "edge_midpoints", "fourier_modes", "fourier_eval", "rff_field",
+    "rff_eval", "diffusion_case", "config1", "config2", "config4_instance",
+    "small_case",
+]
+
+
+def p1_grid(nx: int, ny: int, lx: float = 1.0, ly: float = 1.0):
+    """Structured P1 triangulation of [0,lx]x[0,ly] with nx*ny cells.
+
+    Node (i,j) has index g = j*(nx+1) + i and coordinates (i*lx/nx, j*ly/ny).
+    Cell (i,j) yields two triangles, element 2*(j*nx+i) = [(i,j),(i+1,j),
+    (i+1,j+1)] and element 2*(j*nx+i)+1 = [(i,j),(i+1,j+1),(i,j+1)].
+    """
+    i = np.arange(nx + 1, dtype=np.float64)
+    j = np.arange(ny + 1, dtype=np.float64)
+    X, Y = np.meshgrid(i * (lx / nx), j * (ly / ny))
+    xy = np.stack([X.ravel(), Y.ravel()], axis=1)
+    ci, cj = np.meshgrid(np.arange(nx), np.arange(ny))
+    ci = ci.ravel()
+    cj = cj.ravel()
+    n00 = cj * (nx + 1) + ci
+    n10 = n00 + 1
+    n11 = n00 + (nx + 1) + 1
+    n01 = n00 + (nx + 1)
+    conn = np.empty((2 * nx * ny, 3), dtype=np.int32)
+    conn[0::2] = np.stack([n00, n10, n11], axis=1)
+    conn[1::2] = np.stack([n00, n11, n01], axis=1)
+    return xy, conn
+
+
+def even_cuts(n_cells: int, n_boxes: int) -> np.ndarray:
+    """Cut positions 0 = c_0 < ... < c_n = n_cells splitting cells evenly."""
+    return np.array([(k * n_cells) // n_boxes for k in range(n_boxes + 1)],
+                    dtype=np.int64)
+
+
+def box_partition(nx: int, ny: int, cuts_x, cuts_y) -> np.ndarray:
+    """Element -> subdomain map for box partitions of a p1_grid mesh.
+
+    Box (bx,by) covers cells cuts_x[bx] <= i < cuts_x[bx+1],
+    cuts_y[by] <= j < cuts_y[by+1] and has id bx + (len(cuts_x)-1)*by.
+    Both triangles of a cell belong to the cell's box.
+    """
+    cuts_x = np.asarray(cuts_x)
+    cuts_y = np.asarray(cuts_y)
+    bx_of_i = np.searchsorted(cuts_x, np.arange(nx), side="right") - 1
+    by_of_j = np.searchsorted(cuts_y, np.arange(ny), side="right") - 1
+    nbx = len(cuts_x) - 1
+    cell_box = (by_of_j[:, None] * nbx + bx_of_i[None, :]).ravel()
+    return np.repeat(cell_box, 2).astype(np.int32)
+
+
+def boundary_nodes(nx: int, ny: int, sides=("left", "right", "bottom", "top")):
+    """Indices of p1_grid nodes lying on the chosen sides of the rectangle."""
+    i, j = np.meshgrid(np.arange(nx + 1), np.arange(ny + 1))
+    i = i.ravel()
+    j = j.ravel()
+    mask = np.zeros(i.shape, dtype=bool)
+    if "left" in sides:
+        mask |= i == 0
+    if "right" in sides:
+        mask |= i == nx
+    if "bottom" in sides:
+        mask |= j == 0
+    if "top" in sides:
+        mask |= j == ny
+    return np.nonzero(mask)[0].astype(np.int64)
+
+
+def edge_midpoints(xy: np.ndarray, conn: np.ndarray) -> np.ndarray:
+    """(E,3,2) midpoints of the element edges (v0,v1), (v1,v2), (v2,v0)."""
+    p = xy[conn]
+    return 0.5 * np.stack([p[:, 0] + p[:, 1], p[:, 1] + p[:, 2],
+                           p[:, 2] + p[:, 0]], axis=1)
+
+
+def fourier_modes(seed: int, n_modes: int = 8, amp: float = 10.0,
+                  kmax: int = 8):
+    """Amplitudes a ~ U(0,amp) and integer wave numbers k, l ~ U{1..kmax}.
+
+    Drawn with NumPy's PCG64 in the order a, k, l.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    a = rng.uniform(0.0, amp, size=n_modes)
+    k = rng.integers(1, kmax + 1, size=n_modes)
+    l = rng.integers(1, kmax + 1, size=n_modes)
+    return a, k, l
+
+
+def fourier_eval(pts: np.ndarray, modes) -> np.ndarray:
+    """f(x,y) = sum_m a_m sin(pi k_m x) sin(pi l_m y) at points (...,2)."""
+    a, k, l = modes
+    x = pts[..., 0][..., None]
+    y = pts[..., 1][..., None]
+    return np.sum(a * np.sin(np.pi * k * x) * np.sin(np.pi * l * y), axis=-1)
+
+
+def rff_field(seed: int, n_features: int = 512, corr_len: float = 0.1):
+    """Random Fourier features of a unit-variance squared-exponential field.
+
+    Frequencies omega ~ N(0, corr_len^-2 I), phases ~ U(0, 2 pi).
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    omega = rng.normal(0.0, 1.0 / corr_len, size=(n_features, 2))
+    phase = rng.uniform(0.0, 2.0 * np.pi, size=n_features)
+    return omega, phase
+
+
+def rff_eval(pts: np.ndarray, field) -> np.ndarray:
+    """g(x) = sqrt(2/M) sum_m cos(omega_m . x + phase_m) at points (...,2)."""
+    omega, phase = field
+    arg = pts @ omega.T + phase
+    return np.sqrt(2.0 / len(phase)) * np.cos(arg).sum(axis=-1)
+
+
+def diffusion_case(nx, ny, cuts_x, cuts_y, overlap, *, two_level=False,
+                   forcing=None, coef_field=None, beta=1.0, name="diffusion"):
+    """Assemble the input dictionary of one diffusion problem.
+
+    forcing:    None (f = 1) or a callable f(points) -> values.
+    coef_field: None (kappa = 1) or a callable g(points); kappa_e = exp(g) at
+                the element centroid.
+    beta:       nonlinearity scale, coefficient (1 + beta u^2); beta = 0 gives
+                the linear problem used by the reduction tests.
+    """
+    xy, conn = p1_grid(nx, ny)
+    part = box_partition(nx, ny, cuts_x, cuts_y)
+    bnd = boundary_nodes(nx, ny)
+    elem_load = None
+    if forcing is not None:
+        elem_load = np.ascontiguousarray(forcing(edge_midpoints(xy, conn)))
+    elem_coef = None
+    if coef_field is not None:
+        cen = xy[conn].mean(axis=1)
+        elem_coef = np.exp(coef_field(cen))
+    return {
+        "name": name,
+        "kind": "diffusion",
+        "nx": nx, "ny": ny,
+        "xy": xy, "conn": conn,
+        "elem_part": part,
+        "n_sub": (len(cuts_x) - 1) * (len(cuts_y) - 1),
+        "overlap": int(overlap),
+        "dirichlet": bnd,
+        "dirichlet_vals": np.zeros(len(bnd)),
+        "elem_load": elem_load,
+        "elem_coef": elem_coef,
+        "beta": float(beta),
+        "two_level": bool(two_level),
+    }
+
+
+def config1():
+    """64x64 P1 grid on the unit square, 4x4 boxes, overlap 1, f = 1,
+    one-level (the paper's diffusion problem at small scale)."""
+    return diffusion_case(64, 64, even_cuts(64, 4), even_cuts(64, 4), 1,
+                          two_level=False, name="diffusion_64x64_4x4_ov1")
+
+
+def config2(seed: int = 2):
+    """512x512 P1 grid, 16x16 boxes, overlap 2, two-level, f a seeded sum
+    of 8 Fourier modes with amplitudes U(0,10)."""
+    modes = fourier_modes(seed)
+    return diffusion_case(512, 512, even_cuts(512, 16), even_cuts(512, 16), 2,
+                          two_level=True,
+                          forcing=lambda p: fourier_eval(p, modes),
+                          name="diffusion_512x512_16x16_ov2_gdsw")
+
+
+def config4_instance(b: int):
+    """One instance of the batched diffusion workload: grid n x n with
+    n ~ U{128..384}, k x k boxes with k ~ U{8..16}, overlap 2, two-level,
+    coefficient exp(g) with g a unit-variance random field (length 0.1)."""
+    rng = np.random.Generator(np.random.PCG64(4000 + b))
+    n = int(rng.integers(128, 385))
+    k = int(rng.integers(8, 17))
+    field = rff_field(4000 + b)
+    return diffusion_case(n, n, even_cuts(n, k), even_cuts(n, k), 2,
+                          two_level=True,
+                          coef_field=lambda p: rff_eval(p, field),
+                          name=f"diffusion_batch_{b}_{n}x{n}_{k}x{k}")
+
+
+def small_case(n=12, boxes=3, overlap=1, two_level=False, beta=1.0,
+               forcing_seed=None, coef_seed=None, uneven=False):
+    """Small diffusion problems for oracle pins and parity tests."""
+    cx = even_cuts(n, boxes)
+    cy = even_cuts(n, boxes)
+    if uneven:
+        # shift interior cuts to make the boxes unequal and the tail ragged
+        cx = cx.copy()
+        cy = cy.copy()
+        cx[1:-1] = np.maximum(cx[1:-1] - 1, np.arange(1, boxes))
+        cy[1:-1] = np.minimum(cy[1:-1] + 1, n - np.arange(boxes - 1, 0, -1))
+    forcing = None
+    if forcing_seed is not None:
+        modes = fourier_modes(forcing_seed)
+        forcing = lambda p: fourier_eval(p, modes)  # noqa: E731
+    coef = None
+    if coef_seed is not None:
+        field = rff_field(coef_seed)
+        coef = lambda p: rff_eval(p, field)  # noqa: E731
+    return diffusion_case(n, n, cx, cy, overlap, two_level=two_level,
+                          forcing=forcing, coef_field=coef, beta=beta,
+                          name=f"small_{n}_{boxes}_{overlap}")

@@ -1,0 +1,194 @@
+"""Pins of the oracle's nonlinear Schwarz method against mathematics.
+
+  * partition of unity and owned-in-V_i invariants (eq. 8);
+  * reduction to linear restricted additive Schwarz for beta = 0, checked
+    against explicit matrices cut from the globally assembled operator;
+  * the fixed point of the preconditioned system equals the brute-force
+    global Newton solution (one-level and additive);
+  * GDSW: reproduction of constants on floating subdomains, discrete
+    harmonicity of the interior extension, number of coarse functions;
+  * coarse correction of a linear problem in one Newton step;
+  * exact tangent against its literal definition and central differences;
+  * GMRES against a dense solve of the assembled tangent;
+  * quadratic convergence of the local Newton iteration.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import synth
+from oracle.p1 import P1Problem
+from oracle.schwarz import Schwarz, global_newton, gmres_mgs
+
+
+def _schwarz(coupling="one_level", inner_eta=1e-10, **kw):
+    case = synth.small_case(**kw)
+    P = P1Problem(case)
+    return P, Schwarz(P, coupling, inner_eta=inner_eta)
+
+
+@pytest.mark.parametrize("overlap", [1, 2])
+@pytest.mark.parametrize("uneven", [False, True])
+def test_partition_of_unity(overlap, uneven):
+    P, S = _schwarz(n=13, boxes=3, overlap=overlap, uneven=uneven)
+    counts = np.zeros(P.N, dtype=int)
+    for s in S.subs:
+        counts[s["owned"]] += 1
+        # owned(i) subset of V_i
+        assert np.all(np.isin(s["owned"], s["V"]))
+        # V_i and Gamma_i are disjoint and every element touching V_i is in the patch
+        assert not np.intersect1d(s["V"], s["Gam"]).size
+        touching = np.nonzero(np.isin(P.conn, s["V"]).any(axis=1))[0]
+        assert np.all(np.isin(touching, s["elems"]))
+    assert np.all(counts == 1)
+    # sum_i P~_i R_i v = v
+    v = np.random.default_rng(1).normal(size=P.N)
+    acc = np.zeros(P.N)
+    for s in S.subs:
+        x = v[s["V"]]
+        acc[s["owned"]] += x[s["owned_loc"]]
+    np.testing.assert_array_equal(acc, v)
+
+
+def _ras_matrix(A, S, with_coarse):
+    """M^-1 = sum_i P~_i (R_i A R_i^T)^-1 R_i (+ Phi (Phi^T A Phi)^-1 Phi^T),
+    from the globally assembled A (independent of the local assembly)."""
+    N = A.shape[0]
+    Ad = A.toarray()
+    M = np.zeros((N, N))
+    for s in S.subs:
+        V = s["V"]
+        Ainv = np.linalg.inv(Ad[np.ix_(V, V)])
+        Pt = np.zeros((N, len(V)))
+        Pt[s["owned"], s["owned_loc"]] = 1.0
+        Rm = np.zeros((len(V), N))
+        Rm[np.arange(len(V)), V] = 1.0
+        M += Pt @ Ainv @ Rm
+    if with_coarse:
+        Phi = S.Phi.toarray()
+        M += Phi @ np.linalg.inv(Phi.T @ Ad @ Phi) @ Phi.T
+    return M
+
+
+@pytest.mark.parametrize("coupling", ["one_level", "additive"])
+def test_linear_reduction_to_ras(coupling):
+    """beta = 0: T_i(u) = J_ii^-1 R_i (A u - b) and F_x(u) = M^-1 (A u - b)
+    with M^-1 the (two-level additive) RAS preconditioner; the outer Newton
+    iteration converges in one step."""
+    P, S = _schwarz(coupling, n=12, boxes=3, overlap=1, beta=0.0,
+                    forcing_seed=4, coef_seed=9)
+    rng = np.random.default_rng(5)
+    u = rng.normal(size=P.N)
+    u[P.is_dir] = 0.0
+    A = P.jacobian(np.zeros(P.N))
+    res = A @ u - P.b
+    Fx = S.evaluate(u)
+    M = _ras_matrix(A, S, coupling == "additive")
+    np.testing.assert_allclose(Fx, M @ res, rtol=0, atol=1e-13 * np.abs(M @ res).max())
+    for sol in S.state["sols"]:
+        assert sol["its"] <= 2
+    # tangent is M^-1 A
+    v = rng.normal(size=P.N)
+    np.testing.assert_allclose(S.tangent(v), M @ (A @ v), rtol=0,
+                               atol=1e-12 * np.abs(M @ (A @ v)).max())
+    usol, st = S.solve(rtol=1e-10, gmres_rtol=1e-13)
+    assert st["outer"] == 1
+    uex = np.linalg.solve(A.toarray(), P.b)
+    assert np.abs(usol - uex).max() <= 1e-11 * np.abs(uex).max()
+
+
+@pytest.mark.parametrize("coupling", ["one_level", "additive"])
+@pytest.mark.parametrize("n,boxes,overlap", [(8, 2, 1), (12, 3, 1), (12, 3, 2), (13, 3, 2)])
+def test_fixed_point_is_global_solution(coupling, n, boxes, overlap):
+    """If F(u*) = 0 then every T_i(u*) = 0 and T_0(u*) = 0 (eqs. 4, 9), so
+    the nonlinear Schwarz solution equals the global Newton solution."""
+    P, S = _schwarz(coupling, n=n, boxes=boxes, overlap=overlap,
+                    forcing_seed=3, uneven=(n == 13), inner_eta=1e-14)
+    ug, _ = global_newton(P, dense=True)
+    Fx0 = np.linalg.norm(S.evaluate(np.zeros(P.N)))
+    assert np.linalg.norm(S.evaluate(ug)) <= 1e-13 * Fx0
+    u, st = S.solve(rtol=1e-14, gmres_rtol=1e-12)
+    assert st["converged"]
+    assert np.linalg.norm(u - ug) <= 1e-12 * np.linalg.norm(ug)
+
+
+def test_gdsw_invariants():
+    """Sum of the scalar GDSW functions is 1 on every node of subdomains
+    away from the Dirichlet boundary; interior rows are discrete harmonic;
+    the count is (bx-1)(by-1) vertices + bx(by-1) + by(bx-1) edges."""
+    P, S = _schwarz("additive", n=16, boxes=4, overlap=1)
+    assert S.n0 == 3 * 3 + 4 * 3 + 4 * 3
+    Phi = S.Phi.toarray()
+    rowsum = Phi.sum(axis=1)
+    A = P.jacobian(np.zeros(P.N)).toarray()
+    for i in range(S.n_sub):
+        el = np.nonzero(S.part == i)[0]
+        nodes = np.unique(P.conn[el])
+        if not P.is_dir[nodes].any():
+            np.testing.assert_allclose(rowsum[nodes], 1.0, atol=1e-13)
+    for (i, I, bnd) in S.interior_blocks:
+        np.testing.assert_allclose(A[I] @ Phi, 0.0, atol=1e-13)
+    # Dirichlet rows vanish; interface rows are indicator functions
+    assert np.all(Phi[P.is_dir] == 0.0)
+    for k, (nodes, _) in enumerate(S.components):
+        np.testing.assert_array_equal(Phi[nodes, k], 1.0)
+
+
+def test_coarse_linear_one_step():
+    """beta = 0: T_0(u) = (Phi^T A Phi)^-1 Phi^T (A u - b)."""
+    P, S = _schwarz("additive", n=12, boxes=3, overlap=1, beta=0.0,
+                    forcing_seed=8)
+    u = np.random.default_rng(2).normal(size=P.N)
+    A = P.jacobian(np.zeros(P.N)).toarray()
+    Phi = S.Phi.toarray()
+    ref = np.linalg.solve(Phi.T @ A @ Phi, Phi.T @ (A @ u - P.b))
+    co = S.coarse_solve(u)
+    assert co["its"] <= 2
+    np.testing.assert_allclose(co["c"], ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("coupling", ["one_level", "additive"])
+def test_tangent_identity_literal_and_fd(coupling):
+    P, S = _schwarz(coupling, n=10, boxes=2, overlap=1, forcing_seed=6,
+                    coef_seed=1)
+    rng = np.random.default_rng(7)
+    ug, _ = global_newton(P)
+    u = ug + 0.3 * rng.normal(size=P.N) * np.abs(ug).max()
+    u[P.is_dir] = 0.0
+    S.evaluate(u)
+    v = rng.normal(size=P.N)
+    v[P.is_dir] = 0.0
+    y = S.tangent(v)
+    yl = S.tangent_literal(v)
+    np.testing.assert_allclose(y, yl, rtol=0, atol=1e-13 * np.abs(y).max())
+    eps = 1e-6 * np.linalg.norm(u) / np.linalg.norm(v)
+    S2 = Schwarz(P, coupling)
+    S2.inner_eta = 1e-14
+    S2.inner_rtol = 1e-15
+    fd = (S2.evaluate(u + eps * v) - S2.evaluate(u - eps * v)) / (2 * eps)
+    np.testing.assert_allclose(y, fd, rtol=0, atol=1e-6 * np.abs(y).max())
+
+
+def test_gmres_matches_dense_solve():
+    P, S = _schwarz("additive", n=10, boxes=2, overlap=1, forcing_seed=1)
+    S.evaluate(np.zeros(P.N))
+    N = P.N
+    T = np.stack([S.tangent(e) for e in np.eye(N)], axis=1)
+    b = S.evaluate(np.zeros(N))
+    x, its = gmres_mgs(S.tangent, b, rtol=1e-12, restart=7, maxit=500)
+    xd = np.linalg.solve(T, b)
+    assert its > 7  # restarts exercised
+    np.testing.assert_allclose(x, xd, rtol=0, atol=1e-10 * np.abs(xd).max())
+
+
+def test_local_newton_quadratic():
+    P, S = _schwarz("one_level", n=16, boxes=2, overlap=2, forcing_seed=2)
+    ug, _ = global_newton(P)
+    sol = S.local_solve(0, 40.0 * ug)
+    h = sol["hist"]
+    assert sol["its"] >= 3
+    for a, b in zip(h[:-1], h[1:]):
+        if b > 1e-13 and a > 1e-13:
+            assert b <= 10.0 * a * a / max(h[0], 1e-300) * 1e3 or b < 1e-3 * a
+    # terminal iterations contract at least quadratically-fast
+    assert h[-1] <= 1e-12 * h[0] + 1e-14
