@@ -1,0 +1,219 @@
+/*
+ * nls.h -- C ABI of the MI355X two-level nonlinear Schwarz library (libnls).
+ *
+ * Method: nonlinear restricted additive Schwarz with exact tangent (RASPEN)
+ * and an optional GDSW coarse level, driven by an outer Newton iteration on
+ * the nonlinearly preconditioned system (Heinlein, Ho, Klawonn, Lanser,
+ * "Nonlinear Two-Level Schwarz Methods: A Parallel Implementation in
+ * FROSch", Section 2, eqs. (3)-(13)).
+ *
+ * Conventions
+ *  - Every call returns an int: 0 success, negative error, positive
+ *    "completed but not converged".  No C++ exception crosses the ABI.
+ *  - Host arrays passed to setters are copied before the call returns; the
+ *    library never keeps or frees caller memory.
+ *  - Device pointers (argument names ending in _dev) must point to memory of
+ *    the handle's device; the library reads and writes them in stream order
+ *    on the handle's stream and synchronises that stream before returning.
+ *  - Global node indices are 0-based; vectors hold one value per mesh node
+ *    (scalar problems), in node order.
+ *  - A handle is used by one host thread at a time.
+ *  - All floating point at the ABI is IEEE binary64.
+ */
+#ifndef NLS_H
+#define NLS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------- */
+#define NLS_OK            0
+#define NLS_ENOCONV       1   /* outer Newton hit its iteration limit; last iterate written */
+#define NLS_EINVAL       -1   /* bad argument (null pointer, out-of-range index, size) */
+#define NLS_EHIP         -2   /* a HIP runtime call failed */
+#define NLS_ENOMEM       -3   /* device allocation failed */
+#define NLS_EPARTITION   -4   /* empty subdomain, or owned nodes not inside V_i (overlap < 1) */
+#define NLS_ESINGULAR    -5   /* zero pivot in a local, interior or coarse LU */
+#define NLS_ELOCAL       -6   /* an inner (local or coarse) Newton iteration failed */
+#define NLS_ENAN         -7   /* non-finite value in a residual */
+#define NLS_ESTATE       -8   /* call out of order (e.g. solve before set_partition) */
+#define NLS_ELIMIT       -9   /* a subdomain exceeds a kernel limit (band too wide for LDS) */
+
+/* ---- enumerations ---------------------------------------------------- */
+#define NLS_ELEM_P1_TRI   3   /* 3-node triangles, counter-clockwise */
+
+#define NLS_PROBLEM_DIFFUSION 1  /* -div(kappa (1 + beta u^2) grad u) = f, eq. (1) */
+
+#define NLS_PREC_FP64     0   /* every step in binary64 */
+#define NLS_PREC_FP32_IR  1   /* local LU in binary32, binary64 residuals and
+                                 iterative refinement of every local solve */
+
+#define NLS_ONE_LEVEL     0   /* F_1(u) = sum_i P~_i T_i(u), eq. (5) with (8) */
+#define NLS_ADDITIVE      1   /* F_a(u) = F_1(u) + P_0 T_0(u), eq. (10) */
+
+#define NLS_COARSE_NONE   0
+#define NLS_COARSE_GDSW   1   /* vertex + edge components, harmonic extension */
+
+/* ---- options --------------------------------------------------------- */
+typedef struct nls_options {
+    int    device;        /* HIP device ordinal */
+    void*  stream;        /* hipStream_t to run on; NULL = the null stream */
+    int    precision;     /* NLS_PREC_* */
+    int    coupling;      /* NLS_ONE_LEVEL or NLS_ADDITIVE */
+    double outer_rtol;    /* stop when ||F_x(u_k)||_2 <= outer_rtol ||F_x(u_0)||_2 */
+    int    outer_maxit;
+    double inner_rtol;    /* local/coarse Newton: ||r||_2 <= max(inner_rtol rho_0,  */
+    double inner_eta;     /*   inner_eta ||b||_inf sqrt(n)), b the load vector      */
+    double stagnation;    /*   or last step <= stagnation ||x||_inf                  */
+    int    inner_maxit;
+    double gmres_rtol;    /* GMRES on eq. (13): ||r||_2 <= gmres_rtol ||F_x(u_k)||_2 */
+    int    gmres_maxit;
+    int    gmres_restart;
+    int    flags;         /* reserved, 0 */
+} nls_options;
+
+/* ---- statistics of the last solve ------------------------------------ */
+#define NLS_MAX_OUTER 64
+typedef struct nls_stats {
+    int       converged;            /* 1 if the outer stopping rule was met */
+    int       outer_its;            /* outer Newton iterations taken */
+    int       gmres_its[NLS_MAX_OUTER];
+    int       gmres_its_total;
+    int64_t   inner_its_total;      /* sum over evaluations and subdomains */
+    int       inner_its_max;        /* largest local iteration count seen */
+    int64_t   local_solves;         /* number of local nonlinear solves T_i */
+    int       coarse_its_total;
+    int       failed_subdomain;     /* -1, or the subdomain whose Newton failed */
+    double    res0;                 /* ||F_x(u_0)||_2 */
+    double    res_final;            /* ||F_x(u_final)||_2 */
+    double    ms_inner;             /* phase times (device-synchronised wall) */
+    double    ms_coarse;
+    double    ms_gmres;
+    double    ms_other;
+    double    ms_total;
+} nls_stats;
+
+typedef struct nls_handle nls_handle;
+
+/* Fill *opt with defaults: FP64, one-level, outer_rtol 1e-8, outer_maxit 50,
+   inner_rtol 1e-12, inner_eta 1e-10, stagnation 1e-14, inner_maxit 30,
+   gmres_rtol 1e-6, gmres_maxit 1000, gmres_restart 50. */
+int nls_default_options(nls_options* opt);
+
+/* Create a handle on opt->device.  *out receives the handle; the library
+   owns it and every device buffer it allocates until nls_destroy.
+   Errors: NLS_EINVAL (null pointers, bad enum), NLS_EHIP. */
+int nls_create(const nls_options* opt, nls_handle** out);
+
+/* Free every resource of h (NULL is accepted). */
+int nls_destroy(nls_handle* h);
+
+/* The mesh of the abstract discrete problem F(u) = 0 (eq. (3)).
+   xy: n_nodes x 2 coordinates (row-major); conn: n_elems x 3 node indices
+   per element, counter-clockwise.  Copied.  Errors: NLS_EINVAL on an index
+   out of range or a non-positive element area. */
+int nls_set_mesh(nls_handle* h, int elem_kind, int64_t n_nodes,
+                 const double* xy, int64_t n_elems, const int32_t* conn);
+
+/* The nonlinear problem on that mesh (eq. (1) generalised):
+     -div( kappa_e (1 + beta u^2) grad u ) = f.
+   params[0] = beta.  elem_coef: kappa per element, or NULL for 1.
+   elem_load: f sampled at the midpoints of each element's edges
+   (v0,v1), (v1,v2), (v2,v0) (n_elems x 3), or NULL for f = 1; the load is
+   integrated with the edge-midpoint rule.  Copied. */
+int nls_set_problem(nls_handle* h, int kind, const double* params,
+                    const double* elem_coef, const double* elem_load);
+
+/* Dirichlet nodes and values; F_g(u) = u_g - value on those rows.  Copied. */
+int nls_set_dirichlet(nls_handle* h, int64_t n, const int64_t* nodes,
+                      const double* values);
+
+/* Element-based partition into n_sub subdomains (Section 2, last paragraph:
+   the overlap is built on elements so each subdomain can assemble locally).
+   elem_part[e] in [0, n_sub).  Each subdomain is grown by `overlap` layers
+   of elements sharing a node with it.  V_i is the set of patch nodes whose
+   every element is in the patch; node g is owned by the largest subdomain
+   id among its elements (restricted prolongation, eq. (8)).
+   Errors: NLS_EPARTITION (empty subdomain, overlap < 1), NLS_ELIMIT. */
+int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* elem_part,
+                      int32_t overlap);
+
+/* Build the coarse space P_0 = Phi (Section 2; GDSW family).  kind
+   NLS_COARSE_GDSW: one function per connected interface component
+   (vertices: nodes of >= 3 subdomains, edges: 2), equal to 1 on it,
+   extended harmonically with DF(0) into every subdomain interior.
+   Errors: NLS_ESTATE (no partition), NLS_ESINGULAR. */
+int nls_build_coarse(nls_handle* h, int kind);
+
+/* Outer Newton iteration on F_x(u) = 0 (eq. (13)): solve
+   D F_x(u_k) du = F_x(u_k) by GMRES and set u_{k+1} = u_k - du.
+   u: n_nodes values, read as the initial iterate and overwritten with the
+   last iterate; a device pointer if u_on_device != 0, else host memory.
+   st may be NULL.  Returns NLS_OK, NLS_ENOCONV, or an error. */
+int nls_solve(nls_handle* h, double* u, int u_on_device, nls_stats* st);
+
+/* ---- hooks at the internal boundaries (device pointers) --------------- */
+
+/* F(u) (eq. (3)), n_nodes values. */
+int nls_eval_residual(nls_handle* h, const double* u_dev, double* F_dev);
+
+/* F_x(u) for the handle's coupling (eqs. (5), (10)); also keeps the local
+   and coarse states at u for nls_apply_tangent. */
+int nls_eval_precond_residual(nls_handle* h, const double* u_dev,
+                              double* Fx_dev);
+
+/* y = D F_x(u) v at the u of the last nls_eval_precond_residual
+   (eqs. (6), (7), (12)).  Errors: NLS_ESTATE if no state is kept. */
+int nls_apply_tangent(nls_handle* h, const double* v_dev, double* y_dev);
+
+/* Local Newton iteration counts of the last evaluation, n_sub ints (host). */
+int nls_get_inner_iterations(nls_handle* h, int32_t* its_host);
+
+/* Number of subdomains and coarse functions; sizes of V_i (host, n_sub). */
+int nls_get_sizes(nls_handle* h, int32_t* n_sub, int32_t* n_coarse,
+                  int32_t* nv_host);
+
+/* Coarse basis Phi (n_nodes x n_coarse) as CSR in host memory.  Call with
+   rowptr == NULL to query *nnz; then rowptr (n_nodes+1), col and val (nnz)
+   must be caller-allocated.  Columns are ordered by the smallest node index
+   of their interface component. */
+int nls_get_coarse_basis(nls_handle* h, int64_t* nnz, int64_t* rowptr,
+                         int32_t* col, double* val);
+
+/* ---- host-only inspection (no device is touched) ----------------------- */
+
+/* Build the overlapping subdomains of nls_set_partition on the host and
+   report them.  Call once with the output arrays NULL to get
+   counts[0] = sum_i |V_i| and counts[1] = sum_i |Gamma_i|; then pass
+   off_v, off_g (n_sub+1), v_nodes (counts[0]), g_nodes (counts[1]),
+   own_pos (n_nodes: position in v_nodes of the owner's copy of node g) and
+   kl, ku (n_sub: band widths of J_ii under the ascending-node local
+   order).  Any output pointer may be NULL.  Errors as nls_set_partition. */
+int nls_inspect_partition(int64_t n_nodes, int64_t n_elems, const int32_t* conn,
+                          int32_t n_sub, const int32_t* elem_part, int32_t overlap,
+                          int64_t* counts, int32_t* off_v, int32_t* v_nodes,
+                          int32_t* off_g, int32_t* g_nodes, int32_t* own_pos,
+                          int32_t* kl, int32_t* ku);
+
+/* Interface components of the GDSW coarse space (host only).  dirichlet:
+   n_dir node indices excluded from the interface.  First call with
+   comp_off == NULL gives counts[0] = n_coarse, counts[1] = total component
+   nodes; then comp_off (n_coarse+1) and comp_nodes receive the components,
+   ordered by smallest node, nodes ascending. */
+int nls_inspect_coarse(int64_t n_nodes, int64_t n_elems, const int32_t* conn,
+                       int32_t n_sub, const int32_t* elem_part, int64_t n_dir,
+                       const int64_t* dirichlet, int64_t* counts,
+                       int32_t* comp_off, int32_t* comp_nodes);
+
+/* Message for a status code; message of the last error on h.  Strings are
+   owned by the library. */
+const char* nls_strerror(int code);
+const char* nls_last_error(nls_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NLS_H */

@@ -1,0 +1,897 @@
+// C ABI of libnls: handle, setup, and the outer Newton-GMRES driver of
+// two-level nonlinear restricted additive Schwarz (paper, Section 2).
+//
+// The driver runs on the host thread and launches every numerical step as
+// a HIP kernel on the handle's stream:
+//   F_x(u)   local nonlinear solves (one fused launch over all subdomains),
+//            coarse Newton iteration (eq. 9), restricted prolongation and
+//            additive combination (eqs. 5, 8, 10);
+//   tangent  y = v + sum_i P~_i J_ii^{-1} B_i v_Gi + Phi A0^{-1} Phi^T DF(u_0) v
+//            (eqs. 6, 7, 12, using R_i DF(u_i) v = J_ii R_i v + B_i v_Gi);
+//   GMRES    restarted, classical Gram-Schmidt with one reorthogonalisation,
+//            Givens rotations on the host (a few scalars per iteration);
+//   Newton   u <- u - du (eq. 13).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "nls.h"
+#include "nls_device.h"
+#include "nls_internal.h"
+
+namespace {
+
+enum BufGroup { G_MESH = 0, G_MAPS = 1, G_COARSE = 2, G_NGROUPS = 3 };
+
+struct Timer {
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+    double ms() const {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+            .count();
+    }
+};
+
+}  // namespace
+
+struct nls_handle {
+    nls_options opt{};
+    hipStream_t stream = nullptr;
+    std::string err;
+    HostMesh mesh;
+    bool have_mesh = false, have_part = false, have_coarse = false, have_state = false;
+    int kind = NLS_PROBLEM_DIFFUSION;
+    double beta = 1.0;
+    std::vector<double> kappa_h, fmid_h;
+    std::vector<int> part_h;
+    HostMaps maps;
+    HostCoarse co;
+    std::vector<void*> bufs[G_NGROUPS];
+    DevMesh dm{};
+    DevMaps dp{};
+    DevLocal dl{};
+    DevCoarse dc{};
+    NewtonParams np{};
+    double b_inf = 0.0, phib_inf = 0.0;
+    int npl_local = 1, lds_local = 0, lds_tangent = 0;
+    int npl_coarse = 1, lds_coarse_lu = 0, lds_coarse_q = 0;
+    // GMRES / outer workspace
+    int m = 0;
+    double *V = nullptr, *wv = nullptr, *hbuf = nullptr, *hbuf2 = nullptr, *hn2 = nullptr,
+           *partial = nullptr, *Fx = nullptr, *du = nullptr, *tmp = nullptr, *ctmp = nullptr,
+           *ydev = nullptr, *ubuf = nullptr;
+    int* stat2 = nullptr;
+    int nb_dot = 0;
+    std::vector<int> its_h;
+    nls_stats* st = nullptr;  // stats of the running solve (may be null)
+
+    ~nls_handle() {
+        for (auto& g : bufs)
+            for (void* p : g) (void)hipFree(p);
+    }
+    void free_group(int g) {
+        for (void* p : bufs[g]) (void)hipFree(p);
+        bufs[g].clear();
+    }
+    template <class T>
+    int alloc(int group, T** out, size_t count) {
+        void* p = nullptr;
+        size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            err = "device allocation of " + std::to_string(bytes) + " bytes failed";
+            *out = nullptr;
+            return NLS_ENOMEM;
+        }
+        bufs[group].push_back(p);
+        *out = (T*)p;
+        return NLS_OK;
+    }
+    template <class T>
+    int upload(int group, T** out, const std::vector<T>& h) {
+        int rc = alloc(group, out, h.size());
+        if (rc) return rc;
+        if (!h.empty() &&
+            hipMemcpyAsync(*out, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, stream) !=
+                hipSuccess) {
+            err = "host-to-device copy failed";
+            return NLS_EHIP;
+        }
+        return NLS_OK;
+    }
+};
+
+#define HIPCHK(x)                                                          \
+    do {                                                                   \
+        hipError_t e_ = (x);                                               \
+        if (e_ != hipSuccess) {                                            \
+            h->err = std::string(#x) + ": " + hipGetErrorString(e_);       \
+            return NLS_EHIP;                                               \
+        }                                                                  \
+    } while (0)
+#define RC(x)                   \
+    do {                        \
+        int rc_ = (x);          \
+        if (rc_ != NLS_OK) return rc_; \
+    } while (0)
+
+static int fail(nls_handle* h, int code, const std::string& msg) {
+    if (h) h->err = msg;
+    return code;
+}
+
+static int sync(nls_handle* h) {
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return NLS_OK;
+}
+
+// ---------------------------------------------------------------------------
+extern "C" int nls_default_options(nls_options* o) {
+    if (!o) return NLS_EINVAL;
+    std::memset(o, 0, sizeof(*o));
+    o->device = 0;
+    o->stream = nullptr;
+    o->precision = NLS_PREC_FP64;
+    o->coupling = NLS_ONE_LEVEL;
+    o->outer_rtol = 1e-8;
+    o->outer_maxit = 50;
+    o->inner_rtol = 1e-12;
+    o->inner_eta = 1e-10;
+    o->stagnation = 1e-14;
+    o->inner_maxit = 30;
+    o->gmres_rtol = 1e-6;
+    o->gmres_maxit = 1000;
+    o->gmres_restart = 50;
+    o->flags = 0;
+    return NLS_OK;
+}
+
+extern "C" int nls_create(const nls_options* opt, nls_handle** out) {
+    if (!opt || !out) return NLS_EINVAL;
+    if (opt->precision != NLS_PREC_FP64 && opt->precision != NLS_PREC_FP32_IR) return NLS_EINVAL;
+    if (opt->coupling != NLS_ONE_LEVEL && opt->coupling != NLS_ADDITIVE) return NLS_EINVAL;
+    if (opt->gmres_restart < 1 || opt->gmres_maxit < 1 || opt->outer_maxit < 0 ||
+        opt->outer_maxit > NLS_MAX_OUTER || opt->inner_maxit < 1)
+        return NLS_EINVAL;
+    if (hipSetDevice(opt->device) != hipSuccess) return NLS_EHIP;
+    auto* h = new (std::nothrow) nls_handle();
+    if (!h) return NLS_ENOMEM;
+    h->opt = *opt;
+    h->stream = (hipStream_t)opt->stream;
+    *out = h;
+    return NLS_OK;
+}
+
+extern "C" int nls_destroy(nls_handle* h) {
+    if (!h) return NLS_OK;
+    (void)hipSetDevice(h->opt.device);
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    delete h;
+    return NLS_OK;
+}
+
+extern "C" int nls_set_mesh(nls_handle* h, int elem_kind, int64_t n_nodes, const double* xy,
+                            int64_t n_elems, const int32_t* conn) {
+    if (!h) return NLS_EINVAL;
+    if (elem_kind != NLS_ELEM_P1_TRI) return fail(h, NLS_EINVAL, "only P1 triangles are supported");
+    if (n_nodes <= 0 || n_elems <= 0 || !xy || !conn || n_nodes > (1 << 28) ||
+        n_elems > (1 << 28))
+        return fail(h, NLS_EINVAL, "bad mesh sizes or null arrays");
+    HostMesh m;
+    m.N = (int)n_nodes;
+    m.E = (int)n_elems;
+    m.xy.assign(xy, xy + 2 * n_nodes);
+    m.conn.assign(conn, conn + 3 * n_elems);
+    std::string err;
+    int rc = nls_build_node_incidence(m, err);
+    if (rc) return fail(h, rc, err);
+    m.dflag.assign(m.N, 0);
+    m.dval.assign(m.N, 0.0);
+    h->mesh = std::move(m);
+    h->have_mesh = true;
+    h->have_part = h->have_coarse = h->have_state = false;
+    h->kappa_h.clear();
+    h->fmid_h.clear();
+    h->beta = 1.0;
+    return NLS_OK;
+}
+
+extern "C" int nls_set_problem(nls_handle* h, int kind, const double* params,
+                               const double* elem_coef, const double* elem_load) {
+    if (!h) return NLS_EINVAL;
+    if (!h->have_mesh) return fail(h, NLS_ESTATE, "nls_set_mesh first");
+    if (kind != NLS_PROBLEM_DIFFUSION) return fail(h, NLS_EINVAL, "unknown problem kind");
+    h->kind = kind;
+    h->beta = params ? params[0] : 1.0;
+    if (!std::isfinite(h->beta)) return fail(h, NLS_EINVAL, "beta must be finite");
+    const int E = h->mesh.E;
+    if (elem_coef) {
+        h->kappa_h.assign(elem_coef, elem_coef + E);
+        for (double k : h->kappa_h)
+            if (!(k > 0.0) || !std::isfinite(k))
+                return fail(h, NLS_EINVAL, "element coefficients must be positive and finite");
+    } else {
+        h->kappa_h.clear();
+    }
+    if (elem_load) {
+        h->fmid_h.assign(elem_load, elem_load + 3 * (size_t)E);
+    } else {
+        h->fmid_h.clear();
+    }
+    h->have_part = h->have_coarse = h->have_state = false;
+    return NLS_OK;
+}
+
+extern "C" int nls_set_dirichlet(nls_handle* h, int64_t n, const int64_t* nodes,
+                                 const double* values) {
+    if (!h) return NLS_EINVAL;
+    if (!h->have_mesh) return fail(h, NLS_ESTATE, "nls_set_mesh first");
+    if (n < 0 || (n > 0 && (!nodes || !values))) return fail(h, NLS_EINVAL, "bad Dirichlet arrays");
+    std::fill(h->mesh.dflag.begin(), h->mesh.dflag.end(), 0);
+    std::fill(h->mesh.dval.begin(), h->mesh.dval.end(), 0.0);
+    for (int64_t k = 0; k < n; ++k) {
+        if (nodes[k] < 0 || nodes[k] >= h->mesh.N) return fail(h, NLS_EINVAL, "Dirichlet node out of range");
+        h->mesh.dflag[nodes[k]] = 1;
+        h->mesh.dval[nodes[k]] = values[k];
+    }
+    h->have_part = h->have_coarse = h->have_state = false;
+    return NLS_OK;
+}
+
+static int upload_problem(nls_handle* h) {
+    const HostMesh& m = h->mesh;
+    h->free_group(G_MESH);
+    DevMesh d{};
+    d.N = m.N;
+    d.E = m.E;
+    d.beta = h->beta;
+    int *conn, *nptr, *nel;
+    double *xy, *G6, *kap, *eload, *bload, *dval, *coef = nullptr, *fmid = nullptr;
+    unsigned char* dflag;
+    std::vector<int> nelc(m.nel.size());
+    for (int g = 0; g < m.N; ++g)
+        for (int k = m.nptr[g]; k < m.nptr[g + 1]; ++k) {
+            int e = m.nel[k], pos = 0;
+            for (int v = 0; v < 3; ++v)
+                if (m.conn[3 * e + v] == g) pos = v;
+            nelc[k] = (e << 2) | pos;
+        }
+    RC(h->upload(G_MESH, &conn, m.conn));
+    RC(h->upload(G_MESH, &nptr, m.nptr));
+    RC(h->upload(G_MESH, &nel, nelc));
+    RC(h->upload(G_MESH, &xy, m.xy));
+    RC(h->upload(G_MESH, &dflag, m.dflag));
+    RC(h->upload(G_MESH, &dval, m.dval));
+    if (!h->kappa_h.empty()) RC(h->upload(G_MESH, &coef, h->kappa_h));
+    if (!h->fmid_h.empty()) RC(h->upload(G_MESH, &fmid, h->fmid_h));
+    RC(h->alloc(G_MESH, &G6, 6 * (size_t)m.E));
+    RC(h->alloc(G_MESH, &kap, m.E));
+    RC(h->alloc(G_MESH, &eload, 3 * (size_t)m.E));
+    RC(h->alloc(G_MESH, &bload, m.N));
+    int* bad;
+    double *part, *mx;
+    int nb = 256;
+    RC(h->alloc(G_MESH, &bad, 1));
+    RC(h->alloc(G_MESH, &part, nb));
+    RC(h->alloc(G_MESH, &mx, 1));
+    d.conn = conn;
+    d.nptr = nptr;
+    d.nel = nel;
+    d.G6 = G6;
+    d.kappa = kap;
+    d.eload = eload;
+    d.bload = bload;
+    d.dflag = dflag;
+    d.dval = dval;
+    HIPCHK(hipMemsetAsync(bad, 0, sizeof(int), h->stream));
+    HIPCHK(launch_p1_setup(d, xy, coef, fmid, G6, kap, eload, bad, h->stream));
+    HIPCHK(launch_assemble_load(d, bload, h->stream));
+    HIPCHK(launch_max_abs(bload, m.N, part, mx, nb, h->stream));
+    int bad_h = 0;
+    HIPCHK(hipMemcpyAsync(&bad_h, bad, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(&h->b_inf, mx, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    RC(sync(h));
+    if (bad_h) return fail(h, NLS_EINVAL, "an element is clockwise or degenerate");
+    h->dm = d;
+    return NLS_OK;
+}
+
+static int npl_for(int band) { return band <= 64 ? 1 : (band <= 128 ? 2 : 4); }
+
+extern "C" int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* elem_part,
+                                 int32_t overlap) {
+    if (!h) return NLS_EINVAL;
+    if (!h->have_mesh) return fail(h, NLS_ESTATE, "nls_set_mesh first");
+    if (!elem_part) return fail(h, NLS_EINVAL, "elem_part is null");
+    HIPCHK(hipSetDevice(h->opt.device));
+    h->have_part = h->have_coarse = h->have_state = false;
+    h->free_group(G_MAPS);
+    h->free_group(G_COARSE);
+    RC(upload_problem(h));
+    std::string err;
+    int rc = nls_build_maps(h->mesh, elem_part, n_sub, overlap, h->maps, err);
+    if (rc) return fail(h, rc, err);
+    h->part_h.assign(elem_part, elem_part + h->mesh.E);
+    const HostMaps& M = h->maps;
+    const bool mixed = h->opt.precision == NLS_PREC_FP32_IR;
+    // kernel limits
+    int maxband = 0, maxkl = 0, maxn = 0, maxng = 0;
+    for (int i = 0; i < M.nsub; ++i) {
+        maxkl = std::max(maxkl, M.kl[i]);
+        maxband = std::max(maxband, M.kl[i] + M.ku[i]);
+        maxn = std::max(maxn, M.off_n[i + 1] - M.off_n[i]);
+        maxng = std::max(maxng, M.off_g[i + 1] - M.off_g[i]);
+    }
+    if (maxkl > 127 || maxband > 256)
+        return fail(h, NLS_ELIMIT, "local band too wide (kl <= 127, kl+ku <= 256)");
+    int lds = 0;
+    for (int i = 0; i < M.nsub; ++i) {
+        int n = M.off_n[i + 1] - M.off_n[i], ng = M.off_g[i + 1] - M.off_g[i];
+        int dbl = (n + ng) + n + (mixed ? 2 * n : 0) + 24 + std::max(M.kl[i], 1) + 1;
+        int bytes = dbl * 8 + band_window_doubles(M.kl[i], M.ku[i]) * (mixed ? 4 : 8);
+        lds = std::max(lds, bytes);
+    }
+    if (lds > 160 * 1024) return fail(h, NLS_ELIMIT, "subdomain too large for the LDS working set");
+    h->lds_local = lds;
+    h->lds_tangent = (maxn + (mixed ? 2 * maxn : 0) + 24) * 8;
+    h->npl_local = npl_for(std::max(maxkl, maxband));
+    // tables
+    DevMaps d{};
+    d.nsub = M.nsub;
+    int *off_n, *off_g, *off_e, *l2g, *g2g, *pe_conn, *pe_gid, *rinc_ptr, *rinc, *jptr, *jcol,
+        *kl, *ku, *order, *own;
+    int64_t *off_u, *off_l;
+    RC(h->upload(G_MAPS, &off_n, M.off_n));
+    RC(h->upload(G_MAPS, &off_g, M.off_g));
+    RC(h->upload(G_MAPS, &off_e, M.off_e));
+    RC(h->upload(G_MAPS, &l2g, M.l2g));
+    RC(h->upload(G_MAPS, &g2g, M.g2g));
+    RC(h->upload(G_MAPS, &pe_conn, M.pe_conn));
+    RC(h->upload(G_MAPS, &pe_gid, M.pe_gid));
+    RC(h->upload(G_MAPS, &rinc_ptr, M.rinc_ptr));
+    RC(h->upload(G_MAPS, &rinc, M.rinc));
+    RC(h->upload(G_MAPS, &jptr, M.jptr));
+    RC(h->upload(G_MAPS, &jcol, M.jcol));
+    RC(h->upload(G_MAPS, &kl, M.kl));
+    RC(h->upload(G_MAPS, &ku, M.ku));
+    RC(h->upload(G_MAPS, &order, M.order));
+    RC(h->upload(G_MAPS, &own, M.own_pidx));
+    RC(h->upload(G_MAPS, &off_u, M.off_u));
+    RC(h->upload(G_MAPS, &off_l, M.off_l));
+    d.off_n = off_n; d.off_g = off_g; d.off_e = off_e; d.l2g = l2g; d.g2g = g2g;
+    d.pe_conn = pe_conn; d.pe_gid = pe_gid; d.rinc_ptr = rinc_ptr; d.rinc = rinc;
+    d.jptr = jptr; d.jcol = jcol; d.kl = kl; d.ku = ku; d.order = order; d.own_pidx = own;
+    d.off_u = off_u; d.off_l = off_l;
+    h->dp = d;
+    // local state
+    DevLocal L{};
+    const size_t nrows = M.l2g.size();
+    RC(h->alloc(G_MAPS, &L.jval, M.jcol.size()));
+    RC(h->alloc(G_MAPS, &L.Uf, (size_t)M.factor_u_total));
+    RC(h->alloc(G_MAPS, &L.Lf, (size_t)M.factor_l_total));
+    if (mixed) {
+        RC(h->alloc(G_MAPS, &L.Uf32, (size_t)M.factor_u_total));
+        RC(h->alloc(G_MAPS, &L.Lf32, (size_t)M.factor_l_total));
+    }
+    RC(h->alloc(G_MAPS, &L.piv, nrows));
+    RC(h->alloc(G_MAPS, &L.xstar, nrows));
+    RC(h->alloc(G_MAPS, &L.T, nrows));
+    RC(h->alloc(G_MAPS, &L.z, nrows));
+    RC(h->alloc(G_MAPS, &L.its, M.nsub));
+    RC(h->alloc(G_MAPS, &L.status, M.nsub));
+    h->dl = L;
+    h->its_h.assign(M.nsub, 0);
+    // Newton parameters
+    NewtonParams np{};
+    np.rtol = h->opt.inner_rtol;
+    np.abs_tol = h->opt.inner_eta * h->b_inf;
+    np.stagnation = h->opt.stagnation;
+    np.maxit = h->opt.inner_maxit;
+    np.mixed = mixed ? 1 : 0;
+    np.ir_maxit = 10;
+    np.ir_rtol = 1e-14;
+    h->np = np;
+    // GMRES workspace
+    const int N = h->mesh.N;
+    h->m = h->opt.gmres_restart;
+    h->nb_dot = std::min(512, std::max(1, (N + 1023) / 1024));
+    RC(h->alloc(G_MAPS, &h->V, (size_t)(h->m + 1) * N));
+    RC(h->alloc(G_MAPS, &h->wv, N));
+    RC(h->alloc(G_MAPS, &h->hbuf, h->m + 2));
+    RC(h->alloc(G_MAPS, &h->hbuf2, h->m + 2));
+    RC(h->alloc(G_MAPS, &h->hn2, 4));
+    RC(h->alloc(G_MAPS, &h->partial, (size_t)h->nb_dot * (h->m + 2)));
+    RC(h->alloc(G_MAPS, &h->Fx, N));
+    RC(h->alloc(G_MAPS, &h->du, N));
+    RC(h->alloc(G_MAPS, &h->tmp, N));
+    RC(h->alloc(G_MAPS, &h->ydev, h->m + 2));
+    RC(h->alloc(G_MAPS, &h->ubuf, N));
+    RC(h->alloc(G_MAPS, &h->stat2, 2));
+    RC(sync(h));
+    h->have_part = true;
+    if (h->opt.coupling == NLS_ADDITIVE) {
+        // a two-level handle needs nls_build_coarse before solving
+    }
+    return NLS_OK;
+}
+
+// ------------------------------------------------------------ coarse space
+extern "C" int nls_build_coarse(nls_handle* h, int kind) {
+    if (!h) return NLS_EINVAL;
+    if (!h->have_part) return fail(h, NLS_ESTATE, "nls_set_partition first");
+    HIPCHK(hipSetDevice(h->opt.device));
+    h->free_group(G_COARSE);
+    h->have_coarse = false;
+    h->have_state = false;
+    if (kind == NLS_COARSE_NONE) return NLS_OK;
+    if (kind != NLS_COARSE_GDSW) return fail(h, NLS_EINVAL, "unknown coarse space kind");
+    std::string err;
+    int rc = nls_build_coarse_symbolic(h->mesh, h->part_h.data(), h->maps.nsub, h->co, err);
+    if (rc) return fail(h, rc, err);
+    const HostCoarse& C = h->co;
+    if (C.n0 == 0) return NLS_OK;  // a single subdomain has no interface
+    if (C.a0kl > 127 || C.a0kl + C.a0ku > 256)
+        return fail(h, NLS_ELIMIT, "coarse matrix band too wide");
+    int maxikl = 0, maxiband = 0, maxnc = 0;
+    for (int i = 0; i < h->maps.nsub; ++i) {
+        maxikl = std::max(maxikl, C.ikl[i]);
+        maxiband = std::max(maxiband, C.ikl[i] + C.iku[i]);
+        maxnc = std::max(maxnc, C.off_c[i + 1] - C.off_c[i]);
+    }
+    if (maxikl > 127 || maxiband > 256)
+        return fail(h, NLS_ELIMIT, "interior band too wide");
+    const int lds_gdsw = C.max_ilds_doubles * 8 + 64;
+    h->lds_coarse_lu = (C.n0 + std::max(C.a0kl, 1) + 1 + band_window_doubles(C.a0kl, C.a0ku)) * 8;
+    h->lds_coarse_q = maxnc * 8;
+    if (lds_gdsw > 160 * 1024 || h->lds_coarse_lu > 160 * 1024 || h->lds_coarse_q > 160 * 1024)
+        return fail(h, NLS_ELIMIT, "coarse working set exceeds LDS");
+    h->npl_coarse = npl_for(std::max(C.a0kl, C.a0kl + C.a0ku));
+    DevCoarse d{};
+    d.n0 = C.n0;
+    d.nsub = h->maps.nsub;
+    d.a0kl = C.a0kl;
+    d.a0ku = C.a0ku;
+    int *off_c, *cnode, *ctype, *off_k, *klist, *ccomp, *off_ne, *ne_conn, *ne_gid, *cinc_ptr,
+        *cinc, *iidx, *off_ni, *inode, *iptr, *icol, *ikl, *iku, *perm, *a0ptr, *a0col,
+        *a0src_ptr, *a0src, *gsrc_ptr, *gsrc, *cpos, *cown;
+    int64_t *off_phi, *off_iu, *off_il, *off_kk;
+    RC(h->upload(G_COARSE, &off_c, C.off_c));
+    RC(h->upload(G_COARSE, &cnode, C.cnode));
+    RC(h->upload(G_COARSE, &ctype, C.ctype));
+    RC(h->upload(G_COARSE, &off_k, C.off_k));
+    RC(h->upload(G_COARSE, &klist, C.klist));
+    RC(h->upload(G_COARSE, &ccomp, C.ccomp));
+    RC(h->upload(G_COARSE, &off_ne, C.off_ne));
+    RC(h->upload(G_COARSE, &ne_conn, C.ne_conn));
+    RC(h->upload(G_COARSE, &ne_gid, C.ne_gid));
+    RC(h->upload(G_COARSE, &cinc_ptr, C.cinc_ptr));
+    RC(h->upload(G_COARSE, &cinc, C.cinc));
+    RC(h->upload(G_COARSE, &iidx, C.iidx));
+    RC(h->upload(G_COARSE, &off_ni, C.off_ni));
+    RC(h->upload(G_COARSE, &inode, C.inode));
+    RC(h->upload(G_COARSE, &iptr, C.iptr));
+    RC(h->upload(G_COARSE, &icol, C.icol));
+    RC(h->upload(G_COARSE, &ikl, C.ikl));
+    RC(h->upload(G_COARSE, &iku, C.iku));
+    RC(h->upload(G_COARSE, &perm, C.perm));
+    RC(h->upload(G_COARSE, &a0ptr, C.a0ptr));
+    RC(h->upload(G_COARSE, &a0col, C.a0col));
+    RC(h->upload(G_COARSE, &a0src_ptr, C.a0src_ptr));
+    RC(h->upload(G_COARSE, &a0src, C.a0src));
+    RC(h->upload(G_COARSE, &gsrc_ptr, C.gsrc_ptr));
+    RC(h->upload(G_COARSE, &gsrc, C.gsrc));
+    RC(h->upload(G_COARSE, &cpos, C.cpos));
+    RC(h->upload(G_COARSE, &cown, C.cown));
+    RC(h->upload(G_COARSE, &off_phi, C.off_phi));
+    RC(h->upload(G_COARSE, &off_iu, C.off_iu));
+    RC(h->upload(G_COARSE, &off_il, C.off_il));
+    RC(h->upload(G_COARSE, &off_kk, C.off_kk));
+    d.off_c = off_c; d.cnode = cnode; d.ctype = ctype; d.off_k = off_k; d.klist = klist;
+    d.ccomp = ccomp; d.off_ne = off_ne; d.ne_conn = ne_conn; d.ne_gid = ne_gid;
+    d.cinc_ptr = cinc_ptr; d.cinc = cinc; d.iidx = iidx; d.off_ni = off_ni; d.inode = inode;
+    d.iptr = iptr; d.icol = icol; d.ikl = ikl; d.iku = iku; d.perm = perm; d.a0ptr = a0ptr;
+    d.a0col = a0col; d.a0src_ptr = a0src_ptr; d.a0src = a0src; d.gsrc_ptr = gsrc_ptr;
+    d.gsrc = gsrc; d.cpos = cpos; d.cown = cown; d.off_phi = off_phi; d.off_iu = off_iu;
+    d.off_il = off_il; d.off_kk = off_kk;
+    const int64_t nphi = C.off_phi.back();
+    RC(h->alloc(G_COARSE, &d.phi, (size_t)nphi));
+    RC(h->alloc(G_COARSE, &d.zbuf, (size_t)nphi));
+    RC(h->alloc(G_COARSE, &d.ival, C.icol.size()));
+    RC(h->alloc(G_COARSE, &d.iU, (size_t)C.iu_total));
+    RC(h->alloc(G_COARSE, &d.iL, (size_t)C.il_total));
+    RC(h->alloc(G_COARSE, &d.ipiv, C.inode.size()));
+    RC(h->alloc(G_COARSE, &d.gblk, C.klist.size()));
+    RC(h->alloc(G_COARSE, &d.ablk, (size_t)C.off_kk.back()));
+    RC(h->alloc(G_COARSE, &d.a0val, C.a0col.size()));
+    RC(h->alloc(G_COARSE, &d.a0U, (size_t)C.n0 * (C.a0kl + C.a0ku + 1)));
+    RC(h->alloc(G_COARSE, &d.a0L, (size_t)C.n0 * std::max(C.a0kl, 1)));
+    RC(h->alloc(G_COARSE, &d.a0piv, C.n0));
+    RC(h->alloc(G_COARSE, &d.rhs, C.n0));
+    RC(h->alloc(G_COARSE, &d.c, C.n0));
+    RC(h->alloc(G_COARSE, &d.w, h->mesh.N));
+    RC(h->alloc(G_COARSE, &d.scal, 4));
+    RC(h->alloc(G_COARSE, &d.flag, 1));
+    RC(h->alloc(G_COARSE, &h->ctmp, C.n0));
+    HIPCHK(hipMemsetAsync(d.flag, 0, sizeof(int), h->stream));
+    h->dc = d;
+    HIPCHK(launch_gdsw_extend(h->dm, d, lds_gdsw, npl_for(std::max(maxikl, maxiband)), h->stream));
+    int flag = 0;
+    HIPCHK(hipMemcpyAsync(&flag, d.flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    RC(sync(h));
+    if (flag) return fail(h, NLS_ESINGULAR, "zero pivot in an interior block of the extension");
+    // ||Phi^T b||_inf: G(c) at u = 0, c = 0 equals Phi^T F(0) = -Phi^T b
+    HIPCHK(hipMemsetAsync(d.w, 0, sizeof(double) * h->mesh.N, h->stream));
+    HIPCHK(launch_coarse_q(h->dm, d, d.w, nullptr, 0, h->lds_coarse_q, h->stream));
+    HIPCHK(launch_coarse_assemble(d, 0, h->stream));
+    double* part;
+    double* mx;
+    RC(h->alloc(G_COARSE, &part, 64));
+    RC(h->alloc(G_COARSE, &mx, 1));
+    HIPCHK(launch_max_abs(d.rhs, C.n0, part, mx, 64, h->stream));
+    HIPCHK(hipMemcpyAsync(&h->phib_inf, mx, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    RC(sync(h));
+    h->have_coarse = true;
+    return NLS_OK;
+}
+
+// ------------------------------------------------------------ evaluation
+static bool two_level(nls_handle* h) {
+    return h->opt.coupling == NLS_ADDITIVE && h->have_coarse && h->co.n0 > 0;
+}
+
+// Coarse Newton iteration for T_0(u) (eq. 9): c <- c + A0^{-1} Phi^T F(u - Phi c)
+// from c = 0; keeps LU(A0) at the converged c and u_0 = u - Phi c in dc.w.
+static int coarse_solve(nls_handle* h, const double* u, int* its_out) {
+    DevCoarse& d = h->dc;
+    const int n0 = d.n0;
+    HIPCHK(hipMemsetAsync(d.c, 0, sizeof(double) * n0, h->stream));
+    double tol = 0.0, dprev = -1.0, cmax = 0.0;
+    int its = 0;
+    for (;;) {
+        HIPCHK(launch_coarse_w(h->dm, d, u, d.w, h->stream));
+        HIPCHK(launch_coarse_q(h->dm, d, d.w, nullptr, 0, h->lds_coarse_q, h->stream));
+        HIPCHK(launch_coarse_assemble(d, 0, h->stream));
+        double gn = 0.0;
+        HIPCHK(hipMemcpyAsync(&gn, d.scal, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        RC(sync(h));
+        if (its == 0)
+            tol = std::max(h->opt.inner_rtol * gn, h->opt.inner_eta * h->phib_inf * std::sqrt((double)n0));
+        if (!std::isfinite(gn)) return fail(h, NLS_ENAN, "coarse residual is not finite");
+        if (gn <= tol) break;
+        if (dprev >= 0.0 && dprev <= h->opt.stagnation * cmax) break;
+        if (its == h->opt.inner_maxit) return fail(h, NLS_ELOCAL, "coarse Newton did not converge");
+        HIPCHK(launch_coarse_galerkin(h->dm, d, d.w, h->stream));
+        HIPCHK(launch_coarse_assemble(d, 1, h->stream));
+        HIPCHK(launch_coarse_lu(d, 1, h->lds_coarse_lu, h->npl_coarse, h->stream));
+        HIPCHK(launch_coarse_update(d, h->stream));
+        double sc[3];
+        int flag = 0;
+        HIPCHK(hipMemcpyAsync(sc, d.scal, 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipMemcpyAsync(&flag, d.flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+        RC(sync(h));
+        if (flag) return fail(h, NLS_ESINGULAR, "zero pivot in the coarse matrix");
+        dprev = sc[1];
+        cmax = sc[2];
+        ++its;
+    }
+    // Galerkin matrix and its LU at the converged point, for the tangent
+    HIPCHK(launch_coarse_galerkin(h->dm, d, d.w, h->stream));
+    HIPCHK(launch_coarse_assemble(d, 1, h->stream));
+    HIPCHK(launch_coarse_lu(d, 1, h->lds_coarse_lu, h->npl_coarse, h->stream));
+    if (its_out) *its_out = its;
+    return NLS_OK;
+}
+
+static int dot_host(nls_handle* h, const double* x, const double* y, int n, double* out) {
+    HIPCHK(launch_mdot(x, n, 1, y, n, h->partial, h->hn2 + 2, h->nb_dot, h->stream));
+    HIPCHK(hipMemcpyAsync(out, h->hn2 + 2, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    return sync(h);
+}
+
+// F_x(u) into Fx (device); keeps local and coarse states for the tangent.
+static int evaluate(nls_handle* h, const double* u, double* Fx) {
+    Timer t;
+    h->have_state = false;
+    HIPCHK(launch_local_newton(h->dm, h->dp, h->dl, h->np, u, h->lds_local, h->npl_local, h->stream));
+    HIPCHK(launch_any_status(h->dl.status, h->maps.nsub, h->stat2, h->stream));
+    int st2[2];
+    HIPCHK(hipMemcpyAsync(st2, h->stat2, 2 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(h->its_h.data(), h->dl.its, h->maps.nsub * sizeof(int),
+                          hipMemcpyDeviceToHost, h->stream));
+    RC(sync(h));
+    if (h->st) {
+        h->st->ms_inner += t.ms();
+        for (int v : h->its_h) {
+            h->st->inner_its_total += v;
+            h->st->inner_its_max = std::max(h->st->inner_its_max, v);
+        }
+        h->st->local_solves += h->maps.nsub;
+    }
+    if (st2[0] >= 0) {
+        if (h->st) h->st->failed_subdomain = st2[0];
+        if (st2[1] == 2) return fail(h, NLS_ENAN, "non-finite local residual in subdomain " + std::to_string(st2[0]));
+        if (st2[1] == 3) return fail(h, NLS_ESINGULAR, "zero pivot in subdomain " + std::to_string(st2[0]));
+        return fail(h, NLS_ELOCAL, "local Newton failed in subdomain " + std::to_string(st2[0]));
+    }
+    if (two_level(h)) {
+        Timer tc;
+        int cits = 0;
+        RC(coarse_solve(h, u, &cits));
+        RC(sync(h));
+        if (h->st) {
+            h->st->ms_coarse += tc.ms();
+            h->st->coarse_its_total += cits;
+        }
+        HIPCHK(launch_prolong(h->dm, h->dp, h->dl.T, &h->dc, h->dc.c, Fx, nullptr, h->stream));
+    } else {
+        HIPCHK(launch_prolong(h->dm, h->dp, h->dl.T, nullptr, nullptr, Fx, nullptr, h->stream));
+    }
+    h->have_state = true;
+    return NLS_OK;
+}
+
+// y = D F_x(u) v (eqs. 6, 7, 12) at the last evaluated point.
+static int tangent(nls_handle* h, const double* v, double* y) {
+    HIPCHK(launch_tangent_local(h->dm, h->dp, h->dl, h->np, v, h->lds_tangent, h->npl_local, h->stream));
+    if (two_level(h)) {
+        DevCoarse& d = h->dc;
+        HIPCHK(launch_coarse_q(h->dm, d, d.w, v, 1, h->lds_coarse_q, h->stream));
+        HIPCHK(launch_coarse_assemble(d, 0, h->stream));
+        HIPCHK(launch_coarse_lu(d, 0, h->lds_coarse_lu, h->npl_coarse, h->stream));
+        HIPCHK(launch_coarse_scatter(d, h->ctmp, h->stream));
+        HIPCHK(launch_prolong(h->dm, h->dp, h->dl.z, &d, h->ctmp, y, v, h->stream));
+    } else {
+        HIPCHK(launch_prolong(h->dm, h->dp, h->dl.z, nullptr, nullptr, y, v, h->stream));
+    }
+    return NLS_OK;
+}
+
+// Restarted GMRES(m) for D F_x(u) x = b from x = 0 (classical Gram-Schmidt
+// with one reorthogonalisation).  Returns the iteration count in *its.
+static int gmres(nls_handle* h, const double* b, double* x, int* its_out) {
+    const int N = h->mesh.N, m = h->m;
+    const int64_t ld = N;
+    double bn2 = 0.0;
+    RC(dot_host(h, b, b, N, &bn2));
+    const double bn = std::sqrt(bn2);
+    HIPCHK(hipMemsetAsync(x, 0, sizeof(double) * N, h->stream));
+    int its = 0;
+    *its_out = 0;
+    if (bn == 0.0) return NLS_OK;
+    const double rtol = h->opt.gmres_rtol;
+    std::vector<double> H((m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), hh(m + 2), hh2(m + 2), y(m);
+    bool first = true;
+    while (its < h->opt.gmres_maxit) {
+        double beta2;
+        if (first) {
+            HIPCHK(hipMemcpyAsync(h->V, b, sizeof(double) * N, hipMemcpyDeviceToDevice, h->stream));
+            beta2 = bn2;
+        } else {
+            RC(tangent(h, x, h->tmp));
+            HIPCHK(hipMemcpyAsync(h->V, b, sizeof(double) * N, hipMemcpyDeviceToDevice, h->stream));
+            HIPCHK(launch_axpy(-1.0, h->tmp, h->V, N, h->stream));
+            RC(dot_host(h, h->V, h->V, N, &beta2));
+        }
+        first = false;
+        const double beta = std::sqrt(beta2);
+        if (beta <= rtol * bn) break;
+        HIPCHK(hipMemcpyAsync(h->hn2, &beta2, sizeof(double), hipMemcpyHostToDevice, h->stream));
+        HIPCHK(launch_scale_by(h->V, h->hn2, h->V, N, h->stream));
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int j = 0;
+        bool done = false;
+        while (j < m && its < h->opt.gmres_maxit) {
+            double* vj = h->V + (int64_t)j * ld;
+            double* vn = h->V + (int64_t)(j + 1) * ld;
+            RC(tangent(h, vj, h->wv));
+            ++its;
+            HIPCHK(launch_mdot(h->V, ld, j + 1, h->wv, N, h->partial, h->hbuf, h->nb_dot, h->stream));
+            HIPCHK(launch_maxpy(h->V, ld, j + 1, h->hbuf, h->wv, N, 1.0, h->stream));
+            HIPCHK(launch_mdot(h->V, ld, j + 1, h->wv, N, h->partial, h->hbuf2, h->nb_dot, h->stream));
+            HIPCHK(launch_maxpy(h->V, ld, j + 1, h->hbuf2, h->wv, N, 1.0, h->stream));
+            HIPCHK(launch_mdot(h->wv, ld, 1, h->wv, N, h->partial, h->hn2, h->nb_dot, h->stream));
+            HIPCHK(launch_scale_by(h->wv, h->hn2, vn, N, h->stream));
+            double hn2;
+            HIPCHK(hipMemcpyAsync(hh.data(), h->hbuf, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+            HIPCHK(hipMemcpyAsync(hh2.data(), h->hbuf2, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+            HIPCHK(hipMemcpyAsync(&hn2, h->hn2, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+            RC(sync(h));
+            for (int i = 0; i <= j; ++i) H[i * m + j] = hh[i] + hh2[i];
+            H[(j + 1) * m + j] = std::sqrt(hn2);
+            for (int i = 0; i < j; ++i) {
+                const double t = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
+                H[(i + 1) * m + j] = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
+                H[i * m + j] = t;
+            }
+            const double den = std::hypot(H[j * m + j], H[(j + 1) * m + j]);
+            cs[j] = den > 0.0 ? H[j * m + j] / den : 1.0;
+            sn[j] = den > 0.0 ? H[(j + 1) * m + j] / den : 0.0;
+            H[j * m + j] = den;
+            H[(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++j;
+            if (!std::isfinite(g[j])) return fail(h, NLS_ENAN, "GMRES breakdown (non-finite)");
+            if (std::fabs(g[j]) <= rtol * bn) { done = true; break; }
+        }
+        for (int i = j - 1; i >= 0; --i) {
+            double s = g[i];
+            for (int k = i + 1; k < j; ++k) s -= H[i * m + k] * y[k];
+            y[i] = s / H[i * m + i];
+        }
+        HIPCHK(hipMemcpyAsync(h->ydev, y.data(), j * sizeof(double), hipMemcpyHostToDevice, h->stream));
+        HIPCHK(launch_maxpy(h->V, ld, j, h->ydev, x, N, -1.0, h->stream));
+        RC(sync(h));
+        if (done) break;
+    }
+    *its_out = its;
+    return NLS_OK;
+}
+
+extern "C" int nls_solve(nls_handle* h, double* u, int u_on_device, nls_stats* st) {
+    if (!h || !u) return NLS_EINVAL;
+    if (!h->have_part) return fail(h, NLS_ESTATE, "nls_set_partition first");
+    if (h->opt.coupling == NLS_ADDITIVE && !h->have_coarse)
+        return fail(h, NLS_ESTATE, "two-level coupling needs nls_build_coarse");
+    HIPCHK(hipSetDevice(h->opt.device));
+    Timer ttot;
+    nls_stats local{};
+    nls_stats* S = st ? st : &local;
+    std::memset(S, 0, sizeof(*S));
+    S->failed_subdomain = -1;
+    h->st = S;
+    const int N = h->mesh.N;
+    double* ud = u;
+    if (!u_on_device) {
+        ud = h->ubuf;
+        HIPCHK(hipMemcpyAsync(ud, u, sizeof(double) * N, hipMemcpyHostToDevice, h->stream));
+    }
+    auto finish = [&](int code) {
+        if (!u_on_device)
+            (void)hipMemcpyAsync(u, ud, sizeof(double) * N, hipMemcpyDeviceToHost, h->stream);
+        (void)hipStreamSynchronize(h->stream);
+        S->ms_total = ttot.ms();
+        S->ms_other = S->ms_total - S->ms_inner - S->ms_coarse - S->ms_gmres;
+        h->st = nullptr;
+        return code;
+    };
+    int rc = evaluate(h, ud, h->Fx);
+    if (rc) return finish(rc);
+    double r2 = 0.0;
+    rc = dot_host(h, h->Fx, h->Fx, N, &r2);
+    if (rc) return finish(rc);
+    const double r0 = std::sqrt(r2);
+    S->res0 = r0;
+    S->res_final = r0;
+    if (!std::isfinite(r0)) return finish(fail(h, NLS_ENAN, "F_x(u_0) is not finite"));
+    for (int k = 0;; ++k) {
+        if (S->res_final <= h->opt.outer_rtol * r0) {
+            S->converged = 1;
+            break;
+        }
+        if (k == h->opt.outer_maxit) break;
+        Timer tg;
+        int gits = 0;
+        rc = gmres(h, h->Fx, h->du, &gits);
+        S->ms_gmres += tg.ms();
+        if (rc) return finish(rc);
+        S->gmres_its[k] = gits;
+        S->gmres_its_total += gits;
+        rc = 0;
+        if (launch_axpy(-1.0, h->du, ud, N, h->stream) != hipSuccess)
+            return finish(fail(h, NLS_EHIP, "update failed"));
+        rc = evaluate(h, ud, h->Fx);
+        if (rc) return finish(rc);
+        S->outer_its = k + 1;
+        rc = dot_host(h, h->Fx, h->Fx, N, &r2);
+        if (rc) return finish(rc);
+        S->res_final = std::sqrt(r2);
+        if (!std::isfinite(S->res_final)) return finish(fail(h, NLS_ENAN, "F_x is not finite"));
+    }
+    return finish(S->converged ? NLS_OK : NLS_ENOCONV);
+}
+
+// ------------------------------------------------------------------- hooks
+extern "C" int nls_eval_residual(nls_handle* h, const double* u, double* F) {
+    if (!h || !u || !F) return NLS_EINVAL;
+    if (!h->have_part) return fail(h, NLS_ESTATE, "nls_set_partition first");
+    HIPCHK(hipSetDevice(h->opt.device));
+    HIPCHK(launch_global_residual(h->dm, u, F, h->stream));
+    return sync(h);
+}
+
+extern "C" int nls_eval_precond_residual(nls_handle* h, const double* u, double* Fx) {
+    if (!h || !u || !Fx) return NLS_EINVAL;
+    if (!h->have_part) return fail(h, NLS_ESTATE, "nls_set_partition first");
+    if (h->opt.coupling == NLS_ADDITIVE && !h->have_coarse)
+        return fail(h, NLS_ESTATE, "two-level coupling needs nls_build_coarse");
+    HIPCHK(hipSetDevice(h->opt.device));
+    RC(evaluate(h, u, Fx));
+    return sync(h);
+}
+
+extern "C" int nls_apply_tangent(nls_handle* h, const double* v, double* y) {
+    if (!h || !v || !y) return NLS_EINVAL;
+    if (!h->have_state) return fail(h, NLS_ESTATE, "no evaluated point (nls_eval_precond_residual)");
+    HIPCHK(hipSetDevice(h->opt.device));
+    RC(tangent(h, v, y));
+    return sync(h);
+}
+
+extern "C" int nls_get_inner_iterations(nls_handle* h, int32_t* its) {
+    if (!h || !its) return NLS_EINVAL;
+    if (!h->have_part) return fail(h, NLS_ESTATE, "nls_set_partition first");
+    for (int i = 0; i < h->maps.nsub; ++i) its[i] = h->its_h[i];
+    return NLS_OK;
+}
+
+extern "C" int nls_get_sizes(nls_handle* h, int32_t* n_sub, int32_t* n_coarse, int32_t* nv) {
+    if (!h) return NLS_EINVAL;
+    if (!h->have_part) return fail(h, NLS_ESTATE, "nls_set_partition first");
+    if (n_sub) *n_sub = h->maps.nsub;
+    if (n_coarse) *n_coarse = h->have_coarse ? h->co.n0 : 0;
+    if (nv)
+        for (int i = 0; i < h->maps.nsub; ++i) nv[i] = h->maps.off_n[i + 1] - h->maps.off_n[i];
+    return NLS_OK;
+}
+
+extern "C" int nls_get_coarse_basis(nls_handle* h, int64_t* nnz, int64_t* rowptr, int32_t* col,
+                                    double* val) {
+    if (!h || !nnz) return NLS_EINVAL;
+    if (!h->have_coarse) return fail(h, NLS_ESTATE, "nls_build_coarse first");
+    const HostCoarse& C = h->co;
+    const int N = h->mesh.N;
+    std::vector<double> phi(C.off_phi.back());
+    if (!phi.empty()) {
+        HIPCHK(hipMemcpyAsync(phi.data(), h->dc.phi, phi.size() * sizeof(double),
+                              hipMemcpyDeviceToHost, h->stream));
+        RC(sync(h));
+    }
+    // row g of Phi from the owner's block (the basis is single-valued)
+    int64_t cnt = 0;
+    std::vector<int64_t> rp(N + 1, 0);
+    for (int g = 0; g < N; ++g) {
+        const int o = C.cown[g];
+        const int nk = C.off_k[o + 1] - C.off_k[o];
+        const double* pr = phi.data() + C.off_phi[o] + (int64_t)(C.cpos[g] - C.off_c[o]) * nk;
+        for (int l = 0; l < nk; ++l)
+            if (pr[l] != 0.0) {
+                if (rowptr) {
+                    col[cnt] = C.klist[C.off_k[o] + l];
+                    val[cnt] = pr[l];
+                }
+                ++cnt;
+            }
+        rp[g + 1] = cnt;
+    }
+    if (rowptr && cnt > *nnz) return fail(h, NLS_EINVAL, "nnz buffer too small");
+    if (rowptr)
+        for (int g = 0; g <= N; ++g) rowptr[g] = rp[g];
+    *nnz = cnt;
+    return NLS_OK;
+}
+
+extern "C" const char* nls_strerror(int code) {
+    switch (code) {
+        case NLS_OK: return "success";
+        case NLS_ENOCONV: return "outer Newton iteration did not converge";
+        case NLS_EINVAL: return "invalid argument";
+        case NLS_EHIP: return "HIP runtime error";
+        case NLS_ENOMEM: return "device allocation failed";
+        case NLS_EPARTITION: return "invalid partition";
+        case NLS_ESINGULAR: return "zero pivot";
+        case NLS_ELOCAL: return "inner Newton iteration failed";
+        case NLS_ENAN: return "non-finite value";
+        case NLS_ESTATE: return "call out of order";
+        case NLS_ELIMIT: return "size exceeds a kernel limit";
+        default: return "unknown status";
+    }
+}
+
+extern "C" const char* nls_last_error(nls_handle* h) {
+    return h ? h->err.c_str() : "null handle";
+}

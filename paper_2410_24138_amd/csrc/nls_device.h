@@ -1,0 +1,125 @@
+// Device-side views (plain device pointers) shared by the solver driver and
+// the HIP kernels of libnls.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+// Global mesh and problem data, all resident in HBM.
+struct DevMesh {
+    int N, E;
+    const int* conn;            // 3E
+    const int* nptr;            // N+1: node -> incident elements
+    const int* nel;             // (element << 2) | vertex position
+    const double* G6;           // 6E: |T| grad(phi_a).grad(phi_b): G00 G11 G22 G01 G12 G20
+    const double* kappa;        // E
+    const double* eload;        // 3E: element load vectors
+    const double* bload;        // N: assembled load, 0 on Dirichlet rows
+    const unsigned char* dflag; // N
+    const double* dval;         // N
+    double beta;
+};
+
+// Overlapping-subdomain tables (see HostMaps).
+struct DevMaps {
+    int nsub;
+    const int *off_n, *off_g, *off_e, *l2g, *g2g, *pe_conn, *pe_gid;
+    const int *rinc_ptr, *rinc, *jptr, *jcol, *kl, *ku, *order, *own_pidx;
+    const int64_t *off_u, *off_l;
+};
+
+// Per-evaluation state of the local level.
+struct DevLocal {
+    double* jval;               // CSR values of [J_ii | B_i] at the current point
+    double* Uf;                 // FP64 factors (column-band U, column L)
+    double* Lf;
+    float* Uf32;                // FP32 factors (mixed precision)
+    float* Lf32;
+    int* piv;                   // packed, one per V row
+    double* xstar;              // packed converged local states
+    double* T;                  // packed T_i(u) = R_i u - x*
+    double* z;                  // packed scratch of the tangent
+    int* its;                   // per subdomain
+    int* status;                // per subdomain: 0 ok, 1 no convergence, 2 NaN, 3 zero pivot
+};
+
+struct NewtonParams {
+    double rtol;                // relative to ||R_i F(u)||
+    double abs_tol;             // eta * ||b||_inf (times sqrt(n_i) in the kernel)
+    double stagnation;
+    int maxit;
+    int mixed;                  // 1: FP32 LU + FP64 iterative refinement
+    int ir_maxit;
+    double ir_rtol;
+};
+
+// GDSW coarse space tables (see HostCoarse) and state.
+struct DevCoarse {
+    int n0, nsub;
+    const int *off_c, *cnode, *ctype, *off_k, *klist, *ccomp, *off_ne, *ne_conn, *ne_gid;
+    const int *cinc_ptr, *cinc, *iidx, *off_ni, *inode, *iptr, *icol, *ikl, *iku;
+    const int64_t *off_phi, *off_iu, *off_il, *off_kk;
+    const int *perm, *a0ptr, *a0col, *a0src_ptr, *a0src, *gsrc_ptr, *gsrc, *cpos, *cown;
+    int a0kl, a0ku;
+    double* phi;                // dense |C_i| x |K_i| blocks
+    double* zbuf;               // same shape: DF Phi rows (scratch)
+    double* ival;               // interior CSR values (setup scratch)
+    double* iU;                 // interior factors (setup scratch)
+    double* iL;
+    int* ipiv;
+    double* gblk;               // per-subdomain Phi_i^T q (packed by off_k)
+    double* ablk;               // per-subdomain Galerkin blocks (packed by off_kk)
+    double* a0val;              // CSR values of A0 (band order)
+    double* a0U;                // A0 factors
+    double* a0L;
+    int* a0piv;
+    double* rhs;                // n0, band order
+    double* c;                  // n0, coarse iterate (coarse id order)
+    double* w;                  // N: u - Phi c
+    double* scal;               // device scalars: [0] ||G||, [1] max|dc|, [2] max|c|
+    int* flag;                  // [0] zero pivot in the coarse/interior LU
+};
+
+// ---- launchers (kernels.hip) ------------------------------------------------
+hipError_t launch_p1_setup(const DevMesh& M, const double* xy, const double* elem_coef,
+                           const double* elem_load, double* G6, double* kappa,
+                           double* eload, int* bad, hipStream_t s);
+hipError_t launch_assemble_load(const DevMesh& M, double* bload, hipStream_t s);
+hipError_t launch_global_residual(const DevMesh& M, const double* u, double* F,
+                                  hipStream_t s);
+hipError_t launch_local_newton(const DevMesh& M, const DevMaps& P, const DevLocal& L,
+                               const NewtonParams& np, const double* u, int lds_bytes,
+                               int nb_per_lane, hipStream_t s);
+hipError_t launch_prolong(const DevMesh& M, const DevMaps& P, const double* T,
+                          const DevCoarse* C, const double* cvec, double* out,
+                          const double* addv, hipStream_t s);
+hipError_t launch_tangent_local(const DevMesh& M, const DevMaps& P, const DevLocal& L,
+                                const NewtonParams& np, const double* v, int lds_bytes,
+                                int nb_per_lane, hipStream_t s);
+hipError_t launch_gdsw_extend(const DevMesh& M, const DevCoarse& C, int lds_bytes,
+                              int nb_per_lane, hipStream_t s);
+hipError_t launch_coarse_w(const DevMesh& M, const DevCoarse& C, const double* u,
+                           double* w, hipStream_t s);
+hipError_t launch_coarse_q(const DevMesh& M, const DevCoarse& C, const double* w,
+                           const double* v, int mode, int lds_bytes, hipStream_t s);
+hipError_t launch_coarse_galerkin(const DevMesh& M, const DevCoarse& C, const double* w,
+                                  hipStream_t s);
+hipError_t launch_coarse_assemble(const DevCoarse& C, int with_matrix, hipStream_t s);
+hipError_t launch_coarse_lu(const DevCoarse& C, int factor, int lds_bytes, int nb_per_lane,
+                            hipStream_t s);
+hipError_t launch_coarse_update(const DevCoarse& C, hipStream_t s);
+hipError_t launch_coarse_scatter(const DevCoarse& C, double* cout, hipStream_t s);
+
+// vector kernels for GMRES (deterministic reductions)
+hipError_t launch_mdot(const double* V, int64_t ld, int m, const double* w, int n,
+                       double* partial, double* out, int nblocks, hipStream_t s);
+hipError_t launch_maxpy(const double* V, int64_t ld, int m, const double* h,
+                        double* w, int n, double sign, hipStream_t s);
+hipError_t launch_scale_by(const double* x, const double* denom_sq, double* y, int n,
+                           hipStream_t s);
+hipError_t launch_axpy(double a, const double* x, double* y, int n, hipStream_t s);
+hipError_t launch_add_inplace(const double* x, double* y, int n, hipStream_t s);
+hipError_t launch_max_abs(const double* x, int n, double* partial, double* out,
+                          int nblocks, hipStream_t s);
+hipError_t launch_any_status(const int* status, int n, int* out, hipStream_t s);

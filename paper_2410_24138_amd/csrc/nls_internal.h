@@ -1,0 +1,108 @@
+// Internal data structures of libnls shared by the host setup, the solver
+// driver and the HIP kernels.  Not part of the public ABI.
+#pragma once
+
+#include <algorithm>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+// Band-window size of the LU kernels: a ring buffer of (kl+1) rows by
+// (kl+ku+1) columns.
+inline int band_window_doubles(int kl, int ku) { return (kl + 1) * (kl + ku + 1); }
+// LDS of the fused local Newton kernel, in doubles:
+//   patch values (n + ng) | residual / step (n) | LU window | multipliers | scratch
+inline int local_lds_doubles(int n, int ng, int kl, int ku) {
+    return 2 * n + ng + band_window_doubles(kl, ku) + std::max(kl, 1) + 72;
+}
+// LDS of the interior (harmonic extension) kernel, in doubles.
+inline int interior_lds_doubles(int ni, int kl, int ku, int nk) {
+    (void)nk;
+    return ni + band_window_doubles(kl, ku) + std::max(kl, 1) + 72;
+}
+
+// ---------------------------------------------------------------- host side
+
+struct HostMesh {
+    int N = 0;                     // nodes
+    int E = 0;                     // triangles
+    std::vector<double> xy;        // 2N
+    std::vector<int> conn;         // 3E
+    std::vector<int> nptr, nel;    // node -> incident elements (CSR, ascending)
+    std::vector<unsigned char> dflag;  // N, 1 on Dirichlet nodes
+    std::vector<double> dval;      // N
+};
+
+// Overlapping subdomains and the tables the local kernels read.
+// "Packed" arrays concatenate the per-subdomain arrays in subdomain order.
+struct HostMaps {
+    int nsub = 0;
+    std::vector<int> off_n;        // nsub+1, offsets into packed V rows
+    std::vector<int> off_g;        // nsub+1, offsets into packed Gamma nodes
+    std::vector<int> off_e;        // nsub+1, offsets into packed patch elements
+    std::vector<int> l2g;          // packed V_i global node ids (ascending per subdomain)
+    std::vector<int> g2g;          // packed Gamma_i global node ids
+    std::vector<int> pe_conn;      // 3 per packed patch element, patch-local node ids
+                                   //   (< n_i: V_i position, else n_i + Gamma_i position)
+    std::vector<int> pe_gid;       // global element id of each packed patch element
+    std::vector<int> rinc_ptr;     // packed V row -> [rinc_ptr, rinc_ptr+1) in rinc
+    std::vector<int> rinc;         // (patch element local index << 2) | vertex position
+    std::vector<int> jptr;         // packed V row -> CSR slots (global over all rows)
+    std::vector<int> jcol;         // patch-local column of each slot (sorted per row)
+    std::vector<int> kl, ku;       // band widths of J_ii per subdomain
+    std::vector<int64_t> off_u;    // offset (doubles) of the U factor, n_i*(kl+ku+1)
+    std::vector<int64_t> off_l;    // offset (doubles) of the L factor, n_i*max(kl,1)
+    int64_t factor_u_total = 0, factor_l_total = 0;
+    std::vector<int> own_pidx;     // N: packed V row of the owner's copy of node g
+    std::vector<int> order;        // launch order of subdomains (largest first)
+    std::vector<int> lds_doubles;  // per subdomain LDS need of the local Newton kernel
+    int max_lds_doubles = 0;
+};
+
+// GDSW coarse space: symbolic part (host) plus the tables its kernels read.
+struct HostCoarse {
+    int n0 = 0;
+    std::vector<std::vector<int>> comps;   // interface components, by smallest node
+    std::vector<int> comp_of;              // N: component id or -1
+    // per non-overlapping subdomain i
+    std::vector<int> off_c;        // nsub+1: closure nodes (nodes of elements of part i)
+    std::vector<int> cnode;        // packed closure node global ids (ascending)
+    std::vector<int> ctype;        // 0 interior, 1 interface, 2 Dirichlet/other
+    std::vector<int> off_k;        // nsub+1: coarse functions touching subdomain i
+    std::vector<int> klist;        // packed coarse ids (ascending per subdomain)
+    std::vector<int> ccomp;        // packed closure: local position in K_i, or -1
+    std::vector<int64_t> off_phi;  // nsub+1: dense |C_i| x |K_i| blocks (row-major)
+    std::vector<int> off_ne;       // nsub+1: elements of part i
+    std::vector<int> ne_conn;      // 3 per element, closure-local node ids
+    std::vector<int> ne_gid;       // global element ids
+    std::vector<int> cinc_ptr;     // packed closure node -> incident part-i elements
+    std::vector<int> cinc;         // (element local index << 2) | vertex position
+    std::vector<int> iidx;         // packed closure: interior-local index or -1
+    std::vector<int> off_ni;       // nsub+1: interior rows
+    std::vector<int> inode;        // packed interior row -> closure-local index
+    std::vector<int> iptr, icol;   // interior CSR (interior-local columns)
+    std::vector<int> ikl, iku;     // band widths of A_II
+    std::vector<int64_t> off_iu, off_il;
+    int64_t iu_total = 0, il_total = 0;
+    std::vector<int> ilds_doubles; // LDS need of the extension kernel
+    int max_ilds_doubles = 0;
+    // Galerkin matrix A0 = Phi^T DF Phi in CSR over the banded ordering
+    std::vector<int> perm;         // coarse id -> band position
+    std::vector<int> a0ptr, a0col; // CSR in band positions
+    std::vector<int> a0src_ptr;    // slot -> [ptr, ptr+1) of a0src
+    std::vector<int> a0src;        // packed position in the per-subdomain blocks
+    std::vector<int64_t> off_kk;   // nsub+1: offsets of the |K_i|^2 blocks
+    std::vector<int> gsrc_ptr;     // coarse id -> contributions to Phi^T q
+    std::vector<int> gsrc;         // packed position in the per-subdomain vectors
+    int a0kl = 0, a0ku = 0;
+    std::vector<int> cpos;         // N: packed closure index in the owner's block
+    std::vector<int> cown;         // N: owner subdomain
+    int max_k = 0;
+};
+
+// Setup entry points (setup.cpp).  Return 0 or an NLS_* error with err set.
+int nls_build_node_incidence(HostMesh& m, std::string& err);
+int nls_build_maps(const HostMesh& m, const int* part, int nsub, int overlap,
+                   HostMaps& out, std::string& err);
+int nls_build_coarse_symbolic(const HostMesh& m, const int* part, int nsub,
+                              HostCoarse& out, std::string& err);

@@ -1,0 +1,534 @@
+// Host-side setup of libnls: overlapping subdomains, local orderings and
+// band widths, restricted-prolongation owners, and the symbolic part of the
+// GDSW coarse space.  Integer work only; every floating-point step of the
+// method runs in the HIP kernels.
+//
+// Overlap (paper, Section 2, last paragraph): the overlapping partition is
+// element based so that each subdomain assembles its own residual and
+// tangent.  Each subdomain's element set is grown by `overlap` layers of
+// elements that share a node with it.  V_i holds the patch nodes whose
+// every element lies in the patch (so R_i F can be assembled from patch
+// elements alone); the remaining patch nodes Gamma_i carry the current
+// global values.  Restricted prolongation P~_i (eq. 8): node g belongs to
+// the largest subdomain id among its elements.
+#include <algorithm>
+#include <cstdlib>
+#include <map>
+#include <numeric>
+#include <queue>
+
+#include "nls.h"
+#include "nls_internal.h"
+
+int nls_build_node_incidence(HostMesh& m, std::string& err) {
+    m.nptr.assign(m.N + 1, 0);
+    for (int e = 0; e < m.E; ++e)
+        for (int v = 0; v < 3; ++v) {
+            int g = m.conn[3 * e + v];
+            if (g < 0 || g >= m.N) {
+                err = "element node index out of range";
+                return NLS_EINVAL;
+            }
+            m.nptr[g + 1]++;
+        }
+    for (int g = 0; g < m.N; ++g) m.nptr[g + 1] += m.nptr[g];
+    m.nel.assign(m.nptr[m.N], 0);
+    std::vector<int> fill(m.nptr.begin(), m.nptr.end() - 1);
+    for (int e = 0; e < m.E; ++e)
+        for (int v = 0; v < 3; ++v) m.nel[fill[m.conn[3 * e + v]]++] = e;
+    return NLS_OK;
+}
+
+static inline int vertex_pos(const HostMesh& m, int e, int g) {
+    for (int v = 0; v < 3; ++v)
+        if (m.conn[3 * e + v] == g) return v;
+    return -1;
+}
+
+int nls_build_maps(const HostMesh& m, const int* part, int nsub, int overlap,
+                   HostMaps& out, std::string& err) {
+    const int N = m.N, E = m.E;
+    if (nsub <= 0 || overlap < 1) {
+        err = "need n_sub >= 1 and overlap >= 1 (owned nodes must lie in V_i)";
+        return NLS_EPARTITION;
+    }
+    std::vector<std::vector<int>> elems_of(nsub);
+    for (int e = 0; e < E; ++e) {
+        if (part[e] < 0 || part[e] >= nsub) {
+            err = "elem_part entry out of range";
+            return NLS_EINVAL;
+        }
+        elems_of[part[e]].push_back(e);
+    }
+    for (int i = 0; i < nsub; ++i)
+        if (elems_of[i].empty()) {
+            err = "subdomain " + std::to_string(i) + " is empty";
+            return NLS_EPARTITION;
+        }
+    std::vector<int> owner(N, -1);
+    for (int e = 0; e < E; ++e)
+        for (int v = 0; v < 3; ++v) {
+            int g = m.conn[3 * e + v];
+            owner[g] = std::max(owner[g], part[e]);
+        }
+
+    HostMaps& M = out;
+    M = HostMaps();
+    M.nsub = nsub;
+    M.off_n.assign(1, 0);
+    M.off_g.assign(1, 0);
+    M.off_e.assign(1, 0);
+    M.rinc_ptr.assign(1, 0);
+    M.jptr.assign(1, 0);
+    std::vector<char> inpatch(E, 0), nmark(N, 0);
+    std::vector<int> cnt(N, 0), loc(N, -1), eloc(E, -1);
+
+    for (int i = 0; i < nsub; ++i) {
+        std::vector<int> pe = elems_of[i];
+        for (int e : pe) inpatch[e] = 1;
+        for (int layer = 0; layer < overlap; ++layer) {
+            std::vector<int> nodes;
+            for (int e : pe)
+                for (int v = 0; v < 3; ++v) {
+                    int g = m.conn[3 * e + v];
+                    if (!nmark[g]) { nmark[g] = 1; nodes.push_back(g); }
+                }
+            std::vector<int> add;
+            for (int g : nodes) {
+                nmark[g] = 0;
+                for (int k = m.nptr[g]; k < m.nptr[g + 1]; ++k) {
+                    int e = m.nel[k];
+                    if (!inpatch[e]) { inpatch[e] = 1; add.push_back(e); }
+                }
+            }
+            pe.insert(pe.end(), add.begin(), add.end());
+        }
+        std::sort(pe.begin(), pe.end());
+        std::vector<int> pnodes;
+        for (int e : pe)
+            for (int v = 0; v < 3; ++v) {
+                int g = m.conn[3 * e + v];
+                if (cnt[g]++ == 0) pnodes.push_back(g);
+            }
+        std::vector<int> V, G;
+        for (int g : pnodes) {
+            if (cnt[g] == m.nptr[g + 1] - m.nptr[g]) V.push_back(g);
+            else G.push_back(g);
+        }
+        std::sort(V.begin(), V.end());
+        std::sort(G.begin(), G.end());
+        const int n = (int)V.size();
+        for (int a = 0; a < n; ++a) loc[V[a]] = a;
+        for (int j = 0; j < (int)G.size(); ++j) loc[G[j]] = n + j;
+        for (int k = 0; k < (int)pe.size(); ++k) eloc[pe[k]] = k;
+        for (int e : pe) {
+            for (int v = 0; v < 3; ++v) M.pe_conn.push_back(loc[m.conn[3 * e + v]]);
+            M.pe_gid.push_back(e);
+        }
+        int kl = 0, ku = 0;
+        std::vector<int> cols;
+        for (int a = 0; a < n; ++a) {
+            int g = V[a];
+            cols.clear();
+            for (int k = m.nptr[g]; k < m.nptr[g + 1]; ++k) {
+                int e = m.nel[k];
+                M.rinc.push_back((eloc[e] << 2) | vertex_pos(m, e, g));
+                for (int v = 0; v < 3; ++v) cols.push_back(loc[m.conn[3 * e + v]]);
+            }
+            std::sort(cols.begin(), cols.end());
+            cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+            for (int c : cols) {
+                M.jcol.push_back(c);
+                if (c < n) {
+                    kl = std::max(kl, a - c);
+                    ku = std::max(ku, c - a);
+                }
+            }
+            M.rinc_ptr.push_back((int)M.rinc.size());
+            M.jptr.push_back((int)M.jcol.size());
+        }
+        M.l2g.insert(M.l2g.end(), V.begin(), V.end());
+        M.g2g.insert(M.g2g.end(), G.begin(), G.end());
+        M.off_n.push_back((int)M.l2g.size());
+        M.off_g.push_back((int)M.g2g.size());
+        M.off_e.push_back((int)M.pe_gid.size());
+        M.kl.push_back(kl);
+        M.ku.push_back(ku);
+        for (int g : pnodes) { cnt[g] = 0; loc[g] = -1; }
+        for (int e : pe) { eloc[e] = -1; inpatch[e] = 0; }
+    }
+
+    // owners: the owned nodes of subdomain o must lie in V_o
+    M.own_pidx.assign(N, -1);
+    for (int g = 0; g < N; ++g) {
+        int o = owner[g];
+        if (o < 0) {
+            err = "node " + std::to_string(g) + " belongs to no element";
+            return NLS_EINVAL;
+        }
+        auto b = M.l2g.begin() + M.off_n[o], en = M.l2g.begin() + M.off_n[o + 1];
+        auto it = std::lower_bound(b, en, g);
+        if (it == en || *it != g) {
+            err = "subdomain " + std::to_string(o) + ": owned node " +
+                  std::to_string(g) + " not in V_i";
+            return NLS_EPARTITION;
+        }
+        M.own_pidx[g] = (int)(it - M.l2g.begin());
+    }
+
+    // factor storage and launch order
+    M.off_u.assign(nsub + 1, 0);
+    M.off_l.assign(nsub + 1, 0);
+    M.lds_doubles.assign(nsub, 0);
+    for (int i = 0; i < nsub; ++i) {
+        int64_t n = M.off_n[i + 1] - M.off_n[i];
+        int ng = M.off_g[i + 1] - M.off_g[i];
+        M.off_u[i + 1] = M.off_u[i] + n * (M.kl[i] + M.ku[i] + 1);
+        M.off_l[i + 1] = M.off_l[i] + n * std::max(M.kl[i], 1);
+        M.lds_doubles[i] = local_lds_doubles((int)n, ng, M.kl[i], M.ku[i]);
+        M.max_lds_doubles = std::max(M.max_lds_doubles, M.lds_doubles[i]);
+    }
+    M.factor_u_total = M.off_u[nsub];
+    M.factor_l_total = M.off_l[nsub];
+    M.order.resize(nsub);
+    std::iota(M.order.begin(), M.order.end(), 0);
+    std::stable_sort(M.order.begin(), M.order.end(), [&](int a, int b) {
+        return M.lds_doubles[a] > M.lds_doubles[b];
+    });
+    return NLS_OK;
+}
+
+// Reverse Cuthill-McKee ordering of a symmetric pattern (adjacency lists).
+static std::vector<int> rcm_order(const std::vector<std::vector<int>>& adj) {
+    const int n = (int)adj.size();
+    std::vector<int> order, deg(n);
+    for (int i = 0; i < n; ++i) deg[i] = (int)adj[i].size();
+    std::vector<char> seen(n, 0);
+    std::vector<int> byDeg(n);
+    std::iota(byDeg.begin(), byDeg.end(), 0);
+    std::stable_sort(byDeg.begin(), byDeg.end(),
+                     [&](int a, int b) { return deg[a] < deg[b]; });
+    for (int s : byDeg) {
+        if (seen[s]) continue;
+        std::queue<int> q;
+        q.push(s);
+        seen[s] = 1;
+        while (!q.empty()) {
+            int v = q.front();
+            q.pop();
+            order.push_back(v);
+            std::vector<int> nb;
+            for (int w : adj[v])
+                if (!seen[w]) { seen[w] = 1; nb.push_back(w); }
+            std::stable_sort(nb.begin(), nb.end(),
+                             [&](int a, int b) { return deg[a] < deg[b]; });
+            for (int w : nb) q.push(w);
+        }
+    }
+    std::reverse(order.begin(), order.end());
+    return order;  // order[p] = vertex at position p
+}
+
+int nls_build_coarse_symbolic(const HostMesh& m, const int* part, int nsub,
+                              HostCoarse& out, std::string& err) {
+    const int N = m.N, E = m.E;
+    HostCoarse& C = out;
+    C = HostCoarse();
+    // subdomain sets of every node
+    std::vector<std::vector<int>> sset(N);
+    for (int g = 0; g < N; ++g) {
+        for (int k = m.nptr[g]; k < m.nptr[g + 1]; ++k) sset[g].push_back(part[m.nel[k]]);
+        std::sort(sset[g].begin(), sset[g].end());
+        sset[g].erase(std::unique(sset[g].begin(), sset[g].end()), sset[g].end());
+    }
+    std::vector<char> iface(N, 0);
+    for (int g = 0; g < N; ++g) iface[g] = sset[g].size() >= 2 && !m.dflag[g];
+    // classes keyed by the subdomain set, split into connected components
+    std::map<std::vector<int>, int> key_id;
+    std::vector<int> cls(N, -1);
+    for (int g = 0; g < N; ++g)
+        if (iface[g]) {
+            auto it = key_id.find(sset[g]);
+            if (it == key_id.end()) it = key_id.emplace(sset[g], (int)key_id.size()).first;
+            cls[g] = it->second;
+        }
+    C.comp_of.assign(N, -1);
+    std::vector<std::vector<int>> comps;
+    for (int g = 0; g < N; ++g) {
+        if (cls[g] < 0 || C.comp_of[g] >= 0) continue;
+        int cid = (int)comps.size();
+        comps.emplace_back();
+        std::queue<int> q;
+        q.push(g);
+        C.comp_of[g] = cid;
+        while (!q.empty()) {
+            int v = q.front();
+            q.pop();
+            comps[cid].push_back(v);
+            for (int k = m.nptr[v]; k < m.nptr[v + 1]; ++k) {
+                int e = m.nel[k];
+                for (int t = 0; t < 3; ++t) {
+                    int w = m.conn[3 * e + t];
+                    if (cls[w] == cls[g] && C.comp_of[w] < 0) {
+                        C.comp_of[w] = cid;
+                        q.push(w);
+                    }
+                }
+            }
+        }
+        std::sort(comps[cid].begin(), comps[cid].end());
+    }
+    // order components by their smallest node (canonical)
+    std::vector<int> cperm(comps.size());
+    std::iota(cperm.begin(), cperm.end(), 0);
+    std::sort(cperm.begin(), cperm.end(),
+              [&](int a, int b) { return comps[a][0] < comps[b][0]; });
+    std::vector<int> rank(comps.size());
+    for (int r = 0; r < (int)cperm.size(); ++r) rank[cperm[r]] = r;
+    C.comps.resize(comps.size());
+    for (int c = 0; c < (int)comps.size(); ++c) C.comps[rank[c]] = comps[c];
+    for (int g = 0; g < N; ++g)
+        if (C.comp_of[g] >= 0) C.comp_of[g] = rank[C.comp_of[g]];
+    C.n0 = (int)C.comps.size();
+
+    std::vector<std::vector<int>> elems_of(nsub);
+    for (int e = 0; e < E; ++e) elems_of[part[e]].push_back(e);
+
+    C.off_c.assign(1, 0);
+    C.off_k.assign(1, 0);
+    C.off_phi.assign(1, 0);
+    C.off_ne.assign(1, 0);
+    C.off_ni.assign(1, 0);
+    C.cinc_ptr.assign(1, 0);
+    C.iptr.assign(1, 0);
+    C.off_iu.assign(1, 0);
+    C.off_il.assign(1, 0);
+    C.off_kk.assign(1, 0);
+    std::vector<int> cl(N, -1), el(E, -1);
+    for (int i = 0; i < nsub; ++i) {
+        std::vector<int> nodes;
+        for (int e : elems_of[i])
+            for (int v = 0; v < 3; ++v) nodes.push_back(m.conn[3 * e + v]);
+        std::sort(nodes.begin(), nodes.end());
+        nodes.erase(std::unique(nodes.begin(), nodes.end()), nodes.end());
+        for (int a = 0; a < (int)nodes.size(); ++a) cl[nodes[a]] = a;
+        for (int k = 0; k < (int)elems_of[i].size(); ++k) el[elems_of[i][k]] = k;
+        std::vector<int> K;
+        for (int g : nodes)
+            if (iface[g]) K.push_back(C.comp_of[g]);
+        std::sort(K.begin(), K.end());
+        K.erase(std::unique(K.begin(), K.end()), K.end());
+        C.max_k = std::max(C.max_k, (int)K.size());
+        int ni = 0;
+        std::vector<int> inter;
+        for (int a = 0; a < (int)nodes.size(); ++a) {
+            int g = nodes[a];
+            int t = m.dflag[g] ? 2 : (iface[g] ? 1 : (sset[g].size() == 1 ? 0 : 2));
+            C.cnode.push_back(g);
+            C.ctype.push_back(t);
+            int kp = -1;
+            if (t == 1)
+                kp = (int)(std::lower_bound(K.begin(), K.end(), C.comp_of[g]) - K.begin());
+            C.ccomp.push_back(kp);
+            C.iidx.push_back(t == 0 ? ni : -1);
+            if (t == 0) { inter.push_back(a); ++ni; }
+            for (int k = m.nptr[g]; k < m.nptr[g + 1]; ++k) {
+                int e = m.nel[k];
+                if (part[e] == i) C.cinc.push_back((el[e] << 2) | vertex_pos(m, e, g));
+            }
+            C.cinc_ptr.push_back((int)C.cinc.size());
+        }
+        for (int e : elems_of[i]) {
+            for (int v = 0; v < 3; ++v) C.ne_conn.push_back(cl[m.conn[3 * e + v]]);
+            C.ne_gid.push_back(e);
+        }
+        // interior CSR and band of A_II
+        int kl = 0, ku = 0;
+        const int cbase = C.off_c.back();
+        std::vector<int> cols;
+        for (int r = 0; r < ni; ++r) {
+            int g = nodes[inter[r]];
+            cols.clear();
+            for (int k = m.nptr[g]; k < m.nptr[g + 1]; ++k) {
+                int e = m.nel[k];
+                for (int v = 0; v < 3; ++v) {
+                    int c = C.iidx[cbase + cl[m.conn[3 * e + v]]];
+                    if (c >= 0) cols.push_back(c);
+                }
+            }
+            std::sort(cols.begin(), cols.end());
+            cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+            for (int c : cols) {
+                C.icol.push_back(c);
+                kl = std::max(kl, r - c);
+                ku = std::max(ku, c - r);
+            }
+            C.iptr.push_back((int)C.icol.size());
+            C.inode.push_back(inter[r]);
+        }
+        C.ikl.push_back(kl);
+        C.iku.push_back(ku);
+        C.off_iu.push_back(C.off_iu.back() + (int64_t)ni * (kl + ku + 1));
+        C.off_il.push_back(C.off_il.back() + (int64_t)ni * std::max(kl, 1));
+        int ld = interior_lds_doubles(ni, kl, ku, (int)K.size());
+        C.ilds_doubles.push_back(ld);
+        C.max_ilds_doubles = std::max(C.max_ilds_doubles, ld);
+        C.klist.insert(C.klist.end(), K.begin(), K.end());
+        C.off_c.push_back((int)C.cnode.size());
+        C.off_k.push_back((int)C.klist.size());
+        C.off_phi.push_back(C.off_phi.back() + (int64_t)nodes.size() * K.size());
+        C.off_ne.push_back((int)C.ne_gid.size());
+        C.off_ni.push_back((int)C.inode.size());
+        C.off_kk.push_back(C.off_kk.back() + (int64_t)K.size() * K.size());
+        for (int g : nodes) cl[g] = -1;
+        for (int e : elems_of[i]) el[e] = -1;
+    }
+    C.iu_total = C.off_iu.back();
+    C.il_total = C.off_il.back();
+
+    // owner closure positions for prolongation of coarse vectors
+    C.cpos.assign(N, -1);
+    C.cown.assign(N, -1);
+    for (int g = 0; g < N; ++g) {
+        int o = -1;
+        for (int k = m.nptr[g]; k < m.nptr[g + 1]; ++k) o = std::max(o, part[m.nel[k]]);
+        auto b = C.cnode.begin() + C.off_c[o], en = C.cnode.begin() + C.off_c[o + 1];
+        auto it = std::lower_bound(b, en, g);
+        C.cown[g] = o;
+        C.cpos[g] = (int)(it - C.cnode.begin());
+    }
+
+    // Galerkin pattern, banded ordering and deterministic source lists
+    const int n0 = C.n0;
+    std::vector<std::vector<int>> adj(n0);
+    std::map<std::pair<int, int>, std::vector<int>> src;
+    std::vector<std::vector<int>> gs(n0);
+    for (int i = 0; i < nsub; ++i) {
+        int k0 = C.off_k[i], nk = C.off_k[i + 1] - k0;
+        for (int p = 0; p < nk; ++p) {
+            int kp = C.klist[k0 + p];
+            gs[kp].push_back(k0 + p);
+            for (int q = 0; q < nk; ++q) {
+                int kq = C.klist[k0 + q];
+                src[{kp, kq}].push_back((int)(C.off_kk[i] + (int64_t)p * nk + q));
+                if (kp != kq) adj[kp].push_back(kq);
+            }
+        }
+    }
+    for (auto& a : adj) {
+        std::sort(a.begin(), a.end());
+        a.erase(std::unique(a.begin(), a.end()), a.end());
+    }
+    // banded ordering of A0: reverse Cuthill-McKee, or the canonical order
+    // (components by smallest node) when that is narrower
+    std::vector<int> ord = n0 ? rcm_order(adj) : std::vector<int>();
+    std::vector<int> prcm(n0), pnat(n0);
+    for (int p = 0; p < n0; ++p) { prcm[ord[p]] = p; pnat[p] = p; }
+    auto width = [&](const std::vector<int>& pm) {
+        int w = 0;
+        for (int k = 0; k < n0; ++k)
+            for (int l : adj[k]) w = std::max(w, std::abs(pm[k] - pm[l]));
+        return w;
+    };
+    C.perm = width(prcm) < width(pnat) ? prcm : pnat;
+    std::vector<std::vector<std::pair<int, std::vector<int>*>>> rows(n0);
+    for (auto& kv : src) {
+        int r = C.perm[kv.first.first], c = C.perm[kv.first.second];
+        rows[r].push_back({c, &kv.second});
+        C.a0kl = std::max(C.a0kl, r - c);
+        C.a0ku = std::max(C.a0ku, c - r);
+    }
+    C.a0ptr.assign(1, 0);
+    C.a0src_ptr.assign(1, 0);
+    for (int r = 0; r < n0; ++r) {
+        std::sort(rows[r].begin(), rows[r].end(),
+                  [](const auto& a, const auto& b) { return a.first < b.first; });
+        for (auto& e : rows[r]) {
+            C.a0col.push_back(e.first);
+            C.a0src.insert(C.a0src.end(), e.second->begin(), e.second->end());
+            C.a0src_ptr.push_back((int)C.a0src.size());
+        }
+        C.a0ptr.push_back((int)C.a0col.size());
+    }
+    C.gsrc_ptr.assign(1, 0);
+    for (int k = 0; k < n0; ++k) {
+        C.gsrc.insert(C.gsrc.end(), gs[k].begin(), gs[k].end());
+        C.gsrc_ptr.push_back((int)C.gsrc.size());
+    }
+    (void)err;
+    return NLS_OK;
+}
+
+// ---------------------------------------------------------------- inspection
+static int inspect_mesh(int64_t n_nodes, int64_t n_elems, const int32_t* conn, HostMesh& m,
+                        std::string& err) {
+    if (n_nodes <= 0 || n_elems <= 0 || !conn) return NLS_EINVAL;
+    m.N = (int)n_nodes;
+    m.E = (int)n_elems;
+    m.conn.assign(conn, conn + 3 * n_elems);
+    m.dflag.assign(m.N, 0);
+    m.dval.assign(m.N, 0.0);
+    return nls_build_node_incidence(m, err);
+}
+
+extern "C" int nls_inspect_partition(int64_t n_nodes, int64_t n_elems, const int32_t* conn,
+                                     int32_t n_sub, const int32_t* elem_part, int32_t overlap,
+                                     int64_t* counts, int32_t* off_v, int32_t* v_nodes,
+                                     int32_t* off_g, int32_t* g_nodes, int32_t* own_pos,
+                                     int32_t* kl, int32_t* ku) {
+    HostMesh m;
+    std::string err;
+    if (!elem_part) return NLS_EINVAL;
+    int rc = inspect_mesh(n_nodes, n_elems, conn, m, err);
+    if (rc) return rc;
+    HostMaps M;
+    rc = nls_build_maps(m, elem_part, n_sub, overlap, M, err);
+    if (rc) return rc;
+    if (counts) {
+        counts[0] = (int64_t)M.l2g.size();
+        counts[1] = (int64_t)M.g2g.size();
+    }
+    if (off_v) std::copy(M.off_n.begin(), M.off_n.end(), off_v);
+    if (off_g) std::copy(M.off_g.begin(), M.off_g.end(), off_g);
+    if (v_nodes) std::copy(M.l2g.begin(), M.l2g.end(), v_nodes);
+    if (g_nodes) std::copy(M.g2g.begin(), M.g2g.end(), g_nodes);
+    if (own_pos) std::copy(M.own_pidx.begin(), M.own_pidx.end(), own_pos);
+    if (kl) std::copy(M.kl.begin(), M.kl.end(), kl);
+    if (ku) std::copy(M.ku.begin(), M.ku.end(), ku);
+    return NLS_OK;
+}
+
+extern "C" int nls_inspect_coarse(int64_t n_nodes, int64_t n_elems, const int32_t* conn,
+                                  int32_t n_sub, const int32_t* elem_part, int64_t n_dir,
+                                  const int64_t* dirichlet, int64_t* counts, int32_t* comp_off,
+                                  int32_t* comp_nodes) {
+    HostMesh m;
+    std::string err;
+    if (!elem_part || n_sub <= 0 || n_dir < 0 || (n_dir > 0 && !dirichlet)) return NLS_EINVAL;
+    int rc = inspect_mesh(n_nodes, n_elems, conn, m, err);
+    if (rc) return rc;
+    for (int64_t k = 0; k < n_dir; ++k) {
+        if (dirichlet[k] < 0 || dirichlet[k] >= n_nodes) return NLS_EINVAL;
+        m.dflag[dirichlet[k]] = 1;
+    }
+    for (int64_t e = 0; e < n_elems; ++e)
+        if (elem_part[e] < 0 || elem_part[e] >= n_sub) return NLS_EINVAL;
+    HostCoarse C;
+    rc = nls_build_coarse_symbolic(m, elem_part, n_sub, C, err);
+    if (rc) return rc;
+    int64_t tot = 0;
+    for (auto& c : C.comps) tot += (int64_t)c.size();
+    if (counts) {
+        counts[0] = C.n0;
+        counts[1] = tot;
+    }
+    if (comp_off && comp_nodes) {
+        int64_t p = 0;
+        comp_off[0] = 0;
+        for (int k = 0; k < C.n0; ++k) {
+            for (int g : C.comps[k]) comp_nodes[p++] = g;
+            comp_off[k + 1] = (int32_t)p;
+        }
+    }
+    return NLS_OK;
+}

@@ -1,0 +1,330 @@
+"""ctypes binding of libnls (the C ABI declared in include/nls.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library.
+PyTorch supplies device memory (tensors) and the stream.  The binding fails
+loudly when libnls.so has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnls.so")
+
+NLS_OK = 0
+NLS_ENOCONV = 1
+NLS_EINVAL = -1
+NLS_EHIP = -2
+NLS_ENOMEM = -3
+NLS_EPARTITION = -4
+NLS_ESINGULAR = -5
+NLS_ELOCAL = -6
+NLS_ENAN = -7
+NLS_ESTATE = -8
+NLS_ELIMIT = -9
+
+ELEM_P1_TRI = 3
+PROBLEM_DIFFUSION = 1
+PREC_FP64 = 0
+PREC_FP32_IR = 1
+ONE_LEVEL = 0
+ADDITIVE = 1
+COARSE_NONE = 0
+COARSE_GDSW = 1
+MAX_OUTER = 64
+
+# every symbol include/nls.h declares
+SYMBOLS = (
+    "nls_default_options", "nls_create", "nls_destroy", "nls_set_mesh",
+    "nls_set_problem", "nls_set_dirichlet", "nls_set_partition",
+    "nls_build_coarse", "nls_solve", "nls_eval_residual",
+    "nls_eval_precond_residual", "nls_apply_tangent",
+    "nls_get_inner_iterations", "nls_get_sizes", "nls_get_coarse_basis",
+    "nls_strerror", "nls_last_error", "nls_inspect_partition",
+    "nls_inspect_coarse",
+)
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("device", ctypes.c_int), ("stream", ctypes.c_void_p),
+        ("precision", ctypes.c_int), ("coupling", ctypes.c_int),
+        ("outer_rtol", ctypes.c_double), ("outer_maxit", ctypes.c_int),
+        ("inner_rtol", ctypes.c_double), ("inner_eta", ctypes.c_double),
+        ("stagnation", ctypes.c_double), ("inner_maxit", ctypes.c_int),
+        ("gmres_rtol", ctypes.c_double), ("gmres_maxit", ctypes.c_int),
+        ("gmres_restart", ctypes.c_int), ("flags", ctypes.c_int),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("converged", ctypes.c_int), ("outer_its", ctypes.c_int),
+        ("gmres_its", ctypes.c_int * MAX_OUTER), ("gmres_its_total", ctypes.c_int),
+        ("inner_its_total", ctypes.c_int64), ("inner_its_max", ctypes.c_int),
+        ("local_solves", ctypes.c_int64), ("coarse_its_total", ctypes.c_int),
+        ("failed_subdomain", ctypes.c_int), ("res0", ctypes.c_double),
+        ("res_final", ctypes.c_double), ("ms_inner", ctypes.c_double),
+        ("ms_coarse", ctypes.c_double), ("ms_gmres", ctypes.c_double),
+        ("ms_other", ctypes.c_double), ("ms_total", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "gmres_its"}
+        d["gmres_its"] = list(self.gmres_its[: self.outer_its])
+        return d
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libnls.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2410_24138_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "nls_default_options": ([ctypes.POINTER(Options)], ctypes.c_int),
+        "nls_create": ([ctypes.POINTER(Options), ctypes.POINTER(P)], ctypes.c_int),
+        "nls_destroy": ([P], ctypes.c_int),
+        "nls_set_mesh": ([P, ctypes.c_int, i64, P, i64, P], ctypes.c_int),
+        "nls_set_problem": ([P, ctypes.c_int, P, P, P], ctypes.c_int),
+        "nls_set_dirichlet": ([P, i64, P, P], ctypes.c_int),
+        "nls_set_partition": ([P, i32, P, i32], ctypes.c_int),
+        "nls_build_coarse": ([P, ctypes.c_int], ctypes.c_int),
+        "nls_solve": ([P, P, ctypes.c_int, ctypes.POINTER(Stats)], ctypes.c_int),
+        "nls_eval_residual": ([P, P, P], ctypes.c_int),
+        "nls_eval_precond_residual": ([P, P, P], ctypes.c_int),
+        "nls_apply_tangent": ([P, P, P], ctypes.c_int),
+        "nls_get_inner_iterations": ([P, P], ctypes.c_int),
+        "nls_get_sizes": ([P, P, P, P], ctypes.c_int),
+        "nls_get_coarse_basis": ([P, ctypes.POINTER(i64), P, P, P], ctypes.c_int),
+        "nls_strerror": ([ctypes.c_int], ctypes.c_char_p),
+        "nls_inspect_partition": ([i64, i64, P, i32, P, i32, P, P, P, P, P, P, P, P],
+                                  ctypes.c_int),
+        "nls_inspect_coarse": ([i64, i64, P, i32, P, i64, P, P, P, P], ctypes.c_int),
+        "nls_last_error": ([P], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _ = dbl
+    _lib = lib
+    return lib
+
+
+class NLSError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libnls error {code}: {msg}")
+        self.code = code
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def inspect_partition(case: dict):
+    """Host-only: the subdomain maps libnls builds for a case (no device)."""
+    lib = load()
+    conn = np.ascontiguousarray(case["conn"], dtype=np.int32)
+    part = np.ascontiguousarray(case["elem_part"], dtype=np.int32)
+    N, E, ns, ov = len(case["xy"]), len(conn), int(case["n_sub"]), int(case["overlap"])
+    cnt = np.zeros(2, dtype=np.int64)
+    args = (N, E, _ptr(conn), ns, _ptr(part), ov)
+    rc = lib.nls_inspect_partition(*args, _ptr(cnt), None, None, None, None, None, None, None)
+    if rc:
+        raise NLSError(rc, lib.nls_strerror(rc).decode())
+    off_v = np.zeros(ns + 1, np.int32)
+    off_g = np.zeros(ns + 1, np.int32)
+    v = np.zeros(cnt[0], np.int32)
+    g = np.zeros(cnt[1], np.int32)
+    own = np.zeros(N, np.int32)
+    kl = np.zeros(ns, np.int32)
+    ku = np.zeros(ns, np.int32)
+    rc = lib.nls_inspect_partition(*args, _ptr(cnt), _ptr(off_v), _ptr(v), _ptr(off_g),
+                                   _ptr(g), _ptr(own), _ptr(kl), _ptr(ku))
+    if rc:
+        raise NLSError(rc, lib.nls_strerror(rc).decode())
+    return {"off_v": off_v, "v": v, "off_g": off_g, "g": g, "own_pos": own,
+            "kl": kl, "ku": ku}
+
+
+def inspect_coarse(case: dict):
+    """Host-only: the GDSW interface components libnls builds for a case."""
+    lib = load()
+    conn = np.ascontiguousarray(case["conn"], dtype=np.int32)
+    part = np.ascontiguousarray(case["elem_part"], dtype=np.int32)
+    dn = np.ascontiguousarray(case["dirichlet"], dtype=np.int64)
+    N, E, ns = len(case["xy"]), len(conn), int(case["n_sub"])
+    cnt = np.zeros(2, dtype=np.int64)
+    args = (N, E, _ptr(conn), ns, _ptr(part), len(dn), _ptr(dn))
+    rc = lib.nls_inspect_coarse(*args, _ptr(cnt), None, None)
+    if rc:
+        raise NLSError(rc, lib.nls_strerror(rc).decode())
+    off = np.zeros(cnt[0] + 1, np.int32)
+    nodes = np.zeros(cnt[1], np.int32)
+    rc = lib.nls_inspect_coarse(*args, _ptr(cnt), _ptr(off), _ptr(nodes))
+    if rc:
+        raise NLSError(rc, lib.nls_strerror(rc).decode())
+    return [nodes[off[k]:off[k + 1]] for k in range(cnt[0])]
+
+
+def default_options() -> Options:
+    o = Options()
+    load().nls_default_options(ctypes.byref(o))
+    return o
+
+
+class Solver:
+    """One libnls handle set up for an input case (see synth.diffusion_case).
+
+    coupling: "one_level" or "additive"; precision: "fp64" or "fp32_ir".
+    Options not given keep the library defaults.
+    """
+
+    def __init__(self, case: dict, coupling: Optional[str] = None,
+                 precision: str = "fp64", device: int = 0, stream=None,
+                 **opts):
+        import torch
+        self.lib = load()
+        self.torch = torch
+        self.device = torch.device("cuda", device)
+        o = default_options()
+        o.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+        o.stream = ctypes.c_void_p(int(stream))
+        if coupling is None:
+            coupling = "additive" if case.get("two_level") else "one_level"
+        o.coupling = {"one_level": ONE_LEVEL, "additive": ADDITIVE}[coupling]
+        o.precision = {"fp64": PREC_FP64, "fp32_ir": PREC_FP32_IR}[precision]
+        for k, v in opts.items():
+            setattr(o, k, v)
+        self.opts = o
+        h = ctypes.c_void_p()
+        self._check(self.lib.nls_create(ctypes.byref(o), ctypes.byref(h)), None)
+        self.h = h
+        self.case = case
+        xy = np.ascontiguousarray(case["xy"], dtype=np.float64)
+        conn = np.ascontiguousarray(case["conn"], dtype=np.int32)
+        self.N = len(xy)
+        self._check(self.lib.nls_set_mesh(h, ELEM_P1_TRI, len(xy), _ptr(xy),
+                                          len(conn), _ptr(conn)))
+        params = np.array([case.get("beta", 1.0)], dtype=np.float64)
+        coef = case.get("elem_coef")
+        load_ = case.get("elem_load")
+        coef = None if coef is None else np.ascontiguousarray(coef, dtype=np.float64)
+        load_ = None if load_ is None else np.ascontiguousarray(load_, dtype=np.float64)
+        self._check(self.lib.nls_set_problem(
+            h, PROBLEM_DIFFUSION, _ptr(params),
+            None if coef is None else _ptr(coef),
+            None if load_ is None else _ptr(load_)))
+        dn = np.ascontiguousarray(case["dirichlet"], dtype=np.int64)
+        dv = np.ascontiguousarray(case["dirichlet_vals"], dtype=np.float64)
+        self._check(self.lib.nls_set_dirichlet(h, len(dn), _ptr(dn), _ptr(dv)))
+        part = np.ascontiguousarray(case["elem_part"], dtype=np.int32)
+        self._check(self.lib.nls_set_partition(h, int(case["n_sub"]), _ptr(part),
+                                               int(case["overlap"])))
+        if coupling == "additive":
+            self._check(self.lib.nls_build_coarse(h, COARSE_GDSW))
+
+    def _check(self, rc, h="self"):
+        if rc < 0:
+            hh = self.h if h == "self" else None
+            msg = (self.lib.nls_last_error(hh) if hh else self.lib.nls_strerror(rc))
+            raise NLSError(rc, msg.decode() if msg else "")
+        return rc
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.nls_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _dev(self, x):
+        t = self.torch
+        if isinstance(x, np.ndarray):
+            x = t.from_numpy(np.ascontiguousarray(x, dtype=np.float64))
+        x = x.to(self.device, t.float64).contiguous()
+        return x
+
+    def _vp(self, t):
+        return ctypes.c_void_p(t.data_ptr())
+
+    # ---- entry points ------------------------------------------------------
+    def solve(self, u0=None):
+        """Outer Newton from u0 (default 0).  Returns (u tensor, stats, rc)."""
+        t = self.torch
+        u = t.zeros(self.N, dtype=t.float64, device=self.device) if u0 is None \
+            else self._dev(u0).clone()
+        st = Stats()
+        rc = self._check(self.lib.nls_solve(self.h, self._vp(u), 1, ctypes.byref(st)))
+        return u, st.as_dict(), rc
+
+    def solve_host(self, u: np.ndarray):
+        """Same on a host array (updated in place)."""
+        assert u.dtype == np.float64 and u.flags.c_contiguous
+        st = Stats()
+        rc = self._check(self.lib.nls_solve(self.h, _ptr(u), 0, ctypes.byref(st)))
+        return st.as_dict(), rc
+
+    def residual(self, u):
+        u = self._dev(u)
+        F = self.torch.empty_like(u)
+        self._check(self.lib.nls_eval_residual(self.h, self._vp(u), self._vp(F)))
+        return F
+
+    def precond_residual(self, u):
+        u = self._dev(u)
+        Fx = self.torch.empty_like(u)
+        self._check(self.lib.nls_eval_precond_residual(self.h, self._vp(u), self._vp(Fx)))
+        self._keep = u
+        return Fx
+
+    def tangent(self, v):
+        v = self._dev(v)
+        y = self.torch.empty_like(v)
+        self._check(self.lib.nls_apply_tangent(self.h, self._vp(v), self._vp(y)))
+        return y
+
+    def inner_iterations(self):
+        n_sub, _, _ = self.sizes()
+        its = np.zeros(n_sub, dtype=np.int32)
+        self._check(self.lib.nls_get_inner_iterations(self.h, _ptr(its)))
+        return its
+
+    def sizes(self):
+        ns = ctypes.c_int32()
+        n0 = ctypes.c_int32()
+        self._check(self.lib.nls_get_sizes(self.h, ctypes.byref(ns), ctypes.byref(n0), None))
+        nv = np.zeros(ns.value, dtype=np.int32)
+        self._check(self.lib.nls_get_sizes(self.h, None, None, _ptr(nv)))
+        return ns.value, n0.value, nv
+
+    def coarse_basis(self):
+        import scipy.sparse as sp
+        nnz = ctypes.c_int64(0)
+        self._check(self.lib.nls_get_coarse_basis(self.h, ctypes.byref(nnz), None, None, None))
+        rp = np.zeros(self.N + 1, dtype=np.int64)
+        col = np.zeros(nnz.value, dtype=np.int32)
+        val = np.zeros(nnz.value, dtype=np.float64)
+        self._check(self.lib.nls_get_coarse_basis(self.h, ctypes.byref(nnz), _ptr(rp),
+                                                  _ptr(col), _ptr(val)))
+        _, n0, _ = self.sizes()
+        return sp.csr_matrix((val, col, rp), shape=(self.N, n0))

@@ -1,0 +1,200 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances (FP64 mode):
+  * F(u): element-wise 1e-13 of max|F| (same formula, different summation
+    order: a few ulps of the largest term);
+  * F_x(u), tangent: element-wise 1e-11 of the max (local solves stop at the
+    same Newton step on both sides; the rest is rounding of band LU vs
+    dense LU, bounded by cond(J_ii) * eps ~ 1e3 * 1e-16 per solve);
+  * solution of the outer iteration: relative 2-norm error 1e-10 against the
+    oracle run with the same settings, and equal outer iteration counts.
+Mixed mode (FP32 LU + FP64 refinement): relative error 1e-8 against FP64.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import P1Problem, Schwarz, global_newton
+from tests._lib import ensure_built
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    ensure_built()
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _solver(case, **kw):
+    from paper_2410_24138_amd import Solver
+    return Solver(case, **kw)
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _close(a, b, rel):
+    scale = max(np.abs(b).max(), 1e-300)
+    err = np.abs(a - b).max() / scale
+    assert err <= rel, f"max err {err:.3e} > {rel:.1e}"
+
+
+SMALL = [
+    dict(n=12, boxes=3, overlap=1),
+    dict(n=13, boxes=3, overlap=2, uneven=True, forcing_seed=3),
+    dict(n=20, boxes=4, overlap=2, coef_seed=7, forcing_seed=5),
+    dict(n=17, boxes=2, overlap=1, forcing_seed=1, uneven=True),
+]
+
+
+@pytest.mark.parametrize("kw", SMALL)
+def test_global_residual(kw):
+    case = synth.small_case(**kw)
+    P = P1Problem(case)
+    s = _solver(case)
+    rng = np.random.default_rng(0)
+    u = rng.normal(size=P.N)
+    _close(_np(s.residual(u)), P.residual(u), 1e-13)
+
+
+def _probe_point(P, case, scale=0.5, seed=1):
+    ug, _ = global_newton(P)
+    rng = np.random.default_rng(seed)
+    u = scale * ug + 0.1 * np.abs(ug).max() * rng.normal(size=P.N)
+    u[P.is_dir] = P.dir_value[P.is_dir]
+    return u
+
+
+@pytest.mark.parametrize("coupling", ["one_level", "additive"])
+@pytest.mark.parametrize("kw", SMALL)
+def test_precond_residual_and_tangent(kw, coupling):
+    case = synth.small_case(two_level=(coupling == "additive"), **kw)
+    P = P1Problem(case)
+    S = Schwarz(P, coupling)
+    s = _solver(case, coupling=coupling)
+    u = _probe_point(P, case)
+    Fx_ref = S.evaluate(u)
+    Fx = _np(s.precond_residual(u))
+    _close(Fx, Fx_ref, 1e-11)
+    its = s.inner_iterations()
+    np.testing.assert_array_equal(its, [sol["its"] for sol in S.state["sols"]])
+    rng = np.random.default_rng(3)
+    for _ in range(2):
+        v = rng.normal(size=P.N)
+        _close(_np(s.tangent(v)), S.tangent(v), 1e-11)
+
+
+@pytest.mark.parametrize("kw", [dict(n=16, boxes=4, overlap=1),
+                                dict(n=13, boxes=3, overlap=2, uneven=True, coef_seed=2),
+                                dict(n=24, boxes=3, overlap=2, forcing_seed=9)])
+def test_coarse_basis(kw):
+    case = synth.small_case(two_level=True, **kw)
+    S = Schwarz(P1Problem(case), "additive")
+    s = _solver(case, coupling="additive")
+    Phi = s.coarse_basis().toarray()
+    _close(Phi, S.Phi.toarray(), 1e-12)
+
+
+@pytest.mark.parametrize("coupling", ["one_level", "additive"])
+@pytest.mark.parametrize("kw", [dict(n=12, boxes=3, overlap=1),
+                                dict(n=24, boxes=4, overlap=2, forcing_seed=2),
+                                dict(n=21, boxes=3, overlap=1, uneven=True, coef_seed=3)])
+def test_solve_matches_oracle(kw, coupling):
+    case = synth.small_case(two_level=(coupling == "additive"), **kw)
+    P = P1Problem(case)
+    S = Schwarz(P, coupling)
+    u_ref, st_ref = S.solve()
+    s = _solver(case, coupling=coupling)
+    u, st, rc = s.solve()
+    u = _np(u)
+    assert rc == 0 and st["converged"]
+    assert st["outer_its"] == st_ref["outer"]
+    assert np.linalg.norm(u - u_ref) <= 1e-10 * np.linalg.norm(u_ref)
+    assert st["inner_its_total"] == sum(st_ref["inner"])
+    for a, b in zip(st["gmres_its"], st_ref["gmres"]):
+        assert abs(a - b) <= 1
+
+
+def test_solve_config1():
+    case = synth.config1()
+    golden = json.load(open(os.path.join(HERE, "golden", case["name"] + ".json")))
+    s = _solver(case)
+    u, st, rc = s.solve()
+    u = _np(u)
+    assert rc == 0 and st["converged"]
+    assert st["outer_its"] == golden["outer"]
+    idx = np.array(golden["sample_nodes"])
+    ref = np.array(golden["u_sample"])
+    assert np.abs(u[idx] - ref).max() <= 1e-10 * np.abs(ref).max()
+    assert abs(np.linalg.norm(u) - golden["u_norm"]) <= 1e-10 * golden["u_norm"]
+    assert st["inner_its_total"] == sum(golden["inner"])
+
+
+def test_solve_config2_fp64():
+    """512x512 grid, 16x16 subdomains, two-level: compare the stored oracle
+    trace (same settings) and the brute-force global solution."""
+    case = synth.config2()
+    golden = json.load(open(os.path.join(HERE, "golden", case["name"] + ".json")))
+    s = _solver(case)
+    u, st, rc = s.solve()
+    u = _np(u)
+    assert rc == 0 and st["converged"]
+    assert st["outer_its"] == golden["outer"]
+    idx = np.array(golden["sample_nodes"])
+    ref = np.array(golden["u_sample"])
+    assert np.abs(u[idx] - ref).max() <= 1e-10 * np.abs(ref).max()
+    assert abs(np.linalg.norm(u) - golden["u_norm"]) <= 1e-10 * golden["u_norm"]
+    gn = np.array(golden["u_global_newton_sample"])
+    assert np.abs(u[idx] - gn).max() <= 1e-8 * np.abs(gn).max()
+
+
+@pytest.mark.parametrize("two_level", [False, True])
+def test_mixed_precision_matches_fp64(two_level):
+    case = synth.small_case(n=32, boxes=4, overlap=2, forcing_seed=4,
+                            two_level=two_level)
+    u64, st64, _ = _solver(case).solve()
+    u32, st32, rc = _solver(case, precision="fp32_ir").solve()
+    assert rc == 0 and st32["converged"]
+    u64, u32 = _np(u64), _np(u32)
+    assert np.linalg.norm(u32 - u64) <= 1e-8 * np.linalg.norm(u64)
+
+
+def test_deterministic():
+    case = synth.small_case(n=20, boxes=4, overlap=2, forcing_seed=6, two_level=True)
+    s = _solver(case)
+    u = np.random.default_rng(4).normal(size=len(case["xy"])) * 0.01
+    a = _np(s.precond_residual(u))
+    b = _np(s.precond_residual(u))
+    np.testing.assert_array_equal(a, b)
+
+
+def test_error_paths():
+    from paper_2410_24138_amd import NLSError
+    import paper_2410_24138_amd.nls as nls
+    case = synth.small_case(n=12, boxes=3, overlap=1, forcing_seed=1)
+    bad = dict(case)
+    fl = case["elem_load"].copy()
+    fl[5, 1] = np.nan
+    bad["elem_load"] = fl
+    with pytest.raises(NLSError) as e:
+        _solver(bad).solve()
+    assert e.value.code == nls.NLS_ENAN
+    with pytest.raises(NLSError) as e:
+        _solver(case, inner_maxit=1).solve(np.full(len(case["xy"]), 0.0))
+    assert e.value.code == nls.NLS_ELOCAL
+    s = _solver(case, gmres_maxit=1, outer_maxit=2)
+    u, st, rc = s.solve()
+    assert rc == nls.NLS_ENOCONV and not st["converged"] and st["outer_its"] == 2
+    with pytest.raises(NLSError) as e:
+        s.tangent(np.zeros(len(case["xy"]))) if False else _solver(case).tangent(
+            np.zeros(len(case["xy"])))
+    assert e.value.code == nls.NLS_ESTATE
