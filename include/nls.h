@@ -72,8 +72,12 @@ typedef struct nls_options {
     double gmres_rtol;    /* GMRES on eq. (13): ||r||_2 <= gmres_rtol ||F_x(u_k)||_2 */
     int    gmres_maxit;
     int    gmres_restart;
-    int    flags;         /* reserved, 0 */
+    int    flags;         /* NLS_FLAG_* bits */
 } nls_options;
+
+/* options.flags: time the local-solve and local-tangent kernels with HIP
+   events on the handle's stream (adds one event pair per launch). */
+#define NLS_FLAG_PROFILE  1
 
 /* ---- statistics of the last solve ------------------------------------ */
 #define NLS_MAX_OUTER 64
@@ -94,6 +98,12 @@ typedef struct nls_stats {
     double    ms_gmres;
     double    ms_other;
     double    ms_total;
+    /* with NLS_FLAG_PROFILE: event-timed launches of the fused local Newton
+       kernel and of the local tangent kernel */
+    int       n_local_launches;
+    double    ms_local_kernel;
+    int       n_tangent_launches;
+    double    ms_tangent_kernel;
 } nls_stats;
 
 typedef struct nls_handle nls_handle;

@@ -55,6 +55,12 @@ struct nls_handle {
     DevMaps dp{};
     DevLocal dl{};
     DevCoarse dc{};
+    DevTangent dt{};
+    bool tangent_w = false;       // W_i = J^{-1} B on owned rows (else per-apply solves)
+    int tangent_bucket = 0, max_ng = 0;
+    bool coarse_inv = false;      // explicit A0^{-1} for the tangent
+    int coarse_bucket = 0;
+    double* rhs2 = nullptr;
     NewtonParams np{};
     double b_inf = 0.0, phib_inf = 0.0;
     int npl_local = 1, lds_local = 0, lds_tangent = 0;
@@ -68,10 +74,43 @@ struct nls_handle {
     int nb_dot = 0;
     std::vector<int> its_h;
     nls_stats* st = nullptr;  // stats of the running solve (may be null)
+    // event pairs of profiled launches (kind 0: local Newton, 1: tangent)
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
+    bool profiling() const { return (opt.flags & NLS_FLAG_PROFILE) != 0 && st != nullptr; }
+    hipEvent_t take_event() {
+        if (!ev_pool.empty()) {
+            hipEvent_t e = ev_pool.back();
+            ev_pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        (void)hipEventCreate(&e);
+        return e;
+    }
+    void collect_events() {
+        for (auto& u : ev_used) {
+            float ms = 0.f;
+            (void)hipEventSynchronize(u.second.second);
+            (void)hipEventElapsedTime(&ms, u.second.first, u.second.second);
+            if (st) {
+                if (u.first == 0) { st->n_local_launches++; st->ms_local_kernel += ms; }
+                else { st->n_tangent_launches++; st->ms_tangent_kernel += ms; }
+            }
+            ev_pool.push_back(u.second.first);
+            ev_pool.push_back(u.second.second);
+        }
+        ev_used.clear();
+    }
 
     ~nls_handle() {
         for (auto& g : bufs)
             for (void* p : g) (void)hipFree(p);
+        for (auto& u : ev_used) {
+            (void)hipEventDestroy(u.second.first);
+            (void)hipEventDestroy(u.second.second);
+        }
+        for (auto e : ev_pool) (void)hipEventDestroy(e);
     }
     void free_group(int g) {
         for (void* p : bufs[g]) (void)hipFree(p);
@@ -331,7 +370,8 @@ extern "C" int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* el
     for (int i = 0; i < M.nsub; ++i) {
         int n = M.off_n[i + 1] - M.off_n[i], ng = M.off_g[i + 1] - M.off_g[i];
         int dbl = (n + ng) + n + (mixed ? 2 * n : 0) + 24 + std::max(M.kl[i], 1) + 1;
-        int bytes = dbl * 8 + band_window_doubles(M.kl[i], M.ku[i]) * (mixed ? 4 : 8);
+        // the factorization at the converged state is FP64 in every mode
+        int bytes = dbl * 8 + band_window_doubles(M.kl[i], M.ku[i]) * 8;
         lds = std::max(lds, bytes);
     }
     if (lds > 160 * 1024) return fail(h, NLS_ELIMIT, "subdomain too large for the LDS working set");
@@ -384,6 +424,35 @@ extern "C" int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* el
     RC(h->alloc(G_MAPS, &L.status, M.nsub));
     h->dl = L;
     h->its_h.assign(M.nsub, 0);
+    // exact-tangent blocks W_i = (J_ii^{-1} B_i)[owned rows, :]
+    {
+        int bucket = 0;
+        h->max_ng = 0;
+        for (int i = 0; i < M.nsub; ++i) {
+            bucket = std::max(bucket, mrhs_bucket_kl(M.kl[i], M.ku[i]));
+            h->max_ng = std::max(h->max_ng, M.off_g[i + 1] - M.off_g[i]);
+        }
+        h->tangent_bucket = bucket;
+        h->tangent_w = bucket <= 48 && M.max_bcol <= NLS_MAX_BCOL && h->max_ng * 8 <= 64 * 1024;
+        if (h->tangent_w) {
+            DevTangent T{};
+            int *bptr, *brow, *bslot, *off_own, *ownrow, *rowown;
+            int64_t *off_W, *off_F;
+            RC(h->upload(G_MAPS, &bptr, M.bptr));
+            RC(h->upload(G_MAPS, &brow, M.brow));
+            RC(h->upload(G_MAPS, &bslot, M.bslot));
+            RC(h->upload(G_MAPS, &off_own, M.off_own));
+            RC(h->upload(G_MAPS, &ownrow, M.ownrow));
+            RC(h->upload(G_MAPS, &rowown, M.rowown));
+            RC(h->upload(G_MAPS, &off_W, M.off_W));
+            RC(h->upload(G_MAPS, &off_F, M.off_F));
+            T.bptr = bptr; T.brow = brow; T.bslot = bslot; T.off_own = off_own;
+            T.ownrow = ownrow; T.rowown = rowown; T.off_W = off_W; T.off_F = off_F;
+            RC(h->alloc(G_MAPS, &T.W, (size_t)M.off_W.back()));
+            RC(h->alloc(G_MAPS, &T.fwd, (size_t)M.off_F.back()));
+            h->dt = T;
+        }
+    }
     // Newton parameters
     NewtonParams np{};
     np.rtol = h->opt.inner_rtol;
@@ -515,6 +584,13 @@ extern "C" int nls_build_coarse(nls_handle* h, int kind) {
     RC(h->alloc(G_COARSE, &d.scal, 4));
     RC(h->alloc(G_COARSE, &d.flag, 1));
     RC(h->alloc(G_COARSE, &h->ctmp, C.n0));
+    RC(h->alloc(G_COARSE, &h->rhs2, C.n0));
+    h->coarse_bucket = mrhs_bucket_kl(C.a0kl, C.a0ku);
+    h->coarse_inv = h->coarse_bucket <= 48;
+    if (h->coarse_inv) {
+        RC(h->alloc(G_COARSE, &d.a0inv, (size_t)C.n0 * C.n0));
+        RC(h->alloc(G_COARSE, &d.a0fwd, (size_t)C.n0 * C.n0));
+    }
     HIPCHK(hipMemsetAsync(d.flag, 0, sizeof(int), h->stream));
     h->dc = d;
     HIPCHK(launch_gdsw_extend(h->dm, d, lds_gdsw, npl_for(std::max(maxikl, maxiband)), h->stream));
@@ -581,6 +657,7 @@ static int coarse_solve(nls_handle* h, const double* u, int* its_out) {
     HIPCHK(launch_coarse_galerkin(h->dm, d, d.w, h->stream));
     HIPCHK(launch_coarse_assemble(d, 1, h->stream));
     HIPCHK(launch_coarse_lu(d, 1, h->lds_coarse_lu, h->npl_coarse, h->stream));
+    if (h->coarse_inv) HIPCHK(launch_coarse_inverse(d, h->coarse_bucket, h->stream));
     if (its_out) *its_out = its;
     return NLS_OK;
 }
@@ -595,7 +672,17 @@ static int dot_host(nls_handle* h, const double* x, const double* y, int n, doub
 static int evaluate(nls_handle* h, const double* u, double* Fx) {
     Timer t;
     h->have_state = false;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (h->profiling()) {
+        e0 = h->take_event();
+        e1 = h->take_event();
+        HIPCHK(hipEventRecord(e0, h->stream));
+    }
     HIPCHK(launch_local_newton(h->dm, h->dp, h->dl, h->np, u, h->lds_local, h->npl_local, h->stream));
+    if (e0) {
+        HIPCHK(hipEventRecord(e1, h->stream));
+        h->ev_used.push_back({0, {e0, e1}});
+    }
     HIPCHK(launch_any_status(h->dl.status, h->maps.nsub, h->stat2, h->stream));
     int st2[2];
     HIPCHK(hipMemcpyAsync(st2, h->stat2, 2 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
@@ -609,6 +696,12 @@ static int evaluate(nls_handle* h, const double* u, double* Fx) {
             h->st->inner_its_max = std::max(h->st->inner_its_max, v);
         }
         h->st->local_solves += h->maps.nsub;
+    }
+    if (st2[0] < 0 && h->tangent_w) {
+        Timer tp;
+        HIPCHK(launch_tangent_prep(h->dp, h->dl, h->dt, h->tangent_bucket, h->max_ng, h->stream));
+        RC(sync(h));
+        if (h->st) h->st->ms_inner += tp.ms();
     }
     if (st2[0] >= 0) {
         if (h->st) h->st->failed_subdomain = st2[0];
@@ -635,13 +728,31 @@ static int evaluate(nls_handle* h, const double* u, double* Fx) {
 
 // y = D F_x(u) v (eqs. 6, 7, 12) at the last evaluated point.
 static int tangent(nls_handle* h, const double* v, double* y) {
-    HIPCHK(launch_tangent_local(h->dm, h->dp, h->dl, h->np, v, h->lds_tangent, h->npl_local, h->stream));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (h->profiling()) {
+        e0 = h->take_event();
+        e1 = h->take_event();
+        HIPCHK(hipEventRecord(e0, h->stream));
+    }
+    if (h->tangent_w)
+        HIPCHK(launch_tangent_gemv(h->dp, h->dt, v, h->dl.z, h->max_ng, h->stream));
+    else
+        HIPCHK(launch_tangent_local(h->dm, h->dp, h->dl, h->np, v, h->lds_tangent, h->npl_local, h->stream));
+    if (e0) {
+        HIPCHK(hipEventRecord(e1, h->stream));
+        h->ev_used.push_back({1, {e0, e1}});
+    }
     if (two_level(h)) {
         DevCoarse& d = h->dc;
         HIPCHK(launch_coarse_q(h->dm, d, d.w, v, 1, h->lds_coarse_q, h->stream));
         HIPCHK(launch_coarse_assemble(d, 0, h->stream));
-        HIPCHK(launch_coarse_lu(d, 0, h->lds_coarse_lu, h->npl_coarse, h->stream));
-        HIPCHK(launch_coarse_scatter(d, h->ctmp, h->stream));
+        if (h->coarse_inv) {
+            HIPCHK(launch_dense_gemv(d.n0, d.a0inv, d.rhs, h->rhs2, h->stream));
+            HIPCHK(launch_coarse_scatter(d, h->rhs2, h->ctmp, h->stream));
+        } else {
+            HIPCHK(launch_coarse_lu(d, 0, h->lds_coarse_lu, h->npl_coarse, h->stream));
+            HIPCHK(launch_coarse_scatter(d, nullptr, h->ctmp, h->stream));
+        }
         HIPCHK(launch_prolong(h->dm, h->dp, h->dl.z, &d, h->ctmp, y, v, h->stream));
     } else {
         HIPCHK(launch_prolong(h->dm, h->dp, h->dl.z, nullptr, nullptr, y, v, h->stream));
@@ -754,6 +865,7 @@ extern "C" int nls_solve(nls_handle* h, double* u, int u_on_device, nls_stats* s
         if (!u_on_device)
             (void)hipMemcpyAsync(u, ud, sizeof(double) * N, hipMemcpyDeviceToHost, h->stream);
         (void)hipStreamSynchronize(h->stream);
+        h->collect_events();
         S->ms_total = ttot.ms();
         S->ms_other = S->ms_total - S->ms_inner - S->ms_coarse - S->ms_gmres;
         h->st = nullptr;

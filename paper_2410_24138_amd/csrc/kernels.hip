@@ -21,6 +21,7 @@
 //    order), so norms and dot products do not depend on scheduling.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 #include <cmath>
 
@@ -49,7 +50,7 @@ __device__ __forceinline__ double wave_max(double v) {
 }
 
 // Deterministic workgroup reductions; red must hold >= 24 doubles of LDS.
-__device__ double block_sum(double v, double* red) {
+__device__ __forceinline__ double block_sum(double v, double* red) {
     v = wave_sum(v);
     const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
     __syncthreads();
@@ -64,7 +65,7 @@ __device__ double block_sum(double v, double* red) {
     return red[16];
 }
 
-__device__ double block_max(double v, double* red) {
+__device__ __forceinline__ double block_max(double v, double* red) {
     v = wave_max(v);
     const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
     __syncthreads();
@@ -95,7 +96,7 @@ __device__ __forceinline__ void g_row(const double* __restrict__ G6, int pos, do
 // ----------------------------------------------------------------------------
 
 // Residual of the rows of V_i held by this thread; vp = patch values in LDS.
-__device__ void local_residual(const DevMesh& M, const DevMaps& P, int n, int rowbase,
+__device__ __forceinline__ void local_residual(const DevMesh& M, const DevMaps& P, int n, int rowbase,
                                int ebase, const double* vp, double* rb) {
     for (int a = threadIdx.x; a < n; a += blockDim.x) {
         const int row = rowbase + a;
@@ -123,7 +124,7 @@ __device__ void local_residual(const DevMesh& M, const DevMaps& P, int n, int ro
 }
 
 // Jacobian rows [J_ii | B_i] into the CSR values jval (slots fixed at setup).
-__device__ void local_jacobian(const DevMesh& M, const DevMaps& P, int n, int rowbase,
+__device__ __forceinline__ void local_jacobian(const DevMesh& M, const DevMaps& P, int n, int rowbase,
                                int ebase, const double* vp, double* __restrict__ jval) {
     for (int a = threadIdx.x; a < n; a += blockDim.x) {
         const int row = rowbase + a;
@@ -171,7 +172,7 @@ __device__ void local_jacobian(const DevMesh& M, const DevMaps& P, int n, int ro
 // Returns nonzero if a zero pivot occurred.
 // ----------------------------------------------------------------------------
 template <typename T>
-__device__ int band_lu(int n, int kl, int ku, const int* __restrict__ rptr,
+__device__ __forceinline__ int band_lu(int n, int kl, int ku, const int* __restrict__ rptr,
                        const int* __restrict__ cols, const double* __restrict__ vals,
                        T* W, T* mult, int* sflag, T* __restrict__ Uf, T* __restrict__ Lf,
                        int* __restrict__ piv) {
@@ -278,6 +279,302 @@ __device__ int band_lu(int n, int kl, int ku, const int* __restrict__ rptr,
     return sflag[1];
 }
 
+// Broadcast lane l's value (l uniform) through v_readlane.
+__device__ __forceinline__ double rdlane(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float rdlane(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_max(double v) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    const int lo2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWMASK, 0xf, false);
+    const int hi2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWMASK, 0xf, false);
+    return fmax(v, __hiloint2double(hi2, lo2));
+}
+
+// Lane of the largest |a| over the wavefront (a < 0 marks lanes that do not
+// take part); ties go to the lowest lane.  The lane number is packed into the
+// 6 low mantissa bits of |a| (a relative perturbation below 2^-46, which only
+// matters for values that are equal to that precision), then a DPP max
+// reduction leaves the winner in lane 63.
+__device__ __forceinline__ int wave_argmax(double a, int lane) {
+    double key;
+    if (a >= 0.0) {
+        const long long bits = (__double_as_longlong(a) & ~63ll) | (long long)(63 - lane);
+        key = __longlong_as_double(bits);
+    } else {
+        key = -1.0;
+    }
+    key = dpp_max<0xB1, 0xf>(key);   // quad_perm [1,0,3,2]
+    key = dpp_max<0x4E, 0xf>(key);   // quad_perm [2,3,0,1]
+    key = dpp_max<0x141, 0xf>(key);  // row_half_mirror
+    key = dpp_max<0x140, 0xf>(key);  // row_mirror
+    key = dpp_max<0x142, 0xa>(key);  // row_bcast:15 into rows 1, 3
+    key = dpp_max<0x143, 0xc>(key);  // row_bcast:31 into rows 2, 3
+    key = rdlane(key, 63);
+    return 63 - (int)(__double_as_longlong(key) & 63ll);
+}
+
+// ----------------------------------------------------------------------------
+// Blocked band LU with partial pivoting (same results layout as band_lu).
+// Panels of NB columns: one wavefront factors the panel in registers (lane r
+// holds window row r, NB <= 64 - kl), then the workgroup applies the panel's
+// row interchanges and L11^{-1} to the trailing columns (one thread per
+// column) and the rank-NB update A22 -= L21 U12 with 4x4 register tiles.
+// The window is an LDS ring buffer of H = NB + kl rows by Wd = NB + kl + ku
+// columns; it slides by NB rows and columns per panel.
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ int wrap(int x, int m) { return x < m ? x : x - m; }
+
+// Workgroup barrier that orders LDS only: waits for this wave's LDS traffic
+// (lgkmcnt = 0) but leaves global stores in flight.  Used inside the
+// factorization, whose HBM outputs are read back only after a full
+// __syncthreads().
+__device__ __forceinline__ void lds_barrier() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __builtin_amdgcn_s_barrier();
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+template <typename T, int NB>
+__device__ __forceinline__ int band_lu_blocked(int n, int kl, int ku, const int* __restrict__ rptr,
+                               const int* __restrict__ cols, const double* __restrict__ vals,
+                               T* W, int* sh, T* __restrict__ Uf, T* __restrict__ Lf,
+                               int* __restrict__ piv) {
+    T* lt = W + (NB + kl) * (NB + kl + ku);  // L11 of the current panel, NB x NB
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int lane = tid & 63, wv = tid >> 6;
+    const int H = NB + kl, Wd = NB + kl + ku;
+    const int ldu = kl + ku + 1, ldl = kl > 1 ? kl : 1;
+    for (int i = tid; i < H * Wd; i += nt) W[i] = T(0);
+    if (tid == 0) sh[NB] = 0;
+    __syncthreads();
+    for (int r = tid; r < min(H, n); r += nt)
+        for (int s = rptr[r]; s < rptr[r + 1]; ++s) {
+            const int c = cols[s];
+            if (c < n) W[r * Wd + c] = T(vals[s]);
+        }
+    __syncthreads();
+    int rb = 0, cb = 0;  // ring slots of global row / column k0
+    for (int k0 = 0; k0 < n; k0 += NB) {
+        const int nbp = min(NB, n - k0);
+        const int rvalid = min(H, n - k0);
+        const int k1 = k0 + NB, cb1 = wrap(cb + NB, Wd);
+        // waves 1.. fetch the CSR entries of the rows that enter the window
+        // after this panel while wave 0 factors it
+        constexpr int PF = 2;
+        const int rn0 = k0 + H, rn1 = min(k0 + H + NB, n);
+        int pf_slot[PF];
+        T pf_val[PF];
+#pragma unroll
+        for (int e = 0; e < PF; ++e) {
+            pf_slot[e] = -1;
+            pf_val[e] = T(0);
+        }
+        int s_end = 0, s_done = 0;
+        if (rn0 < n && wv > 0) {
+            int rp[NB + 1];
+#pragma unroll
+            for (int q = 0; q <= NB; ++q) rp[q] = rptr[min(rn0 + q, rn1)];
+            s_end = rp[NB];
+            s_done = rp[0] + (nt - 64) * PF;
+#pragma unroll
+            for (int e = 0; e < PF; ++e) {
+                const int sidx = rp[0] + (tid - 64) + (nt - 64) * e;
+                if (sidx < s_end) {
+                    int q = 0;
+#pragma unroll
+                    for (int t = 1; t < NB; ++t) q += (rp[t] <= sidx) ? 1 : 0;
+                    const int c = cols[sidx];
+                    if (c < n) {
+                        pf_slot[e] = wrap(rb + q, H) * Wd + wrap(cb1 + (c - k1), Wd);
+                        pf_val[e] = T(vals[sidx]);
+                    }
+                }
+            }
+        }
+        // ---- panel: columns k0..k0+nbp-1, rows k0..k0+rvalid-1 (wave 0)
+        if (wv == 0) {
+            T p[NB];
+            const bool have = lane < rvalid;
+            const int sr = wrap(rb + (lane < H ? lane : 0), H);
+#pragma unroll
+            for (int c = 0; c < NB; ++c) p[c] = have ? W[sr * Wd + wrap(cb + c, Wd)] : T(0);
+            int sing = 0;
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                if (j < nbp) {
+                    const int rmx = min(j + kl, rvalid - 1);
+                    const int d = __builtin_amdgcn_readfirstlane(wave_argmax(
+                        (lane >= j && lane <= rmx) ? fabs((double)p[j]) : -1.0, lane));
+                    if (lane == 0) {
+                        piv[k0 + j] = k0 + d;
+                        sh[j] = d;
+                    }
+                    // whole panel rows are exchanged (the multipliers of
+                    // earlier columns included), so that L21 in the window
+                    // matches the row order the delayed update A22 -= L21 U12
+                    // needs; the multipliers are stored to HBM at their own
+                    // step, in the interleaved order the band solve applies.
+                    if (d != j) {
+#pragma unroll
+                        for (int c = 0; c < NB; ++c) {
+                            const T pj = rdlane(p[c], j);
+                            const T pd = rdlane(p[c], d);
+                            if (lane == j) p[c] = pd;
+                            if (lane == d) p[c] = pj;
+                        }
+                    }
+                    const T pivv = rdlane(p[j], j);
+                    if (pivv == T(0)) sing = 1;
+                    const T inv = pivv != T(0) ? T(1) / pivv : T(0);
+                    const bool below = lane > j && lane <= rmx;
+                    const T l = below ? p[j] * inv : T(0);
+                    if (below) {
+                        p[j] = l;
+                        Lf[(size_t)(k0 + j) * ldl + (lane - j - 1)] = l;
+                    }
+#pragma unroll
+                    for (int c = j + 1; c < NB; ++c) {
+                        const T pr = rdlane(p[c], j);
+                        if (below) p[c] -= l * pr;
+                    }
+                }
+            }
+            if (lane < H && have) {
+#pragma unroll
+                for (int c = 0; c < NB; ++c) W[sr * Wd + wrap(cb + c, Wd)] = p[c];
+            }
+            if (lane < NB) {
+#pragma unroll
+                for (int c = 0; c < NB; ++c) lt[lane * NB + c] = p[c];
+            }
+            if (lane == 0 && sing) sh[NB] = 1;
+        }
+        lds_barrier();
+        // ---- trailing columns: interchanges, then U12 = L11^{-1} A12
+        const int ntr = min(Wd - NB, n - k0 - nbp);
+        for (int t = tid; t < ntr; t += nt) {
+            const int sc = wrap(cb + NB + t, Wd);
+            for (int j = 0; j < nbp; ++j) {
+                const int d = sh[j];
+                if (d != j) {
+                    T* a = W + wrap(rb + j, H) * Wd + sc;
+                    T* b = W + wrap(rb + d, H) * Wd + sc;
+                    const T x = *a;
+                    *a = *b;
+                    *b = x;
+                }
+            }
+            T x[NB];
+#pragma unroll
+            for (int j = 0; j < NB; ++j) x[j] = (j < nbp) ? W[wrap(rb + j, H) * Wd + sc] : T(0);
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+#pragma unroll
+                for (int r = j + 1; r < NB; ++r) x[r] -= lt[r * NB + j] * x[j];
+            }
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                if (j < nbp) W[wrap(rb + j, H) * Wd + sc] = x[j];
+        }
+        lds_barrier();
+        // ---- A22 -= L21 U12 (rows NB..rvalid-1) in 4x4 tiles; U rows out
+        {
+            const int nr2 = rvalid - NB;
+            if (nr2 > 0 && ntr > 0) {
+                const int tr = (nr2 + 3) >> 2, tc = (ntr + 3) >> 2;
+                for (int t = tid; t < tr * tc; t += nt) {
+                    const int r0 = NB + 4 * (t / tc), c0 = NB + 4 * (t % tc);
+                    T acc[4][4];
+                    int srow[4], scol[4];
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) {
+                        srow[a] = wrap(rb + min(r0 + a, H - 1), H);
+                        scol[a] = wrap(cb + min(c0 + a, Wd - 1), Wd);
+#pragma unroll
+                        for (int b = 0; b < 4; ++b) acc[a][b] = T(0);
+                    }
+#pragma unroll 2
+                    for (int j = 0; j < nbp; ++j) {
+                        {
+                            const int sj = wrap(rb + j, H), cj = wrap(cb + j, Wd);
+                            T lv[4], uv[4];
+#pragma unroll
+                            for (int a = 0; a < 4; ++a) {
+                                lv[a] = W[srow[a] * Wd + cj];
+                                uv[a] = W[sj * Wd + scol[a]];
+                            }
+#pragma unroll
+                            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                                for (int b = 0; b < 4; ++b) acc[a][b] += lv[a] * uv[b];
+                        }
+                    }
+#pragma unroll
+                    for (int a = 0; a < 4; ++a)
+#pragma unroll
+                        for (int b = 0; b < 4; ++b)
+                            if (r0 + a < rvalid && c0 + b < NB + ntr)
+                                W[srow[a] * Wd + scol[b]] -= acc[a][b];
+                }
+            }
+            for (int idx = tid; idx < nbp * ldu; idx += nt) {
+                const int r = idx / ldu, o = idx - r * ldu;
+                const int c = r + o;
+                if (k0 + c < n) Uf[(size_t)(k0 + c) * ldu + o] = W[wrap(rb + r, H) * Wd + wrap(cb + c, Wd)];
+            }
+        }
+        lds_barrier();
+        // ---- slide by NB: rows k0.. and columns k0.. leave the window
+        for (int i = tid; i < NB * Wd; i += nt) {
+            const int q = i / Wd, c = i - q * Wd;
+            W[wrap(rb + q, H) * Wd + c] = T(0);
+        }
+        for (int i = tid; i < H * NB; i += nt) {
+            const int r = i / NB, q = i - r * NB;
+            W[r * Wd + wrap(cb + q, Wd)] = T(0);
+        }
+        lds_barrier();
+        if (wv > 0) {
+#pragma unroll
+            for (int e = 0; e < PF; ++e)
+                if (pf_slot[e] >= 0) W[pf_slot[e]] = pf_val[e];
+            // rows with more entries than the prefetch covers
+            for (int sidx = s_done + (tid - 64); sidx < s_end; sidx += nt - 64) {
+                int q = 0;
+                while (q + 1 < NB && rptr[rn0 + q + 1] <= sidx) ++q;
+                const int c = cols[sidx];
+                if (c < n) W[wrap(rb + q, H) * Wd + wrap(cb1 + (c - k1), Wd)] = T(vals[sidx]);
+            }
+        }
+        lds_barrier();
+        rb = wrap(rb + NB, H);
+        cb = cb1;
+    }
+    __syncthreads();  // factors in HBM are complete for the workgroup
+    return sh[NB];
+}
+
+// Choose the blocked factorization when its panel fits a wavefront.
+template <typename T>
+__device__ __forceinline__ int band_lu_auto(int n, int kl, int ku, const int* __restrict__ rptr,
+                            const int* __restrict__ cols, const double* __restrict__ vals,
+                            T* W, T* mult, int* sflag, T* __restrict__ Uf, T* __restrict__ Lf,
+                            int* __restrict__ piv) {
+    if (kl + 16 <= 64)
+        return band_lu_blocked<T, 16>(n, kl, ku, rptr, cols, vals, W, sflag, Uf, Lf, piv);
+    if (kl + 8 <= 64)
+        return band_lu_blocked<T, 8>(n, kl, ku, rptr, cols, vals, W, sflag, Uf, Lf, piv);
+    return band_lu<T>(n, kl, ku, rptr, cols, vals, W, mult, sflag, Uf, Lf, piv);
+}
+
 // ----------------------------------------------------------------------------
 // Band triangular solves with the factors of band_lu, executed by ONE
 // wavefront (threads 0..63), right-hand side b in LDS (FP64).  NPL values per
@@ -285,7 +582,7 @@ __device__ int band_lu(int n, int kl, int ku, const int* __restrict__ rptr,
 // ahead into registers so that HBM latency is paid once per chunk.
 // ----------------------------------------------------------------------------
 template <typename T, int NPL>
-__device__ void band_solve_wave(int n, int kl, int ku, const T* __restrict__ Uf,
+__device__ __forceinline__ void band_solve_wave(int n, int kl, int ku, const T* __restrict__ Uf,
                                 const T* __restrict__ Lf, const int* __restrict__ piv,
                                 double* b) {
     constexpr int S = 8;
@@ -362,7 +659,7 @@ __device__ void band_solve_wave(int n, int kl, int ku, const T* __restrict__ Uf,
 }
 
 template <int NPL>
-__device__ void band_solve_any(bool f32, int n, int kl, int ku, const double* Ud,
+__device__ __forceinline__ void band_solve_any(bool f32, int n, int kl, int ku, const double* Ud,
                                const double* Ld, const float* Us, const float* Ls,
                                const int* piv, double* b) {
     if (f32) band_solve_wave<float, NPL>(n, kl, ku, Us, Ls, piv, b);
@@ -373,7 +670,7 @@ __device__ void band_solve_any(bool f32, int n, int kl, int ku, const double* Ud
 // factors: iterative refinement with FP64 residuals r0 - J d computed from
 // the FP64 CSR values (columns < n), until ||res|| <= ir_rtol ||r0||.
 template <int NPL>
-__device__ void local_linear_solve(const DevMaps& P, const DevLocal& L, const NewtonParams& np,
+__device__ __forceinline__ void local_linear_solve(const DevMaps& P, const DevLocal& L, const NewtonParams& np,
                                    int i, int n, int rowbase, double* rb, double* r0,
                                    double* dl, double* red) {
     const int kl = P.kl[i], ku = P.ku[i];
@@ -418,14 +715,14 @@ __device__ void local_linear_solve(const DevMaps& P, const DevLocal& L, const Ne
 }
 
 // Factor J at the current point into FP64 or FP32 storage.
-__device__ int local_factor(const DevMaps& P, const DevLocal& L, const NewtonParams& np, int i,
-                            int n, int rowbase, void* W, void* mult, int* sflag) {
+__device__ __forceinline__ int local_factor(const DevMaps& P, const DevLocal& L, const NewtonParams& np, int i,
+                            int n, int rowbase, void* W, void* mult, int* sflag, bool fp64 = false) {
     const int kl = P.kl[i], ku = P.ku[i];
     const int* rptr = P.jptr + rowbase;
-    if (np.mixed)
-        return band_lu<float>(n, kl, ku, rptr, P.jcol, L.jval, (float*)W, (float*)mult, sflag,
+    if (np.mixed && !fp64)
+        return band_lu_auto<float>(n, kl, ku, rptr, P.jcol, L.jval, (float*)W, (float*)mult, sflag,
                               L.Uf32 + P.off_u[i], L.Lf32 + P.off_l[i], L.piv + rowbase);
-    return band_lu<double>(n, kl, ku, rptr, P.jcol, L.jval, (double*)W, (double*)mult, sflag,
+    return band_lu_auto<double>(n, kl, ku, rptr, P.jcol, L.jval, (double*)W, (double*)mult, sflag,
                            L.Uf + P.off_u[i], L.Lf + P.off_l[i], L.piv + rowbase);
 }
 
@@ -443,7 +740,7 @@ template <int NPL>
 __global__ void __launch_bounds__(NLS_BLOCK)
 k_local_newton(DevMesh M, DevMaps P, DevLocal L, NewtonParams np, const double* __restrict__ u) {
     extern __shared__ double smem[];
-    __shared__ int sflag[4];
+    __shared__ int sflag[20];
     const int i = P.order[blockIdx.x];
     const int rowbase = P.off_n[i], n = P.off_n[i + 1] - rowbase;
     const int gbase = P.off_g[i], ng = P.off_g[i + 1] - gbase;
@@ -493,9 +790,10 @@ k_local_newton(DevMesh M, DevMaps P, DevLocal L, NewtonParams np, const double* 
         rn = sqrt(block_sum(ss, red));
     }
     if (status == 0) {
+        // J and its LU at x*, in FP64, are kept for the exact tangent
         local_jacobian(M, P, n, rowbase, ebase, vp, L.jval);
         __syncthreads();
-        if (local_factor(P, L, np, i, n, rowbase, W, mult, sflag)) status = 3;
+        if (local_factor(P, L, np, i, n, rowbase, W, mult, sflag, true)) status = 3;
     }
     for (int a = threadIdx.x; a < n; a += blockDim.x) {
         const int row = rowbase + a;
@@ -506,6 +804,292 @@ k_local_newton(DevMesh M, DevMaps P, DevLocal L, NewtonParams np, const double* 
         L.its[i] = its;
         L.status[i] = status;
     }
+}
+
+// ----------------------------------------------------------------------------
+// Multi right-hand-side band solve X = J^{-1} R with the FP64 factors of
+// band_lu: one right-hand side per lane (column c = blockIdx.y*256 + tid).
+// Each lane keeps its forward window (KL+1 rows) and its backward window of
+// partial sums (KW+1 rows) in registers, so the sweeps need no cross-lane
+// traffic; the coefficients of MR_CH steps (pivots, L columns, U columns with
+// the reciprocal of the diagonal) are staged through LDS by the whole
+// workgroup, double-buffered, and read as broadcasts.  The forward results
+// go to the per-column scratch fwd (row-major, ld = ldf).
+// KL >= kl and KW >= kl + ku are compile-time window sizes.
+// ----------------------------------------------------------------------------
+constexpr int MR_CH = 8;
+constexpr int MR_THREADS = 256;
+
+// RHS columns given as sorted (row, value) lists, kept in registers.
+template <int MAXE>
+struct MrhsSparseSrc {
+    int re[MAXE];
+    double ve[MAXE];
+    __device__ __forceinline__ void init(const int* __restrict__ ptr, const int* __restrict__ row,
+                                         const int* __restrict__ slot,
+                                         const double* __restrict__ val, int c, bool valid) {
+        const int b = valid ? ptr[c] : 0, e = valid ? ptr[c + 1] : 0;
+#pragma unroll
+        for (int q = 0; q < MAXE; ++q) {
+            re[q] = (b + q < e) ? row[b + q] : INT_MAX;
+            ve[q] = (b + q < e) ? val[slot[b + q]] : 0.0;
+        }
+    }
+    __device__ __forceinline__ double take(int r) {
+        if (re[0] != r) return 0.0;
+        const double v = ve[0];
+#pragma unroll
+        for (int q = 0; q + 1 < MAXE; ++q) {
+            re[q] = re[q + 1];
+            ve[q] = ve[q + 1];
+        }
+        re[MAXE - 1] = INT_MAX;
+        return v;
+    }
+};
+
+struct MrhsIdentitySrc {
+    int c;
+    __device__ __forceinline__ double take(int r) const { return r == c ? 1.0 : 0.0; }
+};
+
+template <int KL, int KW, class Src, class Put>
+__device__ __forceinline__ void band_solve_mrhs(int n, int kl, int ku,
+                                                const double* __restrict__ Uf,
+                                                const double* __restrict__ Lf,
+                                                const int* __restrict__ piv, Src& src,
+                                                bool valid, int col, double* __restrict__ fwd,
+                                                int ldf, double* stage, int* sint, Put put) {
+    constexpr int CH = MR_CH, NT = MR_THREADS;
+    constexpr int FROW = KL, BROW = KW + 1;
+    constexpr int PF = (CH * BROW + NT - 1) / NT;  // staged doubles per thread
+    const int tid = threadIdx.x;
+    const int ldu = kl + ku + 1, ldl = kl > 1 ? kl : 1;
+    const int nch = (n + CH - 1) / CH;
+    double pre[PF];
+    int prei = 0;
+    // ---------------------------------------------------------- forward sweep
+    auto fload = [&](int ch) {
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int idx = tid + q * NT;
+            double v = 0.0;
+            if (idx < CH * FROW) {
+                const int st = idx / FROW, j = idx - st * FROW;
+                const int k = ch * CH + st;
+                if (k < n && j < kl && k + 1 + j < n) v = Lf[(size_t)k * ldl + j];
+            }
+            pre[q] = v;
+        }
+        prei = 0;
+        if (tid < CH) {
+            const int k = ch * CH + tid;
+            prei = k < n ? piv[k] : k;
+        }
+    };
+    auto fstore = [&](int slot) {
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int idx = tid + q * NT;
+            if (idx < CH * FROW) stage[slot * CH * BROW + idx] = pre[q];
+        }
+        if (tid < CH) sint[slot * CH + tid] = prei;
+    };
+    double x[KL + 1];
+#pragma unroll
+    for (int j = 0; j <= KL; ++j) x[j] = (j < n) ? src.take(j) : 0.0;
+    fload(0);
+    fstore(0);
+    if (nch > 1) fload(1);
+    __syncthreads();
+    for (int ch = 0; ch < nch; ++ch) {
+        const int slot = ch & 1;
+        const double* L0 = stage + slot * CH * BROW;
+#pragma unroll
+        for (int st = 0; st < CH; ++st) {
+            const int k = ch * CH + st;
+            if (k < n) {
+                const int d = sint[slot * CH + st] - k;
+                if (d != 0) {
+#pragma unroll
+                    for (int q = 1; q <= KL; ++q)
+                        if (q == d) {
+                            const double t = x[0];
+                            x[0] = x[q];
+                            x[q] = t;
+                        }
+                }
+                const double x0 = x[0];
+                if (valid) fwd[(size_t)k * ldf + col] = x0;
+                const double* Lk = L0 + st * FROW;
+#pragma unroll
+                for (int j = 0; j < KL; ++j) x[j] = x[j + 1] - Lk[j] * x0;
+                x[KL] = (k + KL + 1 < n) ? src.take(k + KL + 1) : 0.0;
+            }
+        }
+        if (ch + 1 < nch) {
+            fstore((ch + 1) & 1);
+            if (ch + 2 < nch) fload(ch + 2);
+        }
+        lds_barrier();
+    }
+    __syncthreads();  // forward results visible in HBM to this workgroup
+    // --------------------------------------------------------- backward sweep
+    // chunk ch covers steps k = n-1-ch*CH-st, st = 0..CH-1
+    auto bload = [&](int ch) {
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int idx = tid + q * NT;
+            double v = 0.0;
+            if (idx < CH * BROW) {
+                const int st = idx / BROW, j = idx - st * BROW;
+                const int k = n - 1 - ch * CH - st;
+                if (k >= 0) {
+                    if (j == 0) v = 1.0 / Uf[(size_t)k * ldu];
+                    else if (j - 1 < min(kl + ku, k)) v = Uf[(size_t)k * ldu + j];
+                }
+            }
+            pre[q] = v;
+        }
+    };
+    auto bstore = [&](int slot) {
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int idx = tid + q * NT;
+            if (idx < CH * BROW) stage[slot * CH * BROW + idx] = pre[q];
+        }
+    };
+    double p[KW + 1];
+#pragma unroll
+    for (int j = 0; j <= KW; ++j) {
+        const int r = n - 1 - j;
+        p[j] = (valid && r >= 0) ? fwd[(size_t)r * ldf + col] : 0.0;
+    }
+    double ent[CH], entn[CH];
+    auto eload = [&](int ch, double* e) {
+#pragma unroll
+        for (int st = 0; st < CH; ++st) {
+            const int r = n - 1 - ch * CH - st - 1 - KW;
+            e[st] = (valid && r >= 0) ? fwd[(size_t)r * ldf + col] : 0.0;
+        }
+    };
+    bload(0);
+    bstore(0);
+    if (nch > 1) bload(1);
+    eload(0, ent);
+    __syncthreads();
+    for (int ch = 0; ch < nch; ++ch) {
+        const int slot = ch & 1;
+        const double* U0 = stage + slot * CH * BROW;
+        if (ch + 1 < nch) eload(ch + 1, entn);
+#pragma unroll
+        for (int st = 0; st < CH; ++st) {
+            const int k = n - 1 - ch * CH - st;
+            if (k >= 0) {
+                const double* Uk = U0 + st * BROW;
+                const double y = p[0] * Uk[0];
+                put(k, y);
+#pragma unroll
+                for (int j = 0; j < KW; ++j) p[j] = p[j + 1] - Uk[1 + j] * y;
+                p[KW] = ent[st];
+            }
+        }
+#pragma unroll
+        for (int st = 0; st < CH; ++st) ent[st] = entn[st];
+        if (ch + 1 < nch) {
+            bstore((ch + 1) & 1);
+            if (ch + 2 < nch) bload(ch + 2);
+        }
+        lds_barrier();
+    }
+}
+
+// W_i = (J_ii^{-1} B_i) on the owned rows of subdomain i (row-major, ld =
+// |Gamma_i|), with J, B at the converged local state: the exact tangent's
+// local term P~_i J_ii^{-1} B_i v_Gamma_i (eqs. 6, 7) becomes a GEMV.
+template <int KL, int KW>
+__global__ void __launch_bounds__(MR_THREADS)
+k_tangent_prep(DevMaps P, DevLocal L, DevTangent Tg) {
+    extern __shared__ double smem[];
+    __shared__ int sint[2 * MR_CH];
+    const int i = P.order[blockIdx.x];
+    const int rowbase = P.off_n[i], n = P.off_n[i + 1] - rowbase;
+    const int gbase = P.off_g[i], ng = P.off_g[i + 1] - gbase;
+    const int kl = P.kl[i], ku = P.ku[i];
+    const int col = blockIdx.y * MR_THREADS + threadIdx.x;
+    const bool valid = col < ng;
+    if ((int)blockIdx.y * MR_THREADS >= ng) return;  // uniform over the block
+    MrhsSparseSrc<NLS_MAX_BCOL> src;
+    src.init(Tg.bptr + gbase, Tg.brow, Tg.bslot, L.jval, col, valid);
+    double* W = Tg.W + Tg.off_W[i];
+    const int* rowown = Tg.rowown + rowbase;
+    auto put = [&](int k, double y) {
+        const int o = rowown[k];
+        if (valid && o >= 0) W[(size_t)o * ng + col] = y;
+    };
+    band_solve_mrhs<KL, KW>(n, kl, ku, L.Uf + P.off_u[i], L.Lf + P.off_l[i], L.piv + rowbase, src,
+                            valid, col, Tg.fwd + Tg.off_F[i], ng, smem, sint, put);
+}
+
+// z[owned rows of i] = W_i v_Gamma_i: streams W once (HBM-bound).  Grid
+// (nsub, QS): block q of subdomain i takes a contiguous quarter of its rows.
+__global__ void __launch_bounds__(256)
+k_tangent_gemv(DevMaps P, DevTangent Tg, const double* __restrict__ v, double* __restrict__ z) {
+    extern __shared__ double vg[];
+    const int i = blockIdx.x;
+    const int gbase = P.off_g[i], ng = P.off_g[i + 1] - gbase;
+    const int ob = Tg.off_own[i], no = Tg.off_own[i + 1] - ob;
+    for (int j = threadIdx.x; j < ng; j += blockDim.x) vg[j] = v[P.g2g[gbase + j]];
+    __syncthreads();
+    const double* W = Tg.W + Tg.off_W[i];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int r0 = (int)(((int64_t)no * blockIdx.y) / gridDim.y);
+    const int r1 = (int)(((int64_t)no * (blockIdx.y + 1)) / gridDim.y);
+    const int rowbase = P.off_n[i];
+    for (int r = r0 + wv * 4; r < r1; r += nw * 4) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int j = lane; j < ng; j += 64) {
+            const double x = vg[j];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (r + q < r1) acc[q] += W[(size_t)(r + q) * ng + j] * x;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double a = wave_sum(acc[q]);
+            if (lane == 0 && r + q < r1) z[rowbase + Tg.ownrow[ob + r + q]] = a;
+        }
+    }
+}
+
+// A0^{-1} (band order, row-major) from the coarse LU: identity right-hand
+// sides, 256 columns per block.
+template <int KL, int KW>
+__global__ void __launch_bounds__(MR_THREADS) k_coarse_inverse(DevCoarse C) {
+    extern __shared__ double smem[];
+    __shared__ int sint[2 * MR_CH];
+    const int n = C.n0;
+    const int col = blockIdx.x * MR_THREADS + threadIdx.x;
+    const bool valid = col < n;
+    MrhsIdentitySrc src{valid ? col : -1};
+    double* Ainv = C.a0inv;
+    auto put = [&](int k, double y) {
+        if (valid) Ainv[(size_t)k * n + col] = y;
+    };
+    band_solve_mrhs<KL, KW>(n, C.a0kl, C.a0ku, C.a0U, C.a0L, C.a0piv, src, valid, col, C.a0fwd, n,
+                            smem, sint, put);
+}
+
+// y = A x for a dense row-major n x n matrix: one wavefront per row.
+__global__ void __launch_bounds__(256)
+k_dense_gemv(int n, const double* __restrict__ A, const double* __restrict__ x, double* __restrict__ y) {
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (row >= n) return;
+    const double* a = A + (size_t)row * n;
+    double acc = 0.0;
+    for (int j = lane; j < n; j += 64) acc += a[j] * x[j];
+    acc = wave_sum(acc);
+    if (lane == 0) y[row] = acc;
 }
 
 // Local part of the exact tangent: z_i = J_ii^{-1} (B_i v_Gamma_i), with J,
@@ -641,7 +1225,7 @@ template <int NPL>
 __global__ void __launch_bounds__(NLS_BLOCK)
 k_gdsw_extend(DevMesh M, DevCoarse C) {
     extern __shared__ double smem[];
-    __shared__ int sflag[4];
+    __shared__ int sflag[20];
     const int i = blockIdx.x;
     const int cb = C.off_c[i], nc = C.off_c[i + 1] - cb;
     const int k0 = C.off_k[i], nk = C.off_k[i + 1] - k0;
@@ -679,7 +1263,7 @@ k_gdsw_extend(DevMesh M, DevCoarse C) {
         }
     }
     __syncthreads();
-    if (band_lu<double>(ni, kl, ku, C.iptr + ib, C.icol, C.ival, W, mult, sflag,
+    if (band_lu_auto<double>(ni, kl, ku, C.iptr + ib, C.icol, C.ival, W, mult, sflag,
                         C.iU + C.off_iu[i], C.iL + C.off_il[i], C.ipiv + ib)) {
         if (threadIdx.x == 0) atomicOr(C.flag, 1);
         return;
@@ -857,13 +1441,13 @@ template <int NPL>
 __global__ void __launch_bounds__(NLS_BLOCK)
 k_coarse_lu(DevCoarse C, int factor) {
     extern __shared__ double smem[];
-    __shared__ int sflag[4];
+    __shared__ int sflag[20];
     const int n = C.n0, kl = C.a0kl, ku = C.a0ku;
     double* b = smem;
     double* mult = b + n;
     double* W = mult + ((kl > 1 ? kl : 1) + 1);
     if (factor) {
-        if (band_lu<double>(n, kl, ku, C.a0ptr, C.a0col, C.a0val, W, mult, sflag, C.a0U, C.a0L,
+        if (band_lu_auto<double>(n, kl, ku, C.a0ptr, C.a0col, C.a0val, W, mult, sflag, C.a0U, C.a0L,
                             C.a0piv)) {
             if (threadIdx.x == 0) atomicOr(C.flag, 2);
         }
@@ -895,9 +1479,9 @@ __global__ void __launch_bounds__(NLS_BLOCK) k_coarse_update(DevCoarse C) {
 }
 
 // cout[k] = rhs[perm[k]] (band order back to coarse ids).
-__global__ void k_coarse_scatter(DevCoarse C, double* __restrict__ cout) {
+__global__ void k_coarse_scatter(DevCoarse C, const double* __restrict__ src, double* __restrict__ cout) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < C.n0) cout[k] = C.rhs[C.perm[k]];
+    if (k < C.n0) cout[k] = src[C.perm[k]];
 }
 
 // ----------------------------------------------------------------------------
@@ -1110,8 +1694,50 @@ hipError_t launch_coarse_update(const DevCoarse& C, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_coarse_scatter(const DevCoarse& C, double* cout, hipStream_t s) {
-    k_coarse_scatter<<<nblocks(C.n0), NLS_BLOCK, 0, s>>>(C, cout);
+hipError_t launch_coarse_scatter(const DevCoarse& C, const double* src, double* cout, hipStream_t s) {
+    k_coarse_scatter<<<nblocks(C.n0), NLS_BLOCK, 0, s>>>(C, src ? src : C.rhs, cout);
+    return hipGetLastError();
+}
+
+// window buckets (KL, KW) of the multi-RHS solve
+#define NLS_MR_BUCKETS(X) X(16, 32) X(24, 48) X(32, 64) X(40, 80) X(48, 96)
+
+int mrhs_bucket_kl(int kl, int ku) {
+    const int need = std::max(kl, (kl + ku + 1) / 2);
+    const int b = (need + 7) / 8 * 8;
+    return b < 16 ? 16 : b;
+}
+
+int mrhs_lds_bytes(int kl_bucket) { return 2 * MR_CH * (2 * kl_bucket + 1) * 8; }
+
+hipError_t launch_tangent_prep(const DevMaps& P, const DevLocal& L, const DevTangent& Tg,
+                               int kl_bucket, int max_ng, hipStream_t s) {
+    dim3 grid(P.nsub, (max_ng + MR_THREADS - 1) / MR_THREADS);
+    const int lds = mrhs_lds_bytes(kl_bucket);
+#define NLS_TP(A, B)                                                                      if (kl_bucket == A) {                                                                     k_tangent_prep<A, B><<<grid, MR_THREADS, lds, s>>>(P, L, Tg);                         return hipGetLastError();                                                         }
+    NLS_MR_BUCKETS(NLS_TP)
+#undef NLS_TP
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_tangent_gemv(const DevMaps& P, const DevTangent& Tg, const double* v, double* z,
+                               int max_ng, hipStream_t s) {
+    dim3 grid(P.nsub, 4);
+    k_tangent_gemv<<<grid, 256, max_ng * 8, s>>>(P, Tg, v, z);
+    return hipGetLastError();
+}
+
+hipError_t launch_coarse_inverse(const DevCoarse& C, int kl_bucket, hipStream_t s) {
+    const int nb = (C.n0 + MR_THREADS - 1) / MR_THREADS;
+    const int lds = mrhs_lds_bytes(kl_bucket);
+#define NLS_CI(A, B)                                                                      if (kl_bucket == A) {                                                                     k_coarse_inverse<A, B><<<nb, MR_THREADS, lds, s>>>(C);                                return hipGetLastError();                                                         }
+    NLS_MR_BUCKETS(NLS_CI)
+#undef NLS_CI
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_dense_gemv(int n, const double* A, const double* x, double* y, hipStream_t s) {
+    k_dense_gemv<<<(n + 3) / 4, 256, 0, s>>>(n, A, x, y);
     return hipGetLastError();
 }
 

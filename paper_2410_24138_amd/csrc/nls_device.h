@@ -44,6 +44,16 @@ struct DevLocal {
     int* status;                // per subdomain: 0 ok, 1 no convergence, 2 NaN, 3 zero pivot
 };
 
+// Exact-tangent tables and storage: W_i = (J_ii^{-1} B_i) on owned rows.
+#define NLS_MAX_BCOL 8
+struct DevTangent {
+    const int *bptr, *brow, *bslot;   // B_i by columns (packed over Gamma columns)
+    const int *off_own, *ownrow, *rowown;
+    const int64_t *off_W, *off_F;
+    double* W;                        // sum |owned_i| |Gamma_i|
+    double* fwd;                      // sum n_i |Gamma_i| (forward-sweep scratch)
+};
+
 struct NewtonParams {
     double rtol;                // relative to ||R_i F(u)||
     double abs_tol;             // eta * ||b||_inf (times sqrt(n_i) in the kernel)
@@ -75,6 +85,8 @@ struct DevCoarse {
     double* a0L;
     int* a0piv;
     double* rhs;                // n0, band order
+    double* a0inv;              // n0 x n0 inverse of A0 (band order, row-major)
+    double* a0fwd;              // n0 x n0 scratch of the inverse
     double* c;                  // n0, coarse iterate (coarse id order)
     double* w;                  // N: u - Phi c
     double* scal;               // device scalars: [0] ||G||, [1] max|dc|, [2] max|c|
@@ -109,7 +121,16 @@ hipError_t launch_coarse_assemble(const DevCoarse& C, int with_matrix, hipStream
 hipError_t launch_coarse_lu(const DevCoarse& C, int factor, int lds_bytes, int nb_per_lane,
                             hipStream_t s);
 hipError_t launch_coarse_update(const DevCoarse& C, hipStream_t s);
-hipError_t launch_coarse_scatter(const DevCoarse& C, double* cout, hipStream_t s);
+hipError_t launch_coarse_scatter(const DevCoarse& C, const double* src, double* cout, hipStream_t s);
+
+int mrhs_bucket_kl(int kl, int ku);
+int mrhs_lds_bytes(int kl_bucket);
+hipError_t launch_tangent_prep(const DevMaps& P, const DevLocal& L, const DevTangent& Tg,
+                               int kl_bucket, int max_ng, hipStream_t s);
+hipError_t launch_tangent_gemv(const DevMaps& P, const DevTangent& Tg, const double* v, double* z,
+                               int max_ng, hipStream_t s);
+hipError_t launch_coarse_inverse(const DevCoarse& C, int kl_bucket, hipStream_t s);
+hipError_t launch_dense_gemv(int n, const double* A, const double* x, double* y, hipStream_t s);
 
 // vector kernels for GMRES (deterministic reductions)
 hipError_t launch_mdot(const double* V, int64_t ld, int m, const double* w, int n,

@@ -7,9 +7,13 @@
 #include <string>
 #include <vector>
 
-// Band-window size of the LU kernels: a ring buffer of (kl+1) rows by
-// (kl+ku+1) columns.
-inline int band_window_doubles(int kl, int ku) { return (kl + 1) * (kl + ku + 1); }
+// Band-window size of the LU kernels (ring buffers): blocked panels of NB
+// columns need (NB+kl) x (NB+kl+ku); the unblocked form (kl+1) x (kl+ku+1).
+inline int band_window_doubles(int kl, int ku) {
+    if (kl + 16 <= 64) return (16 + kl) * (16 + kl + ku) + 16 * 16;
+    if (kl + 8 <= 64) return (8 + kl) * (8 + kl + ku) + 8 * 8;
+    return (kl + 1) * (kl + ku + 1);
+}
 // LDS of the fused local Newton kernel, in doubles:
 //   patch values (n + ng) | residual / step (n) | LU window | multipliers | scratch
 inline int local_lds_doubles(int n, int ng, int kl, int ku) {
@@ -54,6 +58,16 @@ struct HostMaps {
     std::vector<int64_t> off_l;    // offset (doubles) of the L factor, n_i*max(kl,1)
     int64_t factor_u_total = 0, factor_l_total = 0;
     std::vector<int> own_pidx;     // N: packed V row of the owner's copy of node g
+    // exact-tangent tables: B_i by columns, owned rows of each subdomain
+    std::vector<int> bptr;         // packed Gamma column -> [bptr, bptr+1) entries
+    std::vector<int> brow;         // local row of each B entry (ascending per column)
+    std::vector<int> bslot;        // CSR slot of the entry in jptr/jcol/jval
+    int max_bcol = 0;              // longest B column
+    std::vector<int> off_own;      // nsub+1: owned rows, packed
+    std::vector<int> ownrow;       // packed owned index -> local V row
+    std::vector<int> rowown;       // packed V row -> owned index in its subdomain, or -1
+    std::vector<int64_t> off_W;    // nsub+1: |owned_i| x |Gamma_i| tangent blocks
+    std::vector<int64_t> off_F;    // nsub+1: n_i x |Gamma_i| forward-sweep scratch
     std::vector<int> order;        // launch order of subdomains (largest first)
     std::vector<int> lds_doubles;  // per subdomain LDS need of the local Newton kernel
     int max_lds_doubles = 0;

@@ -176,6 +176,37 @@ int nls_build_maps(const HostMesh& m, const int* part, int nsub, int overlap,
         M.own_pidx[g] = (int)(it - M.l2g.begin());
     }
 
+    // B_i by columns (Gamma columns of the local CSR rows), owned rows
+    M.bptr.assign(1, 0);
+    M.off_own.assign(1, 0);
+    M.rowown.assign(M.l2g.size(), -1);
+    M.off_W.assign(1, 0);
+    M.off_F.assign(1, 0);
+    for (int i = 0; i < nsub; ++i) {
+        const int rb = M.off_n[i], n = M.off_n[i + 1] - rb, ng = M.off_g[i + 1] - M.off_g[i];
+        std::vector<std::vector<std::pair<int, int>>> colent(ng);
+        for (int a = 0; a < n; ++a)
+            for (int s = M.jptr[rb + a]; s < M.jptr[rb + a + 1]; ++s)
+                if (M.jcol[s] >= n) colent[M.jcol[s] - n].push_back({a, s});
+        for (int j = 0; j < ng; ++j) {
+            for (auto& e : colent[j]) {
+                M.brow.push_back(e.first);
+                M.bslot.push_back(e.second);
+            }
+            M.max_bcol = std::max(M.max_bcol, (int)colent[j].size());
+            M.bptr.push_back((int)M.brow.size());
+        }
+        int no = 0;
+        for (int a = 0; a < n; ++a)
+            if (owner[M.l2g[rb + a]] == i) {
+                M.rowown[rb + a] = no++;
+                M.ownrow.push_back(a);
+            }
+        M.off_own.push_back((int)M.ownrow.size());
+        M.off_W.push_back(M.off_W.back() + (int64_t)no * ng);
+        M.off_F.push_back(M.off_F.back() + (int64_t)n * ng);
+    }
+
     // factor storage and launch order
     M.off_u.assign(nsub + 1, 0);
     M.off_l.assign(nsub + 1, 0);

@@ -36,6 +36,7 @@ ADDITIVE = 1
 COARSE_NONE = 0
 COARSE_GDSW = 1
 MAX_OUTER = 64
+FLAG_PROFILE = 1
 
 # every symbol include/nls.h declares
 SYMBOLS = (
@@ -71,6 +72,8 @@ class Stats(ctypes.Structure):
         ("res_final", ctypes.c_double), ("ms_inner", ctypes.c_double),
         ("ms_coarse", ctypes.c_double), ("ms_gmres", ctypes.c_double),
         ("ms_other", ctypes.c_double), ("ms_total", ctypes.c_double),
+        ("n_local_launches", ctypes.c_int), ("ms_local_kernel", ctypes.c_double),
+        ("n_tangent_launches", ctypes.c_int), ("ms_tangent_kernel", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -276,6 +279,14 @@ class Solver:
         st = Stats()
         rc = self._check(self.lib.nls_solve(self.h, self._vp(u), 1, ctypes.byref(st)))
         return u, st.as_dict(), rc
+
+    def solve_(self, u):
+        """Outer Newton in place on a float64 device tensor u; returns stats."""
+        t = self.torch
+        assert u.dtype == t.float64 and u.is_cuda and u.is_contiguous() and u.numel() == self.N
+        st = Stats()
+        self._check(self.lib.nls_solve(self.h, self._vp(u), 1, ctypes.byref(st)))
+        return st.as_dict()
 
     def solve_host(self, u: np.ndarray):
         """Same on a host array (updated in place)."""
