@@ -410,8 +410,10 @@ extern "C" int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* el
     DevLocal L{};
     const size_t nrows = M.l2g.size();
     RC(h->alloc(G_MAPS, &L.jval, M.jcol.size()));
-    RC(h->alloc(G_MAPS, &L.Uf, (size_t)M.factor_u_total));
-    RC(h->alloc(G_MAPS, &L.Lf, (size_t)M.factor_l_total));
+    // factor arrays carry 1024 elements of padding: the multi-RHS solve reads
+    // up to its window size past a column's band (masked)
+    RC(h->alloc(G_MAPS, &L.Uf, (size_t)M.factor_u_total + 1024));
+    RC(h->alloc(G_MAPS, &L.Lf, (size_t)M.factor_l_total + 1024));
     if (mixed) {
         RC(h->alloc(G_MAPS, &L.Uf32, (size_t)M.factor_u_total));
         RC(h->alloc(G_MAPS, &L.Lf32, (size_t)M.factor_l_total));
@@ -461,7 +463,7 @@ extern "C" int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* el
     np.maxit = h->opt.inner_maxit;
     np.mixed = mixed ? 1 : 0;
     np.ir_maxit = 10;
-    np.ir_rtol = 1e-14;
+    np.ir_rtol = 1e-10;  // a Newton step needs no more; residuals stay FP64
     h->np = np;
     // GMRES workspace
     const int N = h->mesh.N;
@@ -568,6 +570,7 @@ extern "C" int nls_build_coarse(nls_handle* h, int kind) {
     const int64_t nphi = C.off_phi.back();
     RC(h->alloc(G_COARSE, &d.phi, (size_t)nphi));
     RC(h->alloc(G_COARSE, &d.zbuf, (size_t)nphi));
+    RC(h->alloc(G_COARSE, &d.ybuf, (size_t)nphi));
     RC(h->alloc(G_COARSE, &d.ival, C.icol.size()));
     RC(h->alloc(G_COARSE, &d.iU, (size_t)C.iu_total));
     RC(h->alloc(G_COARSE, &d.iL, (size_t)C.il_total));
@@ -575,8 +578,8 @@ extern "C" int nls_build_coarse(nls_handle* h, int kind) {
     RC(h->alloc(G_COARSE, &d.gblk, C.klist.size()));
     RC(h->alloc(G_COARSE, &d.ablk, (size_t)C.off_kk.back()));
     RC(h->alloc(G_COARSE, &d.a0val, C.a0col.size()));
-    RC(h->alloc(G_COARSE, &d.a0U, (size_t)C.n0 * (C.a0kl + C.a0ku + 1)));
-    RC(h->alloc(G_COARSE, &d.a0L, (size_t)C.n0 * std::max(C.a0kl, 1)));
+    RC(h->alloc(G_COARSE, &d.a0U, (size_t)C.n0 * (C.a0kl + C.a0ku + 1) + 1024));
+    RC(h->alloc(G_COARSE, &d.a0L, (size_t)C.n0 * std::max(C.a0kl, 1) + 1024));
     RC(h->alloc(G_COARSE, &d.a0piv, C.n0));
     RC(h->alloc(G_COARSE, &d.rhs, C.n0));
     RC(h->alloc(G_COARSE, &d.c, C.n0));
@@ -639,7 +642,7 @@ static int coarse_solve(nls_handle* h, const double* u, int* its_out) {
         if (gn <= tol) break;
         if (dprev >= 0.0 && dprev <= h->opt.stagnation * cmax) break;
         if (its == h->opt.inner_maxit) return fail(h, NLS_ELOCAL, "coarse Newton did not converge");
-        HIPCHK(launch_coarse_galerkin(h->dm, d, d.w, h->stream));
+        HIPCHK(launch_coarse_galerkin(h->dm, d, d.w, 0, h->stream));
         HIPCHK(launch_coarse_assemble(d, 1, h->stream));
         HIPCHK(launch_coarse_lu(d, 1, h->lds_coarse_lu, h->npl_coarse, h->stream));
         HIPCHK(launch_coarse_update(d, h->stream));
@@ -654,7 +657,7 @@ static int coarse_solve(nls_handle* h, const double* u, int* its_out) {
         ++its;
     }
     // Galerkin matrix and its LU at the converged point, for the tangent
-    HIPCHK(launch_coarse_galerkin(h->dm, d, d.w, h->stream));
+    HIPCHK(launch_coarse_galerkin(h->dm, d, d.w, 1, h->stream));
     HIPCHK(launch_coarse_assemble(d, 1, h->stream));
     HIPCHK(launch_coarse_lu(d, 1, h->lds_coarse_lu, h->npl_coarse, h->stream));
     if (h->coarse_inv) HIPCHK(launch_coarse_inverse(d, h->coarse_bucket, h->stream));
@@ -744,7 +747,7 @@ static int tangent(nls_handle* h, const double* v, double* y) {
     }
     if (two_level(h)) {
         DevCoarse& d = h->dc;
-        HIPCHK(launch_coarse_q(h->dm, d, d.w, v, 1, h->lds_coarse_q, h->stream));
+        HIPCHK(launch_coarse_ty(d, v, h->stream));
         HIPCHK(launch_coarse_assemble(d, 0, h->stream));
         if (h->coarse_inv) {
             HIPCHK(launch_dense_gemv(d.n0, d.a0inv, d.rhs, h->rhs2, h->stream));

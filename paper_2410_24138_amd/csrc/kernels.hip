@@ -1023,16 +1023,18 @@ k_tangent_prep(DevMaps P, DevLocal L, DevTangent Tg) {
     src.init(Tg.bptr + gbase, Tg.brow, Tg.bslot, L.jval, col, valid);
     double* W = Tg.W + Tg.off_W[i];
     const int* rowown = Tg.rowown + rowbase;
+    const int nown = Tg.off_own[i + 1] - Tg.off_own[i];
     auto put = [&](int k, double y) {
-        const int o = rowown[k];
-        if (valid && o >= 0) W[(size_t)o * ng + col] = y;
+        const int o = __builtin_amdgcn_readfirstlane(rowown[k]);
+        if (valid && o >= 0) W[(size_t)col * nown + o] = y;
     };
     band_solve_mrhs<KL, KW>(n, kl, ku, L.Uf + P.off_u[i], L.Lf + P.off_l[i], L.piv + rowbase, src,
                             valid, col, Tg.fwd + Tg.off_F[i], ng, smem, sint, put);
 }
 
-// z[owned rows of i] = W_i v_Gamma_i: streams W once (HBM-bound).  Grid
-// (nsub, QS): block q of subdomain i takes a contiguous quarter of its rows.
+// z[owned rows of i] = W_i v_Gamma_i: streams W (column-major, one owned
+// row per thread) once; HBM-bound.  Grid (nsub, QS) splits each
+// subdomain's rows over QS blocks.
 __global__ void __launch_bounds__(256)
 k_tangent_gemv(DevMaps P, DevTangent Tg, const double* __restrict__ v, double* __restrict__ z) {
     extern __shared__ double vg[];
@@ -1042,23 +1044,18 @@ k_tangent_gemv(DevMaps P, DevTangent Tg, const double* __restrict__ v, double* _
     for (int j = threadIdx.x; j < ng; j += blockDim.x) vg[j] = v[P.g2g[gbase + j]];
     __syncthreads();
     const double* W = Tg.W + Tg.off_W[i];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    const int r0 = (int)(((int64_t)no * blockIdx.y) / gridDim.y);
-    const int r1 = (int)(((int64_t)no * (blockIdx.y + 1)) / gridDim.y);
     const int rowbase = P.off_n[i];
-    for (int r = r0 + wv * 4; r < r1; r += nw * 4) {
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int j = lane; j < ng; j += 64) {
-            const double x = vg[j];
-#pragma unroll
-            for (int q = 0; q < 4; ++q)
-                if (r + q < r1) acc[q] += W[(size_t)(r + q) * ng + j] * x;
+    for (int r = blockIdx.y * blockDim.x + threadIdx.x; r < no; r += gridDim.y * blockDim.x) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int j = 0;
+        for (; j + 3 < ng; j += 4) {
+            a0 += W[(size_t)j * no + r] * vg[j];
+            a1 += W[(size_t)(j + 1) * no + r] * vg[j + 1];
+            a2 += W[(size_t)(j + 2) * no + r] * vg[j + 2];
+            a3 += W[(size_t)(j + 3) * no + r] * vg[j + 3];
         }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const double a = wave_sum(acc[q]);
-            if (lane == 0 && r + q < r1) z[rowbase + Tg.ownrow[ob + r + q]] = a;
-        }
+        for (; j < ng; ++j) a0 += W[(size_t)j * no + r] * vg[j];
+        z[rowbase + Tg.ownrow[ob + r]] = (a0 + a1) + (a2 + a3);
     }
 }
 
@@ -1362,9 +1359,11 @@ k_coarse_q(DevMesh M, DevCoarse C, const double* __restrict__ w, const double* _
     }
 }
 
-// Per subdomain Galerkin block A_i = Phi_i^T K_i(w) Phi_i (K_i: part-i elements).
+// Per subdomain Galerkin block A_i = Phi_i^T K_i(w) Phi_i (K_i: part-i
+// elements).  With with_y, also Y_i = K_i(w)^T Phi_i, so that the coarse
+// term of the tangent, Phi^T DF(u_0) v = sum_i Y_i^T v_i, is a GEMV.
 __global__ void __launch_bounds__(NLS_BLOCK)
-k_coarse_galerkin(DevMesh M, DevCoarse C, const double* __restrict__ w) {
+k_coarse_galerkin(DevMesh M, DevCoarse C, const double* __restrict__ w, int with_y) {
     const int i = blockIdx.x;
     const int cb = C.off_c[i], nc = C.off_c[i + 1] - cb;
     const int k0 = C.off_k[i], nk = C.off_k[i + 1] - k0;
@@ -1400,6 +1399,37 @@ k_coarse_galerkin(DevMesh M, DevCoarse C, const double* __restrict__ w) {
             }
         }
     }
+    if (with_y) {
+        double* y = C.ybuf + C.off_phi[i];
+        for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+            double* yr = y + (int64_t)c * nk;
+            for (int l = 0; l < nk; ++l) yr[l] = 0.0;
+            for (int t = C.cinc_ptr[cb + c]; t < C.cinc_ptr[cb + c + 1]; ++t) {
+                const int code = C.cinc[t];
+                const int e = eb + (code >> 2), pc = code & 3;
+                const int ge = C.ne_gid[e];
+                double uu[3];
+                int cn[3];
+                for (int a = 0; a < 3; ++a) {
+                    cn[a] = C.ne_conn[3 * e + a];
+                    uu[a] = w[C.cnode[cb + cn[a]]];
+                }
+                const double U = uu[0] + uu[1] + uu[2];
+                const double m = (U * U + uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2]) * (1.0 / 12.0);
+                const double kap = M.kappa[ge];
+                const double coef = kap * (1.0 + M.beta * m);
+                for (int a = 0; a < 3; ++a) {
+                    double gr[3];
+                    g_row(M.G6 + 6 * (size_t)ge, a, gr[0], gr[1], gr[2]);
+                    const double sa = gr[0] * uu[0] + gr[1] * uu[1] + gr[2] * uu[2];
+                    // K_T[a][pc]
+                    const double K = coef * gr[pc] + M.beta * kap * sa * (U + uu[pc]) * (1.0 / 6.0);
+                    const double* pr = ph + (int64_t)cn[a] * nk;
+                    for (int l = 0; l < nk; ++l) yr[l] += K * pr[l];
+                }
+            }
+        }
+    }
     __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int kk = wv; kk < nk * nk; kk += nw) {
@@ -1408,6 +1438,22 @@ k_coarse_galerkin(DevMesh M, DevCoarse C, const double* __restrict__ w) {
         for (int a = lane; a < nc; a += 64) acc += ph[(int64_t)a * nk + k] * z[(int64_t)a * nk + l];
         acc = wave_sum(acc);
         if (lane == 0) C.ablk[C.off_kk[i] + kk] = acc;
+    }
+}
+
+// gblk_i = Y_i^T v on the closure of subdomain i (coarse term of the tangent).
+__global__ void __launch_bounds__(NLS_BLOCK)
+k_coarse_ty(DevCoarse C, const double* __restrict__ v) {
+    const int i = blockIdx.x;
+    const int cb = C.off_c[i], nc = C.off_c[i + 1] - cb;
+    const int k0 = C.off_k[i], nk = C.off_k[i + 1] - k0;
+    const double* y = C.ybuf + C.off_phi[i];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int k = wv; k < nk; k += nw) {
+        double acc = 0.0;
+        for (int c = lane; c < nc; c += 64) acc += y[(int64_t)c * nk + k] * v[C.cnode[cb + c]];
+        acc = wave_sum(acc);
+        if (lane == 0) C.gblk[k0 + k] = acc;
     }
 }
 
@@ -1513,12 +1559,14 @@ k_mdot_partial(const double* __restrict__ V, int64_t ld, int m, const double* __
     }
 }
 
-__global__ void k_mdot_final(const double* __restrict__ partial, int nb, int m, double* __restrict__ out) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= m) return;
+__global__ void __launch_bounds__(256)
+k_mdot_final(const double* __restrict__ partial, int nb, int m, double* __restrict__ out) {
+    __shared__ double red[24];
+    const int j = blockIdx.x;
     double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += partial[(int64_t)b * m + j];
-    out[j] = s;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) s += partial[(int64_t)b * m + j];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) out[j] = s;
 }
 
 // w -= sign * sum_j h[j] V[j]  (sign = +1)   or  w += sum_j h[j] V[j] (sign = -1)
@@ -1668,8 +1716,13 @@ hipError_t launch_coarse_q(const DevMesh& M, const DevCoarse& C, const double* w
 }
 
 hipError_t launch_coarse_galerkin(const DevMesh& M, const DevCoarse& C, const double* w,
-                                  hipStream_t s) {
-    k_coarse_galerkin<<<C.nsub, NLS_BLOCK, 0, s>>>(M, C, w);
+                                  int with_y, hipStream_t s) {
+    k_coarse_galerkin<<<C.nsub, NLS_BLOCK, 0, s>>>(M, C, w, with_y);
+    return hipGetLastError();
+}
+
+hipError_t launch_coarse_ty(const DevCoarse& C, const double* v, hipStream_t s) {
+    k_coarse_ty<<<C.nsub, NLS_BLOCK, 0, s>>>(C, v);
     return hipGetLastError();
 }
 
@@ -1722,7 +1775,7 @@ hipError_t launch_tangent_prep(const DevMaps& P, const DevLocal& L, const DevTan
 
 hipError_t launch_tangent_gemv(const DevMaps& P, const DevTangent& Tg, const double* v, double* z,
                                int max_ng, hipStream_t s) {
-    dim3 grid(P.nsub, 4);
+    dim3 grid(P.nsub, 2);
     k_tangent_gemv<<<grid, 256, max_ng * 8, s>>>(P, Tg, v, z);
     return hipGetLastError();
 }
@@ -1744,7 +1797,7 @@ hipError_t launch_dense_gemv(int n, const double* A, const double* x, double* y,
 hipError_t launch_mdot(const double* V, int64_t ld, int m, const double* w, int n,
                        double* partial, double* out, int nb, hipStream_t s) {
     k_mdot_partial<<<nb, NLS_BLOCK, 0, s>>>(V, ld, m, w, n, partial);
-    k_mdot_final<<<nblocks(m, 64), 64, 0, s>>>(partial, nb, m, out);
+    k_mdot_final<<<m, 256, 0, s>>>(partial, nb, m, out);
     return hipGetLastError();
 }
 

@@ -74,6 +74,7 @@ struct DevCoarse {
     int a0kl, a0ku;
     double* phi;                // dense |C_i| x |K_i| blocks
     double* zbuf;               // same shape: DF Phi rows (scratch)
+    double* ybuf;               // same shape: DF^T Phi at the converged coarse point
     double* ival;               // interior CSR values (setup scratch)
     double* iU;                 // interior factors (setup scratch)
     double* iL;
@@ -116,7 +117,8 @@ hipError_t launch_coarse_w(const DevMesh& M, const DevCoarse& C, const double* u
 hipError_t launch_coarse_q(const DevMesh& M, const DevCoarse& C, const double* w,
                            const double* v, int mode, int lds_bytes, hipStream_t s);
 hipError_t launch_coarse_galerkin(const DevMesh& M, const DevCoarse& C, const double* w,
-                                  hipStream_t s);
+                                  int with_y, hipStream_t s);
+hipError_t launch_coarse_ty(const DevCoarse& C, const double* v, hipStream_t s);
 hipError_t launch_coarse_assemble(const DevCoarse& C, int with_matrix, hipStream_t s);
 hipError_t launch_coarse_lu(const DevCoarse& C, int factor, int lds_bytes, int nb_per_lane,
                             hipStream_t s);
