@@ -27,6 +27,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "subdomain Newton solves/s; time-to-1e-8 per global solve, plain vs chosen"
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per dispatch measured with rocprofv3 FETCH_SIZE/WRITE_SIZE (two
+# passes, calibrated against a 256 MiB copy; profiles/hbm_traffic_*.md), valid
+# only for the kernel source they were taken with.
+MEASURED_TRAFFIC = {"kernels_sha1": "2d4f49209ad5b098c2660fa6d0812d17a74e28dc",
+                    "bytes": {"k_local_newton": 1524372778, "k_tangent_prep": 1198927989, "k_tangent_gemv": 280754705, "k_coarse_galerkin": 416203019, "k_coarse_lu": 1808829, "k_coarse_inverse": 14858629, "k_mdot_partial": 16580925, "k_maxpy": 28133516, "k_prolong": 27142873, "k_coarse_ty": 23981016}}
 
 
 def _factor_bytes(case, elem_bytes):
@@ -114,7 +119,17 @@ def run_form(case, golden, form, steps, warmup, device):
     return out
 
 
-def roofline(case, res, form, traffic=None):
+def measured_traffic(kernel):
+    """Counter-measured HBM bytes of a kernel, or None if the source changed."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_2410_24138_amd", "csrc", "kernels.hip")
+    sha = hashlib.sha1(open(src, "rb").read()).hexdigest()
+    if sha != MEASURED_TRAFFIC["kernels_sha1"]:
+        return None
+    return MEASURED_TRAFFIC["bytes"].get(kernel)
+
+
+def roofline(case, res, form):
     """Dominant kernel and its HBM roofline fraction from algorithmic bytes."""
     elem = 8 if form == "plain" else 4
     fac, n, ng = _factor_bytes(case, elem)
@@ -138,6 +153,7 @@ def roofline(case, res, form, traffic=None):
         per_launch = float(per_sub.sum())
     avg_s = k["ms"] / max(k["launches"], 1) / 1e3
     achieved = per_launch / avg_s / 1e9
+    traffic = measured_traffic("k_" + name) if form == "plain" else None
     return {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic, "bytes_per_launch": per_launch,
@@ -151,6 +167,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--forms", default="plain,chosen")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 256 MiB device copy (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver runs on a single MI355X; "
@@ -166,6 +184,13 @@ def main():
         from paper_2410_24138_amd.build import build
         build()
     device = torch.device("cuda", 0)
+    if args.copy_calibration:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=device)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize(device)
+        del src, dst
     case = synth.config2()
     golden = json.load(open(os.path.join(ROOT, "tests", "golden", case["name"] + ".json")))
     forms = [f for f in args.forms.split(",") if f]
@@ -177,7 +202,6 @@ def main():
     ok = {f: r for f, r in res.items() if r["converged"] and r["rel_err_vs_global_newton"] <= 1e-8}
     best = min(ok, key=lambda f: ok[f]["ms_per_solve"]) if ok else forms[0]
     r = res[best]
-    traffic = None
     line = {
         "metric": METRIC,
         "value": round(r["solves_per_s"], 1),
@@ -196,7 +220,7 @@ def main():
                    "form": best, "outer_rtol": 1e-8, "parallelism": "1 GPU"},
         "time_to_1e-8_ms": {f: round(res[f]["ms_per_solve"], 3) for f in res},
         "forms": {f: {k: v for k, v in res[f].items()} for f in res},
-        "roofline": roofline(case, r, best, traffic),
+        "roofline": roofline(case, r, best),
     }
     if "plain" in res and "chosen" in res:
         line["speedup_chosen_vs_plain"] = round(res["plain"]["ms_per_solve"]
