@@ -119,6 +119,66 @@ def run_form(case, golden, form, steps, warmup, device):
     return out
 
 
+def run_batch(steps, warmup, device, n_inst=32):
+    """Batch of independent diffusion solves (grids 128..384, 8..16 boxes per
+    side, overlap 2, GDSW, kappa = exp(g) with a unit-variance random field):
+    one handle over all instances (every local solve of every instance in the
+    same launches, block-diagonal coarse level) vs the instances solved one
+    after another."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2410_24138_amd import Solver, nls
+    cases = [synth.config4_instance(b) for b in range(n_inst)]
+    joined = synth.concat_cases(cases, name=f"diffusion_batch_{n_inst}_grf")
+    sj = Solver(joined, flags=nls.FLAG_PROFILE)
+    N = sj.N
+    for _ in range(warmup):
+        sj.solve_(torch.zeros(N, dtype=torch.float64, device=device))
+    us = [torch.zeros(N, dtype=torch.float64, device=device) for _ in range(steps)]
+    torch.cuda.synchronize(device)
+    t0 = time.perf_counter()
+    st_j = [sj.solve_(u) for u in us]
+    torch.cuda.synchronize(device)
+    t_joined = (time.perf_counter() - t0) / steps
+    sj.close()
+    hs = [Solver(c) for c in cases]
+    for _ in range(warmup):
+        for h in hs:
+            h.solve_(torch.zeros(h.N, dtype=torch.float64, device=device))
+    useq = [[torch.zeros(h.N, dtype=torch.float64, device=device) for h in hs]
+            for _ in range(steps)]
+    torch.cuda.synchronize(device)
+    t0 = time.perf_counter()
+    st_s = [[h.solve_(u) for h, u in zip(hs, row)] for row in useq]
+    torch.cuda.synchronize(device)
+    t_seq = (time.perf_counter() - t0) / steps
+    # per-instance agreement of the two solutions
+    uj = us[0].cpu().numpy()
+    off, diffs = 0, []
+    for h, u in zip(hs, useq[0]):
+        ui = u.cpu().numpy()
+        diffs.append(float(np.linalg.norm(uj[off:off + h.N] - ui) / np.linalg.norm(ui)))
+        off += h.N
+    solves_j = sum(s["local_solves"] for s in st_j) / steps
+    solves_s = sum(s["local_solves"] for row in st_s for s in row) / steps
+    return {
+        "metric": "subdomain Newton solves/s (batch of independent solves)",
+        "workload": joined["name"], "instances": n_inst, "nodes": N,
+        "subdomains": int(joined["n_sub"]),
+        "one_launch_per_bucket": {"ms_per_batch": round(1e3 * t_joined, 2),
+                                  "solves_per_s": round(solves_j / t_joined, 1),
+                                  "outer_its": st_j[-1]["outer_its"],
+                                  "gmres_its": st_j[-1]["gmres_its"],
+                                  "converged": all(s["converged"] for s in st_j)},
+        "one_instance_after_another": {"ms_per_batch": round(1e3 * t_seq, 2),
+                                       "solves_per_s": round(solves_s / t_seq, 1),
+                                       "converged": all(s["converged"] for row in st_s for s in row)},
+        "speedup": round(t_seq / t_joined, 3),
+        "max_rel_diff_joined_vs_separate": max(diffs),
+    }
+
+
 def measured_traffic(kernel):
     """Counter-measured HBM bytes of a kernel, or None if the source changed."""
     import hashlib
@@ -166,6 +226,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--forms", default="plain,chosen")
+    ap.add_argument("--workload", default="diffusion512", choices=["diffusion512", "batch"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy (reference for HBM counters)")
@@ -191,6 +252,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize(device)
         del src, dst
+    if args.workload == "batch":
+        print(json.dumps(run_batch(args.steps, args.warmup, device)), flush=True)
+        return
     case = synth.config2()
     golden = json.load(open(os.path.join(ROOT, "tests", "golden", case["name"] + ".json")))
     forms = [f for f in args.forms.split(",") if f]

@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <numeric>
 #include <string>
 #include <vector>
 
@@ -59,7 +60,10 @@ struct nls_handle {
     bool tangent_w = false;       // W_i = J^{-1} B on owned rows (else per-apply solves)
     int tangent_bucket = 0, max_ng = 0;
     bool coarse_inv = false;      // explicit A0^{-1} for the tangent
-    int coarse_bucket = 0;
+    int coarse_bucket = 0, max_block = 0;
+    // size buckets of the local-solve launches: [start, end) in the launch
+    // order, LDS bytes and solve width of each
+    std::vector<int> bk_start, bk_end, bk_lds, bk_npl;
     double* rhs2 = nullptr;
     NewtonParams np{};
     double b_inf = 0.0, phib_inf = 0.0;
@@ -376,6 +380,33 @@ extern "C" int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* el
     }
     if (lds > 160 * 1024) return fail(h, NLS_ELIMIT, "subdomain too large for the LDS working set");
     h->lds_local = lds;
+    // launch order: largest LDS first; size buckets of equal occupancy (WGs
+    // per CU allowed by LDS), one launch each
+    std::vector<int> sub_lds(M.nsub), sub_band(M.nsub);
+    for (int i = 0; i < M.nsub; ++i) {
+        int n = M.off_n[i + 1] - M.off_n[i], ng = M.off_g[i + 1] - M.off_g[i];
+        int dbl = (n + ng) + n + (mixed ? 2 * n : 0) + 24 + std::max(M.kl[i], 1) + 1;
+        sub_lds[i] = dbl * 8 + band_window_doubles(M.kl[i], M.ku[i]) * 8;
+        sub_band[i] = std::max(M.kl[i], M.kl[i] + M.ku[i]);
+    }
+    std::vector<int> lorder(M.nsub);
+    std::iota(lorder.begin(), lorder.end(), 0);
+    std::stable_sort(lorder.begin(), lorder.end(), [&](int a, int b) { return sub_lds[a] > sub_lds[b]; });
+    h->maps.order = lorder;
+    h->bk_start.clear(); h->bk_end.clear(); h->bk_lds.clear(); h->bk_npl.clear();
+    auto occ = [](int bytes) { return std::min(8, std::max(1, (160 * 1024) / std::max(bytes, 1))); };
+    for (int p = 0; p < M.nsub;) {
+        int q = p, band = 0;
+        while (q < M.nsub && occ(sub_lds[lorder[q]]) == occ(sub_lds[lorder[p]])) {
+            band = std::max(band, sub_band[lorder[q]]);
+            ++q;
+        }
+        h->bk_start.push_back(p);
+        h->bk_end.push_back(q);
+        h->bk_lds.push_back(sub_lds[lorder[p]]);
+        h->bk_npl.push_back(npl_for(band));
+        p = q;
+    }
     h->lds_tangent = (maxn + (mixed ? 2 * maxn : 0) + 24) * 8;
     h->npl_local = npl_for(std::max(maxkl, maxband));
     // tables
@@ -397,7 +428,7 @@ extern "C" int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* el
     RC(h->upload(G_MAPS, &jcol, M.jcol));
     RC(h->upload(G_MAPS, &kl, M.kl));
     RC(h->upload(G_MAPS, &ku, M.ku));
-    RC(h->upload(G_MAPS, &order, M.order));
+    RC(h->upload(G_MAPS, &order, h->maps.order));
     RC(h->upload(G_MAPS, &own, M.own_pidx));
     RC(h->upload(G_MAPS, &off_u, M.off_u));
     RC(h->upload(G_MAPS, &off_l, M.off_l));
@@ -435,7 +466,7 @@ extern "C" int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* el
             h->max_ng = std::max(h->max_ng, M.off_g[i + 1] - M.off_g[i]);
         }
         h->tangent_bucket = bucket;
-        h->tangent_w = bucket <= 48 && M.max_bcol <= NLS_MAX_BCOL && h->max_ng * 8 <= 64 * 1024;
+        h->tangent_w = bucket <= 56 && M.max_bcol <= NLS_MAX_BCOL && h->max_ng * 8 <= 64 * 1024;
         if (h->tangent_w) {
             DevTangent T{};
             int *bptr, *brow, *bslot, *off_own, *ownrow, *rowown;
@@ -515,7 +546,9 @@ extern "C" int nls_build_coarse(nls_handle* h, int kind) {
     if (maxikl > 127 || maxiband > 256)
         return fail(h, NLS_ELIMIT, "interior band too wide");
     const int lds_gdsw = C.max_ilds_doubles * 8 + 64;
-    h->lds_coarse_lu = (C.n0 + std::max(C.a0kl, 1) + 1 + band_window_doubles(C.a0kl, C.a0ku)) * 8;
+    int maxb = 0;
+    for (size_t b = 0; b + 1 < C.boff.size(); ++b) maxb = std::max(maxb, C.boff[b + 1] - C.boff[b]);
+    h->lds_coarse_lu = (maxb + std::max(C.a0kl, 1) + 1 + band_window_doubles(C.a0kl, C.a0ku)) * 8;
     h->lds_coarse_q = maxnc * 8;
     if (lds_gdsw > 160 * 1024 || h->lds_coarse_lu > 160 * 1024 || h->lds_coarse_q > 160 * 1024)
         return fail(h, NLS_ELIMIT, "coarse working set exceeds LDS");
@@ -560,6 +593,22 @@ extern "C" int nls_build_coarse(nls_handle* h, int kind) {
     RC(h->upload(G_COARSE, &off_iu, C.off_iu));
     RC(h->upload(G_COARSE, &off_il, C.off_il));
     RC(h->upload(G_COARSE, &off_kk, C.off_kk));
+    {
+        int *boff, *bkl, *bku, *rblk;
+        int64_t *offU, *offL, *offI;
+        RC(h->upload(G_COARSE, &boff, C.boff));
+        RC(h->upload(G_COARSE, &bkl, C.bkl));
+        RC(h->upload(G_COARSE, &bku, C.bku));
+        RC(h->upload(G_COARSE, &rblk, C.rblk));
+        RC(h->upload(G_COARSE, &offU, C.offU));
+        RC(h->upload(G_COARSE, &offL, C.offL));
+        RC(h->upload(G_COARSE, &offI, C.offI));
+        d.nblk = (int)C.bkl.size();
+        d.boff = boff; d.bkl = bkl; d.bku = bku; d.rblk = rblk;
+        d.offU = offU; d.offL = offL; d.offI = offI;
+        h->max_block = 0;
+        for (int b = 0; b < d.nblk; ++b) h->max_block = std::max(h->max_block, C.boff[b + 1] - C.boff[b]);
+    }
     d.off_c = off_c; d.cnode = cnode; d.ctype = ctype; d.off_k = off_k; d.klist = klist;
     d.ccomp = ccomp; d.off_ne = off_ne; d.ne_conn = ne_conn; d.ne_gid = ne_gid;
     d.cinc_ptr = cinc_ptr; d.cinc = cinc; d.iidx = iidx; d.off_ni = off_ni; d.inode = inode;
@@ -578,8 +627,8 @@ extern "C" int nls_build_coarse(nls_handle* h, int kind) {
     RC(h->alloc(G_COARSE, &d.gblk, C.klist.size()));
     RC(h->alloc(G_COARSE, &d.ablk, (size_t)C.off_kk.back()));
     RC(h->alloc(G_COARSE, &d.a0val, C.a0col.size()));
-    RC(h->alloc(G_COARSE, &d.a0U, (size_t)C.n0 * (C.a0kl + C.a0ku + 1) + 1024));
-    RC(h->alloc(G_COARSE, &d.a0L, (size_t)C.n0 * std::max(C.a0kl, 1) + 1024));
+    RC(h->alloc(G_COARSE, &d.a0U, (size_t)C.offU.back() + 1024));
+    RC(h->alloc(G_COARSE, &d.a0L, (size_t)C.offL.back() + 1024));
     RC(h->alloc(G_COARSE, &d.a0piv, C.n0));
     RC(h->alloc(G_COARSE, &d.rhs, C.n0));
     RC(h->alloc(G_COARSE, &d.c, C.n0));
@@ -589,10 +638,10 @@ extern "C" int nls_build_coarse(nls_handle* h, int kind) {
     RC(h->alloc(G_COARSE, &h->ctmp, C.n0));
     RC(h->alloc(G_COARSE, &h->rhs2, C.n0));
     h->coarse_bucket = mrhs_bucket_kl(C.a0kl, C.a0ku);
-    h->coarse_inv = h->coarse_bucket <= 48;
+    h->coarse_inv = h->coarse_bucket <= 56;
     if (h->coarse_inv) {
-        RC(h->alloc(G_COARSE, &d.a0inv, (size_t)C.n0 * C.n0));
-        RC(h->alloc(G_COARSE, &d.a0fwd, (size_t)C.n0 * C.n0));
+        RC(h->alloc(G_COARSE, &d.a0inv, (size_t)C.offI.back()));
+        RC(h->alloc(G_COARSE, &d.a0fwd, (size_t)C.offI.back()));
     }
     HIPCHK(hipMemsetAsync(d.flag, 0, sizeof(int), h->stream));
     h->dc = d;
@@ -660,7 +709,7 @@ static int coarse_solve(nls_handle* h, const double* u, int* its_out) {
     HIPCHK(launch_coarse_galerkin(h->dm, d, d.w, 1, h->stream));
     HIPCHK(launch_coarse_assemble(d, 1, h->stream));
     HIPCHK(launch_coarse_lu(d, 1, h->lds_coarse_lu, h->npl_coarse, h->stream));
-    if (h->coarse_inv) HIPCHK(launch_coarse_inverse(d, h->coarse_bucket, h->stream));
+    if (h->coarse_inv) HIPCHK(launch_coarse_inverse(d, h->coarse_bucket, h->max_block, h->stream));
     if (its_out) *its_out = its;
     return NLS_OK;
 }
@@ -681,7 +730,12 @@ static int evaluate(nls_handle* h, const double* u, double* Fx) {
         e1 = h->take_event();
         HIPCHK(hipEventRecord(e0, h->stream));
     }
-    HIPCHK(launch_local_newton(h->dm, h->dp, h->dl, h->np, u, h->lds_local, h->npl_local, h->stream));
+    for (size_t b = 0; b < h->bk_start.size(); ++b) {
+        DevMaps pb = h->dp;
+        pb.order = h->dp.order + h->bk_start[b];
+        HIPCHK(launch_local_newton(h->dm, pb, h->dl, h->np, u, h->bk_end[b] - h->bk_start[b],
+                                   h->bk_lds[b], h->bk_npl[b], h->stream));
+    }
     if (e0) {
         HIPCHK(hipEventRecord(e1, h->stream));
         h->ev_used.push_back({0, {e0, e1}});
@@ -750,7 +804,7 @@ static int tangent(nls_handle* h, const double* v, double* y) {
         HIPCHK(launch_coarse_ty(d, v, h->stream));
         HIPCHK(launch_coarse_assemble(d, 0, h->stream));
         if (h->coarse_inv) {
-            HIPCHK(launch_dense_gemv(d.n0, d.a0inv, d.rhs, h->rhs2, h->stream));
+            HIPCHK(launch_coarse_apply_inverse(d, d.rhs, h->rhs2, h->stream));
             HIPCHK(launch_coarse_scatter(d, h->rhs2, h->ctmp, h->stream));
         } else {
             HIPCHK(launch_coarse_lu(d, 0, h->lds_coarse_lu, h->npl_coarse, h->stream));

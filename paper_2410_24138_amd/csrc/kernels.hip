@@ -175,7 +175,7 @@ template <typename T>
 __device__ __forceinline__ int band_lu(int n, int kl, int ku, const int* __restrict__ rptr,
                        const int* __restrict__ cols, const double* __restrict__ vals,
                        T* W, T* mult, int* sflag, T* __restrict__ Uf, T* __restrict__ Lf,
-                       int* __restrict__ piv) {
+                       int* __restrict__ piv, int cbase = 0) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
     // ring buffer of R rows x C columns; row r sits in slot r mod R, column c
@@ -187,7 +187,7 @@ __device__ __forceinline__ int band_lu(int n, int kl, int ku, const int* __restr
     __syncthreads();
     for (int r = tid; r <= min(kl, n - 1); r += nt)
         for (int s = rptr[r]; s < rptr[r + 1]; ++s) {
-            const int c = cols[s];
+            const int c = cols[s] - cbase;
             if (c < n) W[r * C + c] = T(vals[s]);
         }
     __syncthreads();
@@ -264,7 +264,7 @@ __device__ __forceinline__ int band_lu(int n, int kl, int ku, const int* __restr
         const int rn = k + R;
         if (rn < n) {
             for (int s = rptr[rn] + tid; s < rptr[rn + 1]; s += nt) {
-                const int c = cols[s];
+                const int c = cols[s] - cbase;
                 if (c < n) {
                     const int d = c - k;  // in [1, C]
                     const int sc = kc + d < C ? kc + d : kc + d - C;
@@ -346,7 +346,7 @@ template <typename T, int NB>
 __device__ __forceinline__ int band_lu_blocked(int n, int kl, int ku, const int* __restrict__ rptr,
                                const int* __restrict__ cols, const double* __restrict__ vals,
                                T* W, int* sh, T* __restrict__ Uf, T* __restrict__ Lf,
-                               int* __restrict__ piv) {
+                               int* __restrict__ piv, int cbase = 0) {
     T* lt = W + (NB + kl) * (NB + kl + ku);  // L11 of the current panel, NB x NB
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wv = tid >> 6;
@@ -357,7 +357,7 @@ __device__ __forceinline__ int band_lu_blocked(int n, int kl, int ku, const int*
     __syncthreads();
     for (int r = tid; r < min(H, n); r += nt)
         for (int s = rptr[r]; s < rptr[r + 1]; ++s) {
-            const int c = cols[s];
+            const int c = cols[s] - cbase;
             if (c < n) W[r * Wd + c] = T(vals[s]);
         }
     __syncthreads();
@@ -391,7 +391,7 @@ __device__ __forceinline__ int band_lu_blocked(int n, int kl, int ku, const int*
                     int q = 0;
 #pragma unroll
                     for (int t = 1; t < NB; ++t) q += (rp[t] <= sidx) ? 1 : 0;
-                    const int c = cols[sidx];
+                    const int c = cols[sidx] - cbase;
                     if (c < n) {
                         pf_slot[e] = wrap(rb + q, H) * Wd + wrap(cb1 + (c - k1), Wd);
                         pf_val[e] = T(vals[sidx]);
@@ -550,7 +550,7 @@ __device__ __forceinline__ int band_lu_blocked(int n, int kl, int ku, const int*
             for (int sidx = s_done + (tid - 64); sidx < s_end; sidx += nt - 64) {
                 int q = 0;
                 while (q + 1 < NB && rptr[rn0 + q + 1] <= sidx) ++q;
-                const int c = cols[sidx];
+                const int c = cols[sidx] - cbase;
                 if (c < n) W[wrap(rb + q, H) * Wd + wrap(cb1 + (c - k1), Wd)] = T(vals[sidx]);
             }
         }
@@ -567,12 +567,12 @@ template <typename T>
 __device__ __forceinline__ int band_lu_auto(int n, int kl, int ku, const int* __restrict__ rptr,
                             const int* __restrict__ cols, const double* __restrict__ vals,
                             T* W, T* mult, int* sflag, T* __restrict__ Uf, T* __restrict__ Lf,
-                            int* __restrict__ piv) {
+                            int* __restrict__ piv, int cbase = 0) {
     if (kl + 16 <= 64)
-        return band_lu_blocked<T, 16>(n, kl, ku, rptr, cols, vals, W, sflag, Uf, Lf, piv);
+        return band_lu_blocked<T, 16>(n, kl, ku, rptr, cols, vals, W, sflag, Uf, Lf, piv, cbase);
     if (kl + 8 <= 64)
-        return band_lu_blocked<T, 8>(n, kl, ku, rptr, cols, vals, W, sflag, Uf, Lf, piv);
-    return band_lu<T>(n, kl, ku, rptr, cols, vals, W, mult, sflag, Uf, Lf, piv);
+        return band_lu_blocked<T, 8>(n, kl, ku, rptr, cols, vals, W, sflag, Uf, Lf, piv, cbase);
+    return band_lu<T>(n, kl, ku, rptr, cols, vals, W, mult, sflag, Uf, Lf, piv, cbase);
 }
 
 // ----------------------------------------------------------------------------
@@ -1059,22 +1059,38 @@ k_tangent_gemv(DevMaps P, DevTangent Tg, const double* __restrict__ v, double* _
     }
 }
 
-// A0^{-1} (band order, row-major) from the coarse LU: identity right-hand
-// sides, 256 columns per block.
+// Inverse of every diagonal block of A0 (band order, row-major per block)
+// from its LU: identity right-hand sides, 256 columns per workgroup.
 template <int KL, int KW>
 __global__ void __launch_bounds__(MR_THREADS) k_coarse_inverse(DevCoarse C) {
     extern __shared__ double smem[];
     __shared__ int sint[2 * MR_CH];
-    const int n = C.n0;
+    const int b = blockIdx.y;
+    const int off = C.boff[b], n = C.boff[b + 1] - off;
+    if ((int)blockIdx.x * MR_THREADS >= n) return;  // uniform over the block
     const int col = blockIdx.x * MR_THREADS + threadIdx.x;
     const bool valid = col < n;
     MrhsIdentitySrc src{valid ? col : -1};
-    double* Ainv = C.a0inv;
+    double* Ainv = C.a0inv + C.offI[b];
     auto put = [&](int k, double y) {
         if (valid) Ainv[(size_t)k * n + col] = y;
     };
-    band_solve_mrhs<KL, KW>(n, C.a0kl, C.a0ku, C.a0U, C.a0L, C.a0piv, src, valid, col, C.a0fwd, n,
-                            smem, sint, put);
+    band_solve_mrhs<KL, KW>(n, C.bkl[b], C.bku[b], C.a0U + C.offU[b], C.a0L + C.offL[b],
+                            C.a0piv + off, src, valid, col, C.a0fwd + C.offI[b], n, smem, sint, put);
+}
+
+// y = A0^{-1} x, block by block: one wavefront per row.
+__global__ void __launch_bounds__(256)
+k_coarse_apply_inverse(DevCoarse C, const double* __restrict__ x, double* __restrict__ y) {
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (row >= C.n0) return;
+    const int b = C.rblk[row];
+    const int off = C.boff[b], n = C.boff[b + 1] - off;
+    const double* a = C.a0inv + C.offI[b] + (size_t)(row - off) * n;
+    double acc = 0.0;
+    for (int j = lane; j < n; j += 64) acc += a[j] * x[off + j];
+    acc = wave_sum(acc);
+    if (lane == 0) y[row] = acc;
 }
 
 // y = A x for a dense row-major n x n matrix: one wavefront per row.
@@ -1482,27 +1498,32 @@ k_coarse_assemble(DevCoarse C, int with_matrix) {
     if (threadIdx.x == 0) C.scal[0] = sqrt(ss);
 }
 
-// Single workgroup: (factor A0 and) solve A0 d = rhs in place (band order).
+// One workgroup per diagonal block of A0 (independent problems give one
+// block each): (factor and) solve A0 d = rhs in place (band order).
 template <int NPL>
 __global__ void __launch_bounds__(NLS_BLOCK)
 k_coarse_lu(DevCoarse C, int factor) {
     extern __shared__ double smem[];
     __shared__ int sflag[20];
-    const int n = C.n0, kl = C.a0kl, ku = C.a0ku;
-    double* b = smem;
-    double* mult = b + n;
+    const int b = blockIdx.x;
+    const int off = C.boff[b], n = C.boff[b + 1] - off, kl = C.bkl[b], ku = C.bku[b];
+    double* x = smem;
+    double* mult = x + n;
     double* W = mult + ((kl > 1 ? kl : 1) + 1);
+    double* U = C.a0U + C.offU[b];
+    double* L = C.a0L + C.offL[b];
+    int* piv = C.a0piv + off;
     if (factor) {
-        if (band_lu_auto<double>(n, kl, ku, C.a0ptr, C.a0col, C.a0val, W, mult, sflag, C.a0U, C.a0L,
-                            C.a0piv)) {
+        if (band_lu_auto<double>(n, kl, ku, C.a0ptr + off, C.a0col, C.a0val, W, mult, sflag, U, L,
+                                 piv, off)) {
             if (threadIdx.x == 0) atomicOr(C.flag, 2);
         }
     }
-    for (int k = threadIdx.x; k < n; k += blockDim.x) b[k] = C.rhs[k];
+    for (int k = threadIdx.x; k < n; k += blockDim.x) x[k] = C.rhs[off + k];
     __syncthreads();
-    if (threadIdx.x < 64) band_solve_wave<double, NPL>(n, kl, ku, C.a0U, C.a0L, C.a0piv, b);
+    if (threadIdx.x < 64) band_solve_wave<double, NPL>(n, kl, ku, U, L, piv, x);
     __syncthreads();
-    for (int k = threadIdx.x; k < n; k += blockDim.x) C.rhs[k] = b[k];
+    for (int k = threadIdx.x; k < n; k += blockDim.x) C.rhs[off + k] = x[k];
 }
 
 // c += d (d in band order); scal[1] = max|d|, scal[2] = max|c| (new c).
@@ -1655,13 +1676,13 @@ hipError_t launch_global_residual(const DevMesh& M, const double* u, double* F, 
 }
 
 hipError_t launch_local_newton(const DevMesh& M, const DevMaps& P, const DevLocal& L,
-                               const NewtonParams& np, const double* u, int lds_bytes,
+                               const NewtonParams& np, const double* u, int nblk, int lds_bytes,
                                int npl, hipStream_t s) {
     hipError_t e;
 #define NLS_LN(NPL)                                                                  \
     e = set_lds(k_local_newton<NPL>, lds_bytes);                                     \
     if (e != hipSuccess) return e;                                                   \
-    k_local_newton<NPL><<<P.nsub, NLS_BLOCK, lds_bytes, s>>>(M, P, L, np, u);
+    k_local_newton<NPL><<<nblk, NLS_BLOCK, lds_bytes, s>>>(M, P, L, np, u);
     if (npl <= 1) { NLS_LN(1) } else if (npl == 2) { NLS_LN(2) } else { NLS_LN(4) }
 #undef NLS_LN
     return hipGetLastError();
@@ -1736,7 +1757,7 @@ hipError_t launch_coarse_lu(const DevCoarse& C, int factor, int lds_bytes, int n
 #define NLS_CL(NPL)                                                                  \
     e = set_lds(k_coarse_lu<NPL>, lds_bytes);                                        \
     if (e != hipSuccess) return e;                                                   \
-    k_coarse_lu<NPL><<<1, NLS_BLOCK, lds_bytes, s>>>(C, factor);
+    k_coarse_lu<NPL><<<C.nblk, NLS_BLOCK, lds_bytes, s>>>(C, factor);
     if (npl <= 1) { NLS_CL(1) } else if (npl == 2) { NLS_CL(2) } else { NLS_CL(4) }
 #undef NLS_CL
     return hipGetLastError();
@@ -1753,7 +1774,7 @@ hipError_t launch_coarse_scatter(const DevCoarse& C, const double* src, double* 
 }
 
 // window buckets (KL, KW) of the multi-RHS solve
-#define NLS_MR_BUCKETS(X) X(16, 32) X(24, 48) X(32, 64) X(40, 80) X(48, 96)
+#define NLS_MR_BUCKETS(X) X(16, 32) X(24, 48) X(32, 64) X(40, 80) X(48, 96) X(56, 112)
 
 int mrhs_bucket_kl(int kl, int ku) {
     const int need = std::max(kl, (kl + ku + 1) / 2);
@@ -1780,8 +1801,8 @@ hipError_t launch_tangent_gemv(const DevMaps& P, const DevTangent& Tg, const dou
     return hipGetLastError();
 }
 
-hipError_t launch_coarse_inverse(const DevCoarse& C, int kl_bucket, hipStream_t s) {
-    const int nb = (C.n0 + MR_THREADS - 1) / MR_THREADS;
+hipError_t launch_coarse_inverse(const DevCoarse& C, int kl_bucket, int max_block, hipStream_t s) {
+    const dim3 nb((max_block + MR_THREADS - 1) / MR_THREADS, C.nblk);
     const int lds = mrhs_lds_bytes(kl_bucket);
 #define NLS_CI(A, B)                                                                      if (kl_bucket == A) {                                                                     k_coarse_inverse<A, B><<<nb, MR_THREADS, lds, s>>>(C);                                return hipGetLastError();                                                         }
     NLS_MR_BUCKETS(NLS_CI)
@@ -1791,6 +1812,11 @@ hipError_t launch_coarse_inverse(const DevCoarse& C, int kl_bucket, hipStream_t 
 
 hipError_t launch_dense_gemv(int n, const double* A, const double* x, double* y, hipStream_t s) {
     k_dense_gemv<<<(n + 3) / 4, 256, 0, s>>>(n, A, x, y);
+    return hipGetLastError();
+}
+
+hipError_t launch_coarse_apply_inverse(const DevCoarse& C, const double* x, double* y, hipStream_t s) {
+    k_coarse_apply_inverse<<<(C.n0 + 3) / 4, 256, 0, s>>>(C, x, y);
     return hipGetLastError();
 }
 

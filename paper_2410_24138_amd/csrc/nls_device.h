@@ -72,6 +72,9 @@ struct DevCoarse {
     const int64_t *off_phi, *off_iu, *off_il, *off_kk;
     const int *perm, *a0ptr, *a0col, *a0src_ptr, *a0src, *gsrc_ptr, *gsrc, *cpos, *cown;
     int a0kl, a0ku;
+    int nblk;                   // diagonal blocks of A0 (connected components)
+    const int *boff, *bkl, *bku, *rblk;
+    const int64_t *offU, *offL, *offI;
     double* phi;                // dense |C_i| x |K_i| blocks
     double* zbuf;               // same shape: DF Phi rows (scratch)
     double* ybuf;               // same shape: DF^T Phi at the converged coarse point
@@ -102,7 +105,7 @@ hipError_t launch_assemble_load(const DevMesh& M, double* bload, hipStream_t s);
 hipError_t launch_global_residual(const DevMesh& M, const double* u, double* F,
                                   hipStream_t s);
 hipError_t launch_local_newton(const DevMesh& M, const DevMaps& P, const DevLocal& L,
-                               const NewtonParams& np, const double* u, int lds_bytes,
+                               const NewtonParams& np, const double* u, int nblk, int lds_bytes,
                                int nb_per_lane, hipStream_t s);
 hipError_t launch_prolong(const DevMesh& M, const DevMaps& P, const double* T,
                           const DevCoarse* C, const double* cvec, double* out,
@@ -131,7 +134,8 @@ hipError_t launch_tangent_prep(const DevMaps& P, const DevLocal& L, const DevTan
                                int kl_bucket, int max_ng, hipStream_t s);
 hipError_t launch_tangent_gemv(const DevMaps& P, const DevTangent& Tg, const double* v, double* z,
                                int max_ng, hipStream_t s);
-hipError_t launch_coarse_inverse(const DevCoarse& C, int kl_bucket, hipStream_t s);
+hipError_t launch_coarse_inverse(const DevCoarse& C, int kl_bucket, int max_block, hipStream_t s);
+hipError_t launch_coarse_apply_inverse(const DevCoarse& C, const double* x, double* y, hipStream_t s);
 hipError_t launch_dense_gemv(int n, const double* A, const double* x, double* y, hipStream_t s);
 
 // vector kernels for GMRES (deterministic reductions)

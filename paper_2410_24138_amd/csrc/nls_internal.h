@@ -108,7 +108,10 @@ struct HostCoarse {
     std::vector<int64_t> off_kk;   // nsub+1: offsets of the |K_i|^2 blocks
     std::vector<int> gsrc_ptr;     // coarse id -> contributions to Phi^T q
     std::vector<int> gsrc;         // packed position in the per-subdomain vectors
-    int a0kl = 0, a0ku = 0;
+    int a0kl = 0, a0ku = 0;           // largest block band widths
+    // diagonal blocks of A0 in band order (one per connected component)
+    std::vector<int> boff, bkl, bku, rblk;
+    std::vector<int64_t> offU, offL, offI;
     std::vector<int> cpos;         // N: packed closure index in the owner's block
     std::vector<int> cown;         // N: owner subdomain
     int max_k = 0;

@@ -461,13 +461,61 @@ int nls_build_coarse_symbolic(const HostMesh& m, const int* part, int nsub,
             for (int l : adj[k]) w = std::max(w, std::abs(pm[k] - pm[l]));
         return w;
     };
-    C.perm = width(prcm) < width(pnat) ? prcm : pnat;
+    std::vector<int> perm0 = width(prcm) < width(pnat) ? prcm : pnat;
+    // independent problems give a block-diagonal A0: make every connected
+    // component contiguous in band order (relative order kept) and factor
+    // the blocks separately
+    std::vector<int> comp(n0, -1);
+    int ncomp = 0;
+    {
+        std::vector<int> pos2k(n0);
+        for (int k = 0; k < n0; ++k) pos2k[perm0[k]] = k;
+        for (int p = 0; p < n0; ++p) {
+            const int k0 = pos2k[p];
+            if (comp[k0] >= 0) continue;
+            std::queue<int> q;
+            q.push(k0);
+            comp[k0] = ncomp;
+            while (!q.empty()) {
+                const int v = q.front();
+                q.pop();
+                for (int w : adj[v])
+                    if (comp[w] < 0) { comp[w] = ncomp; q.push(w); }
+            }
+            ++ncomp;
+        }
+        std::vector<int> bypos(n0);
+        std::iota(bypos.begin(), bypos.end(), 0);  // band positions
+        std::stable_sort(bypos.begin(), bypos.end(),
+                         [&](int a, int b) { return comp[pos2k[a]] < comp[pos2k[b]]; });
+        C.perm.assign(n0, 0);
+        for (int p = 0; p < n0; ++p) C.perm[pos2k[bypos[p]]] = p;
+    }
+    C.boff.assign(ncomp + 1, 0);
+    for (int k = 0; k < n0; ++k) C.boff[comp[k] + 1]++;
+    for (int b = 0; b < ncomp; ++b) C.boff[b + 1] += C.boff[b];
+    C.bkl.assign(ncomp, 0);
+    C.bku.assign(ncomp, 0);
+    C.rblk.assign(n0, 0);
+    for (int k = 0; k < n0; ++k) C.rblk[C.perm[k]] = comp[k];
     std::vector<std::vector<std::pair<int, std::vector<int>*>>> rows(n0);
     for (auto& kv : src) {
         int r = C.perm[kv.first.first], c = C.perm[kv.first.second];
         rows[r].push_back({c, &kv.second});
-        C.a0kl = std::max(C.a0kl, r - c);
-        C.a0ku = std::max(C.a0ku, c - r);
+        const int b = C.rblk[r];
+        C.bkl[b] = std::max(C.bkl[b], r - c);
+        C.bku[b] = std::max(C.bku[b], c - r);
+    }
+    C.offU.assign(ncomp + 1, 0);
+    C.offL.assign(ncomp + 1, 0);
+    C.offI.assign(ncomp + 1, 0);
+    for (int b = 0; b < ncomp; ++b) {
+        const int64_t nb = C.boff[b + 1] - C.boff[b];
+        C.offU[b + 1] = C.offU[b] + nb * (C.bkl[b] + C.bku[b] + 1);
+        C.offL[b + 1] = C.offL[b] + nb * std::max(C.bkl[b], 1);
+        C.offI[b + 1] = C.offI[b] + nb * nb;
+        C.a0kl = std::max(C.a0kl, C.bkl[b]);
+        C.a0ku = std::max(C.a0ku, C.bku[b]);
     }
     C.a0ptr.assign(1, 0);
     C.a0src_ptr.assign(1, 0);

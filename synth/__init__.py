@@ -26,7 +26,7 @@ __all__ = [
     "p1_grid", "even_cuts", "box_partition", "boundary_nodes",
     "edge_midpoints", "fourier_modes", "fourier_eval", "rff_field",
     "rff_eval", "diffusion_case", "config1", "config2", "config4_instance",
-    "small_case",
+    "config4", "concat_cases", "small_case",
 ]
 
 
@@ -133,10 +133,26 @@ def rff_field(seed: int, n_features: int = 512, corr_len: float = 0.1):
 
 
 def rff_eval(pts: np.ndarray, field) -> np.ndarray:
-    """g(x) = sqrt(2/M) sum_m cos(omega_m . x + phase_m) at points (...,2)."""
+    """g(x) = sqrt(2/M) sum_m cos(omega_m . x + phase_m) at points (...,2).
+
+    Points on few distinct x and y values (grid centroids) use the identity
+    cos(a + b) = cos a cos b - sin a sin b, which turns the sum into one
+    small matrix product over the distinct coordinates.
+    """
     omega, phase = field
-    arg = pts @ omega.T + phase
-    return np.sqrt(2.0 / len(phase)) * np.cos(arg).sum(axis=-1)
+    pts = np.asarray(pts, dtype=np.float64)
+    shape = pts.shape[:-1]
+    p2 = pts.reshape(-1, 2)
+    xs, ix = np.unique(p2[:, 0], return_inverse=True)
+    ys, iy = np.unique(p2[:, 1], return_inverse=True)
+    scale = np.sqrt(2.0 / len(phase))
+    if len(xs) * len(ys) <= 4 * len(p2) and len(xs) * len(ys) <= 2 ** 24:
+        ax = np.outer(xs, omega[:, 0])
+        by = np.outer(ys, omega[:, 1]) + phase
+        grid = np.cos(ax) @ np.cos(by).T - np.sin(ax) @ np.sin(by).T
+        return (scale * grid[ix, iy]).reshape(shape)
+    arg = p2 @ omega.T + phase
+    return (scale * np.cos(arg).sum(axis=-1)).reshape(shape)
 
 
 def diffusion_case(nx, ny, cuts_x, cuts_y, overlap, *, two_level=False,
@@ -205,6 +221,42 @@ def config4_instance(b: int):
                           two_level=True,
                           coef_field=lambda p: rff_eval(p, field),
                           name=f"diffusion_batch_{b}_{n}x{n}_{k}x{k}")
+
+
+def concat_cases(cases, name="batch"):
+    """Join independent problems into one disconnected mesh: node, element
+    and subdomain indices of case b are offset by those of cases 0..b-1.
+    All cases must agree on overlap and two_level; beta must be equal."""
+    xy, conn, part, dn, dv, fl, kc = [], [], [], [], [], [], []
+    n_off = e_off = s_off = 0
+    for c in cases:
+        xy.append(c["xy"])
+        conn.append(c["conn"] + n_off)
+        part.append(c["elem_part"] + s_off)
+        dn.append(c["dirichlet"] + n_off)
+        dv.append(c["dirichlet_vals"])
+        E = len(c["conn"])
+        fl.append(c["elem_load"] if c["elem_load"] is not None else np.ones((E, 3)))
+        kc.append(c["elem_coef"] if c["elem_coef"] is not None else np.ones(E))
+        n_off += len(c["xy"])
+        e_off += E
+        s_off += c["n_sub"]
+    return {
+        "name": name, "kind": "diffusion",
+        "xy": np.concatenate(xy), "conn": np.concatenate(conn).astype(np.int32),
+        "elem_part": np.concatenate(part).astype(np.int32), "n_sub": s_off,
+        "overlap": cases[0]["overlap"],
+        "dirichlet": np.concatenate(dn), "dirichlet_vals": np.concatenate(dv),
+        "elem_load": np.concatenate(fl), "elem_coef": np.concatenate(kc),
+        "beta": cases[0]["beta"], "two_level": cases[0]["two_level"],
+        "instances": [(len(c["xy"]), c["name"]) for c in cases],
+    }
+
+
+def config4(n_instances: int = 32):
+    """The batch of independent diffusion solves as one disconnected mesh."""
+    return concat_cases([config4_instance(b) for b in range(n_instances)],
+                        name=f"diffusion_batch_{n_instances}_grf")
 
 
 def small_case(n=12, boxes=3, overlap=1, two_level=False, beta=1.0,

@@ -198,3 +198,29 @@ def test_error_paths():
         s.tangent(np.zeros(len(case["xy"]))) if False else _solver(case).tangent(
             np.zeros(len(case["xy"])))
     assert e.value.code == nls.NLS_ESTATE
+
+
+def _batch_case():
+    cs = [synth.small_case(n=12, boxes=3, overlap=2, forcing_seed=1, two_level=True),
+          synth.small_case(n=17, boxes=2, overlap=2, coef_seed=3, two_level=True, uneven=True),
+          synth.small_case(n=24, boxes=4, overlap=2, forcing_seed=5, two_level=True)]
+    return synth.concat_cases(cs)
+
+
+def test_batch_of_instances():
+    """Independent problems joined into one disconnected mesh: one launch per
+    size bucket over all their subdomains and a block-diagonal coarse level;
+    F_x, the tangent and the solve match the oracle on the joined problem."""
+    case = _batch_case()
+    P = P1Problem(case)
+    S = Schwarz(P, "additive")
+    s = _solver(case, coupling="additive")
+    u = _probe_point(P, case)
+    _close(_np(s.precond_residual(u)), S.evaluate(u), 1e-11)
+    v = np.random.default_rng(9).normal(size=P.N)
+    _close(_np(s.tangent(v)), S.tangent(v), 1e-11)
+    u_ref, st_ref = S.solve()
+    uu, st, rc = _solver(case, coupling="additive").solve()
+    uu = _np(uu)
+    assert rc == 0 and st["outer_its"] == st_ref["outer"]
+    assert np.linalg.norm(uu - u_ref) <= 1e-10 * np.linalg.norm(u_ref)

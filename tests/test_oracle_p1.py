@@ -151,3 +151,14 @@ def test_global_newton_dense_sparse_agree_and_quadratic():
         u = u - np.linalg.solve(P.jacobian(u).toarray(), P.residual(u))
         errs.append(np.abs(u - u1).max())
     assert errs[2] <= 10 * errs[1] ** 2 + 1e-15
+
+
+def test_random_field_separable_form():
+    """The generator's separable evaluation of the random-feature field on
+    grid centroids equals the direct sum, and has unit variance."""
+    f = synth.rff_field(11)
+    xy, conn = synth.p1_grid(48, 48)
+    cen = xy[conn].mean(axis=1)
+    omega, phase = f
+    direct = np.sqrt(2.0 / len(phase)) * np.cos(cen @ omega.T + phase).sum(axis=-1)
+    np.testing.assert_allclose(synth.rff_eval(cen, f), direct, rtol=0, atol=1e-12)
