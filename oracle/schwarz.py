@@ -169,13 +169,18 @@ class Schwarz:
         Jf[d, d] = 1.0
         return Jf[:, :nV].copy(), Jf[:, nV:].copy()
 
-    def local_solve(self, i, u, x0=None):
+    def local_solve(self, i, u, x0=None, guess=None):
         """T_i(u) by Newton's method on R_i F(u - P_i T_i(u)) = 0 (eq. 4).
 
         Starts from x = R_i u (T_i = 0) unless x0 is given; the stopping rule
         is measured against rho_plain = ||R_i F(u)||.  Returns the converged
         local state, T_i(u) = R_i u - x*, and the LU of J_ii and B_i at x*
         (the exact tangent, eq. 6, needs DF at u_i = u - P_i T_i(u)).
+
+        guess: a predicted start (learned initial guess).  It is taken only
+        when its residual is finite and below rho_plain; if Newton from it
+        fails, the solve restarts from R_i u.  "start" in the result is
+        "plain", "guess" or "fallback".
         """
         s = self.subs[i]
         xu = u[s["V"]].copy()
@@ -184,9 +189,27 @@ class Schwarz:
         rho_plain = float(np.linalg.norm(r))
         tol = _stop_tol(rho_plain, self.b_inf, len(xu), self.inner_rtol,
                         self.inner_eta)
+        start = "plain"
+        if guess is not None:
+            xg = np.array(guess, dtype=np.float64)
+            rg = self.local_residual(i, xg, tr)
+            rho_g = float(np.linalg.norm(rg))
+            if np.isfinite(rho_g) and rho_g < rho_plain:
+                try:
+                    out = self._newton(i, xg, rg, tr, tol)
+                    return self._finish(i, xu, tr, out, rho_plain, "guess")
+                except LocalFailure:
+                    start = "fallback"
+            else:
+                start = "fallback"
         x = xu if x0 is None else np.array(x0, dtype=np.float64)
         if x0 is not None:
             r = self.local_residual(i, x, tr)
+        out = self._newton(i, x, r, tr, tol)
+        return self._finish(i, xu, tr, out, rho_plain, start)
+
+    def _newton(self, i, x, r, tr, tol):
+        """Inner Newton steps x <- x - J(x)^{-1} r(x) until the stopping rule."""
         its = 0
         dprev = None
         hist = [float(np.linalg.norm(r))]
@@ -208,14 +231,22 @@ class Schwarz:
             dprev = float(np.max(np.abs(d)))
             r = self.local_residual(i, x, tr)
             hist.append(float(np.linalg.norm(r)))
+        return x, its, hist
+
+    def _finish(self, i, xu, tr, out, rho_plain, start):
+        x, its, hist = out
         J, B = self.local_jacobian(i, x, tr)
         return {"x": x, "T": xu - x, "lu": sla.lu_factor(J, check_finite=False),
-                "B": B, "its": its, "rho_plain": rho_plain, "hist": hist}
+                "B": B, "its": its, "rho_plain": rho_plain, "hist": hist,
+                "start": start}
 
-    def F1(self, u, sols=None):
+    def F1(self, u, sols=None, guesses=None):
         """One-level RASPEN residual F_1(u)[g] = T_{o(g)}(u)[l(g)] (eqs. 5, 8)."""
         if sols is None:
-            sols = [self.local_solve(i, u) for i in range(self.n_sub)]
+            if guesses is None:
+                guesses = [None] * self.n_sub
+            sols = [self.local_solve(i, u, guess=guesses[i])
+                    for i in range(self.n_sub)]
         Fx = np.empty(self.P.N)
         for s, sol in zip(self.subs, sols):
             Fx[s["owned"]] = sol["T"][s["owned_loc"]]
@@ -330,9 +361,11 @@ class Schwarz:
                 "DF0": DF0, "its": its, "A0": A0}
 
     # --------------------------------------------------------- combinations
-    def evaluate(self, u):
-        """F_x(u) for the configured coupling; keeps the state for the tangent."""
-        Fx, sols = self.F1(u)
+    def evaluate(self, u, guesses=None):
+        """F_x(u) for the configured coupling; keeps the state for the tangent.
+
+        guesses: optional per-subdomain predicted starts (see local_solve)."""
+        Fx, sols = self.F1(u, guesses=guesses)
         co = None
         if self.coupling == "additive":
             co = self.coarse_solve(u)
@@ -374,11 +407,17 @@ class Schwarz:
         return y
 
     def solve(self, u0=None, rtol=1e-8, maxit=50, gmres_rtol=1e-6,
-              gmres_restart=50, gmres_maxit=1000):
+              gmres_restart=50, gmres_maxit=1000, predictor=None):
         """Outer Newton on F_x(u) = 0: solve D F_x(u_k) du = F_x(u_k) (eq. 13)
-        by GMRES and set u_{k+1} = u_k - du."""
+        by GMRES and set u_{k+1} = u_k - du.
+
+        predictor: optional object whose guesses(u) gives the learned starts
+        of the local solves (oracle.guess.Predictor)."""
+        def ev(u):
+            g = predictor.guesses(u) if predictor is not None else None
+            return self.evaluate(u, guesses=g)
         u = np.zeros(self.P.N) if u0 is None else np.array(u0, dtype=np.float64)
-        Fx = self.evaluate(u)
+        Fx = ev(u)
         r0 = float(np.linalg.norm(Fx))
         stats = {"outer": 0, "gmres": [], "inner": [], "coarse": [],
                  "res": [r0], "converged": False}
@@ -393,7 +432,7 @@ class Schwarz:
                                 restart=gmres_restart, maxit=gmres_maxit)
             stats["gmres"].append(its)
             u = u - du
-            Fx = self.evaluate(u)
+            Fx = ev(u)
             stats["outer"] += 1
             stats["res"].append(float(np.linalg.norm(Fx)))
             stats["inner"].append(sum(s["its"] for s in self.state["sols"]))

@@ -26,7 +26,8 @@ __all__ = [
     "p1_grid", "even_cuts", "box_partition", "boundary_nodes",
     "edge_midpoints", "fourier_modes", "fourier_eval", "rff_field",
     "rff_eval", "diffusion_case", "config1", "config2", "config4_instance",
-    "config4", "concat_cases", "small_case",
+    "config4", "concat_cases", "small_case", "mlp_init", "mlp_batch",
+    "epoch_orders",
 ]
 
 
@@ -281,3 +282,33 @@ def small_case(n=12, boxes=3, overlap=1, two_level=False, beta=1.0,
     return diffusion_case(n, n, cx, cy, overlap, two_level=two_level,
                           forcing=forcing, coef_field=coef, beta=beta,
                           name=f"small_{n}_{boxes}_{overlap}")
+
+
+# ------------------------------------------------------ learned initial guess
+def mlp_init(seed: int, dims=(320, 256, 256, 256, 256)) -> np.ndarray:
+    """Initial network parameters, flat float32: for each affine layer the
+    weights [out][in] row-major, then the biases, all ~ U(-1/sqrt(in),
+    1/sqrt(in)) (PCG64, layer by layer, weights before biases)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for l in range(len(dims) - 1):
+        ni, no = dims[l], dims[l + 1]
+        bound = 1.0 / np.sqrt(ni)
+        parts.append(rng.uniform(-bound, bound, size=no * ni))
+        parts.append(rng.uniform(-bound, bound, size=no))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def mlp_batch(seed: int, n: int, n_in: int = 320, n_out: int = 256):
+    """A synthetic batch (inputs ~ N(0,1), targets ~ N(0,1)), float32."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    X = rng.standard_normal((n, n_in)).astype(np.float32)
+    T = rng.standard_normal((n, n_out)).astype(np.float32)
+    return X, T
+
+
+def epoch_orders(seed: int, n: int, epochs: int) -> np.ndarray:
+    """Sample order of every training epoch: `epochs` PCG64 permutations of
+    range(n), concatenated, int32."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.concatenate([rng.permutation(n) for _ in range(epochs)]).astype(np.int32)
