@@ -104,6 +104,11 @@ typedef struct nls_stats {
     double    ms_local_kernel;
     int       n_tangent_launches;
     double    ms_tangent_kernel;
+    /* learned initial guess (when enabled): local solves that started from
+       the prediction, and those whose prediction was rejected by the judge
+       or whose Newton iteration from it failed (then started from R_i u) */
+    int64_t   guess_used;
+    int64_t   guess_fallback;
 } nls_stats;
 
 typedef struct nls_handle nls_handle;
@@ -158,6 +163,14 @@ int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* elem_part,
    Errors: NLS_ESTATE (no partition), NLS_ESINGULAR. */
 int nls_build_coarse(nls_handle* h, int kind);
 
+/* Replace the load samples only (same layout and meaning as elem_load of
+   nls_set_problem; NULL for f = 1), keeping mesh, coefficients, Dirichlet
+   data, partition and coarse space: neither the overlapping subdomains nor
+   the GDSW basis (extended with DF(0), which does not involve f) depend on
+   f.  The load vector b, ||b||_inf and ||Phi^T b||_inf of the stopping
+   rules are recomputed.  Errors: NLS_ESTATE (no partition), NLS_EINVAL. */
+int nls_set_load(nls_handle* h, const double* elem_load);
+
 /* Outer Newton iteration on F_x(u) = 0 (eq. (13)): solve
    D F_x(u_k) du = F_x(u_k) by GMRES and set u_{k+1} = u_k - du.
    u: n_nodes values, read as the initial iterate and overwritten with the
@@ -192,6 +205,93 @@ int nls_get_sizes(nls_handle* h, int32_t* n_sub, int32_t* n_coarse,
    of their interface component. */
 int nls_get_coarse_basis(nls_handle* h, int64_t* nnz, int64_t* rowptr,
                          int32_t* col, double* val);
+
+/* ---- learned initial guess of the local solves ------------------------
+   Not part of the paper's method, which starts every inner Newton
+   iteration for T_i(u) (eq. (4)) from R_i u.  A network proposes another
+   start for each subdomain; the local solve takes it only when
+   ||R_i F(v(x_pred))||_2 < ||R_i F(u)||_2, keeps its stopping rule relative
+   to ||R_i F(u)||_2, and restarts from R_i u if Newton from the prediction
+   fails, so T_i(u) is the same up to the stopping tolerance.
+
+   Features of subdomain i (320): u at 64 points of the perimeter of the
+   patch box (16 per side at t = j/16, counter-clockwise from the lower-left
+   corner), then the nodal load (mean of the edge-midpoint samples of f
+   around each node) at the 16 x 16 reference nodes (x0 + p W/15,
+   y0 + q H/15), index q*16 + p; each sample is the linear interpolant of
+   the nodal field in the mesh element containing the point.  Output (256):
+   coefficients at the reference nodes; x_pred = transfinite (Coons)
+   interpolant of the perimeter samples + bilinear interpolant of the
+   coefficients, Dirichlet nodes exact.  Training target: v(x*) - Coons at
+   the reference nodes, v(x*) = x* on V_i and u elsewhere (eq. (4)).
+
+   Network: affine layers 320 -> 256 -> 256 -> 256 -> 256, GELU (exact erf)
+   after the first three; parameters flat float32 W1 b1 W2 b2 W3 b3 W4 b4
+   (W_l row-major [out][in]), 279552 values.  Products in bfloat16 on the
+   matrix cores with FP32 accumulation; FP32 master weights.  norm: 1152
+   floats [x_mean(320) x_dev(320) y_mean(256) y_dev(256)]; the network maps
+   (x - x_mean)/x_dev to (y - y_mean)/y_dev.  Arrays named _dev below are
+   device pointers. */
+#define NLS_GUESS_PARAMS 279552
+#define NLS_GUESS_NORM   1152
+#define NLS_GUESS_IN     320
+#define NLS_GUESS_OUT    256
+
+/* Set the network (copied; host arrays).  norm NULL: identity.  Resets the
+   Adam state.  Errors: NLS_EINVAL (size, non-finite values). */
+int nls_guess_set_model(nls_handle* h, const float* params, int64_t n_params,
+                        const float* norm);
+/* Copy the network out (host arrays; either may be NULL). */
+int nls_guess_get_model(nls_handle* h, float* params, float* norm);
+/* Use the network in every following evaluation (0 turns it off).
+   Errors: NLS_ESTATE without a network. */
+int nls_guess_enable(nls_handle* h, int enable);
+/* Start capturing (features, target) pairs of converged local solves, up
+   to `capacity` rows (subdomain order, evaluation after evaluation); the
+   library allocates the store.  0 stops and frees it. */
+int nls_guess_capture(nls_handle* h, int64_t capacity);
+/* Copy min(rows captured, max_rows) rows to X_dev (rows x 320) and T_dev
+   (rows x 256) and report the count in *n_rows; with both NULL only the
+   count is reported. */
+int nls_guess_captured(nls_handle* h, float* X_dev, float* T_dev,
+                       int64_t max_rows, int64_t* n_rows);
+/* Features of every subdomain at u_dev (n_sub x 320, raw). */
+int nls_guess_features(nls_handle* h, const double* u_dev, float* X_dev);
+/* x_pred (packed V rows, subdomain order, as the lengths of
+   nls_get_sizes) from caller coefficients coef_dev (n_sub x 256). */
+int nls_guess_lift(nls_handle* h, const double* u_dev, const float* coef_dev,
+                   double* xpred_dev);
+/* Network output in target units for n raw feature rows. */
+int nls_guess_predict(nls_handle* h, const float* X_dev, int64_t n, float* Y_dev);
+/* Mean squared error over all outputs of the standardised batch (X_dev,
+   T_dev raw, n rows <= 65536) and its gradient (NLS_GUESS_PARAMS floats,
+   device; may be NULL), without changing the network. */
+int nls_guess_loss_grad(nls_handle* h, const float* X_dev, const float* T_dev,
+                        int64_t n, float* grad_dev, double* loss);
+
+#define NLS_TRAIN_FIT_NORM 1   /* first set norm from the training data */
+#define NLS_TRAIN_COSINE   2   /* cosine decay of the learning rate to 0 */
+#define NLS_MAX_EPOCHS     256
+typedef struct nls_train_opts {
+    int    epochs;
+    int    batch;        /* rows per Adam step (<= 65536) */
+    double lr;
+    double beta1, beta2, eps;
+    int    flags;        /* NLS_TRAIN_* bits */
+} nls_train_opts;
+typedef struct nls_train_stats {
+    int64_t steps;
+    double  final_loss;                  /* mean step loss of the last epoch */
+    double  epoch_loss[NLS_MAX_EPOCHS];  /* mean step loss per epoch */
+    double  ms;
+} nls_train_stats;
+/* Train the network by Adam (Kingma and Ba) on n rows X_dev (n x 320),
+   T_dev (n x 256) in the library's own kernels.  order_dev: epochs x n
+   row indices (one permutation per epoch), or NULL for the stored order.
+   The last batch of an epoch may be short. */
+int nls_guess_train(nls_handle* h, const nls_train_opts* opts, const float* X_dev,
+                    const float* T_dev, int64_t n, const int32_t* order_dev,
+                    nls_train_stats* st);
 
 /* ---- host-only inspection (no device is touched) ----------------------- */
 

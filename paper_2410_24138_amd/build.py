@@ -11,6 +11,7 @@ import os
 import shutil
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
@@ -24,7 +25,8 @@ ARCH = os.environ.get("NLS_OFFLOAD_ARCH", "gfx950")
 HIP_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE, "-I" + CSRC, "-Wall",
           "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-but-set-variable"]
-SOURCES = [("setup.cpp", False), ("api.cpp", True), ("kernels.hip", True)]
+SOURCES = [("setup.cpp", False), ("api.cpp", True), ("guess_api.cpp", True),
+           ("kernels.hip", True), ("guess.hip", True)]
 
 
 def hipcc() -> str:
@@ -37,7 +39,7 @@ def hipcc() -> str:
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     cc = hipcc()
-    objs = []
+    jobs = []
     for src, is_hip in SOURCES:
         obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
         cmd = [cc, "-c", os.path.join(CSRC, src), "-o", obj] + COMMON
@@ -47,8 +49,11 @@ def build(verbose: bool = False) -> str:
             cmd = cmd[:2] + ["-x", "c++"] + cmd[2:]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
-        objs.append(obj)
+        jobs.append((cmd, obj))
+    with ThreadPoolExecutor(max_workers=min(4, len(jobs))) as ex:
+        for f in [ex.submit(subprocess.run, cmd, check=True) for cmd, _ in jobs]:
+            f.result()
+    objs = [obj for _, obj in jobs]
     tmp = LIB + ".tmp"
     cmd = [cc, "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
     if verbose:

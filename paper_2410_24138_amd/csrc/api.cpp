@@ -13,163 +13,12 @@
 //   Newton   u <- u - du (eq. 13).
 #include <hip/hip_runtime.h>
 
-#include <chrono>
-#include <cmath>
-#include <cstring>
 #include <memory>
 #include <numeric>
-#include <string>
-#include <vector>
 
-#include "nls.h"
-#include "nls_device.h"
-#include "nls_internal.h"
+#include "handle.h"
 
-namespace {
-
-enum BufGroup { G_MESH = 0, G_MAPS = 1, G_COARSE = 2, G_NGROUPS = 3 };
-
-struct Timer {
-    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
-    double ms() const {
-        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
-            .count();
-    }
-};
-
-}  // namespace
-
-struct nls_handle {
-    nls_options opt{};
-    hipStream_t stream = nullptr;
-    std::string err;
-    HostMesh mesh;
-    bool have_mesh = false, have_part = false, have_coarse = false, have_state = false;
-    int kind = NLS_PROBLEM_DIFFUSION;
-    double beta = 1.0;
-    std::vector<double> kappa_h, fmid_h;
-    std::vector<int> part_h;
-    HostMaps maps;
-    HostCoarse co;
-    std::vector<void*> bufs[G_NGROUPS];
-    DevMesh dm{};
-    DevMaps dp{};
-    DevLocal dl{};
-    DevCoarse dc{};
-    DevTangent dt{};
-    bool tangent_w = false;       // W_i = J^{-1} B on owned rows (else per-apply solves)
-    int tangent_bucket = 0, max_ng = 0;
-    bool coarse_inv = false;      // explicit A0^{-1} for the tangent
-    int coarse_bucket = 0, max_block = 0;
-    // size buckets of the local-solve launches: [start, end) in the launch
-    // order, LDS bytes and solve width of each
-    std::vector<int> bk_start, bk_end, bk_lds, bk_npl;
-    double* rhs2 = nullptr;
-    NewtonParams np{};
-    double b_inf = 0.0, phib_inf = 0.0;
-    int npl_local = 1, lds_local = 0, lds_tangent = 0;
-    int npl_coarse = 1, lds_coarse_lu = 0, lds_coarse_q = 0;
-    // GMRES / outer workspace
-    int m = 0;
-    double *V = nullptr, *wv = nullptr, *hbuf = nullptr, *hbuf2 = nullptr, *hn2 = nullptr,
-           *partial = nullptr, *Fx = nullptr, *du = nullptr, *tmp = nullptr, *ctmp = nullptr,
-           *ydev = nullptr, *ubuf = nullptr;
-    int* stat2 = nullptr;
-    int nb_dot = 0;
-    std::vector<int> its_h;
-    nls_stats* st = nullptr;  // stats of the running solve (may be null)
-    // event pairs of profiled launches (kind 0: local Newton, 1: tangent)
-    std::vector<hipEvent_t> ev_pool;
-    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
-    bool profiling() const { return (opt.flags & NLS_FLAG_PROFILE) != 0 && st != nullptr; }
-    hipEvent_t take_event() {
-        if (!ev_pool.empty()) {
-            hipEvent_t e = ev_pool.back();
-            ev_pool.pop_back();
-            return e;
-        }
-        hipEvent_t e = nullptr;
-        (void)hipEventCreate(&e);
-        return e;
-    }
-    void collect_events() {
-        for (auto& u : ev_used) {
-            float ms = 0.f;
-            (void)hipEventSynchronize(u.second.second);
-            (void)hipEventElapsedTime(&ms, u.second.first, u.second.second);
-            if (st) {
-                if (u.first == 0) { st->n_local_launches++; st->ms_local_kernel += ms; }
-                else { st->n_tangent_launches++; st->ms_tangent_kernel += ms; }
-            }
-            ev_pool.push_back(u.second.first);
-            ev_pool.push_back(u.second.second);
-        }
-        ev_used.clear();
-    }
-
-    ~nls_handle() {
-        for (auto& g : bufs)
-            for (void* p : g) (void)hipFree(p);
-        for (auto& u : ev_used) {
-            (void)hipEventDestroy(u.second.first);
-            (void)hipEventDestroy(u.second.second);
-        }
-        for (auto e : ev_pool) (void)hipEventDestroy(e);
-    }
-    void free_group(int g) {
-        for (void* p : bufs[g]) (void)hipFree(p);
-        bufs[g].clear();
-    }
-    template <class T>
-    int alloc(int group, T** out, size_t count) {
-        void* p = nullptr;
-        size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
-        if (hipMalloc(&p, bytes) != hipSuccess) {
-            err = "device allocation of " + std::to_string(bytes) + " bytes failed";
-            *out = nullptr;
-            return NLS_ENOMEM;
-        }
-        bufs[group].push_back(p);
-        *out = (T*)p;
-        return NLS_OK;
-    }
-    template <class T>
-    int upload(int group, T** out, const std::vector<T>& h) {
-        int rc = alloc(group, out, h.size());
-        if (rc) return rc;
-        if (!h.empty() &&
-            hipMemcpyAsync(*out, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, stream) !=
-                hipSuccess) {
-            err = "host-to-device copy failed";
-            return NLS_EHIP;
-        }
-        return NLS_OK;
-    }
-};
-
-#define HIPCHK(x)                                                          \
-    do {                                                                   \
-        hipError_t e_ = (x);                                               \
-        if (e_ != hipSuccess) {                                            \
-            h->err = std::string(#x) + ": " + hipGetErrorString(e_);       \
-            return NLS_EHIP;                                               \
-        }                                                                  \
-    } while (0)
-#define RC(x)                   \
-    do {                        \
-        int rc_ = (x);          \
-        if (rc_ != NLS_OK) return rc_; \
-    } while (0)
-
-static int fail(nls_handle* h, int code, const std::string& msg) {
-    if (h) h->err = msg;
-    return code;
-}
-
-static int sync(nls_handle* h) {
-    HIPCHK(hipStreamSynchronize(h->stream));
-    return NLS_OK;
-}
+void guess_invalidate(nls_handle* h);
 
 // ---------------------------------------------------------------------------
 extern "C" int nls_default_options(nls_options* o) {
@@ -333,6 +182,12 @@ static int upload_problem(nls_handle* h) {
     HIPCHK(launch_p1_setup(d, xy, coef, fmid, G6, kap, eload, bad, h->stream));
     HIPCHK(launch_assemble_load(d, bload, h->stream));
     HIPCHK(launch_max_abs(bload, m.N, part, mx, nb, h->stream));
+    h->d_xy = xy;
+    h->d_coef = coef;
+    h->d_fmid = fmid;
+    h->d_bad = bad;
+    h->d_part = part;
+    h->d_mx = mx;
     int bad_h = 0;
     HIPCHK(hipMemcpyAsync(&bad_h, bad, sizeof(int), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipMemcpyAsync(&h->b_inf, mx, sizeof(double), hipMemcpyDeviceToHost, h->stream));
@@ -351,6 +206,7 @@ extern "C" int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* el
     if (!elem_part) return fail(h, NLS_EINVAL, "elem_part is null");
     HIPCHK(hipSetDevice(h->opt.device));
     h->have_part = h->have_coarse = h->have_state = false;
+    guess_invalidate(h);
     h->free_group(G_MAPS);
     h->free_group(G_COARSE);
     RC(upload_problem(h));
@@ -455,6 +311,7 @@ extern "C" int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* el
     RC(h->alloc(G_MAPS, &L.z, nrows));
     RC(h->alloc(G_MAPS, &L.its, M.nsub));
     RC(h->alloc(G_MAPS, &L.status, M.nsub));
+    RC(h->alloc(G_MAPS, &L.start, M.nsub));
     h->dl = L;
     h->its_h.assign(M.nsub, 0);
     // exact-tangent blocks W_i = (J_ii^{-1} B_i)[owned rows, :]
@@ -521,6 +378,19 @@ extern "C" int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* el
 }
 
 // ------------------------------------------------------------ coarse space
+// ||Phi^T b||_inf, the scale of the coarse stopping rule: G(c) at u = 0,
+// c = 0 equals Phi^T F(0) = -Phi^T b.
+static int coarse_rhs_scale(nls_handle* h) {
+    DevCoarse& d = h->dc;
+    HIPCHK(hipMemsetAsync(d.w, 0, sizeof(double) * h->mesh.N, h->stream));
+    HIPCHK(launch_coarse_q(h->dm, d, d.w, nullptr, 0, h->lds_coarse_q, h->stream));
+    HIPCHK(launch_coarse_assemble(d, 0, h->stream));
+    HIPCHK(launch_max_abs(d.rhs, h->co.n0, h->d_part, h->d_mx, 64, h->stream));
+    HIPCHK(hipMemcpyAsync(&h->phib_inf, h->d_mx, sizeof(double), hipMemcpyDeviceToHost,
+                          h->stream));
+    return sync(h);
+}
+
 extern "C" int nls_build_coarse(nls_handle* h, int kind) {
     if (!h) return NLS_EINVAL;
     if (!h->have_part) return fail(h, NLS_ESTATE, "nls_set_partition first");
@@ -650,20 +520,52 @@ extern "C" int nls_build_coarse(nls_handle* h, int kind) {
     HIPCHK(hipMemcpyAsync(&flag, d.flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
     RC(sync(h));
     if (flag) return fail(h, NLS_ESINGULAR, "zero pivot in an interior block of the extension");
-    // ||Phi^T b||_inf: G(c) at u = 0, c = 0 equals Phi^T F(0) = -Phi^T b
-    HIPCHK(hipMemsetAsync(d.w, 0, sizeof(double) * h->mesh.N, h->stream));
-    HIPCHK(launch_coarse_q(h->dm, d, d.w, nullptr, 0, h->lds_coarse_q, h->stream));
-    HIPCHK(launch_coarse_assemble(d, 0, h->stream));
-    double* part;
-    double* mx;
-    RC(h->alloc(G_COARSE, &part, 64));
-    RC(h->alloc(G_COARSE, &mx, 1));
-    HIPCHK(launch_max_abs(d.rhs, C.n0, part, mx, 64, h->stream));
-    HIPCHK(hipMemcpyAsync(&h->phib_inf, mx, sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    RC(sync(h));
+    RC(coarse_rhs_scale(h));
     h->have_coarse = true;
     return NLS_OK;
 }
+
+// New load samples on the same mesh, coefficients and partition: the maps,
+// the band structure and the GDSW basis (extended with DF at u = 0, which
+// does not involve f) are kept; the element loads, b, ||b||_inf and
+// ||Phi^T b||_inf are recomputed.
+int guess_refresh_load(nls_handle* h);
+
+extern "C" int nls_set_load(nls_handle* h, const double* elem_load) {
+    if (!h) return NLS_EINVAL;
+    if (!h->have_part) return fail(h, NLS_ESTATE, "nls_set_partition first");
+    HIPCHK(hipSetDevice(h->opt.device));
+    const int E = h->mesh.E;
+    if (elem_load) {
+        for (size_t k = 0; k < 3 * (size_t)E; ++k)
+            if (!std::isfinite(elem_load[k])) return fail(h, NLS_EINVAL, "load samples must be finite");
+        h->fmid_h.assign(elem_load, elem_load + 3 * (size_t)E);
+        if (!h->d_fmid) RC(h->alloc(G_MESH, &h->d_fmid, 3 * (size_t)E));
+        HIPCHK(hipMemcpyAsync(h->d_fmid, elem_load, 3 * (size_t)E * sizeof(double),
+                              hipMemcpyHostToDevice, h->stream));
+    } else {
+        h->fmid_h.clear();
+    }
+    DevMesh& d = h->dm;
+    HIPCHK(hipMemsetAsync(h->d_bad, 0, sizeof(int), h->stream));
+    HIPCHK(launch_p1_setup(d, h->d_xy, h->d_coef, elem_load ? h->d_fmid : nullptr,
+                           const_cast<double*>(d.G6), const_cast<double*>(d.kappa),
+                           const_cast<double*>(d.eload), h->d_bad, h->stream));
+    HIPCHK(launch_assemble_load(d, const_cast<double*>(d.bload), h->stream));
+    HIPCHK(launch_max_abs(d.bload, h->mesh.N, h->d_part, h->d_mx, 256, h->stream));
+    HIPCHK(hipMemcpyAsync(&h->b_inf, h->d_mx, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    RC(sync(h));
+    h->np.abs_tol = h->opt.inner_eta * h->b_inf;
+    if (h->have_coarse) RC(coarse_rhs_scale(h));
+    if (h->guess) RC(guess_refresh_load(h));
+    h->have_state = false;
+    return NLS_OK;
+}
+
+// learned initial guess (guess_api.cpp)
+bool guess_enabled(const nls_handle* h);
+int guess_prepare(nls_handle* h, const double* u, const double** xpred);
+int guess_after_local(nls_handle* h, const double* u);
 
 // ------------------------------------------------------------ evaluation
 static bool two_level(nls_handle* h) {
@@ -724,6 +626,9 @@ static int dot_host(nls_handle* h, const double* x, const double* y, int n, doub
 static int evaluate(nls_handle* h, const double* u, double* Fx) {
     Timer t;
     h->have_state = false;
+    NewtonParams np = h->np;
+    np.xpred = nullptr;
+    if (guess_enabled(h)) RC(guess_prepare(h, u, &np.xpred));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (h->profiling()) {
         e0 = h->take_event();
@@ -733,7 +638,7 @@ static int evaluate(nls_handle* h, const double* u, double* Fx) {
     for (size_t b = 0; b < h->bk_start.size(); ++b) {
         DevMaps pb = h->dp;
         pb.order = h->dp.order + h->bk_start[b];
-        HIPCHK(launch_local_newton(h->dm, pb, h->dl, h->np, u, h->bk_end[b] - h->bk_start[b],
+        HIPCHK(launch_local_newton(h->dm, pb, h->dl, np, u, h->bk_end[b] - h->bk_start[b],
                                    h->bk_lds[b], h->bk_npl[b], h->stream));
     }
     if (e0) {
@@ -766,6 +671,7 @@ static int evaluate(nls_handle* h, const double* u, double* Fx) {
         if (st2[1] == 3) return fail(h, NLS_ESINGULAR, "zero pivot in subdomain " + std::to_string(st2[0]));
         return fail(h, NLS_ELOCAL, "local Newton failed in subdomain " + std::to_string(st2[0]));
     }
+    RC(guess_after_local(h, u));
     if (two_level(h)) {
         Timer tc;
         int cits = 0;

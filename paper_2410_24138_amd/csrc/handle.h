@@ -1,0 +1,171 @@
+// The solver handle: host state, device buffers and the helpers every
+// entry point of libnls uses.  Internal, not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "nls.h"
+#include "nls_device.h"
+#include "nls_internal.h"
+
+struct GuessState;  // learned initial guess (guess_api.cpp)
+void guess_state_free(GuessState* g);
+
+enum BufGroup { G_MESH = 0, G_MAPS = 1, G_COARSE = 2, G_NGROUPS = 3 };
+
+struct Timer {
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+    double ms() const {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+            .count();
+    }
+};
+
+struct nls_handle {
+    nls_options opt{};
+    hipStream_t stream = nullptr;
+    std::string err;
+    HostMesh mesh;
+    bool have_mesh = false, have_part = false, have_coarse = false, have_state = false;
+    int kind = NLS_PROBLEM_DIFFUSION;
+    double beta = 1.0;
+    std::vector<double> kappa_h, fmid_h;
+    std::vector<int> part_h;
+    HostMaps maps;
+    HostCoarse co;
+    std::vector<void*> bufs[G_NGROUPS];
+    DevMesh dm{};
+    DevMaps dp{};
+    DevLocal dl{};
+    DevCoarse dc{};
+    DevTangent dt{};
+    bool tangent_w = false;       // W_i = J^{-1} B on owned rows (else per-apply solves)
+    int tangent_bucket = 0, max_ng = 0;
+    bool coarse_inv = false;      // explicit A0^{-1} for the tangent
+    int coarse_bucket = 0, max_block = 0;
+    // size buckets of the local-solve launches: [start, end) in the launch
+    // order, LDS bytes and solve width of each
+    std::vector<int> bk_start, bk_end, bk_lds, bk_npl;
+    double* rhs2 = nullptr;
+    NewtonParams np{};
+    double b_inf = 0.0, phib_inf = 0.0;
+    int npl_local = 1, lds_local = 0, lds_tangent = 0;
+    int npl_coarse = 1, lds_coarse_lu = 0, lds_coarse_q = 0;
+    // GMRES / outer workspace
+    int m = 0;
+    double *V = nullptr, *wv = nullptr, *hbuf = nullptr, *hbuf2 = nullptr, *hn2 = nullptr,
+           *partial = nullptr, *Fx = nullptr, *du = nullptr, *tmp = nullptr, *ctmp = nullptr,
+           *ydev = nullptr, *ubuf = nullptr;
+    int* stat2 = nullptr;
+    int nb_dot = 0;
+    // problem data kept on the device for nls_set_load
+    const double *d_xy = nullptr, *d_coef = nullptr;
+    double* d_fmid = nullptr;
+    int* d_bad = nullptr;
+    double *d_part = nullptr, *d_mx = nullptr;
+    // learned initial guess (null until first used)
+    GuessState* guess = nullptr;
+    std::vector<int> its_h;
+    nls_stats* st = nullptr;  // stats of the running solve (may be null)
+    // event pairs of profiled launches (kind 0: local Newton, 1: tangent)
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
+    bool profiling() const { return (opt.flags & NLS_FLAG_PROFILE) != 0 && st != nullptr; }
+    hipEvent_t take_event() {
+        if (!ev_pool.empty()) {
+            hipEvent_t e = ev_pool.back();
+            ev_pool.pop_back();
+            return e;
+        }
+        hipEvent_t e = nullptr;
+        (void)hipEventCreate(&e);
+        return e;
+    }
+    void collect_events() {
+        for (auto& u : ev_used) {
+            float ms = 0.f;
+            (void)hipEventSynchronize(u.second.second);
+            (void)hipEventElapsedTime(&ms, u.second.first, u.second.second);
+            if (st) {
+                if (u.first == 0) { st->n_local_launches++; st->ms_local_kernel += ms; }
+                else { st->n_tangent_launches++; st->ms_tangent_kernel += ms; }
+            }
+            ev_pool.push_back(u.second.first);
+            ev_pool.push_back(u.second.second);
+        }
+        ev_used.clear();
+    }
+
+    ~nls_handle() {
+        guess_state_free(guess);
+        for (auto& g : bufs)
+            for (void* p : g) (void)hipFree(p);
+        for (auto& u : ev_used) {
+            (void)hipEventDestroy(u.second.first);
+            (void)hipEventDestroy(u.second.second);
+        }
+        for (auto e : ev_pool) (void)hipEventDestroy(e);
+    }
+    void free_group(int g) {
+        for (void* p : bufs[g]) (void)hipFree(p);
+        bufs[g].clear();
+    }
+    template <class T>
+    int alloc(int group, T** out, size_t count) {
+        void* p = nullptr;
+        size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            err = "device allocation of " + std::to_string(bytes) + " bytes failed";
+            *out = nullptr;
+            return NLS_ENOMEM;
+        }
+        bufs[group].push_back(p);
+        *out = (T*)p;
+        return NLS_OK;
+    }
+    template <class T>
+    int upload(int group, T** out, const std::vector<T>& h) {
+        int rc = alloc(group, out, h.size());
+        if (rc) return rc;
+        if (!h.empty() &&
+            hipMemcpyAsync(*out, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, stream) !=
+                hipSuccess) {
+            err = "host-to-device copy failed";
+            return NLS_EHIP;
+        }
+        return NLS_OK;
+    }
+};
+
+#define HIPCHK(x)                                                          \
+    do {                                                                   \
+        hipError_t e_ = (x);                                               \
+        if (e_ != hipSuccess) {                                            \
+            h->err = std::string(#x) + ": " + hipGetErrorString(e_);       \
+            return NLS_EHIP;                                               \
+        }                                                                  \
+    } while (0)
+#define RC(x)                   \
+    do {                        \
+        int rc_ = (x);          \
+        if (rc_ != NLS_OK) return rc_; \
+    } while (0)
+
+inline int fail(nls_handle* h, int code, const std::string& msg) {
+    if (h) h->err = msg;
+    return code;
+}
+
+inline int sync(nls_handle* h) {
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return NLS_OK;
+}
+

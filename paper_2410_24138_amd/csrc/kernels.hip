@@ -759,35 +759,68 @@ k_local_newton(DevMesh M, DevMaps P, DevLocal L, NewtonParams np, const double* 
     local_residual(M, P, n, rowbase, ebase, vp, rb);
     double ss = 0.0;
     for (int a = threadIdx.x; a < n; a += blockDim.x) ss += rb[a] * rb[a];
-    double rn = sqrt(block_sum(ss, red));
-    const double tol = fmax(np.rtol * rn, np.abs_tol * sqrt((double)n));
-    int its = 0, status = 0;
-    double dprev = -1.0;
-    for (;;) {
-        if (!(rn == rn) || isinf(rn)) { status = 2; break; }
-        if (rn <= tol) break;
-        if (dprev >= 0.0) {
-            double xm = 0.0;
-            for (int a = threadIdx.x; a < n; a += blockDim.x) xm = fmax(xm, fabs(vp[a]));
-            xm = block_max(xm, red);
-            if (dprev <= np.stagnation * xm) break;
-        }
-        if (its == np.maxit) { status = 1; break; }
-        local_jacobian(M, P, n, rowbase, ebase, vp, L.jval);
+    const double rho_plain = sqrt(block_sum(ss, red));
+    const double tol = fmax(np.rtol * rho_plain, np.abs_tol * sqrt((double)n));
+    double rn = rho_plain;
+    // Predicted start: taken only if its residual is finite and below
+    // rho_plain; the stopping rule stays relative to rho_plain.
+    int start = 0;
+    if (np.xpred) {
+        for (int a = threadIdx.x; a < n; a += blockDim.x) vp[a] = np.xpred[rowbase + a];
         __syncthreads();
-        if (local_factor(P, L, np, i, n, rowbase, W, mult, sflag)) { status = 3; break; }
-        local_linear_solve<NPL>(P, L, np, i, n, rowbase, rb, r0, dl, red);
-        double dm = 0.0;
-        for (int a = threadIdx.x; a < n; a += blockDim.x) {
-            vp[a] -= rb[a];
-            dm = fmax(dm, fabs(rb[a]));
-        }
-        dprev = block_max(dm, red);
-        ++its;
         local_residual(M, P, n, rowbase, ebase, vp, rb);
         ss = 0.0;
         for (int a = threadIdx.x; a < n; a += blockDim.x) ss += rb[a] * rb[a];
-        rn = sqrt(block_sum(ss, red));
+        const double rg = sqrt(block_sum(ss, red));
+        if (rg == rg && !isinf(rg) && rg < rho_plain) {
+            start = 1;
+            rn = rg;
+        } else {
+            start = 2;
+        }
+    }
+    int its = 0, status = 0;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        if (attempt == 1 || start == 2) {
+            // from R_i u (plain start, or after the predicted start failed)
+            for (int a = threadIdx.x; a < n; a += blockDim.x) vp[a] = u[P.l2g[rowbase + a]];
+            __syncthreads();
+            if (np.xpred) {
+                local_residual(M, P, n, rowbase, ebase, vp, rb);
+                rn = rho_plain;
+            }
+        }
+        its = 0;
+        status = 0;
+        double dprev = -1.0;
+        for (;;) {
+            if (!(rn == rn) || isinf(rn)) { status = 2; break; }
+            if (rn <= tol) break;
+            if (dprev >= 0.0) {
+                double xm = 0.0;
+                for (int a = threadIdx.x; a < n; a += blockDim.x) xm = fmax(xm, fabs(vp[a]));
+                xm = block_max(xm, red);
+                if (dprev <= np.stagnation * xm) break;
+            }
+            if (its == np.maxit) { status = 1; break; }
+            local_jacobian(M, P, n, rowbase, ebase, vp, L.jval);
+            __syncthreads();
+            if (local_factor(P, L, np, i, n, rowbase, W, mult, sflag)) { status = 3; break; }
+            local_linear_solve<NPL>(P, L, np, i, n, rowbase, rb, r0, dl, red);
+            double dm = 0.0;
+            for (int a = threadIdx.x; a < n; a += blockDim.x) {
+                vp[a] -= rb[a];
+                dm = fmax(dm, fabs(rb[a]));
+            }
+            dprev = block_max(dm, red);
+            ++its;
+            local_residual(M, P, n, rowbase, ebase, vp, rb);
+            ss = 0.0;
+            for (int a = threadIdx.x; a < n; a += blockDim.x) ss += rb[a] * rb[a];
+            rn = sqrt(block_sum(ss, red));
+        }
+        if (status == 0 || start != 1) break;
+        start = 2;
     }
     if (status == 0) {
         // J and its LU at x*, in FP64, are kept for the exact tangent
@@ -803,6 +836,7 @@ k_local_newton(DevMesh M, DevMaps P, DevLocal L, NewtonParams np, const double* 
     if (threadIdx.x == 0) {
         L.its[i] = its;
         L.status[i] = status;
+        L.start[i] = start;
     }
 }
 

@@ -42,6 +42,8 @@ struct DevLocal {
     double* z;                  // packed scratch of the tangent
     int* its;                   // per subdomain
     int* status;                // per subdomain: 0 ok, 1 no convergence, 2 NaN, 3 zero pivot
+    int* start;                 // per subdomain: 0 from R_i u, 1 from the predicted start,
+                                //   2 prediction rejected or failed, then from R_i u
 };
 
 // Exact-tangent tables and storage: W_i = (J_ii^{-1} B_i) on owned rows.
@@ -62,6 +64,7 @@ struct NewtonParams {
     int mixed;                  // 1: FP32 LU + FP64 iterative refinement
     int ir_maxit;
     double ir_rtol;
+    const double* xpred;        // packed predicted starts, or null
 };
 
 // GDSW coarse space tables (see HostCoarse) and state.

@@ -117,9 +117,23 @@ struct HostCoarse {
     int max_k = 0;
 };
 
+// Sampling tables of the learned initial guess, per subdomain: the patch box
+// and, for 64 perimeter points followed by the 256 reference-grid nodes, the
+// mesh element containing the point (its three nodes and barycentric
+// weights); for the grid nodes also the packed V row of each node in the
+// subdomain, or -1.
+struct HostGuess {
+    std::vector<double> box;       // 4 per subdomain: x0, y0, x1, y1
+    std::vector<int> snode;        // nsub x 320 x 3
+    std::vector<double> sw;        // nsub x 320 x 3
+    std::vector<int> sloc;         // nsub x 256 x 3
+};
+
 // Setup entry points (setup.cpp).  Return 0 or an NLS_* error with err set.
 int nls_build_node_incidence(HostMesh& m, std::string& err);
 int nls_build_maps(const HostMesh& m, const int* part, int nsub, int overlap,
                    HostMaps& out, std::string& err);
 int nls_build_coarse_symbolic(const HostMesh& m, const int* part, int nsub,
                               HostCoarse& out, std::string& err);
+int nls_build_guess_tables(const HostMesh& m, const HostMaps& maps, HostGuess& out,
+                           std::string& err);

@@ -12,6 +12,7 @@
 // global values.  Restricted prolongation P~_i (eq. 8): node g belongs to
 // the largest subdomain id among its elements.
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <map>
 #include <numeric>
@@ -539,6 +540,190 @@ int nls_build_coarse_symbolic(const HostMesh& m, const int* part, int nsub,
 }
 
 // ---------------------------------------------------------------- inspection
+// ---------------------------------------------------------------------------
+// Learned initial guess: patch boxes and sampling tables.
+//
+// Each sample is the linear interpolant of a global nodal field in the mesh
+// element containing the sample point: among the candidate elements the one
+// with the largest smallest barycentric coordinate (on a shared edge either
+// neighbour gives the same value up to rounding).  The candidates come from
+// a uniform bucket grid over the mesh; a point whose bucket holds no element
+// containing it widens the search ring by ring (points outside the mesh end
+// with the nearest element, i.e. linear extrapolation).
+// ---------------------------------------------------------------------------
+namespace {
+struct BucketGrid {
+    double x0, y0, hx, hy;
+    int nx, ny;
+    std::vector<int> ptr, elems;
+};
+
+void barycentric(const HostMesh& m, int e, double px, double py, double lam[3]) {
+    const int a = m.conn[3 * e], b = m.conn[3 * e + 1], c = m.conn[3 * e + 2];
+    const double ax = m.xy[2 * a], ay = m.xy[2 * a + 1];
+    const double bx = m.xy[2 * b], by = m.xy[2 * b + 1];
+    const double cx = m.xy[2 * c], cy = m.xy[2 * c + 1];
+    const double det = (bx - ax) * (cy - ay) - (cx - ax) * (by - ay);
+    const double dx = px - ax, dy = py - ay;
+    const double l1 = (dx * (cy - ay) - dy * (cx - ax)) / det;
+    const double l2 = ((bx - ax) * dy - (by - ay) * dx) / det;
+    lam[0] = 1.0 - l1 - l2;
+    lam[1] = l1;
+    lam[2] = l2;
+}
+
+BucketGrid build_buckets(const HostMesh& m) {
+    BucketGrid g;
+    double xmin = m.xy[0], xmax = m.xy[0], ymin = m.xy[1], ymax = m.xy[1];
+    for (int v = 0; v < m.N; ++v) {
+        xmin = std::min(xmin, m.xy[2 * v]);
+        xmax = std::max(xmax, m.xy[2 * v]);
+        ymin = std::min(ymin, m.xy[2 * v + 1]);
+        ymax = std::max(ymax, m.xy[2 * v + 1]);
+    }
+    const int nb = std::max(1, (int)std::sqrt((double)m.E / 4.0));
+    g.nx = g.ny = nb;
+    g.x0 = xmin;
+    g.y0 = ymin;
+    g.hx = std::max(xmax - xmin, 1e-300) / nb;
+    g.hy = std::max(ymax - ymin, 1e-300) / nb;
+    auto cell = [&](double v, double o, double h, int n) {
+        return std::min(n - 1, std::max(0, (int)std::floor((v - o) / h)));
+    };
+    std::vector<int> cnt((size_t)nb * nb + 1, 0);
+    std::vector<int> lo(4 * (size_t)m.E);
+    for (int e = 0; e < m.E; ++e) {
+        double ex0 = 1e300, ex1 = -1e300, ey0 = 1e300, ey1 = -1e300;
+        for (int k = 0; k < 3; ++k) {
+            const int v = m.conn[3 * e + k];
+            ex0 = std::min(ex0, m.xy[2 * v]);
+            ex1 = std::max(ex1, m.xy[2 * v]);
+            ey0 = std::min(ey0, m.xy[2 * v + 1]);
+            ey1 = std::max(ey1, m.xy[2 * v + 1]);
+        }
+        int* L = &lo[4 * (size_t)e];
+        L[0] = cell(ex0, g.x0, g.hx, nb);
+        L[1] = cell(ex1, g.x0, g.hx, nb);
+        L[2] = cell(ey0, g.y0, g.hy, nb);
+        L[3] = cell(ey1, g.y0, g.hy, nb);
+        for (int j = L[2]; j <= L[3]; ++j)
+            for (int i = L[0]; i <= L[1]; ++i) cnt[(size_t)j * nb + i + 1]++;
+    }
+    for (size_t k = 1; k < cnt.size(); ++k) cnt[k] += cnt[k - 1];
+    g.ptr = cnt;
+    g.elems.resize(cnt.back());
+    std::vector<int> fill(cnt.begin(), cnt.end() - 1);
+    for (int e = 0; e < m.E; ++e) {
+        const int* L = &lo[4 * (size_t)e];
+        for (int j = L[2]; j <= L[3]; ++j)
+            for (int i = L[0]; i <= L[1]; ++i) g.elems[fill[(size_t)j * nb + i]++] = e;
+    }
+    return g;
+}
+
+// Element containing (px, py) and its barycentric weights.
+int locate(const HostMesh& m, const BucketGrid& g, double px, double py, double w[3]) {
+    const int ci = std::min(g.nx - 1, std::max(0, (int)std::floor((px - g.x0) / g.hx)));
+    const int cj = std::min(g.ny - 1, std::max(0, (int)std::floor((py - g.y0) / g.hy)));
+    int best = -1;
+    double bmin = -1e300;
+    const int rmax = std::max(g.nx, g.ny);
+    for (int r = 0; r <= rmax; ++r) {
+        for (int j = cj - r; j <= cj + r; ++j) {
+            if (j < 0 || j >= g.ny) continue;
+            for (int i = ci - r; i <= ci + r; ++i) {
+                if (i < 0 || i >= g.nx) continue;
+                if (std::max(std::abs(i - ci), std::abs(j - cj)) != r) continue;
+                const size_t b = (size_t)j * g.nx + i;
+                for (int k = g.ptr[b]; k < g.ptr[b + 1]; ++k) {
+                    const int e = g.elems[k];
+                    double lam[3];
+                    barycentric(m, e, px, py, lam);
+                    const double mn = std::min(lam[0], std::min(lam[1], lam[2]));
+                    if (mn > bmin || (mn == bmin && e < best)) {
+                        bmin = mn;
+                        best = e;
+                        w[0] = lam[0];
+                        w[1] = lam[1];
+                        w[2] = lam[2];
+                    }
+                }
+            }
+        }
+        if (best >= 0 && bmin >= -1e-12) break;
+    }
+    return best;
+}
+}  // namespace
+
+int nls_build_guess_tables(const HostMesh& m, const HostMaps& M, HostGuess& out,
+                           std::string& err) {
+    constexpr int NS = 16, NT = 64, NG = 16, NIN = 320;
+    const int nsub = M.nsub;
+    if (m.E == 0) {
+        err = "empty mesh";
+        return NLS_EINVAL;
+    }
+    const BucketGrid grid = build_buckets(m);
+    out.box.assign(4 * (size_t)nsub, 0.0);
+    out.snode.assign((size_t)nsub * NIN * 3, 0);
+    out.sw.assign((size_t)nsub * NIN * 3, 0.0);
+    out.sloc.assign((size_t)nsub * (NIN - NT) * 3, -1);
+    for (int i = 0; i < nsub; ++i) {
+        double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
+        auto take = [&](int g) {
+            x0 = std::min(x0, m.xy[2 * g]);
+            x1 = std::max(x1, m.xy[2 * g]);
+            y0 = std::min(y0, m.xy[2 * g + 1]);
+            y1 = std::max(y1, m.xy[2 * g + 1]);
+        };
+        for (int r = M.off_n[i]; r < M.off_n[i + 1]; ++r) take(M.l2g[r]);
+        for (int r = M.off_g[i]; r < M.off_g[i + 1]; ++r) take(M.g2g[r]);
+        const double W = x1 - x0, H = y1 - y0;
+        if (!(W > 0.0) || !(H > 0.0)) {
+            err = "subdomain " + std::to_string(i) + " has a degenerate patch box";
+            return NLS_EPARTITION;
+        }
+        double* bx = &out.box[4 * (size_t)i];
+        bx[0] = x0;
+        bx[1] = y0;
+        bx[2] = x1;
+        bx[3] = y1;
+        for (int k = 0; k < NIN; ++k) {
+            double px, py;
+            if (k < NT) {
+                const int sd = k / NS;
+                const double t = (double)(k % NS) / NS;
+                if (sd == 0) { px = x0 + t * W; py = y0; }
+                else if (sd == 1) { px = x1; py = y0 + t * H; }
+                else if (sd == 2) { px = x1 - t * W; py = y1; }
+                else { px = x0; py = y1 - t * H; }
+            } else {
+                const int q = (k - NT) / NG, p = (k - NT) % NG;
+                px = x0 + ((double)p / (NG - 1)) * W;
+                py = y0 + ((double)q / (NG - 1)) * H;
+            }
+            double w[3];
+            const int e = locate(m, grid, px, py, w);
+            const size_t o = ((size_t)i * NIN + k) * 3;
+            for (int v = 0; v < 3; ++v) {
+                const int g = m.conn[3 * e + v];
+                out.snode[o + v] = g;
+                out.sw[o + v] = w[v];
+                if (k >= NT) {
+                    // packed V row of g in subdomain i (l2g ascending per subdomain)
+                    const int* b = M.l2g.data() + M.off_n[i];
+                    const int* en = M.l2g.data() + M.off_n[i + 1];
+                    const int* it = std::lower_bound(b, en, g);
+                    out.sloc[((size_t)i * (NIN - NT) + (k - NT)) * 3 + v] =
+                        (it != en && *it == g) ? M.off_n[i] + (int)(it - b) : -1;
+                }
+            }
+        }
+    }
+    return NLS_OK;
+}
+
 static int inspect_mesh(int64_t n_nodes, int64_t n_elems, const int32_t* conn, HostMesh& m,
                         std::string& err) {
     if (n_nodes <= 0 || n_elems <= 0 || !conn) return NLS_EINVAL;

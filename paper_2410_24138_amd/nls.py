@@ -46,8 +46,19 @@ SYMBOLS = (
     "nls_eval_precond_residual", "nls_apply_tangent",
     "nls_get_inner_iterations", "nls_get_sizes", "nls_get_coarse_basis",
     "nls_strerror", "nls_last_error", "nls_inspect_partition",
-    "nls_inspect_coarse",
+    "nls_inspect_coarse", "nls_set_load", "nls_guess_set_model",
+    "nls_guess_get_model", "nls_guess_enable", "nls_guess_capture",
+    "nls_guess_captured", "nls_guess_features", "nls_guess_lift",
+    "nls_guess_predict", "nls_guess_loss_grad", "nls_guess_train",
 )
+
+GUESS_PARAMS = 279552
+GUESS_NORM = 1152
+GUESS_IN = 320
+GUESS_OUT = 256
+TRAIN_FIT_NORM = 1
+TRAIN_COSINE = 2
+MAX_EPOCHS = 256
 
 
 class Options(ctypes.Structure):
@@ -74,12 +85,28 @@ class Stats(ctypes.Structure):
         ("ms_other", ctypes.c_double), ("ms_total", ctypes.c_double),
         ("n_local_launches", ctypes.c_int), ("ms_local_kernel", ctypes.c_double),
         ("n_tangent_launches", ctypes.c_int), ("ms_tangent_kernel", ctypes.c_double),
+        ("guess_used", ctypes.c_int64), ("guess_fallback", ctypes.c_int64),
     ]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_ if k != "gmres_its"}
         d["gmres_its"] = list(self.gmres_its[: self.outer_its])
         return d
+
+
+class TrainOpts(ctypes.Structure):
+    _fields_ = [
+        ("epochs", ctypes.c_int), ("batch", ctypes.c_int), ("lr", ctypes.c_double),
+        ("beta1", ctypes.c_double), ("beta2", ctypes.c_double), ("eps", ctypes.c_double),
+        ("flags", ctypes.c_int),
+    ]
+
+
+class TrainStats(ctypes.Structure):
+    _fields_ = [
+        ("steps", ctypes.c_int64), ("final_loss", ctypes.c_double),
+        ("epoch_loss", ctypes.c_double * MAX_EPOCHS), ("ms", ctypes.c_double),
+    ]
 
 
 _lib = None
@@ -117,6 +144,18 @@ def load() -> ctypes.CDLL:
                                   ctypes.c_int),
         "nls_inspect_coarse": ([i64, i64, P, i32, P, i64, P, P, P, P], ctypes.c_int),
         "nls_last_error": ([P], ctypes.c_char_p),
+        "nls_set_load": ([P, P], ctypes.c_int),
+        "nls_guess_set_model": ([P, P, i64, P], ctypes.c_int),
+        "nls_guess_get_model": ([P, P, P], ctypes.c_int),
+        "nls_guess_enable": ([P, ctypes.c_int], ctypes.c_int),
+        "nls_guess_capture": ([P, i64], ctypes.c_int),
+        "nls_guess_captured": ([P, P, P, i64, ctypes.POINTER(i64)], ctypes.c_int),
+        "nls_guess_features": ([P, P, P], ctypes.c_int),
+        "nls_guess_lift": ([P, P, P, P], ctypes.c_int),
+        "nls_guess_predict": ([P, P, i64, P], ctypes.c_int),
+        "nls_guess_loss_grad": ([P, P, P, i64, P, ctypes.POINTER(dbl)], ctypes.c_int),
+        "nls_guess_train": ([P, ctypes.POINTER(TrainOpts), P, P, i64, P,
+                             ctypes.POINTER(TrainStats)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -339,3 +378,99 @@ class Solver:
                                                   _ptr(col), _ptr(val)))
         _, n0, _ = self.sizes()
         return sp.csr_matrix((val, col, rp), shape=(self.N, n0))
+
+    # ---- load and learned initial guess ------------------------------------
+    def set_load(self, elem_load):
+        """New load samples (E x 3, or None for f = 1) on the same partition."""
+        if elem_load is None:
+            self._check(self.lib.nls_set_load(self.h, None))
+        else:
+            a = np.ascontiguousarray(elem_load, dtype=np.float64)
+            self._check(self.lib.nls_set_load(self.h, _ptr(a)))
+
+    def _f32(self, x, cols):
+        t = self.torch
+        if isinstance(x, np.ndarray):
+            x = t.from_numpy(np.ascontiguousarray(x, dtype=np.float32))
+        x = x.to(self.device, t.float32).contiguous()
+        assert x.dim() == 2 and x.shape[1] == cols
+        return x
+
+    def guess_set_model(self, params, norm=None):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        nm = None if norm is None else np.ascontiguousarray(norm, dtype=np.float32)
+        assert nm is None or nm.size == GUESS_NORM
+        self._check(self.lib.nls_guess_set_model(self.h, _ptr(p), p.size,
+                                                 None if nm is None else _ptr(nm)))
+
+    def guess_get_model(self):
+        p = np.zeros(GUESS_PARAMS, dtype=np.float32)
+        nm = np.zeros(GUESS_NORM, dtype=np.float32)
+        self._check(self.lib.nls_guess_get_model(self.h, _ptr(p), _ptr(nm)))
+        return p, nm
+
+    def guess_enable(self, on=True):
+        self._check(self.lib.nls_guess_enable(self.h, 1 if on else 0))
+
+    def guess_capture(self, capacity):
+        self._check(self.lib.nls_guess_capture(self.h, int(capacity)))
+
+    def guess_captured(self):
+        t = self.torch
+        n = ctypes.c_int64(0)
+        self._check(self.lib.nls_guess_captured(self.h, None, None, 0, ctypes.byref(n)))
+        X = t.empty((n.value, GUESS_IN), dtype=t.float32, device=self.device)
+        T = t.empty((n.value, GUESS_OUT), dtype=t.float32, device=self.device)
+        if n.value:
+            self._check(self.lib.nls_guess_captured(self.h, self._vp(X), self._vp(T),
+                                                    n.value, ctypes.byref(n)))
+        return X, T
+
+    def guess_features(self, u):
+        u = self._dev(u)
+        ns, _, _ = self.sizes()
+        X = self.torch.empty((ns, GUESS_IN), dtype=self.torch.float32, device=self.device)
+        self._check(self.lib.nls_guess_features(self.h, self._vp(u), self._vp(X)))
+        return X
+
+    def guess_lift(self, u, coef):
+        u = self._dev(u)
+        c = self._f32(coef, GUESS_OUT)
+        _, _, nv = self.sizes()
+        x = self.torch.empty(int(nv.sum()), dtype=self.torch.float64, device=self.device)
+        self._check(self.lib.nls_guess_lift(self.h, self._vp(u), self._vp(c), self._vp(x)))
+        return x
+
+    def guess_predict(self, X):
+        X = self._f32(X, GUESS_IN)
+        Y = self.torch.empty((X.shape[0], GUESS_OUT), dtype=self.torch.float32,
+                             device=self.device)
+        self._check(self.lib.nls_guess_predict(self.h, self._vp(X), X.shape[0], self._vp(Y)))
+        return Y
+
+    def guess_loss_grad(self, X, T):
+        X = self._f32(X, GUESS_IN)
+        T = self._f32(T, GUESS_OUT)
+        g = self.torch.empty(GUESS_PARAMS, dtype=self.torch.float32, device=self.device)
+        loss = ctypes.c_double(0.0)
+        self._check(self.lib.nls_guess_loss_grad(self.h, self._vp(X), self._vp(T), X.shape[0],
+                                                 self._vp(g), ctypes.byref(loss)))
+        return g, loss.value
+
+    def guess_train(self, X, T, epochs, batch=256, lr=1e-3, order=None, fit_norm=True,
+                    cosine=False, beta1=0.9, beta2=0.999, eps=1e-8):
+        X = self._f32(X, GUESS_IN)
+        T = self._f32(T, GUESS_OUT)
+        o = TrainOpts(epochs=int(epochs), batch=int(batch), lr=float(lr), beta1=beta1,
+                      beta2=beta2, eps=eps,
+                      flags=(TRAIN_FIT_NORM if fit_norm else 0) | (TRAIN_COSINE if cosine else 0))
+        ordt = None
+        if order is not None:
+            ordt = self.torch.as_tensor(np.ascontiguousarray(order, dtype=np.int32)).to(self.device)
+            assert ordt.numel() == int(epochs) * X.shape[0]
+        st = TrainStats()
+        self._check(self.lib.nls_guess_train(self.h, ctypes.byref(o), self._vp(X), self._vp(T),
+                                             X.shape[0], None if ordt is None else self._vp(ordt),
+                                             ctypes.byref(st)))
+        return {"steps": st.steps, "final_loss": st.final_loss, "ms": st.ms,
+                "epoch_loss": list(st.epoch_loss[:min(int(epochs), MAX_EPOCHS)])}
