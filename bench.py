@@ -179,6 +179,99 @@ def run_batch(steps, warmup, device, n_inst=32):
     }
 
 
+def run_learned(device, amp, train_seeds, eval_seeds, epochs, batch=256, capacity=100_000):
+    """Learned initial guess on the 512x512 / 16x16 / overlap-2 / GDSW shape:
+    capture (features, target) pairs from the solver's own local solves on
+    training forcings (8 Fourier modes, amplitudes U(0, amp)), train the
+    network on the GPU, then solve held-out forcings with and without it.
+    Every held-out solve is timed from u = 0 to 1e-8; the solutions with and
+    without the network are compared."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2410_24138_amd import Solver
+    base = synth.config2()
+    mid = synth.edge_midpoints(base["xy"], base["conn"])
+
+    def load(seed):
+        return synth.fourier_eval(mid, synth.fourier_modes(seed, amp=amp))
+
+    s = Solver(base)
+    N = s.N
+    s.guess_capture(capacity)
+    t0 = time.perf_counter()
+    n_solves = 0
+    for sd in train_seeds:
+        s.set_load(load(sd))
+        s.solve_(torch.zeros(N, dtype=torch.float64, device=device))
+        n_solves += 1
+        if s.guess_count() >= capacity:
+            break
+    torch.cuda.synchronize(device)
+    t_capture = time.perf_counter() - t0
+    X, T = s.guess_captured()
+    n = X.shape[0]
+    s.guess_capture(0)
+    s.guess_set_model(synth.mlp_init(1))
+    order = synth.epoch_orders(2, n, epochs)
+    tr = s.guess_train(X, T, epochs=epochs, batch=batch, lr=1e-3, order=order, cosine=True)
+    del X, T
+    rows = []
+    for sd in eval_seeds:
+        s.set_load(load(sd))
+        out = {}
+        for mode in ("plain", "learned"):
+            s.guess_enable(mode == "learned")
+            s.solve_(torch.zeros(N, dtype=torch.float64, device=device))  # warm-up
+            u = torch.zeros(N, dtype=torch.float64, device=device)
+            torch.cuda.synchronize(device)
+            t1 = time.perf_counter()
+            st = s.solve_(u)
+            torch.cuda.synchronize(device)
+            out[mode] = {"ms": 1e3 * (time.perf_counter() - t1), "u": u, "st": st}
+        diff = float(torch.linalg.norm(out["learned"]["u"] - out["plain"]["u"])
+                     / torch.linalg.norm(out["plain"]["u"]))
+        rows.append({"seed": sd,
+                     "ms_plain": out["plain"]["ms"], "ms_learned": out["learned"]["ms"],
+                     "inner_plain": out["plain"]["st"]["inner_its_total"],
+                     "inner_learned": out["learned"]["st"]["inner_its_total"],
+                     "outer_plain": out["plain"]["st"]["outer_its"],
+                     "outer_learned": out["learned"]["st"]["outer_its"],
+                     "used": out["learned"]["st"]["guess_used"],
+                     "fallback": out["learned"]["st"]["guess_fallback"],
+                     "solves": out["learned"]["st"]["local_solves"],
+                     "converged": bool(out["plain"]["st"]["converged"]
+                                       and out["learned"]["st"]["converged"]),
+                     "rel_diff": diff})
+    s.close()
+    med = lambda k: float(np.median([r[k] for r in rows]))  # noqa: E731
+    ip = sum(r["inner_plain"] for r in rows)
+    il = sum(r["inner_learned"] for r in rows)
+    return {
+        "metric": "time-to-1e-8 per global solve with and without the learned initial guess",
+        "workload": f"diffusion_512x512_16x16_ov2_gdsw_amp{amp:g}",
+        "forcing": f"8 Fourier modes, amplitudes U(0,{amp:g}), k,l in 1..8",
+        "train": {"seeds": f"{train_seeds[0]}..{train_seeds[0] + n_solves - 1}",
+                  "samples": int(n), "capture_s": round(t_capture, 2), "epochs": epochs,
+                  "batch": batch, "steps": tr["steps"], "train_ms": round(tr["ms"], 1),
+                  "loss_first_epoch": tr["epoch_loss"][0], "loss_last_epoch": tr["final_loss"]},
+        "eval_seeds": f"{eval_seeds[0]}..{eval_seeds[-1]}",
+        "median_ms_plain": round(med("ms_plain"), 3),
+        "median_ms_learned": round(med("ms_learned"), 3),
+        "speedup": round(med("ms_plain") / med("ms_learned"), 4),
+        "inner_its_plain": ip, "inner_its_learned": il,
+        "inner_its_saved_frac": round(1 - il / ip, 4) if ip else None,
+        "guess_used": sum(r["used"] for r in rows),
+        "guess_fallback": sum(r["fallback"] for r in rows),
+        "local_solves": sum(r["solves"] for r in rows),
+        "outer_its_equal": all(r["outer_plain"] == r["outer_learned"] for r in rows),
+        "all_converged": all(r["converged"] for r in rows),
+        "max_rel_diff_learned_vs_plain": max(r["rel_diff"] for r in rows),
+        "per_seed": [{k: (round(v, 3) if isinstance(v, float) and k != "rel_diff" else v)
+                      for k, v in r.items()} for r in rows],
+    }
+
+
 def measured_traffic(kernel):
     """Counter-measured HBM bytes of a kernel, or None if the source changed."""
     import hashlib
@@ -226,7 +319,12 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--forms", default="plain,chosen")
-    ap.add_argument("--workload", default="diffusion512", choices=["diffusion512", "batch"])
+    ap.add_argument("--workload", default="diffusion512",
+                    choices=["diffusion512", "batch", "learned"])
+    ap.add_argument("--amp", type=float, default=10.0,
+                    help="forcing amplitude of the learned workload")
+    ap.add_argument("--train-seeds", type=int, default=130)
+    ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device copy (reference for HBM counters)")
@@ -254,6 +352,11 @@ def main():
         del src, dst
     if args.workload == "batch":
         print(json.dumps(run_batch(args.steps, args.warmup, device)), flush=True)
+        return
+    if args.workload == "learned":
+        res = run_learned(device, args.amp, list(range(5000, 5000 + args.train_seeds)),
+                          list(range(6000, 6010)), args.epochs)
+        print(json.dumps(res), flush=True)
         return
     case = synth.config2()
     golden = json.load(open(os.path.join(ROOT, "tests", "golden", case["name"] + ".json")))

@@ -415,6 +415,12 @@ class Solver:
     def guess_capture(self, capacity):
         self._check(self.lib.nls_guess_capture(self.h, int(capacity)))
 
+    def guess_count(self):
+        """Rows captured so far."""
+        n = ctypes.c_int64(0)
+        self._check(self.lib.nls_guess_captured(self.h, None, None, 0, ctypes.byref(n)))
+        return n.value
+
     def guess_captured(self):
         t = self.torch
         n = ctypes.c_int64(0)
