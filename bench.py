@@ -8,8 +8,13 @@ sum of 8 Fourier modes with amplitudes U(0,10), u_0 = 0, outer tolerance
 1e-8.  One step = one complete outer Newton solve from u = 0 (all local
 nonlinear solves, coarse corrections, GMRES on the exact tangent).
 
-Forms: "plain" (FP64 everywhere) and "chosen" (FP32 local LU with FP64
-iterative refinement; everything else FP64).  Every timed solve is checked
+Forms: "plain" (FP64 everywhere, Newton for the coarse correction, GMRES
+driven step by step from the host); "fp64_tuned" (FP64, GMRES rotations on
+the device with blocks of Arnoldi steps replayed as HIP graphs, chord steps
+for the coarse correction, autotuned LU variant per size bucket and coarse
+apply strategy); "chosen" (as fp64_tuned with FP32 local LU and FP64
+iterative refinement).  The JSON value is the fastest form whose solution
+meets 1e-8 against the stored global Newton solution.  Every timed solve is checked
 against the stored FP64 oracle trace (sampled solution, norm, outer count).
 
 Prints one JSON line.  Metric: subdomain Newton solves per second
@@ -26,6 +31,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "subdomain Newton solves/s; time-to-1e-8 per global solve, plain vs chosen"
+# form -> (local LU precision, driver features)
+FORMS = {
+    "plain": ("fp64", ()),                 # FP64, GMRES step by step from the host
+    "fp64_graph": ("fp64", ("graph",)),    # FP64, graph-replayed GMRES blocks
+    "fp64_graph_chord": ("fp64", ("graph", "chord")),
+    "fp64_graph_chord_luapply": ("fp64", ("graph", "chord", "luapply")),
+    "fp64_tuned": ("fp64", ("graph", "chord", "autotune")),
+    # FP32 local LU + FP64 refinement with graphs, chord coarse steps, autotuner
+    "chosen": ("fp32_ir", ("graph", "chord", "autotune")),
+}
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per dispatch measured with rocprofv3 FETCH_SIZE/WRITE_SIZE (two
 # passes, calibrated against a 256 MiB copy; profiles/hbm_traffic_*.md), valid
@@ -72,8 +87,12 @@ def run_form(case, golden, form, steps, warmup, device):
     import numpy as np
     import torch
     from paper_2410_24138_amd import Solver, nls
-    prec = {"plain": "fp64", "chosen": "fp32_ir"}[form]
-    s = Solver(case, precision=prec, device=device.index or 0, flags=nls.FLAG_PROFILE)
+    prec, extra = FORMS[form]
+    s = Solver(case, precision=prec, device=device.index or 0,
+               flags=nls.FLAG_PROFILE | (nls.FLAG_GRAPH if "graph" in extra else 0)
+               | (nls.FLAG_COARSE_CHORD if "chord" in extra else 0)
+               | (nls.FLAG_COARSE_LU_APPLY if "luapply" in extra else 0)
+               | (nls.FLAG_AUTOTUNE if "autotune" in extra else 0))
     N = s.N
     for _ in range(warmup):
         u = torch.zeros(N, dtype=torch.float64, device=device)
@@ -114,6 +133,7 @@ def run_form(case, golden, form, steps, warmup, device):
                               "ms": sum(st["ms_tangent_kernel"] for st in stats)},
         },
         "inner_its_steps": sum(st["inner_its_total"] for st in stats),
+        "tuning": s.tuning(),
     }
     s.close()
     return out
@@ -284,7 +304,7 @@ def measured_traffic(kernel):
 
 def roofline(case, res, form):
     """Dominant kernel and its HBM roofline fraction from algorithmic bytes."""
-    elem = 8 if form == "plain" else 4
+    elem = 8 if FORMS[form][0] == "fp64" else 4
     fac, n, ng = _factor_bytes(case, elem)
     kern = res["kernels"]
     k_t, k_l = kern["tangent_local"], kern["local_newton"]
@@ -306,7 +326,7 @@ def roofline(case, res, form):
         per_launch = float(per_sub.sum())
     avg_s = k["ms"] / max(k["launches"], 1) / 1e3
     achieved = per_launch / avg_s / 1e9
-    traffic = measured_traffic("k_" + name) if form == "plain" else None
+    traffic = measured_traffic("k_" + name) if FORMS[form][0] == "fp64" else None
     return {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic, "bytes_per_launch": per_launch,
@@ -318,7 +338,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--forms", default="plain,chosen")
+    ap.add_argument("--forms", default="plain,fp64_tuned,chosen")
     ap.add_argument("--workload", default="diffusion512",
                     choices=["diffusion512", "batch", "learned"])
     ap.add_argument("--amp", type=float, default=10.0,
@@ -380,7 +400,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if best == "plain" else "f32+f64",
+        "dtype": "f64" if FORMS[best][0] == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": case["name"], "grid": "512x512 P1", "nodes": len(case["xy"]),
                    "subdomains": 256, "overlap": 2, "coarse": "GDSW vertex+edge",

@@ -73,11 +73,42 @@ typedef struct nls_options {
     int    gmres_maxit;
     int    gmres_restart;
     int    flags;         /* NLS_FLAG_* bits */
+    int    lu_variant;    /* local band LU: 0 widest blocked panel the band
+                             allows (NB = 16 if kl <= 48, 8 if kl <= 56),
+                             1 blocked NB = 16, 2 blocked NB = 8, 3 unblocked
+                             (a variant that cannot hold a band falls back
+                             to the unblocked form); NLS_FLAG_AUTOTUNE
+                             overrides it per size bucket */
 } nls_options;
 
 /* options.flags: time the local-solve and local-tangent kernels with HIP
    events on the handle's stream (adds one event pair per launch). */
 #define NLS_FLAG_PROFILE  1
+/* options.flags: run GMRES with the Hessenberg rotations on the device and
+   every block of 4 Arnoldi steps replayed as one HIP graph (captured on
+   first use on a stream of the library's own), one host synchronisation
+   per block instead of per step.  Used when the tangent has its explicit
+   local blocks and, for two-level coupling, an explicit coarse inverse;
+   otherwise GMRES runs step by step. */
+#define NLS_FLAG_GRAPH    2
+/* options.flags: the coarse iteration for T_0 (eq. (9)) takes chord steps
+   with the last factorisation of A0 (from the previous evaluation or its
+   own first step), refactoring when the residual fails to halve; T_0 is
+   the same up to the coarse stopping rule.  A0 and its LU at the converged
+   coarse state are formed in every mode (exact tangent, eq. (12)). */
+#define NLS_FLAG_COARSE_CHORD 4
+/* options.flags: apply A0^{-1} in the tangent by band LU solves instead of
+   an explicit inverse formed once per evaluation. */
+#define NLS_FLAG_COARSE_LU_APPLY 8
+/* options.flags: at the first solve after the partition (or coarse space)
+   is set, time the candidates on the device and keep the fastest: for each
+   size bucket of local solves the band LU variant (blocked NB = 16, NB = 8,
+   unblocked; each with its own LDS size and hence occupancy), timed as the
+   bucket's fused local Newton launch at the initial iterate; for the coarse
+   term of the tangent the explicit inverse against a band LU solve per
+   GMRES step, priced at 20 steps per evaluation.  nls_get_tuning reports
+   the decisions. */
+#define NLS_FLAG_AUTOTUNE 16
 
 /* ---- statistics of the last solve ------------------------------------ */
 #define NLS_MAX_OUTER 64
@@ -205,6 +236,17 @@ int nls_get_sizes(nls_handle* h, int32_t* n_sub, int32_t* n_coarse,
    of their interface component. */
 int nls_get_coarse_basis(nls_handle* h, int64_t* nnz, int64_t* rowptr,
                          int32_t* col, double* val);
+
+/* Decisions of NLS_FLAG_AUTOTUNE (or the defaults before tuning), host
+   arrays with room for one entry per size bucket (at most n_sub):
+   *n_buckets; per bucket the LU variant (1 NB = 16, 2 NB = 8, 3 unblocked,
+   0 by band width), its LDS bytes and its subdomain count; *coarse_inverse
+   (1 explicit inverse, 0 LU solves) and coarse_ms[3] = measured ms of the
+   inverse, one inverse apply and one LU solve (0 if not tuned).  Any output
+   may be NULL. */
+int nls_get_tuning(nls_handle* h, int32_t* n_buckets, int32_t* lu_variant,
+                   int32_t* lds_bytes, int32_t* n_sub, int32_t* coarse_inverse,
+                   double* coarse_ms);
 
 /* ---- learned initial guess of the local solves ------------------------
    Not part of the paper's method, which starts every inner Newton

@@ -42,6 +42,7 @@ extern "C" int nls_default_options(nls_options* o) {
 }
 
 extern "C" int nls_create(const nls_options* opt, nls_handle** out) {
+    if (opt && (opt->lu_variant < 0 || opt->lu_variant > 3)) return NLS_EINVAL;
     if (!opt || !out) return NLS_EINVAL;
     if (opt->precision != NLS_PREC_FP64 && opt->precision != NLS_PREC_FP32_IR) return NLS_EINVAL;
     if (opt->coupling != NLS_ONE_LEVEL && opt->coupling != NLS_ADDITIVE) return NLS_EINVAL;
@@ -197,6 +198,18 @@ static int upload_problem(nls_handle* h) {
     return NLS_OK;
 }
 
+// LDS bytes of the fused local Newton kernel for subdomain i with LU variant v:
+// patch values, residual/step (and refinement vectors in mixed mode),
+// reduction scratch, multipliers, and the band window of the factorisation
+// (FP64 in every mode: the factorisation at the converged state is FP64).
+static int local_lds_bytes(const HostMaps& M, int i, bool mixed, int v) {
+    const int n = M.off_n[i + 1] - M.off_n[i], ng = M.off_g[i + 1] - M.off_g[i];
+    const int dbl = (n + ng) + n + (mixed ? 2 * n : 0) + 24 + std::max(M.kl[i], 1) + 1;
+    int w = band_window_doubles_v(M.kl[i], M.ku[i], v);
+    if (w < 0) w = band_window_doubles_v(M.kl[i], M.ku[i], 3);
+    return dbl * 8 + w * 8;
+}
+
 static int npl_for(int band) { return band <= 64 ? 1 : (band <= 128 ? 2 : 4); }
 
 extern "C" int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* elem_part,
@@ -207,6 +220,8 @@ extern "C" int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* el
     HIPCHK(hipSetDevice(h->opt.device));
     h->have_part = h->have_coarse = h->have_state = false;
     guess_invalidate(h);
+    h->drop_graphs();
+    h->tuned = false;
     h->free_group(G_MAPS);
     h->free_group(G_COARSE);
     RC(upload_problem(h));
@@ -227,22 +242,15 @@ extern "C" int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* el
     if (maxkl > 127 || maxband > 256)
         return fail(h, NLS_ELIMIT, "local band too wide (kl <= 127, kl+ku <= 256)");
     int lds = 0;
-    for (int i = 0; i < M.nsub; ++i) {
-        int n = M.off_n[i + 1] - M.off_n[i], ng = M.off_g[i + 1] - M.off_g[i];
-        int dbl = (n + ng) + n + (mixed ? 2 * n : 0) + 24 + std::max(M.kl[i], 1) + 1;
-        // the factorization at the converged state is FP64 in every mode
-        int bytes = dbl * 8 + band_window_doubles(M.kl[i], M.ku[i]) * 8;
-        lds = std::max(lds, bytes);
-    }
+    const int var0 = h->opt.lu_variant;
+    for (int i = 0; i < M.nsub; ++i) lds = std::max(lds, local_lds_bytes(M, i, mixed, var0));
     if (lds > 160 * 1024) return fail(h, NLS_ELIMIT, "subdomain too large for the LDS working set");
     h->lds_local = lds;
     // launch order: largest LDS first; size buckets of equal occupancy (WGs
     // per CU allowed by LDS), one launch each
     std::vector<int> sub_lds(M.nsub), sub_band(M.nsub);
     for (int i = 0; i < M.nsub; ++i) {
-        int n = M.off_n[i + 1] - M.off_n[i], ng = M.off_g[i + 1] - M.off_g[i];
-        int dbl = (n + ng) + n + (mixed ? 2 * n : 0) + 24 + std::max(M.kl[i], 1) + 1;
-        sub_lds[i] = dbl * 8 + band_window_doubles(M.kl[i], M.ku[i]) * 8;
+        sub_lds[i] = local_lds_bytes(M, i, mixed, var0);
         sub_band[i] = std::max(M.kl[i], M.kl[i] + M.ku[i]);
     }
     std::vector<int> lorder(M.nsub);
@@ -250,6 +258,8 @@ extern "C" int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* el
     std::stable_sort(lorder.begin(), lorder.end(), [&](int a, int b) { return sub_lds[a] > sub_lds[b]; });
     h->maps.order = lorder;
     h->bk_start.clear(); h->bk_end.clear(); h->bk_lds.clear(); h->bk_npl.clear();
+    h->bk_var.clear();
+    h->tuned = false;
     auto occ = [](int bytes) { return std::min(8, std::max(1, (160 * 1024) / std::max(bytes, 1))); };
     for (int p = 0; p < M.nsub;) {
         int q = p, band = 0;
@@ -261,6 +271,7 @@ extern "C" int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* el
         h->bk_end.push_back(q);
         h->bk_lds.push_back(sub_lds[lorder[p]]);
         h->bk_npl.push_back(npl_for(band));
+        h->bk_var.push_back(var0);
         p = q;
     }
     h->lds_tangent = (maxn + (mixed ? 2 * maxn : 0) + 24) * 8;
@@ -352,6 +363,7 @@ extern "C" int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* el
     np.mixed = mixed ? 1 : 0;
     np.ir_maxit = 10;
     np.ir_rtol = 1e-10;  // a Newton step needs no more; residuals stay FP64
+    np.lu_variant = var0;
     h->np = np;
     // GMRES workspace
     const int N = h->mesh.N;
@@ -369,6 +381,12 @@ extern "C" int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* el
     RC(h->alloc(G_MAPS, &h->ydev, h->m + 2));
     RC(h->alloc(G_MAPS, &h->ubuf, N));
     RC(h->alloc(G_MAPS, &h->stat2, 2));
+    RC(h->alloc(G_MAPS, &h->Hd, (size_t)(h->m + 1) * h->m));
+    RC(h->alloc(G_MAPS, &h->csd, h->m));
+    RC(h->alloc(G_MAPS, &h->snd, h->m));
+    RC(h->alloc(G_MAPS, &h->gd, h->m + 1));
+    RC(h->alloc(G_MAPS, &h->gtol, 1));
+    RC(h->alloc(G_MAPS, &h->gst, 2));
     RC(sync(h));
     h->have_part = true;
     if (h->opt.coupling == NLS_ADDITIVE) {
@@ -392,6 +410,8 @@ static int coarse_rhs_scale(nls_handle* h) {
 }
 
 extern "C" int nls_build_coarse(nls_handle* h, int kind) {
+    if (h) h->tuned = false;
+    if (h) h->drop_graphs();
     if (!h) return NLS_EINVAL;
     if (!h->have_part) return fail(h, NLS_ESTATE, "nls_set_partition first");
     HIPCHK(hipSetDevice(h->opt.device));
@@ -508,7 +528,8 @@ extern "C" int nls_build_coarse(nls_handle* h, int kind) {
     RC(h->alloc(G_COARSE, &h->ctmp, C.n0));
     RC(h->alloc(G_COARSE, &h->rhs2, C.n0));
     h->coarse_bucket = mrhs_bucket_kl(C.a0kl, C.a0ku);
-    h->coarse_inv = h->coarse_bucket <= 56;
+    h->coarse_inv = h->coarse_bucket <= 56 && !(h->opt.flags & NLS_FLAG_COARSE_LU_APPLY);
+    h->coarse_lu_valid = false;
     if (h->coarse_inv) {
         RC(h->alloc(G_COARSE, &d.a0inv, (size_t)C.offI.back()));
         RC(h->alloc(G_COARSE, &d.a0fwd, (size_t)C.offI.back()));
@@ -574,12 +595,19 @@ static bool two_level(nls_handle* h) {
 
 // Coarse Newton iteration for T_0(u) (eq. 9): c <- c + A0^{-1} Phi^T F(u - Phi c)
 // from c = 0; keeps LU(A0) at the converged c and u_0 = u - Phi c in dc.w.
+// T_0(u) (eq. 9): Newton on G(c) = Phi^T F(u - Phi c) = 0 from c = 0.  With
+// NLS_FLAG_COARSE_CHORD the steps reuse the last factorisation of A0 (from
+// the previous evaluation, or the first step's) and refactor only when the
+// residual fails to halve; A0 and its LU at the converged c* (kept for the
+// tangent, eq. 12) are formed in every mode.
 static int coarse_solve(nls_handle* h, const double* u, int* its_out) {
     DevCoarse& d = h->dc;
     const int n0 = d.n0;
+    const bool chord = (h->opt.flags & NLS_FLAG_COARSE_CHORD) != 0;
     HIPCHK(hipMemsetAsync(d.c, 0, sizeof(double) * n0, h->stream));
-    double tol = 0.0, dprev = -1.0, cmax = 0.0;
+    double tol = 0.0, dprev = -1.0, cmax = 0.0, gprev = 0.0;
     int its = 0;
+    bool have_lu = chord && h->coarse_lu_valid;
     for (;;) {
         HIPCHK(launch_coarse_w(h->dm, d, u, d.w, h->stream));
         HIPCHK(launch_coarse_q(h->dm, d, d.w, nullptr, 0, h->lds_coarse_q, h->stream));
@@ -593,9 +621,13 @@ static int coarse_solve(nls_handle* h, const double* u, int* its_out) {
         if (gn <= tol) break;
         if (dprev >= 0.0 && dprev <= h->opt.stagnation * cmax) break;
         if (its == h->opt.inner_maxit) return fail(h, NLS_ELOCAL, "coarse Newton did not converge");
-        HIPCHK(launch_coarse_galerkin(h->dm, d, d.w, 0, h->stream));
-        HIPCHK(launch_coarse_assemble(d, 1, h->stream));
-        HIPCHK(launch_coarse_lu(d, 1, h->lds_coarse_lu, h->npl_coarse, h->stream));
+        const bool refactor = !have_lu || (its > 0 && gn > 0.5 * gprev);
+        if (refactor) {
+            HIPCHK(launch_coarse_galerkin(h->dm, d, d.w, 0, h->stream));
+            HIPCHK(launch_coarse_assemble(d, 1, h->stream));
+        }
+        HIPCHK(launch_coarse_lu(d, refactor ? 1 : 0, h->lds_coarse_lu, h->npl_coarse, h->stream));
+        have_lu = chord;
         HIPCHK(launch_coarse_update(d, h->stream));
         double sc[3];
         int flag = 0;
@@ -605,12 +637,14 @@ static int coarse_solve(nls_handle* h, const double* u, int* its_out) {
         if (flag) return fail(h, NLS_ESINGULAR, "zero pivot in the coarse matrix");
         dprev = sc[1];
         cmax = sc[2];
+        gprev = gn;
         ++its;
     }
     // Galerkin matrix and its LU at the converged point, for the tangent
     HIPCHK(launch_coarse_galerkin(h->dm, d, d.w, 1, h->stream));
     HIPCHK(launch_coarse_assemble(d, 1, h->stream));
     HIPCHK(launch_coarse_lu(d, 1, h->lds_coarse_lu, h->npl_coarse, h->stream));
+    h->coarse_lu_valid = true;
     if (h->coarse_inv) HIPCHK(launch_coarse_inverse(d, h->coarse_bucket, h->max_block, h->stream));
     if (its_out) *its_out = its;
     return NLS_OK;
@@ -638,6 +672,7 @@ static int evaluate(nls_handle* h, const double* u, double* Fx) {
     for (size_t b = 0; b < h->bk_start.size(); ++b) {
         DevMaps pb = h->dp;
         pb.order = h->dp.order + h->bk_start[b];
+        np.lu_variant = h->bk_var[b];
         HIPCHK(launch_local_newton(h->dm, pb, h->dl, np, u, h->bk_end[b] - h->bk_start[b],
                                    h->bk_lds[b], h->bk_npl[b], h->stream));
     }
@@ -689,37 +724,299 @@ static int evaluate(nls_handle* h, const double* u, double* Fx) {
     return NLS_OK;
 }
 
+// ------------------------------------------------------------ autotuner
+// Times each candidate with HIP events on the handle's stream (second of
+// two runs) and keeps the fastest.
+template <class F>
+static int time_ms(nls_handle* h, F&& launch, float* ms) {
+    hipEvent_t a = nullptr, b = nullptr;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    float best = 0.f;
+    for (int rep = 0; rep < 2; ++rep) {
+        HIPCHK(hipEventRecord(a, h->stream));
+        int rc = launch();
+        if (rc) {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+            return rc;
+        }
+        HIPCHK(hipEventRecord(b, h->stream));
+        HIPCHK(hipEventSynchronize(b));
+        HIPCHK(hipEventElapsedTime(&best, a, b));
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *ms = best;
+    return NLS_OK;
+}
+
+// Per size bucket: the LU variants that hold the bucket's widest band
+// (blocked NB=16, NB=8, unblocked), each timed as the bucket's fused local
+// Newton launch at u; each variant sizes its own LDS, so a narrower window
+// may also raise the workgroups per CU.
+static int autotune_local(nls_handle* h, const double* u) {
+    const HostMaps& M = h->maps;
+    const bool mixed = h->opt.precision == NLS_PREC_FP32_IR;
+    for (size_t b = 0; b < h->bk_start.size(); ++b) {
+        int kmax = 0;
+        for (int p = h->bk_start[b]; p < h->bk_end[b]; ++p) kmax = std::max(kmax, M.kl[M.order[p]]);
+        float best = 1e30f;
+        int bv = h->bk_var[b], blds = h->bk_lds[b];
+        for (int v = 1; v <= 3; ++v) {
+            if (v == 1 && kmax + 16 > 64) continue;
+            if (v == 2 && kmax + 8 > 64) continue;
+            int lds = 0;
+            for (int p = h->bk_start[b]; p < h->bk_end[b]; ++p)
+                lds = std::max(lds, local_lds_bytes(M, M.order[p], mixed, v));
+            if (lds > 160 * 1024) continue;
+            NewtonParams np = h->np;
+            np.xpred = nullptr;
+            np.lu_variant = v;
+            DevMaps pb = h->dp;
+            pb.order = h->dp.order + h->bk_start[b];
+            const int nb = h->bk_end[b] - h->bk_start[b];
+            float ms = 0.f;
+            RC(time_ms(h, [&]() -> int {
+                HIPCHK(launch_local_newton(h->dm, pb, h->dl, np, u, nb, lds, h->bk_npl[b], h->stream));
+                return NLS_OK;
+            }, &ms));
+            if (ms < best) {
+                best = ms;
+                bv = v;
+                blds = lds;
+            }
+        }
+        h->bk_var[b] = bv;
+        h->bk_lds[b] = blds;
+    }
+    return NLS_OK;
+}
+
+// Coarse term of the tangent: explicit A0^{-1} (formed once per evaluation,
+// then a GEMV per GMRES step) against a band LU solve per step, priced with
+// the measured kernel times at TUNE_STEPS steps per evaluation.
+static constexpr int TUNE_STEPS = 20;
+static int autotune_coarse(nls_handle* h) {
+    if (!two_level(h) || h->coarse_bucket > 56 || (h->opt.flags & NLS_FLAG_COARSE_LU_APPLY))
+        return NLS_OK;
+    DevCoarse& d = h->dc;
+    float t_inv = 0.f, t_apply = 0.f, t_lu = 0.f;
+    RC(time_ms(h, [&]() -> int {
+        HIPCHK(launch_coarse_inverse(d, h->coarse_bucket, h->max_block, h->stream));
+        return NLS_OK;
+    }, &t_inv));
+    RC(time_ms(h, [&]() -> int {
+        HIPCHK(launch_coarse_apply_inverse(d, d.rhs, h->rhs2, h->stream));
+        return NLS_OK;
+    }, &t_apply));
+    RC(time_ms(h, [&]() -> int {
+        HIPCHK(launch_coarse_lu(d, 0, h->lds_coarse_lu, h->npl_coarse, h->stream));
+        return NLS_OK;
+    }, &t_lu));
+    const bool inv = t_inv + TUNE_STEPS * t_apply <= TUNE_STEPS * t_lu;
+    if (inv != h->coarse_inv) {
+        h->coarse_inv = inv;
+        h->drop_graphs();
+        if (inv) HIPCHK(launch_coarse_inverse(d, h->coarse_bucket, h->max_block, h->stream));
+    }
+    h->tune_ms[0] = t_inv;
+    h->tune_ms[1] = t_apply;
+    h->tune_ms[2] = t_lu;
+    return sync(h);
+}
+
 // y = D F_x(u) v (eqs. 6, 7, 12) at the last evaluated point.
-static int tangent(nls_handle* h, const double* v, double* y) {
+// Enqueued on s (the handle's stream by default); no host synchronisation,
+// so the sequence can be captured into a graph (events only when eager).
+static int tangent(nls_handle* h, const double* v, double* y, hipStream_t s = nullptr) {
+    const bool eager = s == nullptr;
+    if (eager) s = h->stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (h->profiling()) {
+    if (eager && h->profiling()) {
         e0 = h->take_event();
         e1 = h->take_event();
-        HIPCHK(hipEventRecord(e0, h->stream));
+        HIPCHK(hipEventRecord(e0, s));
     }
     if (h->tangent_w)
-        HIPCHK(launch_tangent_gemv(h->dp, h->dt, v, h->dl.z, h->max_ng, h->stream));
+        HIPCHK(launch_tangent_gemv(h->dp, h->dt, v, h->dl.z, h->max_ng, s));
     else
-        HIPCHK(launch_tangent_local(h->dm, h->dp, h->dl, h->np, v, h->lds_tangent, h->npl_local, h->stream));
+        HIPCHK(launch_tangent_local(h->dm, h->dp, h->dl, h->np, v, h->lds_tangent, h->npl_local, s));
     if (e0) {
-        HIPCHK(hipEventRecord(e1, h->stream));
+        HIPCHK(hipEventRecord(e1, s));
         h->ev_used.push_back({1, {e0, e1}});
     }
     if (two_level(h)) {
         DevCoarse& d = h->dc;
-        HIPCHK(launch_coarse_ty(d, v, h->stream));
-        HIPCHK(launch_coarse_assemble(d, 0, h->stream));
+        HIPCHK(launch_coarse_ty(d, v, s));
+        HIPCHK(launch_coarse_assemble(d, 0, s));
         if (h->coarse_inv) {
-            HIPCHK(launch_coarse_apply_inverse(d, d.rhs, h->rhs2, h->stream));
-            HIPCHK(launch_coarse_scatter(d, h->rhs2, h->ctmp, h->stream));
+            HIPCHK(launch_coarse_apply_inverse(d, d.rhs, h->rhs2, s));
+            HIPCHK(launch_coarse_scatter(d, h->rhs2, h->ctmp, s));
         } else {
-            HIPCHK(launch_coarse_lu(d, 0, h->lds_coarse_lu, h->npl_coarse, h->stream));
-            HIPCHK(launch_coarse_scatter(d, nullptr, h->ctmp, h->stream));
+            HIPCHK(launch_coarse_lu(d, 0, h->lds_coarse_lu, h->npl_coarse, s));
+            HIPCHK(launch_coarse_scatter(d, nullptr, h->ctmp, s));
         }
-        HIPCHK(launch_prolong(h->dm, h->dp, h->dl.z, &d, h->ctmp, y, v, h->stream));
+        HIPCHK(launch_prolong(h->dm, h->dp, h->dl.z, &d, h->ctmp, y, v, s));
     } else {
-        HIPCHK(launch_prolong(h->dm, h->dp, h->dl.z, nullptr, nullptr, y, v, h->stream));
+        HIPCHK(launch_prolong(h->dm, h->dp, h->dl.z, nullptr, nullptr, y, v, s));
     }
+    return NLS_OK;
+}
+
+// ---------------------------------------------------- graph-captured GMRES
+static GmresDev gmres_dev(nls_handle* h) {
+    GmresDev G{};
+    G.H = h->Hd;
+    G.cs = h->csd;
+    G.sn = h->snd;
+    G.g = h->gd;
+    G.h1 = h->hbuf;
+    G.h2 = h->hbuf2;
+    G.hn2 = h->hn2;
+    G.tol = h->gtol;
+    G.st = h->gst;
+    G.m = h->m;
+    return G;
+}
+
+// Arnoldi step j on stream s: w = A v_j, two classical Gram-Schmidt passes,
+// v_{j+1} = w / ||w||, then rotation j on the device.  No host contact.
+static int arnoldi_step(nls_handle* h, int j, hipStream_t s) {
+    const int N = h->mesh.N;
+    const int64_t ld = N;
+    double* vj = h->V + (int64_t)j * ld;
+    double* vn = h->V + (int64_t)(j + 1) * ld;
+    RC(tangent(h, vj, h->wv, s));
+    HIPCHK(launch_mdot(h->V, ld, j + 1, h->wv, N, h->partial, h->hbuf, h->nb_dot, s));
+    HIPCHK(launch_maxpy(h->V, ld, j + 1, h->hbuf, h->wv, N, 1.0, s));
+    HIPCHK(launch_mdot(h->V, ld, j + 1, h->wv, N, h->partial, h->hbuf2, h->nb_dot, s));
+    HIPCHK(launch_maxpy(h->V, ld, j + 1, h->hbuf2, h->wv, N, 1.0, s));
+    HIPCHK(launch_mdot(h->wv, ld, 1, h->wv, N, h->partial, h->hn2, h->nb_dot, s));
+    HIPCHK(launch_scale_by(h->wv, h->hn2, vn, N, s));
+    HIPCHK(launch_gmres_givens(gmres_dev(h), j, s));
+    return NLS_OK;
+}
+
+static bool graph_gmres_ok(const nls_handle* h) {
+    return (h->opt.flags & NLS_FLAG_GRAPH) && h->tangent_w;
+}
+
+// Steps [b*K, min((b+1)*K, m)) of a cycle as one graph, captured on first use.
+static int block_graph(nls_handle* h, int b, hipGraphExec_t* out) {
+    const int K = h->gblock;
+    if ((int)h->gexec.size() <= b) h->gexec.resize(b + 1, nullptr);
+    if (!h->gexec[b]) {
+        // kernel attributes are set before capture, never inside it
+        if (two_level(h) && !h->coarse_inv)
+            HIPCHK(prepare_coarse_lu(h->lds_coarse_lu, h->npl_coarse));
+        hipGraph_t graph = nullptr;
+        HIPCHK(hipStreamBeginCapture(h->gstream, hipStreamCaptureModeThreadLocal));
+        int rc = NLS_OK;
+        for (int j = b * K; j < std::min((b + 1) * K, h->m) && rc == NLS_OK; ++j)
+            rc = arnoldi_step(h, j, h->gstream);
+        hipError_t ec = hipStreamEndCapture(h->gstream, &graph);
+        if (rc != NLS_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        HIPCHK(ec);
+        hipGraphExec_t ex = nullptr;
+        hipError_t ei = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIPCHK(ei);
+        h->gexec[b] = ex;
+    }
+    *out = h->gexec[b];
+    return NLS_OK;
+}
+
+// Restarted GMRES as gmres() below, with the Hessenberg rotations on the
+// device and each block of gblock Arnoldi steps replayed as one graph; the
+// host reads the convergence state once per block.  Steps of a block after
+// convergence run but are not used.
+static int gmres_graph(nls_handle* h, const double* b, double* x, int* its_out) {
+    const int N = h->mesh.N, m = h->m, K = h->gblock;
+    double bn2 = 0.0;
+    RC(dot_host(h, b, b, N, &bn2));
+    const double bn = std::sqrt(bn2);
+    HIPCHK(hipMemsetAsync(x, 0, sizeof(double) * N, h->stream));
+    *its_out = 0;
+    if (bn == 0.0) return NLS_OK;
+    if (!h->gstream) {
+        HIPCHK(hipStreamCreateWithFlags(&h->gstream, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&h->gev[0], hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&h->gev[1], hipEventDisableTiming));
+    }
+    const double tol = h->opt.gmres_rtol * bn;
+    HIPCHK(hipMemcpyAsync(h->gtol, &tol, sizeof(double), hipMemcpyHostToDevice, h->stream));
+    std::vector<double> H((size_t)(m + 1) * m), g(m + 1), y(m), g0(m + 1);
+    int its = 0;
+    bool first = true;
+    while (its < h->opt.gmres_maxit) {
+        double beta2;
+        if (first) {
+            HIPCHK(hipMemcpyAsync(h->V, b, sizeof(double) * N, hipMemcpyDeviceToDevice, h->stream));
+            beta2 = bn2;
+        } else {
+            RC(tangent(h, x, h->tmp));
+            HIPCHK(hipMemcpyAsync(h->V, b, sizeof(double) * N, hipMemcpyDeviceToDevice, h->stream));
+            HIPCHK(launch_axpy(-1.0, h->tmp, h->V, N, h->stream));
+            RC(dot_host(h, h->V, h->V, N, &beta2));
+        }
+        first = false;
+        const double beta = std::sqrt(beta2);
+        if (beta <= tol) break;
+        HIPCHK(hipMemcpyAsync(h->hn2, &beta2, sizeof(double), hipMemcpyHostToDevice, h->stream));
+        HIPCHK(launch_scale_by(h->V, h->hn2, h->V, N, h->stream));
+        std::fill(g0.begin(), g0.end(), 0.0);
+        g0[0] = beta;
+        const int st0[2] = {0, 0};
+        HIPCHK(hipMemcpyAsync(h->gd, g0.data(), (m + 1) * sizeof(double), hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipMemcpyAsync(h->gst, st0, sizeof(st0), hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipEventRecord(h->gev[0], h->stream));
+        HIPCHK(hipStreamWaitEvent(h->gstream, h->gev[0], 0));
+        int j = 0, conv = 0;
+        while (j < m) {
+            const int budget = h->opt.gmres_maxit - its - j;
+            if (budget <= 0) break;
+            const int blk = j / K, jn = std::min((blk + 1) * K, m);
+            if (j == blk * K && jn - j <= budget) {
+                hipGraphExec_t ex = nullptr;
+                RC(block_graph(h, blk, &ex));
+                HIPCHK(hipGraphLaunch(ex, h->gstream));
+            } else {
+                for (int jj = j; jj < std::min(jn, j + budget); ++jj) RC(arnoldi_step(h, jj, h->gstream));
+            }
+            int st[2];
+            HIPCHK(hipMemcpyAsync(st, h->gst, sizeof(st), hipMemcpyDeviceToHost, h->gstream));
+            HIPCHK(hipStreamSynchronize(h->gstream));
+            if (st[0] < 0) return fail(h, NLS_ENAN, "GMRES breakdown (non-finite)");
+            if (st[0] > 0) {
+                conv = st[0];
+                j = conv;
+                break;
+            }
+            j = st[1];
+        }
+        if (j == 0) break;
+        HIPCHK(hipMemcpyAsync(H.data(), h->Hd, H.size() * sizeof(double), hipMemcpyDeviceToHost, h->gstream));
+        HIPCHK(hipMemcpyAsync(g.data(), h->gd, (m + 1) * sizeof(double), hipMemcpyDeviceToHost, h->gstream));
+        HIPCHK(hipStreamSynchronize(h->gstream));
+        for (int i = j - 1; i >= 0; --i) {
+            double s = g[i];
+            for (int k = i + 1; k < j; ++k) s -= H[(size_t)i * m + k] * y[k];
+            y[i] = s / H[(size_t)i * m + i];
+        }
+        HIPCHK(hipMemcpyAsync(h->ydev, y.data(), j * sizeof(double), hipMemcpyHostToDevice, h->gstream));
+        HIPCHK(launch_maxpy(h->V, N, j, h->ydev, x, N, -1.0, h->gstream));
+        HIPCHK(hipEventRecord(h->gev[1], h->gstream));
+        HIPCHK(hipStreamWaitEvent(h->stream, h->gev[1], 0));
+        its += j;
+        RC(sync(h));
+        if (conv) break;
+    }
+    *its_out = its;
     return NLS_OK;
 }
 
@@ -818,6 +1115,7 @@ extern "C" int nls_solve(nls_handle* h, double* u, int u_on_device, nls_stats* s
     std::memset(S, 0, sizeof(*S));
     S->failed_subdomain = -1;
     h->st = S;
+    h->coarse_lu_valid = false;  // chord steps reuse factorisations within one solve only
     const int N = h->mesh.N;
     double* ud = u;
     if (!u_on_device) {
@@ -834,8 +1132,16 @@ extern "C" int nls_solve(nls_handle* h, double* u, int u_on_device, nls_stats* s
         h->st = nullptr;
         return code;
     };
-    int rc = evaluate(h, ud, h->Fx);
+    const bool tune = (h->opt.flags & NLS_FLAG_AUTOTUNE) && !h->tuned;
+    int rc = tune ? autotune_local(h, ud) : NLS_OK;
     if (rc) return finish(rc);
+    rc = evaluate(h, ud, h->Fx);
+    if (rc) return finish(rc);
+    if (tune) {
+        rc = autotune_coarse(h);
+        if (rc) return finish(rc);
+        h->tuned = true;
+    }
     double r2 = 0.0;
     rc = dot_host(h, h->Fx, h->Fx, N, &r2);
     if (rc) return finish(rc);
@@ -851,7 +1157,7 @@ extern "C" int nls_solve(nls_handle* h, double* u, int u_on_device, nls_stats* s
         if (k == h->opt.outer_maxit) break;
         Timer tg;
         int gits = 0;
-        rc = gmres(h, h->Fx, h->du, &gits);
+        rc = graph_gmres_ok(h) ? gmres_graph(h, h->Fx, h->du, &gits) : gmres(h, h->Fx, h->du, &gits);
         S->ms_gmres += tg.ms();
         if (rc) return finish(rc);
         S->gmres_its[k] = gits;
@@ -885,6 +1191,7 @@ extern "C" int nls_eval_precond_residual(nls_handle* h, const double* u, double*
     if (h->opt.coupling == NLS_ADDITIVE && !h->have_coarse)
         return fail(h, NLS_ESTATE, "two-level coupling needs nls_build_coarse");
     HIPCHK(hipSetDevice(h->opt.device));
+    h->coarse_lu_valid = false;
     RC(evaluate(h, u, Fx));
     return sync(h);
 }
@@ -969,4 +1276,22 @@ extern "C" const char* nls_strerror(int code) {
 
 extern "C" const char* nls_last_error(nls_handle* h) {
     return h ? h->err.c_str() : "null handle";
+}
+
+extern "C" int nls_get_tuning(nls_handle* h, int32_t* n_buckets, int32_t* lu_variant,
+                              int32_t* lds_bytes, int32_t* n_sub, int32_t* coarse_inverse,
+                              double* coarse_ms) {
+    if (!h) return NLS_EINVAL;
+    if (!h->have_part) return fail(h, NLS_ESTATE, "nls_set_partition first");
+    const int nb = (int)h->bk_start.size();
+    if (n_buckets) *n_buckets = nb;
+    for (int b = 0; b < nb; ++b) {
+        if (lu_variant) lu_variant[b] = h->bk_var[b];
+        if (lds_bytes) lds_bytes[b] = h->bk_lds[b];
+        if (n_sub) n_sub[b] = h->bk_end[b] - h->bk_start[b];
+    }
+    if (coarse_inverse) *coarse_inverse = h->coarse_inv ? 1 : 0;
+    if (coarse_ms)
+        for (int k = 0; k < 3; ++k) coarse_ms[k] = h->tune_ms[k];
+    return NLS_OK;
 }

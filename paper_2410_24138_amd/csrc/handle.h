@@ -50,10 +50,14 @@ struct nls_handle {
     bool tangent_w = false;       // W_i = J^{-1} B on owned rows (else per-apply solves)
     int tangent_bucket = 0, max_ng = 0;
     bool coarse_inv = false;      // explicit A0^{-1} for the tangent
+    bool coarse_lu_valid = false; // a factorisation of A0 is held (chord steps)
     int coarse_bucket = 0, max_block = 0;
     // size buckets of the local-solve launches: [start, end) in the launch
     // order, LDS bytes and solve width of each
     std::vector<int> bk_start, bk_end, bk_lds, bk_npl;
+    std::vector<int> bk_var;      // LU variant of each bucket (see NewtonParams)
+    bool tuned = false;           // NLS_FLAG_AUTOTUNE decisions taken
+    double tune_ms[3] = {0.0, 0.0, 0.0};  // coarse: inverse, inverse apply, LU solve
     double* rhs2 = nullptr;
     NewtonParams np{};
     double b_inf = 0.0, phib_inf = 0.0;
@@ -73,6 +77,19 @@ struct nls_handle {
     double *d_part = nullptr, *d_mx = nullptr;
     // learned initial guess (null until first used)
     GuessState* guess = nullptr;
+    // GMRES cycles with device-side rotations; blocks of gblock Arnoldi
+    // steps captured once as HIP graphs and replayed on gstream
+    hipStream_t gstream = nullptr;
+    hipEvent_t gev[2] = {nullptr, nullptr};
+    std::vector<hipGraphExec_t> gexec;
+    double *Hd = nullptr, *csd = nullptr, *snd = nullptr, *gd = nullptr, *gtol = nullptr;
+    int* gst = nullptr;
+    int gblock = 4;
+    void drop_graphs() {
+        for (auto e : gexec)
+            if (e) (void)hipGraphExecDestroy(e);
+        gexec.clear();
+    }
     std::vector<int> its_h;
     nls_stats* st = nullptr;  // stats of the running solve (may be null)
     // event pairs of profiled launches (kind 0: local Newton, 1: tangent)
@@ -106,6 +123,10 @@ struct nls_handle {
 
     ~nls_handle() {
         guess_state_free(guess);
+        drop_graphs();
+        for (auto e : gev)
+            if (e) (void)hipEventDestroy(e);
+        if (gstream) (void)hipStreamDestroy(gstream);
         for (auto& g : bufs)
             for (void* p : g) (void)hipFree(p);
         for (auto& u : ev_used) {

@@ -567,10 +567,11 @@ template <typename T>
 __device__ __forceinline__ int band_lu_auto(int n, int kl, int ku, const int* __restrict__ rptr,
                             const int* __restrict__ cols, const double* __restrict__ vals,
                             T* W, T* mult, int* sflag, T* __restrict__ Uf, T* __restrict__ Lf,
-                            int* __restrict__ piv, int cbase = 0) {
-    if (kl + 16 <= 64)
+                            int* __restrict__ piv, int cbase = 0, int variant = 0) {
+    // variant: 0 widest panel the band allows, 1 NB=16, 2 NB=8, 3 unblocked
+    if ((variant == 0 || variant == 1) && kl + 16 <= 64)
         return band_lu_blocked<T, 16>(n, kl, ku, rptr, cols, vals, W, sflag, Uf, Lf, piv, cbase);
-    if (kl + 8 <= 64)
+    if ((variant == 0 || variant == 2) && kl + 8 <= 64)
         return band_lu_blocked<T, 8>(n, kl, ku, rptr, cols, vals, W, sflag, Uf, Lf, piv, cbase);
     return band_lu<T>(n, kl, ku, rptr, cols, vals, W, mult, sflag, Uf, Lf, piv, cbase);
 }
@@ -721,9 +722,11 @@ __device__ __forceinline__ int local_factor(const DevMaps& P, const DevLocal& L,
     const int* rptr = P.jptr + rowbase;
     if (np.mixed && !fp64)
         return band_lu_auto<float>(n, kl, ku, rptr, P.jcol, L.jval, (float*)W, (float*)mult, sflag,
-                              L.Uf32 + P.off_u[i], L.Lf32 + P.off_l[i], L.piv + rowbase);
+                              L.Uf32 + P.off_u[i], L.Lf32 + P.off_l[i], L.piv + rowbase, 0,
+                              np.lu_variant);
     return band_lu_auto<double>(n, kl, ku, rptr, P.jcol, L.jval, (double*)W, (double*)mult, sflag,
-                           L.Uf + P.off_u[i], L.Lf + P.off_l[i], L.piv + rowbase);
+                           L.Uf + P.off_u[i], L.Lf + P.off_l[i], L.piv + rowbase, 0,
+                           np.lu_variant);
 }
 
 // ----------------------------------------------------------------------------
@@ -1678,6 +1681,38 @@ __global__ void k_any_status(const int* __restrict__ st, int n, int* __restrict_
     out[1] = code;
 }
 
+// Column j of the Arnoldi process on the device: H(:,j) = h1 + h2 (the two
+// classical Gram-Schmidt passes), H(j+1,j) = ||w||; the previous rotations
+// are applied, rotation j is formed and the residual vector g updated.
+// Columns after the cycle has converged (st[0] != 0) are ignored.
+__global__ void k_gmres_givens(GmresDev G, int j) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (G.st[0] != 0) return;
+    const int m = G.m;
+    double* H = G.H;
+    for (int i = 0; i <= j; ++i) H[i * m + j] = G.h1[i] + G.h2[i];
+    H[(j + 1) * m + j] = sqrt(G.hn2[0]);
+    for (int i = 0; i < j; ++i) {
+        const double a = H[i * m + j], b = H[(i + 1) * m + j];
+        H[(i + 1) * m + j] = -G.sn[i] * a + G.cs[i] * b;
+        H[i * m + j] = G.cs[i] * a + G.sn[i] * b;
+    }
+    const double a = H[j * m + j], b = H[(j + 1) * m + j];
+    const double den = hypot(a, b);
+    const double c = den > 0.0 ? a / den : 1.0, sn = den > 0.0 ? b / den : 0.0;
+    G.cs[j] = c;
+    G.sn[j] = sn;
+    H[j * m + j] = den;
+    H[(j + 1) * m + j] = 0.0;
+    const double gj = G.g[j];
+    G.g[j + 1] = -sn * gj;
+    G.g[j] = c * gj;
+    G.st[1] = j + 1;
+    const double r = fabs(G.g[j + 1]);
+    if (!(r == r) || isinf(r)) G.st[0] = -(j + 1);
+    else if (r <= G.tol[0]) G.st[0] = j + 1;
+}
+
 inline int nblocks(int n, int b = NLS_BLOCK) { return (n + b - 1) / b; }
 
 template <typename K>
@@ -1797,6 +1832,12 @@ hipError_t launch_coarse_lu(const DevCoarse& C, int factor, int lds_bytes, int n
     return hipGetLastError();
 }
 
+hipError_t prepare_coarse_lu(int lds_bytes, int npl) {
+    if (npl <= 1) return set_lds(k_coarse_lu<1>, lds_bytes);
+    if (npl == 2) return set_lds(k_coarse_lu<2>, lds_bytes);
+    return set_lds(k_coarse_lu<4>, lds_bytes);
+}
+
 hipError_t launch_coarse_update(const DevCoarse& C, hipStream_t s) {
     k_coarse_update<<<1, NLS_BLOCK, 0, s>>>(C);
     return hipGetLastError();
@@ -1891,5 +1932,10 @@ hipError_t launch_max_abs(const double* x, int n, double* partial, double* out, 
 
 hipError_t launch_any_status(const int* status, int n, int* out, hipStream_t s) {
     k_any_status<<<1, 64, 0, s>>>(status, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gmres_givens(const GmresDev& G, int j, hipStream_t s) {
+    k_gmres_givens<<<1, 64, 0, s>>>(G, j);
     return hipGetLastError();
 }

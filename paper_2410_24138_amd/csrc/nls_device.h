@@ -65,6 +65,7 @@ struct NewtonParams {
     int ir_maxit;
     double ir_rtol;
     const double* xpred;        // packed predicted starts, or null
+    int lu_variant;             // 0 by band width, 1 blocked NB=16, 2 NB=8, 3 unblocked
 };
 
 // GDSW coarse space tables (see HostCoarse) and state.
@@ -153,3 +154,16 @@ hipError_t launch_add_inplace(const double* x, double* y, int n, hipStream_t s);
 hipError_t launch_max_abs(const double* x, int n, double* partial, double* out,
                           int nblocks, hipStream_t s);
 hipError_t launch_any_status(const int* status, int n, int* out, hipStream_t s);
+
+// Device-resident state of one GMRES restart cycle (Hessenberg matrix H,
+// (m+1) x m row-major, Givens rotations, residual vector g).  st[0]: 0 while
+// |g_j| > tol, j when column j first met it, -j if it became non-finite;
+// st[1]: columns processed.
+struct GmresDev {
+    double *H, *cs, *sn, *g;
+    const double *h1, *h2, *hn2, *tol;
+    int* st;
+    int m;
+};
+hipError_t prepare_coarse_lu(int lds_bytes, int npl);
+hipError_t launch_gmres_givens(const GmresDev& G, int j, hipStream_t s);

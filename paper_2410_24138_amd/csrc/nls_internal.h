@@ -14,6 +14,14 @@ inline int band_window_doubles(int kl, int ku) {
     if (kl + 8 <= 64) return (8 + kl) * (8 + kl + ku) + 8 * 8;
     return (kl + 1) * (kl + ku + 1);
 }
+// Window of a forced LU variant: 1 blocked NB=16, 2 blocked NB=8,
+// 3 unblocked, 0 the automatic choice above; -1 if the variant cannot hold kl.
+inline int band_window_doubles_v(int kl, int ku, int v) {
+    if (v == 0) return band_window_doubles(kl, ku);
+    if (v == 1) return kl + 16 <= 64 ? (16 + kl) * (16 + kl + ku) + 16 * 16 : -1;
+    if (v == 2) return kl + 8 <= 64 ? (8 + kl) * (8 + kl + ku) + 8 * 8 : -1;
+    return (kl + 1) * (kl + ku + 1);
+}
 // LDS of the fused local Newton kernel, in doubles:
 //   patch values (n + ng) | residual / step (n) | LU window | multipliers | scratch
 inline int local_lds_doubles(int n, int ng, int kl, int ku) {

@@ -37,6 +37,10 @@ COARSE_NONE = 0
 COARSE_GDSW = 1
 MAX_OUTER = 64
 FLAG_PROFILE = 1
+FLAG_GRAPH = 2
+FLAG_COARSE_CHORD = 4
+FLAG_COARSE_LU_APPLY = 8
+FLAG_AUTOTUNE = 16
 
 # every symbol include/nls.h declares
 SYMBOLS = (
@@ -50,6 +54,7 @@ SYMBOLS = (
     "nls_guess_get_model", "nls_guess_enable", "nls_guess_capture",
     "nls_guess_captured", "nls_guess_features", "nls_guess_lift",
     "nls_guess_predict", "nls_guess_loss_grad", "nls_guess_train",
+    "nls_get_tuning",
 )
 
 GUESS_PARAMS = 279552
@@ -70,6 +75,7 @@ class Options(ctypes.Structure):
         ("stagnation", ctypes.c_double), ("inner_maxit", ctypes.c_int),
         ("gmres_rtol", ctypes.c_double), ("gmres_maxit", ctypes.c_int),
         ("gmres_restart", ctypes.c_int), ("flags", ctypes.c_int),
+        ("lu_variant", ctypes.c_int),
     ]
 
 
@@ -145,6 +151,7 @@ def load() -> ctypes.CDLL:
         "nls_inspect_coarse": ([i64, i64, P, i32, P, i64, P, P, P, P], ctypes.c_int),
         "nls_last_error": ([P], ctypes.c_char_p),
         "nls_set_load": ([P, P], ctypes.c_int),
+        "nls_get_tuning": ([P, P, P, P, P, P, P], ctypes.c_int),
         "nls_guess_set_model": ([P, P, i64, P], ctypes.c_int),
         "nls_guess_get_model": ([P, P, P], ctypes.c_int),
         "nls_guess_enable": ([P, ctypes.c_int], ctypes.c_int),
@@ -480,3 +487,19 @@ class Solver:
                                              ctypes.byref(st)))
         return {"steps": st.steps, "final_loss": st.final_loss, "ms": st.ms,
                 "epoch_loss": list(st.epoch_loss[:min(int(epochs), MAX_EPOCHS)])}
+
+    def tuning(self):
+        """Bucket LU variants, LDS bytes and sizes; coarse apply strategy."""
+        ns, _, _ = self.sizes()
+        nb = ctypes.c_int32(0)
+        var = np.zeros(ns, np.int32)
+        lds = np.zeros(ns, np.int32)
+        cnt = np.zeros(ns, np.int32)
+        ci = ctypes.c_int32(0)
+        cms = np.zeros(3, np.float64)
+        self._check(self.lib.nls_get_tuning(self.h, ctypes.byref(nb), _ptr(var), _ptr(lds),
+                                            _ptr(cnt), ctypes.byref(ci), _ptr(cms)))
+        k = nb.value
+        return {"lu_variant": var[:k].tolist(), "lds_bytes": lds[:k].tolist(),
+                "n_sub": cnt[:k].tolist(), "coarse_inverse": bool(ci.value),
+                "coarse_ms": cms.tolist()}

@@ -224,3 +224,90 @@ def test_batch_of_instances():
     uu = _np(uu)
     assert rc == 0 and st["outer_its"] == st_ref["outer"]
     assert np.linalg.norm(uu - u_ref) <= 1e-10 * np.linalg.norm(u_ref)
+
+
+@pytest.mark.parametrize("coupling", ["one_level", "additive"])
+def test_graph_gmres_matches_step_by_step(coupling):
+    """GMRES with device-side rotations and graph-replayed Arnoldi blocks:
+    same outer and GMRES counts and the same solution as the step-by-step
+    driver; the captured graphs are replayed across outer iterations and
+    solves, with eager work in between, and give identical results."""
+    from paper_2410_24138_amd import nls
+    case = synth.small_case(n=32, boxes=4, overlap=2, forcing_seed=7, coef_seed=2,
+                            two_level=(coupling == "additive"))
+    ue, ste, _ = _solver(case, coupling=coupling).solve()
+    sg = _solver(case, coupling=coupling, flags=nls.FLAG_GRAPH)
+    ug1, stg1, rc = sg.solve()
+    assert rc == 0 and stg1["outer_its"] == ste["outer_its"]
+    for a, b in zip(stg1["gmres_its"], ste["gmres_its"]):
+        assert abs(a - b) <= 1
+    ue, ug1 = _np(ue), _np(ug1)
+    assert np.linalg.norm(ug1 - ue) <= 1e-10 * np.linalg.norm(ue)
+    F = _np(sg.residual(ug1))
+    assert np.all(np.isfinite(F))
+    for _ in range(2):
+        ug2, stg2, _ = sg.solve()
+        np.testing.assert_array_equal(_np(ug2), ug1)
+        assert stg2["gmres_its"] == stg1["gmres_its"]
+
+
+@pytest.mark.parametrize("flags", ["chord", "lu_apply", "chord+lu_apply+graph"])
+def test_coarse_variants_match_oracle(flags):
+    """Chord steps for T_0 and/or band LU solves in place of the explicit
+    coarse inverse: F_x, the tangent and the solve match the oracle."""
+    from paper_2410_24138_amd import nls
+    f = 0
+    f |= nls.FLAG_COARSE_CHORD if "chord" in flags else 0
+    f |= nls.FLAG_COARSE_LU_APPLY if "lu_apply" in flags else 0
+    f |= nls.FLAG_GRAPH if "graph" in flags else 0
+    case = synth.small_case(n=24, boxes=4, overlap=2, forcing_seed=2, two_level=True)
+    P = P1Problem(case)
+    S = Schwarz(P, "additive")
+    u = _probe_point(P, case)
+    s = _solver(case, coupling="additive", flags=f)
+    _close(_np(s.precond_residual(u)), S.evaluate(u), 1e-10)
+    v = np.random.default_rng(5).normal(size=P.N)
+    _close(_np(s.tangent(v)), S.tangent(v), 1e-10)
+    u_ref, st_ref = S.solve()
+    uu, st, rc = _solver(case, coupling="additive", flags=f).solve()
+    assert rc == 0 and st["outer_its"] == st_ref["outer"]
+    assert np.linalg.norm(_np(uu) - u_ref) <= 1e-10 * np.linalg.norm(u_ref)
+
+
+@pytest.mark.parametrize("variant", [1, 2, 3])
+def test_lu_variants_match_oracle(variant):
+    """Each band LU form (blocked NB=16, NB=8, unblocked) in the fused local
+    solve: same F_x, tangent and inner iteration counts as the oracle."""
+    kw = dict(n=21, boxes=3, overlap=2, uneven=True, coef_seed=4, forcing_seed=8)
+    for coupling in ("one_level", "additive"):
+        case = synth.small_case(two_level=(coupling == "additive"), **kw)
+        P = P1Problem(case)
+        S = Schwarz(P, coupling)
+        s = _solver(case, coupling=coupling, lu_variant=variant)
+        u = _probe_point(P, case)
+        _close(_np(s.precond_residual(u)), S.evaluate(u), 1e-11)
+        np.testing.assert_array_equal(s.inner_iterations(),
+                                      [sol["its"] for sol in S.state["sols"]])
+        v = np.random.default_rng(2).normal(size=P.N)
+        _close(_np(s.tangent(v)), S.tangent(v), 1e-11)
+
+
+def test_autotuned_solve_matches_oracle():
+    from paper_2410_24138_amd import nls
+    case = _batch_case()
+    S = Schwarz(P1Problem(case), "additive")
+    u_ref, st_ref = S.solve()
+    f = nls.FLAG_AUTOTUNE | nls.FLAG_GRAPH | nls.FLAG_COARSE_CHORD
+    s = _solver(case, coupling="additive", flags=f)
+    before = s.tuning()
+    uu, st, rc = s.solve()
+    after = s.tuning()
+    assert rc == 0 and st["outer_its"] == st_ref["outer"]
+    assert np.linalg.norm(_np(uu) - u_ref) <= 1e-10 * np.linalg.norm(u_ref)
+    assert before["lu_variant"] == [0] * len(before["lu_variant"])
+    assert all(v in (1, 2, 3) for v in after["lu_variant"])
+    assert all(0 < b <= 160 * 1024 for b in after["lds_bytes"])
+    assert sum(after["n_sub"]) == int(case["n_sub"])
+    assert min(after["coarse_ms"]) > 0.0
+    uu2, st2, _ = s.solve()
+    np.testing.assert_array_equal(_np(uu2), _np(uu))
