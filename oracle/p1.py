@@ -83,6 +83,8 @@ def p1_element(ue, G, kappa, beta, load):
 class P1Problem:
     """The discrete nonlinear problem F(u) = 0 (eq. 3) of one input case."""
 
+    d = 1  # dofs per node
+
     def __init__(self, case: dict):
         self.case = case
         self.xy = np.asarray(case["xy"], dtype=np.float64)
@@ -105,6 +107,18 @@ class P1Problem:
         np.add.at(b, self.conn, self.load)
         b[self.is_dir] = 0.0
         self.b = b
+        self.ndof = self.N
+        # the load is part of the element residuals; no nodal forces
+        self.ext_load = np.zeros(self.N)
+
+    def element_local(self, elems, ve):
+        """Element residuals (load included) and Jacobians for local values."""
+        return p1_element(ve, self.G[elems], self.kappa[elems], self.beta,
+                          self.load[elems])
+
+    def nullspace(self, nodes):
+        """Interface values of the GDSW function of one component: 1."""
+        return [np.ones(len(nodes))]
 
     def element(self, u, elems=None):
         """Element residuals and Jacobians at the global vector u."""

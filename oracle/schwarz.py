@@ -51,7 +51,8 @@ def _stop_tol(rho0, b_inf, n, rtol, eta):
 
 
 class Schwarz:
-    """RASPEN with optional GDSW coarse level for one P1Problem.
+    """RASPEN with optional GDSW coarse level for one problem (P1Problem or
+    NHProblem: d dofs per node, element_local, residual, jacobian).
 
     coupling: "one_level" (F_1, eq. 5) or "additive" (F_a, eq. 10).
     """
@@ -68,7 +69,7 @@ class Schwarz:
         self.inner_eta = inner_eta
         self.inner_maxit = inner_maxit
         self.stagnation = stagnation
-        self.b_inf = float(np.max(np.abs(problem.b))) if problem.N else 0.0
+        self.b_inf = float(np.max(np.abs(problem.b))) if problem.ndof else 0.0
         self._build_maps()
         self.Phi = None
         if coupling == "additive":
@@ -82,22 +83,34 @@ class Schwarz:
         The paper builds an element-based overlap from the dual graph; here
         the non-overlapping element set of each subdomain is grown by
         `overlap` layers of elements sharing a node with the current set.
+        Maps are built on nodes and expanded to the problem's d dofs per
+        node (node-major, interleaved); a node's dofs share its subdomains,
+        its V/Gamma status and its owner.
         """
         P = self.P
         conn = P.conn
+        nv = conn.shape[1]
+        dd = P.d
         part = np.asarray(self.case["elem_part"], dtype=np.int64)
         n_sub = int(self.case["n_sub"])
         delta = int(self.case["overlap"])
         N, E = P.N, P.E
         self.part = part
         self.n_sub = n_sub
-        inc = sp.csr_matrix((np.ones(3 * E), (conn.ravel(),
-                             np.repeat(np.arange(E), 3))), shape=(N, E))
+        self.d = dd
+        inc = sp.csr_matrix((np.ones(nv * E), (conn.ravel(),
+                             np.repeat(np.arange(E), nv))), shape=(N, E))
         self.inc = inc
         deg = np.asarray(inc.sum(axis=1)).ravel()
         owner = np.full(N, -1, dtype=np.int64)
-        np.maximum.at(owner, conn.ravel(), np.repeat(part, 3))
+        np.maximum.at(owner, conn.ravel(), np.repeat(part, nv))
         self.owner = owner
+        # a node is a Dirichlet node when any of its dofs is
+        self.node_dir = P.is_dir.reshape(N, dd).any(axis=1)
+
+        def dofs(nodes):
+            return (dd * np.asarray(nodes)[:, None] + np.arange(dd)).ravel()
+
         subs = []
         for i in range(n_sub):
             pe = (part == i).astype(np.float64)
@@ -114,9 +127,12 @@ class Schwarz:
             loc = np.full(N, -1, dtype=np.int64)
             loc[V] = np.arange(len(V))
             loc[Gam] = len(V) + np.arange(len(Gam))
-            subs.append({"V": V, "Gam": Gam, "elems": elems,
-                         "lconn": loc[conn[elems]], "dirV": P.is_dir[V],
-                         "loc": loc})
+            lconn = loc[conn[elems]]
+            ldof = (dd * lconn[:, :, None] + np.arange(dd)).reshape(len(elems), nv * dd)
+            Vd = dofs(V)
+            subs.append({"V": V, "Gam": Gam, "elems": elems, "lconn": lconn,
+                         "Vd": Vd, "Gd": dofs(Gam), "ldof": ldof,
+                         "dirV": P.is_dir[Vd], "loc": loc})
         self.subs = subs
         # restricted prolongation P~_i: owned nodes and their positions in V_i
         own_loc = np.empty(N, dtype=np.int64)
@@ -127,8 +143,8 @@ class Schwarz:
                 raise ValueError(f"subdomain {i}: owned nodes not in V_i "
                                  "(overlap must be >= 1)")
             own_loc[owned] = li
-            s["owned"] = owned
-            s["owned_loc"] = li
+            s["owned"] = dofs(owned)
+            s["owned_loc"] = dofs(li)
         self.own_loc = own_loc
 
     # ----------------------------------------------------------- local level
@@ -141,13 +157,12 @@ class Schwarz:
         s = self.subs[i]
         P = self.P
         v = np.concatenate([x, trace])
-        r_e, _ = p1_element(v[s["lconn"]], P.G[s["elems"]],
-                            P.kappa[s["elems"]], P.beta, P.load[s["elems"]])
+        r_e, _ = P.element_local(s["elems"], v[s["ldof"]])
         R = np.zeros(len(v))
-        np.add.at(R, s["lconn"], r_e)
-        r = R[:len(x)]
+        np.add.at(R, s["ldof"], r_e)
+        r = R[:len(x)] - P.ext_load[s["Vd"]]
         d = s["dirV"]
-        r[d] = x[d] - P.dir_value[s["V"][d]]
+        r[d] = x[d] - P.dir_value[s["Vd"][d]]
         return r
 
     def local_jacobian(self, i, x, trace):
@@ -156,9 +171,8 @@ class Schwarz:
         P = self.P
         nV = len(x)
         v = np.concatenate([x, trace])
-        _, K = p1_element(v[s["lconn"]], P.G[s["elems"]],
-                          P.kappa[s["elems"]], P.beta, P.load[s["elems"]])
-        lc = s["lconn"]
+        _, K = P.element_local(s["elems"], v[s["ldof"]])
+        lc = s["ldof"]
         rows = np.broadcast_to(lc[:, :, None], K.shape).ravel()
         cols = np.broadcast_to(lc[:, None, :], K.shape).ravel()
         keep = rows < nV
@@ -183,8 +197,8 @@ class Schwarz:
         "plain", "guess" or "fallback".
         """
         s = self.subs[i]
-        xu = u[s["V"]].copy()
-        tr = u[s["Gam"]].copy()
+        xu = u[s["Vd"]].copy()
+        tr = u[s["Gd"]].copy()
         r = self.local_residual(i, xu, tr)
         rho_plain = float(np.linalg.norm(r))
         tol = _stop_tol(rho_plain, self.b_inf, len(xu), self.inner_rtol,
@@ -247,38 +261,44 @@ class Schwarz:
                 guesses = [None] * self.n_sub
             sols = [self.local_solve(i, u, guess=guesses[i])
                     for i in range(self.n_sub)]
-        Fx = np.empty(self.P.N)
+        Fx = np.empty(self.P.ndof)
         for s, sol in zip(self.subs, sols):
             Fx[s["owned"]] = sol["T"][s["owned_loc"]]
         return Fx, sols
 
     # ---------------------------------------------------------- coarse level
     def _build_gdsw(self, u_lin=None):
-        """GDSW coarse basis Phi (N x n0) (Section 1 and 2).
+        """GDSW coarse basis Phi (ndof x n0) (Section 1 and 2).
 
         Interface nodes (not Dirichlet, adjacent to elements of >= 2
         subdomains) are grouped by the set of subdomains they touch and each
         group is split into connected components (vertices: >= 3 subdomains,
-        edges: 2).  A scalar problem has one basis function per component,
-        equal to 1 on it and 0 on the rest of the interface; it is extended
-        into each subdomain interior by the discrete harmonic extension
-        Phi_I = -A_II^{-1} A_IG Phi_G with A = DF(u_lin), u_lin = 0.
+        edges: 2).  Each component contributes the problem's null-space
+        vectors restricted to it (scalar problem: 1; elasticity: the two
+        translations, plus the rotation about the component's centroid when
+        it has two or more nodes), zero on the rest of the interface, and
+        every function is extended into each subdomain interior by the
+        discrete harmonic extension Phi_I = -A_II^{-1} A_IG Phi_G with
+        A = DF(u_lin), u_lin = 0.
         """
         P = self.P
         N = P.N
+        dd = P.d
+        nd = P.ndof
         conn = P.conn
+        nv = conn.shape[1]
         part = self.part
-        NS = sp.csr_matrix((np.ones(3 * P.E), (conn.ravel(), np.repeat(part, 3))),
+        NS = sp.csr_matrix((np.ones(nv * P.E), (conn.ravel(), np.repeat(part, nv))),
                            shape=(N, self.n_sub))
         NS.sort_indices()
         nsub = np.diff(NS.indptr)
-        iface = (nsub >= 2) & ~P.is_dir
+        iface = (nsub >= 2) & ~self.node_dir
         keys = {}
         for g in np.nonzero(iface)[0]:
             k = tuple(NS.indices[NS.indptr[g]:NS.indptr[g + 1]].tolist())
             keys.setdefault(k, []).append(g)
-        # mesh edges for connectivity of a class
-        e = np.concatenate([conn[:, [0, 1]], conn[:, [1, 2]], conn[:, [2, 0]]])
+        # mesh edges (consecutive element nodes) for connectivity of a class
+        e = np.concatenate([conn[:, [a, (a + 1) % nv]] for a in range(nv)])
         adj = sp.csr_matrix((np.ones(len(e)), (e[:, 0], e[:, 1])), shape=(N, N))
         adj = ((adj + adj.T) > 0).tocsr()
         comps = []
@@ -289,23 +309,34 @@ class Schwarz:
             for c in range(nc):
                 comps.append((nodes[lab == c], len(k)))
         comps.sort(key=lambda t: int(t[0].min()))
-        n0 = len(comps)
-        rows = np.concatenate([c[0] for c in comps]) if n0 else np.zeros(0, int)
-        cols = np.concatenate([np.full(len(c[0]), k) for k, c in enumerate(comps)]) \
-            if n0 else np.zeros(0, int)
-        PhiG = sp.csr_matrix((np.ones(len(rows)), (rows, cols)), shape=(N, n0))
+        rows, cols, vals = [], [], []
+        n0 = 0
+        for nodes, _ in comps:
+            cd = (dd * nodes[:, None] + np.arange(dd)).ravel()
+            for vec in P.nullspace(nodes):
+                nz = vec != 0.0
+                rows.append(cd[nz])
+                cols.append(np.full(int(nz.sum()), n0))
+                vals.append(vec[nz])
+                n0 += 1
+        rows = np.concatenate(rows) if rows else np.zeros(0, int)
+        cols = np.concatenate(cols) if cols else np.zeros(0, int)
+        vals = np.concatenate(vals) if vals else np.zeros(0)
+        PhiG = sp.csr_matrix((vals, (rows, cols)), shape=(nd, n0))
         self.components = comps
-        u0 = np.zeros(N) if u_lin is None else u_lin
+        u0 = np.zeros(nd) if u_lin is None else u_lin
         A = P.jacobian(u0)
-        prow, pcol, pval = [rows], [cols], [np.ones(len(rows))]
-        interior = (nsub == 1) & ~P.is_dir
+        prow, pcol, pval = [rows], [cols], [vals]
+        interior_node = (nsub == 1) & ~self.node_dir
+        interior = np.repeat(interior_node, dd)
         self.interior_blocks = []
         for i in range(self.n_sub):
             el = np.nonzero(part == i)[0]
             clos = np.zeros(N, dtype=bool)
             clos[conn[el].ravel()] = True
-            I = np.nonzero(clos & interior)[0]
-            bnd = np.nonzero(clos & ~(clos & interior))[0]
+            closd = np.repeat(clos, dd)
+            I = np.nonzero(closd & interior)[0]
+            bnd = np.nonzero(closd & ~interior)[0]
             if len(I) == 0:
                 continue
             AII = A[I][:, I].toarray()
@@ -317,11 +348,19 @@ class Schwarz:
             pval.append(PhiI[:, nzc].ravel())
             self.interior_blocks.append((i, I, bnd))
         self.Phi = sp.csr_matrix((np.concatenate(pval), (np.concatenate(prow),
-                                  np.concatenate(pcol))), shape=(N, n0))
+                                  np.concatenate(pcol))), shape=(nd, n0))
         self.Phi.eliminate_zeros()
         self.PhiT = self.Phi.T.tocsr()
         self.n0 = n0
         self.phib_inf = float(np.max(np.abs(self.PhiT @ P.b))) if n0 else 0.0
+
+    def refresh_load(self):
+        """Recompute the load scales of the stopping rules after the
+        problem's load changed (load stepping)."""
+        P = self.P
+        self.b_inf = float(np.max(np.abs(P.b))) if P.ndof else 0.0
+        if self.Phi is not None:
+            self.phib_inf = float(np.max(np.abs(self.PhiT @ P.b))) if self.n0 else 0.0
 
     def coarse_solve(self, u):
         """T_0(u) by Newton on G(c) = Phi^T F(u - Phi c) = 0 (eq. 9, R_0 =
@@ -381,7 +420,7 @@ class Schwarz:
         st = self.state
         y = v.copy()
         for s, sol in zip(self.subs, st["sols"]):
-            z = sla.lu_solve(sol["lu"], sol["B"] @ v[s["Gam"]])
+            z = sla.lu_solve(sol["lu"], sol["B"] @ v[s["Gd"]])
             y[s["owned"]] += z[s["owned_loc"]]
         co = st["coarse"]
         if co is not None:
@@ -397,8 +436,8 @@ class Schwarz:
         y = np.zeros_like(v)
         for s, sol in zip(self.subs, st["sols"]):
             ui = st["u"].copy()
-            ui[s["V"]] = sol["x"]
-            w = (P.jacobian(ui) @ v)[s["V"]]
+            ui[s["Vd"]] = sol["x"]
+            w = (P.jacobian(ui) @ v)[s["Vd"]]
             z = sla.lu_solve(sol["lu"], w)
             y[s["owned"]] += z[s["owned_loc"]]
         co = st["coarse"]
@@ -416,7 +455,7 @@ class Schwarz:
         def ev(u):
             g = predictor.guesses(u) if predictor is not None else None
             return self.evaluate(u, guesses=g)
-        u = np.zeros(self.P.N) if u0 is None else np.array(u0, dtype=np.float64)
+        u = np.zeros(self.P.ndof) if u0 is None else np.array(u0, dtype=np.float64)
         Fx = ev(u)
         r0 = float(np.linalg.norm(Fx))
         stats = {"outer": 0, "gmres": [], "inner": [], "coarse": [],
@@ -441,6 +480,22 @@ class Schwarz:
         else:
             stats["converged"] = float(np.linalg.norm(Fx)) <= rtol * r0
         return u, stats
+
+    def solve_load_steps(self, n_steps, u0=None, **kw):
+        """Load stepping (continuation): the external load is raised to
+        s / n_steps of its full value in steps s = 1..n_steps, each outer
+        solve starting from the previous step's solution.  Returns the last
+        solution and the per-step statistics."""
+        u = np.zeros(self.P.ndof) if u0 is None else np.array(u0, dtype=np.float64)
+        steps = []
+        for st in range(1, n_steps + 1):
+            self.P.set_load_scale(st / n_steps)
+            self.refresh_load()
+            u, stats = self.solve(u0=u, **kw)
+            steps.append(stats)
+            if not stats["converged"]:
+                break
+        return u, steps
 
 
 def gmres_mgs(apply, b, rtol=1e-6, restart=50, maxit=1000):
@@ -500,11 +555,11 @@ def gmres_mgs(apply, b, rtol=1e-6, restart=50, maxit=1000):
     return x, its
 
 
-def global_newton(problem: P1Problem, u0=None, maxit=50, dense=False):
+def global_newton(problem, u0=None, maxit=50, dense=False):
     """Plain definition of the discrete solution u*: Newton's method on
     F(u) = 0 (eq. 3) with a direct solve of DF(u) du = F(u), run until the
     step is at the rounding level (|du|_inf <= 1e-13 |u|_inf) or F = 0."""
-    u = np.zeros(problem.N) if u0 is None else np.array(u0, dtype=np.float64)
+    u = np.zeros(problem.ndof) if u0 is None else np.array(u0, dtype=np.float64)
     its = 0
     for its in range(1, maxit + 1):
         F = problem.residual(u)

@@ -27,7 +27,8 @@ __all__ = [
     "edge_midpoints", "fourier_modes", "fourier_eval", "rff_field",
     "rff_eval", "diffusion_case", "config1", "config2", "config4_instance",
     "config4", "concat_cases", "small_case", "mlp_init", "mlp_batch",
-    "epoch_orders",
+    "epoch_orders", "q1_grid", "seeded_cuts", "elasticity_case", "config3",
+    "small_elasticity_case",
 ]
 
 
@@ -312,3 +313,99 @@ def epoch_orders(seed: int, n: int, epochs: int) -> np.ndarray:
     range(n), concatenated, int32."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return np.concatenate([rng.permutation(n) for _ in range(epochs)]).astype(np.int32)
+
+
+# ------------------------------------------------------------ elasticity
+def q1_grid(nx: int, ny: int, lx: float = 1.0, ly: float = 1.0):
+    """Structured Q1 mesh of [0,lx]x[0,ly] with nx*ny square cells.
+
+    Node (i,j) has index g = j*(nx+1) + i; element j*nx+i has the nodes
+    (i,j), (i+1,j), (i+1,j+1), (i,j+1) (counter-clockwise)."""
+    i = np.arange(nx + 1, dtype=np.float64)
+    j = np.arange(ny + 1, dtype=np.float64)
+    X, Y = np.meshgrid(i * (lx / nx), j * (ly / ny))
+    xy = np.stack([X.ravel(), Y.ravel()], axis=1)
+    ci, cj = np.meshgrid(np.arange(nx), np.arange(ny))
+    n00 = (cj * (nx + 1) + ci).ravel()
+    conn = np.stack([n00, n00 + 1, n00 + nx + 2, n00 + nx + 1], axis=1).astype(np.int32)
+    return xy, conn
+
+
+def _largest_remainder(w, total):
+    q = w / w.sum() * total
+    base = np.floor(q).astype(np.int64)
+    rest = total - base.sum()
+    order = np.argsort(-(q - base), kind="stable")
+    base[order[:rest]] += 1
+    return base
+
+
+def seeded_cuts(seed: int, nx: int, ny: int, nbx: int = 8, nby: int = 8,
+                ratio=(2.0, 3.0)):
+    """Box cuts at seeded positions: widths w ~ U(1, sqrt 3) per direction
+    (x first, then y), scaled to whole cells by largest remainder; drawn
+    again until the largest/smallest box area lies in [ratio[0], ratio[1]]
+    (PCG64).  Returns (cuts_x, cuts_y)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    while True:
+        wx = _largest_remainder(rng.uniform(1.0, np.sqrt(3.0), nbx), nx)
+        wy = _largest_remainder(rng.uniform(1.0, np.sqrt(3.0), nby), ny)
+        if wx.min() < 1 or wy.min() < 1:
+            continue
+        area = np.outer(wy, wx)
+        r = area.max() / area.min()
+        if ratio[0] <= r <= ratio[1]:
+            return (np.concatenate([[0], np.cumsum(wx)]),
+                    np.concatenate([[0], np.cumsum(wy)]))
+
+
+def elasticity_case(nx, ny, lx, ly, cuts_x, cuts_y, overlap, *, E=210.0, nu=0.3,
+                    traction=(0.0, -4.0), two_level=True, name="elasticity"):
+    """Compressible Neo-Hooke cantilever on [0,lx]x[0,ly] with Q1 cells:
+    x = 0 clamped (both dofs), traction t on the edge x = lx, lumped to
+    nodal forces t * (edge length)/2 per node of every edge segment.
+    Lame parameters from E, nu: mu = E/(2(1+nu)), lambda = E nu/((1+nu)(1-2nu)).
+    Dofs are node-major, interleaved (u_x, u_y)."""
+    xy, conn = q1_grid(nx, ny, lx, ly)
+    cuts_x = np.asarray(cuts_x)
+    cuts_y = np.asarray(cuts_y)
+    bx = np.searchsorted(cuts_x, np.arange(nx), side="right") - 1
+    by = np.searchsorted(cuts_y, np.arange(ny), side="right") - 1
+    part = (by[:, None] * (len(cuts_x) - 1) + bx[None, :]).ravel().astype(np.int32)
+    left = np.nonzero(np.isclose(xy[:, 0], 0.0))[0]
+    dofs = np.sort(np.concatenate([2 * left, 2 * left + 1])).astype(np.int64)
+    right = np.nonzero(np.isclose(xy[:, 0], lx))[0]
+    right = right[np.argsort(xy[right, 1])]
+    f = np.zeros(2 * len(xy))
+    hy = ly / ny
+    for a, b in zip(right[:-1], right[1:]):
+        for g in (a, b):
+            f[2 * g] += traction[0] * hy / 2
+            f[2 * g + 1] += traction[1] * hy / 2
+    mu = E / (2.0 * (1.0 + nu))
+    lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu))
+    return {
+        "name": name, "kind": "neohooke",
+        "nx": nx, "ny": ny, "xy": xy, "conn": conn, "elem_part": part,
+        "n_sub": (len(cuts_x) - 1) * (len(cuts_y) - 1), "overlap": int(overlap),
+        "dirichlet": dofs, "dirichlet_vals": np.zeros(len(dofs)),
+        "nodal_force": f, "mu": mu, "lam": lam, "E": E, "nu": nu,
+        "two_level": bool(two_level),
+    }
+
+
+def config3(traction_max: float = 4.0):
+    """256x128 Q1 cells on [0,2]x[0,1], 8x8 subdomains at seeded cuts (area
+    ratio 2..3, seed 3), overlap 2, GDSW, E = 210, nu = 0.3, right-edge
+    traction (0, -traction_max) at the last of the load steps."""
+    cx, cy = seeded_cuts(3, 256, 128)
+    return elasticity_case(256, 128, 2.0, 1.0, cx, cy, 2, traction=(0.0, -traction_max),
+                           name="neohooke_256x128_8x8_ov2_gdsw")
+
+
+def small_elasticity_case(nx=8, ny=4, boxes=(2, 2), overlap=1, traction=(0.0, -1.0),
+                          two_level=True, lx=2.0, ly=1.0):
+    """Small cantilevers for oracle pins and parity tests."""
+    return elasticity_case(nx, ny, lx, ly, even_cuts(nx, boxes[0]), even_cuts(ny, boxes[1]),
+                           overlap, traction=traction, two_level=two_level,
+                           name=f"small_nh_{nx}x{ny}_{boxes[0]}x{boxes[1]}_{overlap}")
