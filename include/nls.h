@@ -15,8 +15,9 @@
  *  - Device pointers (argument names ending in _dev) must point to memory of
  *    the handle's device; the library reads and writes them in stream order
  *    on the handle's stream and synchronises that stream before returning.
- *  - Global node indices are 0-based; vectors hold one value per mesh node
- *    (scalar problems), in node order.
+ *  - Global node indices are 0-based; vectors hold d values per mesh node
+ *    (d = 1 for diffusion, 2 for elasticity), node-major and interleaved:
+ *    dof d*g + c is component c of node g.  Dirichlet lists name dofs.
  *  - A handle is used by one host thread at a time.
  *  - All floating point at the ABI is IEEE binary64.
  */
@@ -44,8 +45,13 @@ extern "C" {
 
 /* ---- enumerations ---------------------------------------------------- */
 #define NLS_ELEM_P1_TRI   3   /* 3-node triangles, counter-clockwise */
+#define NLS_ELEM_Q1_QUAD  4   /* 4-node bilinear quadrilaterals, counter-clockwise */
 
-#define NLS_PROBLEM_DIFFUSION 1  /* -div(kappa (1 + beta u^2) grad u) = f, eq. (1) */
+#define NLS_PROBLEM_DIFFUSION 1  /* -div(kappa (1 + beta u^2) grad u) = f, eq. (1);
+                                    P1 triangles, d = 1 */
+#define NLS_PROBLEM_NEOHOOKE  2  /* -div P(F) = 0, eq. (2), compressible Neo-Hooke
+                                    P = mu (F - F^-T) + lambda ln(det F) F^-T;
+                                    Q1 quadrilaterals, 2 x 2 Gauss points, d = 2 */
 
 #define NLS_PREC_FP64     0   /* every step in binary64 */
 #define NLS_PREC_FP32_IR  1   /* local LU in binary32, binary64 residuals and
@@ -164,12 +170,18 @@ int nls_destroy(nls_handle* h);
 int nls_set_mesh(nls_handle* h, int elem_kind, int64_t n_nodes,
                  const double* xy, int64_t n_elems, const int32_t* conn);
 
-/* The nonlinear problem on that mesh (eq. (1) generalised):
+/* The nonlinear problem on that mesh.
+   NLS_PROBLEM_DIFFUSION (eq. (1) generalised), P1 mesh:
      -div( kappa_e (1 + beta u^2) grad u ) = f.
    params[0] = beta.  elem_coef: kappa per element, or NULL for 1.
    elem_load: f sampled at the midpoints of each element's edges
    (v0,v1), (v1,v2), (v2,v0) (n_elems x 3), or NULL for f = 1; the load is
-   integrated with the edge-midpoint rule.  Copied. */
+   integrated with the edge-midpoint rule.
+   NLS_PROBLEM_NEOHOOKE (eq. (2)), Q1 mesh: params[0] = mu, params[1] =
+   lambda (Lame parameters, mu > 0); elem_coef and elem_load must be NULL;
+   external forces are nodal, see nls_set_nodal_load (zero until set); a
+   quadrature point with det F <= 0 makes the residual non-finite
+   (NLS_ENAN).  Copied.  Dirichlet data must be set after the problem. */
 int nls_set_problem(nls_handle* h, int kind, const double* params,
                     const double* elem_coef, const double* elem_load);
 
@@ -193,6 +205,13 @@ int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* elem_part,
    extended harmonically with DF(0) into every subdomain interior.
    Errors: NLS_ESTATE (no partition), NLS_ESINGULAR. */
 int nls_build_coarse(nls_handle* h, int kind);
+
+/* Nodal external forces f (n_nodes * d values, dof order) of a problem
+   whose load is nodal (NLS_PROBLEM_NEOHOOKE): F(u) = f_int(u) - f on free
+   dofs.  Entries on Dirichlet dofs are ignored.  Like nls_set_load it keeps
+   the partition and the coarse space (load stepping calls it once per
+   step).  Errors: NLS_ESTATE, NLS_EINVAL. */
+int nls_set_nodal_load(nls_handle* h, const double* f);
 
 /* Replace the load samples only (same layout and meaning as elem_load of
    nls_set_problem; NULL for f = 1), keeping mesh, coefficients, Dirichlet

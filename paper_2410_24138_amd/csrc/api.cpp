@@ -69,18 +69,32 @@ extern "C" int nls_destroy(nls_handle* h) {
 extern "C" int nls_set_mesh(nls_handle* h, int elem_kind, int64_t n_nodes, const double* xy,
                             int64_t n_elems, const int32_t* conn) {
     if (!h) return NLS_EINVAL;
-    if (elem_kind != NLS_ELEM_P1_TRI) return fail(h, NLS_EINVAL, "only P1 triangles are supported");
-    if (n_nodes <= 0 || n_elems <= 0 || !xy || !conn || n_nodes > (1 << 28) ||
-        n_elems > (1 << 28))
+    if (elem_kind != NLS_ELEM_P1_TRI && elem_kind != NLS_ELEM_Q1_QUAD)
+        return fail(h, NLS_EINVAL, "element kind must be P1 triangles or Q1 quadrilaterals");
+    if (n_nodes <= 0 || n_elems <= 0 || !xy || !conn || n_nodes > (1 << 27) ||
+        n_elems > (1 << 27))
         return fail(h, NLS_EINVAL, "bad mesh sizes or null arrays");
     HostMesh m;
     m.N = (int)n_nodes;
     m.E = (int)n_elems;
+    m.nv = elem_kind == NLS_ELEM_Q1_QUAD ? 4 : 3;
     m.xy.assign(xy, xy + 2 * n_nodes);
-    m.conn.assign(conn, conn + 3 * n_elems);
+    m.conn.assign(conn, conn + (size_t)m.nv * n_elems);
     std::string err;
     int rc = nls_build_node_incidence(m, err);
     if (rc) return fail(h, rc, err);
+    if (m.nv == 4) {
+        // counter-clockwise: every corner turns left
+        for (int e = 0; e < m.E; ++e)
+            for (int a = 0; a < 4; ++a) {
+                const int p = m.conn[4 * e + a], q = m.conn[4 * e + (a + 1) % 4],
+                          r = m.conn[4 * e + (a + 3) % 4];
+                const double ux = m.xy[2 * q] - m.xy[2 * p], uy = m.xy[2 * q + 1] - m.xy[2 * p + 1];
+                const double vx = m.xy[2 * r] - m.xy[2 * p], vy = m.xy[2 * r + 1] - m.xy[2 * p + 1];
+                if (!(ux * vy - uy * vx > 0.0))
+                    return fail(h, NLS_EINVAL, "a quadrilateral is clockwise, degenerate or not convex");
+            }
+    }
     m.dflag.assign(m.N, 0);
     m.dval.assign(m.N, 0.0);
     h->mesh = std::move(m);
@@ -96,7 +110,33 @@ extern "C" int nls_set_problem(nls_handle* h, int kind, const double* params,
                                const double* elem_coef, const double* elem_load) {
     if (!h) return NLS_EINVAL;
     if (!h->have_mesh) return fail(h, NLS_ESTATE, "nls_set_mesh first");
-    if (kind != NLS_PROBLEM_DIFFUSION) return fail(h, NLS_EINVAL, "unknown problem kind");
+    if (kind != NLS_PROBLEM_DIFFUSION && kind != NLS_PROBLEM_NEOHOOKE)
+        return fail(h, NLS_EINVAL, "unknown problem kind");
+    if (kind == NLS_PROBLEM_NEOHOOKE) {
+        if (h->mesh.nv != 4) return fail(h, NLS_EINVAL, "elasticity needs a Q1 mesh");
+        if (!params || !(params[0] > 0.0) || !std::isfinite(params[0]) || !std::isfinite(params[1]))
+            return fail(h, NLS_EINVAL, "need finite Lame parameters with mu > 0");
+        if (elem_coef || elem_load)
+            return fail(h, NLS_EINVAL, "elasticity takes nodal loads (nls_set_nodal_load)");
+        h->kind = kind;
+        h->mu = params[0];
+        h->lam = params[1];
+        h->kappa_h.clear();
+        h->fmid_h.clear();
+        h->mesh.d = 2;
+        h->fnode_h.assign((size_t)h->mesh.ndof(), 0.0);
+        h->mesh.dflag.assign(h->mesh.ndof(), 0);
+        h->mesh.dval.assign(h->mesh.ndof(), 0.0);
+        h->have_part = h->have_coarse = h->have_state = false;
+        return NLS_OK;
+    }
+    if (h->mesh.nv != 3) return fail(h, NLS_EINVAL, "diffusion needs a P1 mesh");
+    if (h->mesh.d != 1) {
+        h->mesh.d = 1;
+        h->mesh.dflag.assign(h->mesh.N, 0);
+        h->mesh.dval.assign(h->mesh.N, 0.0);
+    }
+    h->fnode_h.clear();
     h->kind = kind;
     h->beta = params ? params[0] : 1.0;
     if (!std::isfinite(h->beta)) return fail(h, NLS_EINVAL, "beta must be finite");
@@ -126,7 +166,7 @@ extern "C" int nls_set_dirichlet(nls_handle* h, int64_t n, const int64_t* nodes,
     std::fill(h->mesh.dflag.begin(), h->mesh.dflag.end(), 0);
     std::fill(h->mesh.dval.begin(), h->mesh.dval.end(), 0.0);
     for (int64_t k = 0; k < n; ++k) {
-        if (nodes[k] < 0 || nodes[k] >= h->mesh.N) return fail(h, NLS_EINVAL, "Dirichlet node out of range");
+        if (nodes[k] < 0 || nodes[k] >= h->mesh.ndof()) return fail(h, NLS_EINVAL, "Dirichlet dof out of range");
         h->mesh.dflag[nodes[k]] = 1;
         h->mesh.dval[nodes[k]] = values[k];
     }
@@ -140,16 +180,24 @@ static int upload_problem(nls_handle* h) {
     DevMesh d{};
     d.N = m.N;
     d.E = m.E;
+    d.kind = h->kind;
+    d.nv = m.nv;
+    d.d = m.d;
+    d.ndof = m.ndof();
     d.beta = h->beta;
+    d.mu = h->mu;
+    d.lam = h->lam;
+    const int nv = m.nv, nd = m.ndof();
     int *conn, *nptr, *nel;
-    double *xy, *G6, *kap, *eload, *bload, *dval, *coef = nullptr, *fmid = nullptr;
+    double *xy, *G6 = nullptr, *kap = nullptr, *eload = nullptr, *bload, *dval, *coef = nullptr,
+           *fmid = nullptr;
     unsigned char* dflag;
     std::vector<int> nelc(m.nel.size());
     for (int g = 0; g < m.N; ++g)
         for (int k = m.nptr[g]; k < m.nptr[g + 1]; ++k) {
             int e = m.nel[k], pos = 0;
-            for (int v = 0; v < 3; ++v)
-                if (m.conn[3 * e + v] == g) pos = v;
+            for (int v = 0; v < nv; ++v)
+                if (m.conn[nv * e + v] == g) pos = v;
             nelc[k] = (e << 2) | pos;
         }
     RC(h->upload(G_MESH, &conn, m.conn));
@@ -158,12 +206,7 @@ static int upload_problem(nls_handle* h) {
     RC(h->upload(G_MESH, &xy, m.xy));
     RC(h->upload(G_MESH, &dflag, m.dflag));
     RC(h->upload(G_MESH, &dval, m.dval));
-    if (!h->kappa_h.empty()) RC(h->upload(G_MESH, &coef, h->kappa_h));
-    if (!h->fmid_h.empty()) RC(h->upload(G_MESH, &fmid, h->fmid_h));
-    RC(h->alloc(G_MESH, &G6, 6 * (size_t)m.E));
-    RC(h->alloc(G_MESH, &kap, m.E));
-    RC(h->alloc(G_MESH, &eload, 3 * (size_t)m.E));
-    RC(h->alloc(G_MESH, &bload, m.N));
+    RC(h->alloc(G_MESH, &bload, nd));
     int* bad;
     double *part, *mx;
     int nb = 256;
@@ -171,18 +214,32 @@ static int upload_problem(nls_handle* h) {
     RC(h->alloc(G_MESH, &part, nb));
     RC(h->alloc(G_MESH, &mx, 1));
     d.conn = conn;
+    d.xy = xy;
     d.nptr = nptr;
     d.nel = nel;
-    d.G6 = G6;
-    d.kappa = kap;
-    d.eload = eload;
     d.bload = bload;
     d.dflag = dflag;
     d.dval = dval;
     HIPCHK(hipMemsetAsync(bad, 0, sizeof(int), h->stream));
-    HIPCHK(launch_p1_setup(d, xy, coef, fmid, G6, kap, eload, bad, h->stream));
-    HIPCHK(launch_assemble_load(d, bload, h->stream));
-    HIPCHK(launch_max_abs(bload, m.N, part, mx, nb, h->stream));
+    if (h->kind == NLS_PROBLEM_DIFFUSION) {
+        if (!h->kappa_h.empty()) RC(h->upload(G_MESH, &coef, h->kappa_h));
+        if (!h->fmid_h.empty()) RC(h->upload(G_MESH, &fmid, h->fmid_h));
+        RC(h->alloc(G_MESH, &G6, 6 * (size_t)m.E));
+        RC(h->alloc(G_MESH, &kap, m.E));
+        RC(h->alloc(G_MESH, &eload, 3 * (size_t)m.E));
+        d.G6 = G6;
+        d.kappa = kap;
+        d.eload = eload;
+        HIPCHK(launch_p1_setup(d, xy, coef, fmid, G6, kap, eload, bad, h->stream));
+        HIPCHK(launch_assemble_load(d, bload, h->stream));
+    } else {
+        // nodal forces, zero on Dirichlet dofs
+        std::vector<double> f(h->fnode_h);
+        for (int k = 0; k < nd; ++k)
+            if (m.dflag[k]) f[k] = 0.0;
+        HIPCHK(hipMemcpyAsync(bload, f.data(), nd * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    }
+    HIPCHK(launch_max_abs(bload, nd, part, mx, nb, h->stream));
     h->d_xy = xy;
     h->d_coef = coef;
     h->d_fmid = fmid;
@@ -366,7 +423,7 @@ extern "C" int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* el
     np.lu_variant = var0;
     h->np = np;
     // GMRES workspace
-    const int N = h->mesh.N;
+    const int N = h->mesh.ndof();
     h->m = h->opt.gmres_restart;
     h->nb_dot = std::min(512, std::max(1, (N + 1023) / 1024));
     RC(h->alloc(G_MAPS, &h->V, (size_t)(h->m + 1) * N));
@@ -400,7 +457,7 @@ extern "C" int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* el
 // c = 0 equals Phi^T F(0) = -Phi^T b.
 static int coarse_rhs_scale(nls_handle* h) {
     DevCoarse& d = h->dc;
-    HIPCHK(hipMemsetAsync(d.w, 0, sizeof(double) * h->mesh.N, h->stream));
+    HIPCHK(hipMemsetAsync(d.w, 0, sizeof(double) * h->mesh.ndof(), h->stream));
     HIPCHK(launch_coarse_q(h->dm, d, d.w, nullptr, 0, h->lds_coarse_q, h->stream));
     HIPCHK(launch_coarse_assemble(d, 0, h->stream));
     HIPCHK(launch_max_abs(d.rhs, h->co.n0, h->d_part, h->d_mx, 64, h->stream));
@@ -414,6 +471,7 @@ extern "C" int nls_build_coarse(nls_handle* h, int kind) {
     if (h) h->drop_graphs();
     if (!h) return NLS_EINVAL;
     if (!h->have_part) return fail(h, NLS_ESTATE, "nls_set_partition first");
+    if (h->mesh.d != 1) return fail(h, NLS_EINVAL, "GDSW coarse space for elasticity: not available");
     HIPCHK(hipSetDevice(h->opt.device));
     h->free_group(G_COARSE);
     h->have_coarse = false;
@@ -522,7 +580,7 @@ extern "C" int nls_build_coarse(nls_handle* h, int kind) {
     RC(h->alloc(G_COARSE, &d.a0piv, C.n0));
     RC(h->alloc(G_COARSE, &d.rhs, C.n0));
     RC(h->alloc(G_COARSE, &d.c, C.n0));
-    RC(h->alloc(G_COARSE, &d.w, h->mesh.N));
+    RC(h->alloc(G_COARSE, &d.w, h->mesh.ndof()));
     RC(h->alloc(G_COARSE, &d.scal, 4));
     RC(h->alloc(G_COARSE, &d.flag, 1));
     RC(h->alloc(G_COARSE, &h->ctmp, C.n0));
@@ -552,9 +610,34 @@ extern "C" int nls_build_coarse(nls_handle* h, int kind) {
 // ||Phi^T b||_inf are recomputed.
 int guess_refresh_load(nls_handle* h);
 
+extern "C" int nls_set_nodal_load(nls_handle* h, const double* f) {
+    if (!h || !f) return NLS_EINVAL;
+    if (h->kind != NLS_PROBLEM_NEOHOOKE) return fail(h, NLS_EINVAL, "the problem's load is not nodal");
+    const int nd = h->mesh.ndof();
+    for (int k = 0; k < nd; ++k)
+        if (!std::isfinite(f[k])) return fail(h, NLS_EINVAL, "nodal forces must be finite");
+    h->fnode_h.assign(f, f + nd);
+    if (!h->have_part) return NLS_OK;  // uploaded with the partition
+    HIPCHK(hipSetDevice(h->opt.device));
+    std::vector<double> fz(h->fnode_h);
+    for (int k = 0; k < nd; ++k)
+        if (h->mesh.dflag[k]) fz[k] = 0.0;
+    DevMesh& d = h->dm;
+    HIPCHK(hipMemcpyAsync(const_cast<double*>(d.bload), fz.data(), nd * sizeof(double),
+                          hipMemcpyHostToDevice, h->stream));
+    HIPCHK(launch_max_abs(d.bload, nd, h->d_part, h->d_mx, 256, h->stream));
+    HIPCHK(hipMemcpyAsync(&h->b_inf, h->d_mx, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    RC(sync(h));
+    h->np.abs_tol = h->opt.inner_eta * h->b_inf;
+    if (h->have_coarse) RC(coarse_rhs_scale(h));
+    h->have_state = false;
+    return NLS_OK;
+}
+
 extern "C" int nls_set_load(nls_handle* h, const double* elem_load) {
     if (!h) return NLS_EINVAL;
     if (!h->have_part) return fail(h, NLS_ESTATE, "nls_set_partition first");
+    if (h->kind != NLS_PROBLEM_DIFFUSION) return fail(h, NLS_EINVAL, "use nls_set_nodal_load");
     HIPCHK(hipSetDevice(h->opt.device));
     const int E = h->mesh.E;
     if (elem_load) {
@@ -573,7 +656,7 @@ extern "C" int nls_set_load(nls_handle* h, const double* elem_load) {
                            const_cast<double*>(d.G6), const_cast<double*>(d.kappa),
                            const_cast<double*>(d.eload), h->d_bad, h->stream));
     HIPCHK(launch_assemble_load(d, const_cast<double*>(d.bload), h->stream));
-    HIPCHK(launch_max_abs(d.bload, h->mesh.N, h->d_part, h->d_mx, 256, h->stream));
+    HIPCHK(launch_max_abs(d.bload, h->mesh.ndof(), h->d_part, h->d_mx, 256, h->stream));
     HIPCHK(hipMemcpyAsync(&h->b_inf, h->d_mx, sizeof(double), hipMemcpyDeviceToHost, h->stream));
     RC(sync(h));
     h->np.abs_tol = h->opt.inner_eta * h->b_inf;
@@ -883,7 +966,7 @@ static GmresDev gmres_dev(nls_handle* h) {
 // Arnoldi step j on stream s: w = A v_j, two classical Gram-Schmidt passes,
 // v_{j+1} = w / ||w||, then rotation j on the device.  No host contact.
 static int arnoldi_step(nls_handle* h, int j, hipStream_t s) {
-    const int N = h->mesh.N;
+    const int N = h->mesh.ndof();
     const int64_t ld = N;
     double* vj = h->V + (int64_t)j * ld;
     double* vn = h->V + (int64_t)(j + 1) * ld;
@@ -936,7 +1019,7 @@ static int block_graph(nls_handle* h, int b, hipGraphExec_t* out) {
 // host reads the convergence state once per block.  Steps of a block after
 // convergence run but are not used.
 static int gmres_graph(nls_handle* h, const double* b, double* x, int* its_out) {
-    const int N = h->mesh.N, m = h->m, K = h->gblock;
+    const int N = h->mesh.ndof(), m = h->m, K = h->gblock;
     double bn2 = 0.0;
     RC(dot_host(h, b, b, N, &bn2));
     const double bn = std::sqrt(bn2);
@@ -1023,7 +1106,7 @@ static int gmres_graph(nls_handle* h, const double* b, double* x, int* its_out) 
 // Restarted GMRES(m) for D F_x(u) x = b from x = 0 (classical Gram-Schmidt
 // with one reorthogonalisation).  Returns the iteration count in *its.
 static int gmres(nls_handle* h, const double* b, double* x, int* its_out) {
-    const int N = h->mesh.N, m = h->m;
+    const int N = h->mesh.ndof(), m = h->m;
     const int64_t ld = N;
     double bn2 = 0.0;
     RC(dot_host(h, b, b, N, &bn2));
@@ -1116,7 +1199,7 @@ extern "C" int nls_solve(nls_handle* h, double* u, int u_on_device, nls_stats* s
     S->failed_subdomain = -1;
     h->st = S;
     h->coarse_lu_valid = false;  // chord steps reuse factorisations within one solve only
-    const int N = h->mesh.N;
+    const int N = h->mesh.ndof();
     double* ud = u;
     if (!u_on_device) {
         ud = h->ubuf;

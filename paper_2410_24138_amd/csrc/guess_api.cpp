@@ -86,6 +86,8 @@ static int ensure_tables(nls_handle* h) {
     GuessState* g = state(h);
     if (g->tables) return NLS_OK;
     if (!h->have_part) return fail(h, NLS_ESTATE, "nls_set_partition first");
+    if (h->mesh.d != 1 || h->kind != NLS_PROBLEM_DIFFUSION)
+        return fail(h, NLS_EINVAL, "the learned guess is built for the scalar diffusion problem");
     HostGuess hg;
     std::string err;
     int rc = nls_build_guess_tables(h->mesh, h->maps, hg, err);

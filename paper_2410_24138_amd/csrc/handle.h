@@ -37,7 +37,9 @@ struct nls_handle {
     bool have_mesh = false, have_part = false, have_coarse = false, have_state = false;
     int kind = NLS_PROBLEM_DIFFUSION;
     double beta = 1.0;
+    double mu = 0.0, lam = 0.0;                // elasticity
     std::vector<double> kappa_h, fmid_h;
+    std::vector<double> fnode_h;               // nodal forces (elasticity), ndof
     std::vector<int> part_h;
     HostMaps maps;
     HostCoarse co;

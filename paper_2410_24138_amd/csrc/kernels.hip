@@ -25,6 +25,7 @@
 #include <climits>
 #include <cmath>
 
+#include "nls.h"
 #include "nls_device.h"
 
 #define NLS_BLOCK 256
@@ -96,6 +97,135 @@ __device__ __forceinline__ void g_row(const double* __restrict__ G6, int pos, do
 // ----------------------------------------------------------------------------
 
 // Residual of the rows of V_i held by this thread; vp = patch values in LDS.
+// ----------------------------------------------------------------------------
+// Q1 compressible Neo-Hooke (eq. 2): P = mu (F - F^-T) + lambda ln J F^-T,
+// A_iJkL = mu d_ik d_JL + lambda Finv_Ji Finv_Lk - (lambda ln J - mu) Finv_Jk Finv_Li.
+// Bilinear quadrilaterals, nodes counter-clockwise from the reference corner
+// (-1,-1), 2 x 2 Gauss points with unit weights.
+// ----------------------------------------------------------------------------
+struct NHPoint {
+    double wdet;        // quadrature weight x det(dX/dxi)
+    double gr[4][2];    // material gradients of the shape functions
+    double P[2][2];     // first Piola-Kirchhoff stress
+    double Fi[2][2];    // F^{-1}
+    double lnJ;
+    bool ok;            // det F > 0
+};
+
+__device__ __forceinline__ void nh_point(const double X[4][2], const double ue[4][2], int q,
+                                         double mu, double lam, NHPoint& o) {
+    constexpr double g = 0.57735026918962576451;  // 1/sqrt(3)
+    const double xa[4] = {-1.0, 1.0, 1.0, -1.0}, ya[4] = {-1.0, -1.0, 1.0, 1.0};
+    const double xi = xa[q] * g, eta = ya[q] * g;
+    double dN[4][2];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        dN[a][0] = 0.25 * xa[a] * (1.0 + ya[a] * eta);
+        dN[a][1] = 0.25 * ya[a] * (1.0 + xa[a] * xi);
+    }
+    double J00 = 0, J01 = 0, J10 = 0, J11 = 0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        J00 += X[a][0] * dN[a][0];
+        J01 += X[a][0] * dN[a][1];
+        J10 += X[a][1] * dN[a][0];
+        J11 += X[a][1] * dN[a][1];
+    }
+    const double det = J00 * J11 - J01 * J10;
+    const double id = 1.0 / det;
+    const double I00 = J11 * id, I01 = -J01 * id, I10 = -J10 * id, I11 = J00 * id;
+    double F00 = 1.0, F01 = 0.0, F10 = 0.0, F11 = 1.0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const double g0 = dN[a][0] * I00 + dN[a][1] * I10;
+        const double g1 = dN[a][0] * I01 + dN[a][1] * I11;
+        o.gr[a][0] = g0;
+        o.gr[a][1] = g1;
+        F00 += ue[a][0] * g0;
+        F01 += ue[a][0] * g1;
+        F10 += ue[a][1] * g0;
+        F11 += ue[a][1] * g1;
+    }
+    const double JF = F00 * F11 - F01 * F10;
+    o.ok = JF > 0.0;
+    const double iJ = 1.0 / JF;
+    o.Fi[0][0] = F11 * iJ;
+    o.Fi[0][1] = -F01 * iJ;
+    o.Fi[1][0] = -F10 * iJ;
+    o.Fi[1][1] = F00 * iJ;
+    o.lnJ = log(JF);
+    // P_iJ = mu (F_iJ - Finv_Ji) + lambda ln J Finv_Ji
+    const double a1 = lam * o.lnJ - mu;
+    o.P[0][0] = mu * F00 + a1 * o.Fi[0][0];
+    o.P[0][1] = mu * F01 + a1 * o.Fi[1][0];
+    o.P[1][0] = mu * F10 + a1 * o.Fi[0][1];
+    o.P[1][1] = mu * F11 + a1 * o.Fi[1][1];
+    o.wdet = det;
+}
+
+// Element geometry and displacements: global element ge, local dof values
+// from vp through the patch-local node ids, or the global vector u.
+__device__ __forceinline__ void nh_coords(const DevMesh& M, int ge, double X[4][2]) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int g = M.conn[4 * ge + v];
+        X[v][0] = M.xy[2 * g];
+        X[v][1] = M.xy[2 * g + 1];
+    }
+}
+
+// Internal force of dof (pos, c) of one element.
+__device__ __forceinline__ double nh_force(const DevMesh& M, const double X[4][2],
+                                           const double ue[4][2], int pos, int c, bool& ok) {
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        NHPoint p;
+        nh_point(X, ue, q, M.mu, M.lam, p);
+        ok = ok && p.ok;
+        acc += p.wdet * (p.P[c][0] * p.gr[pos][0] + p.P[c][1] * p.gr[pos][1]);
+    }
+    return acc;
+}
+
+// Stiffness row (pos, c) of one element: K[(pos,c),(b,k)] into kr[b][k].
+__device__ __forceinline__ void nh_stiff_row(const DevMesh& M, const double X[4][2],
+                                             const double ue[4][2], int pos, int c,
+                                             double kr[4][2]) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b) kr[b][0] = kr[b][1] = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        NHPoint p;
+        nh_point(X, ue, q, M.mu, M.lam, p);
+        // alpha_k = sum_J gr_pos,J Finv_Jk ; beta_k(b) = sum_L Finv_Lk gr_b,L
+        const double al0 = p.gr[pos][0] * p.Fi[0][0] + p.gr[pos][1] * p.Fi[1][0];
+        const double al1 = p.gr[pos][0] * p.Fi[0][1] + p.gr[pos][1] * p.Fi[1][1];
+        const double alc = c == 0 ? al0 : al1;
+        const double t = M.lam * p.lnJ - M.mu;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const double be0 = p.Fi[0][0] * p.gr[b][0] + p.Fi[1][0] * p.gr[b][1];
+            const double be1 = p.Fi[0][1] * p.gr[b][0] + p.Fi[1][1] * p.gr[b][1];
+            const double bec = c == 0 ? be0 : be1;
+            const double gg = p.gr[pos][0] * p.gr[b][0] + p.gr[pos][1] * p.gr[b][1];
+            // k = 0, 1: mu d_ck gg + lambda alpha_c beta_k - t alpha_k beta_c
+            kr[b][0] += p.wdet * ((c == 0 ? M.mu * gg : 0.0) + M.lam * alc * be0 - t * al0 * bec);
+            kr[b][1] += p.wdet * ((c == 1 ? M.mu * gg : 0.0) + M.lam * alc * be1 - t * al1 * bec);
+        }
+    }
+}
+
+__device__ __forceinline__ void nh_local_values(const DevMaps& P, int e, const double* vp,
+                                                int nd[4], double ue[4][2]) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        nd[v] = P.pe_conn[4 * e + v];
+        ue[v][0] = vp[2 * nd[v]];
+        ue[v][1] = vp[2 * nd[v] + 1];
+    }
+}
+
 __device__ __forceinline__ void local_residual(const DevMesh& M, const DevMaps& P, int n, int rowbase,
                                int ebase, const double* vp, double* rb) {
     for (int a = threadIdx.x; a < n; a += blockDim.x) {
@@ -103,6 +233,24 @@ __device__ __forceinline__ void local_residual(const DevMesh& M, const DevMaps& 
         const int g = P.l2g[row];
         if (M.dflag[g]) {
             rb[a] = vp[a] - M.dval[g];
+            continue;
+        }
+        if (M.kind == NLS_PROBLEM_NEOHOOKE) {
+            // row a = dof (a & 1) of a V node; a non-admissible deformation
+            // (det F <= 0) makes the residual NaN
+            const int c = a & 1;
+            double acc = 0.0;
+            bool ok = true;
+            for (int k = P.rinc_ptr[row]; k < P.rinc_ptr[row + 1]; ++k) {
+                const int code = P.rinc[k];
+                const int e = ebase + (code >> 2), pos = code & 3;
+                double X[4][2], ue[4][2];
+                int nd[4];
+                nh_coords(M, P.pe_gid[e], X);
+                nh_local_values(P, e, vp, nd, ue);
+                acc += nh_force(M, X, ue, pos, c, ok);
+            }
+            rb[a] = ok ? acc - M.bload[g] : __builtin_nan("");
             continue;
         }
         double acc = 0.0;
@@ -134,6 +282,27 @@ __device__ __forceinline__ void local_jacobian(const DevMesh& M, const DevMaps& 
         if (M.dflag[g]) {
             for (int s = js; s < je; ++s)
                 if (P.jcol[s] == a) jval[s] = 1.0;
+            continue;
+        }
+        if (M.kind == NLS_PROBLEM_NEOHOOKE) {
+            const int c = a & 1;
+            for (int k = P.rinc_ptr[row]; k < P.rinc_ptr[row + 1]; ++k) {
+                const int code = P.rinc[k];
+                const int e = ebase + (code >> 2), pos = code & 3;
+                double X[4][2], ue[4][2], kr[4][2];
+                int nd[4];
+                nh_coords(M, P.pe_gid[e], X);
+                nh_local_values(P, e, vp, nd, ue);
+                nh_stiff_row(M, X, ue, pos, c, kr);
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+#pragma unroll
+                    for (int kk = 0; kk < 2; ++kk) {
+                        const int col = 2 * nd[b] + kk;
+                        for (int t = js; t < je; ++t)
+                            if (P.jcol[t] == col) { jval[t] += kr[b][kk]; break; }
+                    }
+            }
             continue;
         }
         for (int k = P.rinc_ptr[row]; k < P.rinc_ptr[row + 1]; ++k) {
@@ -1211,6 +1380,33 @@ __global__ void k_global_residual(DevMesh M, const double* __restrict__ u, doubl
     F[g] = acc - M.bload[g];
 }
 
+// Global residual of the elasticity problem: one thread per dof.
+__global__ void k_global_residual_nh(DevMesh M, const double* __restrict__ u, double* __restrict__ F) {
+    const int gd = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gd >= M.ndof) return;
+    if (M.dflag[gd]) {
+        F[gd] = u[gd] - M.dval[gd];
+        return;
+    }
+    const int g = gd >> 1, c = gd & 1;
+    double acc = 0.0;
+    bool ok = true;
+    for (int k = M.nptr[g]; k < M.nptr[g + 1]; ++k) {
+        const int code = M.nel[k];
+        const int e = code >> 2, pos = code & 3;
+        double X[4][2], ue[4][2];
+        nh_coords(M, e, X);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int gn = M.conn[4 * e + v];
+            ue[v][0] = u[2 * gn];
+            ue[v][1] = u[2 * gn + 1];
+        }
+        acc += nh_force(M, X, ue, pos, c, ok);
+    }
+    F[gd] = ok ? acc - M.bload[gd] : __builtin_nan("");
+}
+
 // Element geometry G = |T| grad(phi).grad(phi), coefficient and load vectors.
 // With b_a = y_{a+1}-y_{a+2}, c_a = x_{a+2}-x_{a+1}: G_ab = (b_a b_b + c_a c_b)/(4|T|).
 // Load by the edge-midpoint rule: l_a = |T|/6 (f(m_{a,a+1}) + f(m_{a-1,a})).
@@ -1740,7 +1936,10 @@ hipError_t launch_assemble_load(const DevMesh& M, double* bload, hipStream_t s) 
 }
 
 hipError_t launch_global_residual(const DevMesh& M, const double* u, double* F, hipStream_t s) {
-    k_global_residual<<<nblocks(M.N), NLS_BLOCK, 0, s>>>(M, u, F);
+    if (M.kind == NLS_PROBLEM_NEOHOOKE)
+        k_global_residual_nh<<<nblocks(M.ndof), NLS_BLOCK, 0, s>>>(M, u, F);
+    else
+        k_global_residual<<<nblocks(M.N), NLS_BLOCK, 0, s>>>(M, u, F);
     return hipGetLastError();
 }
 
@@ -1774,7 +1973,7 @@ hipError_t launch_prolong(const DevMesh& M, const DevMaps& P, const double* T,
                           const DevCoarse* C, const double* cvec, double* out, const double* addv,
                           hipStream_t s) {
     DevCoarse dummy{};
-    k_prolong<<<nblocks(M.N), NLS_BLOCK, 0, s>>>(M.N, P.own_pidx, T, addv, C ? *C : dummy,
+    k_prolong<<<nblocks(M.ndof), NLS_BLOCK, 0, s>>>(M.ndof, P.own_pidx, T, addv, C ? *C : dummy,
                                                  C ? 1 : 0, cvec, out);
     return hipGetLastError();
 }

@@ -9,16 +9,21 @@
 // Global mesh and problem data, all resident in HBM.
 struct DevMesh {
     int N, E;
-    const int* conn;            // 3E
+    int kind;                   // NLS_PROBLEM_*
+    int nv, d, ndof;            // nodes per element, dofs per node, N*d
+    const int* conn;            // nv*E
+    const double* xy;           // 2N
     const int* nptr;            // N+1: node -> incident elements
     const int* nel;             // (element << 2) | vertex position
     const double* G6;           // 6E: |T| grad(phi_a).grad(phi_b): G00 G11 G22 G01 G12 G20
     const double* kappa;        // E
     const double* eload;        // 3E: element load vectors
-    const double* bload;        // N: assembled load, 0 on Dirichlet rows
-    const unsigned char* dflag; // N
-    const double* dval;         // N
-    double beta;
+    const double* bload;        // ndof: assembled load (diffusion) or nodal
+                                //   forces (elasticity), 0 on Dirichlet rows
+    const unsigned char* dflag; // ndof
+    const double* dval;         // ndof
+    double beta;                // diffusion
+    double mu, lam;             // elasticity
 };
 
 // Overlapping-subdomain tables (see HostMaps).

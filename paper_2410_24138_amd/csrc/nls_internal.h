@@ -37,25 +37,32 @@ inline int interior_lds_doubles(int ni, int kl, int ku, int nk) {
 
 struct HostMesh {
     int N = 0;                     // nodes
-    int E = 0;                     // triangles
+    int E = 0;                     // elements
+    int nv = 3;                    // nodes per element: 3 (P1 triangle), 4 (Q1 quad)
+    int d = 1;                     // dofs per node (node-major, interleaved)
     std::vector<double> xy;        // 2N
-    std::vector<int> conn;         // 3E
+    std::vector<int> conn;         // nv * E
     std::vector<int> nptr, nel;    // node -> incident elements (CSR, ascending)
-    std::vector<unsigned char> dflag;  // N, 1 on Dirichlet nodes
-    std::vector<double> dval;      // N
+    std::vector<unsigned char> dflag;  // N*d, 1 on Dirichlet dofs
+    std::vector<double> dval;      // N*d
+    int ndof() const { return N * d; }
 };
 
 // Overlapping subdomains and the tables the local kernels read.
 // "Packed" arrays concatenate the per-subdomain arrays in subdomain order.
+// Rows are dofs: row d*a + c is component c of the a-th node of V_i; the
+// patch-local id of a node is its position in V_i, or n_V + its position
+// in Gamma_i, and its dof c has local index d*id + c.
 struct HostMaps {
     int nsub = 0;
     std::vector<int> off_n;        // nsub+1, offsets into packed V rows
     std::vector<int> off_g;        // nsub+1, offsets into packed Gamma nodes
     std::vector<int> off_e;        // nsub+1, offsets into packed patch elements
-    std::vector<int> l2g;          // packed V_i global node ids (ascending per subdomain)
-    std::vector<int> g2g;          // packed Gamma_i global node ids
-    std::vector<int> pe_conn;      // 3 per packed patch element, patch-local node ids
-                                   //   (< n_i: V_i position, else n_i + Gamma_i position)
+    std::vector<int> l2g;          // packed V_i global dof ids (node order of V_i:
+                                   //   ascending, or along the shorter side of the
+                                   //   patch box for vector problems)
+    std::vector<int> g2g;          // packed Gamma_i global dof ids (nodes ascending)
+    std::vector<int> pe_conn;      // nv per packed patch element, patch-local node ids
     std::vector<int> pe_gid;       // global element id of each packed patch element
     std::vector<int> rinc_ptr;     // packed V row -> [rinc_ptr, rinc_ptr+1) in rinc
     std::vector<int> rinc;         // (patch element local index << 2) | vertex position
@@ -65,7 +72,7 @@ struct HostMaps {
     std::vector<int64_t> off_u;    // offset (doubles) of the U factor, n_i*(kl+ku+1)
     std::vector<int64_t> off_l;    // offset (doubles) of the L factor, n_i*max(kl,1)
     int64_t factor_u_total = 0, factor_l_total = 0;
-    std::vector<int> own_pidx;     // N: packed V row of the owner's copy of node g
+    std::vector<int> own_pidx;     // N*d: packed V row of the owner's copy of dof g
     // exact-tangent tables: B_i by columns, owned rows of each subdomain
     std::vector<int> bptr;         // packed Gamma column -> [bptr, bptr+1) entries
     std::vector<int> brow;         // local row of each B entry (ascending per column)

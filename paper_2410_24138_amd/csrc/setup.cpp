@@ -22,10 +22,11 @@
 #include "nls_internal.h"
 
 int nls_build_node_incidence(HostMesh& m, std::string& err) {
+    const int nv = m.nv;
     m.nptr.assign(m.N + 1, 0);
     for (int e = 0; e < m.E; ++e)
-        for (int v = 0; v < 3; ++v) {
-            int g = m.conn[3 * e + v];
+        for (int v = 0; v < nv; ++v) {
+            int g = m.conn[nv * e + v];
             if (g < 0 || g >= m.N) {
                 err = "element node index out of range";
                 return NLS_EINVAL;
@@ -36,19 +37,19 @@ int nls_build_node_incidence(HostMesh& m, std::string& err) {
     m.nel.assign(m.nptr[m.N], 0);
     std::vector<int> fill(m.nptr.begin(), m.nptr.end() - 1);
     for (int e = 0; e < m.E; ++e)
-        for (int v = 0; v < 3; ++v) m.nel[fill[m.conn[3 * e + v]]++] = e;
+        for (int v = 0; v < nv; ++v) m.nel[fill[m.conn[nv * e + v]]++] = e;
     return NLS_OK;
 }
 
 static inline int vertex_pos(const HostMesh& m, int e, int g) {
-    for (int v = 0; v < 3; ++v)
-        if (m.conn[3 * e + v] == g) return v;
+    for (int v = 0; v < m.nv; ++v)
+        if (m.conn[m.nv * e + v] == g) return v;
     return -1;
 }
 
 int nls_build_maps(const HostMesh& m, const int* part, int nsub, int overlap,
                    HostMaps& out, std::string& err) {
-    const int N = m.N, E = m.E;
+    const int N = m.N, E = m.E, nv = m.nv, dd = m.d;
     if (nsub <= 0 || overlap < 1) {
         err = "need n_sub >= 1 and overlap >= 1 (owned nodes must lie in V_i)";
         return NLS_EPARTITION;
@@ -68,8 +69,8 @@ int nls_build_maps(const HostMesh& m, const int* part, int nsub, int overlap,
         }
     std::vector<int> owner(N, -1);
     for (int e = 0; e < E; ++e)
-        for (int v = 0; v < 3; ++v) {
-            int g = m.conn[3 * e + v];
+        for (int v = 0; v < nv; ++v) {
+            int g = m.conn[nv * e + v];
             owner[g] = std::max(owner[g], part[e]);
         }
 
@@ -81,6 +82,7 @@ int nls_build_maps(const HostMesh& m, const int* part, int nsub, int overlap,
     M.off_e.assign(1, 0);
     M.rinc_ptr.assign(1, 0);
     M.jptr.assign(1, 0);
+    M.own_pidx.assign((size_t)N * dd, -1);
     std::vector<char> inpatch(E, 0), nmark(N, 0);
     std::vector<int> cnt(N, 0), loc(N, -1), eloc(E, -1);
 
@@ -90,8 +92,8 @@ int nls_build_maps(const HostMesh& m, const int* part, int nsub, int overlap,
         for (int layer = 0; layer < overlap; ++layer) {
             std::vector<int> nodes;
             for (int e : pe)
-                for (int v = 0; v < 3; ++v) {
-                    int g = m.conn[3 * e + v];
+                for (int v = 0; v < nv; ++v) {
+                    int g = m.conn[nv * e + v];
                     if (!nmark[g]) { nmark[g] = 1; nodes.push_back(g); }
                 }
             std::vector<int> add;
@@ -107,8 +109,8 @@ int nls_build_maps(const HostMesh& m, const int* part, int nsub, int overlap,
         std::sort(pe.begin(), pe.end());
         std::vector<int> pnodes;
         for (int e : pe)
-            for (int v = 0; v < 3; ++v) {
-                int g = m.conn[3 * e + v];
+            for (int v = 0; v < nv; ++v) {
+                int g = m.conn[nv * e + v];
                 if (cnt[g]++ == 0) pnodes.push_back(g);
             }
         std::vector<int> V, G;
@@ -118,38 +120,66 @@ int nls_build_maps(const HostMesh& m, const int* part, int nsub, int overlap,
         }
         std::sort(V.begin(), V.end());
         std::sort(G.begin(), G.end());
-        const int n = (int)V.size();
-        for (int a = 0; a < n; ++a) loc[V[a]] = a;
-        for (int j = 0; j < (int)G.size(); ++j) loc[G[j]] = n + j;
+        if (dd > 1 && !V.empty()) {
+            // vector problems: the shorter side of the patch box varies
+            // fastest, so the dof band of J_ii stays near d x (short side)
+            double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
+            for (int g : V) {
+                x0 = std::min(x0, m.xy[2 * g]);
+                x1 = std::max(x1, m.xy[2 * g]);
+                y0 = std::min(y0, m.xy[2 * g + 1]);
+                y1 = std::max(y1, m.xy[2 * g + 1]);
+            }
+            if (x1 - x0 > y1 - y0)
+                std::stable_sort(V.begin(), V.end(), [&](int a, int b) {
+                    if (m.xy[2 * a] != m.xy[2 * b]) return m.xy[2 * a] < m.xy[2 * b];
+                    return m.xy[2 * a + 1] < m.xy[2 * b + 1];
+                });
+        }
+        const int nn = (int)V.size(), n = dd * nn;
+        for (int a = 0; a < nn; ++a) loc[V[a]] = a;
+        for (int j = 0; j < (int)G.size(); ++j) loc[G[j]] = nn + j;
         for (int k = 0; k < (int)pe.size(); ++k) eloc[pe[k]] = k;
         for (int e : pe) {
-            for (int v = 0; v < 3; ++v) M.pe_conn.push_back(loc[m.conn[3 * e + v]]);
+            for (int v = 0; v < nv; ++v) M.pe_conn.push_back(loc[m.conn[nv * e + v]]);
             M.pe_gid.push_back(e);
         }
         int kl = 0, ku = 0;
-        std::vector<int> cols;
-        for (int a = 0; a < n; ++a) {
+        std::vector<int> cols, inc;
+        for (int a = 0; a < nn; ++a) {
             int g = V[a];
             cols.clear();
+            inc.clear();
             for (int k = m.nptr[g]; k < m.nptr[g + 1]; ++k) {
                 int e = m.nel[k];
-                M.rinc.push_back((eloc[e] << 2) | vertex_pos(m, e, g));
-                for (int v = 0; v < 3; ++v) cols.push_back(loc[m.conn[3 * e + v]]);
+                inc.push_back((eloc[e] << 2) | vertex_pos(m, e, g));
+                for (int v = 0; v < nv; ++v)
+                    for (int c = 0; c < dd; ++c) cols.push_back(dd * loc[m.conn[nv * e + v]] + c);
             }
             std::sort(cols.begin(), cols.end());
             cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
-            for (int c : cols) {
-                M.jcol.push_back(c);
-                if (c < n) {
-                    kl = std::max(kl, a - c);
-                    ku = std::max(ku, c - a);
+            for (int c = 0; c < dd; ++c) {
+                const int row = dd * a + c;
+                M.rinc.insert(M.rinc.end(), inc.begin(), inc.end());
+                for (int col : cols) {
+                    M.jcol.push_back(col);
+                    if (col < n) {
+                        kl = std::max(kl, row - col);
+                        ku = std::max(ku, col - row);
+                    }
                 }
+                M.rinc_ptr.push_back((int)M.rinc.size());
+                M.jptr.push_back((int)M.jcol.size());
             }
-            M.rinc_ptr.push_back((int)M.rinc.size());
-            M.jptr.push_back((int)M.jcol.size());
         }
-        M.l2g.insert(M.l2g.end(), V.begin(), V.end());
-        M.g2g.insert(M.g2g.end(), G.begin(), G.end());
+        const int rb = (int)M.l2g.size();
+        for (int a = 0; a < nn; ++a)
+            for (int c = 0; c < dd; ++c) {
+                M.l2g.push_back(dd * V[a] + c);
+                if (owner[V[a]] == i) M.own_pidx[(size_t)dd * V[a] + c] = rb + dd * a + c;
+            }
+        for (int g : G)
+            for (int c = 0; c < dd; ++c) M.g2g.push_back(dd * g + c);
         M.off_n.push_back((int)M.l2g.size());
         M.off_g.push_back((int)M.g2g.size());
         M.off_e.push_back((int)M.pe_gid.size());
@@ -160,21 +190,17 @@ int nls_build_maps(const HostMesh& m, const int* part, int nsub, int overlap,
     }
 
     // owners: the owned nodes of subdomain o must lie in V_o
-    M.own_pidx.assign(N, -1);
     for (int g = 0; g < N; ++g) {
         int o = owner[g];
         if (o < 0) {
             err = "node " + std::to_string(g) + " belongs to no element";
             return NLS_EINVAL;
         }
-        auto b = M.l2g.begin() + M.off_n[o], en = M.l2g.begin() + M.off_n[o + 1];
-        auto it = std::lower_bound(b, en, g);
-        if (it == en || *it != g) {
+        if (M.own_pidx[(size_t)dd * g] < 0) {
             err = "subdomain " + std::to_string(o) + ": owned node " +
                   std::to_string(g) + " not in V_i";
             return NLS_EPARTITION;
         }
-        M.own_pidx[g] = (int)(it - M.l2g.begin());
     }
 
     // B_i by columns (Gamma columns of the local CSR rows), owned rows
@@ -199,7 +225,7 @@ int nls_build_maps(const HostMesh& m, const int* part, int nsub, int overlap,
         }
         int no = 0;
         for (int a = 0; a < n; ++a)
-            if (owner[M.l2g[rb + a]] == i) {
+            if (owner[M.l2g[rb + a] / dd] == i) {
                 M.rowown[rb + a] = no++;
                 M.ownrow.push_back(a);
             }

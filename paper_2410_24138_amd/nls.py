@@ -28,7 +28,9 @@ NLS_ESTATE = -8
 NLS_ELIMIT = -9
 
 ELEM_P1_TRI = 3
+ELEM_Q1_QUAD = 4
 PROBLEM_DIFFUSION = 1
+PROBLEM_NEOHOOKE = 2
 PREC_FP64 = 0
 PREC_FP32_IR = 1
 ONE_LEVEL = 0
@@ -54,7 +56,7 @@ SYMBOLS = (
     "nls_guess_get_model", "nls_guess_enable", "nls_guess_capture",
     "nls_guess_captured", "nls_guess_features", "nls_guess_lift",
     "nls_guess_predict", "nls_guess_loss_grad", "nls_guess_train",
-    "nls_get_tuning",
+    "nls_get_tuning", "nls_set_nodal_load",
 )
 
 GUESS_PARAMS = 279552
@@ -151,6 +153,7 @@ def load() -> ctypes.CDLL:
         "nls_inspect_coarse": ([i64, i64, P, i32, P, i64, P, P, P, P], ctypes.c_int),
         "nls_last_error": ([P], ctypes.c_char_p),
         "nls_set_load": ([P, P], ctypes.c_int),
+        "nls_set_nodal_load": ([P, P], ctypes.c_int),
         "nls_get_tuning": ([P, P, P, P, P, P, P], ctypes.c_int),
         "nls_guess_set_model": ([P, P, i64, P], ctypes.c_int),
         "nls_guess_get_model": ([P, P, P], ctypes.c_int),
@@ -267,26 +270,40 @@ class Solver:
         self.case = case
         xy = np.ascontiguousarray(case["xy"], dtype=np.float64)
         conn = np.ascontiguousarray(case["conn"], dtype=np.int32)
-        self.N = len(xy)
-        self._check(self.lib.nls_set_mesh(h, ELEM_P1_TRI, len(xy), _ptr(xy),
-                                          len(conn), _ptr(conn)))
-        params = np.array([case.get("beta", 1.0)], dtype=np.float64)
-        coef = case.get("elem_coef")
-        load_ = case.get("elem_load")
-        coef = None if coef is None else np.ascontiguousarray(coef, dtype=np.float64)
-        load_ = None if load_ is None else np.ascontiguousarray(load_, dtype=np.float64)
-        self._check(self.lib.nls_set_problem(
-            h, PROBLEM_DIFFUSION, _ptr(params),
-            None if coef is None else _ptr(coef),
-            None if load_ is None else _ptr(load_)))
+        elastic = case.get("kind") == "neohooke"
+        self.d = 2 if elastic else 1
+        self.N = self.d * len(xy)
+        self._check(self.lib.nls_set_mesh(h, ELEM_Q1_QUAD if elastic else ELEM_P1_TRI,
+                                          len(xy), _ptr(xy), len(conn), _ptr(conn)))
+        if elastic:
+            params = np.array([case["mu"], case["lam"]], dtype=np.float64)
+            self._check(self.lib.nls_set_problem(h, PROBLEM_NEOHOOKE, _ptr(params), None, None))
+        else:
+            params = np.array([case.get("beta", 1.0)], dtype=np.float64)
+            coef = case.get("elem_coef")
+            load_ = case.get("elem_load")
+            coef = None if coef is None else np.ascontiguousarray(coef, dtype=np.float64)
+            load_ = None if load_ is None else np.ascontiguousarray(load_, dtype=np.float64)
+            self._check(self.lib.nls_set_problem(
+                h, PROBLEM_DIFFUSION, _ptr(params),
+                None if coef is None else _ptr(coef),
+                None if load_ is None else _ptr(load_)))
         dn = np.ascontiguousarray(case["dirichlet"], dtype=np.int64)
         dv = np.ascontiguousarray(case["dirichlet_vals"], dtype=np.float64)
         self._check(self.lib.nls_set_dirichlet(h, len(dn), _ptr(dn), _ptr(dv)))
+        if elastic:
+            self.set_nodal_load(case["nodal_force"])
         part = np.ascontiguousarray(case["elem_part"], dtype=np.int32)
         self._check(self.lib.nls_set_partition(h, int(case["n_sub"]), _ptr(part),
                                                int(case["overlap"])))
         if coupling == "additive":
             self._check(self.lib.nls_build_coarse(h, COARSE_GDSW))
+
+    def set_nodal_load(self, f):
+        """Nodal forces (elasticity), n_nodes * 2 values in dof order."""
+        a = np.ascontiguousarray(f, dtype=np.float64)
+        assert a.size == self.N
+        self._check(self.lib.nls_set_nodal_load(self.h, _ptr(a)))
 
     def _check(self, rc, h="self"):
         if rc < 0:

@@ -1,0 +1,89 @@
+"""Compressible Neo-Hooke elasticity (Q1, two dofs per node): HIP path
+through the C ABI against the FP64 oracle.
+
+Tolerances as for diffusion: F(u) 1e-12 of its largest entry (same formula,
+different summation order); F_x and the tangent 1e-10 of their largest
+entries (band LU vs dense LU on stiffer local problems); the solution of the
+outer iteration 1e-10 relative with equal outer iteration counts.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import NHProblem, Schwarz, global_newton
+from tests._lib import ensure_built
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    ensure_built()
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _solver(case, **kw):
+    from paper_2410_24138_amd import Solver
+    return Solver(case, **kw)
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _close(a, b, rel):
+    scale = max(np.abs(b).max(), 1e-300)
+    err = np.abs(a - b).max() / scale
+    assert err <= rel, f"max err {err:.3e} > {rel:.1e}"
+
+
+CASES = [
+    dict(nx=8, ny=4, boxes=(2, 2), overlap=1, traction=(0.0, -2.0)),
+    dict(nx=12, ny=6, boxes=(3, 2), overlap=2, traction=(0.5, -3.0)),
+    dict(nx=10, ny=5, boxes=(2, 2), overlap=1, traction=(0.0, -4.0)),
+]
+
+
+def _probe(P, seed=1):
+    ug, _ = global_newton(P)
+    rng = np.random.default_rng(seed)
+    u = 0.5 * ug + 0.02 * np.abs(ug).max() * rng.normal(size=P.ndof)
+    u[P.is_dir] = 0.0
+    return u
+
+
+@pytest.mark.parametrize("kw", CASES)
+def test_global_residual(kw):
+    case = synth.small_elasticity_case(two_level=False, **kw)
+    P = NHProblem(case)
+    s = _solver(case, coupling="one_level")
+    u = _probe(P)
+    _close(_np(s.residual(u)), P.residual(u), 1e-12)
+
+
+@pytest.mark.parametrize("kw", CASES)
+def test_precond_residual_and_tangent_one_level(kw):
+    case = synth.small_elasticity_case(two_level=False, **kw)
+    P = NHProblem(case)
+    S = Schwarz(P, "one_level")
+    s = _solver(case, coupling="one_level")
+    u = _probe(P, 2)
+    _close(_np(s.precond_residual(u)), S.evaluate(u), 1e-10)
+    np.testing.assert_array_equal(s.inner_iterations(), [sol["its"] for sol in S.state["sols"]])
+    rng = np.random.default_rng(3)
+    for _ in range(2):
+        v = rng.normal(size=P.ndof)
+        _close(_np(s.tangent(v)), S.tangent(v), 1e-10)
+
+
+@pytest.mark.parametrize("kw", CASES[:2])
+def test_solve_one_level(kw):
+    case = synth.small_elasticity_case(two_level=False, **kw)
+    P = NHProblem(case)
+    S = Schwarz(P, "one_level")
+    u_ref, st_ref = S.solve()
+    uu, st, rc = _solver(case, coupling="one_level").solve()
+    assert rc == 0 and st["converged"] and st["outer_its"] == st_ref["outer"]
+    assert np.linalg.norm(_np(uu) - u_ref) <= 1e-10 * np.linalg.norm(u_ref)
