@@ -471,7 +471,6 @@ extern "C" int nls_build_coarse(nls_handle* h, int kind) {
     if (h) h->drop_graphs();
     if (!h) return NLS_EINVAL;
     if (!h->have_part) return fail(h, NLS_ESTATE, "nls_set_partition first");
-    if (h->mesh.d != 1) return fail(h, NLS_EINVAL, "GDSW coarse space for elasticity: not available");
     HIPCHK(hipSetDevice(h->opt.device));
     h->free_group(G_COARSE);
     h->have_coarse = false;
@@ -506,7 +505,8 @@ extern "C" int nls_build_coarse(nls_handle* h, int kind) {
     d.nsub = h->maps.nsub;
     d.a0kl = C.a0kl;
     d.a0ku = C.a0ku;
-    int *off_c, *cnode, *ctype, *off_k, *klist, *ccomp, *off_ne, *ne_conn, *ne_gid, *cinc_ptr,
+    double* cval;
+    int *off_c, *cnode, *ctype, *off_k, *klist, *cfun, *off_ne, *ne_conn, *ne_gid, *cinc_ptr,
         *cinc, *iidx, *off_ni, *inode, *iptr, *icol, *ikl, *iku, *perm, *a0ptr, *a0col,
         *a0src_ptr, *a0src, *gsrc_ptr, *gsrc, *cpos, *cown;
     int64_t *off_phi, *off_iu, *off_il, *off_kk;
@@ -515,7 +515,8 @@ extern "C" int nls_build_coarse(nls_handle* h, int kind) {
     RC(h->upload(G_COARSE, &ctype, C.ctype));
     RC(h->upload(G_COARSE, &off_k, C.off_k));
     RC(h->upload(G_COARSE, &klist, C.klist));
-    RC(h->upload(G_COARSE, &ccomp, C.ccomp));
+    RC(h->upload(G_COARSE, &cfun, C.cfun));
+    RC(h->upload(G_COARSE, &cval, C.cval));
     RC(h->upload(G_COARSE, &off_ne, C.off_ne));
     RC(h->upload(G_COARSE, &ne_conn, C.ne_conn));
     RC(h->upload(G_COARSE, &ne_gid, C.ne_gid));
@@ -558,7 +559,7 @@ extern "C" int nls_build_coarse(nls_handle* h, int kind) {
         for (int b = 0; b < d.nblk; ++b) h->max_block = std::max(h->max_block, C.boff[b + 1] - C.boff[b]);
     }
     d.off_c = off_c; d.cnode = cnode; d.ctype = ctype; d.off_k = off_k; d.klist = klist;
-    d.ccomp = ccomp; d.off_ne = off_ne; d.ne_conn = ne_conn; d.ne_gid = ne_gid;
+    d.cfun = cfun; d.cval = cval; d.off_ne = off_ne; d.ne_conn = ne_conn; d.ne_gid = ne_gid;
     d.cinc_ptr = cinc_ptr; d.cinc = cinc; d.iidx = iidx; d.off_ni = off_ni; d.inode = inode;
     d.iptr = iptr; d.icol = icol; d.ikl = ikl; d.iku = iku; d.perm = perm; d.a0ptr = a0ptr;
     d.a0col = a0col; d.a0src_ptr = a0src_ptr; d.a0src = a0src; d.gsrc_ptr = gsrc_ptr;
@@ -1309,7 +1310,7 @@ extern "C" int nls_get_coarse_basis(nls_handle* h, int64_t* nnz, int64_t* rowptr
     if (!h || !nnz) return NLS_EINVAL;
     if (!h->have_coarse) return fail(h, NLS_ESTATE, "nls_build_coarse first");
     const HostCoarse& C = h->co;
-    const int N = h->mesh.N;
+    const int N = h->mesh.ndof();
     std::vector<double> phi(C.off_phi.back());
     if (!phi.empty()) {
         HIPCHK(hipMemcpyAsync(phi.data(), h->dc.phi, phi.size() * sizeof(double),

@@ -174,6 +174,21 @@ __device__ __forceinline__ void nh_coords(const DevMesh& M, int ge, double X[4][
     }
 }
 
+// Entries selected by a runtime index through unrolled compares (keeps the
+// small arrays in registers).
+__device__ __forceinline__ void nh_pick(const NHPoint& p, int pos, int c, double& g0, double& g1,
+                                        double& P0, double& P1) {
+    g0 = g1 = 0.0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+        if (a == pos) {
+            g0 = p.gr[a][0];
+            g1 = p.gr[a][1];
+        }
+    P0 = c == 0 ? p.P[0][0] : p.P[1][0];
+    P1 = c == 0 ? p.P[0][1] : p.P[1][1];
+}
+
 // Internal force of dof (pos, c) of one element.
 __device__ __forceinline__ double nh_force(const DevMesh& M, const double X[4][2],
                                            const double ue[4][2], int pos, int c, bool& ok) {
@@ -183,7 +198,9 @@ __device__ __forceinline__ double nh_force(const DevMesh& M, const double X[4][2
         NHPoint p;
         nh_point(X, ue, q, M.mu, M.lam, p);
         ok = ok && p.ok;
-        acc += p.wdet * (p.P[c][0] * p.gr[pos][0] + p.P[c][1] * p.gr[pos][1]);
+        double g0, g1, P0, P1;
+        nh_pick(p, pos, c, g0, g1, P0, P1);
+        acc += p.wdet * (P0 * g0 + P1 * g1);
     }
     return acc;
 }
@@ -199,8 +216,10 @@ __device__ __forceinline__ void nh_stiff_row(const DevMesh& M, const double X[4]
         NHPoint p;
         nh_point(X, ue, q, M.mu, M.lam, p);
         // alpha_k = sum_J gr_pos,J Finv_Jk ; beta_k(b) = sum_L Finv_Lk gr_b,L
-        const double al0 = p.gr[pos][0] * p.Fi[0][0] + p.gr[pos][1] * p.Fi[1][0];
-        const double al1 = p.gr[pos][0] * p.Fi[0][1] + p.gr[pos][1] * p.Fi[1][1];
+        double gp0, gp1, P0, P1;
+        nh_pick(p, pos, c, gp0, gp1, P0, P1);
+        const double al0 = gp0 * p.Fi[0][0] + gp1 * p.Fi[1][0];
+        const double al1 = gp0 * p.Fi[0][1] + gp1 * p.Fi[1][1];
         const double alc = c == 0 ? al0 : al1;
         const double t = M.lam * p.lnJ - M.mu;
 #pragma unroll
@@ -208,7 +227,7 @@ __device__ __forceinline__ void nh_stiff_row(const DevMesh& M, const double X[4]
             const double be0 = p.Fi[0][0] * p.gr[b][0] + p.Fi[1][0] * p.gr[b][1];
             const double be1 = p.Fi[0][1] * p.gr[b][0] + p.Fi[1][1] * p.gr[b][1];
             const double bec = c == 0 ? be0 : be1;
-            const double gg = p.gr[pos][0] * p.gr[b][0] + p.gr[pos][1] * p.gr[b][1];
+            const double gg = gp0 * p.gr[b][0] + gp1 * p.gr[b][1];
             // k = 0, 1: mu d_ck gg + lambda alpha_c beta_k - t alpha_k beta_c
             kr[b][0] += p.wdet * ((c == 0 ? M.mu * gg : 0.0) + M.lam * alc * be0 - t * al0 * bec);
             kr[b][1] += p.wdet * ((c == 1 ? M.mu * gg : 0.0) + M.lam * alc * be1 - t * al1 * bec);
@@ -226,6 +245,7 @@ __device__ __forceinline__ void nh_local_values(const DevMaps& P, int e, const d
     }
 }
 
+template <bool ELAST>
 __device__ __forceinline__ void local_residual(const DevMesh& M, const DevMaps& P, int n, int rowbase,
                                int ebase, const double* vp, double* rb) {
     for (int a = threadIdx.x; a < n; a += blockDim.x) {
@@ -235,7 +255,7 @@ __device__ __forceinline__ void local_residual(const DevMesh& M, const DevMaps& 
             rb[a] = vp[a] - M.dval[g];
             continue;
         }
-        if (M.kind == NLS_PROBLEM_NEOHOOKE) {
+        if (ELAST) {
             // row a = dof (a & 1) of a V node; a non-admissible deformation
             // (det F <= 0) makes the residual NaN
             const int c = a & 1;
@@ -272,6 +292,7 @@ __device__ __forceinline__ void local_residual(const DevMesh& M, const DevMaps& 
 }
 
 // Jacobian rows [J_ii | B_i] into the CSR values jval (slots fixed at setup).
+template <bool ELAST>
 __device__ __forceinline__ void local_jacobian(const DevMesh& M, const DevMaps& P, int n, int rowbase,
                                int ebase, const double* vp, double* __restrict__ jval) {
     for (int a = threadIdx.x; a < n; a += blockDim.x) {
@@ -284,7 +305,7 @@ __device__ __forceinline__ void local_jacobian(const DevMesh& M, const DevMaps& 
                 if (P.jcol[s] == a) jval[s] = 1.0;
             continue;
         }
-        if (M.kind == NLS_PROBLEM_NEOHOOKE) {
+        if (ELAST) {
             const int c = a & 1;
             for (int k = P.rinc_ptr[row]; k < P.rinc_ptr[row + 1]; ++k) {
                 const int code = P.rinc[k];
@@ -908,7 +929,7 @@ __device__ __forceinline__ int local_factor(const DevMaps& P, const DevLocal& L,
 // Stopping: ||r||_2 <= max(rtol rho_plain, abs_tol sqrt(n_i)) or
 // max|step| <= stagnation max|x|, at most maxit steps.
 // ----------------------------------------------------------------------------
-template <int NPL>
+template <int NPL, bool ELAST>
 __global__ void __launch_bounds__(NLS_BLOCK)
 k_local_newton(DevMesh M, DevMaps P, DevLocal L, NewtonParams np, const double* __restrict__ u) {
     extern __shared__ double smem[];
@@ -928,7 +949,7 @@ k_local_newton(DevMesh M, DevMaps P, DevLocal L, NewtonParams np, const double* 
     for (int a = threadIdx.x; a < n; a += blockDim.x) vp[a] = u[P.l2g[rowbase + a]];
     for (int j = threadIdx.x; j < ng; j += blockDim.x) vp[n + j] = u[P.g2g[gbase + j]];
     __syncthreads();
-    local_residual(M, P, n, rowbase, ebase, vp, rb);
+    local_residual<ELAST>(M, P, n, rowbase, ebase, vp, rb);
     double ss = 0.0;
     for (int a = threadIdx.x; a < n; a += blockDim.x) ss += rb[a] * rb[a];
     const double rho_plain = sqrt(block_sum(ss, red));
@@ -940,7 +961,7 @@ k_local_newton(DevMesh M, DevMaps P, DevLocal L, NewtonParams np, const double* 
     if (np.xpred) {
         for (int a = threadIdx.x; a < n; a += blockDim.x) vp[a] = np.xpred[rowbase + a];
         __syncthreads();
-        local_residual(M, P, n, rowbase, ebase, vp, rb);
+        local_residual<ELAST>(M, P, n, rowbase, ebase, vp, rb);
         ss = 0.0;
         for (int a = threadIdx.x; a < n; a += blockDim.x) ss += rb[a] * rb[a];
         const double rg = sqrt(block_sum(ss, red));
@@ -958,7 +979,7 @@ k_local_newton(DevMesh M, DevMaps P, DevLocal L, NewtonParams np, const double* 
             for (int a = threadIdx.x; a < n; a += blockDim.x) vp[a] = u[P.l2g[rowbase + a]];
             __syncthreads();
             if (np.xpred) {
-                local_residual(M, P, n, rowbase, ebase, vp, rb);
+                local_residual<ELAST>(M, P, n, rowbase, ebase, vp, rb);
                 rn = rho_plain;
             }
         }
@@ -975,7 +996,7 @@ k_local_newton(DevMesh M, DevMaps P, DevLocal L, NewtonParams np, const double* 
                 if (dprev <= np.stagnation * xm) break;
             }
             if (its == np.maxit) { status = 1; break; }
-            local_jacobian(M, P, n, rowbase, ebase, vp, L.jval);
+            local_jacobian<ELAST>(M, P, n, rowbase, ebase, vp, L.jval);
             __syncthreads();
             if (local_factor(P, L, np, i, n, rowbase, W, mult, sflag)) { status = 3; break; }
             local_linear_solve<NPL>(P, L, np, i, n, rowbase, rb, r0, dl, red);
@@ -986,7 +1007,7 @@ k_local_newton(DevMesh M, DevMaps P, DevLocal L, NewtonParams np, const double* 
             }
             dprev = block_max(dm, red);
             ++its;
-            local_residual(M, P, n, rowbase, ebase, vp, rb);
+            local_residual<ELAST>(M, P, n, rowbase, ebase, vp, rb);
             ss = 0.0;
             for (int a = threadIdx.x; a < n; a += blockDim.x) ss += rb[a] * rb[a];
             rn = sqrt(block_sum(ss, red));
@@ -996,7 +1017,7 @@ k_local_newton(DevMesh M, DevMaps P, DevLocal L, NewtonParams np, const double* 
     }
     if (status == 0) {
         // J and its LU at x*, in FP64, are kept for the exact tangent
-        local_jacobian(M, P, n, rowbase, ebase, vp, L.jval);
+        local_jacobian<ELAST>(M, P, n, rowbase, ebase, vp, L.jval);
         __syncthreads();
         if (local_factor(P, L, np, i, n, rowbase, W, mult, sflag, true)) status = 3;
     }
@@ -1465,11 +1486,64 @@ __global__ void k_assemble_load(DevMesh M, double* __restrict__ b) {
 // closure C_i of subdomain i (K_i: the coarse functions touching it).
 // ----------------------------------------------------------------------------
 
-// Harmonic extension Phi_I = -A_II^{-1} A_IG Phi_G with A = DF(0) = kappa G
-// (one workgroup per subdomain; setup only).
-template <int NPL>
+// Interface value of function k (local index in K_i) at closure dof ca.
+__device__ __forceinline__ double iface_value(const DevCoarse& C, int ca, int k) {
+    double v = 0.0;
+    if (C.cfun[2 * ca] == k) v += C.cval[2 * ca];
+    if (C.cfun[2 * ca + 1] == k) v += C.cval[2 * ca + 1];
+    return v;
+}
+
+// Element stiffness row of closure dof (pos, c) of part-i element e at the
+// nodal values w (global vector), columns as closure dofs: K row entries
+// kr[b][k] for closure dof ELDOF(b, k).  Diffusion: K_T = kappa[(1+beta m) G
+// + beta s (U + u)/6]; elasticity: the Q1 Neo-Hooke stiffness.
+template <bool ELAST>
+__device__ __forceinline__ void coarse_elem_row(const DevMesh& M, const DevCoarse& C, int cb, int e,
+                                                int pos, int c, const double* __restrict__ w,
+                                                double kr[4][2], int cn[4]) {
+    const int ge = C.ne_gid[e];
+    if (ELAST) {
+        double X[4][2], ue[4][2];
+        nh_coords(M, ge, X);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            cn[v] = C.ne_conn[4 * e + v];
+            ue[v][0] = w ? w[C.cnode[cb + 2 * cn[v]]] : 0.0;
+            ue[v][1] = w ? w[C.cnode[cb + 2 * cn[v] + 1]] : 0.0;
+        }
+        nh_stiff_row(M, X, ue, pos, c, kr);
+    } else {
+        double uu[3];
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            cn[v] = C.ne_conn[3 * e + v];
+            uu[v] = w ? w[C.cnode[cb + cn[v]]] : 0.0;
+        }
+        cn[3] = -1;
+        const double U = uu[0] + uu[1] + uu[2];
+        const double m = (U * U + uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2]) * (1.0 / 12.0);
+        double gr[3];
+        g_row(M.G6 + 6 * (size_t)ge, pos, gr[0], gr[1], gr[2]);
+        const double s = gr[0] * uu[0] + gr[1] * uu[1] + gr[2] * uu[2];
+        const double kap = M.kappa[ge];
+        const double coef = kap * (1.0 + M.beta * m);
+        const double rk = M.beta * kap * s * (1.0 / 6.0);
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            kr[v][0] = coef * gr[v] + rk * (U + uu[v]);
+            kr[v][1] = 0.0;
+        }
+        kr[3][0] = kr[3][1] = 0.0;
+    }
+}
+
+// Harmonic extension Phi_I = -A_II^{-1} A_IG Phi_G with A = DF(0) (one
+// workgroup per subdomain; setup only).
+template <int NPL, bool ELAST>
 __global__ void __launch_bounds__(NLS_BLOCK)
 k_gdsw_extend(DevMesh M, DevCoarse C) {
+    constexpr int D = ELAST ? 2 : 1, NV = ELAST ? 4 : 3;
     extern __shared__ double smem[];
     __shared__ int sflag[20];
     const int i = blockIdx.x;
@@ -1482,14 +1556,14 @@ k_gdsw_extend(DevMesh M, DevCoarse C) {
     // interface and Dirichlet rows of Phi_i
     for (int t = threadIdx.x; t < nc * nk; t += blockDim.x) {
         const int a = t / nk, k = t - a * nk;
-        ph[t] = (C.ctype[cb + a] == 1 && C.ccomp[cb + a] == k) ? 1.0 : 0.0;
+        ph[t] = C.ctype[cb + a] == 1 ? iface_value(C, cb + a, k) : 0.0;
     }
     if (ni == 0 || nk == 0) return;
     double* rhs = smem;
     double* red = rhs + ni;
     double* mult = red + 24;
     double* W = mult + ((kl > 1 ? kl : 1) + 1);
-    // A_II values
+    // A_II values (DF at u = 0)
     for (int r = threadIdx.x; r < ni; r += blockDim.x) {
         const int ca = C.inode[ib + r];
         const int js = C.iptr[ib + r], je = C.iptr[ib + r + 1];
@@ -1497,15 +1571,18 @@ k_gdsw_extend(DevMesh M, DevCoarse C) {
         for (int q = C.cinc_ptr[cb + ca]; q < C.cinc_ptr[cb + ca + 1]; ++q) {
             const int code = C.cinc[q];
             const int e = eb + (code >> 2), pos = code & 3;
-            double gr[3];
-            const int ge = C.ne_gid[e];
-            g_row(M.G6 + 6 * (size_t)ge, pos, gr[0], gr[1], gr[2]);
-            for (int c = 0; c < 3; ++c) {
-                const int cc = C.iidx[cb + C.ne_conn[3 * e + c]];
-                if (cc < 0) continue;
-                for (int s = js; s < je; ++s)
-                    if (C.icol[s] == cc) { C.ival[s] += M.kappa[ge] * gr[c]; break; }
-            }
+            double kr[4][2];
+            int cn[4];
+            coarse_elem_row<ELAST>(M, C, cb, e, pos, ca % D, nullptr, kr, cn);
+#pragma unroll
+            for (int b = 0; b < NV; ++b)
+#pragma unroll
+                for (int kk = 0; kk < D; ++kk) {
+                    const int cc = C.iidx[cb + D * cn[b] + kk];
+                    if (cc < 0) continue;
+                    for (int s = js; s < je; ++s)
+                        if (C.icol[s] == cc) { C.ival[s] += kr[b][kk]; break; }
+                }
         }
     }
     __syncthreads();
@@ -1521,13 +1598,16 @@ k_gdsw_extend(DevMesh M, DevCoarse C) {
             for (int q = C.cinc_ptr[cb + ca]; q < C.cinc_ptr[cb + ca + 1]; ++q) {
                 const int code = C.cinc[q];
                 const int e = eb + (code >> 2), pos = code & 3;
-                double gr[3];
-                const int ge = C.ne_gid[e];
-                g_row(M.G6 + 6 * (size_t)ge, pos, gr[0], gr[1], gr[2]);
-                for (int c = 0; c < 3; ++c) {
-                    const int cn = cb + C.ne_conn[3 * e + c];
-                    if (C.ctype[cn] == 1 && C.ccomp[cn] == k) acc -= M.kappa[ge] * gr[c];
-                }
+                double kr[4][2];
+                int cn[4];
+                coarse_elem_row<ELAST>(M, C, cb, e, pos, ca % D, nullptr, kr, cn);
+#pragma unroll
+                for (int b = 0; b < NV; ++b)
+#pragma unroll
+                    for (int kk = 0; kk < D; ++kk) {
+                        const int cd = cb + D * cn[b] + kk;
+                        if (C.ctype[cd] == 1) acc -= kr[b][kk] * iface_value(C, cd, k);
+                    }
             }
             rhs[r] = acc;
         }
@@ -1542,7 +1622,7 @@ k_gdsw_extend(DevMesh M, DevCoarse C) {
     }
 }
 
-// w = u - Phi c at every node (owner's block).
+// w = u - Phi c at every dof (owner's block).
 __global__ void k_coarse_w(int N, DevCoarse C, const double* __restrict__ u, double* __restrict__ w) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= N) return;
@@ -1554,13 +1634,16 @@ __global__ void k_coarse_w(int N, DevCoarse C, const double* __restrict__ u, dou
     w[g] = u[g] - acc;
 }
 
-// Per subdomain: gblk_i = Phi_i^T q_i where, on closure nodes,
+// Per subdomain: gblk_i = Phi_i^T q_i where, on closure dofs,
 //   mode 0: q = sum over part-i elements of the element residual at w
-//           (so that sum_i gblk_i = Phi^T F(w));
+//           (so that sum_i gblk_i = Phi^T F(w)); nodal loads are counted
+//           by the owner subdomain of their dof;
 //   mode 1: q = sum over part-i elements of K_T(w) v_T
 //           (so that sum_i gblk_i = Phi^T DF(w) v).
+template <bool ELAST>
 __global__ void __launch_bounds__(NLS_BLOCK)
 k_coarse_q(DevMesh M, DevCoarse C, const double* __restrict__ w, const double* __restrict__ v, int mode) {
+    constexpr int D = ELAST ? 2 : 1, NV = ELAST ? 4 : 3;
     extern __shared__ double smem[];
     const int i = blockIdx.x;
     const int cb = C.off_c[i], nc = C.off_c[i + 1] - cb;
@@ -1570,33 +1653,64 @@ k_coarse_q(DevMesh M, DevCoarse C, const double* __restrict__ w, const double* _
     for (int a = threadIdx.x; a < nc; a += blockDim.x) {
         double acc = 0.0;
         if (C.ctype[cb + a] != 2) {
+            const int c = a % D;
+            bool ok = true;
             for (int t = C.cinc_ptr[cb + a]; t < C.cinc_ptr[cb + a + 1]; ++t) {
                 const int code = C.cinc[t];
                 const int e = eb + (code >> 2), pos = code & 3;
                 const int ge = C.ne_gid[e];
-                double uu[3], vv[3];
-                for (int c = 0; c < 3; ++c) {
-                    const int gn = C.cnode[cb + C.ne_conn[3 * e + c]];
-                    uu[c] = w[gn];
-                    vv[c] = mode ? v[gn] : 0.0;
-                }
-                const double U = uu[0] + uu[1] + uu[2];
-                const double m = (U * U + uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2]) * (1.0 / 12.0);
-                double gr[3];
-                g_row(M.G6 + 6 * (size_t)ge, pos, gr[0], gr[1], gr[2]);
-                const double s = gr[0] * uu[0] + gr[1] * uu[1] + gr[2] * uu[2];
-                const double kap = M.kappa[ge];
-                const double coef = kap * (1.0 + M.beta * m);
-                if (mode == 0) {
-                    acc += coef * s - M.eload[3 * ge + pos];
+                if (ELAST) {
+                    if (mode == 0) {
+                        double X[4][2], ue[4][2];
+                        nh_coords(M, ge, X);
+#pragma unroll
+                        for (int vv = 0; vv < 4; ++vv) {
+                            const int cn = C.ne_conn[4 * e + vv];
+                            ue[vv][0] = w[C.cnode[cb + 2 * cn]];
+                            ue[vv][1] = w[C.cnode[cb + 2 * cn + 1]];
+                        }
+                        acc += nh_force(M, X, ue, pos, c, ok);
+                    } else {
+                        double kr[4][2];
+                        int cn[4];
+                        coarse_elem_row<true>(M, C, cb, e, pos, c, w, kr, cn);
+#pragma unroll
+                        for (int b = 0; b < 4; ++b)
+#pragma unroll
+                            for (int kk = 0; kk < 2; ++kk)
+                                acc += kr[b][kk] * v[C.cnode[cb + 2 * cn[b] + kk]];
+                    }
                 } else {
-                    const double rk = M.beta * kap * s * (1.0 / 6.0);
-                    for (int c = 0; c < 3; ++c) acc += (coef * gr[c] + rk * (U + uu[c])) * vv[c];
+                    double uu[3], vv[3];
+                    for (int cc = 0; cc < 3; ++cc) {
+                        const int gn = C.cnode[cb + C.ne_conn[3 * e + cc]];
+                        uu[cc] = w[gn];
+                        vv[cc] = mode ? v[gn] : 0.0;
+                    }
+                    const double U = uu[0] + uu[1] + uu[2];
+                    const double m = (U * U + uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2]) * (1.0 / 12.0);
+                    double gr[3];
+                    g_row(M.G6 + 6 * (size_t)ge, pos, gr[0], gr[1], gr[2]);
+                    const double s = gr[0] * uu[0] + gr[1] * uu[1] + gr[2] * uu[2];
+                    const double kap = M.kappa[ge];
+                    const double coef = kap * (1.0 + M.beta * m);
+                    if (mode == 0) {
+                        acc += coef * s - M.eload[3 * ge + pos];
+                    } else {
+                        const double rk = M.beta * kap * s * (1.0 / 6.0);
+                        for (int cc = 0; cc < 3; ++cc) acc += (coef * gr[cc] + rk * (U + uu[cc])) * vv[cc];
+                    }
                 }
+            }
+            if (ELAST && mode == 0) {
+                const int gd = C.cnode[cb + a];
+                if (C.cown[gd] == i) acc -= M.bload[gd];
+                if (!ok) acc = __builtin_nan("");
             }
         }
         q[a] = acc;
     }
+    (void)NV;
     __syncthreads();
     const double* ph = C.phi + C.off_phi[i];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -1611,6 +1725,7 @@ k_coarse_q(DevMesh M, DevCoarse C, const double* __restrict__ w, const double* _
 // Per subdomain Galerkin block A_i = Phi_i^T K_i(w) Phi_i (K_i: part-i
 // elements).  With with_y, also Y_i = K_i(w)^T Phi_i, so that the coarse
 // term of the tangent, Phi^T DF(u_0) v = sum_i Y_i^T v_i, is a GEMV.
+template <bool ELAST>
 __global__ void __launch_bounds__(NLS_BLOCK)
 k_coarse_galerkin(DevMesh M, DevCoarse C, const double* __restrict__ w, int with_y) {
     const int i = blockIdx.x;
@@ -1619,6 +1734,46 @@ k_coarse_galerkin(DevMesh M, DevCoarse C, const double* __restrict__ w, int with
     const int eb = C.off_ne[i];
     const double* ph = C.phi + C.off_phi[i];
     double* z = C.zbuf + C.off_phi[i];
+    if (ELAST) {
+        // the element stiffness is symmetric, so Y_i = K_i^T Phi_i = Z_i,
+        // with rows on every closure dof (Dirichlet ones included: Phi is
+        // zero there, so they do not change A_i, but Y needs them)
+        double* y = C.ybuf + C.off_phi[i];
+        for (int a = threadIdx.x; a < nc; a += blockDim.x) {
+            double* zr = z + (int64_t)a * nk;
+            for (int l = 0; l < nk; ++l) zr[l] = 0.0;
+            {
+                for (int t = C.cinc_ptr[cb + a]; t < C.cinc_ptr[cb + a + 1]; ++t) {
+                    const int code = C.cinc[t];
+                    const int e = eb + (code >> 2), pos = code & 3;
+                    double kr[4][2];
+                    int cn[4];
+                    coarse_elem_row<true>(M, C, cb, e, pos, a & 1, w, kr, cn);
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+#pragma unroll
+                        for (int kk = 0; kk < 2; ++kk) {
+                            const double* pr = ph + (int64_t)(2 * cn[b] + kk) * nk;
+                            for (int l = 0; l < nk; ++l) zr[l] += kr[b][kk] * pr[l];
+                        }
+                }
+            }
+            if (with_y) {
+                double* yr = y + (int64_t)a * nk;
+                for (int l = 0; l < nk; ++l) yr[l] = zr[l];
+            }
+        }
+        __syncthreads();
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+        for (int kk = wv; kk < nk * nk; kk += nw) {
+            const int k = kk / nk, l = kk - k * nk;
+            double acc = 0.0;
+            for (int a = lane; a < nc; a += 64) acc += ph[(int64_t)a * nk + k] * z[(int64_t)a * nk + l];
+            acc = wave_sum(acc);
+            if (lane == 0) C.ablk[C.off_kk[i] + kk] = acc;
+        }
+        return;
+    }
     for (int a = threadIdx.x; a < nc; a += blockDim.x) {
         double* zr = z + (int64_t)a * nk;
         for (int l = 0; l < nk; ++l) zr[l] = 0.0;
@@ -1947,11 +2102,15 @@ hipError_t launch_local_newton(const DevMesh& M, const DevMaps& P, const DevLoca
                                const NewtonParams& np, const double* u, int nblk, int lds_bytes,
                                int npl, hipStream_t s) {
     hipError_t e;
-#define NLS_LN(NPL)                                                                  \
-    e = set_lds(k_local_newton<NPL>, lds_bytes);                                     \
+#define NLS_LN(NPL, EL)                                                              \
+    e = set_lds(k_local_newton<NPL, EL>, lds_bytes);                                 \
     if (e != hipSuccess) return e;                                                   \
-    k_local_newton<NPL><<<nblk, NLS_BLOCK, lds_bytes, s>>>(M, P, L, np, u);
-    if (npl <= 1) { NLS_LN(1) } else if (npl == 2) { NLS_LN(2) } else { NLS_LN(4) }
+    k_local_newton<NPL, EL><<<nblk, NLS_BLOCK, lds_bytes, s>>>(M, P, L, np, u);
+    if (M.kind == NLS_PROBLEM_NEOHOOKE) {
+        if (npl <= 1) { NLS_LN(1, true) } else if (npl == 2) { NLS_LN(2, true) } else { NLS_LN(4, true) }
+    } else {
+        if (npl <= 1) { NLS_LN(1, false) } else if (npl == 2) { NLS_LN(2, false) } else { NLS_LN(4, false) }
+    }
 #undef NLS_LN
     return hipGetLastError();
 }
@@ -1981,32 +2140,45 @@ hipError_t launch_prolong(const DevMesh& M, const DevMaps& P, const double* T,
 hipError_t launch_gdsw_extend(const DevMesh& M, const DevCoarse& C, int lds_bytes, int npl,
                               hipStream_t s) {
     hipError_t e;
-#define NLS_GE(NPL)                                                                  \
-    e = set_lds(k_gdsw_extend<NPL>, lds_bytes);                                      \
+#define NLS_GE(NPL, EL)                                                              \
+    e = set_lds(k_gdsw_extend<NPL, EL>, lds_bytes);                                  \
     if (e != hipSuccess) return e;                                                   \
-    k_gdsw_extend<NPL><<<C.nsub, NLS_BLOCK, lds_bytes, s>>>(M, C);
-    if (npl <= 1) { NLS_GE(1) } else if (npl == 2) { NLS_GE(2) } else { NLS_GE(4) }
+    k_gdsw_extend<NPL, EL><<<C.nsub, NLS_BLOCK, lds_bytes, s>>>(M, C);
+    if (M.kind == NLS_PROBLEM_NEOHOOKE) {
+        if (npl <= 1) { NLS_GE(1, true) } else if (npl == 2) { NLS_GE(2, true) } else { NLS_GE(4, true) }
+    } else {
+        if (npl <= 1) { NLS_GE(1, false) } else if (npl == 2) { NLS_GE(2, false) } else { NLS_GE(4, false) }
+    }
 #undef NLS_GE
     return hipGetLastError();
 }
 
 hipError_t launch_coarse_w(const DevMesh& M, const DevCoarse& C, const double* u, double* w,
                            hipStream_t s) {
-    k_coarse_w<<<nblocks(M.N), NLS_BLOCK, 0, s>>>(M.N, C, u, w);
+    k_coarse_w<<<nblocks(M.ndof), NLS_BLOCK, 0, s>>>(M.ndof, C, u, w);
     return hipGetLastError();
 }
 
 hipError_t launch_coarse_q(const DevMesh& M, const DevCoarse& C, const double* w, const double* v,
                            int mode, int lds_bytes, hipStream_t s) {
-    hipError_t e = set_lds(k_coarse_q, lds_bytes);
-    if (e != hipSuccess) return e;
-    k_coarse_q<<<C.nsub, NLS_BLOCK, lds_bytes, s>>>(M, C, w, v, mode);
+    if (M.kind == NLS_PROBLEM_NEOHOOKE) {
+        hipError_t e = set_lds(k_coarse_q<true>, lds_bytes);
+        if (e != hipSuccess) return e;
+        k_coarse_q<true><<<C.nsub, NLS_BLOCK, lds_bytes, s>>>(M, C, w, v, mode);
+    } else {
+        hipError_t e = set_lds(k_coarse_q<false>, lds_bytes);
+        if (e != hipSuccess) return e;
+        k_coarse_q<false><<<C.nsub, NLS_BLOCK, lds_bytes, s>>>(M, C, w, v, mode);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_coarse_galerkin(const DevMesh& M, const DevCoarse& C, const double* w,
                                   int with_y, hipStream_t s) {
-    k_coarse_galerkin<<<C.nsub, NLS_BLOCK, 0, s>>>(M, C, w, with_y);
+    if (M.kind == NLS_PROBLEM_NEOHOOKE)
+        k_coarse_galerkin<true><<<C.nsub, NLS_BLOCK, 0, s>>>(M, C, w, with_y);
+    else
+        k_coarse_galerkin<false><<<C.nsub, NLS_BLOCK, 0, s>>>(M, C, w, with_y);
     return hipGetLastError();
 }
 

@@ -76,7 +76,8 @@ struct NewtonParams {
 // GDSW coarse space tables (see HostCoarse) and state.
 struct DevCoarse {
     int n0, nsub;
-    const int *off_c, *cnode, *ctype, *off_k, *klist, *ccomp, *off_ne, *ne_conn, *ne_gid;
+    const int *off_c, *cnode, *ctype, *off_k, *klist, *cfun, *off_ne, *ne_conn, *ne_gid;
+    const double* cval;         // interface values of the functions named in cfun
     const int *cinc_ptr, *cinc, *iidx, *off_ni, *inode, *iptr, *icol, *ikl, *iku;
     const int64_t *off_phi, *off_iu, *off_il, *off_kk;
     const int *perm, *a0ptr, *a0col, *a0src_ptr, *a0src, *gsrc_ptr, *gsrc, *cpos, *cown;

@@ -89,20 +89,26 @@ struct HostMaps {
 };
 
 // GDSW coarse space: symbolic part (host) plus the tables its kernels read.
+// Closure arrays are per dof (d per closure node, node-major): closure dof
+// d*a + c is component c of the a-th closure node.
 struct HostCoarse {
-    int n0 = 0;
+    int n0 = 0;                            // coarse functions
     std::vector<std::vector<int>> comps;   // interface components, by smallest node
     std::vector<int> comp_of;              // N: component id or -1
+    std::vector<int> fun_base, nfun;       // per component: its first function, count
+                                           //   (1 scalar; 2 translations + rotation if
+                                           //   the component has >= 2 nodes, elasticity)
     // per non-overlapping subdomain i
-    std::vector<int> off_c;        // nsub+1: closure nodes (nodes of elements of part i)
-    std::vector<int> cnode;        // packed closure node global ids (ascending)
+    std::vector<int> off_c;        // nsub+1: closure dofs (dofs of nodes of part-i elements)
+    std::vector<int> cnode;        // packed closure dof global ids (ascending)
     std::vector<int> ctype;        // 0 interior, 1 interface, 2 Dirichlet/other
     std::vector<int> off_k;        // nsub+1: coarse functions touching subdomain i
     std::vector<int> klist;        // packed coarse ids (ascending per subdomain)
-    std::vector<int> ccomp;        // packed closure: local position in K_i, or -1
+    std::vector<int> cfun;         // 2 per packed closure dof: local positions in K_i of
+    std::vector<double> cval;      //   the functions nonzero there (or -1), and values
     std::vector<int64_t> off_phi;  // nsub+1: dense |C_i| x |K_i| blocks (row-major)
     std::vector<int> off_ne;       // nsub+1: elements of part i
-    std::vector<int> ne_conn;      // 3 per element, closure-local node ids
+    std::vector<int> ne_conn;      // nv per element, closure-local node positions
     std::vector<int> ne_gid;       // global element ids
     std::vector<int> cinc_ptr;     // packed closure node -> incident part-i elements
     std::vector<int> cinc;         // (element local index << 2) | vertex position
@@ -127,8 +133,8 @@ struct HostCoarse {
     // diagonal blocks of A0 in band order (one per connected component)
     std::vector<int> boff, bkl, bku, rblk;
     std::vector<int64_t> offU, offL, offI;
-    std::vector<int> cpos;         // N: packed closure index in the owner's block
-    std::vector<int> cown;         // N: owner subdomain
+    std::vector<int> cpos;         // N*d: packed closure index in the owner's block
+    std::vector<int> cown;         // N*d: owner subdomain
     int max_k = 0;
 };
 

@@ -289,7 +289,7 @@ static std::vector<int> rcm_order(const std::vector<std::vector<int>>& adj) {
 
 int nls_build_coarse_symbolic(const HostMesh& m, const int* part, int nsub,
                               HostCoarse& out, std::string& err) {
-    const int N = m.N, E = m.E;
+    const int N = m.N, E = m.E, nv = m.nv, dd = m.d;
     HostCoarse& C = out;
     C = HostCoarse();
     // subdomain sets of every node
@@ -299,8 +299,12 @@ int nls_build_coarse_symbolic(const HostMesh& m, const int* part, int nsub,
         std::sort(sset[g].begin(), sset[g].end());
         sset[g].erase(std::unique(sset[g].begin(), sset[g].end()), sset[g].end());
     }
-    std::vector<char> iface(N, 0);
-    for (int g = 0; g < N; ++g) iface[g] = sset[g].size() >= 2 && !m.dflag[g];
+    // a node is a Dirichlet node when any of its dofs is
+    std::vector<char> ndir(N, 0), iface(N, 0);
+    for (int g = 0; g < N; ++g) {
+        for (int c = 0; c < dd; ++c) ndir[g] |= m.dflag[(size_t)dd * g + c];
+        iface[g] = sset[g].size() >= 2 && !ndir[g];
+    }
     // classes keyed by the subdomain set, split into connected components
     std::map<std::vector<int>, int> key_id;
     std::vector<int> cls(N, -1);
@@ -325,8 +329,10 @@ int nls_build_coarse_symbolic(const HostMesh& m, const int* part, int nsub,
             comps[cid].push_back(v);
             for (int k = m.nptr[v]; k < m.nptr[v + 1]; ++k) {
                 int e = m.nel[k];
-                for (int t = 0; t < 3; ++t) {
-                    int w = m.conn[3 * e + t];
+                // neighbours along element edges (consecutive nodes)
+                const int p = vertex_pos(m, e, v);
+                for (int t : {(p + 1) % nv, (p + nv - 1) % nv}) {
+                    int w = m.conn[nv * e + t];
                     if (cls[w] == cls[g] && C.comp_of[w] < 0) {
                         C.comp_of[w] = cid;
                         q.push(w);
@@ -347,7 +353,27 @@ int nls_build_coarse_symbolic(const HostMesh& m, const int* part, int nsub,
     for (int c = 0; c < (int)comps.size(); ++c) C.comps[rank[c]] = comps[c];
     for (int g = 0; g < N; ++g)
         if (C.comp_of[g] >= 0) C.comp_of[g] = rank[C.comp_of[g]];
-    C.n0 = (int)C.comps.size();
+    // coarse functions: scalar 1 per component; elasticity the translations
+    // and, on components of >= 2 nodes, the rotation about the centroid
+    const int ncomps = (int)C.comps.size();
+    C.fun_base.assign(ncomps, 0);
+    C.nfun.assign(ncomps, 0);
+    std::vector<double> cxc(ncomps, 0.0), cyc(ncomps, 0.0);
+    int nfuns = 0;
+    for (int c = 0; c < ncomps; ++c) {
+        C.fun_base[c] = nfuns;
+        C.nfun[c] = dd == 1 ? 1 : (C.comps[c].size() >= 2 ? 3 : 2);
+        nfuns += C.nfun[c];
+        if (C.nfun[c] == 3) {  // rotation about the component's centroid
+            for (int g : C.comps[c]) {
+                cxc[c] += m.xy[2 * g];
+                cyc[c] += m.xy[2 * g + 1];
+            }
+            cxc[c] /= (double)C.comps[c].size();
+            cyc[c] /= (double)C.comps[c].size();
+        }
+    }
+    C.n0 = nfuns;
 
     std::vector<std::vector<int>> elems_of(nsub);
     for (int e = 0; e < E; ++e) elems_of[part[e]].push_back(e);
@@ -366,38 +392,57 @@ int nls_build_coarse_symbolic(const HostMesh& m, const int* part, int nsub,
     for (int i = 0; i < nsub; ++i) {
         std::vector<int> nodes;
         for (int e : elems_of[i])
-            for (int v = 0; v < 3; ++v) nodes.push_back(m.conn[3 * e + v]);
+            for (int v = 0; v < nv; ++v) nodes.push_back(m.conn[nv * e + v]);
         std::sort(nodes.begin(), nodes.end());
         nodes.erase(std::unique(nodes.begin(), nodes.end()), nodes.end());
         for (int a = 0; a < (int)nodes.size(); ++a) cl[nodes[a]] = a;
         for (int k = 0; k < (int)elems_of[i].size(); ++k) el[elems_of[i][k]] = k;
         std::vector<int> K;
         for (int g : nodes)
-            if (iface[g]) K.push_back(C.comp_of[g]);
+            if (iface[g]) {
+                const int c = C.comp_of[g];
+                for (int f = 0; f < C.nfun[c]; ++f) K.push_back(C.fun_base[c] + f);
+            }
         std::sort(K.begin(), K.end());
         K.erase(std::unique(K.begin(), K.end()), K.end());
+        auto kpos = [&](int f) { return (int)(std::lower_bound(K.begin(), K.end(), f) - K.begin()); };
         C.max_k = std::max(C.max_k, (int)K.size());
         int ni = 0;
-        std::vector<int> inter;
+        std::vector<int> inter;   // closure dof index of each interior row
         for (int a = 0; a < (int)nodes.size(); ++a) {
-            int g = nodes[a];
-            int t = m.dflag[g] ? 2 : (iface[g] ? 1 : (sset[g].size() == 1 ? 0 : 2));
-            C.cnode.push_back(g);
-            C.ctype.push_back(t);
-            int kp = -1;
-            if (t == 1)
-                kp = (int)(std::lower_bound(K.begin(), K.end(), C.comp_of[g]) - K.begin());
-            C.ccomp.push_back(kp);
-            C.iidx.push_back(t == 0 ? ni : -1);
-            if (t == 0) { inter.push_back(a); ++ni; }
+            const int g = nodes[a];
+            const int t = ndir[g] ? 2 : (iface[g] ? 1 : (sset[g].size() == 1 ? 0 : 2));
+            std::vector<int> ci;
             for (int k = m.nptr[g]; k < m.nptr[g + 1]; ++k) {
                 int e = m.nel[k];
-                if (part[e] == i) C.cinc.push_back((el[e] << 2) | vertex_pos(m, e, g));
+                if (part[e] == i) ci.push_back((el[e] << 2) | vertex_pos(m, e, g));
             }
-            C.cinc_ptr.push_back((int)C.cinc.size());
+            for (int c = 0; c < dd; ++c) {
+                C.cnode.push_back(dd * g + c);
+                C.ctype.push_back(t);
+                int f0 = -1, f1 = -1;
+                double v0 = 0.0, v1 = 0.0;
+                if (t == 1) {
+                    const int cp = C.comp_of[g], fb = C.fun_base[cp];
+                    f0 = kpos(fb + (dd == 1 ? 0 : c));
+                    v0 = 1.0;
+                    if (C.nfun[cp] == 3) {
+                        f1 = kpos(fb + 2);
+                        v1 = c == 0 ? -(m.xy[2 * g + 1] - cyc[cp]) : (m.xy[2 * g] - cxc[cp]);
+                    }
+                }
+                C.cfun.push_back(f0);
+                C.cfun.push_back(f1);
+                C.cval.push_back(v0);
+                C.cval.push_back(v1);
+                C.iidx.push_back(t == 0 ? ni : -1);
+                if (t == 0) { inter.push_back(dd * a + c); ++ni; }
+                C.cinc.insert(C.cinc.end(), ci.begin(), ci.end());
+                C.cinc_ptr.push_back((int)C.cinc.size());
+            }
         }
         for (int e : elems_of[i]) {
-            for (int v = 0; v < 3; ++v) C.ne_conn.push_back(cl[m.conn[3 * e + v]]);
+            for (int v = 0; v < nv; ++v) C.ne_conn.push_back(cl[m.conn[nv * e + v]]);
             C.ne_gid.push_back(e);
         }
         // interior CSR and band of A_II
@@ -405,14 +450,15 @@ int nls_build_coarse_symbolic(const HostMesh& m, const int* part, int nsub,
         const int cbase = C.off_c.back();
         std::vector<int> cols;
         for (int r = 0; r < ni; ++r) {
-            int g = nodes[inter[r]];
+            const int g = nodes[inter[r] / dd];
             cols.clear();
             for (int k = m.nptr[g]; k < m.nptr[g + 1]; ++k) {
                 int e = m.nel[k];
-                for (int v = 0; v < 3; ++v) {
-                    int c = C.iidx[cbase + cl[m.conn[3 * e + v]]];
-                    if (c >= 0) cols.push_back(c);
-                }
+                for (int v = 0; v < nv; ++v)
+                    for (int c = 0; c < dd; ++c) {
+                        int col = C.iidx[cbase + dd * cl[m.conn[nv * e + v]] + c];
+                        if (col >= 0) cols.push_back(col);
+                    }
             }
             std::sort(cols.begin(), cols.end());
             cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
@@ -434,7 +480,7 @@ int nls_build_coarse_symbolic(const HostMesh& m, const int* part, int nsub,
         C.klist.insert(C.klist.end(), K.begin(), K.end());
         C.off_c.push_back((int)C.cnode.size());
         C.off_k.push_back((int)C.klist.size());
-        C.off_phi.push_back(C.off_phi.back() + (int64_t)nodes.size() * K.size());
+        C.off_phi.push_back(C.off_phi.back() + (int64_t)nodes.size() * dd * K.size());
         C.off_ne.push_back((int)C.ne_gid.size());
         C.off_ni.push_back((int)C.inode.size());
         C.off_kk.push_back(C.off_kk.back() + (int64_t)K.size() * K.size());
@@ -444,16 +490,19 @@ int nls_build_coarse_symbolic(const HostMesh& m, const int* part, int nsub,
     C.iu_total = C.off_iu.back();
     C.il_total = C.off_il.back();
 
-    // owner closure positions for prolongation of coarse vectors
-    C.cpos.assign(N, -1);
-    C.cown.assign(N, -1);
+    // owner closure positions for prolongation of coarse vectors (per dof)
+    C.cpos.assign((size_t)N * dd, -1);
+    C.cown.assign((size_t)N * dd, -1);
     for (int g = 0; g < N; ++g) {
         int o = -1;
         for (int k = m.nptr[g]; k < m.nptr[g + 1]; ++k) o = std::max(o, part[m.nel[k]]);
-        auto b = C.cnode.begin() + C.off_c[o], en = C.cnode.begin() + C.off_c[o + 1];
-        auto it = std::lower_bound(b, en, g);
-        C.cown[g] = o;
-        C.cpos[g] = (int)(it - C.cnode.begin());
+        for (int c = 0; c < dd; ++c) {
+            const int gd = dd * g + c;
+            auto b = C.cnode.begin() + C.off_c[o], en = C.cnode.begin() + C.off_c[o + 1];
+            auto it = std::lower_bound(b, en, gd);
+            C.cown[gd] = o;
+            C.cpos[gd] = (int)(it - C.cnode.begin());
+        }
     }
 
     // Galerkin pattern, banded ordering and deterministic source lists

@@ -87,3 +87,37 @@ def test_solve_one_level(kw):
     uu, st, rc = _solver(case, coupling="one_level").solve()
     assert rc == 0 and st["converged"] and st["outer_its"] == st_ref["outer"]
     assert np.linalg.norm(_np(uu) - u_ref) <= 1e-10 * np.linalg.norm(u_ref)
+
+
+@pytest.mark.parametrize("kw", CASES[:2])
+def test_coarse_basis_rigid_modes(kw):
+    """GDSW basis with translations and rotations: equal to the oracle's."""
+    case = synth.small_elasticity_case(two_level=True, **kw)
+    S = Schwarz(NHProblem(case), "additive")
+    s = _solver(case, coupling="additive")
+    _close(s.coarse_basis().toarray(), S.Phi.toarray(), 1e-12)
+
+
+@pytest.mark.parametrize("kw", CASES)
+def test_precond_residual_and_tangent_additive(kw):
+    case = synth.small_elasticity_case(two_level=True, **kw)
+    P = NHProblem(case)
+    S = Schwarz(P, "additive")
+    s = _solver(case, coupling="additive")
+    u = _probe(P, 4)
+    _close(_np(s.precond_residual(u)), S.evaluate(u), 1e-10)
+    rng = np.random.default_rng(5)
+    for _ in range(2):
+        v = rng.normal(size=P.ndof)
+        _close(_np(s.tangent(v)), S.tangent(v), 1e-10)
+
+
+@pytest.mark.parametrize("kw", CASES[:2])
+def test_solve_additive(kw):
+    case = synth.small_elasticity_case(two_level=True, **kw)
+    P = NHProblem(case)
+    S = Schwarz(P, "additive")
+    u_ref, st_ref = S.solve()
+    uu, st, rc = _solver(case, coupling="additive").solve()
+    assert rc == 0 and st["converged"] and st["outer_its"] == st_ref["outer"]
+    assert np.linalg.norm(_np(uu) - u_ref) <= 1e-10 * np.linalg.norm(u_ref)
