@@ -228,6 +228,17 @@ int nls_set_load(nls_handle* h, const double* elem_load);
    st may be NULL.  Returns NLS_OK, NLS_ENOCONV, or an error. */
 int nls_solve(nls_handle* h, double* u, int u_on_device, nls_stats* st);
 
+/* Load stepping (continuation, Section 3 of the paper: the beam load is
+   increased in steps): the external load is set to s / n_steps of its
+   full value (nodal forces, or the load samples of the diffusion problem)
+   for s = 1..n_steps, and each step runs nls_solve from the previous
+   step's solution.  u: initial iterate in, last solution out (device
+   pointer if u_on_device).  st: n_steps records or NULL.  Stops at the
+   first step that does not return NLS_OK and returns its code; the full
+   load is in place again on return. */
+int nls_solve_load_steps(nls_handle* h, double* u, int u_on_device, int n_steps,
+                         nls_stats* st);
+
 /* ---- hooks at the internal boundaries (device pointers) --------------- */
 
 /* F(u) (eq. (3)), n_nodes values. */

@@ -611,6 +611,8 @@ extern "C" int nls_build_coarse(nls_handle* h, int kind) {
 // ||Phi^T b||_inf are recomputed.
 int guess_refresh_load(nls_handle* h);
 
+static int upload_nodal_load(nls_handle* h, const double* f);
+
 extern "C" int nls_set_nodal_load(nls_handle* h, const double* f) {
     if (!h || !f) return NLS_EINVAL;
     if (h->kind != NLS_PROBLEM_NEOHOOKE) return fail(h, NLS_EINVAL, "the problem's load is not nodal");
@@ -619,8 +621,15 @@ extern "C" int nls_set_nodal_load(nls_handle* h, const double* f) {
         if (!std::isfinite(f[k])) return fail(h, NLS_EINVAL, "nodal forces must be finite");
     h->fnode_h.assign(f, f + nd);
     if (!h->have_part) return NLS_OK;  // uploaded with the partition
+    return upload_nodal_load(h, h->fnode_h.data());
+}
+
+// Device copy of nodal forces f (Dirichlet entries zeroed) and the load
+// scales of the stopping rules.
+static int upload_nodal_load(nls_handle* h, const double* f) {
+    const int nd = h->mesh.ndof();
     HIPCHK(hipSetDevice(h->opt.device));
-    std::vector<double> fz(h->fnode_h);
+    std::vector<double> fz(f, f + nd);
     for (int k = 0; k < nd; ++k)
         if (h->mesh.dflag[k]) fz[k] = 0.0;
     DevMesh& d = h->dm;
@@ -1258,6 +1267,33 @@ extern "C" int nls_solve(nls_handle* h, double* u, int u_on_device, nls_stats* s
         if (!std::isfinite(S->res_final)) return finish(fail(h, NLS_ENAN, "F_x is not finite"));
     }
     return finish(S->converged ? NLS_OK : NLS_ENOCONV);
+}
+
+// Load stepping (continuation): the load at s / n_steps of its full value,
+// s = 1..n_steps, each outer solve starting from the previous solution.
+extern "C" int nls_solve_load_steps(nls_handle* h, double* u, int u_on_device, int n_steps,
+                                    nls_stats* st) {
+    if (!h || !u || n_steps < 1) return NLS_EINVAL;
+    if (!h->have_part) return fail(h, NLS_ESTATE, "nls_set_partition first");
+    const bool nodal = h->kind == NLS_PROBLEM_NEOHOOKE;
+    std::vector<double> full;
+    const bool had_samples = !h->fmid_h.empty();
+    if (nodal) full = h->fnode_h;
+    else full = had_samples ? h->fmid_h : std::vector<double>(3 * (size_t)h->mesh.E, 1.0);
+    std::vector<double> scaled(full.size());
+    int rc = NLS_OK;
+    for (int k = 1; k <= n_steps; ++k) {
+        const double sc = (double)k / (double)n_steps;
+        for (size_t j = 0; j < full.size(); ++j) scaled[j] = sc * full[j];
+        rc = nodal ? upload_nodal_load(h, scaled.data()) : nls_set_load(h, scaled.data());
+        if (rc) break;
+        rc = nls_solve(h, u, u_on_device, st ? st + (k - 1) : nullptr);
+        if (rc) break;
+    }
+    // the full load again (the stored problem is unchanged)
+    int r2 = nodal ? upload_nodal_load(h, full.data())
+                   : nls_set_load(h, had_samples ? full.data() : nullptr);
+    return rc ? rc : r2;
 }
 
 // ------------------------------------------------------------------- hooks

@@ -56,7 +56,7 @@ SYMBOLS = (
     "nls_guess_get_model", "nls_guess_enable", "nls_guess_capture",
     "nls_guess_captured", "nls_guess_features", "nls_guess_lift",
     "nls_guess_predict", "nls_guess_loss_grad", "nls_guess_train",
-    "nls_get_tuning", "nls_set_nodal_load",
+    "nls_get_tuning", "nls_set_nodal_load", "nls_solve_load_steps",
 )
 
 GUESS_PARAMS = 279552
@@ -154,6 +154,8 @@ def load() -> ctypes.CDLL:
         "nls_last_error": ([P], ctypes.c_char_p),
         "nls_set_load": ([P, P], ctypes.c_int),
         "nls_set_nodal_load": ([P, P], ctypes.c_int),
+        "nls_solve_load_steps": ([P, P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(Stats)],
+                                 ctypes.c_int),
         "nls_get_tuning": ([P, P, P, P, P, P, P], ctypes.c_int),
         "nls_guess_set_model": ([P, P, i64, P], ctypes.c_int),
         "nls_guess_get_model": ([P, P, P], ctypes.c_int),
@@ -342,6 +344,16 @@ class Solver:
         st = Stats()
         rc = self._check(self.lib.nls_solve(self.h, self._vp(u), 1, ctypes.byref(st)))
         return u, st.as_dict(), rc
+
+    def solve_load_steps(self, n_steps, u0=None):
+        """Load stepping from u0 (default 0) in n_steps equal increments.
+        Returns (u tensor, per-step stats, rc)."""
+        t = self.torch
+        u = t.zeros(self.N, dtype=t.float64, device=self.device) if u0 is None \
+            else self._dev(u0).clone()
+        st = (Stats * int(n_steps))()
+        rc = self._check(self.lib.nls_solve_load_steps(self.h, self._vp(u), 1, int(n_steps), st))
+        return u, [s.as_dict() for s in st], rc
 
     def solve_(self, u):
         """Outer Newton in place on a float64 device tensor u; returns stats."""
