@@ -59,7 +59,7 @@ class Schwarz:
 
     def __init__(self, problem: P1Problem, coupling: str = "one_level",
                  inner_rtol=1e-12, inner_eta=1e-10, inner_maxit=30,
-                 stagnation=1e-14):
+                 stagnation=1e-14, coarse="gdsw"):
         if coupling not in ("one_level", "additive"):
             raise ValueError(coupling)
         self.P = problem
@@ -72,6 +72,9 @@ class Schwarz:
         self.b_inf = float(np.max(np.abs(problem.b))) if problem.ndof else 0.0
         self._build_maps()
         self.Phi = None
+        if coarse not in ("gdsw", "rgdsw"):
+            raise ValueError(coarse)
+        self.coarse = coarse
         if coupling == "additive":
             self._build_gdsw()
         self.state = None
@@ -311,14 +314,17 @@ class Schwarz:
         comps.sort(key=lambda t: int(t[0].min()))
         rows, cols, vals = [], [], []
         n0 = 0
-        for nodes, _ in comps:
-            cd = (dd * nodes[:, None] + np.arange(dd)).ravel()
-            for vec in P.nullspace(nodes):
-                nz = vec != 0.0
-                rows.append(cd[nz])
-                cols.append(np.full(int(nz.sum()), n0))
-                vals.append(vec[nz])
-                n0 += 1
+        if self.coarse == "gdsw":
+            for nodes, _ in comps:
+                cd = (dd * nodes[:, None] + np.arange(dd)).ravel()
+                for vec in P.nullspace(nodes):
+                    nz = vec != 0.0
+                    rows.append(cd[nz])
+                    cols.append(np.full(int(nz.sum()), n0))
+                    vals.append(vec[nz])
+                    n0 += 1
+        else:
+            n0 = self._rgdsw_values(comps, NS, adj, rows, cols, vals)
         rows = np.concatenate(rows) if rows else np.zeros(0, int)
         cols = np.concatenate(cols) if cols else np.zeros(0, int)
         vals = np.concatenate(vals) if vals else np.zeros(0)
@@ -353,6 +359,72 @@ class Schwarz:
         self.PhiT = self.Phi.T.tocsr()
         self.n0 = n0
         self.phib_inf = float(np.max(np.abs(self.PhiT @ P.b))) if n0 else 0.0
+
+    def _rgdsw_values(self, comps, NS, adj, rows, cols, vals):
+        """Interface values of the RGDSW coarse space, option 2.2 with the
+        paper's modification (Section 2).  Reading: the coarse nodes are the
+        vertices (components shared by >= 3 subdomains); an edge component
+        (2 subdomains) takes its values from its ancestor vertices (those
+        whose subdomain set contains the edge's) with inverse Euclidean
+        distance weights w_c(x) = d_c(x)^-1 / sum d(x)^-1, where a Dirichlet
+        node ending the edge (adjacent to it, in both subdomains) enters the
+        sum as an ancestor with value 0; an edge without ancestor vertices is
+        a coarse node of its own (value 1).  Scalar problems: one function
+        per coarse node; elasticity: translations and the rotation about the
+        coarse node's position (w_c times the rigid mode)."""
+        P = self.P
+        dd = P.d
+        xy = P.xy
+        sets = [frozenset(NS.indices[NS.indptr[c[0][0]]:NS.indptr[c[0][0] + 1]].tolist())
+                for c in comps]
+        vert = [k for k, (nodes, ns) in enumerate(comps) if ns >= 3]
+        anc = {}
+        for k, (nodes, ns) in enumerate(comps):
+            if ns >= 3:
+                continue
+            anc[k] = [v for v in vert if sets[v] >= sets[k]]
+        # coarse nodes in canonical order (smallest node), with positions
+        cnodes = [k for k in range(len(comps)) if comps[k][1] >= 3 or not anc[k]]
+        cnodes.sort(key=lambda k: int(comps[k][0].min()))
+        pos = {k: xy[comps[k][0]].mean(axis=0) for k in cnodes}
+        nfun = 1 if dd == 1 else 3
+        base = {k: nfun * r for r, k in enumerate(cnodes)}
+
+        def put(node, fb, w, center):
+            x, y = xy[node]
+            if dd == 1:
+                rows.append(np.array([node]))
+                cols.append(np.array([fb]))
+                vals.append(np.array([w]))
+                return
+            r = [-(y - center[1]), x - center[0]]
+            for c in range(2):
+                rows.append(np.array([2 * node + c, 2 * node + c]))
+                cols.append(np.array([fb + c, fb + 2]))
+                vals.append(np.array([w, w * r[c]]))
+
+        for k in cnodes:
+            for g in comps[k][0]:
+                put(g, base[k], 1.0, pos[k])
+        node_dir = self.node_dir
+        for k, (nodes, ns) in enumerate(comps):
+            if ns >= 3 or not anc[k]:
+                continue
+            # Dirichlet nodes ending this edge
+            dends = set()
+            for g in nodes:
+                for w_ in adj.indices[adj.indptr[g]:adj.indptr[g + 1]]:
+                    if node_dir[w_]:
+                        sw = frozenset(NS.indices[NS.indptr[w_]:NS.indptr[w_ + 1]].tolist())
+                        if sw >= sets[k]:
+                            dends.add(int(w_))
+            for g in nodes:
+                inv = {v: 1.0 / np.linalg.norm(xy[g] - pos[v]) for v in anc[k]}
+                den = sum(inv.values()) + sum(1.0 / np.linalg.norm(xy[g] - xy[dn]) for dn in dends)
+                for v in anc[k]:
+                    put(g, base[v], inv[v] / den, pos[v])
+        self.coarse_nodes = cnodes
+        return nfun * len(cnodes)
 
     def refresh_load(self):
         """Recompute the load scales of the stopping rules after the

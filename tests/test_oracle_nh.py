@@ -223,3 +223,32 @@ def test_load_stepping_reaches_continuation_solution():
     assert np.linalg.norm(u - ug) <= 1e-10 * np.linalg.norm(ug)
     tip = u[2 * (len(P.xy) - 1) + 1]
     assert tip < -0.01                      # the free end moves down
+
+
+def test_rgdsw_elasticity_reproduces_rigid_modes_away_from_clamp():
+    case = synth.small_elasticity_case(nx=16, ny=12, boxes=(4, 3), overlap=1)
+    P = NHProblem(case)
+    S = Schwarz(P, "additive", coarse="rgdsw")
+    assert S.n0 == 6 * 3          # six interior crosspoints, 3 functions each
+    checked = 0
+    x, y = P.xy[:, 0], P.xy[:, 1]
+    modes = {"tx": np.ravel(np.stack([np.ones_like(x), 0 * x], 1)),
+             "ty": np.ravel(np.stack([0 * x, np.ones_like(x)], 1)),
+             "rot": np.ravel(np.stack([-y, x], 1))}
+    for name, m in modes.items():
+        c = []
+        for k in S.coarse_nodes:
+            cx, cy = P.xy[S.components[k][0]].mean(axis=0)
+            c.extend({"tx": (1.0, 0.0, 0.0), "ty": (0.0, 1.0, 0.0), "rot": (-cy, cx, 1.0)}[name])
+        phi = S.Phi @ np.array(c)
+        for i in range(S.n_sub):
+            el = np.nonzero(S.part == i)[0]
+            nodes = np.unique(P.conn[el])
+            # subdomains whose closure touches no boundary edge of an interface
+            if np.any(np.isclose(P.xy[nodes, 0], 0.0)) or np.any(np.isclose(P.xy[nodes, 0], 2.0)) \
+                    or np.any(np.isclose(P.xy[nodes, 1], 0.0)) or np.any(np.isclose(P.xy[nodes, 1], 1.0)):
+                continue
+            dofs = (2 * nodes[:, None] + np.arange(2)).ravel()
+            np.testing.assert_allclose(phi[dofs], m[dofs], atol=1e-12)
+            checked += 1
+    assert checked >= 2 * 3

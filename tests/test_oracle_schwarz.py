@@ -192,3 +192,52 @@ def test_local_newton_quadratic():
             assert b <= 10.0 * a * a / max(h[0], 1e-300) * 1e3 or b < 1e-3 * a
     # terminal iterations contract at least quadratically-fast
     assert h[-1] <= 1e-12 * h[0] + 1e-14
+
+
+# ------------------------------------------------------------------ RGDSW
+def test_rgdsw_size_weights_and_constants():
+    """RGDSW option 2.2: one function per interior crosspoint on box
+    partitions; on an edge between two ancestor vertices the inverse-distance
+    weights are the linear interpolants (they sum to one); the basis
+    reproduces constants on subdomains away from the boundary."""
+    case = synth.small_case(n=24, boxes=4, overlap=2, two_level=True)
+    P = P1Problem(case)
+    S = Schwarz(P, "additive", coarse="rgdsw")
+    assert S.n0 == 9
+    Phi = S.Phi.toarray()
+    tot = Phi.sum(axis=1)
+    # interface node halfway between two crosspoints (x = 0.25, y = 0.375)
+    xy = P.xy
+    g = int(np.nonzero(np.isclose(xy[:, 0], 0.25) & np.isclose(xy[:, 1], 0.375))[0][0])
+    w = Phi[g][Phi[g] != 0]
+    assert len(w) == 2 and np.allclose(w, 0.5, atol=1e-14)
+    g2 = int(np.nonzero(np.isclose(xy[:, 0], 0.25) & np.isclose(xy[:, 1], 0.25 + 1 / 24))[0][0])
+    w2 = np.sort(Phi[g2][Phi[g2] != 0])
+    np.testing.assert_allclose(w2, [1 / 6, 5 / 6], atol=1e-14)
+    # floating subdomains: the closure of interior boxes
+    for i in (5, 6, 9, 10):
+        el = np.nonzero(S.part == i)[0]
+        nodes = np.unique(P.conn[el])
+        np.testing.assert_allclose(tot[nodes], 1.0, atol=1e-12)
+    # an edge ending at the Dirichlet boundary: weights decay towards it
+    g3 = int(np.nonzero(np.isclose(xy[:, 0], 0.25) & np.isclose(xy[:, 1], 1 / 24))[0][0])
+    assert 0.0 < tot[g3] < 0.2
+
+
+def test_rgdsw_fixed_point_and_linear_coarse():
+    case = synth.small_case(n=12, boxes=3, overlap=1, two_level=True, forcing_seed=4)
+    P = P1Problem(case)
+    ug, _ = global_newton(P)
+    S = Schwarz(P, "additive", coarse="rgdsw")
+    u, st = S.solve(rtol=1e-12, gmres_rtol=1e-12)
+    assert st["converged"]
+    assert np.linalg.norm(u - ug) <= 1e-10 * np.linalg.norm(ug)
+    lin = synth.small_case(n=12, boxes=3, overlap=1, two_level=True, beta=0.0, forcing_seed=4)
+    PL = P1Problem(lin)
+    SL = Schwarz(PL, "additive", coarse="rgdsw")
+    uu = np.random.default_rng(1).normal(size=PL.N)
+    A = PL.jacobian(uu)
+    co = SL.coarse_solve(uu)
+    A0 = (SL.PhiT @ (A @ SL.Phi)).toarray()
+    ref = np.linalg.solve(A0, SL.PhiT @ PL.residual(uu))
+    np.testing.assert_allclose(co["c"], ref, rtol=1e-12, atol=1e-13)
