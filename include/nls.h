@@ -62,6 +62,9 @@ extern "C" {
 
 #define NLS_COARSE_NONE   0
 #define NLS_COARSE_GDSW   1   /* vertex + edge components, harmonic extension */
+#define NLS_COARSE_RGDSW  2   /* reduced: one set of functions per crosspoint,
+                                 option 2.2 (inverse-distance weights on edges;
+                                 Dirichlet edge ends weighted the same way) */
 
 /* ---- options --------------------------------------------------------- */
 typedef struct nls_options {
@@ -200,9 +203,17 @@ int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* elem_part,
                       int32_t overlap);
 
 /* Build the coarse space P_0 = Phi (Section 2; GDSW family).  kind
-   NLS_COARSE_GDSW: one function per connected interface component
-   (vertices: nodes of >= 3 subdomains, edges: 2), equal to 1 on it,
-   extended harmonically with DF(0) into every subdomain interior.
+   NLS_COARSE_GDSW: for every connected interface component (vertices:
+   nodes of >= 3 subdomains, edges: 2) the null-space modes restricted to
+   it (scalar: 1; elasticity: two translations, and the rotation about the
+   component's centroid when it has >= 2 nodes).  NLS_COARSE_RGDSW
+   (Section 2: the paper's choice, option 2.2 with its modification): one
+   set of modes per crosspoint; an edge node takes inverse Euclidean
+   distance weights of the crosspoints whose subdomain sets contain the
+   edge's, a Dirichlet node ending the edge counting as one more ancestor
+   of value 0; an edge without such crosspoints keeps its own modes.
+   Interface values are extended harmonically with DF(0) into every
+   subdomain interior.
    Errors: NLS_ESTATE (no partition), NLS_ESINGULAR. */
 int nls_build_coarse(nls_handle* h, int kind);
 

@@ -476,9 +476,10 @@ extern "C" int nls_build_coarse(nls_handle* h, int kind) {
     h->have_coarse = false;
     h->have_state = false;
     if (kind == NLS_COARSE_NONE) return NLS_OK;
-    if (kind != NLS_COARSE_GDSW) return fail(h, NLS_EINVAL, "unknown coarse space kind");
+    if (kind != NLS_COARSE_GDSW && kind != NLS_COARSE_RGDSW)
+        return fail(h, NLS_EINVAL, "unknown coarse space kind");
     std::string err;
-    int rc = nls_build_coarse_symbolic(h->mesh, h->part_h.data(), h->maps.nsub, h->co, err);
+    int rc = nls_build_coarse_symbolic(h->mesh, h->part_h.data(), h->maps.nsub, kind, h->co, err);
     if (rc) return fail(h, rc, err);
     const HostCoarse& C = h->co;
     if (C.n0 == 0) return NLS_OK;  // a single subdomain has no interface

@@ -1489,8 +1489,9 @@ __global__ void k_assemble_load(DevMesh M, double* __restrict__ b) {
 // Interface value of function k (local index in K_i) at closure dof ca.
 __device__ __forceinline__ double iface_value(const DevCoarse& C, int ca, int k) {
     double v = 0.0;
-    if (C.cfun[2 * ca] == k) v += C.cval[2 * ca];
-    if (C.cfun[2 * ca + 1] == k) v += C.cval[2 * ca + 1];
+#pragma unroll
+    for (int q = 0; q < NLS_CFUN; ++q)
+        if (C.cfun[NLS_CFUN * ca + q] == k) v += C.cval[NLS_CFUN * ca + q];
     return v;
 }
 

@@ -73,11 +73,17 @@ struct NewtonParams {
     int lu_variant;             // 0 by band width, 1 blocked NB=16, 2 NB=8, 3 unblocked
 };
 
+// Most coarse functions nonzero at one interface dof (see HostCoarse).
+#ifndef NLS_CFUN
+#define NLS_CFUN 4
+#endif
+
 // GDSW coarse space tables (see HostCoarse) and state.
 struct DevCoarse {
     int n0, nsub;
     const int *off_c, *cnode, *ctype, *off_k, *klist, *cfun, *off_ne, *ne_conn, *ne_gid;
     const double* cval;         // interface values of the functions named in cfun
+                                //   (NLS_CFUN pairs per closure dof)
     const int *cinc_ptr, *cinc, *iidx, *off_ni, *inode, *iptr, *icol, *ikl, *iku;
     const int64_t *off_phi, *off_iu, *off_il, *off_kk;
     const int *perm, *a0ptr, *a0col, *a0src_ptr, *a0src, *gsrc_ptr, *gsrc, *cpos, *cown;

@@ -104,8 +104,8 @@ struct HostCoarse {
     std::vector<int> ctype;        // 0 interior, 1 interface, 2 Dirichlet/other
     std::vector<int> off_k;        // nsub+1: coarse functions touching subdomain i
     std::vector<int> klist;        // packed coarse ids (ascending per subdomain)
-    std::vector<int> cfun;         // 2 per packed closure dof: local positions in K_i of
-    std::vector<double> cval;      //   the functions nonzero there (or -1), and values
+    std::vector<int> cfun;         // NLS_CFUN per packed closure dof: local positions in
+    std::vector<double> cval;      //   K_i of the functions nonzero there (or -1), values
     std::vector<int64_t> off_phi;  // nsub+1: dense |C_i| x |K_i| blocks (row-major)
     std::vector<int> off_ne;       // nsub+1: elements of part i
     std::vector<int> ne_conn;      // nv per element, closure-local node positions
@@ -150,11 +150,17 @@ struct HostGuess {
     std::vector<int> sloc;         // nsub x 256 x 3
 };
 
+// Most coarse functions nonzero at one interface dof: RGDSW elasticity on an
+// edge between two crosspoints has a translation and a rotation of each.
+#ifndef NLS_CFUN
+#define NLS_CFUN 4
+#endif
+
 // Setup entry points (setup.cpp).  Return 0 or an NLS_* error with err set.
 int nls_build_node_incidence(HostMesh& m, std::string& err);
 int nls_build_maps(const HostMesh& m, const int* part, int nsub, int overlap,
                    HostMaps& out, std::string& err);
-int nls_build_coarse_symbolic(const HostMesh& m, const int* part, int nsub,
+int nls_build_coarse_symbolic(const HostMesh& m, const int* part, int nsub, int kind,
                               HostCoarse& out, std::string& err);
 int nls_build_guess_tables(const HostMesh& m, const HostMaps& maps, HostGuess& out,
                            std::string& err);

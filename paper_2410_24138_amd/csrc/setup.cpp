@@ -287,7 +287,7 @@ static std::vector<int> rcm_order(const std::vector<std::vector<int>>& adj) {
     return order;  // order[p] = vertex at position p
 }
 
-int nls_build_coarse_symbolic(const HostMesh& m, const int* part, int nsub,
+int nls_build_coarse_symbolic(const HostMesh& m, const int* part, int nsub, int kind,
                               HostCoarse& out, std::string& err) {
     const int N = m.N, E = m.E, nv = m.nv, dd = m.d;
     HostCoarse& C = out;
@@ -353,27 +353,110 @@ int nls_build_coarse_symbolic(const HostMesh& m, const int* part, int nsub,
     for (int c = 0; c < (int)comps.size(); ++c) C.comps[rank[c]] = comps[c];
     for (int g = 0; g < N; ++g)
         if (C.comp_of[g] >= 0) C.comp_of[g] = rank[C.comp_of[g]];
-    // coarse functions: scalar 1 per component; elasticity the translations
-    // and, on components of >= 2 nodes, the rotation about the centroid
+    // interface values of the coarse functions at every interface dof:
+    // (function id, value) pairs
     const int ncomps = (int)C.comps.size();
-    C.fun_base.assign(ncomps, 0);
-    C.nfun.assign(ncomps, 0);
+    std::vector<std::vector<std::pair<int, double>>> ifv((size_t)N * dd);
     std::vector<double> cxc(ncomps, 0.0), cyc(ncomps, 0.0);
+    auto centroid = [&](int c) {
+        cxc[c] = cyc[c] = 0.0;
+        for (int g : C.comps[c]) {
+            cxc[c] += m.xy[2 * g];
+            cyc[c] += m.xy[2 * g + 1];
+        }
+        cxc[c] /= (double)C.comps[c].size();
+        cyc[c] /= (double)C.comps[c].size();
+    };
+    // the functions of one coarse node (base fb, center c) at node g with
+    // weight w: scalar w; elasticity translations w and rotation w * r_c(g)
+    auto put = [&](int g, int fb, int nf, double w, double x0, double y0) {
+        if (dd == 1) {
+            ifv[g].push_back({fb, w});
+            return;
+        }
+        const double r[2] = {-(m.xy[2 * g + 1] - y0), m.xy[2 * g] - x0};
+        for (int c = 0; c < 2; ++c) {
+            ifv[2 * (size_t)g + c].push_back({fb + c, w});
+            if (nf == 3 && r[c] != 0.0) ifv[2 * (size_t)g + c].push_back({fb + 2, w * r[c]});
+        }
+    };
+    C.fun_base.assign(ncomps, -1);
+    C.nfun.assign(ncomps, 0);
     int nfuns = 0;
-    for (int c = 0; c < ncomps; ++c) {
-        C.fun_base[c] = nfuns;
-        C.nfun[c] = dd == 1 ? 1 : (C.comps[c].size() >= 2 ? 3 : 2);
-        nfuns += C.nfun[c];
-        if (C.nfun[c] == 3) {  // rotation about the component's centroid
+    if (kind != NLS_COARSE_RGDSW) {
+        // GDSW: every component; scalar 1 function, elasticity the two
+        // translations and, on components of >= 2 nodes, the rotation
+        for (int c = 0; c < ncomps; ++c) {
+            C.fun_base[c] = nfuns;
+            C.nfun[c] = dd == 1 ? 1 : (C.comps[c].size() >= 2 ? 3 : 2);
+            nfuns += C.nfun[c];
+            if (C.nfun[c] == 3) centroid(c);
+            for (int g : C.comps[c]) put(g, C.fun_base[c], C.nfun[c], 1.0, cxc[c], cyc[c]);
+        }
+    } else {
+        // RGDSW option 2.2: coarse nodes are the crosspoint components
+        // (>= 3 subdomains) and edge components without ancestor
+        // crosspoints; other edge nodes take inverse-distance weights of
+        // their ancestors, a Dirichlet node ending the edge counting as an
+        // ancestor of value 0
+        std::vector<std::vector<int>> anc(ncomps);
+        std::vector<char> isvert(ncomps, 0);
+        for (int c = 0; c < ncomps; ++c) isvert[c] = sset[C.comps[c][0]].size() >= 3;
+        for (int c = 0; c < ncomps; ++c) {
+            if (isvert[c]) continue;
+            const auto& se = sset[C.comps[c][0]];
+            for (int v = 0; v < ncomps; ++v)
+                if (isvert[v] && std::includes(sset[C.comps[v][0]].begin(), sset[C.comps[v][0]].end(),
+                                               se.begin(), se.end()))
+                    anc[c].push_back(v);
+        }
+        const int nf = dd == 1 ? 1 : 3;
+        for (int c = 0; c < ncomps; ++c) {   // canonical order: smallest node
+            if (!isvert[c] && !anc[c].empty()) continue;
+            C.fun_base[c] = nfuns;
+            C.nfun[c] = nf;
+            nfuns += nf;
+            centroid(c);
+            for (int g : C.comps[c]) put(g, C.fun_base[c], nf, 1.0, cxc[c], cyc[c]);
+        }
+        for (int c = 0; c < ncomps; ++c) {
+            if (isvert[c] || anc[c].empty()) continue;
+            const auto& se = sset[C.comps[c][0]];
+            std::vector<int> dends;
+            for (int g : C.comps[c])
+                for (int k = m.nptr[g]; k < m.nptr[g + 1]; ++k) {
+                    const int e = m.nel[k], p = vertex_pos(m, e, g);
+                    for (int t : {(p + 1) % nv, (p + nv - 1) % nv}) {
+                        const int w = m.conn[nv * e + t];
+                        if (ndir[w] && std::includes(sset[w].begin(), sset[w].end(), se.begin(), se.end()))
+                            dends.push_back(w);
+                    }
+                }
+            std::sort(dends.begin(), dends.end());
+            dends.erase(std::unique(dends.begin(), dends.end()), dends.end());
             for (int g : C.comps[c]) {
-                cxc[c] += m.xy[2 * g];
-                cyc[c] += m.xy[2 * g + 1];
+                const double gx = m.xy[2 * g], gy = m.xy[2 * g + 1];
+                double den = 0.0;
+                std::vector<double> inv(anc[c].size());
+                for (size_t a = 0; a < anc[c].size(); ++a) {
+                    const int v = anc[c][a];
+                    inv[a] = 1.0 / std::hypot(gx - cxc[v], gy - cyc[v]);
+                    den += inv[a];
+                }
+                for (int w : dends) den += 1.0 / std::hypot(gx - m.xy[2 * w], gy - m.xy[2 * w + 1]);
+                for (size_t a = 0; a < anc[c].size(); ++a) {
+                    const int v = anc[c][a];
+                    put(g, C.fun_base[v], nf, inv[a] / den, cxc[v], cyc[v]);
+                }
             }
-            cxc[c] /= (double)C.comps[c].size();
-            cyc[c] /= (double)C.comps[c].size();
         }
     }
     C.n0 = nfuns;
+    for (auto& l : ifv)
+        if ((int)l.size() > NLS_CFUN) {
+            err = "an interface dof carries more than NLS_CFUN coarse functions";
+            return NLS_ELIMIT;
+        }
 
     std::vector<std::vector<int>> elems_of(nsub);
     for (int e = 0; e < E; ++e) elems_of[part[e]].push_back(e);
@@ -399,10 +482,9 @@ int nls_build_coarse_symbolic(const HostMesh& m, const int* part, int nsub,
         for (int k = 0; k < (int)elems_of[i].size(); ++k) el[elems_of[i][k]] = k;
         std::vector<int> K;
         for (int g : nodes)
-            if (iface[g]) {
-                const int c = C.comp_of[g];
-                for (int f = 0; f < C.nfun[c]; ++f) K.push_back(C.fun_base[c] + f);
-            }
+            if (iface[g])
+                for (int c = 0; c < dd; ++c)
+                    for (auto& fv : ifv[(size_t)dd * g + c]) K.push_back(fv.first);
         std::sort(K.begin(), K.end());
         K.erase(std::unique(K.begin(), K.end()), K.end());
         auto kpos = [&](int f) { return (int)(std::lower_bound(K.begin(), K.end(), f) - K.begin()); };
@@ -420,21 +502,12 @@ int nls_build_coarse_symbolic(const HostMesh& m, const int* part, int nsub,
             for (int c = 0; c < dd; ++c) {
                 C.cnode.push_back(dd * g + c);
                 C.ctype.push_back(t);
-                int f0 = -1, f1 = -1;
-                double v0 = 0.0, v1 = 0.0;
-                if (t == 1) {
-                    const int cp = C.comp_of[g], fb = C.fun_base[cp];
-                    f0 = kpos(fb + (dd == 1 ? 0 : c));
-                    v0 = 1.0;
-                    if (C.nfun[cp] == 3) {
-                        f1 = kpos(fb + 2);
-                        v1 = c == 0 ? -(m.xy[2 * g + 1] - cyc[cp]) : (m.xy[2 * g] - cxc[cp]);
-                    }
+                const auto& fl = ifv[(size_t)dd * g + c];
+                for (int q = 0; q < NLS_CFUN; ++q) {
+                    const bool has = t == 1 && q < (int)fl.size();
+                    C.cfun.push_back(has ? kpos(fl[q].first) : -1);
+                    C.cval.push_back(has ? fl[q].second : 0.0);
                 }
-                C.cfun.push_back(f0);
-                C.cfun.push_back(f1);
-                C.cval.push_back(v0);
-                C.cval.push_back(v1);
                 C.iidx.push_back(t == 0 ? ni : -1);
                 if (t == 0) { inter.push_back(dd * a + c); ++ni; }
                 C.cinc.insert(C.cinc.end(), ci.begin(), ci.end());
@@ -853,7 +926,7 @@ extern "C" int nls_inspect_coarse(int64_t n_nodes, int64_t n_elems, const int32_
     for (int64_t e = 0; e < n_elems; ++e)
         if (elem_part[e] < 0 || elem_part[e] >= n_sub) return NLS_EINVAL;
     HostCoarse C;
-    rc = nls_build_coarse_symbolic(m, elem_part, n_sub, C, err);
+    rc = nls_build_coarse_symbolic(m, elem_part, n_sub, NLS_COARSE_GDSW, C, err);
     if (rc) return rc;
     int64_t tot = 0;
     for (auto& c : C.comps) tot += (int64_t)c.size();

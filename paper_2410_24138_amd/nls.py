@@ -37,6 +37,7 @@ ONE_LEVEL = 0
 ADDITIVE = 1
 COARSE_NONE = 0
 COARSE_GDSW = 1
+COARSE_RGDSW = 2
 MAX_OUTER = 64
 FLAG_PROFILE = 1
 FLAG_GRAPH = 2
@@ -249,7 +250,7 @@ class Solver:
 
     def __init__(self, case: dict, coupling: Optional[str] = None,
                  precision: str = "fp64", device: int = 0, stream=None,
-                 **opts):
+                 coarse: str = "gdsw", **opts):
         import torch
         self.lib = load()
         self.torch = torch
@@ -299,7 +300,8 @@ class Solver:
         self._check(self.lib.nls_set_partition(h, int(case["n_sub"]), _ptr(part),
                                                int(case["overlap"])))
         if coupling == "additive":
-            self._check(self.lib.nls_build_coarse(h, COARSE_GDSW))
+            kind = {"gdsw": COARSE_GDSW, "rgdsw": COARSE_RGDSW}[coarse]
+            self._check(self.lib.nls_build_coarse(h, kind))
 
     def set_nodal_load(self, f):
         """Nodal forces (elasticity), n_nodes * 2 values in dof order."""

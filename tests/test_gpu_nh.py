@@ -145,3 +145,20 @@ def test_config3_load_continuation():
     assert abs(un[golden["tip_dof"]] - tip) <= 1e-8 * abs(tip)
     if "outer" in golden["steps"][0]:
         assert [st["outer_its"] for st in sts] == [st["outer"] for st in golden["steps"]]
+
+
+def test_rgdsw_elasticity():
+    case = synth.small_elasticity_case(nx=16, ny=12, boxes=(4, 3), overlap=1,
+                                       traction=(0.0, -2.0), two_level=True)
+    P = NHProblem(case)
+    S = Schwarz(P, "additive", coarse="rgdsw")
+    s = _solver(case, coupling="additive", coarse="rgdsw")
+    _close(s.coarse_basis().toarray(), S.Phi.toarray(), 1e-12)
+    u = _probe(P, 6)
+    _close(_np(s.precond_residual(u)), S.evaluate(u), 1e-10)
+    v = np.random.default_rng(7).normal(size=P.ndof)
+    _close(_np(s.tangent(v)), S.tangent(v), 1e-10)
+    u_ref, st_ref = S.solve()
+    uu, st, rc = _solver(case, coupling="additive", coarse="rgdsw").solve()
+    assert rc == 0 and st["outer_its"] == st_ref["outer"]
+    assert np.linalg.norm(_np(uu) - u_ref) <= 1e-10 * np.linalg.norm(u_ref)

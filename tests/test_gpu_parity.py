@@ -311,3 +311,23 @@ def test_autotuned_solve_matches_oracle():
     assert min(after["coarse_ms"]) > 0.0
     uu2, st2, _ = s.solve()
     np.testing.assert_array_equal(_np(uu2), _np(uu))
+
+
+@pytest.mark.parametrize("kw", [dict(n=24, boxes=4, overlap=2, forcing_seed=2),
+                                dict(n=21, boxes=3, overlap=1, uneven=True, coef_seed=3)])
+def test_rgdsw_matches_oracle(kw):
+    """RGDSW option 2.2 coarse space (the paper's): basis, F_x, tangent and
+    the solve match the oracle."""
+    case = synth.small_case(two_level=True, **kw)
+    P = P1Problem(case)
+    S = Schwarz(P, "additive", coarse="rgdsw")
+    s = _solver(case, coupling="additive", coarse="rgdsw")
+    _close(s.coarse_basis().toarray(), S.Phi.toarray(), 1e-12)
+    u = _probe_point(P, case)
+    _close(_np(s.precond_residual(u)), S.evaluate(u), 1e-11)
+    v = np.random.default_rng(8).normal(size=P.N)
+    _close(_np(s.tangent(v)), S.tangent(v), 1e-11)
+    u_ref, st_ref = S.solve()
+    uu, st, rc = _solver(case, coupling="additive", coarse="rgdsw").solve()
+    assert rc == 0 and st["outer_its"] == st_ref["outer"]
+    assert np.linalg.norm(_np(uu) - u_ref) <= 1e-10 * np.linalg.norm(u_ref)
