@@ -38,6 +38,8 @@ FORMS = {
     "fp64_graph_chord": ("fp64", ("graph", "chord")),
     "fp64_graph_chord_luapply": ("fp64", ("graph", "chord", "luapply")),
     "fp64_tuned": ("fp64", ("graph", "chord", "autotune")),
+    # as fp64_tuned with the RGDSW coarse space (the paper's choice)
+    "fp64_tuned_rgdsw": ("fp64", ("graph", "chord", "autotune", "rgdsw")),
     # FP32 local LU + FP64 refinement with graphs, chord coarse steps, autotuner
     "chosen": ("fp32_ir", ("graph", "chord", "autotune")),
 }
@@ -89,6 +91,7 @@ def run_form(case, golden, form, steps, warmup, device):
     from paper_2410_24138_amd import Solver, nls
     prec, extra = FORMS[form]
     s = Solver(case, precision=prec, device=device.index or 0,
+               coarse="rgdsw" if "rgdsw" in extra else "gdsw",
                flags=nls.FLAG_PROFILE | (nls.FLAG_GRAPH if "graph" in extra else 0)
                | (nls.FLAG_COARSE_CHORD if "chord" in extra else 0)
                | (nls.FLAG_COARSE_LU_APPLY if "luapply" in extra else 0)
@@ -311,6 +314,7 @@ def run_elasticity(forms, steps, warmup, device, n_load_steps=10):
     for f in forms:
         prec, extra = FORMS[f]
         s = Solver(case, precision=prec, device=device.index or 0,
+                   coarse="rgdsw" if "rgdsw" in extra else "gdsw",
                    flags=nls.FLAG_PROFILE | (nls.FLAG_GRAPH if "graph" in extra else 0)
                    | (nls.FLAG_COARSE_CHORD if "chord" in extra else 0)
                    | (nls.FLAG_AUTOTUNE if "autotune" in extra else 0))
@@ -342,7 +346,8 @@ def run_elasticity(forms, steps, warmup, device, n_load_steps=10):
             res[f]["outer_its_oracle"] = [st["outer"] for st in golden["steps"]]
         s.close()
         print(json.dumps({"form": f, **res[f]}), file=sys.stderr, flush=True)
-    ok = {f: r for f, r in res.items() if r["converged"] and r["rel_err_vs_global_newton"] <= 1e-8}
+    ok = {f: r for f, r in res.items() if r["converged"] and r["rel_err_vs_global_newton"] <= 1e-8
+          and "rgdsw" not in FORMS[f][1]}
     best = min(ok, key=lambda f: ok[f]["ms_per_continuation"]) if ok else forms[0]
     return {
         "metric": "time-to-1e-8 per 10-step load continuation; subdomain Newton solves/s",
@@ -451,7 +456,10 @@ def main():
         res[f] = run_form(case, golden, f, args.steps, args.warmup, device)
         print(json.dumps({"form": f, **{k: v for k, v in res[f].items()
                                         if k not in ("kernels",)}}), file=sys.stderr, flush=True)
-    ok = {f: r for f, r in res.items() if r["converged"] and r["rel_err_vs_global_newton"] <= 1e-8}
+    # the headline is the workload as named (GDSW vertex+edge coarse space);
+    # RGDSW forms are reported beside it
+    ok = {f: r for f, r in res.items() if r["converged"] and r["rel_err_vs_global_newton"] <= 1e-8
+          and "rgdsw" not in FORMS[f][1]}
     best = min(ok, key=lambda f: ok[f]["ms_per_solve"]) if ok else forms[0]
     r = res[best]
     line = {

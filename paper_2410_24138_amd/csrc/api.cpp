@@ -691,9 +691,9 @@ static bool two_level(nls_handle* h) {
 // from c = 0; keeps LU(A0) at the converged c and u_0 = u - Phi c in dc.w.
 // T_0(u) (eq. 9): Newton on G(c) = Phi^T F(u - Phi c) = 0 from c = 0.  With
 // NLS_FLAG_COARSE_CHORD the steps reuse the last factorisation of A0 (from
-// the previous evaluation, or the first step's) and refactor only when the
-// residual fails to halve; A0 and its LU at the converged c* (kept for the
-// tangent, eq. 12) are formed in every mode.
+// the previous tangent, or the first step's) and refactor only when the
+// residual fails to halve.  A0 and its LU at the converged c*, which only
+// the tangent needs, are formed by prepare_tangent.
 static int coarse_solve(nls_handle* h, const double* u, int* its_out) {
     DevCoarse& d = h->dc;
     const int n0 = d.n0;
@@ -734,12 +734,6 @@ static int coarse_solve(nls_handle* h, const double* u, int* its_out) {
         gprev = gn;
         ++its;
     }
-    // Galerkin matrix and its LU at the converged point, for the tangent
-    HIPCHK(launch_coarse_galerkin(h->dm, d, d.w, 1, h->stream));
-    HIPCHK(launch_coarse_assemble(d, 1, h->stream));
-    HIPCHK(launch_coarse_lu(d, 1, h->lds_coarse_lu, h->npl_coarse, h->stream));
-    h->coarse_lu_valid = true;
-    if (h->coarse_inv) HIPCHK(launch_coarse_inverse(d, h->coarse_bucket, h->max_block, h->stream));
     if (its_out) *its_out = its;
     return NLS_OK;
 }
@@ -788,12 +782,6 @@ static int evaluate(nls_handle* h, const double* u, double* Fx) {
         }
         h->st->local_solves += h->maps.nsub;
     }
-    if (st2[0] < 0 && h->tangent_w) {
-        Timer tp;
-        HIPCHK(launch_tangent_prep(h->dp, h->dl, h->dt, h->tangent_bucket, h->max_ng, h->stream));
-        RC(sync(h));
-        if (h->st) h->st->ms_inner += tp.ms();
-    }
     if (st2[0] >= 0) {
         if (h->st) h->st->failed_subdomain = st2[0];
         if (st2[1] == 2) return fail(h, NLS_ENAN, "non-finite local residual in subdomain " + std::to_string(st2[0]));
@@ -815,6 +803,38 @@ static int evaluate(nls_handle* h, const double* u, double* Fx) {
         HIPCHK(launch_prolong(h->dm, h->dp, h->dl.T, nullptr, nullptr, Fx, nullptr, h->stream));
     }
     h->have_state = true;
+    h->tangent_ready = false;
+    return NLS_OK;
+}
+
+// The factorisations the tangent (eqs. 7, 12) needs at the last evaluated
+// point: J_ii^{-1} B_i per subdomain, and A0 with its LU (and inverse) at the
+// converged c*.  Formed on first use, so the evaluation that ends the outer
+// iteration pays for none of them.
+static int prepare_tangent(nls_handle* h) {
+    if (h->tangent_ready) return NLS_OK;
+    if (!h->have_state) return fail(h, NLS_ESTATE, "no evaluated point (nls_eval_precond_residual)");
+    if (h->tangent_w) {
+        Timer tp;
+        HIPCHK(launch_tangent_prep(h->dp, h->dl, h->dt, h->tangent_bucket, h->max_ng, h->stream));
+        RC(sync(h));
+        if (h->st) h->st->ms_inner += tp.ms();
+    }
+    if (two_level(h)) {
+        Timer tc;
+        DevCoarse& d = h->dc;
+        HIPCHK(launch_coarse_galerkin(h->dm, d, d.w, 1, h->stream));
+        HIPCHK(launch_coarse_assemble(d, 1, h->stream));
+        HIPCHK(launch_coarse_lu(d, 1, h->lds_coarse_lu, h->npl_coarse, h->stream));
+        h->coarse_lu_valid = true;
+        if (h->coarse_inv) HIPCHK(launch_coarse_inverse(d, h->coarse_bucket, h->max_block, h->stream));
+        int flag = 0;
+        HIPCHK(hipMemcpyAsync(&flag, d.flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+        RC(sync(h));
+        if (flag) return fail(h, NLS_ESINGULAR, "zero pivot in the coarse matrix");
+        if (h->st) h->st->ms_coarse += tc.ms();
+    }
+    h->tangent_ready = true;
     return NLS_OK;
 }
 
@@ -894,6 +914,7 @@ static constexpr int TUNE_STEPS = 20;
 static int autotune_coarse(nls_handle* h) {
     if (!two_level(h) || h->coarse_bucket > 56 || (h->opt.flags & NLS_FLAG_COARSE_LU_APPLY))
         return NLS_OK;
+    RC(prepare_tangent(h));
     DevCoarse& d = h->dc;
     float t_inv = 0.f, t_apply = 0.f, t_lu = 0.f;
     RC(time_ms(h, [&]() -> int {
@@ -1030,6 +1051,7 @@ static int block_graph(nls_handle* h, int b, hipGraphExec_t* out) {
 // host reads the convergence state once per block.  Steps of a block after
 // convergence run but are not used.
 static int gmres_graph(nls_handle* h, const double* b, double* x, int* its_out) {
+    RC(prepare_tangent(h));
     const int N = h->mesh.ndof(), m = h->m, K = h->gblock;
     double bn2 = 0.0;
     RC(dot_host(h, b, b, N, &bn2));
@@ -1117,6 +1139,7 @@ static int gmres_graph(nls_handle* h, const double* b, double* x, int* its_out) 
 // Restarted GMRES(m) for D F_x(u) x = b from x = 0 (classical Gram-Schmidt
 // with one reorthogonalisation).  Returns the iteration count in *its.
 static int gmres(nls_handle* h, const double* b, double* x, int* its_out) {
+    RC(prepare_tangent(h));
     const int N = h->mesh.ndof(), m = h->m;
     const int64_t ld = N;
     double bn2 = 0.0;
@@ -1249,6 +1272,8 @@ extern "C" int nls_solve(nls_handle* h, double* u, int u_on_device, nls_stats* s
             break;
         }
         if (k == h->opt.outer_maxit) break;
+        rc = prepare_tangent(h);
+        if (rc) return finish(rc);
         Timer tg;
         int gits = 0;
         rc = graph_gmres_ok(h) ? gmres_graph(h, h->Fx, h->du, &gits) : gmres(h, h->Fx, h->du, &gits);
@@ -1321,6 +1346,7 @@ extern "C" int nls_apply_tangent(nls_handle* h, const double* v, double* y) {
     if (!h || !v || !y) return NLS_EINVAL;
     if (!h->have_state) return fail(h, NLS_ESTATE, "no evaluated point (nls_eval_precond_residual)");
     HIPCHK(hipSetDevice(h->opt.device));
+    RC(prepare_tangent(h));
     RC(tangent(h, v, y));
     return sync(h);
 }

@@ -53,6 +53,7 @@ struct nls_handle {
     int tangent_bucket = 0, max_ng = 0;
     bool coarse_inv = false;      // explicit A0^{-1} for the tangent
     bool coarse_lu_valid = false; // a factorisation of A0 is held (chord steps)
+    bool tangent_ready = false;   // prepare_tangent ran at the last evaluated point
     int coarse_bucket = 0, max_block = 0;
     // size buckets of the local-solve launches: [start, end) in the launch
     // order, LDS bytes and solve width of each

@@ -23,6 +23,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cfloat>
 #include <cmath>
 
 #include "nls.h"
@@ -480,34 +481,57 @@ __device__ __forceinline__ float rdlane(float v, int l) {
 }
 
 template <int CTRL, int ROWMASK>
-__device__ __forceinline__ double dpp_max(double v) {
-    const int lo = __double2loint(v), hi = __double2hiint(v);
-    const int lo2 = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROWMASK, 0xf, false);
-    const int hi2 = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROWMASK, 0xf, false);
-    return fmax(v, __hiloint2double(hi2, lo2));
+__device__ __forceinline__ unsigned dpp_umax(unsigned v) {
+    return max(v, (unsigned)__builtin_amdgcn_update_dpp((int)v, (int)v, CTRL, ROWMASK, 0xf, false));
 }
 
-// Lane of the largest |a| over the wavefront (a < 0 marks lanes that do not
-// take part); ties go to the lowest lane.  The lane number is packed into the
-// 6 low mantissa bits of |a| (a relative perturbation below 2^-46, which only
-// matters for values that are equal to that precision), then a DPP max
-// reduction leaves the winner in lane 63.
-__device__ __forceinline__ int wave_argmax(double a, int lane) {
-    double key;
-    if (a >= 0.0) {
-        const long long bits = (__double_as_longlong(a) & ~63ll) | (long long)(63 - lane);
-        key = __longlong_as_double(bits);
-    } else {
-        key = -1.0;
+// Index (0..63) of an entry of largest |a| over the wavefront (a < 0 marks
+// lanes that do not take part), compared on the high word of |a| with its 6
+// low bits replaced by 63 - idx: entries within a relative 2^-14 of each
+// other count as equal and the lowest index wins among them, so every
+// multiplier stays below 1 + 2^-14 in magnitude.
+__device__ __forceinline__ int wave_argmax_hi(double a, int idx) {
+    unsigned key = 0u;
+    if (a >= 0.0) key = ((unsigned)__double2hiint(a) & ~63u) | (unsigned)(63 - idx);
+    key = dpp_umax<0xB1, 0xf>(key);   // quad_perm [1,0,3,2]
+    key = dpp_umax<0x4E, 0xf>(key);   // quad_perm [2,3,0,1]
+    key = dpp_umax<0x141, 0xf>(key);  // row_half_mirror
+    key = dpp_umax<0x140, 0xf>(key);  // row_mirror
+    key = dpp_umax<0x142, 0xa>(key);  // row_bcast:15 into rows 1, 3
+    key = dpp_umax<0x143, 0xc>(key);  // row_bcast:31 into rows 2, 3
+    key = (unsigned)__builtin_amdgcn_readlane((int)key, 63);
+    return 63 - (int)(key & 63u);
+}
+
+// One 16x16x4 matrix-core step D = A B + C: A is 16 x 4 with lane l holding
+// A[l % 16][l / 16], B is 4 x 16 with lane l holding B[l / 16][l % 16], and
+// C, D are 16 x 16 with lane l holding four entries of column l % 16: rows
+// row(l / 16, q), q = 0..3 (FP64: l / 16 + 4 q; FP32: 4 (l / 16) + q).
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+    typedef double acc_t __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ acc_t step(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
-    key = dpp_max<0xB1, 0xf>(key);   // quad_perm [1,0,3,2]
-    key = dpp_max<0x4E, 0xf>(key);   // quad_perm [2,3,0,1]
-    key = dpp_max<0x141, 0xf>(key);  // row_half_mirror
-    key = dpp_max<0x140, 0xf>(key);  // row_mirror
-    key = dpp_max<0x142, 0xa>(key);  // row_bcast:15 into rows 1, 3
-    key = dpp_max<0x143, 0xc>(key);  // row_bcast:31 into rows 2, 3
-    key = rdlane(key, 63);
-    return 63 - (int)(__double_as_longlong(key) & 63ll);
+    static __device__ __forceinline__ int row(int g, int q) { return g + 4 * q; }
+};
+template <> struct Mfma<float> {
+    typedef float acc_t __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ acc_t step(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int g, int q) { return 4 * g + q; }
+};
+
+// 1/x from the hardware reciprocal and two Newton steps (a few ulp).
+__device__ __forceinline__ double recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ float recip(float x) {
+    float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
 }
 
 // ----------------------------------------------------------------------------
@@ -538,6 +562,7 @@ __device__ __forceinline__ int band_lu_blocked(int n, int kl, int ku, const int*
                                T* W, int* sh, T* __restrict__ Uf, T* __restrict__ Lf,
                                int* __restrict__ piv, int cbase = 0) {
     T* lt = W + (NB + kl) * (NB + kl + ku);  // L11 of the current panel, NB x NB
+    int* mv = (int*)(lt + NB * NB);           // moved rows of the panel (<= 64)
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wv = tid >> 6;
     const int H = NB + kl, Wd = NB + kl + ku;
@@ -551,117 +576,166 @@ __device__ __forceinline__ int band_lu_blocked(int n, int kl, int ku, const int*
             if (c < n) W[r * Wd + c] = T(vals[s]);
         }
     __syncthreads();
+    int rpn[NB + 1];     // row pointers of the rows entering after the next panel
+#pragma unroll
+    for (int q = 0; q <= NB; ++q) rpn[q] = wv > 0 ? rptr[min(H + q, min(H + NB, n))] : 0;
     int rb = 0, cb = 0;  // ring slots of global row / column k0
     for (int k0 = 0; k0 < n; k0 += NB) {
         const int nbp = min(NB, n - k0);
         const int rvalid = min(H, n - k0);
         const int k1 = k0 + NB, cb1 = wrap(cb + NB, Wd);
         // waves 1.. fetch the CSR entries of the rows that enter the window
-        // after this panel while wave 0 factors it
+        // after this panel while wave 0 factors it; the row pointers were
+        // fetched one panel ahead, and the entries are only placed at the end
+        // of the panel, so neither load is waited for before then
         constexpr int PF = 2;
         const int rn0 = k0 + H, rn1 = min(k0 + H + NB, n);
-        int pf_slot[PF];
-        T pf_val[PF];
+        int rp[NB + 1];
+#pragma unroll
+        for (int q = 0; q <= NB; ++q) rp[q] = rpn[q];
+        if (wv > 0) {
+            const int m1 = min(rn0 + 2 * NB, n);
+#pragma unroll
+            for (int q = 0; q <= NB; ++q) rpn[q] = rptr[min(rn0 + NB + q, m1)];
+        }
+        int pf_s[PF], pf_c[PF];
+        double pf_v[PF];
 #pragma unroll
         for (int e = 0; e < PF; ++e) {
-            pf_slot[e] = -1;
-            pf_val[e] = T(0);
+            pf_s[e] = -1;
+            pf_c[e] = 0;
+            pf_v[e] = 0.0;
         }
-        int s_end = 0, s_done = 0;
+        const int s_end = rp[NB], s_done = rp[0] + (nt - 64) * PF;
         if (rn0 < n && wv > 0) {
-            int rp[NB + 1];
-#pragma unroll
-            for (int q = 0; q <= NB; ++q) rp[q] = rptr[min(rn0 + q, rn1)];
-            s_end = rp[NB];
-            s_done = rp[0] + (nt - 64) * PF;
 #pragma unroll
             for (int e = 0; e < PF; ++e) {
                 const int sidx = rp[0] + (tid - 64) + (nt - 64) * e;
                 if (sidx < s_end) {
-                    int q = 0;
-#pragma unroll
-                    for (int t = 1; t < NB; ++t) q += (rp[t] <= sidx) ? 1 : 0;
-                    const int c = cols[sidx] - cbase;
-                    if (c < n) {
-                        pf_slot[e] = wrap(rb + q, H) * Wd + wrap(cb1 + (c - k1), Wd);
-                        pf_val[e] = T(vals[sidx]);
-                    }
+                    pf_s[e] = sidx;
+                    pf_c[e] = cols[sidx];
+                    pf_v[e] = vals[sidx];
                 }
             }
         }
-        // ---- panel: columns k0..k0+nbp-1, rows k0..k0+rvalid-1 (wave 0)
+        // ---- panel: columns k0..k0+nbp-1, rows k0..k0+rvalid-1 (wave 0).
+        // Lane r keeps window row r in registers for the whole panel; the
+        // interchanges are tracked as positions (pos = where row r sits in
+        // the interchanged order) instead of moving data between lanes, and
+        // the rows are written back to their final positions at the end.
         if (wv == 0) {
             T p[NB];
             const bool have = lane < rvalid;
             const int sr = wrap(rb + (lane < H ? lane : 0), H);
 #pragma unroll
             for (int c = 0; c < NB; ++c) p[c] = have ? W[sr * Wd + wrap(cb + c, Wd)] : T(0);
-            int sing = 0;
+            int pos = lane, sing = 0;
+            bool used = false;
+            // The steps hold no stores (the multipliers and interchanges are
+            // stored after the loop) and no branch but the one around the
+            // pivot search.
+            int dsel = lane;        // lane j: the pivot position of step j
+            int posj[NB];           // position of this row after step j
+            unsigned below_mask = 0u;
 #pragma unroll
             for (int j = 0; j < NB; ++j) {
-                if (j < nbp) {
-                    const int rmx = min(j + kl, rvalid - 1);
-                    const int d = __builtin_amdgcn_readfirstlane(wave_argmax(
-                        (lane >= j && lane <= rmx) ? fabs((double)p[j]) : -1.0, lane));
-                    if (lane == 0) {
-                        piv[k0 + j] = k0 + d;
-                        sh[j] = d;
-                    }
-                    // whole panel rows are exchanged (the multipliers of
-                    // earlier columns included), so that L21 in the window
-                    // matches the row order the delayed update A22 -= L21 U12
-                    // needs; the multipliers are stored to HBM at their own
-                    // step, in the interleaved order the band solve applies.
-                    if (d != j) {
+                // a step past the last column (j >= nbp, last panel only)
+                // has no candidates, so it changes nothing
+                const bool act = j < nbp;
+                // candidates: the rows at positions j..min(j+kl, rvalid-1),
+                // i.e. the rows r <= j+kl not yet chosen as pivots.  The row
+                // at position j keeps the pivot when no candidate is larger
+                // in magnitude (no reduction needed); otherwise a wavefront
+                // argmax, where a NaN or infinite entry is a candidate of the
+                // largest key, so the chosen position belongs to a candidate.
+                const bool cand = act && have && !used && lane <= j + kl;
+                const double av = fabs((double)p[j]);
+                const int lj = __ffsll((unsigned long long)__ballot(act && have && pos == j)) - 1;
+                const double aj = fabs((double)rdlane(p[j], lj < 0 ? 0 : lj));
+                int d = j, pl = lj;
+                if (__ballot(cand && av > aj) != 0) {
+                    d = __builtin_amdgcn_readfirstlane(
+                        wave_argmax_hi(cand ? (av <= DBL_MAX ? av : DBL_MAX) : -1.0, pos));
+                    pl = __ffsll((unsigned long long)__ballot(cand && pos == d)) - 1;
+                }
+                const int plr = pl < 0 ? 0 : pl;  // lane read when nothing is active
+                dsel = (lane == j) ? d : dsel;
+                pos = (pos == j) ? d : (lane == pl ? j : pos);
+                posj[j] = pos;
+                used = used || lane == pl;
+                const T pivv = rdlane(p[j], plr);
+                sing |= (act && pivv == T(0)) ? 1 : 0;
+                const T inv = pivv != T(0) ? recip(pivv) : T(0);
+                const bool below = cand && lane != pl;
+                below_mask |= below ? (1u << j) : 0u;
+                // l = 0 leaves the rows that are not below the pivot as they are
+                const T l = below ? p[j] * inv : T(0);
+                p[j] = below ? l : p[j];
 #pragma unroll
-                        for (int c = 0; c < NB; ++c) {
-                            const T pj = rdlane(p[c], j);
-                            const T pd = rdlane(p[c], d);
-                            if (lane == j) p[c] = pd;
-                            if (lane == d) p[c] = pj;
-                        }
-                    }
-                    const T pivv = rdlane(p[j], j);
-                    if (pivv == T(0)) sing = 1;
-                    const T inv = pivv != T(0) ? T(1) / pivv : T(0);
-                    const bool below = lane > j && lane <= rmx;
-                    const T l = below ? p[j] * inv : T(0);
-                    if (below) {
-                        p[j] = l;
-                        Lf[(size_t)(k0 + j) * ldl + (lane - j - 1)] = l;
-                    }
+                for (int c = j + 1; c < NB; ++c) p[c] -= l * rdlane(p[c], plr);
+            }
+            if (lane < nbp) piv[k0 + lane] = k0 + dsel;
 #pragma unroll
-                    for (int c = j + 1; c < NB; ++c) {
-                        const T pr = rdlane(p[c], j);
-                        if (below) p[c] -= l * pr;
-                    }
+            for (int j = 0; j < NB; ++j)
+                if ((below_mask >> j) & 1u) Lf[(size_t)(k0 + j) * ldl + (posj[j] - j - 1)] = p[j];
+            if (have) {
+                const int sp = wrap(rb + pos, H);
+#pragma unroll
+                for (int c = 0; c < NB; ++c) W[sp * Wd + wrap(cb + c, Wd)] = p[c];
+                if (pos < NB) {
+#pragma unroll
+                    for (int c = 0; c < NB; ++c) lt[pos * NB + c] = p[c];
                 }
             }
-            if (lane < H && have) {
-#pragma unroll
-                for (int c = 0; c < NB; ++c) W[sr * Wd + wrap(cb + c, Wd)] = p[c];
+            // rows that changed position: (new position << 8) | old position
+            const bool moved = have && pos != lane;
+            const unsigned long long mm = (unsigned long long)__ballot(moved);
+            if (moved) {
+                const int idx = __builtin_amdgcn_mbcnt_hi((unsigned)(mm >> 32),
+                                                          __builtin_amdgcn_mbcnt_lo((unsigned)mm, 0u));
+                mv[idx] = (pos << 8) | lane;
             }
-            if (lane < NB) {
-#pragma unroll
-                for (int c = 0; c < NB; ++c) lt[lane * NB + c] = p[c];
+            if (lane == 0) {
+                sh[NB + 1] = __popcll(mm);
+                if (sing) sh[NB] = 1;
             }
-            if (lane == 0 && sing) sh[NB] = 1;
         }
         lds_barrier();
-        // ---- trailing columns: interchanges, then U12 = L11^{-1} A12
+        // ---- trailing columns: the panel's row permutation, then
+        //      U12 = L11^{-1} A12 (one thread per column)
         const int ntr = min(Wd - NB, n - k0 - nbp);
+        const int nmv = sh[NB + 1];
+        if (nmv > 0) {
+            // moved rows of the trailing columns, whole columns per round:
+            // every source of a column is read before any destination of
+            // that column is written
+            constexpr int E = 8;
+            const int cpr = (E * nt) / nmv;  // columns per round (nmv <= 2 NB)
+            for (int c0 = 0; c0 < ntr; c0 += cpr) {
+                const int tot = min(cpr, ntr - c0) * nmv;
+                T v[E];
+                int dst[E];
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int idx = tid + e * nt;
+                    dst[e] = -1;
+                    v[e] = T(0);
+                    if (idx < tot) {
+                        const int c = c0 + idx / nmv, q = idx - (idx / nmv) * nmv;
+                        const int sc = wrap(cb + NB + c, Wd), m = mv[q];
+                        v[e] = W[wrap(rb + (m & 255), H) * Wd + sc];
+                        dst[e] = wrap(rb + (m >> 8), H) * Wd + sc;
+                    }
+                }
+                lds_barrier();
+#pragma unroll
+                for (int e = 0; e < E; ++e)
+                    if (dst[e] >= 0) W[dst[e]] = v[e];
+                lds_barrier();
+            }
+        }
         for (int t = tid; t < ntr; t += nt) {
             const int sc = wrap(cb + NB + t, Wd);
-            for (int j = 0; j < nbp; ++j) {
-                const int d = sh[j];
-                if (d != j) {
-                    T* a = W + wrap(rb + j, H) * Wd + sc;
-                    T* b = W + wrap(rb + d, H) * Wd + sc;
-                    const T x = *a;
-                    *a = *b;
-                    *b = x;
-                }
-            }
             T x[NB];
 #pragma unroll
             for (int j = 0; j < NB; ++j) x[j] = (j < nbp) ? W[wrap(rb + j, H) * Wd + sc] : T(0);
@@ -675,50 +749,49 @@ __device__ __forceinline__ int band_lu_blocked(int n, int kl, int ku, const int*
                 if (j < nbp) W[wrap(rb + j, H) * Wd + sc] = x[j];
         }
         lds_barrier();
-        // ---- A22 -= L21 U12 (rows NB..rvalid-1) in 4x4 tiles; U rows out
+        // ---- A22 -= L21 U12 (rows NB..rvalid-1) on the matrix cores, one
+        //      16 x 16 tile per wavefront at a time, k in steps of 4; U rows out
         {
             const int nr2 = rvalid - NB;
             if (nr2 > 0 && ntr > 0) {
-                const int tr = (nr2 + 3) >> 2, tc = (ntr + 3) >> 2;
-                for (int t = tid; t < tr * tc; t += nt) {
-                    const int r0 = NB + 4 * (t / tc), c0 = NB + 4 * (t % tc);
-                    T acc[4][4];
-                    int srow[4], scol[4];
+                const int tr = (nr2 + 15) >> 4, tc = (ntr + 15) >> 4;
+                const int li = lane & 15, lk = lane >> 4;
+                for (int t = wv; t < tr * tc; t += nt >> 6) {
+                    const int r0 = NB + 16 * (t / tc), c0 = NB + 16 * (t % tc);
+                    // C: lane holds rows r0 + row(lk, q), column c0 + li
+                    const int cc = c0 + li;
+                    const bool cok = cc < NB + ntr;
+                    const int scc = wrap(cb + (cok ? cc : 0), Wd);
+                    typename Mfma<T>::acc_t acc;
 #pragma unroll
-                    for (int a = 0; a < 4; ++a) {
-                        srow[a] = wrap(rb + min(r0 + a, H - 1), H);
-                        scol[a] = wrap(cb + min(c0 + a, Wd - 1), Wd);
-#pragma unroll
-                        for (int b = 0; b < 4; ++b) acc[a][b] = T(0);
+                    for (int q = 0; q < 4; ++q) {
+                        const int rr = r0 + Mfma<T>::row(lk, q);
+                        acc[q] = (cok && rr < rvalid) ? W[wrap(rb + rr, H) * Wd + scc] : T(0);
                     }
-#pragma unroll 2
-                    for (int j = 0; j < nbp; ++j) {
-                        {
-                            const int sj = wrap(rb + j, H), cj = wrap(cb + j, Wd);
-                            T lv[4], uv[4];
+                    // A = -L21 (rows r0 + li, k = 4 s + lk), B = U12 (rows k, column cc)
+                    const int ra = r0 + li;
+                    const bool aok = ra < rvalid;
+                    const int sra = wrap(rb + (aok ? ra : 0), H);
 #pragma unroll
-                            for (int a = 0; a < 4; ++a) {
-                                lv[a] = W[srow[a] * Wd + cj];
-                                uv[a] = W[sj * Wd + scol[a]];
-                            }
-#pragma unroll
-                            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                                for (int b = 0; b < 4; ++b) acc[a][b] += lv[a] * uv[b];
-                        }
+                    for (int s4 = 0; s4 < NB / 4; ++s4) {
+                        const int k = 4 * s4 + lk;
+                        const T av = (aok && k < nbp) ? -W[sra * Wd + wrap(cb + k, Wd)] : T(0);
+                        const T bv = (cok && k < nbp) ? W[wrap(rb + k, H) * Wd + scc] : T(0);
+                        acc = Mfma<T>::step(av, bv, acc);
                     }
 #pragma unroll
-                    for (int a = 0; a < 4; ++a)
-#pragma unroll
-                        for (int b = 0; b < 4; ++b)
-                            if (r0 + a < rvalid && c0 + b < NB + ntr)
-                                W[srow[a] * Wd + scol[b]] -= acc[a][b];
+                    for (int q = 0; q < 4; ++q) {
+                        const int rr = r0 + Mfma<T>::row(lk, q);
+                        if (cok && rr < rvalid) W[wrap(rb + rr, H) * Wd + scc] = acc[q];
+                    }
                 }
             }
-            for (int idx = tid; idx < nbp * ldu; idx += nt) {
-                const int r = idx / ldu, o = idx - r * ldu;
-                const int c = r + o;
-                if (k0 + c < n) Uf[(size_t)(k0 + c) * ldu + o] = W[wrap(rb + r, H) * Wd + wrap(cb + c, Wd)];
+            // U rows of the panel out, column by column: the (up to NB) entries
+            // of a factor column are contiguous, Uf[c * ldu + (c - r)]
+            for (int idx = tid; idx < (nbp + ldu - 1) * NB; idx += nt) {
+                const int c = idx / NB, r = idx - c * NB, o = c - r;
+                if (r < nbp && o >= 0 && o < ldu && k0 + c < n)
+                    Uf[(size_t)(k0 + c) * ldu + o] = W[wrap(rb + r, H) * Wd + wrap(cb + c, Wd)];
             }
         }
         lds_barrier();
@@ -732,10 +805,17 @@ __device__ __forceinline__ int band_lu_blocked(int n, int kl, int ku, const int*
             W[r * Wd + wrap(cb + q, Wd)] = T(0);
         }
         lds_barrier();
-        if (wv > 0) {
+        if (rn0 < n && wv > 0) {
 #pragma unroll
-            for (int e = 0; e < PF; ++e)
-                if (pf_slot[e] >= 0) W[pf_slot[e]] = pf_val[e];
+            for (int e = 0; e < PF; ++e) {
+                const int c = pf_c[e] - cbase;
+                if (pf_s[e] >= 0 && c < n) {
+                    int q = 0;
+#pragma unroll
+                    for (int t = 1; t < NB; ++t) q += (rp[t] <= pf_s[e]) ? 1 : 0;
+                    W[wrap(rb + q, H) * Wd + wrap(cb1 + (c - k1), Wd)] = T(pf_v[e]);
+                }
+            }
             // rows with more entries than the prefetch covers
             for (int sidx = s_done + (tid - 64); sidx < s_end; sidx += nt - 64) {
                 int q = 0;

@@ -162,3 +162,20 @@ def test_rgdsw_elasticity():
     uu, st, rc = _solver(case, coupling="additive", coarse="rgdsw").solve()
     assert rc == 0 and st["outer_its"] == st_ref["outer"]
     assert np.linalg.norm(_np(uu) - u_ref) <= 1e-10 * np.linalg.norm(u_ref)
+
+
+@pytest.mark.parametrize("variant", [1, 2, 3])
+def test_lu_variants_elasticity(variant):
+    """Each band LU form on Neo-Hooke Jacobians under load, whose pivoting
+    interchanges rows (unlike the diagonally dominant diffusion Jacobians):
+    F_x, inner iteration counts and the tangent as in the oracle."""
+    case = synth.small_elasticity_case(nx=16, ny=8, boxes=(2, 2), overlap=2,
+                                       traction=(1.0, -4.0), two_level=True)
+    P = NHProblem(case)
+    S = Schwarz(P, "additive")
+    s = _solver(case, coupling="additive", lu_variant=variant)
+    u = _probe(P, 9)
+    _close(_np(s.precond_residual(u)), S.evaluate(u), 1e-10)
+    np.testing.assert_array_equal(s.inner_iterations(), [sol["its"] for sol in S.state["sols"]])
+    v = np.random.default_rng(10).normal(size=P.ndof)
+    _close(_np(s.tangent(v)), S.tangent(v), 1e-10)
