@@ -9,6 +9,9 @@ Follows Section 2 of the paper:
     a GDSW coarse space (energy-minimising extension of interface indicator
     functions) and R_0 = P_0^T;
   * additive coupling F_a(u) = F_1(u) + P_0 T_0(u) (eq. 10);
+  * hybrid coupling F_h(u) = F_1(u - P_0 T_0(u)) + P_0 T_0(u) (eq. 11): the
+    coarse correction first, then the local corrections at the coarse-
+    corrected point;
   * the exact tangents (eqs. 6, 7, 12) and the outer Newton iteration on the
     tangent system (eq. 13), solved by restarted GMRES.
 
@@ -54,13 +57,14 @@ class Schwarz:
     """RASPEN with optional GDSW coarse level for one problem (P1Problem or
     NHProblem: d dofs per node, element_local, residual, jacobian).
 
-    coupling: "one_level" (F_1, eq. 5) or "additive" (F_a, eq. 10).
+    coupling: "one_level" (F_1, eq. 5), "additive" (F_a, eq. 10) or
+    "hybrid" (F_h, eq. 11).
     """
 
     def __init__(self, problem: P1Problem, coupling: str = "one_level",
                  inner_rtol=1e-12, inner_eta=1e-10, inner_maxit=30,
                  stagnation=1e-14, coarse="gdsw"):
-        if coupling not in ("one_level", "additive"):
+        if coupling not in ("one_level", "additive", "hybrid"):
             raise ValueError(coupling)
         self.P = problem
         self.case = problem.case
@@ -75,7 +79,7 @@ class Schwarz:
         if coarse not in ("gdsw", "rgdsw"):
             raise ValueError(coarse)
         self.coarse = coarse
-        if coupling == "additive":
+        if coupling in ("additive", "hybrid"):
             self._build_gdsw()
         self.state = None
 
@@ -472,49 +476,73 @@ class Schwarz:
                 "DF0": DF0, "its": its, "A0": A0}
 
     # --------------------------------------------------------- combinations
-    def evaluate(self, u, guesses=None):
+    def evaluate(self, u, guesses=None, predictor=None):
         """F_x(u) for the configured coupling; keeps the state for the tangent.
 
-        guesses: optional per-subdomain predicted starts (see local_solve)."""
-        Fx, sols = self.F1(u, guesses=guesses)
+        guesses: optional per-subdomain predicted starts (see local_solve);
+        predictor: alternatively an object whose guesses(w) gives them at the
+        point w where the local problems are solved."""
         co = None
+        w = u
+        if self.coupling == "hybrid":
+            # eq. (11): T_0 first; the local corrections at u_0 = u - P_0 T_0(u)
+            co = self.coarse_solve(u)
+            w = u - self.Phi @ co["c"]
+        if predictor is not None:
+            guesses = predictor.guesses(w)
+        Fx, sols = self.F1(w, guesses=guesses)
         if self.coupling == "additive":
             co = self.coarse_solve(u)
+        if co is not None:
             Fx = Fx + self.Phi @ co["c"]
-        self.state = {"u": u.copy(), "sols": sols, "coarse": co}
+        self.state = {"u": w.copy(), "sols": sols, "coarse": co}
         return Fx
 
     def tangent(self, v):
         """D F_x(u) v at the last evaluated u, using R_i DF(u_i) v =
         J_ii R_i v + B_i v_Gamma and the partition of unity (eq. 8):
-        D F_a v = v + sum_i P~_i J_ii^{-1} B_i v_Gamma_i
-                    + Phi A0^{-1} Phi^T DF(u_0) v      (eqs. 6, 7, 12)."""
+        D F_1 v = v + sum_i P~_i J_ii^{-1} B_i v_Gamma_i      (eqs. 6, 7),
+        D F_a v = D F_1 v + q,  q = Q_0 v = Phi A0^{-1} Phi^T DF(u_0) v,
+        D F_h v = D F_1 (v - q) + q                        (eq. 12), where
+        D F_1 is taken at the local states of the last evaluation (at u_0
+        for the hybrid coupling)."""
         st = self.state
-        y = v.copy()
-        for s, sol in zip(self.subs, st["sols"]):
-            z = sla.lu_solve(sol["lu"], sol["B"] @ v[s["Gd"]])
-            y[s["owned"]] += z[s["owned_loc"]]
         co = st["coarse"]
+        q = None
         if co is not None:
-            y += self.Phi @ sla.lu_solve(co["lu"], self.PhiT @ (co["DF0"] @ v))
+            q = self.Phi @ sla.lu_solve(co["lu"], self.PhiT @ (co["DF0"] @ v))
+        z = v - q if self.coupling == "hybrid" else v
+        y = z.copy()
+        for s, sol in zip(self.subs, st["sols"]):
+            zz = sla.lu_solve(sol["lu"], sol["B"] @ z[s["Gd"]])
+            y[s["owned"]] += zz[s["owned_loc"]]
+        if q is not None:
+            y += q
         return y
 
     def tangent_literal(self, v):
-        """The same tangent from its definition, sum_i P~_i (R_i DF(u_i) P_i)^-1
-        R_i DF(u_i) v + P_0 DT_0 v, with DF(u_i) assembled globally at
-        u_i = u - P_i T_i(u) (eqs. 6, 7)."""
+        """The same tangent from its definition: with Q_i(w) = P~_i (R_i DF(w)
+        P_i)^-1 R_i DF(w) and DF assembled globally at the local states
+        u_i = u - P_i T_i(u) (eqs. 6, 7),
+        additive: sum_i Q_i(u_i) v + Q_0(u_0) v,
+        hybrid:   sum_i Q_i(v_i) (I - Q_0(u_0)) v + Q_0(u_0) v with
+                  v_i = u_0 - P_i T_i(u_0) (eq. 12)."""
         st = self.state
         P = self.P
+        co = st["coarse"]
+        q = None
+        if co is not None:
+            q = self.Phi @ sla.lu_solve(co["lu"], self.PhiT @ (co["DF0"] @ v))
+        z = v - q if self.coupling == "hybrid" else v
         y = np.zeros_like(v)
         for s, sol in zip(self.subs, st["sols"]):
             ui = st["u"].copy()
             ui[s["Vd"]] = sol["x"]
-            w = (P.jacobian(ui) @ v)[s["Vd"]]
-            z = sla.lu_solve(sol["lu"], w)
-            y[s["owned"]] += z[s["owned_loc"]]
-        co = st["coarse"]
-        if co is not None:
-            y += self.Phi @ sla.lu_solve(co["lu"], self.PhiT @ (co["DF0"] @ v))
+            w = (P.jacobian(ui) @ z)[s["Vd"]]
+            zz = sla.lu_solve(sol["lu"], w)
+            y[s["owned"]] += zz[s["owned_loc"]]
+        if q is not None:
+            y += q
         return y
 
     def solve(self, u0=None, rtol=1e-8, maxit=50, gmres_rtol=1e-6,
@@ -525,8 +553,7 @@ class Schwarz:
         predictor: optional object whose guesses(u) gives the learned starts
         of the local solves (oracle.guess.Predictor)."""
         def ev(u):
-            g = predictor.guesses(u) if predictor is not None else None
-            return self.evaluate(u, guesses=g)
+            return self.evaluate(u, predictor=predictor)
         u = np.zeros(self.P.ndof) if u0 is None else np.array(u0, dtype=np.float64)
         Fx = ev(u)
         r0 = float(np.linalg.norm(Fx))

@@ -50,9 +50,13 @@ def test_partition_of_unity(overlap, uneven):
     np.testing.assert_array_equal(acc, v)
 
 
-def _ras_matrix(A, S, with_coarse):
-    """M^-1 = sum_i P~_i (R_i A R_i^T)^-1 R_i (+ Phi (Phi^T A Phi)^-1 Phi^T),
-    from the globally assembled A (independent of the local assembly)."""
+def _ras_matrix(A, S, coupling):
+    """M^-1 of linear restricted Schwarz from the globally assembled A
+    (independent of the local assembly), with M_1 = sum_i P~_i (R_i A R_i^T)^-1
+    R_i and C_0 = Phi (Phi^T A Phi)^-1 Phi^T:
+      one_level M_1;  additive M_1 + C_0;  hybrid M_1 (I - A C_0) + C_0
+    (coarse correction first, then the local solves on the corrected
+    residual)."""
     N = A.shape[0]
     Ad = A.toarray()
     M = np.zeros((N, N))
@@ -64,13 +68,16 @@ def _ras_matrix(A, S, with_coarse):
         Rm = np.zeros((len(V), N))
         Rm[np.arange(len(V)), V] = 1.0
         M += Pt @ Ainv @ Rm
-    if with_coarse:
+    if coupling != "one_level":
         Phi = S.Phi.toarray()
-        M += Phi @ np.linalg.inv(Phi.T @ Ad @ Phi) @ Phi.T
+        C0 = Phi @ np.linalg.inv(Phi.T @ Ad @ Phi) @ Phi.T
+        if coupling == "hybrid":
+            M = M @ (np.eye(N) - Ad @ C0)
+        M += C0
     return M
 
 
-@pytest.mark.parametrize("coupling", ["one_level", "additive"])
+@pytest.mark.parametrize("coupling", ["one_level", "additive", "hybrid"])
 def test_linear_reduction_to_ras(coupling):
     """beta = 0: T_i(u) = J_ii^-1 R_i (A u - b) and F_x(u) = M^-1 (A u - b)
     with M^-1 the (two-level additive) RAS preconditioner; the outer Newton
@@ -83,7 +90,7 @@ def test_linear_reduction_to_ras(coupling):
     A = P.jacobian(np.zeros(P.N))
     res = A @ u - P.b
     Fx = S.evaluate(u)
-    M = _ras_matrix(A, S, coupling == "additive")
+    M = _ras_matrix(A, S, coupling)
     np.testing.assert_allclose(Fx, M @ res, rtol=0, atol=1e-13 * np.abs(M @ res).max())
     for sol in S.state["sols"]:
         assert sol["its"] <= 2
@@ -97,7 +104,7 @@ def test_linear_reduction_to_ras(coupling):
     assert np.abs(usol - uex).max() <= 1e-11 * np.abs(uex).max()
 
 
-@pytest.mark.parametrize("coupling", ["one_level", "additive"])
+@pytest.mark.parametrize("coupling", ["one_level", "additive", "hybrid"])
 @pytest.mark.parametrize("n,boxes,overlap", [(8, 2, 1), (12, 3, 1), (12, 3, 2), (13, 3, 2)])
 def test_fixed_point_is_global_solution(coupling, n, boxes, overlap):
     """If F(u*) = 0 then every T_i(u*) = 0 and T_0(u*) = 0 (eqs. 4, 9), so
@@ -147,7 +154,7 @@ def test_coarse_linear_one_step():
     np.testing.assert_allclose(co["c"], ref, rtol=0, atol=1e-13 * np.abs(ref).max())
 
 
-@pytest.mark.parametrize("coupling", ["one_level", "additive"])
+@pytest.mark.parametrize("coupling", ["one_level", "additive", "hybrid"])
 def test_tangent_identity_literal_and_fd(coupling):
     P, S = _schwarz(coupling, n=10, boxes=2, overlap=1, forcing_seed=6,
                     coef_seed=1)
