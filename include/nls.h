@@ -59,6 +59,9 @@ extern "C" {
 
 #define NLS_ONE_LEVEL     0   /* F_1(u) = sum_i P~_i T_i(u), eq. (5) with (8) */
 #define NLS_ADDITIVE      1   /* F_a(u) = F_1(u) + P_0 T_0(u), eq. (10) */
+#define NLS_HYBRID        2   /* F_h(u) = F_1(u - P_0 T_0(u)) + P_0 T_0(u), eq. (11):
+                                 coarse correction first, local corrections at
+                                 the coarse-corrected point; tangent eq. (12) */
 
 #define NLS_COARSE_NONE   0
 #define NLS_COARSE_GDSW   1   /* vertex + edge components, harmonic extension */
@@ -71,7 +74,7 @@ typedef struct nls_options {
     int    device;        /* HIP device ordinal */
     void*  stream;        /* hipStream_t to run on; NULL = the null stream */
     int    precision;     /* NLS_PREC_* */
-    int    coupling;      /* NLS_ONE_LEVEL or NLS_ADDITIVE */
+    int    coupling;      /* NLS_ONE_LEVEL, NLS_ADDITIVE or NLS_HYBRID */
     double outer_rtol;    /* stop when ||F_x(u_k)||_2 <= outer_rtol ||F_x(u_0)||_2 */
     int    outer_maxit;
     double inner_rtol;    /* local/coarse Newton: ||r||_2 <= max(inner_rtol rho_0,  */

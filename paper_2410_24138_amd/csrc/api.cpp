@@ -45,7 +45,9 @@ extern "C" int nls_create(const nls_options* opt, nls_handle** out) {
     if (opt && (opt->lu_variant < 0 || opt->lu_variant > 3)) return NLS_EINVAL;
     if (!opt || !out) return NLS_EINVAL;
     if (opt->precision != NLS_PREC_FP64 && opt->precision != NLS_PREC_FP32_IR) return NLS_EINVAL;
-    if (opt->coupling != NLS_ONE_LEVEL && opt->coupling != NLS_ADDITIVE) return NLS_EINVAL;
+    if (opt->coupling != NLS_ONE_LEVEL && opt->coupling != NLS_ADDITIVE &&
+        opt->coupling != NLS_HYBRID)
+        return NLS_EINVAL;
     if (opt->gmres_restart < 1 || opt->gmres_maxit < 1 || opt->outer_maxit < 0 ||
         opt->outer_maxit > NLS_MAX_OUTER || opt->inner_maxit < 1)
         return NLS_EINVAL;
@@ -435,6 +437,7 @@ extern "C" int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* el
     RC(h->alloc(G_MAPS, &h->Fx, N));
     RC(h->alloc(G_MAPS, &h->du, N));
     RC(h->alloc(G_MAPS, &h->tmp, N));
+    RC(h->alloc(G_MAPS, &h->zbuf, N));
     RC(h->alloc(G_MAPS, &h->ydev, h->m + 2));
     RC(h->alloc(G_MAPS, &h->ubuf, N));
     RC(h->alloc(G_MAPS, &h->stat2, 2));
@@ -446,9 +449,6 @@ extern "C" int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* el
     RC(h->alloc(G_MAPS, &h->gst, 2));
     RC(sync(h));
     h->have_part = true;
-    if (h->opt.coupling == NLS_ADDITIVE) {
-        // a two-level handle needs nls_build_coarse before solving
-    }
     return NLS_OK;
 }
 
@@ -684,7 +684,7 @@ int guess_after_local(nls_handle* h, const double* u);
 
 // ------------------------------------------------------------ evaluation
 static bool two_level(nls_handle* h) {
-    return h->opt.coupling == NLS_ADDITIVE && h->have_coarse && h->co.n0 > 0;
+    return h->opt.coupling != NLS_ONE_LEVEL && h->have_coarse && h->co.n0 > 0;
 }
 
 // Coarse Newton iteration for T_0(u) (eq. 9): c <- c + A0^{-1} Phi^T F(u - Phi c)
@@ -744,10 +744,29 @@ static int dot_host(nls_handle* h, const double* x, const double* y, int n, doub
     return sync(h);
 }
 
+static int coarse_phase(nls_handle* h, const double* u) {
+    Timer tc;
+    int cits = 0;
+    RC(coarse_solve(h, u, &cits));
+    RC(sync(h));
+    if (h->st) {
+        h->st->ms_coarse += tc.ms();
+        h->st->coarse_its_total += cits;
+    }
+    return NLS_OK;
+}
+
 // F_x(u) into Fx (device); keeps local and coarse states for the tangent.
+// Hybrid coupling (eq. 11): T_0(u) first, and the local problems are solved
+// at u_0 = u - P_0 T_0(u), which the coarse solve leaves in dc.w.
 static int evaluate(nls_handle* h, const double* u, double* Fx) {
-    Timer t;
     h->have_state = false;
+    const bool hybrid = h->opt.coupling == NLS_HYBRID && two_level(h);
+    if (hybrid) {
+        RC(coarse_phase(h, u));
+        u = h->dc.w;
+    }
+    Timer t;
     NewtonParams np = h->np;
     np.xpred = nullptr;
     if (guess_enabled(h)) RC(guess_prepare(h, u, &np.xpred));
@@ -790,14 +809,7 @@ static int evaluate(nls_handle* h, const double* u, double* Fx) {
     }
     RC(guess_after_local(h, u));
     if (two_level(h)) {
-        Timer tc;
-        int cits = 0;
-        RC(coarse_solve(h, u, &cits));
-        RC(sync(h));
-        if (h->st) {
-            h->st->ms_coarse += tc.ms();
-            h->st->coarse_its_total += cits;
-        }
+        if (!hybrid) RC(coarse_phase(h, u));
         HIPCHK(launch_prolong(h->dm, h->dp, h->dl.T, &h->dc, h->dc.c, Fx, nullptr, h->stream));
     } else {
         HIPCHK(launch_prolong(h->dm, h->dp, h->dl.T, nullptr, nullptr, Fx, nullptr, h->stream));
@@ -953,15 +965,8 @@ static int tangent(nls_handle* h, const double* v, double* y, hipStream_t s = nu
         e1 = h->take_event();
         HIPCHK(hipEventRecord(e0, s));
     }
-    if (h->tangent_w)
-        HIPCHK(launch_tangent_gemv(h->dp, h->dt, v, h->dl.z, h->max_ng, s));
-    else
-        HIPCHK(launch_tangent_local(h->dm, h->dp, h->dl, h->np, v, h->lds_tangent, h->npl_local, s));
-    if (e0) {
-        HIPCHK(hipEventRecord(e1, s));
-        h->ev_used.push_back({1, {e0, e1}});
-    }
-    if (two_level(h)) {
+    // coarse term q = Q_0 v = Phi A0^{-1} Phi^T DF(u_0) v, as coefficients in ctmp
+    auto coarse_term = [&]() -> int {
         DevCoarse& d = h->dc;
         HIPCHK(launch_coarse_ty(d, v, s));
         HIPCHK(launch_coarse_assemble(d, 0, s));
@@ -972,7 +977,28 @@ static int tangent(nls_handle* h, const double* v, double* y, hipStream_t s = nu
             HIPCHK(launch_coarse_lu(d, 0, h->lds_coarse_lu, h->npl_coarse, s));
             HIPCHK(launch_coarse_scatter(d, nullptr, h->ctmp, s));
         }
-        HIPCHK(launch_prolong(h->dm, h->dp, h->dl.z, &d, h->ctmp, y, v, s));
+        return NLS_OK;
+    };
+    // Hybrid (eq. 12): D F_h v = D F_1 (v - q) + q = v + sum_i P~_i J_ii^{-1}
+    // B_i (v - q)_Gamma_i, so the local term acts on z = v - q.
+    const bool hybrid = h->opt.coupling == NLS_HYBRID && two_level(h);
+    const double* vloc = v;
+    if (hybrid) {
+        RC(coarse_term());
+        HIPCHK(launch_sub_coarse(h->dm, h->dc, h->ctmp, v, h->zbuf, s));
+        vloc = h->zbuf;
+    }
+    if (h->tangent_w)
+        HIPCHK(launch_tangent_gemv(h->dp, h->dt, vloc, h->dl.z, h->max_ng, s));
+    else
+        HIPCHK(launch_tangent_local(h->dm, h->dp, h->dl, h->np, vloc, h->lds_tangent, h->npl_local, s));
+    if (e0) {
+        HIPCHK(hipEventRecord(e1, s));
+        h->ev_used.push_back({1, {e0, e1}});
+    }
+    if (two_level(h) && !hybrid) {
+        RC(coarse_term());
+        HIPCHK(launch_prolong(h->dm, h->dp, h->dl.z, &h->dc, h->ctmp, y, v, s));
     } else {
         HIPCHK(launch_prolong(h->dm, h->dp, h->dl.z, nullptr, nullptr, y, v, s));
     }
@@ -1223,7 +1249,7 @@ static int gmres(nls_handle* h, const double* b, double* x, int* its_out) {
 extern "C" int nls_solve(nls_handle* h, double* u, int u_on_device, nls_stats* st) {
     if (!h || !u) return NLS_EINVAL;
     if (!h->have_part) return fail(h, NLS_ESTATE, "nls_set_partition first");
-    if (h->opt.coupling == NLS_ADDITIVE && !h->have_coarse)
+    if (h->opt.coupling != NLS_ONE_LEVEL && !h->have_coarse)
         return fail(h, NLS_ESTATE, "two-level coupling needs nls_build_coarse");
     HIPCHK(hipSetDevice(h->opt.device));
     Timer ttot;
@@ -1334,7 +1360,7 @@ extern "C" int nls_eval_residual(nls_handle* h, const double* u, double* F) {
 extern "C" int nls_eval_precond_residual(nls_handle* h, const double* u, double* Fx) {
     if (!h || !u || !Fx) return NLS_EINVAL;
     if (!h->have_part) return fail(h, NLS_ESTATE, "nls_set_partition first");
-    if (h->opt.coupling == NLS_ADDITIVE && !h->have_coarse)
+    if (h->opt.coupling != NLS_ONE_LEVEL && !h->have_coarse)
         return fail(h, NLS_ESTATE, "two-level coupling needs nls_build_coarse");
     HIPCHK(hipSetDevice(h->opt.device));
     h->coarse_lu_valid = false;

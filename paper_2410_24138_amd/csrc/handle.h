@@ -69,7 +69,7 @@ struct nls_handle {
     // GMRES / outer workspace
     int m = 0;
     double *V = nullptr, *wv = nullptr, *hbuf = nullptr, *hbuf2 = nullptr, *hn2 = nullptr,
-           *partial = nullptr, *Fx = nullptr, *du = nullptr, *tmp = nullptr, *ctmp = nullptr,
+           *partial = nullptr, *Fx = nullptr, *du = nullptr, *tmp = nullptr, *zbuf = nullptr, *ctmp = nullptr,
            *ydev = nullptr, *ubuf = nullptr;
     int* stat2 = nullptr;
     int nb_dot = 0;

@@ -1459,6 +1459,20 @@ __global__ void k_prolong(int N, const int* __restrict__ own_pidx, const double*
     out[g] = y;
 }
 
+// out = v - Phi c: the coarse prolongation subtracted from v, one thread per
+// dof (the rows of Phi held by the dof's owner, as in k_prolong).
+__global__ void k_sub_coarse(int N, DevCoarse C, const double* __restrict__ cvec,
+                             const double* __restrict__ v, double* __restrict__ out) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= N) return;
+    const int o = C.cown[g];
+    const int k0 = C.off_k[o], nk = C.off_k[o + 1] - k0;
+    const double* ph = C.phi + C.off_phi[o] + (int64_t)(C.cpos[g] - C.off_c[o]) * nk;
+    double acc = 0.0;
+    for (int l = 0; l < nk; ++l) acc += ph[l] * cvec[C.klist[k0 + l]];
+    out[g] = v[g] - acc;
+}
+
 // Global residual F(u) (eq. 3): node-centric over incident elements.
 __global__ void k_global_residual(DevMesh M, const double* __restrict__ u, double* __restrict__ F) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -2215,6 +2229,12 @@ hipError_t launch_prolong(const DevMesh& M, const DevMaps& P, const double* T,
     DevCoarse dummy{};
     k_prolong<<<nblocks(M.ndof), NLS_BLOCK, 0, s>>>(M.ndof, P.own_pidx, T, addv, C ? *C : dummy,
                                                  C ? 1 : 0, cvec, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_sub_coarse(const DevMesh& M, const DevCoarse& C, const double* cvec,
+                             const double* v, double* out, hipStream_t s) {
+    k_sub_coarse<<<nblocks(M.ndof), NLS_BLOCK, 0, s>>>(M.ndof, C, cvec, v, out);
     return hipGetLastError();
 }
 

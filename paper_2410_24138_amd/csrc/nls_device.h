@@ -129,6 +129,9 @@ hipError_t launch_prolong(const DevMesh& M, const DevMaps& P, const double* T,
 hipError_t launch_tangent_local(const DevMesh& M, const DevMaps& P, const DevLocal& L,
                                 const NewtonParams& np, const double* v, int lds_bytes,
                                 int nb_per_lane, hipStream_t s);
+// out = v - Phi c over all dofs (hybrid tangent)
+hipError_t launch_sub_coarse(const DevMesh& M, const DevCoarse& C, const double* cvec,
+                             const double* v, double* out, hipStream_t s);
 hipError_t launch_gdsw_extend(const DevMesh& M, const DevCoarse& C, int lds_bytes,
                               int nb_per_lane, hipStream_t s);
 hipError_t launch_coarse_w(const DevMesh& M, const DevCoarse& C, const double* u,

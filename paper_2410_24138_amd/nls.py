@@ -35,6 +35,7 @@ PREC_FP64 = 0
 PREC_FP32_IR = 1
 ONE_LEVEL = 0
 ADDITIVE = 1
+HYBRID = 2
 COARSE_NONE = 0
 COARSE_GDSW = 1
 COARSE_RGDSW = 2
@@ -244,7 +245,7 @@ def default_options() -> Options:
 class Solver:
     """One libnls handle set up for an input case (see synth.diffusion_case).
 
-    coupling: "one_level" or "additive"; precision: "fp64" or "fp32_ir".
+    coupling: "one_level", "additive" or "hybrid"; precision: "fp64" or "fp32_ir".
     Options not given keep the library defaults.
     """
 
@@ -262,7 +263,7 @@ class Solver:
         o.stream = ctypes.c_void_p(int(stream))
         if coupling is None:
             coupling = "additive" if case.get("two_level") else "one_level"
-        o.coupling = {"one_level": ONE_LEVEL, "additive": ADDITIVE}[coupling]
+        o.coupling = {"one_level": ONE_LEVEL, "additive": ADDITIVE, "hybrid": HYBRID}[coupling]
         o.precision = {"fp64": PREC_FP64, "fp32_ir": PREC_FP32_IR}[precision]
         for k, v in opts.items():
             setattr(o, k, v)
@@ -299,7 +300,7 @@ class Solver:
         part = np.ascontiguousarray(case["elem_part"], dtype=np.int32)
         self._check(self.lib.nls_set_partition(h, int(case["n_sub"]), _ptr(part),
                                                int(case["overlap"])))
-        if coupling == "additive":
+        if coupling in ("additive", "hybrid"):
             kind = {"gdsw": COARSE_GDSW, "rgdsw": COARSE_RGDSW}[coarse]
             self._check(self.lib.nls_build_coarse(h, kind))
 

@@ -179,3 +179,23 @@ def test_lu_variants_elasticity(variant):
     np.testing.assert_array_equal(s.inner_iterations(), [sol["its"] for sol in S.state["sols"]])
     v = np.random.default_rng(10).normal(size=P.ndof)
     _close(_np(s.tangent(v)), S.tangent(v), 1e-10)
+
+
+@pytest.mark.parametrize("coarse", ["gdsw", "rgdsw"])
+def test_hybrid_elasticity(coarse):
+    """Hybrid coupling (eq. 11) on Neo-Hooke: F_h, the tangent (eq. 12) and
+    the outer iteration as in the oracle."""
+    case = synth.small_elasticity_case(nx=16, ny=8, boxes=(4, 2), overlap=1,
+                                       traction=(0.5, -3.0), two_level=True)
+    P = NHProblem(case)
+    S = Schwarz(P, "hybrid", coarse=coarse)
+    s = _solver(case, coupling="hybrid", coarse=coarse)
+    u = _probe(P, 11)
+    _close(_np(s.precond_residual(u)), S.evaluate(u), 1e-10)
+    np.testing.assert_array_equal(s.inner_iterations(), [sol["its"] for sol in S.state["sols"]])
+    v = np.random.default_rng(12).normal(size=P.ndof)
+    _close(_np(s.tangent(v)), S.tangent(v), 1e-10)
+    u_ref, st_ref = S.solve()
+    uu, st, rc = _solver(case, coupling="hybrid", coarse=coarse).solve()
+    assert rc == 0 and st["outer_its"] == st_ref["outer"]
+    assert np.linalg.norm(_np(uu) - u_ref) <= 1e-10 * np.linalg.norm(u_ref)

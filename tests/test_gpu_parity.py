@@ -74,10 +74,10 @@ def _probe_point(P, case, scale=0.5, seed=1):
     return u
 
 
-@pytest.mark.parametrize("coupling", ["one_level", "additive"])
+@pytest.mark.parametrize("coupling", ["one_level", "additive", "hybrid"])
 @pytest.mark.parametrize("kw", SMALL)
 def test_precond_residual_and_tangent(kw, coupling):
-    case = synth.small_case(two_level=(coupling == "additive"), **kw)
+    case = synth.small_case(two_level=(coupling != "one_level"), **kw)
     P = P1Problem(case)
     S = Schwarz(P, coupling)
     s = _solver(case, coupling=coupling)
@@ -104,12 +104,12 @@ def test_coarse_basis(kw):
     _close(Phi, S.Phi.toarray(), 1e-12)
 
 
-@pytest.mark.parametrize("coupling", ["one_level", "additive"])
+@pytest.mark.parametrize("coupling", ["one_level", "additive", "hybrid"])
 @pytest.mark.parametrize("kw", [dict(n=12, boxes=3, overlap=1),
                                 dict(n=24, boxes=4, overlap=2, forcing_seed=2),
                                 dict(n=21, boxes=3, overlap=1, uneven=True, coef_seed=3)])
 def test_solve_matches_oracle(kw, coupling):
-    case = synth.small_case(two_level=(coupling == "additive"), **kw)
+    case = synth.small_case(two_level=(coupling != "one_level"), **kw)
     P = P1Problem(case)
     S = Schwarz(P, coupling)
     u_ref, st_ref = S.solve()
@@ -226,7 +226,7 @@ def test_batch_of_instances():
     assert np.linalg.norm(uu - u_ref) <= 1e-10 * np.linalg.norm(u_ref)
 
 
-@pytest.mark.parametrize("coupling", ["one_level", "additive"])
+@pytest.mark.parametrize("coupling", ["one_level", "additive", "hybrid"])
 def test_graph_gmres_matches_step_by_step(coupling):
     """GMRES with device-side rotations and graph-replayed Arnoldi blocks:
     same outer and GMRES counts and the same solution as the step-by-step
@@ -234,7 +234,7 @@ def test_graph_gmres_matches_step_by_step(coupling):
     solves, with eager work in between, and give identical results."""
     from paper_2410_24138_amd import nls
     case = synth.small_case(n=32, boxes=4, overlap=2, forcing_seed=7, coef_seed=2,
-                            two_level=(coupling == "additive"))
+                            two_level=(coupling != "one_level"))
     ue, ste, _ = _solver(case, coupling=coupling).solve()
     sg = _solver(case, coupling=coupling, flags=nls.FLAG_GRAPH)
     ug1, stg1, rc = sg.solve()
