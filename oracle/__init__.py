@@ -15,11 +15,14 @@ Layout
               lifting, training targets, the network, Adam, the judge.
   schwarz.py  overlapping subdomains and transfer operators, local nonlinear
               corrections T_i (eq. 4), RASPEN residual (eqs. 5, 8), GDSW
-              coarse space, coarse correction T_0 (eq. 9), additive coupling
-              (eq. 10), exact tangents (eqs. 6, 7, 12), GMRES and the outer
+              and RGDSW coarse spaces, coarse correction T_0 (eq. 9),
+              additive and hybrid couplings (eqs. 10, 11), exact tangents
+              (eqs. 6, 7, 12), GMRES and the outer
               Newton iteration on the tangent system (eq. 13), and a
               brute-force global Newton solve as the plain definition of the
               end result; load stepping.
+  nks.py      the Newton-Krylov-Schwarz comparator: Newton on F(u) = 0 with
+              GMRES right-preconditioned by linear two-level Schwarz.
 
 Every function cites the passage of the paper it follows; where the paper is
 silent the docstring states the reading taken.  Pins (independent checks of
@@ -28,3 +31,4 @@ this code against mathematics) live in tests/test_oracle_*.py.
 from .nh import NHProblem  # noqa: F401
 from .p1 import P1Problem  # noqa: F401
 from .schwarz import Schwarz, gmres_mgs, global_newton  # noqa: F401
+from .nks import NKS  # noqa: F401
