@@ -253,6 +253,19 @@ int nls_solve(nls_handle* h, double* u, int u_on_device, nls_stats* st);
 int nls_solve_load_steps(nls_handle* h, double* u, int u_on_device, int n_steps,
                          nls_stats* st);
 
+/* Newton-Krylov-Schwarz comparator (Section 3 of the paper, the beam test):
+   Newton's method on F(u) = 0 itself; each step solves DF(u_k) du = F(u_k)
+   by GMRES right-preconditioned with linear restricted additive Schwarz
+   built at u_k: M^{-1} = sum_i P~_i (R_i DF(u_k) P_i)^{-1} R_i, plus
+   Phi (Phi^T DF(u_k) Phi)^{-1} Phi^T on a two-level handle (the coarse
+   basis of nls_build_coarse); u_{k+1} = u_k - du.  Same subdomains, band
+   LU (FP64), GMRES and stopping rules as nls_solve, with ||F(u_k)||_2 in
+   place of ||F_x(u_k)||_2.  u and st as for nls_solve (inner_its_total and
+   local_solves stay 0; ms_inner / ms_coarse time the factorisations).
+   Overwrites the state kept for nls_apply_tangent.  Returns NLS_OK,
+   NLS_ENOCONV, NLS_ESINGULAR (zero pivot), NLS_ENAN, or an error. */
+int nls_solve_nks(nls_handle* h, double* u, int u_on_device, nls_stats* st);
+
 /* ---- hooks at the internal boundaries (device pointers) --------------- */
 
 /* F(u) (eq. (3)), n_nodes values. */

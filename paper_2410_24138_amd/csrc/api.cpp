@@ -956,9 +956,12 @@ static int autotune_coarse(nls_handle* h) {
 // y = D F_x(u) v (eqs. 6, 7, 12) at the last evaluated point.
 // Enqueued on s (the handle's stream by default); no host synchronisation,
 // so the sequence can be captured into a graph (events only when eager).
+static int nks_apply(nls_handle* h, const double* x, double* y, hipStream_t s);
+
 static int tangent(nls_handle* h, const double* v, double* y, hipStream_t s = nullptr) {
     const bool eager = s == nullptr;
     if (eager) s = h->stream;
+    if (h->nks_mode) return nks_apply(h, v, y, s);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (eager && h->profiling()) {
         e0 = h->take_event();
@@ -1040,7 +1043,7 @@ static int arnoldi_step(nls_handle* h, int j, hipStream_t s) {
 }
 
 static bool graph_gmres_ok(const nls_handle* h) {
-    return (h->opt.flags & NLS_FLAG_GRAPH) && h->tangent_w;
+    return (h->opt.flags & NLS_FLAG_GRAPH) && h->tangent_w && !h->nks_mode;
 }
 
 // Steps [b*K, min((b+1)*K, m)) of a cycle as one graph, captured on first use.
@@ -1165,7 +1168,7 @@ static int gmres_graph(nls_handle* h, const double* b, double* x, int* its_out) 
 // Restarted GMRES(m) for D F_x(u) x = b from x = 0 (classical Gram-Schmidt
 // with one reorthogonalisation).  Returns the iteration count in *its.
 static int gmres(nls_handle* h, const double* b, double* x, int* its_out) {
-    RC(prepare_tangent(h));
+    if (!h->nks_mode) RC(prepare_tangent(h));
     const int N = h->mesh.ndof(), m = h->m;
     const int64_t ld = N;
     double bn2 = 0.0;
@@ -1346,6 +1349,145 @@ extern "C" int nls_solve_load_steps(nls_handle* h, double* u, int u_on_device, i
     int r2 = nodal ? upload_nodal_load(h, full.data())
                    : nls_set_load(h, had_samples ? full.data() : nullptr);
     return rc ? rc : r2;
+}
+
+// ------------------------------------------------ Newton-Krylov-Schwarz
+// y = DF(u) M^{-1} x with the linear Schwarz preconditioner M^{-1} x =
+// sum_i P~_i J_ii(u)^{-1} R_i x (+ Phi A0(u)^{-1} Phi^T x) factored at the
+// current iterate (h->nks_u); M^{-1} x is left in h->zbuf.
+static int nks_precond(nls_handle* h, const double* x, hipStream_t s) {
+    NewtonParams np = h->np;
+    np.mixed = 0;
+    HIPCHK(launch_tangent_local(h->dm, h->dp, h->dl, np, x, h->lds_tangent, h->npl_local, s, 1));
+    if (two_level(h)) {
+        DevCoarse& d = h->dc;
+        HIPCHK(launch_coarse_phit(d, x, s));
+        HIPCHK(launch_coarse_assemble(d, 0, s));
+        if (h->coarse_inv) {
+            HIPCHK(launch_coarse_apply_inverse(d, d.rhs, h->rhs2, s));
+            HIPCHK(launch_coarse_scatter(d, h->rhs2, h->ctmp, s));
+        } else {
+            HIPCHK(launch_coarse_lu(d, 0, h->lds_coarse_lu, h->npl_coarse, s));
+            HIPCHK(launch_coarse_scatter(d, nullptr, h->ctmp, s));
+        }
+        HIPCHK(launch_prolong(h->dm, h->dp, h->dl.z, &d, h->ctmp, h->zbuf, nullptr, s));
+    } else {
+        HIPCHK(launch_prolong(h->dm, h->dp, h->dl.z, nullptr, nullptr, h->zbuf, nullptr, s));
+    }
+    return NLS_OK;
+}
+
+static int nks_apply(nls_handle* h, const double* x, double* y, hipStream_t s) {
+    RC(nks_precond(h, x, s));
+    HIPCHK(launch_global_jv(h->dm, h->nks_u, h->zbuf, y, s));
+    return NLS_OK;
+}
+
+// Factorisations of the preconditioner at u: J_ii(u) per subdomain (FP64
+// band LU) and, on a two-level handle, A0(u) = Phi^T DF(u) Phi.
+static int nks_factor(nls_handle* h, const double* u) {
+    Timer t;
+    NewtonParams np = h->np;
+    np.mixed = 0;
+    for (size_t b = 0; b < h->bk_start.size(); ++b) {
+        DevMaps pb = h->dp;
+        pb.order = h->dp.order + h->bk_start[b];
+        np.lu_variant = h->bk_var[b];
+        HIPCHK(launch_local_factor(h->dm, pb, h->dl, np, u, h->bk_end[b] - h->bk_start[b],
+                                   h->bk_lds[b], h->stream));
+    }
+    HIPCHK(launch_any_status(h->dl.status, h->maps.nsub, h->stat2, h->stream));
+    int st2[2];
+    HIPCHK(hipMemcpyAsync(st2, h->stat2, 2 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    RC(sync(h));
+    if (h->st) h->st->ms_inner += t.ms();
+    if (st2[0] >= 0) {
+        if (h->st) h->st->failed_subdomain = st2[0];
+        return fail(h, NLS_ESINGULAR, "zero pivot in subdomain " + std::to_string(st2[0]));
+    }
+    if (two_level(h)) {
+        Timer tc;
+        DevCoarse& d = h->dc;
+        HIPCHK(launch_coarse_galerkin(h->dm, d, u, 0, h->stream));
+        HIPCHK(launch_coarse_assemble(d, 1, h->stream));
+        HIPCHK(launch_coarse_lu(d, 1, h->lds_coarse_lu, h->npl_coarse, h->stream));
+        if (h->coarse_inv) HIPCHK(launch_coarse_inverse(d, h->coarse_bucket, h->max_block, h->stream));
+        int flag = 0;
+        HIPCHK(hipMemcpyAsync(&flag, d.flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+        RC(sync(h));
+        if (flag) return fail(h, NLS_ESINGULAR, "zero pivot in the coarse matrix");
+        if (h->st) h->st->ms_coarse += tc.ms();
+    }
+    return NLS_OK;
+}
+
+extern "C" int nls_solve_nks(nls_handle* h, double* u, int u_on_device, nls_stats* st) {
+    if (!h || !u) return NLS_EINVAL;
+    if (!h->have_part) return fail(h, NLS_ESTATE, "nls_set_partition first");
+    if (h->opt.coupling != NLS_ONE_LEVEL && !h->have_coarse)
+        return fail(h, NLS_ESTATE, "two-level coupling needs nls_build_coarse");
+    HIPCHK(hipSetDevice(h->opt.device));
+    Timer ttot;
+    nls_stats local{};
+    nls_stats* S = st ? st : &local;
+    std::memset(S, 0, sizeof(*S));
+    S->failed_subdomain = -1;
+    h->st = S;
+    h->have_state = false;  // the local factors and J values are overwritten
+    const int N = h->mesh.ndof();
+    double* ud = u;
+    if (!u_on_device) {
+        ud = h->ubuf;
+        HIPCHK(hipMemcpyAsync(ud, u, sizeof(double) * N, hipMemcpyHostToDevice, h->stream));
+    }
+    h->nks_u = ud;
+    auto finish = [&](int code) {
+        h->nks_mode = false;
+        h->nks_u = nullptr;
+        if (!u_on_device)
+            (void)hipMemcpyAsync(u, ud, sizeof(double) * N, hipMemcpyDeviceToHost, h->stream);
+        (void)hipStreamSynchronize(h->stream);
+        S->ms_total = ttot.ms();
+        S->ms_other = S->ms_total - S->ms_inner - S->ms_coarse - S->ms_gmres;
+        h->st = nullptr;
+        return code;
+    };
+    double r2 = 0.0;
+    HIPCHK(launch_global_residual(h->dm, ud, h->Fx, h->stream));
+    int rc = dot_host(h, h->Fx, h->Fx, N, &r2);
+    if (rc) return finish(rc);
+    const double r0 = std::sqrt(r2);
+    S->res0 = S->res_final = r0;
+    if (!std::isfinite(r0)) return finish(fail(h, NLS_ENAN, "F(u_0) is not finite"));
+    for (int k = 0;; ++k) {
+        if (S->res_final <= h->opt.outer_rtol * r0) {
+            S->converged = 1;
+            break;
+        }
+        if (k == h->opt.outer_maxit) break;
+        rc = nks_factor(h, ud);
+        if (rc) return finish(rc);
+        Timer tg;
+        int gits = 0;
+        h->nks_mode = true;
+        rc = gmres(h, h->Fx, h->du, &gits);  // right-preconditioned: du holds y
+        if (rc == NLS_OK) rc = nks_precond(h, h->du, h->stream) ? NLS_EHIP : NLS_OK;
+        h->nks_mode = false;
+        S->ms_gmres += tg.ms();
+        if (rc) return finish(rc);
+        S->gmres_its[k] = gits;
+        S->gmres_its_total += gits;
+        if (launch_axpy(-1.0, h->zbuf, ud, N, h->stream) != hipSuccess)
+            return finish(fail(h, NLS_EHIP, "update failed"));
+        if (launch_global_residual(h->dm, ud, h->Fx, h->stream) != hipSuccess)
+            return finish(fail(h, NLS_EHIP, "residual failed"));
+        rc = dot_host(h, h->Fx, h->Fx, N, &r2);
+        if (rc) return finish(rc);
+        S->outer_its = k + 1;
+        S->res_final = std::sqrt(r2);
+        if (!std::isfinite(S->res_final)) return finish(fail(h, NLS_ENAN, "F(u) is not finite"));
+    }
+    return finish(S->converged ? NLS_OK : NLS_ENOCONV);
 }
 
 // ------------------------------------------------------------------- hooks

@@ -1416,7 +1416,8 @@ k_dense_gemv(int n, const double* __restrict__ A, const double* __restrict__ x, 
 // B at the converged local state (eq. 6 with R_i DF(u_i) v = J R_i v + B v_G).
 template <int NPL>
 __global__ void __launch_bounds__(NLS_BLOCK)
-k_tangent_local(DevMesh M, DevMaps P, DevLocal L, NewtonParams np, const double* __restrict__ v) {
+k_tangent_local(DevMesh M, DevMaps P, DevLocal L, NewtonParams np, const double* __restrict__ v,
+                int restrict_rhs) {
     extern __shared__ double smem[];
     const int i = P.order[blockIdx.x];
     const int rowbase = P.off_n[i], n = P.off_n[i + 1] - rowbase;
@@ -1428,9 +1429,13 @@ k_tangent_local(DevMesh M, DevMaps P, DevLocal L, NewtonParams np, const double*
     for (int a = threadIdx.x; a < n; a += blockDim.x) {
         const int row = rowbase + a;
         double acc = 0.0;
-        for (int s = P.jptr[row]; s < P.jptr[row + 1]; ++s) {
-            const int c = P.jcol[s];
-            if (c >= n) acc += L.jval[s] * v[P.g2g[gbase + c - n]];
+        if (restrict_rhs) {
+            acc = v[P.l2g[row]];  // R_i v (local Schwarz solve)
+        } else {
+            for (int s = P.jptr[row]; s < P.jptr[row + 1]; ++s) {
+                const int c = P.jcol[s];
+                if (c >= n) acc += L.jval[s] * v[P.g2g[gbase + c - n]];
+            }
         }
         rb[a] = acc;
     }
@@ -1457,6 +1462,118 @@ __global__ void k_prolong(int N, const int* __restrict__ own_pidx, const double*
         y += acc;
     }
     out[g] = y;
+}
+
+// out = DF(u) v, one thread per node (P1): the rows of the element
+// Jacobians K_T = kappa [(1 + beta m) G + beta s (U 1 + u)^T / 6] (the same
+// entries as the local Jacobian) over the incident elements; Dirichlet rows
+// are identity rows.
+__global__ void k_global_jv(DevMesh M, const double* __restrict__ u, const double* __restrict__ v,
+                            double* __restrict__ out) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= M.N) return;
+    if (M.dflag[g]) {
+        out[g] = v[g];
+        return;
+    }
+    double acc = 0.0;
+    for (int k = M.nptr[g]; k < M.nptr[g + 1]; ++k) {
+        const int code = M.nel[k];
+        const int e = code >> 2, pos = code & 3;
+        const int nd[3] = {M.conn[3 * e], M.conn[3 * e + 1], M.conn[3 * e + 2]};
+        const double uu[3] = {u[nd[0]], u[nd[1]], u[nd[2]]};
+        const double U = uu[0] + uu[1] + uu[2];
+        const double m = (U * U + uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2]) * (1.0 / 12.0);
+        double gr[3];
+        g_row(M.G6 + 6 * (size_t)e, pos, gr[0], gr[1], gr[2]);
+        const double sa = gr[0] * uu[0] + gr[1] * uu[1] + gr[2] * uu[2];
+        const double coef = M.kappa[e] * (1.0 + M.beta * m);
+        const double rk = M.beta * M.kappa[e] * sa * (1.0 / 6.0);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc += (coef * gr[c] + rk * (U + uu[c])) * v[nd[c]];
+    }
+    out[g] = acc;
+}
+
+// out = DF(u) v for the elasticity problem, one thread per dof.
+__global__ void k_global_jv_nh(DevMesh M, const double* __restrict__ u, const double* __restrict__ v,
+                               double* __restrict__ out) {
+    const int gd = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gd >= M.ndof) return;
+    if (M.dflag[gd]) {
+        out[gd] = v[gd];
+        return;
+    }
+    const int g = gd >> 1, c = gd & 1;
+    double acc = 0.0;
+    for (int k = M.nptr[g]; k < M.nptr[g + 1]; ++k) {
+        const int code = M.nel[k];
+        const int e = code >> 2, pos = code & 3;
+        double X[4][2], ue[4][2], kr[4][2];
+        nh_coords(M, e, X);
+        int gn[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            gn[a] = M.conn[4 * e + a];
+            ue[a][0] = u[2 * gn[a]];
+            ue[a][1] = u[2 * gn[a] + 1];
+        }
+        nh_stiff_row(M, X, ue, pos, c, kr);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc += kr[b][0] * v[2 * gn[b]] + kr[b][1] * v[2 * gn[b] + 1];
+    }
+    out[gd] = acc;
+}
+
+// Per subdomain: gblk_i = Phi_i^T r over the closure dofs the subdomain owns,
+// so that sum_i gblk_i = Phi^T r (each dof counted once).
+__global__ void __launch_bounds__(NLS_BLOCK) k_coarse_phit(DevCoarse C, const double* __restrict__ r) {
+    const int i = blockIdx.x;
+    const int cb = C.off_c[i], nc = C.off_c[i + 1] - cb;
+    const int k0 = C.off_k[i], nk = C.off_k[i + 1] - k0;
+    const double* ph = C.phi + C.off_phi[i];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int k = wv; k < nk; k += nw) {
+        double acc = 0.0;
+        for (int a = lane; a < nc; a += 64) {
+            const int gd = C.cnode[cb + a];
+            if (C.cown[gd] == i) acc += ph[(int64_t)a * nk + k] * r[gd];
+        }
+        acc = wave_sum(acc);
+        if (lane == 0) C.gblk[k0 + k] = acc;
+    }
+}
+
+// J_ii = R_i DF(u) P_i at the global iterate u and its FP64 band LU (the
+// local factors of the linear Schwarz preconditioner); status 3 on a zero
+// pivot.  LDS as the fused local Newton kernel.
+template <bool ELAST>
+__global__ void __launch_bounds__(NLS_BLOCK)
+k_local_factor(DevMesh M, DevMaps P, DevLocal L, NewtonParams np, const double* __restrict__ u) {
+    extern __shared__ double smem[];
+    __shared__ int sflag[20];
+    const int i = P.order[blockIdx.x];
+    const int rowbase = P.off_n[i], n = P.off_n[i + 1] - rowbase;
+    const int gbase = P.off_g[i], ng = P.off_g[i + 1] - gbase;
+    const int ebase = P.off_e[i];
+    const int kl = P.kl[i];
+    double* vp = smem;
+    double* rb = vp + n + ng;
+    double* r0 = rb + n;
+    double* dl = r0 + (np.mixed ? n : 0);
+    double* red = dl + (np.mixed ? n : 0);
+    double* mult = red + 24;
+    double* W = mult + ((kl > 1 ? kl : 1) + 1);
+    for (int a = threadIdx.x; a < n; a += blockDim.x) vp[a] = u[P.l2g[rowbase + a]];
+    for (int j = threadIdx.x; j < ng; j += blockDim.x) vp[n + j] = u[P.g2g[gbase + j]];
+    __syncthreads();
+    local_jacobian<ELAST>(M, P, n, rowbase, ebase, vp, L.jval);
+    __syncthreads();
+    const int status = local_factor(P, L, np, i, n, rowbase, W, mult, sflag, true) ? 3 : 0;
+    if (threadIdx.x == 0) {
+        L.its[i] = 0;
+        L.status[i] = status;
+    }
 }
 
 // out = v - Phi c: the coarse prolongation subtracted from v, one thread per
@@ -2212,12 +2329,12 @@ hipError_t launch_local_newton(const DevMesh& M, const DevMaps& P, const DevLoca
 
 hipError_t launch_tangent_local(const DevMesh& M, const DevMaps& P, const DevLocal& L,
                                 const NewtonParams& np, const double* v, int lds_bytes, int npl,
-                                hipStream_t s) {
+                                hipStream_t s, int restrict_rhs) {
     hipError_t e;
 #define NLS_TL(NPL)                                                                  \
     e = set_lds(k_tangent_local<NPL>, lds_bytes);                                    \
     if (e != hipSuccess) return e;                                                   \
-    k_tangent_local<NPL><<<P.nsub, NLS_BLOCK, lds_bytes, s>>>(M, P, L, np, v);
+    k_tangent_local<NPL><<<P.nsub, NLS_BLOCK, lds_bytes, s>>>(M, P, L, np, v, restrict_rhs);
     if (npl <= 1) { NLS_TL(1) } else if (npl == 2) { NLS_TL(2) } else { NLS_TL(4) }
 #undef NLS_TL
     return hipGetLastError();
@@ -2229,6 +2346,36 @@ hipError_t launch_prolong(const DevMesh& M, const DevMaps& P, const double* T,
     DevCoarse dummy{};
     k_prolong<<<nblocks(M.ndof), NLS_BLOCK, 0, s>>>(M.ndof, P.own_pidx, T, addv, C ? *C : dummy,
                                                  C ? 1 : 0, cvec, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_global_jv(const DevMesh& M, const double* u, const double* v, double* out,
+                            hipStream_t s) {
+    if (M.kind == NLS_PROBLEM_NEOHOOKE)
+        k_global_jv_nh<<<nblocks(M.ndof), NLS_BLOCK, 0, s>>>(M, u, v, out);
+    else
+        k_global_jv<<<nblocks(M.N), NLS_BLOCK, 0, s>>>(M, u, v, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_coarse_phit(const DevCoarse& C, const double* r, hipStream_t s) {
+    k_coarse_phit<<<C.nsub, NLS_BLOCK, 0, s>>>(C, r);
+    return hipGetLastError();
+}
+
+hipError_t launch_local_factor(const DevMesh& M, const DevMaps& P, const DevLocal& L,
+                               const NewtonParams& np, const double* u, int nblk, int lds_bytes,
+                               hipStream_t s) {
+    hipError_t e;
+    if (M.kind == NLS_PROBLEM_NEOHOOKE) {
+        e = set_lds(k_local_factor<true>, lds_bytes);
+        if (e != hipSuccess) return e;
+        k_local_factor<true><<<nblk, NLS_BLOCK, lds_bytes, s>>>(M, P, L, np, u);
+    } else {
+        e = set_lds(k_local_factor<false>, lds_bytes);
+        if (e != hipSuccess) return e;
+        k_local_factor<false><<<nblk, NLS_BLOCK, lds_bytes, s>>>(M, P, L, np, u);
+    }
     return hipGetLastError();
 }
 

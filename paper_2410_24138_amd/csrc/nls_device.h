@@ -126,9 +126,19 @@ hipError_t launch_local_newton(const DevMesh& M, const DevMaps& P, const DevLoca
 hipError_t launch_prolong(const DevMesh& M, const DevMaps& P, const double* T,
                           const DevCoarse* C, const double* cvec, double* out,
                           const double* addv, hipStream_t s);
+// z_i = J_ii^{-1} B_i v_Gamma_i (restrict_rhs = 0, the exact tangent) or
+// z_i = J_ii^{-1} R_i v (restrict_rhs = 1, the linear Schwarz preconditioner)
 hipError_t launch_tangent_local(const DevMesh& M, const DevMaps& P, const DevLocal& L,
                                 const NewtonParams& np, const double* v, int lds_bytes,
-                                int nb_per_lane, hipStream_t s);
+                                int nb_per_lane, hipStream_t s, int restrict_rhs = 0);
+// Newton-Krylov-Schwarz pieces: DF(u) v, Phi^T r into the coarse blocks,
+// J_ii(u) and its LU
+hipError_t launch_global_jv(const DevMesh& M, const double* u, const double* v, double* out,
+                            hipStream_t s);
+hipError_t launch_coarse_phit(const DevCoarse& C, const double* r, hipStream_t s);
+hipError_t launch_local_factor(const DevMesh& M, const DevMaps& P, const DevLocal& L,
+                               const NewtonParams& np, const double* u, int nblk, int lds_bytes,
+                               hipStream_t s);
 // out = v - Phi c over all dofs (hybrid tangent)
 hipError_t launch_sub_coarse(const DevMesh& M, const DevCoarse& C, const double* cvec,
                              const double* v, double* out, hipStream_t s);

@@ -58,7 +58,7 @@ SYMBOLS = (
     "nls_guess_get_model", "nls_guess_enable", "nls_guess_capture",
     "nls_guess_captured", "nls_guess_features", "nls_guess_lift",
     "nls_guess_predict", "nls_guess_loss_grad", "nls_guess_train",
-    "nls_get_tuning", "nls_set_nodal_load", "nls_solve_load_steps",
+    "nls_get_tuning", "nls_set_nodal_load", "nls_solve_load_steps", "nls_solve_nks",
 )
 
 GUESS_PARAMS = 279552
@@ -158,6 +158,7 @@ def load() -> ctypes.CDLL:
         "nls_set_nodal_load": ([P, P], ctypes.c_int),
         "nls_solve_load_steps": ([P, P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(Stats)],
                                  ctypes.c_int),
+        "nls_solve_nks": ([P, P, ctypes.c_int, ctypes.POINTER(Stats)], ctypes.c_int),
         "nls_get_tuning": ([P, P, P, P, P, P, P], ctypes.c_int),
         "nls_guess_set_model": ([P, P, i64, P], ctypes.c_int),
         "nls_guess_get_model": ([P, P, P], ctypes.c_int),
@@ -346,6 +347,17 @@ class Solver:
             else self._dev(u0).clone()
         st = Stats()
         rc = self._check(self.lib.nls_solve(self.h, self._vp(u), 1, ctypes.byref(st)))
+        return u, st.as_dict(), rc
+
+    def solve_nks(self, u0=None):
+        """Newton-Krylov-Schwarz comparator from u0 (default 0): Newton on
+        F(u) = 0 with GMRES right-preconditioned by linear Schwarz.
+        Returns (u tensor, stats, rc)."""
+        t = self.torch
+        u = t.zeros(self.N, dtype=t.float64, device=self.device) if u0 is None \
+            else self._dev(u0).clone()
+        st = Stats()
+        rc = self._check(self.lib.nls_solve_nks(self.h, self._vp(u), 1, ctypes.byref(st)))
         return u, st.as_dict(), rc
 
     def solve_load_steps(self, n_steps, u0=None):
