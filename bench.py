@@ -358,6 +358,57 @@ def run_elasticity(forms, steps, warmup, device, n_load_steps=10):
     }
 
 
+# the paper's forces, then larger ones until the methods fail
+BEAM_FORCES = (4.0, 4.5, 5.0, 6.0, 7.0, 7.5, 9.0, 10.0, 11.0, 12.0, 13.0, 14.0, 15.0)
+
+
+def run_beam(device, forces=BEAM_FORCES, nx=320, ny=64, boxes=(20, 4)):
+    """Robustness sweep on the paper's beam (both ends clamped, volume force
+    (0, -f)): Newton-Krylov-Schwarz and the additive and hybrid nonlinear
+    Schwarz methods, all with the RGDSW coarse space, each force solved from
+    u = 0 with the paper's settings for this test (outer rtol 1e-4, inner
+    rtol 1e-5, at most 100 GMRES iterations per outer step)."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2410_24138_amd import Solver
+    from paper_2410_24138_amd.nls import NLSError
+    opts = dict(outer_rtol=1e-4, inner_rtol=1e-5, gmres_maxit=100, outer_maxit=30)
+    rows = []
+    for f in forces:
+        case = synth.beam_case(f, nx=nx, ny=ny, boxes=boxes, overlap=2)
+        sols = {}
+        for method in ("nks", "additive", "hybrid"):
+            coupling = "additive" if method == "nks" else method
+            s = Solver(case, coupling=coupling, coarse="rgdsw", device=device.index or 0, **opts)
+            rec = {"force": f, "method": method}
+            t0 = time.perf_counter()
+            try:
+                u, st, rc = s.solve_nks() if method == "nks" else s.solve()
+                torch.cuda.synchronize(device)
+                rec.update(ok=bool(rc == 0 and st["converged"]), rc=int(rc),
+                           outer_its=st["outer_its"], gmres_total=st["gmres_its_total"],
+                           res_ratio=st["res_final"] / max(st["res0"], 1e-300))
+                if rec["ok"]:
+                    sols[method] = u.detach().cpu().numpy()
+            except NLSError as e:
+                rec.update(ok=False, rc=int(e.code), error=str(e))
+            rec["ms"] = round((time.perf_counter() - t0) * 1e3, 2)
+            s.close()
+            rows.append(rec)
+            print(json.dumps(rec), file=sys.stderr, flush=True)
+        if len(sols) > 1:
+            ref = next(iter(sols.values()))
+            spread = max(float(np.abs(v - ref).max()) for v in sols.values())
+            for r in rows:
+                if r["force"] == f:
+                    r["max_diff_between_methods"] = spread
+                    r["tip_scale"] = float(np.abs(ref).max())
+    return {"workload": f"beam_{nx}x{ny}_{boxes[0]}x{boxes[1]}_ov2_rgdsw",
+            "metric": "converged (yes/no), outer and GMRES iterations, time per force",
+            "settings": opts, "runs": rows}
+
+
 def measured_traffic(kernel):
     """Counter-measured HBM bytes of a kernel, or None if the source changed."""
     import hashlib
@@ -406,7 +457,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--forms", default="plain,fp64_tuned,chosen")
     ap.add_argument("--workload", default="diffusion512",
-                    choices=["diffusion512", "batch", "learned", "elasticity"])
+                    choices=["diffusion512", "batch", "learned", "elasticity", "beam"])
     ap.add_argument("--amp", type=float, default=10.0,
                     help="forcing amplitude of the learned workload")
     ap.add_argument("--train-seeds", type=int, default=130)
@@ -438,6 +489,9 @@ def main():
         del src, dst
     if args.workload == "batch":
         print(json.dumps(run_batch(args.steps, args.warmup, device)), flush=True)
+        return
+    if args.workload == "beam":
+        print(json.dumps(run_beam(device)), flush=True)
         return
     if args.workload == "elasticity":
         forms = [f for f in args.forms.split(",") if f]

@@ -360,20 +360,27 @@ def seeded_cuts(seed: int, nx: int, ny: int, nbx: int = 8, nby: int = 8,
 
 
 def elasticity_case(nx, ny, lx, ly, cuts_x, cuts_y, overlap, *, E=210.0, nu=0.3,
-                    traction=(0.0, -4.0), two_level=True, name="elasticity"):
-    """Compressible Neo-Hooke cantilever on [0,lx]x[0,ly] with Q1 cells:
-    x = 0 clamped (both dofs), traction t on the edge x = lx, lumped to
-    nodal forces t * (edge length)/2 per node of every edge segment.
-    Lame parameters from E, nu: mu = E/(2(1+nu)), lambda = E nu/((1+nu)(1-2nu)).
-    Dofs are node-major, interleaved (u_x, u_y)."""
+                    traction=(0.0, -4.0), two_level=True, name="elasticity",
+                    clamp_right=False, body=(0.0, 0.0)):
+    """Compressible Neo-Hooke body on [0,lx]x[0,ly] with Q1 cells:
+    x = 0 clamped (both dofs; with clamp_right also x = lx), traction t on
+    the edge x = lx, lumped to nodal forces t * (edge length)/2 per node of
+    every edge segment, and a volume force b as consistent nodal forces
+    b * |cell| / 4 per node of every cell (the integral of each bilinear
+    shape function over a rectangle).  Lame parameters from E, nu:
+    mu = E/(2(1+nu)), lambda = E nu/((1+nu)(1-2nu)).  Dofs are node-major,
+    interleaved (u_x, u_y)."""
     xy, conn = q1_grid(nx, ny, lx, ly)
     cuts_x = np.asarray(cuts_x)
     cuts_y = np.asarray(cuts_y)
     bx = np.searchsorted(cuts_x, np.arange(nx), side="right") - 1
     by = np.searchsorted(cuts_y, np.arange(ny), side="right") - 1
     part = (by[:, None] * (len(cuts_x) - 1) + bx[None, :]).ravel().astype(np.int32)
-    left = np.nonzero(np.isclose(xy[:, 0], 0.0))[0]
-    dofs = np.sort(np.concatenate([2 * left, 2 * left + 1])).astype(np.int64)
+    fixed = np.isclose(xy[:, 0], 0.0)
+    if clamp_right:
+        fixed |= np.isclose(xy[:, 0], lx)
+    clamped = np.nonzero(fixed)[0]
+    dofs = np.sort(np.concatenate([2 * clamped, 2 * clamped + 1])).astype(np.int64)
     right = np.nonzero(np.isclose(xy[:, 0], lx))[0]
     right = right[np.argsort(xy[right, 1])]
     f = np.zeros(2 * len(xy))
@@ -382,6 +389,10 @@ def elasticity_case(nx, ny, lx, ly, cuts_x, cuts_y, overlap, *, E=210.0, nu=0.3,
         for g in (a, b):
             f[2 * g] += traction[0] * hy / 2
             f[2 * g + 1] += traction[1] * hy / 2
+    if body[0] != 0.0 or body[1] != 0.0:
+        q = (lx / nx) * (ly / ny) / 4.0
+        for comp in (0, 1):
+            np.add.at(f, 2 * conn.ravel() + comp, body[comp] * q)
     mu = E / (2.0 * (1.0 + nu))
     lam = E * nu / ((1.0 + nu) * (1.0 - 2.0 * nu))
     return {
@@ -401,6 +412,18 @@ def config3(traction_max: float = 4.0):
     cx, cy = seeded_cuts(3, 256, 128)
     return elasticity_case(256, 128, 2.0, 1.0, cx, cy, 2, traction=(0.0, -traction_max),
                            name="neohooke_256x128_8x8_ov2_gdsw")
+
+
+def beam_case(force: float, nx: int = 320, ny: int = 64, boxes=(20, 4), overlap: int = 2,
+              two_level: bool = True):
+    """The paper's beam (Section 1 with eq. 2; Section 3): the rectangle
+    [0,5]x[0,1], both ends clamped, volume force (0, -force), E = 210,
+    nu = 0.3 (nondimensional), Q1 cells nx x ny, boxes[0] x boxes[1] box
+    subdomains with the given overlap."""
+    return elasticity_case(nx, ny, 5.0, 1.0, even_cuts(nx, boxes[0]), even_cuts(ny, boxes[1]),
+                           overlap, traction=(0.0, 0.0), body=(0.0, -float(force)),
+                           clamp_right=True, two_level=two_level,
+                           name=f"beam_{nx}x{ny}_{boxes[0]}x{boxes[1]}_ov{overlap}_f{force:g}")
 
 
 def small_elasticity_case(nx=8, ny=4, boxes=(2, 2), overlap=1, traction=(0.0, -1.0),

@@ -71,3 +71,28 @@ def test_neohooke_solution(coupling):
     ug, _ = global_newton(P)
     assert st["converged"]
     assert np.linalg.norm(u - ug) <= 1e-8 * np.linalg.norm(ug)
+
+
+def test_beam_symmetry_and_methods_agree():
+    """The paper's beam set-up (both ends clamped, volume force) on a small
+    mesh: the consistent load sums to -force * area; the discrete solution
+    is mirror-symmetric about x = 2.5 (u_x odd, u_y even); NKS, additive and
+    hybrid nonlinear Schwarz (RGDSW) reach it."""
+    f = 4.0
+    case = synth.beam_case(f, nx=20, ny=4, boxes=(5, 1), overlap=1)
+    assert abs(case["nodal_force"][1::2].sum() + f * 5.0) <= 1e-12
+    P = NHProblem(case)
+    ug, _ = global_newton(P)
+    xy = P.xy
+    mirror = np.lexsort((xy[:, 1], np.round(5.0 - xy[:, 0], 9)))
+    order = np.lexsort((xy[:, 1], np.round(xy[:, 0], 9)))
+    ux, uy = ug[0::2], ug[1::2]
+    np.testing.assert_allclose(ux[order], -ux[mirror], atol=1e-10 * np.abs(uy).max())
+    np.testing.assert_allclose(uy[order], uy[mirror], atol=1e-10 * np.abs(uy).max())
+    assert uy.min() < -0.05  # it does deform
+    for coupling in ("additive", "hybrid"):
+        S = Schwarz(P, coupling, coarse="rgdsw")
+        u, st = S.solve(rtol=1e-10)
+        assert st["converged"] and np.linalg.norm(u - ug) <= 1e-8 * np.linalg.norm(ug)
+    u, st = NKS(Schwarz(P, "additive", coarse="rgdsw")).solve(rtol=1e-10)
+    assert st["converged"] and np.linalg.norm(u - ug) <= 1e-8 * np.linalg.norm(ug)
