@@ -40,8 +40,12 @@ FORMS = {
     "fp64_tuned": ("fp64", ("graph", "chord", "autotune")),
     # as fp64_tuned with the RGDSW coarse space (the paper's choice)
     "fp64_tuned_rgdsw": ("fp64", ("graph", "chord", "autotune", "rgdsw")),
-    # FP32 local LU + FP64 refinement with graphs, chord coarse steps, autotuner
+    # every pattern: graphs, chord coarse steps, and the autotuner choosing
+    # LU variants, the coarse apply and the local precision (FP32 LU with FP64
+    # refinement, or FP64) by measured time
     "chosen": ("fp32_ir", ("graph", "chord", "autotune")),
+    # FP32 local LU + FP64 refinement kept throughout
+    "fp32_ir": ("fp32_ir", ("graph", "chord")),
 }
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per dispatch measured with rocprofv3 FETCH_SIZE/WRITE_SIZE (two
@@ -419,9 +423,15 @@ def measured_traffic(kernel):
     return MEASURED_TRAFFIC["bytes"].get(kernel)
 
 
+def _local_fp64(res, form):
+    """Whether the local solves ran in FP64 (FP64 form, or the autotuner of
+    a mixed form chose FP64)."""
+    return FORMS[form][0] == "fp64" or res.get("tuning", {}).get("local_precision") == "fp64"
+
+
 def roofline(case, res, form):
     """Dominant kernel and its HBM roofline fraction from algorithmic bytes."""
-    elem = 8 if FORMS[form][0] == "fp64" else 4
+    elem = 8 if _local_fp64(res, form) else 4
     fac, n, ng = _factor_bytes(case, elem)
     kern = res["kernels"]
     k_t, k_l = kern["tangent_local"], kern["local_newton"]
@@ -443,7 +453,7 @@ def roofline(case, res, form):
         per_launch = float(per_sub.sum())
     avg_s = k["ms"] / max(k["launches"], 1) / 1e3
     achieved = per_launch / avg_s / 1e9
-    traffic = measured_traffic("k_" + name) if FORMS[form][0] == "fp64" else None
+    traffic = measured_traffic("k_" + name) if _local_fp64(res, form) else None
     return {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic, "bytes_per_launch": per_launch,
@@ -455,7 +465,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--forms", default="plain,fp64_tuned,chosen")
+    ap.add_argument("--forms", default="plain,fp64_tuned,chosen,fp32_ir,fp64_tuned_rgdsw")
     ap.add_argument("--workload", default="diffusion512",
                     choices=["diffusion512", "batch", "learned", "elasticity", "beam"])
     ap.add_argument("--amp", type=float, default=10.0,
@@ -527,7 +537,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if FORMS[best][0] == "fp64" else "f32+f64",
+        "dtype": "f64" if _local_fp64(r, best) else "f32+f64",
         "data": "synthetic",
         "config": {"workload": case["name"], "grid": "512x512 P1", "nodes": len(case["xy"]),
                    "subdomains": 256, "overlap": 2, "coarse": "GDSW vertex+edge",

@@ -118,8 +118,10 @@ typedef struct nls_options {
    unblocked; each with its own LDS size and hence occupancy), timed as the
    bucket's fused local Newton launch at the initial iterate; for the coarse
    term of the tangent the explicit inverse against a band LU solve per
-   GMRES step, priced at 20 steps per evaluation.  nls_get_tuning reports
-   the decisions. */
+   GMRES step, priced at 20 steps per evaluation.  On an NLS_PREC_FP32_IR
+   handle the local solves are timed in both precisions (binary32 LU with
+   refinement, and binary64 LU) and the faster total is kept for all of
+   them.  nls_get_tuning reports the decisions. */
 #define NLS_FLAG_AUTOTUNE 16
 
 /* ---- statistics of the last solve ------------------------------------ */
@@ -299,11 +301,12 @@ int nls_get_coarse_basis(nls_handle* h, int64_t* nnz, int64_t* rowptr,
    *n_buckets; per bucket the LU variant (1 NB = 16, 2 NB = 8, 3 unblocked,
    0 by band width), its LDS bytes and its subdomain count; *coarse_inverse
    (1 explicit inverse, 0 LU solves) and coarse_ms[3] = measured ms of the
-   inverse, one inverse apply and one LU solve (0 if not tuned).  Any output
+   inverse, one inverse apply and one LU solve (0 if not tuned);
+   *local_precision = the NLS_PREC_* the local solves run in.  Any output
    may be NULL. */
 int nls_get_tuning(nls_handle* h, int32_t* n_buckets, int32_t* lu_variant,
                    int32_t* lds_bytes, int32_t* n_sub, int32_t* coarse_inverse,
-                   double* coarse_ms);
+                   double* coarse_ms, int32_t* local_precision);
 
 /* ---- learned initial guess of the local solves ------------------------
    Not part of the paper's method, which starts every inner Newton

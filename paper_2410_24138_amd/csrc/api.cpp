@@ -880,42 +880,58 @@ static int time_ms(nls_handle* h, F&& launch, float* ms) {
 // Per size bucket: the LU variants that hold the bucket's widest band
 // (blocked NB=16, NB=8, unblocked), each timed as the bucket's fused local
 // Newton launch at u; each variant sizes its own LDS, so a narrower window
-// may also raise the workgroups per CU.
+// may also raise the workgroups per CU.  A mixed-precision handle times the
+// buckets in both precisions and keeps the one with the smaller total.
 static int autotune_local(nls_handle* h, const double* u) {
     const HostMaps& M = h->maps;
-    const bool mixed = h->opt.precision == NLS_PREC_FP32_IR;
-    for (size_t b = 0; b < h->bk_start.size(); ++b) {
-        int kmax = 0;
-        for (int p = h->bk_start[b]; p < h->bk_end[b]; ++p) kmax = std::max(kmax, M.kl[M.order[p]]);
-        float best = 1e30f;
-        int bv = h->bk_var[b], blds = h->bk_lds[b];
-        for (int v = 1; v <= 3; ++v) {
-            if (v == 1 && kmax + 16 > 64) continue;
-            if (v == 2 && kmax + 8 > 64) continue;
-            int lds = 0;
+    const bool can_mixed = h->opt.precision == NLS_PREC_FP32_IR;
+    const int nprec = can_mixed ? 2 : 1;
+    const size_t nbk = h->bk_start.size();
+    std::vector<int> var[2], ldsv[2];
+    double total[2] = {0.0, 0.0};
+    for (int pm = 0; pm < nprec; ++pm) {
+        const bool mixed = can_mixed && pm == 0;  // pass 0: the handle's precision
+        for (size_t b = 0; b < nbk; ++b) {
+            int kmax = 0;
+            for (int p = h->bk_start[b]; p < h->bk_end[b]; ++p) kmax = std::max(kmax, M.kl[M.order[p]]);
+            float best = 1e30f;
+            int bv = 3, blds = 0;
             for (int p = h->bk_start[b]; p < h->bk_end[b]; ++p)
-                lds = std::max(lds, local_lds_bytes(M, M.order[p], mixed, v));
-            if (lds > 160 * 1024) continue;
-            NewtonParams np = h->np;
-            np.xpred = nullptr;
-            np.lu_variant = v;
-            DevMaps pb = h->dp;
-            pb.order = h->dp.order + h->bk_start[b];
-            const int nb = h->bk_end[b] - h->bk_start[b];
-            float ms = 0.f;
-            RC(time_ms(h, [&]() -> int {
-                HIPCHK(launch_local_newton(h->dm, pb, h->dl, np, u, nb, lds, h->bk_npl[b], h->stream));
-                return NLS_OK;
-            }, &ms));
-            if (ms < best) {
-                best = ms;
-                bv = v;
-                blds = lds;
+                blds = std::max(blds, local_lds_bytes(M, M.order[p], mixed, 3));
+            for (int v = 1; v <= 3; ++v) {
+                if (v == 1 && kmax + 16 > 64) continue;
+                if (v == 2 && kmax + 8 > 64) continue;
+                int lds = 0;
+                for (int p = h->bk_start[b]; p < h->bk_end[b]; ++p)
+                    lds = std::max(lds, local_lds_bytes(M, M.order[p], mixed, v));
+                if (lds > 160 * 1024) continue;
+                NewtonParams np = h->np;
+                np.xpred = nullptr;
+                np.lu_variant = v;
+                np.mixed = mixed ? 1 : 0;
+                DevMaps pb = h->dp;
+                pb.order = h->dp.order + h->bk_start[b];
+                const int nb = h->bk_end[b] - h->bk_start[b];
+                float ms = 0.f;
+                RC(time_ms(h, [&]() -> int {
+                    HIPCHK(launch_local_newton(h->dm, pb, h->dl, np, u, nb, lds, h->bk_npl[b], h->stream));
+                    return NLS_OK;
+                }, &ms));
+                if (ms < best) {
+                    best = ms;
+                    bv = v;
+                    blds = lds;
+                }
             }
+            var[pm].push_back(bv);
+            ldsv[pm].push_back(blds);
+            total[pm] += best;
         }
-        h->bk_var[b] = bv;
-        h->bk_lds[b] = blds;
     }
+    const int pick = (nprec == 2 && total[1] < total[0]) ? 1 : 0;
+    h->bk_var = var[pick];
+    h->bk_lds = ldsv[pick];
+    h->np.mixed = (can_mixed && pick == 0) ? 1 : 0;
     return NLS_OK;
 }
 
@@ -1595,7 +1611,7 @@ extern "C" const char* nls_last_error(nls_handle* h) {
 
 extern "C" int nls_get_tuning(nls_handle* h, int32_t* n_buckets, int32_t* lu_variant,
                               int32_t* lds_bytes, int32_t* n_sub, int32_t* coarse_inverse,
-                              double* coarse_ms) {
+                              double* coarse_ms, int32_t* local_precision) {
     if (!h) return NLS_EINVAL;
     if (!h->have_part) return fail(h, NLS_ESTATE, "nls_set_partition first");
     const int nb = (int)h->bk_start.size();
@@ -1608,5 +1624,6 @@ extern "C" int nls_get_tuning(nls_handle* h, int32_t* n_buckets, int32_t* lu_var
     if (coarse_inverse) *coarse_inverse = h->coarse_inv ? 1 : 0;
     if (coarse_ms)
         for (int k = 0; k < 3; ++k) coarse_ms[k] = h->tune_ms[k];
+    if (local_precision) *local_precision = h->np.mixed ? NLS_PREC_FP32_IR : NLS_PREC_FP64;
     return NLS_OK;
 }

@@ -159,7 +159,7 @@ def load() -> ctypes.CDLL:
         "nls_solve_load_steps": ([P, P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(Stats)],
                                  ctypes.c_int),
         "nls_solve_nks": ([P, P, ctypes.c_int, ctypes.POINTER(Stats)], ctypes.c_int),
-        "nls_get_tuning": ([P, P, P, P, P, P, P], ctypes.c_int),
+        "nls_get_tuning": ([P, P, P, P, P, P, P, P], ctypes.c_int),
         "nls_guess_set_model": ([P, P, i64, P], ctypes.c_int),
         "nls_guess_get_model": ([P, P, P], ctypes.c_int),
         "nls_guess_enable": ([P, ctypes.c_int], ctypes.c_int),
@@ -541,9 +541,12 @@ class Solver:
         cnt = np.zeros(ns, np.int32)
         ci = ctypes.c_int32(0)
         cms = np.zeros(3, np.float64)
+        prec = ctypes.c_int32(0)
         self._check(self.lib.nls_get_tuning(self.h, ctypes.byref(nb), _ptr(var), _ptr(lds),
-                                            _ptr(cnt), ctypes.byref(ci), _ptr(cms)))
+                                            _ptr(cnt), ctypes.byref(ci), _ptr(cms),
+                                            ctypes.byref(prec)))
         k = nb.value
         return {"lu_variant": var[:k].tolist(), "lds_bytes": lds[:k].tolist(),
                 "n_sub": cnt[:k].tolist(), "coarse_inverse": bool(ci.value),
-                "coarse_ms": cms.tolist()}
+                "coarse_ms": cms.tolist(),
+                "local_precision": "fp32_ir" if prec.value == PREC_FP32_IR else "fp64"}

@@ -313,6 +313,26 @@ def test_autotuned_solve_matches_oracle():
     np.testing.assert_array_equal(_np(uu2), _np(uu))
 
 
+def test_autotuned_precision_choice():
+    """A mixed-precision handle with the autotuner runs its local solves in
+    the faster of binary32-LU-with-refinement and binary64 LU; either way
+    the solution is the oracle's to the mixed-precision tolerance and the
+    outer iteration count is the same."""
+    from paper_2410_24138_amd import nls
+    case = _batch_case()
+    S = Schwarz(P1Problem(case), "additive")
+    u_ref, st_ref = S.solve()
+    f = nls.FLAG_AUTOTUNE | nls.FLAG_GRAPH | nls.FLAG_COARSE_CHORD
+    s = _solver(case, coupling="additive", precision="fp32_ir", flags=f)
+    assert s.tuning()["local_precision"] == "fp32_ir"
+    uu, st, rc = s.solve()
+    assert rc == 0 and st["outer_its"] == st_ref["outer"]
+    assert s.tuning()["local_precision"] in ("fp32_ir", "fp64")
+    assert np.linalg.norm(_np(uu) - u_ref) <= 1e-8 * np.linalg.norm(u_ref)
+    uu2, st2, _ = s.solve()
+    assert np.linalg.norm(_np(uu2) - u_ref) <= 1e-8 * np.linalg.norm(u_ref)
+
+
 @pytest.mark.parametrize("kw", [dict(n=24, boxes=4, overlap=2, forcing_seed=2),
                                 dict(n=21, boxes=3, overlap=1, uneven=True, coef_seed=3)])
 def test_rgdsw_matches_oracle(kw):
