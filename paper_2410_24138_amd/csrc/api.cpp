@@ -377,6 +377,7 @@ extern "C" int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* el
     }
     RC(h->alloc(G_MAPS, &L.piv, nrows));
     RC(h->alloc(G_MAPS, &L.xstar, nrows));
+    RC(h->alloc(G_MAPS, &L.ghost, std::max<size_t>(M.g2g.size(), 1)));
     RC(h->alloc(G_MAPS, &L.T, nrows));
     RC(h->alloc(G_MAPS, &L.z, nrows));
     RC(h->alloc(G_MAPS, &L.its, M.nsub));
@@ -423,6 +424,7 @@ extern "C" int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* el
     np.ir_maxit = 10;
     np.ir_rtol = 1e-10;  // a Newton step needs no more; residuals stay FP64
     np.lu_variant = var0;
+    np.keep_factor = 1;
     h->np = np;
     // GMRES workspace
     const int N = h->mesh.ndof();
@@ -769,6 +771,8 @@ static int evaluate(nls_handle* h, const double* u, double* Fx) {
     Timer t;
     NewtonParams np = h->np;
     np.xpred = nullptr;
+    np.keep_factor = 0;  // J_ii and its LU at x* are formed by prepare_tangent
+    h->local_factored = false;
     if (guess_enabled(h)) RC(guess_prepare(h, u, &np.xpred));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (h->profiling()) {
@@ -826,6 +830,27 @@ static int evaluate(nls_handle* h, const double* u, double* Fx) {
 static int prepare_tangent(nls_handle* h) {
     if (h->tangent_ready) return NLS_OK;
     if (!h->have_state) return fail(h, NLS_ESTATE, "no evaluated point (nls_eval_precond_residual)");
+    if (!h->local_factored) {
+        // J_ii and its FP64 LU at the converged local states (eq. 6)
+        Timer tf;
+        NewtonParams np = h->np;
+        for (size_t b = 0; b < h->bk_start.size(); ++b) {
+            DevMaps pb = h->dp;
+            pb.order = h->dp.order + h->bk_start[b];
+            np.lu_variant = h->bk_var[b];
+            HIPCHK(launch_local_factor(h->dm, pb, h->dl, np, h->dl.xstar, h->bk_end[b] - h->bk_start[b],
+                                       h->bk_lds[b], h->stream, h->dl.xstar, h->dl.ghost));
+        }
+        HIPCHK(launch_any_status(h->dl.status, h->maps.nsub, h->stat2, h->stream));
+        int st2[2];
+        HIPCHK(hipMemcpyAsync(st2, h->stat2, 2 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+        RC(sync(h));
+        if (st2[0] >= 0)
+            return fail(h, NLS_ESINGULAR, "zero pivot in subdomain " + std::to_string(st2[0]) +
+                                              " at its converged state");
+        h->local_factored = true;
+        if (h->st) h->st->ms_inner += tf.ms();
+    }
     if (h->tangent_w) {
         Timer tp;
         HIPCHK(launch_tangent_prep(h->dp, h->dl, h->dt, h->tangent_bucket, h->max_ng, h->stream));
@@ -909,6 +934,9 @@ static int autotune_local(nls_handle* h, const double* u) {
                 np.xpred = nullptr;
                 np.lu_variant = v;
                 np.mixed = mixed ? 1 : 0;
+                // with the factorisation at x*, so that every subdomain's
+                // time includes at least one LU even where Newton stops at once
+                np.keep_factor = 1;
                 DevMaps pb = h->dp;
                 pb.order = h->dp.order + h->bk_start[b];
                 const int nb = h->bk_end[b] - h->bk_start[b];

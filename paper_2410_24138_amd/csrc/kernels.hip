@@ -1095,7 +1095,7 @@ k_local_newton(DevMesh M, DevMaps P, DevLocal L, NewtonParams np, const double* 
         if (status == 0 || start != 1) break;
         start = 2;
     }
-    if (status == 0) {
+    if (status == 0 && np.keep_factor) {
         // J and its LU at x*, in FP64, are kept for the exact tangent
         local_jacobian<ELAST>(M, P, n, rowbase, ebase, vp, L.jval);
         __syncthreads();
@@ -1106,6 +1106,7 @@ k_local_newton(DevMesh M, DevMaps P, DevLocal L, NewtonParams np, const double* 
         L.xstar[row] = vp[a];
         L.T[row] = u[P.l2g[row]] - vp[a];
     }
+    for (int j = threadIdx.x; j < ng; j += blockDim.x) L.ghost[gbase + j] = vp[n + j];
     if (threadIdx.x == 0) {
         L.its[i] = its;
         L.status[i] = status;
@@ -1544,12 +1545,14 @@ __global__ void __launch_bounds__(NLS_BLOCK) k_coarse_phit(DevCoarse C, const do
     }
 }
 
-// J_ii = R_i DF(u) P_i at the global iterate u and its FP64 band LU (the
-// local factors of the linear Schwarz preconditioner); status 3 on a zero
-// pivot.  LDS as the fused local Newton kernel.
+// J_ii = R_i DF(v) P_i and its FP64 band LU, at v = u (the local factors of
+// the linear Schwarz preconditioner) or at a given local state (x*, Gamma
+// values) for the exact tangent; status 3 on a zero pivot.  LDS as the fused
+// local Newton kernel.
 template <bool ELAST>
 __global__ void __launch_bounds__(NLS_BLOCK)
-k_local_factor(DevMesh M, DevMaps P, DevLocal L, NewtonParams np, const double* __restrict__ u) {
+k_local_factor(DevMesh M, DevMaps P, DevLocal L, NewtonParams np, const double* __restrict__ u,
+               const double* __restrict__ xloc, const double* __restrict__ gloc) {
     extern __shared__ double smem[];
     __shared__ int sflag[20];
     const int i = P.order[blockIdx.x];
@@ -1564,8 +1567,10 @@ k_local_factor(DevMesh M, DevMaps P, DevLocal L, NewtonParams np, const double* 
     double* red = dl + (np.mixed ? n : 0);
     double* mult = red + 24;
     double* W = mult + ((kl > 1 ? kl : 1) + 1);
-    for (int a = threadIdx.x; a < n; a += blockDim.x) vp[a] = u[P.l2g[rowbase + a]];
-    for (int j = threadIdx.x; j < ng; j += blockDim.x) vp[n + j] = u[P.g2g[gbase + j]];
+    for (int a = threadIdx.x; a < n; a += blockDim.x)
+        vp[a] = xloc ? xloc[rowbase + a] : u[P.l2g[rowbase + a]];
+    for (int j = threadIdx.x; j < ng; j += blockDim.x)
+        vp[n + j] = gloc ? gloc[gbase + j] : u[P.g2g[gbase + j]];
     __syncthreads();
     local_jacobian<ELAST>(M, P, n, rowbase, ebase, vp, L.jval);
     __syncthreads();
@@ -2365,16 +2370,16 @@ hipError_t launch_coarse_phit(const DevCoarse& C, const double* r, hipStream_t s
 
 hipError_t launch_local_factor(const DevMesh& M, const DevMaps& P, const DevLocal& L,
                                const NewtonParams& np, const double* u, int nblk, int lds_bytes,
-                               hipStream_t s) {
+                               hipStream_t s, const double* xloc, const double* gloc) {
     hipError_t e;
     if (M.kind == NLS_PROBLEM_NEOHOOKE) {
         e = set_lds(k_local_factor<true>, lds_bytes);
         if (e != hipSuccess) return e;
-        k_local_factor<true><<<nblk, NLS_BLOCK, lds_bytes, s>>>(M, P, L, np, u);
+        k_local_factor<true><<<nblk, NLS_BLOCK, lds_bytes, s>>>(M, P, L, np, u, xloc, gloc);
     } else {
         e = set_lds(k_local_factor<false>, lds_bytes);
         if (e != hipSuccess) return e;
-        k_local_factor<false><<<nblk, NLS_BLOCK, lds_bytes, s>>>(M, P, L, np, u);
+        k_local_factor<false><<<nblk, NLS_BLOCK, lds_bytes, s>>>(M, P, L, np, u, xloc, gloc);
     }
     return hipGetLastError();
 }

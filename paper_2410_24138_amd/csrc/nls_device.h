@@ -43,6 +43,7 @@ struct DevLocal {
     float* Lf32;
     int* piv;                   // packed, one per V row
     double* xstar;              // packed converged local states
+    double* ghost;              // packed Gamma_i values of the last evaluation
     double* T;                  // packed T_i(u) = R_i u - x*
     double* z;                  // packed scratch of the tangent
     int* its;                   // per subdomain
@@ -71,6 +72,8 @@ struct NewtonParams {
     double ir_rtol;
     const double* xpred;        // packed predicted starts, or null
     int lu_variant;             // 0 by band width, 1 blocked NB=16, 2 NB=8, 3 unblocked
+    int keep_factor;            // 1: J and its FP64 LU at x* formed by the local kernel;
+                                // 0: left to launch_local_factor at (xstar, ghost)
 };
 
 // Most coarse functions nonzero at one interface dof (see HostCoarse).
@@ -136,9 +139,12 @@ hipError_t launch_tangent_local(const DevMesh& M, const DevMaps& P, const DevLoc
 hipError_t launch_global_jv(const DevMesh& M, const double* u, const double* v, double* out,
                             hipStream_t s);
 hipError_t launch_coarse_phit(const DevCoarse& C, const double* r, hipStream_t s);
+// J_ii and its FP64 LU at R_i u with Gamma values from u, or, with xloc and
+// gloc (packed like xstar and ghost), at that local state
 hipError_t launch_local_factor(const DevMesh& M, const DevMaps& P, const DevLocal& L,
                                const NewtonParams& np, const double* u, int nblk, int lds_bytes,
-                               hipStream_t s);
+                               hipStream_t s, const double* xloc = nullptr,
+                               const double* gloc = nullptr);
 // out = v - Phi c over all dofs (hybrid tangent)
 hipError_t launch_sub_coarse(const DevMesh& M, const DevCoarse& C, const double* cvec,
                              const double* v, double* out, hipStream_t s);
