@@ -589,13 +589,14 @@ extern "C" int nls_build_coarse(nls_handle* h, int kind) {
     RC(h->alloc(G_COARSE, &d.flag, 1));
     RC(h->alloc(G_COARSE, &h->ctmp, C.n0));
     RC(h->alloc(G_COARSE, &h->rhs2, C.n0));
-    h->coarse_bucket = mrhs_bucket_kl(C.a0kl, C.a0ku);
-    h->coarse_inv = h->coarse_bucket <= 56 && !(h->opt.flags & NLS_FLAG_COARSE_LU_APPLY);
+    h->coarse_ldu = 1;
+    for (size_t b = 0; b < C.bkl.size(); ++b) h->coarse_ldu = std::max(h->coarse_ldu, C.bkl[b] + C.bku[b] + 1);
+    h->coarse_can_inv = h->coarse_ldu <= 511 &&
+                        coarse_inverse_lds_bytes(h->max_block, h->coarse_ldu) <= 160 * 1024 &&
+                        !(h->opt.flags & NLS_FLAG_COARSE_LU_APPLY);
+    h->coarse_inv = h->coarse_can_inv;
     h->coarse_lu_valid = false;
-    if (h->coarse_inv) {
-        RC(h->alloc(G_COARSE, &d.a0inv, (size_t)C.offI.back()));
-        RC(h->alloc(G_COARSE, &d.a0fwd, (size_t)C.offI.back()));
-    }
+    if (h->coarse_inv) RC(h->alloc(G_COARSE, &d.a0inv, (size_t)C.offI.back()));
     HIPCHK(hipMemsetAsync(d.flag, 0, sizeof(int), h->stream));
     h->dc = d;
     HIPCHK(launch_gdsw_extend(h->dm, d, lds_gdsw, npl_for(std::max(maxikl, maxiband)), h->stream));
@@ -864,7 +865,7 @@ static int prepare_tangent(nls_handle* h) {
         HIPCHK(launch_coarse_assemble(d, 1, h->stream));
         HIPCHK(launch_coarse_lu(d, 1, h->lds_coarse_lu, h->npl_coarse, h->stream));
         h->coarse_lu_valid = true;
-        if (h->coarse_inv) HIPCHK(launch_coarse_inverse(d, h->coarse_bucket, h->max_block, h->stream));
+        if (h->coarse_inv) HIPCHK(launch_coarse_inverse(d, h->max_block, h->coarse_ldu, h->stream));
         int flag = 0;
         HIPCHK(hipMemcpyAsync(&flag, d.flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
         RC(sync(h));
@@ -968,13 +969,13 @@ static int autotune_local(nls_handle* h, const double* u) {
 // the measured kernel times at TUNE_STEPS steps per evaluation.
 static constexpr int TUNE_STEPS = 20;
 static int autotune_coarse(nls_handle* h) {
-    if (!two_level(h) || h->coarse_bucket > 56 || (h->opt.flags & NLS_FLAG_COARSE_LU_APPLY))
+    if (!two_level(h) || !h->coarse_can_inv)
         return NLS_OK;
     RC(prepare_tangent(h));
     DevCoarse& d = h->dc;
     float t_inv = 0.f, t_apply = 0.f, t_lu = 0.f;
     RC(time_ms(h, [&]() -> int {
-        HIPCHK(launch_coarse_inverse(d, h->coarse_bucket, h->max_block, h->stream));
+        HIPCHK(launch_coarse_inverse(d, h->max_block, h->coarse_ldu, h->stream));
         return NLS_OK;
     }, &t_inv));
     RC(time_ms(h, [&]() -> int {
@@ -989,7 +990,7 @@ static int autotune_coarse(nls_handle* h) {
     if (inv != h->coarse_inv) {
         h->coarse_inv = inv;
         h->drop_graphs();
-        if (inv) HIPCHK(launch_coarse_inverse(d, h->coarse_bucket, h->max_block, h->stream));
+        if (inv) HIPCHK(launch_coarse_inverse(d, h->max_block, h->coarse_ldu, h->stream));
     }
     h->tune_ms[0] = t_inv;
     h->tune_ms[1] = t_apply;
@@ -1455,7 +1456,7 @@ static int nks_factor(nls_handle* h, const double* u) {
         HIPCHK(launch_coarse_galerkin(h->dm, d, u, 0, h->stream));
         HIPCHK(launch_coarse_assemble(d, 1, h->stream));
         HIPCHK(launch_coarse_lu(d, 1, h->lds_coarse_lu, h->npl_coarse, h->stream));
-        if (h->coarse_inv) HIPCHK(launch_coarse_inverse(d, h->coarse_bucket, h->max_block, h->stream));
+        if (h->coarse_inv) HIPCHK(launch_coarse_inverse(d, h->max_block, h->coarse_ldu, h->stream));
         int flag = 0;
         HIPCHK(hipMemcpyAsync(&flag, d.flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
         RC(sync(h));

@@ -57,7 +57,8 @@ struct nls_handle {
     bool local_factored = false;  // J_ii and its LU at the last evaluation's x* are held
     bool nks_mode = false;        // GMRES operator is DF(u) M^{-1} (Newton-Krylov-Schwarz)
     const double* nks_u = nullptr; // the NKS iterate the preconditioner was factored at
-    int coarse_bucket = 0, max_block = 0;
+    int coarse_ldu = 1, max_block = 0;  // widest coarse band (kl + ku + 1), largest diagonal block
+    bool coarse_can_inv = false;        // the explicit inverse fits (LDS, band width)
     // size buckets of the local-solve launches: [start, end) in the launch
     // order, LDS bytes and solve width of each
     std::vector<int> bk_start, bk_end, bk_lds, bk_npl;

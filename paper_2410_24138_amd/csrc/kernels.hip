@@ -1368,23 +1368,141 @@ k_tangent_gemv(DevMaps P, DevTangent Tg, const double* __restrict__ v, double* _
 }
 
 // Inverse of every diagonal block of A0 (band order, row-major per block)
-// from its LU: identity right-hand sides, 256 columns per workgroup.
-template <int KL, int KW>
-__global__ void __launch_bounds__(MR_THREADS) k_coarse_inverse(DevCoarse C) {
+// from its band LU: INV_CB identity columns per workgroup, held in LDS, so
+// any band width fits; the factor columns (and pivots) of INV_S steps are
+// fetched into registers one chunk ahead and staged into LDS at the chunk
+// boundary, so the sweeps wait for HBM only once per pipeline fill.
+// Forward: interchange k, then column k of L; backward: x_k = X_k / U_kk
+// (written out as row k of the inverse) and the rows above updated with
+// column k of U.  One barrier per step.
+constexpr int INV_CB = 8, INV_S = 8, INV_THREADS = 256, INV_MAXW = 512;
+constexpr int INV_PF = (INV_S * INV_MAXW + INV_THREADS - 1) / INV_THREADS;
+
+__global__ void __launch_bounds__(INV_THREADS) k_coarse_inverse(DevCoarse C, int max_ldu) {
     extern __shared__ double smem[];
-    __shared__ int sint[2 * MR_CH];
     const int b = blockIdx.y;
     const int off = C.boff[b], n = C.boff[b + 1] - off;
-    if ((int)blockIdx.x * MR_THREADS >= n) return;  // uniform over the block
-    const int col = blockIdx.x * MR_THREADS + threadIdx.x;
-    const bool valid = col < n;
-    MrhsIdentitySrc src{valid ? col : -1};
-    double* Ainv = C.a0inv + C.offI[b];
-    auto put = [&](int k, double y) {
-        if (valid) Ainv[(size_t)k * n + col] = y;
+    const int c0 = blockIdx.x * INV_CB;
+    if (c0 >= n) return;  // uniform over the block
+    const int kl = C.bkl[b], ku = C.bku[b];
+    const int ldu = kl + ku + 1, ldl = kl > 1 ? kl : 1;
+    const double* __restrict__ U = C.a0U + C.offU[b];
+    const double* __restrict__ L = C.a0L + C.offL[b];
+    const int* __restrict__ piv = C.a0piv + off;
+    double* __restrict__ Ainv = C.a0inv + C.offI[b];
+    double* X = smem;                                  // n x INV_CB
+    double* st = X + (size_t)n * INV_CB;               // 2 x INV_S x max_ldu
+    int* spiv = (int*)(st + 2 * INV_S * max_ldu);      // 2 x INV_S
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int i = tid; i < n * INV_CB; i += nt) {
+        const int r = i / INV_CB, c = i - r * INV_CB;
+        X[i] = (r == c0 + c) ? 1.0 : 0.0;
+    }
+    const int nq = (n + INV_S - 1) / INV_S;
+    double pre[INV_PF];
+    int ppre = 0;
+    // ---------------------------------------------------------- forward
+    auto issueL = [&](int q) {
+#pragma unroll
+        for (int e = 0; e < INV_PF; ++e) {
+            const int i = tid + e * nt;
+            double v = 0.0;
+            if (i < INV_S * ldl) {
+                const int s = i / ldl, j = i - s * ldl, k = q * INV_S + s;
+                if (k < n && j < kl && k + 1 + j < n) v = L[(size_t)k * ldl + j];
+            }
+            pre[e] = v;
+        }
+        if (tid < INV_S) {
+            const int k = q * INV_S + tid;
+            ppre = k < n ? piv[k] : k;
+        }
     };
-    band_solve_mrhs<KL, KW>(n, C.bkl[b], C.bku[b], C.a0U + C.offU[b], C.a0L + C.offL[b],
-                            C.a0piv + off, src, valid, col, C.a0fwd + C.offI[b], n, smem, sint, put);
+    auto commitL = [&](int q) {
+        double* dst = st + (size_t)(q & 1) * INV_S * max_ldu;
+#pragma unroll
+        for (int e = 0; e < INV_PF; ++e) {
+            const int i = tid + e * nt;
+            if (i < INV_S * ldl) dst[(i / ldl) * max_ldu + (i % ldl)] = pre[e];
+        }
+        if (tid < INV_S) spiv[(q & 1) * INV_S + tid] = ppre;
+    };
+    issueL(0);
+    commitL(0);
+    __syncthreads();
+    for (int q = 0; q < nq; ++q) {
+        if (q + 1 < nq) issueL(q + 1);
+        const double* lc = st + (size_t)(q & 1) * INV_S * max_ldu;
+        const int* pc = spiv + (q & 1) * INV_S;
+        for (int s = 0; s < INV_S; ++s) {
+            const int k = q * INV_S + s;
+            if (k >= n) break;
+            const int p = pc[s];
+            if (p != k) {
+                if (tid < INV_CB) {
+                    const double t = X[k * INV_CB + tid];
+                    X[k * INV_CB + tid] = X[p * INV_CB + tid];
+                    X[p * INV_CB + tid] = t;
+                }
+                __syncthreads();
+            }
+            const int lim = min(kl, n - 1 - k);
+            for (int i = tid; i < lim * INV_CB; i += nt) {
+                const int j = i / INV_CB, c = i - j * INV_CB;
+                X[(k + 1 + j) * INV_CB + c] -= lc[s * max_ldu + j] * X[k * INV_CB + c];
+            }
+            __syncthreads();
+        }
+        if (q + 1 < nq) commitL(q + 1);
+        __syncthreads();
+    }
+    // ---------------------------------------------------------- backward
+    // chunk q covers steps k = n - 1 - (q * INV_S + s)
+    auto issueU = [&](int q) {
+#pragma unroll
+        for (int e = 0; e < INV_PF; ++e) {
+            const int i = tid + e * nt;
+            double v = 0.0;
+            if (i < INV_S * ldu) {
+                const int s = i / ldu, o = i - s * ldu, k = n - 1 - (q * INV_S + s);
+                if (k >= 0 && o <= k) v = U[(size_t)k * ldu + o];
+            }
+            pre[e] = v;
+        }
+    };
+    auto commitU = [&](int q) {
+        double* dst = st + (size_t)(q & 1) * INV_S * max_ldu;
+#pragma unroll
+        for (int e = 0; e < INV_PF; ++e) {
+            const int i = tid + e * nt;
+            if (i < INV_S * ldu) dst[(i / ldu) * max_ldu + (i % ldu)] = pre[e];
+        }
+    };
+    issueU(0);
+    commitU(0);
+    __syncthreads();
+    for (int q = 0; q < nq; ++q) {
+        if (q + 1 < nq) issueU(q + 1);
+        const double* uc = st + (size_t)(q & 1) * INV_S * max_ldu;
+        for (int s = 0; s < INV_S; ++s) {
+            const int k = n - 1 - (q * INV_S + s);
+            if (k < 0) break;
+            const double inv = 1.0 / uc[s * max_ldu];
+            const int lim = min(ldu - 1, k);
+            for (int i = tid; i < (lim + 1) * INV_CB; i += nt) {
+                const int j = i / INV_CB, c = i - j * INV_CB;
+                const double xk = X[k * INV_CB + c] * inv;
+                if (j == 0) {
+                    if (c0 + c < n) Ainv[(size_t)k * n + c0 + c] = xk;
+                } else {
+                    X[(k - j) * INV_CB + c] -= uc[s * max_ldu + j] * xk;
+                }
+            }
+            __syncthreads();
+        }
+        if (q + 1 < nq) commitU(q + 1);
+        __syncthreads();
+    }
 }
 
 // y = A0^{-1} x, block by block: one wavefront per row.
@@ -2482,6 +2600,9 @@ int mrhs_bucket_kl(int kl, int ku) {
 }
 
 int mrhs_lds_bytes(int kl_bucket) { return 2 * MR_CH * (2 * kl_bucket + 1) * 8; }
+int coarse_inverse_lds_bytes(int max_block, int max_ldu) {
+    return (max_block * INV_CB + 2 * INV_S * max_ldu) * 8 + 2 * INV_S * 4;
+}
 
 hipError_t launch_tangent_prep(const DevMaps& P, const DevLocal& L, const DevTangent& Tg,
                                int kl_bucket, int max_ng, hipStream_t s) {
@@ -2500,13 +2621,14 @@ hipError_t launch_tangent_gemv(const DevMaps& P, const DevTangent& Tg, const dou
     return hipGetLastError();
 }
 
-hipError_t launch_coarse_inverse(const DevCoarse& C, int kl_bucket, int max_block, hipStream_t s) {
-    const dim3 nb((max_block + MR_THREADS - 1) / MR_THREADS, C.nblk);
-    const int lds = mrhs_lds_bytes(kl_bucket);
-#define NLS_CI(A, B)                                                                      if (kl_bucket == A) {                                                                     k_coarse_inverse<A, B><<<nb, MR_THREADS, lds, s>>>(C);                                return hipGetLastError();                                                         }
-    NLS_MR_BUCKETS(NLS_CI)
-#undef NLS_CI
-    return hipErrorInvalidValue;
+hipError_t launch_coarse_inverse(const DevCoarse& C, int max_block, int max_ldu, hipStream_t s) {
+    if (max_ldu > INV_MAXW) return hipErrorInvalidValue;
+    const dim3 nb((max_block + INV_CB - 1) / INV_CB, C.nblk);
+    const int lds = coarse_inverse_lds_bytes(max_block, max_ldu);
+    hipError_t e = set_lds(k_coarse_inverse, lds);
+    if (e != hipSuccess) return e;
+    k_coarse_inverse<<<nb, INV_THREADS, lds, s>>>(C, max_ldu);
+    return hipGetLastError();
 }
 
 hipError_t launch_dense_gemv(int n, const double* A, const double* x, double* y, hipStream_t s) {

@@ -109,7 +109,6 @@ struct DevCoarse {
     int* a0piv;
     double* rhs;                // n0, band order
     double* a0inv;              // n0 x n0 inverse of A0 (band order, row-major)
-    double* a0fwd;              // n0 x n0 scratch of the inverse
     double* c;                  // n0, coarse iterate (coarse id order)
     double* w;                  // N: u - Phi c
     double* scal;               // device scalars: [0] ||G||, [1] max|dc|, [2] max|c|
@@ -169,7 +168,9 @@ hipError_t launch_tangent_prep(const DevMaps& P, const DevLocal& L, const DevTan
                                int kl_bucket, int max_ng, hipStream_t s);
 hipError_t launch_tangent_gemv(const DevMaps& P, const DevTangent& Tg, const double* v, double* z,
                                int max_ng, hipStream_t s);
-hipError_t launch_coarse_inverse(const DevCoarse& C, int kl_bucket, int max_block, hipStream_t s);
+// A0^{-1} per diagonal block from its band LU (any band up to 511 wide)
+int coarse_inverse_lds_bytes(int max_block, int max_ldu);
+hipError_t launch_coarse_inverse(const DevCoarse& C, int max_block, int max_ldu, hipStream_t s);
 hipError_t launch_coarse_apply_inverse(const DevCoarse& C, const double* x, double* y, hipStream_t s);
 hipError_t launch_dense_gemv(int n, const double* A, const double* x, double* y, hipStream_t s);
 
