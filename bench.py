@@ -51,8 +51,8 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per dispatch measured with rocprofv3 FETCH_SIZE/WRITE_SIZE (two
 # passes, calibrated against a 256 MiB copy; profiles/hbm_traffic_*.md), valid
 # only for the kernel source they were taken with.
-MEASURED_TRAFFIC = {"kernels_sha1": "2d4f49209ad5b098c2660fa6d0812d17a74e28dc",
-                    "bytes": {"k_local_newton": 1524372778, "k_tangent_prep": 1198927989, "k_tangent_gemv": 280754705, "k_coarse_galerkin": 416203019, "k_coarse_lu": 1808829, "k_coarse_inverse": 14858629, "k_mdot_partial": 16580925, "k_maxpy": 28133516, "k_prolong": 27142873, "k_coarse_ty": 23981016}}
+MEASURED_TRAFFIC = {"kernels_sha1": "b8202df19637f0ba5544e680c5692dcb23205132",
+                    "bytes": {"k_local_newton": 1099027002, "k_local_factor": 433691017, "k_tangent_prep": 1198842258, "k_tangent_gemv": 280731710, "k_coarse_galerkin": 226718423, "k_coarse_lu": 1142085, "k_coarse_inverse": 12186577, "k_coarse_apply_inverse": 4085402, "k_mdot_partial": 18081278, "k_maxpy": 30408732, "k_prolong": 27167760, "k_coarse_ty": 23984418}}
 
 
 def _factor_bytes(case, elem_bytes):
@@ -443,13 +443,15 @@ def roofline(case, res, form):
         per_launch = float(fac.sum() + 8 * (ng.sum() + n.sum()))
     else:
         name, k = "local_newton", k_l
-        # per launch: (k_i + 1) factorizations write the factors and k_i
-        # solves read them; J values written and read; u gathered, T and x*
-        # written.  Averaged over subdomains with the measured totals.
+        # per launch: k_i factorizations write the factors and k_i solves
+        # read them (the factorisation at x* for the tangent runs in its own
+        # kernel when GMRES needs it); J values written and read; u
+        # gathered, T, x* and the Gamma values written.  Averaged over
+        # subdomains with the measured totals.
         launches = max(k["launches"], 1)
         mean_its = res["inner_its_steps"] / (launches * len(n))
         jac = 8 * 2 * 7 * n + 8 * 2 * n  # ~7 nonzeros per row, written and read; residual
-        per_sub = (mean_its + 1) * (fac + jac) + mean_its * fac + 8 * (n + ng + 2 * n)
+        per_sub = mean_its * (fac + jac) + mean_its * fac + 8 * (n + 2 * ng + 2 * n)
         per_launch = float(per_sub.sum())
     avg_s = k["ms"] / max(k["launches"], 1) / 1e3
     achieved = per_launch / avg_s / 1e9

@@ -596,6 +596,7 @@ extern "C" int nls_build_coarse(nls_handle* h, int kind) {
                         !(h->opt.flags & NLS_FLAG_COARSE_LU_APPLY);
     h->coarse_inv = h->coarse_can_inv;
     h->coarse_lu_valid = false;
+    h->coarse_inv_valid = false;
     if (h->coarse_inv) RC(h->alloc(G_COARSE, &d.a0inv, (size_t)C.offI.back()));
     HIPCHK(hipMemsetAsync(d.flag, 0, sizeof(int), h->stream));
     h->dc = d;
@@ -722,8 +723,15 @@ static int coarse_solve(nls_handle* h, const double* u, int* its_out) {
         if (refactor) {
             HIPCHK(launch_coarse_galerkin(h->dm, d, d.w, 0, h->stream));
             HIPCHK(launch_coarse_assemble(d, 1, h->stream));
+            HIPCHK(launch_coarse_lu(d, 1, h->lds_coarse_lu, h->npl_coarse, h->stream));
+            h->coarse_inv_valid = false;
+        } else if (h->coarse_inv_valid) {
+            // chord step with the explicit inverse of the same factorisation
+            HIPCHK(launch_coarse_apply_inverse(d, d.rhs, h->rhs2, h->stream));
+            HIPCHK(hipMemcpyAsync(d.rhs, h->rhs2, sizeof(double) * n0, hipMemcpyDeviceToDevice, h->stream));
+        } else {
+            HIPCHK(launch_coarse_lu(d, 0, h->lds_coarse_lu, h->npl_coarse, h->stream));
         }
-        HIPCHK(launch_coarse_lu(d, refactor ? 1 : 0, h->lds_coarse_lu, h->npl_coarse, h->stream));
         have_lu = chord;
         HIPCHK(launch_coarse_update(d, h->stream));
         double sc[3];
@@ -866,6 +874,7 @@ static int prepare_tangent(nls_handle* h) {
         HIPCHK(launch_coarse_lu(d, 1, h->lds_coarse_lu, h->npl_coarse, h->stream));
         h->coarse_lu_valid = true;
         if (h->coarse_inv) HIPCHK(launch_coarse_inverse(d, h->max_block, h->coarse_ldu, h->stream));
+        h->coarse_inv_valid = h->coarse_inv;
         int flag = 0;
         HIPCHK(hipMemcpyAsync(&flag, d.flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
         RC(sync(h));
@@ -992,6 +1001,7 @@ static int autotune_coarse(nls_handle* h) {
         h->drop_graphs();
         if (inv) HIPCHK(launch_coarse_inverse(d, h->max_block, h->coarse_ldu, h->stream));
     }
+    h->coarse_inv_valid = h->coarse_inv && h->tangent_ready;
     h->tune_ms[0] = t_inv;
     h->tune_ms[1] = t_apply;
     h->tune_ms[2] = t_lu;
@@ -1307,6 +1317,7 @@ extern "C" int nls_solve(nls_handle* h, double* u, int u_on_device, nls_stats* s
     S->failed_subdomain = -1;
     h->st = S;
     h->coarse_lu_valid = false;  // chord steps reuse factorisations within one solve only
+    h->coarse_inv_valid = false;
     const int N = h->mesh.ndof();
     double* ud = u;
     if (!u_on_device) {
@@ -1457,6 +1468,8 @@ static int nks_factor(nls_handle* h, const double* u) {
         HIPCHK(launch_coarse_assemble(d, 1, h->stream));
         HIPCHK(launch_coarse_lu(d, 1, h->lds_coarse_lu, h->npl_coarse, h->stream));
         if (h->coarse_inv) HIPCHK(launch_coarse_inverse(d, h->max_block, h->coarse_ldu, h->stream));
+        h->coarse_lu_valid = false;  // not the coarse Newton's matrix
+        h->coarse_inv_valid = false;
         int flag = 0;
         HIPCHK(hipMemcpyAsync(&flag, d.flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
         RC(sync(h));
@@ -1551,6 +1564,7 @@ extern "C" int nls_eval_precond_residual(nls_handle* h, const double* u, double*
         return fail(h, NLS_ESTATE, "two-level coupling needs nls_build_coarse");
     HIPCHK(hipSetDevice(h->opt.device));
     h->coarse_lu_valid = false;
+    h->coarse_inv_valid = false;
     RC(evaluate(h, u, Fx));
     return sync(h);
 }

@@ -53,6 +53,7 @@ struct nls_handle {
     int tangent_bucket = 0, max_ng = 0;
     bool coarse_inv = false;      // explicit A0^{-1} for the tangent
     bool coarse_lu_valid = false; // a factorisation of A0 is held (chord steps)
+    bool coarse_inv_valid = false; // a0inv is the inverse of that factorisation
     bool tangent_ready = false;   // prepare_tangent ran at the last evaluated point
     bool local_factored = false;  // J_ii and its LU at the last evaluation's x* are held
     bool nks_mode = false;        // GMRES operator is DF(u) M^{-1} (Newton-Krylov-Schwarz)
