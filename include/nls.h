@@ -123,6 +123,11 @@ typedef struct nls_options {
    refinement, and binary64 LU) and the faster total is kept for all of
    them.  nls_get_tuning reports the decisions. */
 #define NLS_FLAG_AUTOTUNE 16
+/* options.flags: with the additive coupling, run the coarse Newton solve
+   T_0(u) (eq. 9) on a second stream of the handle, concurrently with the
+   local solves T_i(u) (eq. 4); both depend on u only.  Results are those
+   of the serial order; the reported inner and coarse phase times overlap. */
+#define NLS_FLAG_OVERLAP  32
 
 /* ---- statistics of the last solve ------------------------------------ */
 #define NLS_MAX_OUTER 64

@@ -698,21 +698,21 @@ static bool two_level(nls_handle* h) {
 // the previous tangent, or the first step's) and refactor only when the
 // residual fails to halve.  A0 and its LU at the converged c*, which only
 // the tangent needs, are formed by prepare_tangent.
-static int coarse_solve(nls_handle* h, const double* u, int* its_out) {
+static int coarse_solve(nls_handle* h, const double* u, int* its_out, hipStream_t cs) {
     DevCoarse& d = h->dc;
     const int n0 = d.n0;
     const bool chord = (h->opt.flags & NLS_FLAG_COARSE_CHORD) != 0;
-    HIPCHK(hipMemsetAsync(d.c, 0, sizeof(double) * n0, h->stream));
+    HIPCHK(hipMemsetAsync(d.c, 0, sizeof(double) * n0, cs));
     double tol = 0.0, dprev = -1.0, cmax = 0.0, gprev = 0.0;
     int its = 0;
     bool have_lu = chord && h->coarse_lu_valid;
     for (;;) {
-        HIPCHK(launch_coarse_w(h->dm, d, u, d.w, h->stream));
-        HIPCHK(launch_coarse_q(h->dm, d, d.w, nullptr, 0, h->lds_coarse_q, h->stream));
-        HIPCHK(launch_coarse_assemble(d, 0, h->stream));
+        HIPCHK(launch_coarse_w(h->dm, d, u, d.w, cs));
+        HIPCHK(launch_coarse_q(h->dm, d, d.w, nullptr, 0, h->lds_coarse_q, cs));
+        HIPCHK(launch_coarse_assemble(d, 0, cs));
         double gn = 0.0;
-        HIPCHK(hipMemcpyAsync(&gn, d.scal, sizeof(double), hipMemcpyDeviceToHost, h->stream));
-        RC(sync(h));
+        HIPCHK(hipMemcpyAsync(&gn, d.scal, sizeof(double), hipMemcpyDeviceToHost, cs));
+        HIPCHK(hipStreamSynchronize(cs));
         if (its == 0)
             tol = std::max(h->opt.inner_rtol * gn, h->opt.inner_eta * h->phib_inf * std::sqrt((double)n0));
         if (!std::isfinite(gn)) return fail(h, NLS_ENAN, "coarse residual is not finite");
@@ -721,24 +721,24 @@ static int coarse_solve(nls_handle* h, const double* u, int* its_out) {
         if (its == h->opt.inner_maxit) return fail(h, NLS_ELOCAL, "coarse Newton did not converge");
         const bool refactor = !have_lu || (its > 0 && gn > 0.5 * gprev);
         if (refactor) {
-            HIPCHK(launch_coarse_galerkin(h->dm, d, d.w, 0, h->stream));
-            HIPCHK(launch_coarse_assemble(d, 1, h->stream));
-            HIPCHK(launch_coarse_lu(d, 1, h->lds_coarse_lu, h->npl_coarse, h->stream));
+            HIPCHK(launch_coarse_galerkin(h->dm, d, d.w, 0, cs));
+            HIPCHK(launch_coarse_assemble(d, 1, cs));
+            HIPCHK(launch_coarse_lu(d, 1, h->lds_coarse_lu, h->npl_coarse, cs));
             h->coarse_inv_valid = false;
         } else if (h->coarse_inv_valid) {
             // chord step with the explicit inverse of the same factorisation
-            HIPCHK(launch_coarse_apply_inverse(d, d.rhs, h->rhs2, h->stream));
-            HIPCHK(hipMemcpyAsync(d.rhs, h->rhs2, sizeof(double) * n0, hipMemcpyDeviceToDevice, h->stream));
+            HIPCHK(launch_coarse_apply_inverse(d, d.rhs, h->rhs2, cs));
+            HIPCHK(hipMemcpyAsync(d.rhs, h->rhs2, sizeof(double) * n0, hipMemcpyDeviceToDevice, cs));
         } else {
-            HIPCHK(launch_coarse_lu(d, 0, h->lds_coarse_lu, h->npl_coarse, h->stream));
+            HIPCHK(launch_coarse_lu(d, 0, h->lds_coarse_lu, h->npl_coarse, cs));
         }
         have_lu = chord;
-        HIPCHK(launch_coarse_update(d, h->stream));
+        HIPCHK(launch_coarse_update(d, cs));
         double sc[3];
         int flag = 0;
-        HIPCHK(hipMemcpyAsync(sc, d.scal, 3 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-        HIPCHK(hipMemcpyAsync(&flag, d.flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
-        RC(sync(h));
+        HIPCHK(hipMemcpyAsync(sc, d.scal, 3 * sizeof(double), hipMemcpyDeviceToHost, cs));
+        HIPCHK(hipMemcpyAsync(&flag, d.flag, sizeof(int), hipMemcpyDeviceToHost, cs));
+        HIPCHK(hipStreamSynchronize(cs));
         if (flag) return fail(h, NLS_ESINGULAR, "zero pivot in the coarse matrix");
         dprev = sc[1];
         cmax = sc[2];
@@ -755,11 +755,11 @@ static int dot_host(nls_handle* h, const double* x, const double* y, int n, doub
     return sync(h);
 }
 
-static int coarse_phase(nls_handle* h, const double* u) {
+static int coarse_phase(nls_handle* h, const double* u, hipStream_t cs) {
     Timer tc;
     int cits = 0;
-    RC(coarse_solve(h, u, &cits));
-    RC(sync(h));
+    RC(coarse_solve(h, u, &cits, cs));
+    HIPCHK(hipStreamSynchronize(cs));
     if (h->st) {
         h->st->ms_coarse += tc.ms();
         h->st->coarse_its_total += cits;
@@ -774,8 +774,21 @@ static int evaluate(nls_handle* h, const double* u, double* Fx) {
     h->have_state = false;
     const bool hybrid = h->opt.coupling == NLS_HYBRID && two_level(h);
     if (hybrid) {
-        RC(coarse_phase(h, u));
+        RC(coarse_phase(h, u, h->stream));
         u = h->dc.w;
+    }
+    // Additive coupling with NLS_FLAG_OVERLAP: T_0(u) depends on u only, so
+    // the coarse Newton solve runs on a second stream while the local solves
+    // run; its small kernels fit beside the local workgroups on each CU.
+    const bool overlap = two_level(h) && !hybrid && (h->opt.flags & NLS_FLAG_OVERLAP);
+    if (overlap) {
+        if (!h->cstream) {
+            HIPCHK(hipStreamCreateWithFlags(&h->cstream, hipStreamNonBlocking));
+            HIPCHK(hipEventCreateWithFlags(&h->cev[0], hipEventDisableTiming));
+            HIPCHK(hipEventCreateWithFlags(&h->cev[1], hipEventDisableTiming));
+        }
+        HIPCHK(hipEventRecord(h->cev[0], h->stream));  // u is final on the main stream
+        HIPCHK(hipStreamWaitEvent(h->cstream, h->cev[0], 0));
     }
     Timer t;
     NewtonParams np = h->np;
@@ -802,6 +815,15 @@ static int evaluate(nls_handle* h, const double* u, double* Fx) {
     }
     HIPCHK(launch_any_status(h->dl.status, h->maps.nsub, h->stat2, h->stream));
     int st2[2];
+    if (overlap) {
+        const int rc = coarse_phase(h, u, h->cstream);
+        HIPCHK(hipEventRecord(h->cev[1], h->cstream));
+        HIPCHK(hipStreamWaitEvent(h->stream, h->cev[1], 0));
+        if (rc) {
+            (void)sync(h);
+            return rc;
+        }
+    }
     HIPCHK(hipMemcpyAsync(st2, h->stat2, 2 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipMemcpyAsync(h->its_h.data(), h->dl.its, h->maps.nsub * sizeof(int),
                           hipMemcpyDeviceToHost, h->stream));
@@ -822,7 +844,7 @@ static int evaluate(nls_handle* h, const double* u, double* Fx) {
     }
     RC(guess_after_local(h, u));
     if (two_level(h)) {
-        if (!hybrid) RC(coarse_phase(h, u));
+        if (!hybrid && !overlap) RC(coarse_phase(h, u, h->stream));
         HIPCHK(launch_prolong(h->dm, h->dp, h->dl.T, &h->dc, h->dc.c, Fx, nullptr, h->stream));
     } else {
         HIPCHK(launch_prolong(h->dm, h->dp, h->dl.T, nullptr, nullptr, Fx, nullptr, h->stream));

@@ -88,6 +88,9 @@ struct nls_handle {
     // GMRES cycles with device-side rotations; blocks of gblock Arnoldi
     // steps captured once as HIP graphs and replayed on gstream
     hipStream_t gstream = nullptr;
+    // second stream of NLS_FLAG_OVERLAP (coarse Newton beside the local solves)
+    hipStream_t cstream = nullptr;
+    hipEvent_t cev[2] = {nullptr, nullptr};
     hipEvent_t gev[2] = {nullptr, nullptr};
     std::vector<hipGraphExec_t> gexec;
     double *Hd = nullptr, *csd = nullptr, *snd = nullptr, *gd = nullptr, *gtol = nullptr;
@@ -135,6 +138,9 @@ struct nls_handle {
         for (auto e : gev)
             if (e) (void)hipEventDestroy(e);
         if (gstream) (void)hipStreamDestroy(gstream);
+        if (cstream) (void)hipStreamDestroy(cstream);
+        for (hipEvent_t& e : cev)
+            if (e) (void)hipEventDestroy(e);
         for (auto& g : bufs)
             for (void* p : g) (void)hipFree(p);
         for (auto& u : ev_used) {

@@ -45,6 +45,7 @@ FLAG_GRAPH = 2
 FLAG_COARSE_CHORD = 4
 FLAG_COARSE_LU_APPLY = 8
 FLAG_AUTOTUNE = 16
+FLAG_OVERLAP = 32
 
 # every symbol include/nls.h declares
 SYMBOLS = (

@@ -251,15 +251,18 @@ def test_graph_gmres_matches_step_by_step(coupling):
         assert stg2["gmres_its"] == stg1["gmres_its"]
 
 
-@pytest.mark.parametrize("flags", ["chord", "lu_apply", "chord+lu_apply+graph"])
+@pytest.mark.parametrize("flags", ["chord", "lu_apply", "chord+lu_apply+graph", "overlap",
+                                   "chord+graph+overlap"])
 def test_coarse_variants_match_oracle(flags):
-    """Chord steps for T_0 and/or band LU solves in place of the explicit
-    coarse inverse: F_x, the tangent and the solve match the oracle."""
+    """Chord steps for T_0, band LU solves in place of the explicit coarse
+    inverse, the coarse solve beside the local solves: F_x, the tangent and
+    the solve match the oracle."""
     from paper_2410_24138_amd import nls
     f = 0
     f |= nls.FLAG_COARSE_CHORD if "chord" in flags else 0
     f |= nls.FLAG_COARSE_LU_APPLY if "lu_apply" in flags else 0
     f |= nls.FLAG_GRAPH if "graph" in flags else 0
+    f |= nls.FLAG_OVERLAP if "overlap" in flags else 0
     case = synth.small_case(n=24, boxes=4, overlap=2, forcing_seed=2, two_level=True)
     P = P1Problem(case)
     S = Schwarz(P, "additive")
