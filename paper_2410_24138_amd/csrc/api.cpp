@@ -1049,7 +1049,7 @@ static int tangent(nls_handle* h, const double* v, double* y, hipStream_t s = nu
     auto coarse_term = [&]() -> int {
         DevCoarse& d = h->dc;
         HIPCHK(launch_coarse_ty(d, v, s));
-        HIPCHK(launch_coarse_assemble(d, 0, s));
+        HIPCHK(launch_coarse_gather(d, s));
         if (h->coarse_inv) {
             HIPCHK(launch_coarse_apply_inverse(d, d.rhs, h->rhs2, s));
             HIPCHK(launch_coarse_scatter(d, h->rhs2, h->ctmp, s));
@@ -1112,8 +1112,7 @@ static int arnoldi_step(nls_handle* h, int j, hipStream_t s) {
     HIPCHK(launch_mdot(h->V, ld, j + 1, h->wv, N, h->partial, h->hbuf, h->nb_dot, s));
     HIPCHK(launch_maxpy(h->V, ld, j + 1, h->hbuf, h->wv, N, 1.0, s));
     HIPCHK(launch_mdot(h->V, ld, j + 1, h->wv, N, h->partial, h->hbuf2, h->nb_dot, s));
-    HIPCHK(launch_maxpy(h->V, ld, j + 1, h->hbuf2, h->wv, N, 1.0, s));
-    HIPCHK(launch_mdot(h->wv, ld, 1, h->wv, N, h->partial, h->hn2, h->nb_dot, s));
+    HIPCHK(launch_maxpy_norm(h->V, ld, j + 1, h->hbuf2, h->wv, N, h->partial, h->hn2, h->nb_dot, s));
     HIPCHK(launch_scale_by(h->wv, h->hn2, vn, N, s));
     HIPCHK(launch_gmres_givens(gmres_dev(h), j, s));
     return NLS_OK;
@@ -1286,8 +1285,8 @@ static int gmres(nls_handle* h, const double* b, double* x, int* its_out) {
             HIPCHK(launch_mdot(h->V, ld, j + 1, h->wv, N, h->partial, h->hbuf, h->nb_dot, h->stream));
             HIPCHK(launch_maxpy(h->V, ld, j + 1, h->hbuf, h->wv, N, 1.0, h->stream));
             HIPCHK(launch_mdot(h->V, ld, j + 1, h->wv, N, h->partial, h->hbuf2, h->nb_dot, h->stream));
-            HIPCHK(launch_maxpy(h->V, ld, j + 1, h->hbuf2, h->wv, N, 1.0, h->stream));
-            HIPCHK(launch_mdot(h->wv, ld, 1, h->wv, N, h->partial, h->hn2, h->nb_dot, h->stream));
+            HIPCHK(launch_maxpy_norm(h->V, ld, j + 1, h->hbuf2, h->wv, N, h->partial, h->hn2,
+                                     h->nb_dot, h->stream));
             HIPCHK(launch_scale_by(h->wv, h->hn2, vn, N, h->stream));
             double hn2;
             HIPCHK(hipMemcpyAsync(hh.data(), h->hbuf, (j + 1) * sizeof(double), hipMemcpyDeviceToHost, h->stream));
@@ -1440,7 +1439,7 @@ static int nks_precond(nls_handle* h, const double* x, hipStream_t s) {
     if (two_level(h)) {
         DevCoarse& d = h->dc;
         HIPCHK(launch_coarse_phit(d, x, s));
-        HIPCHK(launch_coarse_assemble(d, 0, s));
+        HIPCHK(launch_coarse_gather(d, s));
         if (h->coarse_inv) {
             HIPCHK(launch_coarse_apply_inverse(d, d.rhs, h->rhs2, s));
             HIPCHK(launch_coarse_scatter(d, h->rhs2, h->ctmp, s));

@@ -2323,6 +2323,35 @@ __global__ void k_maxpy(const double* __restrict__ V, int64_t ld, int m, const d
     w[t] -= sign * acc;
 }
 
+// w -= sum_j h[j] V[j] and the partial sums of ||w||^2 over the same block
+// chunks as k_mdot_partial (so k_mdot_final with m = 1 completes the norm).
+__global__ void __launch_bounds__(NLS_BLOCK)
+k_maxpy_norm(const double* __restrict__ V, int64_t ld, int m, const double* __restrict__ h,
+             double* __restrict__ w, int n, double* __restrict__ partial) {
+    __shared__ double red[24];
+    const int chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+    double ss = 0.0;
+    for (int t = lo + threadIdx.x; t < hi; t += blockDim.x) {
+        double acc = 0.0;
+        for (int j = 0; j < m; ++j) acc += h[j] * V[(int64_t)j * ld + t];
+        const double x = w[t] - acc;
+        w[t] = x;
+        ss += x * x;
+    }
+    ss = block_sum(ss, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = ss;
+}
+
+// rhs[perm[k]] = sum of the coarse blocks' entries of row k (no norm).
+__global__ void k_coarse_gather(DevCoarse C) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= C.n0) return;
+    double acc = 0.0;
+    for (int t = C.gsrc_ptr[k]; t < C.gsrc_ptr[k + 1]; ++t) acc += C.gblk[C.gsrc[t]];
+    C.rhs[C.perm[k]] = acc;
+}
+
 __global__ void k_scale_by(const double* __restrict__ x, const double* __restrict__ dsq,
                            double* __restrict__ y, int n) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -2651,6 +2680,18 @@ hipError_t launch_mdot(const double* V, int64_t ld, int m, const double* w, int 
 hipError_t launch_maxpy(const double* V, int64_t ld, int m, const double* h, double* w, int n,
                         double sign, hipStream_t s) {
     k_maxpy<<<nblocks(n), NLS_BLOCK, 0, s>>>(V, ld, m, h, w, n, sign);
+    return hipGetLastError();
+}
+
+hipError_t launch_maxpy_norm(const double* V, int64_t ld, int m, const double* h, double* w, int n,
+                             double* partial, double* out, int nb, hipStream_t s) {
+    k_maxpy_norm<<<nb, NLS_BLOCK, 0, s>>>(V, ld, m, h, w, n, partial);
+    k_mdot_final<<<1, 256, 0, s>>>(partial, nb, 1, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_coarse_gather(const DevCoarse& C, hipStream_t s) {
+    k_coarse_gather<<<nblocks(C.n0), NLS_BLOCK, 0, s>>>(C);
     return hipGetLastError();
 }
 

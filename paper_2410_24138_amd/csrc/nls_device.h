@@ -157,6 +157,11 @@ hipError_t launch_coarse_galerkin(const DevMesh& M, const DevCoarse& C, const do
                                   int with_y, hipStream_t s);
 hipError_t launch_coarse_ty(const DevCoarse& C, const double* v, hipStream_t s);
 hipError_t launch_coarse_assemble(const DevCoarse& C, int with_matrix, hipStream_t s);
+// the right-hand side part of launch_coarse_assemble, spread over the grid
+hipError_t launch_coarse_gather(const DevCoarse& C, hipStream_t s);
+// w -= V h (m columns) and out = ||w||^2 (deterministic, nb block partials)
+hipError_t launch_maxpy_norm(const double* V, int64_t ld, int m, const double* h, double* w, int n,
+                             double* partial, double* out, int nb, hipStream_t s);
 hipError_t launch_coarse_lu(const DevCoarse& C, int factor, int lds_bytes, int nb_per_lane,
                             hipStream_t s);
 hipError_t launch_coarse_update(const DevCoarse& C, hipStream_t s);
