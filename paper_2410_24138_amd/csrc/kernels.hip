@@ -2093,10 +2093,8 @@ k_coarse_galerkin(DevMesh M, DevCoarse C, const double* __restrict__ w, int with
                         }
                 }
             }
-            if (with_y) {
-                double* yr = y + (int64_t)a * nk;
-                for (int l = 0; l < nk; ++l) yr[l] = zr[l];
-            }
+            if (with_y)
+                for (int l = 0; l < nk; ++l) y[(int64_t)l * nc + a] = zr[l];
         }
         __syncthreads();
         const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -2141,8 +2139,7 @@ k_coarse_galerkin(DevMesh M, DevCoarse C, const double* __restrict__ w, int with
     if (with_y) {
         double* y = C.ybuf + C.off_phi[i];
         for (int c = threadIdx.x; c < nc; c += blockDim.x) {
-            double* yr = y + (int64_t)c * nk;
-            for (int l = 0; l < nk; ++l) yr[l] = 0.0;
+            for (int l = 0; l < nk; ++l) y[(int64_t)l * nc + c] = 0.0;
             for (int t = C.cinc_ptr[cb + c]; t < C.cinc_ptr[cb + c + 1]; ++t) {
                 const int code = C.cinc[t];
                 const int e = eb + (code >> 2), pc = code & 3;
@@ -2164,7 +2161,7 @@ k_coarse_galerkin(DevMesh M, DevCoarse C, const double* __restrict__ w, int with
                     // K_T[a][pc]
                     const double K = coef * gr[pc] + M.beta * kap * sa * (U + uu[pc]) * (1.0 / 6.0);
                     const double* pr = ph + (int64_t)cn[a] * nk;
-                    for (int l = 0; l < nk; ++l) yr[l] += K * pr[l];
+                    for (int l = 0; l < nk; ++l) y[(int64_t)l * nc + c] += K * pr[l];
                 }
             }
         }
@@ -2180,7 +2177,8 @@ k_coarse_galerkin(DevMesh M, DevCoarse C, const double* __restrict__ w, int with
     }
 }
 
-// gblk_i = Y_i^T v on the closure of subdomain i (coarse term of the tangent).
+// gblk_i = Y_i^T v on the closure of subdomain i (coarse term of the tangent);
+// Y_i is stored column by column (Y[k * nc + c]), so the lanes read along c.
 __global__ void __launch_bounds__(NLS_BLOCK)
 k_coarse_ty(DevCoarse C, const double* __restrict__ v) {
     const int i = blockIdx.x;
@@ -2190,7 +2188,7 @@ k_coarse_ty(DevCoarse C, const double* __restrict__ v) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int k = wv; k < nk; k += nw) {
         double acc = 0.0;
-        for (int c = lane; c < nc; c += 64) acc += y[(int64_t)c * nk + k] * v[C.cnode[cb + c]];
+        for (int c = lane; c < nc; c += 64) acc += y[(int64_t)k * nc + c] * v[C.cnode[cb + c]];
         acc = wave_sum(acc);
         if (lane == 0) C.gblk[k0 + k] = acc;
     }
@@ -2645,7 +2643,9 @@ hipError_t launch_tangent_prep(const DevMaps& P, const DevLocal& L, const DevTan
 
 hipError_t launch_tangent_gemv(const DevMaps& P, const DevTangent& Tg, const double* v, double* z,
                                int max_ng, hipStream_t s) {
-    dim3 grid(P.nsub, 2);
+    // four workgroups per subdomain: one owned row per thread at up to 1024
+    // owned rows, so that enough loads of W are in flight per CU
+    dim3 grid(P.nsub, 4);
     k_tangent_gemv<<<grid, 256, max_ng * 8, s>>>(P, Tg, v, z);
     return hipGetLastError();
 }

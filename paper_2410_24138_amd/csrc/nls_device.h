@@ -96,7 +96,8 @@ struct DevCoarse {
     const int64_t *offU, *offL, *offI;
     double* phi;                // dense |C_i| x |K_i| blocks
     double* zbuf;               // same shape: DF Phi rows (scratch)
-    double* ybuf;               // same shape: DF^T Phi at the converged coarse point
+    double* ybuf;               // DF^T Phi at the converged coarse point, per subdomain
+                                //   column-major (|closure| rows contiguous per function)
     double* ival;               // interior CSR values (setup scratch)
     double* iU;                 // interior factors (setup scratch)
     double* iL;
