@@ -366,7 +366,7 @@ template <typename T>
 __device__ __forceinline__ int band_lu(int n, int kl, int ku, const int* __restrict__ rptr,
                        const int* __restrict__ cols, const double* __restrict__ vals,
                        T* W, T* mult, int* sflag, T* __restrict__ Uf, T* __restrict__ Lf,
-                       int* __restrict__ piv, int cbase = 0) {
+                       int* __restrict__ piv, int cbase = 0, double* rhs = nullptr) {
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
     // ring buffer of R rows x C columns; row r sits in slot r mod R, column c
@@ -421,6 +421,11 @@ __device__ __forceinline__ int band_lu(int n, int kl, int ku, const int* __restr
                 rowk[c] = rowp[c];
                 rowp[c] = t;
             }
+            if (rhs && tid == 0) {
+                const double t = rhs[k];
+                rhs[k] = rhs[k + pd];
+                rhs[k + pd] = t;
+            }
             __syncthreads();
         }
         const T pv = rowk[kc];
@@ -431,6 +436,7 @@ __device__ __forceinline__ int band_lu(int n, int kl, int ku, const int* __restr
             const T l = (pv != T(0)) ? W[sr * C + kc] / pv : T(0);
             mult[j] = l;
             Lf[(size_t)k * ldl + j] = l;
+            if (rhs) rhs[k + 1 + j] -= (double)l * rhs[k];
         }
         for (int c = tid; c <= nc; c += nt) {
             const int sc = kc + c < C ? kc + c : kc + c - C;
@@ -560,7 +566,7 @@ template <typename T, int NB>
 __device__ __forceinline__ int band_lu_blocked(int n, int kl, int ku, const int* __restrict__ rptr,
                                const int* __restrict__ cols, const double* __restrict__ vals,
                                T* W, int* sh, T* __restrict__ Uf, T* __restrict__ Lf,
-                               int* __restrict__ piv, int cbase = 0) {
+                               int* __restrict__ piv, int cbase = 0, double* rhs = nullptr) {
     T* lt = W + (NB + kl) * (NB + kl + ku);  // L11 of the current panel, NB x NB
     int* mv = (int*)(lt + NB * NB);           // moved rows of the panel (<= 64)
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -631,6 +637,9 @@ __device__ __forceinline__ int band_lu_blocked(int n, int kl, int ku, const int*
             for (int c = 0; c < NB; ++c) p[c] = have ? W[sr * Wd + wrap(cb + c, Wd)] : T(0);
             int pos = lane, sing = 0;
             bool used = false;
+            // right-hand side (forward substitution fused with the
+            // factorisation): each row carries its entry through the steps
+            double pb = (rhs && have) ? rhs[k0 + lane] : 0.0;
             // The steps hold no stores (the multipliers and interchanges are
             // stored after the loop) and no branch but the one around the
             // pivot search.
@@ -673,11 +682,13 @@ __device__ __forceinline__ int band_lu_blocked(int n, int kl, int ku, const int*
                 p[j] = below ? l : p[j];
 #pragma unroll
                 for (int c = j + 1; c < NB; ++c) p[c] -= l * rdlane(p[c], plr);
+                if (rhs) pb -= (double)l * rdlane(pb, plr);
             }
             if (lane < nbp) piv[k0 + lane] = k0 + dsel;
 #pragma unroll
             for (int j = 0; j < NB; ++j)
                 if ((below_mask >> j) & 1u) Lf[(size_t)(k0 + j) * ldl + (posj[j] - j - 1)] = p[j];
+            if (rhs && have) rhs[k0 + pos] = pb;
             if (have) {
                 const int sp = wrap(rb + pos, H);
 #pragma unroll
@@ -833,17 +844,20 @@ __device__ __forceinline__ int band_lu_blocked(int n, int kl, int ku, const int*
 }
 
 // Choose the blocked factorization when its panel fits a wavefront.
+// With rhs (length n, LDS), the row operations are applied to it as well,
+// so that it leaves holding the forward-substituted L^{-1} P rhs.
 template <typename T>
 __device__ __forceinline__ int band_lu_auto(int n, int kl, int ku, const int* __restrict__ rptr,
                             const int* __restrict__ cols, const double* __restrict__ vals,
                             T* W, T* mult, int* sflag, T* __restrict__ Uf, T* __restrict__ Lf,
-                            int* __restrict__ piv, int cbase = 0, int variant = 0) {
+                            int* __restrict__ piv, int cbase = 0, int variant = 0,
+                            double* rhs = nullptr) {
     // variant: 0 widest panel the band allows, 1 NB=16, 2 NB=8, 3 unblocked
     if ((variant == 0 || variant == 1) && kl + 16 <= 64)
-        return band_lu_blocked<T, 16>(n, kl, ku, rptr, cols, vals, W, sflag, Uf, Lf, piv, cbase);
+        return band_lu_blocked<T, 16>(n, kl, ku, rptr, cols, vals, W, sflag, Uf, Lf, piv, cbase, rhs);
     if ((variant == 0 || variant == 2) && kl + 8 <= 64)
-        return band_lu_blocked<T, 8>(n, kl, ku, rptr, cols, vals, W, sflag, Uf, Lf, piv, cbase);
-    return band_lu<T>(n, kl, ku, rptr, cols, vals, W, mult, sflag, Uf, Lf, piv, cbase);
+        return band_lu_blocked<T, 8>(n, kl, ku, rptr, cols, vals, W, sflag, Uf, Lf, piv, cbase, rhs);
+    return band_lu<T>(n, kl, ku, rptr, cols, vals, W, mult, sflag, Uf, Lf, piv, cbase, rhs);
 }
 
 // ----------------------------------------------------------------------------
@@ -855,11 +869,11 @@ __device__ __forceinline__ int band_lu_auto(int n, int kl, int ku, const int* __
 template <typename T, int NPL>
 __device__ __forceinline__ void band_solve_wave(int n, int kl, int ku, const T* __restrict__ Uf,
                                 const T* __restrict__ Lf, const int* __restrict__ piv,
-                                double* b) {
+                                double* b, bool backward_only = false) {
     constexpr int S = 8;
     const int lane = threadIdx.x & 63;
     const int ldu = kl + ku + 1, ldl = kl > 1 ? kl : 1;
-    for (int k0 = 0; k0 < n; k0 += S) {
+    for (int k0 = 0; k0 < (backward_only ? 0 : n); k0 += S) {
         double lv[S][NPL];
         int pv[S];
 #pragma unroll
@@ -932,9 +946,9 @@ __device__ __forceinline__ void band_solve_wave(int n, int kl, int ku, const T* 
 template <int NPL>
 __device__ __forceinline__ void band_solve_any(bool f32, int n, int kl, int ku, const double* Ud,
                                const double* Ld, const float* Us, const float* Ls,
-                               const int* piv, double* b) {
-    if (f32) band_solve_wave<float, NPL>(n, kl, ku, Us, Ls, piv, b);
-    else band_solve_wave<double, NPL>(n, kl, ku, Ud, Ld, piv, b);
+                               const int* piv, double* b, bool backward_only = false) {
+    if (f32) band_solve_wave<float, NPL>(n, kl, ku, Us, Ls, piv, b, backward_only);
+    else band_solve_wave<double, NPL>(n, kl, ku, Ud, Ld, piv, b, backward_only);
 }
 
 // Solve J d = rb in place (rb in LDS).  FP64 factors: one band solve.  FP32
@@ -943,7 +957,7 @@ __device__ __forceinline__ void band_solve_any(bool f32, int n, int kl, int ku, 
 template <int NPL>
 __device__ __forceinline__ void local_linear_solve(const DevMaps& P, const DevLocal& L, const NewtonParams& np,
                                    int i, int n, int rowbase, double* rb, double* r0,
-                                   double* dl, double* red) {
+                                   double* dl, double* red, bool forward_done = false) {
     const int kl = P.kl[i], ku = P.ku[i];
     const double* Ud = L.Uf + P.off_u[i];
     const double* Ld = L.Lf + P.off_l[i];
@@ -951,7 +965,7 @@ __device__ __forceinline__ void local_linear_solve(const DevMaps& P, const DevLo
     const float* Ls = np.mixed ? L.Lf32 + P.off_l[i] : nullptr;
     const int* piv = L.piv + rowbase;
     if (!np.mixed) {
-        if (threadIdx.x < 64) band_solve_any<NPL>(false, n, kl, ku, Ud, Ld, Us, Ls, piv, rb);
+        if (threadIdx.x < 64) band_solve_any<NPL>(false, n, kl, ku, Ud, Ld, Us, Ls, piv, rb, forward_done);
         __syncthreads();
         return;
     }
@@ -986,8 +1000,10 @@ __device__ __forceinline__ void local_linear_solve(const DevMaps& P, const DevLo
 }
 
 // Factor J at the current point into FP64 or FP32 storage.
+// rhs (FP64 only): forward substitution fused with the factorisation.
 __device__ __forceinline__ int local_factor(const DevMaps& P, const DevLocal& L, const NewtonParams& np, int i,
-                            int n, int rowbase, void* W, void* mult, int* sflag, bool fp64 = false) {
+                            int n, int rowbase, void* W, void* mult, int* sflag, bool fp64 = false,
+                            double* rhs = nullptr) {
     const int kl = P.kl[i], ku = P.ku[i];
     const int* rptr = P.jptr + rowbase;
     if (np.mixed && !fp64)
@@ -996,7 +1012,7 @@ __device__ __forceinline__ int local_factor(const DevMaps& P, const DevLocal& L,
                               np.lu_variant);
     return band_lu_auto<double>(n, kl, ku, rptr, P.jcol, L.jval, (double*)W, (double*)mult, sflag,
                            L.Uf + P.off_u[i], L.Lf + P.off_l[i], L.piv + rowbase, 0,
-                           np.lu_variant);
+                           np.lu_variant, rhs);
 }
 
 // ----------------------------------------------------------------------------
@@ -1078,8 +1094,13 @@ k_local_newton(DevMesh M, DevMaps P, DevLocal L, NewtonParams np, const double* 
             if (its == np.maxit) { status = 1; break; }
             local_jacobian<ELAST>(M, P, n, rowbase, ebase, vp, L.jval);
             __syncthreads();
-            if (local_factor(P, L, np, i, n, rowbase, W, mult, sflag)) { status = 3; break; }
-            local_linear_solve<NPL>(P, L, np, i, n, rowbase, rb, r0, dl, red);
+            // FP64: the factorisation also carries out the forward
+            // substitution on the residual, the solve only the backward one
+            if (local_factor(P, L, np, i, n, rowbase, W, mult, sflag, false, np.mixed ? nullptr : rb)) {
+                status = 3;
+                break;
+            }
+            local_linear_solve<NPL>(P, L, np, i, n, rowbase, rb, r0, dl, red, !np.mixed);
             double dm = 0.0;
             for (int a = threadIdx.x; a < n; a += blockDim.x) {
                 vp[a] -= rb[a];
