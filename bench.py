@@ -52,22 +52,26 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per dispatch measured with rocprofv3 FETCH_SIZE/WRITE_SIZE (two
 # passes, calibrated against a 256 MiB copy; profiles/hbm_traffic_*.md), valid
 # only for the kernel source they were taken with.
-MEASURED_TRAFFIC = {"kernels_sha1": "b8202df19637f0ba5544e680c5692dcb23205132",
-                    "bytes": {"k_local_newton": 1099027002, "k_local_factor": 433691017, "k_tangent_prep": 1198842258, "k_tangent_gemv": 280731710, "k_coarse_galerkin": 226718423, "k_coarse_lu": 1142085, "k_coarse_inverse": 12186577, "k_coarse_apply_inverse": 4085402, "k_mdot_partial": 18081278, "k_maxpy": 30408732, "k_prolong": 27167760, "k_coarse_ty": 23984418}}
+MEASURED_TRAFFIC = {"kernels_sha1": "f867f7da8fcc5a5c470fa436e711b46aaf92bc23",
+                    "bytes": {"k_local_newton": 977527668, "k_local_factor": 433298891, "k_tangent_prep": 1198831236, "k_tangent_gemv": 280745558, "k_coarse_galerkin": 254010864, "k_coarse_lu": 1399459, "k_coarse_inverse": 12185796, "k_coarse_apply_inverse": 4100905, "k_mdot_partial": 25627489, "k_maxpy": 30807488, "k_prolong": 27169254, "k_coarse_ty": 20666143}}
 
 
 def _factor_bytes(case, elem_bytes):
-    """Band factor storage n_i (2 kl_i + ku_i + 1) summed over subdomains."""
+    """Band factor storage per subdomain: L and U, n_i (2 kl_i + ku_i + 1),
+    and U alone, n_i (kl_i + ku_i + 1)."""
     from paper_2410_24138_amd import nls
     m = nls.inspect_partition(case)
     n = m["off_v"][1:] - m["off_v"][:-1]
     ng = m["off_g"][1:] - m["off_g"][:-1]
     fac = (n * (2 * m["kl"] + m["ku"] + 1)).astype(float) * elem_bytes
-    return fac, n.astype(float), ng.astype(float)
+    facu = (n * (m["kl"] + m["ku"] + 1)).astype(float) * elem_bytes
+    return fac, n.astype(float), ng.astype(float), facu
 
 
-def cpu_baseline(case, n_sample=32):
-    """The oracle's local nonlinear solves T_i(0) on a sample of subdomains."""
+def cpu_baseline(case, n_sample=256, passes=2):
+    """The oracle's local nonlinear solves T_i(0) (the first evaluation of a
+    solve) over a sample of subdomains, repeated `passes` times (about 10 s
+    of host work at the 512x512 workload)."""
     import numpy as np
     from oracle import P1Problem, Schwarz
     try:
@@ -80,14 +84,15 @@ def cpu_baseline(case, n_sample=32):
     u = np.zeros(S.P.N)
     t0 = time.perf_counter()
     its = 0
-    for i in idx:
-        its += S.local_solve(int(i), u)["its"]
+    for _ in range(passes):
+        for i in idx:
+            its += S.local_solve(int(i), u)["its"]
     dt = time.perf_counter() - t0
-    return {"value": n_sample / dt, "unit": "subdomain Newton solves/s", "cores": int(cores),
-            "kind": "oracle",
-            "sample": f"oracle local solves T_i(u=0) of {n_sample} of the 256 subdomains "
-                      f"(first outer iteration, {its} Newton steps, dense LAPACK LU), "
-                      f"{dt:.1f} s"}
+    return {"value": passes * len(idx) / dt, "unit": "subdomain Newton solves/s",
+            "cores": int(cores), "kind": "oracle",
+            "sample": f"oracle local solves T_i(u=0) of {len(idx)} of the {S.n_sub} subdomains "
+                      f"(the first evaluation of a solve), {passes} passes, {its} Newton steps, "
+                      f"dense LAPACK LU, {dt:.1f} s"}
 
 
 def run_form(case, golden, form, steps, warmup, device):
@@ -435,7 +440,7 @@ def _local_fp64(res, form):
 def roofline(case, res, form):
     """Dominant kernel and its HBM roofline fraction from algorithmic bytes."""
     elem = 8 if _local_fp64(res, form) else 4
-    fac, n, ng = _factor_bytes(case, elem)
+    fac, n, ng, facu = _factor_bytes(case, elem)
     kern = res["kernels"]
     k_t, k_l = kern["tangent_local"], kern["local_newton"]
     if k_t["ms"] >= k_l["ms"]:
@@ -446,15 +451,16 @@ def roofline(case, res, form):
         per_launch = float(fac.sum() + 8 * (ng.sum() + n.sum()))
     else:
         name, k = "local_newton", k_l
-        # per launch: k_i factorizations write the factors and k_i solves
-        # read them (the factorisation at x* for the tangent runs in its own
-        # kernel when GMRES needs it); J values written and read; u
-        # gathered, T, x* and the Gamma values written.  Averaged over
-        # subdomains with the measured totals.
+        # per launch: k_i factorizations write L and U (the forward
+        # substitution rides along) and k_i backward solves read U (the
+        # factorisation at x* for the tangent runs in its own kernel when
+        # GMRES needs it); J values written and read; u gathered, T, x* and
+        # the Gamma values written.  Averaged over subdomains with the
+        # measured totals.
         launches = max(k["launches"], 1)
         mean_its = res["inner_its_steps"] / (launches * len(n))
         jac = 8 * 2 * 7 * n + 8 * 2 * n  # ~7 nonzeros per row, written and read; residual
-        per_sub = mean_its * (fac + jac) + mean_its * fac + 8 * (n + 2 * ng + 2 * n)
+        per_sub = mean_its * (fac + jac + facu) + 8 * (n + 2 * ng + 2 * n)
         per_launch = float(per_sub.sum())
     avg_s = k["ms"] / max(k["launches"], 1) / 1e3
     achieved = per_launch / avg_s / 1e9
