@@ -1177,10 +1177,6 @@ struct MrhsSparseSrc {
     }
 };
 
-struct MrhsIdentitySrc {
-    int c;
-    __device__ __forceinline__ double take(int r) const { return r == c ? 1.0 : 0.0; }
-};
 
 template <int KL, int KW, class Src, class Put>
 __device__ __forceinline__ void band_solve_mrhs(int n, int kl, int ku,
@@ -1540,17 +1536,6 @@ k_coarse_apply_inverse(DevCoarse C, const double* __restrict__ x, double* __rest
     if (lane == 0) y[row] = acc;
 }
 
-// y = A x for a dense row-major n x n matrix: one wavefront per row.
-__global__ void __launch_bounds__(256)
-k_dense_gemv(int n, const double* __restrict__ A, const double* __restrict__ x, double* __restrict__ y) {
-    const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-    if (row >= n) return;
-    const double* a = A + (size_t)row * n;
-    double acc = 0.0;
-    for (int j = lane; j < n; j += 64) acc += a[j] * x[j];
-    acc = wave_sum(acc);
-    if (lane == 0) y[row] = acc;
-}
 
 // Local part of the exact tangent: z_i = J_ii^{-1} (B_i v_Gamma_i), with J,
 // B at the converged local state (eq. 6 with R_i DF(u_i) v = J R_i v + B v_G).
@@ -2384,10 +2369,6 @@ __global__ void k_axpy(double a, const double* __restrict__ x, double* __restric
     if (t < n) y[t] += a * x[t];
 }
 
-__global__ void k_add_inplace(const double* __restrict__ x, double* __restrict__ y, int n) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < n) y[t] += x[t];
-}
 
 __global__ void __launch_bounds__(NLS_BLOCK)
 k_max_abs_partial(const double* __restrict__ x, int n, double* __restrict__ partial) {
@@ -2681,10 +2662,6 @@ hipError_t launch_coarse_inverse(const DevCoarse& C, int max_block, int max_ldu,
     return hipGetLastError();
 }
 
-hipError_t launch_dense_gemv(int n, const double* A, const double* x, double* y, hipStream_t s) {
-    k_dense_gemv<<<(n + 3) / 4, 256, 0, s>>>(n, A, x, y);
-    return hipGetLastError();
-}
 
 hipError_t launch_coarse_apply_inverse(const DevCoarse& C, const double* x, double* y, hipStream_t s) {
     k_coarse_apply_inverse<<<(C.n0 + 3) / 4, 256, 0, s>>>(C, x, y);
@@ -2726,10 +2703,6 @@ hipError_t launch_axpy(double a, const double* x, double* y, int n, hipStream_t 
     return hipGetLastError();
 }
 
-hipError_t launch_add_inplace(const double* x, double* y, int n, hipStream_t s) {
-    k_add_inplace<<<nblocks(n), NLS_BLOCK, 0, s>>>(x, y, n);
-    return hipGetLastError();
-}
 
 hipError_t launch_max_abs(const double* x, int n, double* partial, double* out, int nb,
                           hipStream_t s) {

@@ -178,7 +178,6 @@ hipError_t launch_tangent_gemv(const DevMaps& P, const DevTangent& Tg, const dou
 int coarse_inverse_lds_bytes(int max_block, int max_ldu);
 hipError_t launch_coarse_inverse(const DevCoarse& C, int max_block, int max_ldu, hipStream_t s);
 hipError_t launch_coarse_apply_inverse(const DevCoarse& C, const double* x, double* y, hipStream_t s);
-hipError_t launch_dense_gemv(int n, const double* A, const double* x, double* y, hipStream_t s);
 
 // vector kernels for GMRES (deterministic reductions)
 hipError_t launch_mdot(const double* V, int64_t ld, int m, const double* w, int n,
@@ -188,7 +187,6 @@ hipError_t launch_maxpy(const double* V, int64_t ld, int m, const double* h,
 hipError_t launch_scale_by(const double* x, const double* denom_sq, double* y, int n,
                            hipStream_t s);
 hipError_t launch_axpy(double a, const double* x, double* y, int n, hipStream_t s);
-hipError_t launch_add_inplace(const double* x, double* y, int n, hipStream_t s);
 hipError_t launch_max_abs(const double* x, int n, double* partial, double* out,
                           int nblocks, hipStream_t s);
 hipError_t launch_any_status(const int* status, int n, int* out, hipStream_t s);
