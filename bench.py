@@ -52,8 +52,8 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per dispatch measured with rocprofv3 FETCH_SIZE/WRITE_SIZE (two
 # passes, calibrated against a 256 MiB copy; profiles/hbm_traffic_*.md), valid
 # only for the kernel source they were taken with.
-MEASURED_TRAFFIC = {"kernels_sha1": "f867f7da8fcc5a5c470fa436e711b46aaf92bc23",
-                    "bytes": {"k_local_newton": 977527668, "k_local_factor": 433298891, "k_tangent_prep": 1198831236, "k_tangent_gemv": 280745558, "k_coarse_galerkin": 254010864, "k_coarse_lu": 1399459, "k_coarse_inverse": 12185796, "k_coarse_apply_inverse": 4100905, "k_mdot_partial": 25627489, "k_maxpy": 30807488, "k_prolong": 27169254, "k_coarse_ty": 20666143}}
+MEASURED_TRAFFIC = {"kernels_sha1": "20064d52ab213b7da3599f24ceaf8bc3ae131051",
+                    "bytes": {"k_local_newton": 976721743, "k_local_factor": 432747723, "k_tangent_prep": 1198947521, "k_tangent_gemv": 280737755, "k_coarse_galerkin": 262026108, "k_coarse_lu": 1399483, "k_coarse_inverse": 12183556, "k_coarse_apply_inverse": 4100788, "k_mdot_partial": 25611321, "k_maxpy": 30806726, "k_prolong": 27167396, "k_coarse_ty": 20665155}}
 
 
 def _factor_bytes(case, elem_bytes):
