@@ -691,6 +691,16 @@ static bool two_level(nls_handle* h) {
     return h->opt.coupling != NLS_ONE_LEVEL && h->have_coarse && h->co.n0 > 0;
 }
 
+// The second stream of NLS_FLAG_OVERLAP and its two events, created on first
+// use.
+static int ensure_cstream(nls_handle* h) {
+    if (h->cstream) return NLS_OK;
+    HIPCHK(hipStreamCreateWithFlags(&h->cstream, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&h->cev[0], hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&h->cev[1], hipEventDisableTiming));
+    return NLS_OK;
+}
+
 // Coarse Newton iteration for T_0(u) (eq. 9): c <- c + A0^{-1} Phi^T F(u - Phi c)
 // from c = 0; keeps LU(A0) at the converged c and u_0 = u - Phi c in dc.w.
 // T_0(u) (eq. 9): Newton on G(c) = Phi^T F(u - Phi c) = 0 from c = 0.  With
@@ -782,11 +792,7 @@ static int evaluate(nls_handle* h, const double* u, double* Fx) {
     // run; its small kernels fit beside the local workgroups on each CU.
     const bool overlap = two_level(h) && !hybrid && (h->opt.flags & NLS_FLAG_OVERLAP);
     if (overlap) {
-        if (!h->cstream) {
-            HIPCHK(hipStreamCreateWithFlags(&h->cstream, hipStreamNonBlocking));
-            HIPCHK(hipEventCreateWithFlags(&h->cev[0], hipEventDisableTiming));
-            HIPCHK(hipEventCreateWithFlags(&h->cev[1], hipEventDisableTiming));
-        }
+        RC(ensure_cstream(h));
         HIPCHK(hipEventRecord(h->cev[0], h->stream));  // u is final on the main stream
         HIPCHK(hipStreamWaitEvent(h->cstream, h->cev[0], 0));
     }
@@ -854,13 +860,39 @@ static int evaluate(nls_handle* h, const double* u, double* Fx) {
     return NLS_OK;
 }
 
+// A0 at the converged c* (Galerkin product with the rows Y_i for the
+// tangent), its LU and, where chosen, its inverse, enqueued on stream s.
+static int coarse_tangent_enqueue(nls_handle* h, hipStream_t s) {
+    DevCoarse& d = h->dc;
+    HIPCHK(launch_coarse_galerkin(h->dm, d, d.w, 1, s));
+    HIPCHK(launch_coarse_assemble(d, 1, s));
+    HIPCHK(launch_coarse_lu(d, 1, h->lds_coarse_lu, h->npl_coarse, s));
+    if (h->coarse_inv) HIPCHK(launch_coarse_inverse(d, h->max_block, h->coarse_ldu, s));
+    return NLS_OK;
+}
+
 // The factorisations the tangent (eqs. 7, 12) needs at the last evaluated
 // point: J_ii^{-1} B_i per subdomain, and A0 with its LU (and inverse) at the
 // converged c*.  Formed on first use, so the evaluation that ends the outer
-// iteration pays for none of them.
+// iteration pays for none of them.  With NLS_FLAG_OVERLAP the coarse part
+// (which depends on c* only) runs on the second stream beside the local
+// factorisations.
 static int prepare_tangent(nls_handle* h) {
     if (h->tangent_ready) return NLS_OK;
     if (!h->have_state) return fail(h, NLS_ESTATE, "no evaluated point (nls_eval_precond_residual)");
+    const bool two = two_level(h);
+    const bool ovl = two && (h->opt.flags & NLS_FLAG_OVERLAP);
+    if (ovl) {
+        RC(ensure_cstream(h));
+        HIPCHK(hipEventRecord(h->cev[0], h->stream));  // the evaluated state is final
+        HIPCHK(hipStreamWaitEvent(h->cstream, h->cev[0], 0));
+        RC(coarse_tangent_enqueue(h, h->cstream));
+    }
+    // on an error of the local part, let the coarse stream drain first
+    auto bail = [&](int rc) {
+        if (ovl) (void)hipStreamSynchronize(h->cstream);
+        return rc;
+    };
     if (!h->local_factored) {
         // J_ii and its FP64 LU at the converged local states (eq. 6)
         Timer tf;
@@ -869,37 +901,45 @@ static int prepare_tangent(nls_handle* h) {
             DevMaps pb = h->dp;
             pb.order = h->dp.order + h->bk_start[b];
             np.lu_variant = h->bk_var[b];
-            HIPCHK(launch_local_factor(h->dm, pb, h->dl, np, h->dl.xstar, h->bk_end[b] - h->bk_start[b],
-                                       h->bk_lds[b], h->stream, h->dl.xstar, h->dl.ghost));
+            const hipError_t e = launch_local_factor(h->dm, pb, h->dl, np, h->dl.xstar,
+                                                     h->bk_end[b] - h->bk_start[b], h->bk_lds[b],
+                                                     h->stream, h->dl.xstar, h->dl.ghost);
+            if (e != hipSuccess) return bail(fail(h, NLS_EHIP, hipGetErrorString(e)));
         }
-        HIPCHK(launch_any_status(h->dl.status, h->maps.nsub, h->stat2, h->stream));
         int st2[2];
-        HIPCHK(hipMemcpyAsync(st2, h->stat2, 2 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
-        RC(sync(h));
+        hipError_t e = launch_any_status(h->dl.status, h->maps.nsub, h->stat2, h->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(st2, h->stat2, 2 * sizeof(int), hipMemcpyDeviceToHost, h->stream);
+        if (e != hipSuccess) return bail(fail(h, NLS_EHIP, hipGetErrorString(e)));
+        const int rc = sync(h);
+        if (rc) return bail(rc);
         if (st2[0] >= 0)
-            return fail(h, NLS_ESINGULAR, "zero pivot in subdomain " + std::to_string(st2[0]) +
-                                              " at its converged state");
+            return bail(fail(h, NLS_ESINGULAR, "zero pivot in subdomain " + std::to_string(st2[0]) +
+                                                   " at its converged state"));
         h->local_factored = true;
         if (h->st) h->st->ms_inner += tf.ms();
     }
     if (h->tangent_w) {
         Timer tp;
-        HIPCHK(launch_tangent_prep(h->dp, h->dl, h->dt, h->tangent_bucket, h->max_ng, h->stream));
-        RC(sync(h));
+        const hipError_t e = launch_tangent_prep(h->dp, h->dl, h->dt, h->tangent_bucket, h->max_ng,
+                                                 h->stream);
+        if (e != hipSuccess) return bail(fail(h, NLS_EHIP, hipGetErrorString(e)));
+        const int rc = sync(h);
+        if (rc) return bail(rc);
         if (h->st) h->st->ms_inner += tp.ms();
     }
-    if (two_level(h)) {
+    if (two) {
+        // with the overlap, only the part of the coarse work that outlasts
+        // the local part is counted here
         Timer tc;
+        hipStream_t cs = ovl ? h->cstream : h->stream;
+        if (!ovl) RC(coarse_tangent_enqueue(h, cs));
         DevCoarse& d = h->dc;
-        HIPCHK(launch_coarse_galerkin(h->dm, d, d.w, 1, h->stream));
-        HIPCHK(launch_coarse_assemble(d, 1, h->stream));
-        HIPCHK(launch_coarse_lu(d, 1, h->lds_coarse_lu, h->npl_coarse, h->stream));
-        h->coarse_lu_valid = true;
-        if (h->coarse_inv) HIPCHK(launch_coarse_inverse(d, h->max_block, h->coarse_ldu, h->stream));
-        h->coarse_inv_valid = h->coarse_inv;
         int flag = 0;
-        HIPCHK(hipMemcpyAsync(&flag, d.flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
-        RC(sync(h));
+        HIPCHK(hipMemcpyAsync(&flag, d.flag, sizeof(int), hipMemcpyDeviceToHost, cs));
+        HIPCHK(hipStreamSynchronize(cs));
+        h->coarse_lu_valid = true;
+        h->coarse_inv_valid = h->coarse_inv;
         if (flag) return fail(h, NLS_ESINGULAR, "zero pivot in the coarse matrix");
         if (h->st) h->st->ms_coarse += tc.ms();
     }
