@@ -696,8 +696,7 @@ static bool two_level(nls_handle* h) {
 static int ensure_cstream(nls_handle* h) {
     if (h->cstream) return NLS_OK;
     HIPCHK(hipStreamCreateWithFlags(&h->cstream, hipStreamNonBlocking));
-    HIPCHK(hipEventCreateWithFlags(&h->cev[0], hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&h->cev[1], hipEventDisableTiming));
+    for (hipEvent_t& e : h->cev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     return NLS_OK;
 }
 
@@ -1108,6 +1107,21 @@ static int tangent(nls_handle* h, const double* v, double* y, hipStream_t s = nu
         HIPCHK(launch_sub_coarse(h->dm, h->dc, h->ctmp, v, h->zbuf, s));
         vloc = h->zbuf;
     }
+    // Additive coupling with NLS_FLAG_OVERLAP: the coarse term runs on the
+    // second stream beside the local term (a fork and a join, also when the
+    // product is captured into a graph) and both meet in the prolongation.
+    const bool fork = two_level(h) && !hybrid && (h->opt.flags & NLS_FLAG_OVERLAP);
+    if (fork) {
+        RC(ensure_cstream(h));
+        HIPCHK(hipEventRecord(h->cev[2], s));
+        HIPCHK(hipStreamWaitEvent(h->cstream, h->cev[2], 0));
+        const hipStream_t s0 = s;
+        s = h->cstream;
+        const int rc = coarse_term();
+        s = s0;
+        RC(rc);
+        HIPCHK(hipEventRecord(h->cev[3], h->cstream));
+    }
     if (h->tangent_w)
         HIPCHK(launch_tangent_gemv(h->dp, h->dt, vloc, h->dl.z, h->max_ng, s));
     else
@@ -1117,7 +1131,10 @@ static int tangent(nls_handle* h, const double* v, double* y, hipStream_t s = nu
         h->ev_used.push_back({1, {e0, e1}});
     }
     if (two_level(h) && !hybrid) {
-        RC(coarse_term());
+        if (fork)
+            HIPCHK(hipStreamWaitEvent(s, h->cev[3], 0));
+        else
+            RC(coarse_term());
         HIPCHK(launch_prolong(h->dm, h->dp, h->dl.z, &h->dc, h->ctmp, y, v, s));
     } else {
         HIPCHK(launch_prolong(h->dm, h->dp, h->dl.z, nullptr, nullptr, y, v, s));

@@ -88,9 +88,12 @@ struct nls_handle {
     // GMRES cycles with device-side rotations; blocks of gblock Arnoldi
     // steps captured once as HIP graphs and replayed on gstream
     hipStream_t gstream = nullptr;
-    // second stream of NLS_FLAG_OVERLAP (coarse Newton beside the local solves)
+    // second stream of NLS_FLAG_OVERLAP (coarse Newton beside the local
+    // solves, coarse term of the tangent beside its local term); cev[0..1]
+    // order the evaluation and tangent preparation, cev[2..3] the fork and
+    // join inside a tangent product
     hipStream_t cstream = nullptr;
-    hipEvent_t cev[2] = {nullptr, nullptr};
+    hipEvent_t cev[4] = {nullptr, nullptr, nullptr, nullptr};
     hipEvent_t gev[2] = {nullptr, nullptr};
     std::vector<hipGraphExec_t> gexec;
     double *Hd = nullptr, *csd = nullptr, *snd = nullptr, *gd = nullptr, *gtol = nullptr;
