@@ -1184,7 +1184,8 @@ __device__ __forceinline__ void band_solve_mrhs(int n, int kl, int ku,
                                                 const double* __restrict__ Lf,
                                                 const int* __restrict__ piv, Src& src,
                                                 bool valid, int col, double* __restrict__ fwd,
-                                                int ldf, double* stage, int* sint, Put put) {
+                                                int ldf, const int* __restrict__ tag,
+                                                double* stage, int* sint, Put put) {
     constexpr int CH = MR_CH, NT = MR_THREADS;
     constexpr int FROW = KL, BROW = KW + 1;
     constexpr int PF = (CH * BROW + NT - 1) / NT;  // staged doubles per thread
@@ -1261,6 +1262,8 @@ __device__ __forceinline__ void band_solve_mrhs(int n, int kl, int ku,
     __syncthreads();  // forward results visible in HBM to this workgroup
     // --------------------------------------------------------- backward sweep
     // chunk ch covers steps k = n-1-ch*CH-st, st = 0..CH-1
+    // the row tags tag[k] of a chunk are staged with its U columns, so that
+    // a step does not wait for a load of its own
     auto bload = [&](int ch) {
 #pragma unroll
         for (int q = 0; q < PF; ++q) {
@@ -1276,6 +1279,11 @@ __device__ __forceinline__ void band_solve_mrhs(int n, int kl, int ku,
             }
             pre[q] = v;
         }
+        prei = -1;
+        if (tid < CH) {
+            const int k = n - 1 - ch * CH - tid;
+            if (k >= 0) prei = tag[k];
+        }
     };
     auto bstore = [&](int slot) {
 #pragma unroll
@@ -1283,6 +1291,7 @@ __device__ __forceinline__ void band_solve_mrhs(int n, int kl, int ku,
             const int idx = tid + q * NT;
             if (idx < CH * BROW) stage[slot * CH * BROW + idx] = pre[q];
         }
+        if (tid < CH) sint[slot * CH + tid] = prei;
     };
     double p[KW + 1];
 #pragma unroll
@@ -1313,7 +1322,7 @@ __device__ __forceinline__ void band_solve_mrhs(int n, int kl, int ku,
             if (k >= 0) {
                 const double* Uk = U0 + st * BROW;
                 const double y = p[0] * Uk[0];
-                put(k, y);
+                put(k, sint[slot * CH + st], y);
 #pragma unroll
                 for (int j = 0; j < KW; ++j) p[j] = p[j + 1] - Uk[1 + j] * y;
                 p[KW] = ent[st];
@@ -1349,12 +1358,12 @@ k_tangent_prep(DevMaps P, DevLocal L, DevTangent Tg) {
     double* W = Tg.W + Tg.off_W[i];
     const int* rowown = Tg.rowown + rowbase;
     const int nown = Tg.off_own[i + 1] - Tg.off_own[i];
-    auto put = [&](int k, double y) {
-        const int o = __builtin_amdgcn_readfirstlane(rowown[k]);
+    auto put = [&](int k, int o, double y) {
+        (void)k;
         if (valid && o >= 0) W[(size_t)col * nown + o] = y;
     };
     band_solve_mrhs<KL, KW>(n, kl, ku, L.Uf + P.off_u[i], L.Lf + P.off_l[i], L.piv + rowbase, src,
-                            valid, col, Tg.fwd + Tg.off_F[i], ng, smem, sint, put);
+                            valid, col, Tg.fwd + Tg.off_F[i], ng, rowown, smem, sint, put);
 }
 
 // z[owned rows of i] = W_i v_Gamma_i: streams W (column-major, one owned
