@@ -2073,13 +2073,17 @@ k_coarse_q(DevMesh M, DevCoarse C, const double* __restrict__ w, const double* _
 }
 
 // Per subdomain Galerkin block A_i = Phi_i^T K_i(w) Phi_i (K_i: part-i
-// elements).  With with_y, also Y_i = K_i(w)^T Phi_i, so that the coarse
-// term of the tangent, Phi^T DF(u_0) v = sum_i Y_i^T v_i, is a GEMV.
+// elements), first part: the rows Z_i = K_i(w) Phi_i.  With with_y, also
+// Y_i = K_i(w)^T Phi_i, so that the coarse term of the tangent,
+// Phi^T DF(u_0) v = sum_i Y_i^T v_i, is a GEMV.  Grid (nsub, Q): block y
+// takes the closure rows [y nc / Q, (y + 1) nc / Q).
 template <bool ELAST>
 __global__ void __launch_bounds__(NLS_BLOCK)
 k_coarse_galerkin(DevMesh M, DevCoarse C, const double* __restrict__ w, int with_y) {
     const int i = blockIdx.x;
     const int cb = C.off_c[i], nc = C.off_c[i + 1] - cb;
+    const int a0 = (int)((int64_t)nc * blockIdx.y / gridDim.y);
+    const int a1 = (int)((int64_t)nc * (blockIdx.y + 1) / gridDim.y);
     const int k0 = C.off_k[i], nk = C.off_k[i + 1] - k0;
     const int eb = C.off_ne[i];
     const double* ph = C.phi + C.off_phi[i];
@@ -2089,7 +2093,7 @@ k_coarse_galerkin(DevMesh M, DevCoarse C, const double* __restrict__ w, int with
         // with rows on every closure dof (Dirichlet ones included: Phi is
         // zero there, so they do not change A_i, but Y needs them)
         double* y = C.ybuf + C.off_phi[i];
-        for (int a = threadIdx.x; a < nc; a += blockDim.x) {
+        for (int a = a0 + threadIdx.x; a < a1; a += blockDim.x) {
             double* zr = z + (int64_t)a * nk;
             for (int l = 0; l < nk; ++l) zr[l] = 0.0;
             {
@@ -2111,18 +2115,9 @@ k_coarse_galerkin(DevMesh M, DevCoarse C, const double* __restrict__ w, int with
             if (with_y)
                 for (int l = 0; l < nk; ++l) y[(int64_t)l * nc + a] = zr[l];
         }
-        __syncthreads();
-        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-        for (int kk = wv; kk < nk * nk; kk += nw) {
-            const int k = kk / nk, l = kk - k * nk;
-            double acc = 0.0;
-            for (int a = lane; a < nc; a += 64) acc += ph[(int64_t)a * nk + k] * z[(int64_t)a * nk + l];
-            acc = wave_sum(acc);
-            if (lane == 0) C.ablk[C.off_kk[i] + kk] = acc;
-        }
         return;
     }
-    for (int a = threadIdx.x; a < nc; a += blockDim.x) {
+    for (int a = a0 + threadIdx.x; a < a1; a += blockDim.x) {
         double* zr = z + (int64_t)a * nk;
         for (int l = 0; l < nk; ++l) zr[l] = 0.0;
         if (C.ctype[cb + a] == 2) continue;
@@ -2153,7 +2148,7 @@ k_coarse_galerkin(DevMesh M, DevCoarse C, const double* __restrict__ w, int with
     }
     if (with_y) {
         double* y = C.ybuf + C.off_phi[i];
-        for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+        for (int c = a0 + threadIdx.x; c < a1; c += blockDim.x) {
             for (int l = 0; l < nk; ++l) y[(int64_t)l * nc + c] = 0.0;
             for (int t = C.cinc_ptr[cb + c]; t < C.cinc_ptr[cb + c + 1]; ++t) {
                 const int code = C.cinc[t];
@@ -2181,9 +2176,19 @@ k_coarse_galerkin(DevMesh M, DevCoarse C, const double* __restrict__ w, int with
             }
         }
     }
-    __syncthreads();
+}
+
+// Second part: A_i[k][l] = sum_a Phi_i[a][k] Z_i[a][l], one wavefront per
+// entry; grid (nsub, Q), block y takes every Q-th group of entries.
+__global__ void __launch_bounds__(NLS_BLOCK)
+k_coarse_galerkin_sum(DevCoarse C) {
+    const int i = blockIdx.x;
+    const int nc = C.off_c[i + 1] - C.off_c[i];
+    const int nk = C.off_k[i + 1] - C.off_k[i];
+    const double* ph = C.phi + C.off_phi[i];
+    const double* z = C.zbuf + C.off_phi[i];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (int kk = wv; kk < nk * nk; kk += nw) {
+    for (int kk = wv + nw * blockIdx.y; kk < nk * nk; kk += nw * gridDim.y) {
         const int k = kk / nk, l = kk - k * nk;
         double acc = 0.0;
         for (int a = lane; a < nc; a += 64) acc += ph[(int64_t)a * nk + k] * z[(int64_t)a * nk + l];
@@ -2584,10 +2589,15 @@ hipError_t launch_coarse_q(const DevMesh& M, const DevCoarse& C, const double* w
 
 hipError_t launch_coarse_galerkin(const DevMesh& M, const DevCoarse& C, const double* w,
                                   int with_y, hipStream_t s) {
+    // up to four workgroups per subdomain when there are fewer subdomains
+    // than CUs
+    const int q = C.nsub >= 256 ? 1 : (C.nsub >= 128 ? 2 : 4);
+    const dim3 grid(C.nsub, q);
     if (M.kind == NLS_PROBLEM_NEOHOOKE)
-        k_coarse_galerkin<true><<<C.nsub, NLS_BLOCK, 0, s>>>(M, C, w, with_y);
+        k_coarse_galerkin<true><<<grid, NLS_BLOCK, 0, s>>>(M, C, w, with_y);
     else
-        k_coarse_galerkin<false><<<C.nsub, NLS_BLOCK, 0, s>>>(M, C, w, with_y);
+        k_coarse_galerkin<false><<<grid, NLS_BLOCK, 0, s>>>(M, C, w, with_y);
+    k_coarse_galerkin_sum<<<grid, NLS_BLOCK, 0, s>>>(C);
     return hipGetLastError();
 }
 
