@@ -691,6 +691,40 @@ static bool two_level(nls_handle* h) {
     return h->opt.coupling != NLS_ONE_LEVEL && h->have_coarse && h->co.n0 > 0;
 }
 
+// The size buckets of a local kernel run concurrently: bucket 0 on s, bucket
+// b > 0 on a stream of its own that waits for s first, and s waits for them
+// all at the join (the buckets touch disjoint subdomains).
+static int bucket_fork(nls_handle* h, hipStream_t s) {
+    const size_t nb = h->bk_start.size();
+    if (nb <= 1) return NLS_OK;
+    while (h->bstream.size() + 1 < nb) {
+        hipStream_t q = nullptr;
+        HIPCHK(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+        h->bstream.push_back(q);
+    }
+    while (h->bev.size() < nb) {
+        hipEvent_t e = nullptr;
+        HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        h->bev.push_back(e);
+    }
+    HIPCHK(hipEventRecord(h->bev[0], s));
+    for (size_t b = 1; b < nb; ++b) HIPCHK(hipStreamWaitEvent(h->bstream[b - 1], h->bev[0], 0));
+    return NLS_OK;
+}
+
+static hipStream_t bucket_stream(const nls_handle* h, size_t b, hipStream_t s) {
+    return b == 0 ? s : h->bstream[b - 1];
+}
+
+static int bucket_join(nls_handle* h, hipStream_t s) {
+    const size_t nb = h->bk_start.size();
+    for (size_t b = 1; b < nb; ++b) {
+        HIPCHK(hipEventRecord(h->bev[b], h->bstream[b - 1]));
+        HIPCHK(hipStreamWaitEvent(s, h->bev[b], 0));
+    }
+    return NLS_OK;
+}
+
 // The second stream of NLS_FLAG_OVERLAP and its two events, created on first
 // use.
 static int ensure_cstream(nls_handle* h) {
@@ -807,13 +841,15 @@ static int evaluate(nls_handle* h, const double* u, double* Fx) {
         e1 = h->take_event();
         HIPCHK(hipEventRecord(e0, h->stream));
     }
+    RC(bucket_fork(h, h->stream));
     for (size_t b = 0; b < h->bk_start.size(); ++b) {
         DevMaps pb = h->dp;
         pb.order = h->dp.order + h->bk_start[b];
         np.lu_variant = h->bk_var[b];
         HIPCHK(launch_local_newton(h->dm, pb, h->dl, np, u, h->bk_end[b] - h->bk_start[b],
-                                   h->bk_lds[b], h->bk_npl[b], h->stream));
+                                   h->bk_lds[b], h->bk_npl[b], bucket_stream(h, b, h->stream)));
     }
+    RC(bucket_join(h, h->stream));
     if (e0) {
         HIPCHK(hipEventRecord(e1, h->stream));
         h->ev_used.push_back({0, {e0, e1}});
@@ -896,15 +932,20 @@ static int prepare_tangent(nls_handle* h) {
         // J_ii and its FP64 LU at the converged local states (eq. 6)
         Timer tf;
         NewtonParams np = h->np;
+        const int rcf = bucket_fork(h, h->stream);
+        if (rcf) return bail(rcf);
         for (size_t b = 0; b < h->bk_start.size(); ++b) {
             DevMaps pb = h->dp;
             pb.order = h->dp.order + h->bk_start[b];
             np.lu_variant = h->bk_var[b];
             const hipError_t e = launch_local_factor(h->dm, pb, h->dl, np, h->dl.xstar,
                                                      h->bk_end[b] - h->bk_start[b], h->bk_lds[b],
-                                                     h->stream, h->dl.xstar, h->dl.ghost);
+                                                     bucket_stream(h, b, h->stream), h->dl.xstar,
+                                                     h->dl.ghost);
             if (e != hipSuccess) return bail(fail(h, NLS_EHIP, hipGetErrorString(e)));
         }
+        const int rcj = bucket_join(h, h->stream);
+        if (rcj) return bail(rcj);
         int st2[2];
         hipError_t e = launch_any_status(h->dl.status, h->maps.nsub, h->stat2, h->stream);
         if (e == hipSuccess)
@@ -1523,13 +1564,15 @@ static int nks_factor(nls_handle* h, const double* u) {
     Timer t;
     NewtonParams np = h->np;
     np.mixed = 0;
+    RC(bucket_fork(h, h->stream));
     for (size_t b = 0; b < h->bk_start.size(); ++b) {
         DevMaps pb = h->dp;
         pb.order = h->dp.order + h->bk_start[b];
         np.lu_variant = h->bk_var[b];
         HIPCHK(launch_local_factor(h->dm, pb, h->dl, np, u, h->bk_end[b] - h->bk_start[b],
-                                   h->bk_lds[b], h->stream));
+                                   h->bk_lds[b], bucket_stream(h, b, h->stream)));
     }
+    RC(bucket_join(h, h->stream));
     HIPCHK(launch_any_status(h->dl.status, h->maps.nsub, h->stat2, h->stream));
     int st2[2];
     HIPCHK(hipMemcpyAsync(st2, h->stat2, 2 * sizeof(int), hipMemcpyDeviceToHost, h->stream));

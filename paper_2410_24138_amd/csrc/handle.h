@@ -93,6 +93,10 @@ struct nls_handle {
     // order the evaluation and tangent preparation, cev[2..3] the fork and
     // join inside a tangent product
     hipStream_t cstream = nullptr;
+    // size buckets of the local kernels after the first run on streams of
+    // their own, forked from and joined back into the launching stream
+    std::vector<hipStream_t> bstream;
+    std::vector<hipEvent_t> bev;
     hipEvent_t cev[4] = {nullptr, nullptr, nullptr, nullptr};
     hipEvent_t gev[2] = {nullptr, nullptr};
     std::vector<hipGraphExec_t> gexec;
@@ -142,6 +146,8 @@ struct nls_handle {
             if (e) (void)hipEventDestroy(e);
         if (gstream) (void)hipStreamDestroy(gstream);
         if (cstream) (void)hipStreamDestroy(cstream);
+        for (hipStream_t q : bstream) (void)hipStreamDestroy(q);
+        for (hipEvent_t e : bev) (void)hipEventDestroy(e);
         for (hipEvent_t& e : cev)
             if (e) (void)hipEventDestroy(e);
         for (auto& g : bufs)
