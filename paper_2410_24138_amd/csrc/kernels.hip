@@ -1380,16 +1380,15 @@ k_tangent_gemv(DevMaps P, DevTangent Tg, const double* __restrict__ v, double* _
     const double* W = Tg.W + Tg.off_W[i];
     const int rowbase = P.off_n[i];
     for (int r = blockIdx.y * blockDim.x + threadIdx.x; r < no; r += gridDim.y * blockDim.x) {
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        // eight independent loads in flight per thread
+        double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         int j = 0;
-        for (; j + 3 < ng; j += 4) {
-            a0 += W[(size_t)j * no + r] * vg[j];
-            a1 += W[(size_t)(j + 1) * no + r] * vg[j + 1];
-            a2 += W[(size_t)(j + 2) * no + r] * vg[j + 2];
-            a3 += W[(size_t)(j + 3) * no + r] * vg[j + 3];
+        for (; j + 7 < ng; j += 8) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) a[q] += W[(size_t)(j + q) * no + r] * vg[j + q];
         }
-        for (; j < ng; ++j) a0 += W[(size_t)j * no + r] * vg[j];
-        z[rowbase + Tg.ownrow[ob + r]] = (a0 + a1) + (a2 + a3);
+        for (; j < ng; ++j) a[0] += W[(size_t)j * no + r] * vg[j];
+        z[rowbase + Tg.ownrow[ob + r]] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
     }
 }
 
@@ -2664,9 +2663,10 @@ hipError_t launch_tangent_prep(const DevMaps& P, const DevLocal& L, const DevTan
 
 hipError_t launch_tangent_gemv(const DevMaps& P, const DevTangent& Tg, const double* v, double* z,
                                int max_ng, hipStream_t s) {
-    // four workgroups per subdomain: one owned row per thread at up to 1024
-    // owned rows, so that enough loads of W are in flight per CU
-    dim3 grid(P.nsub, 4);
+    // four workgroups per subdomain (eight with fewer subdomains than CUs,
+    // whose patches are larger): one owned row per thread, so that enough
+    // loads of W are in flight per CU
+    dim3 grid(P.nsub, P.nsub < 256 ? 8 : 4);
     k_tangent_gemv<<<grid, 256, max_ng * 8, s>>>(P, Tg, v, z);
     return hipGetLastError();
 }
