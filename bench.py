@@ -52,8 +52,8 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per dispatch measured with rocprofv3 FETCH_SIZE/WRITE_SIZE (two
 # passes, calibrated against a 256 MiB copy; profiles/hbm_traffic_*.md), valid
 # only for the kernel source they were taken with.
-MEASURED_TRAFFIC = {"kernels_sha1": "20064d52ab213b7da3599f24ceaf8bc3ae131051",
-                    "bytes": {"k_local_newton": 976721743, "k_local_factor": 432747723, "k_tangent_prep": 1198947521, "k_tangent_gemv": 280737755, "k_coarse_galerkin": 262026108, "k_coarse_lu": 1399483, "k_coarse_inverse": 12183556, "k_coarse_apply_inverse": 4100788, "k_mdot_partial": 25611321, "k_maxpy": 30806726, "k_prolong": 27167396, "k_coarse_ty": 20665155}}
+MEASURED_TRAFFIC = {"kernels_sha1": "5b01f2611b963e1809be00b2b4f422041e310d16",
+                    "bytes": {"k_local_newton": 977302916, "k_local_factor": 433403278, "k_tangent_prep": 1198546838, "k_tangent_gemv": 280763330, "k_coarse_galerkin": 204467629, "k_coarse_lu": 1398534, "k_coarse_inverse": 12176374, "k_coarse_apply_inverse": 4100779, "k_mdot_partial": 25626695, "k_maxpy": 30790218, "k_prolong": 27168692, "k_coarse_ty": 20665362}}
 
 
 def _factor_bytes(case, elem_bytes):
