@@ -123,10 +123,14 @@ typedef struct nls_options {
    refinement, and binary64 LU) and the faster total is kept for all of
    them.  nls_get_tuning reports the decisions. */
 #define NLS_FLAG_AUTOTUNE 16
-/* options.flags: with the additive coupling, run the coarse Newton solve
-   T_0(u) (eq. 9) on a second stream of the handle, concurrently with the
-   local solves T_i(u) (eq. 4); both depend on u only.  Results are those
-   of the serial order; the reported inner and coarse phase times overlap. */
+/* options.flags: on a second stream of the handle, concurrently with the
+   local work: with the additive coupling, the coarse Newton solve T_0(u)
+   (eq. 9) beside the local solves T_i(u) (eq. 4), both depending on u
+   only; with any two-level coupling, the tangent's coarse Galerkin matrix,
+   LU and inverse at c* beside the local factorisations; with the additive
+   coupling, the coarse term of each tangent product (eqs. 7, 12) beside its
+   local term.  Results are those of the serial order; the reported inner
+   and coarse phase times overlap. */
 #define NLS_FLAG_OVERLAP  32
 
 /* ---- statistics of the last solve ------------------------------------ */
