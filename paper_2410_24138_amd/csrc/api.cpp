@@ -1211,8 +1211,7 @@ static int arnoldi_step(nls_handle* h, int j, hipStream_t s) {
     HIPCHK(launch_maxpy(h->V, ld, j + 1, h->hbuf, h->wv, N, 1.0, s));
     HIPCHK(launch_mdot(h->V, ld, j + 1, h->wv, N, h->partial, h->hbuf2, h->nb_dot, s));
     HIPCHK(launch_maxpy_norm(h->V, ld, j + 1, h->hbuf2, h->wv, N, h->partial, h->hn2, h->nb_dot, s));
-    HIPCHK(launch_scale_by(h->wv, h->hn2, vn, N, s));
-    HIPCHK(launch_gmres_givens(gmres_dev(h), j, s));
+    HIPCHK(launch_scale_givens(h->wv, vn, N, gmres_dev(h), j, s));
     return NLS_OK;
 }
 

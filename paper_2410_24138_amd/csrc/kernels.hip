@@ -2413,8 +2413,7 @@ __global__ void k_any_status(const int* __restrict__ st, int n, int* __restrict_
 // classical Gram-Schmidt passes), H(j+1,j) = ||w||; the previous rotations
 // are applied, rotation j is formed and the residual vector g updated.
 // Columns after the cycle has converged (st[0] != 0) are ignored.
-__global__ void k_gmres_givens(GmresDev G, int j) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ void gmres_givens_step(const GmresDev& G, int j) {
     if (G.st[0] != 0) return;
     const int m = G.m;
     double* H = G.H;
@@ -2439,6 +2438,22 @@ __global__ void k_gmres_givens(GmresDev G, int j) {
     const double r = fabs(G.g[j + 1]);
     if (!(r == r) || isinf(r)) G.st[0] = -(j + 1);
     else if (r <= G.tol[0]) G.st[0] = j + 1;
+}
+
+__global__ void k_gmres_givens(GmresDev G, int j) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    gmres_givens_step(G, j);
+}
+
+// v_{j+1} = w / ||w|| and, by the first thread, rotation j of the Arnoldi
+// column (both read the same ||w||^2 and write disjoint memory).
+__global__ void k_scale_givens(const double* __restrict__ x, double* __restrict__ y, int n,
+                               GmresDev G, int j) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t == 0) gmres_givens_step(G, j);
+    if (t >= n) return;
+    const double d = sqrt(G.hn2[0]);
+    y[t] = (d > 0.0) ? x[t] / d : 0.0;
 }
 
 inline int nblocks(int n, int b = NLS_BLOCK) { return (n + b - 1) / b; }
@@ -2732,6 +2747,12 @@ hipError_t launch_max_abs(const double* x, int n, double* partial, double* out, 
 
 hipError_t launch_any_status(const int* status, int n, int* out, hipStream_t s) {
     k_any_status<<<1, 64, 0, s>>>(status, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_givens(const double* x, double* y, int n, const GmresDev& G, int j,
+                               hipStream_t s) {
+    k_scale_givens<<<nblocks(n), NLS_BLOCK, 0, s>>>(x, y, n, G, j);
     return hipGetLastError();
 }
 

@@ -203,3 +203,6 @@ struct GmresDev {
 };
 hipError_t prepare_coarse_lu(int lds_bytes, int npl);
 hipError_t launch_gmres_givens(const GmresDev& G, int j, hipStream_t s);
+// y = x / sqrt(G.hn2[0]) and rotation j (k_gmres_givens) in one launch
+hipError_t launch_scale_givens(const double* x, double* y, int n, const GmresDev& G, int j,
+                               hipStream_t s);
