@@ -1178,6 +1178,41 @@ struct MrhsSparseSrc {
 };
 
 
+// r[j] = r[j + 1] - c[j] a for j < K (a register window shifted by one),
+// with the coefficients c read from LDS in batches of 8, three batches (two
+// for windows of 96 and more) in flight ahead of the multiply-adds that use
+// them.  Scheduling barriers and
+// empty uses of the results keep the compiler from hoisting all the reads
+// (which would need K more registers) or from issuing them only just
+// before their use (which leaves the LDS latency exposed on every batch).
+template <int K>
+__device__ __forceinline__ void shift_update(double* r, const double* c, double a) {
+    static_assert(K % 8 == 0, "window sizes are multiples of 8");
+    constexpr int B = 8, D = K >= 96 ? 2 : 3, NB = K / B;  // wide windows leave room for two
+    double buf[D][B];
+#pragma unroll
+    for (int d = 0; d < D; ++d)
+        if (d < NB) {
+#pragma unroll
+            for (int t = 0; t < B; ++t) buf[d][t] = c[d * B + t];
+        }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const int sl = q % D;
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int t = 0; t < B; ++t) r[q * B + t] = r[q * B + t + 1] - buf[sl][t] * a;
+#pragma unroll
+        for (int t = 0; t < B; ++t) asm volatile("" ::"v"(r[q * B + t]));
+        __builtin_amdgcn_sched_barrier(0);
+        if (q + D < NB) {
+#pragma unroll
+            for (int t = 0; t < B; ++t) buf[sl][t] = c[(q + D) * B + t];
+        }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+}
+
 template <int KL, int KW, class Src, class Put>
 __device__ __forceinline__ void band_solve_mrhs(int n, int kl, int ku,
                                                 const double* __restrict__ Uf,
@@ -1248,8 +1283,7 @@ __device__ __forceinline__ void band_solve_mrhs(int n, int kl, int ku,
                 const double x0 = x[0];
                 if (valid) fwd[(size_t)k * ldf + col] = x0;
                 const double* Lk = L0 + st * FROW;
-#pragma unroll
-                for (int j = 0; j < KL; ++j) x[j] = x[j + 1] - Lk[j] * x0;
+                shift_update<KL>(x, Lk, x0);
                 x[KL] = (k + KL + 1 < n) ? src.take(k + KL + 1) : 0.0;
             }
         }
@@ -1323,8 +1357,7 @@ __device__ __forceinline__ void band_solve_mrhs(int n, int kl, int ku,
                 const double* Uk = U0 + st * BROW;
                 const double y = p[0] * Uk[0];
                 put(k, sint[slot * CH + st], y);
-#pragma unroll
-                for (int j = 0; j < KW; ++j) p[j] = p[j + 1] - Uk[1 + j] * y;
+                shift_update<KW>(p, Uk + 1, y);
                 p[KW] = ent[st];
             }
         }
