@@ -199,3 +199,27 @@ def test_hybrid_elasticity(coarse):
     uu, st, rc = _solver(case, coupling="hybrid", coarse=coarse).solve()
     assert rc == 0 and st["outer_its"] == st_ref["outer"]
     assert np.linalg.norm(_np(uu) - u_ref) <= 1e-10 * np.linalg.norm(u_ref)
+
+
+@pytest.mark.parametrize("coupling", ["additive", "hybrid"])
+def test_tuned_streams_elasticity(coupling):
+    """Neo-Hooke with every stream option on (graphs, chord coarse steps,
+    the second stream, the autotuner): the outer iteration, F_x and the
+    tangent as in the oracle."""
+    from paper_2410_24138_amd import nls
+    f = nls.FLAG_GRAPH | nls.FLAG_COARSE_CHORD | nls.FLAG_OVERLAP | nls.FLAG_AUTOTUNE
+    case = synth.small_elasticity_case(nx=18, ny=9, boxes=(3, 2), overlap=2,
+                                       traction=(0.5, -3.0), two_level=True)
+    P = NHProblem(case)
+    S = Schwarz(P, coupling)
+    u_ref, st_ref = S.solve()
+    s = _solver(case, coupling=coupling, flags=f)
+    uu, st, rc = s.solve()
+    assert rc == 0 and st["outer_its"] == st_ref["outer"]
+    assert np.linalg.norm(_np(uu) - u_ref) <= 1e-10 * np.linalg.norm(u_ref)
+    u = 0.7 * u_ref  # an admissible point off the solution (det F > 0)
+    ref = S.evaluate(u)
+    assert np.all(np.isfinite(ref))
+    _close(_np(s.precond_residual(u)), ref, 1e-10)
+    v = np.random.default_rng(14).normal(size=P.ndof)
+    _close(_np(s.tangent(v)), S.tangent(v), 1e-10)

@@ -354,3 +354,32 @@ def test_rgdsw_matches_oracle(kw):
     uu, st, rc = _solver(case, coupling="additive", coarse="rgdsw").solve()
     assert rc == 0 and st["outer_its"] == st_ref["outer"]
     assert np.linalg.norm(_np(uu) - u_ref) <= 1e-10 * np.linalg.norm(u_ref)
+
+
+@pytest.mark.parametrize("flags", ["overlap", "chord+graph+overlap", "lu_apply+overlap"])
+def test_hybrid_with_second_stream_matches_oracle(flags):
+    """Hybrid coupling (eqs. 11, 12) with the second stream on: the tangent's
+    coarse factorisations run beside the local ones (the coarse term of the
+    hybrid tangent stays in series, it feeds the local term).  Uneven boxes,
+    so that the local kernels run in several size buckets at once."""
+    from paper_2410_24138_amd import nls
+    f = nls.FLAG_OVERLAP
+    f |= nls.FLAG_COARSE_CHORD if "chord" in flags else 0
+    f |= nls.FLAG_COARSE_LU_APPLY if "lu_apply" in flags else 0
+    f |= nls.FLAG_GRAPH if "graph" in flags else 0
+    case = synth.small_case(n=48, boxes=3, overlap=2, uneven=True, coef_seed=5, forcing_seed=3,
+                            two_level=True)
+    P = P1Problem(case)
+    S = Schwarz(P, "hybrid")
+    s = _solver(case, coupling="hybrid", flags=f)
+    assert len(s.tuning()["n_sub"]) >= 2  # several size buckets, one stream each
+    u = _probe_point(P, case)
+    _close(_np(s.precond_residual(u)), S.evaluate(u), 1e-10)
+    np.testing.assert_array_equal(s.inner_iterations(), [sol["its"] for sol in S.state["sols"]])
+    for seed in (3, 4):
+        v = np.random.default_rng(seed).normal(size=P.N)
+        _close(_np(s.tangent(v)), S.tangent(v), 1e-10)
+    u_ref, st_ref = S.solve()
+    uu, st, rc = _solver(case, coupling="hybrid", flags=f).solve()
+    assert rc == 0 and st["outer_its"] == st_ref["outer"]
+    assert np.linalg.norm(_np(uu) - u_ref) <= 1e-10 * np.linalg.norm(u_ref)
