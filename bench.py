@@ -52,8 +52,8 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per dispatch measured with rocprofv3 FETCH_SIZE/WRITE_SIZE (two
 # passes, calibrated against a 256 MiB copy; profiles/hbm_traffic_*.md), valid
 # only for the kernel source they were taken with.
-MEASURED_TRAFFIC = {"kernels_sha1": "5b01f2611b963e1809be00b2b4f422041e310d16",
-                    "bytes": {"k_local_newton": 977302916, "k_local_factor": 433403278, "k_tangent_prep": 1198546838, "k_tangent_gemv": 280763330, "k_coarse_galerkin": 204467629, "k_coarse_lu": 1398534, "k_coarse_inverse": 12176374, "k_coarse_apply_inverse": 4100779, "k_mdot_partial": 25626695, "k_maxpy": 30790218, "k_prolong": 27168692, "k_coarse_ty": 20665362}}
+MEASURED_TRAFFIC = {"kernels_sha1": "b81584878c19dddf8f0e687fd6e7fa1ac6dd5c7a",
+                    "bytes": {"k_local_newton": 977486099, "k_local_factor": 433604545, "k_tangent_prep": 1198943790, "k_tangent_gemv": 280757367, "k_coarse_galerkin": 204851323, "k_coarse_lu": 1398513, "k_coarse_inverse": 12186833, "k_coarse_apply_inverse": 4085555, "k_mdot_partial": 25627541, "k_maxpy": 30807543, "k_prolong": 27169196, "k_coarse_ty": 20660478}}
 
 
 def _factor_bytes(case, elem_bytes):
