@@ -2231,6 +2231,7 @@ k_coarse_galerkin_sum(DevCoarse C) {
 
 // gblk_i = Y_i^T v on the closure of subdomain i (coarse term of the tangent);
 // Y_i is stored column by column (Y[k * nc + c]), so the lanes read along c.
+// Grid (nsub, Q): one wavefront per coarse function, spread over Q blocks.
 __global__ void __launch_bounds__(NLS_BLOCK)
 k_coarse_ty(DevCoarse C, const double* __restrict__ v) {
     const int i = blockIdx.x;
@@ -2238,7 +2239,7 @@ k_coarse_ty(DevCoarse C, const double* __restrict__ v) {
     const int k0 = C.off_k[i], nk = C.off_k[i + 1] - k0;
     const double* y = C.ybuf + C.off_phi[i];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (int k = wv; k < nk; k += nw) {
+    for (int k = wv + nw * blockIdx.y; k < nk; k += nw * gridDim.y) {
         double acc = 0.0;
         for (int c = lane; c < nc; c += 64) acc += y[(int64_t)k * nc + c] * v[C.cnode[cb + c]];
         acc = wave_sum(acc);
@@ -2649,7 +2650,9 @@ hipError_t launch_coarse_galerkin(const DevMesh& M, const DevCoarse& C, const do
 }
 
 hipError_t launch_coarse_ty(const DevCoarse& C, const double* v, hipStream_t s) {
-    k_coarse_ty<<<C.nsub, NLS_BLOCK, 0, s>>>(C, v);
+    // up to four blocks per subdomain when there are fewer subdomains than CUs
+    const dim3 grid(C.nsub, C.nsub >= 256 ? 1 : (C.nsub >= 128 ? 2 : 4));
+    k_coarse_ty<<<grid, NLS_BLOCK, 0, s>>>(C, v);
     return hipGetLastError();
 }
 
