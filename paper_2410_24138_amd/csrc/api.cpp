@@ -1207,11 +1207,10 @@ static int arnoldi_step(nls_handle* h, int j, hipStream_t s) {
     double* vj = h->V + (int64_t)j * ld;
     double* vn = h->V + (int64_t)(j + 1) * ld;
     RC(tangent(h, vj, h->wv, s));
-    HIPCHK(launch_mdot(h->V, ld, j + 1, h->wv, N, h->partial, h->hbuf, h->nb_dot, s));
-    HIPCHK(launch_maxpy(h->V, ld, j + 1, h->hbuf, h->wv, N, 1.0, s));
-    HIPCHK(launch_mdot(h->V, ld, j + 1, h->wv, N, h->partial, h->hbuf2, h->nb_dot, s));
-    HIPCHK(launch_maxpy_norm(h->V, ld, j + 1, h->hbuf2, h->wv, N, h->partial, h->hn2, h->nb_dot, s));
-    HIPCHK(launch_scale_givens(h->wv, vn, N, gmres_dev(h), j, s));
+    // norm partial sums after the (m + 1) nb dot-product partials
+    double* pnorm = h->partial + (int64_t)h->nb_dot * (h->m + 1);
+    HIPCHK(launch_arnoldi_gs(h->V, ld, j + 1, h->wv, N, h->partial, pnorm, h->hbuf, h->hbuf2,
+                             gmres_dev(h), j, vn, h->nb_dot, s));
     return NLS_OK;
 }
 

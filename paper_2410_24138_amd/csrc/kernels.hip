@@ -2394,6 +2394,90 @@ k_maxpy_norm(const double* __restrict__ V, int64_t ld, int m, const double* __re
     if (threadIdx.x == 0) partial[blockIdx.x] = ss;
 }
 
+// ---------------------------------------------------------------------------
+// Arnoldi step kernels that finish the previous reduction themselves: every
+// block adds up the partial sums of the dot products in the same fixed order
+// (one wavefront per entry), so all blocks hold identical totals and no
+// separate final launch is needed; block 0 also stores the totals.
+// ---------------------------------------------------------------------------
+__device__ void gmres_givens_step(const GmresDev& G, int j);
+
+__device__ __forceinline__ void block_totals(const double* __restrict__ partial, int nb, int m,
+                                             double* hs, double* out) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int j = wv; j < m; j += nw) {
+        double s = 0.0;
+        for (int b = lane; b < nb; b += 64) s += partial[(int64_t)b * m + j];
+        s = wave_sum(s);
+        if (lane == 0) {
+            hs[j] = s;
+            if (blockIdx.x == 0) out[j] = s;
+        }
+    }
+    __syncthreads();
+}
+
+// h = totals of partial (nb x m); w -= V h (one element per thread)
+__global__ void __launch_bounds__(NLS_BLOCK)
+k_maxpy_totals(const double* __restrict__ V, int64_t ld, int m, const double* __restrict__ partial,
+               int nb, double* __restrict__ hout, double* __restrict__ w, int n) {
+    extern __shared__ double hs[];
+    block_totals(partial, nb, m, hs, hout);
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    double acc = 0.0;
+    for (int j = 0; j < m; ++j) acc += hs[j] * V[(int64_t)j * ld + t];
+    w[t] -= acc;
+}
+
+// h = totals of partial; w -= V h and partial sums of ||w||^2 into pnorm
+// (the chunks of k_mdot_partial with gridDim.x blocks)
+__global__ void __launch_bounds__(NLS_BLOCK)
+k_maxpy_norm_totals(const double* __restrict__ V, int64_t ld, int m,
+                    const double* __restrict__ partial, int nb, double* __restrict__ hout,
+                    double* __restrict__ w, int n, double* __restrict__ pnorm) {
+    extern __shared__ double hs[];
+    __shared__ double red[24];
+    block_totals(partial, nb, m, hs, hout);
+    const int chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+    double ss = 0.0;
+    for (int t = lo + threadIdx.x; t < hi; t += blockDim.x) {
+        double acc = 0.0;
+        for (int j = 0; j < m; ++j) acc += hs[j] * V[(int64_t)j * ld + t];
+        const double x = w[t] - acc;
+        w[t] = x;
+        ss += x * x;
+    }
+    ss = block_sum(ss, red);
+    if (threadIdx.x == 0) pnorm[blockIdx.x] = ss;
+}
+
+// ||w||^2 = total of pnorm (nb); y = w / ||w||; block 0 stores ||w||^2 and
+// its first thread applies rotation j of the Arnoldi column
+__global__ void __launch_bounds__(NLS_BLOCK)
+k_scale_givens_totals(const double* __restrict__ x, double* __restrict__ y, int n,
+                      const double* __restrict__ pnorm, int nb, GmresDev G, int j) {
+    __shared__ double tot;
+    if (threadIdx.x < 64) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nb; b += 64) s += pnorm[b];
+        s = wave_sum(s);
+        if (threadIdx.x == 0) {
+            tot = s;
+            if (blockIdx.x == 0) {
+                G.hn2[0] = s;
+                gmres_givens_step(G, j);
+            }
+        }
+    }
+    __syncthreads();
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n) return;
+    const double d = sqrt(tot);
+    y[t] = (d > 0.0) ? x[t] / d : 0.0;
+}
+
 // rhs[perm[k]] = sum of the coarse blocks' entries of row k (no norm).
 __global__ void k_coarse_gather(DevCoarse C) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -2479,16 +2563,6 @@ __global__ void k_gmres_givens(GmresDev G, int j) {
     gmres_givens_step(G, j);
 }
 
-// v_{j+1} = w / ||w|| and, by the first thread, rotation j of the Arnoldi
-// column (both read the same ||w||^2 and write disjoint memory).
-__global__ void k_scale_givens(const double* __restrict__ x, double* __restrict__ y, int n,
-                               GmresDev G, int j) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t == 0) gmres_givens_step(G, j);
-    if (t >= n) return;
-    const double d = sqrt(G.hn2[0]);
-    y[t] = (d > 0.0) ? x[t] / d : 0.0;
-}
 
 inline int nblocks(int n, int b = NLS_BLOCK) { return (n + b - 1) / b; }
 
@@ -2751,6 +2825,18 @@ hipError_t launch_maxpy(const double* V, int64_t ld, int m, const double* h, dou
     return hipGetLastError();
 }
 
+hipError_t launch_arnoldi_gs(const double* V, int64_t ld, int m, double* w, int n, double* partial,
+                             double* pnorm, double* h1, double* h2, const GmresDev& G, int j,
+                             double* vnext, int nb, hipStream_t s) {
+    const int lds = m * (int)sizeof(double);
+    k_mdot_partial<<<nb, NLS_BLOCK, 0, s>>>(V, ld, m, w, n, partial);
+    k_maxpy_totals<<<nblocks(n), NLS_BLOCK, lds, s>>>(V, ld, m, partial, nb, h1, w, n);
+    k_mdot_partial<<<nb, NLS_BLOCK, 0, s>>>(V, ld, m, w, n, partial);
+    k_maxpy_norm_totals<<<nb, NLS_BLOCK, lds, s>>>(V, ld, m, partial, nb, h2, w, n, pnorm);
+    k_scale_givens_totals<<<nblocks(n), NLS_BLOCK, 0, s>>>(w, vnext, n, pnorm, nb, G, j);
+    return hipGetLastError();
+}
+
 hipError_t launch_maxpy_norm(const double* V, int64_t ld, int m, const double* h, double* w, int n,
                              double* partial, double* out, int nb, hipStream_t s) {
     k_maxpy_norm<<<nb, NLS_BLOCK, 0, s>>>(V, ld, m, h, w, n, partial);
@@ -2786,11 +2872,6 @@ hipError_t launch_any_status(const int* status, int n, int* out, hipStream_t s) 
     return hipGetLastError();
 }
 
-hipError_t launch_scale_givens(const double* x, double* y, int n, const GmresDev& G, int j,
-                               hipStream_t s) {
-    k_scale_givens<<<nblocks(n), NLS_BLOCK, 0, s>>>(x, y, n, G, j);
-    return hipGetLastError();
-}
 
 hipError_t launch_gmres_givens(const GmresDev& G, int j, hipStream_t s) {
     k_gmres_givens<<<1, 64, 0, s>>>(G, j);

@@ -197,12 +197,19 @@ hipError_t launch_any_status(const int* status, int n, int* out, hipStream_t s);
 // st[1]: columns processed.
 struct GmresDev {
     double *H, *cs, *sn, *g;
-    const double *h1, *h2, *hn2, *tol;
+    const double *h1, *h2, *tol;
+    double* hn2;
     int* st;
     int m;
 };
 hipError_t prepare_coarse_lu(int lds_bytes, int npl);
 hipError_t launch_gmres_givens(const GmresDev& G, int j, hipStream_t s);
-// y = x / sqrt(G.hn2[0]) and rotation j (k_gmres_givens) in one launch
-hipError_t launch_scale_givens(const double* x, double* y, int n, const GmresDev& G, int j,
-                               hipStream_t s);
+// Both classical Gram-Schmidt passes of Arnoldi column j (h1 = V^T w,
+// w -= V h1, h2 = V^T w, w -= V h2), ||w||^2 into G.hn2, rotation j and
+// vnext = w / ||w||, in five launches: each kernel that consumes a
+// reduction adds up its nb partial sums itself (same fixed order in every
+// block), so no final-sum launches are needed.  pnorm: nb doubles apart
+// from partial (nb x m).
+hipError_t launch_arnoldi_gs(const double* V, int64_t ld, int m, double* w, int n, double* partial,
+                             double* pnorm, double* h1, double* h2, const GmresDev& G, int j,
+                             double* vnext, int nb, hipStream_t s);
