@@ -52,8 +52,8 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per dispatch measured with rocprofv3 FETCH_SIZE/WRITE_SIZE (two
 # passes, calibrated against a 256 MiB copy; profiles/hbm_traffic_*.md), valid
 # only for the kernel source they were taken with.
-MEASURED_TRAFFIC = {"kernels_sha1": "b81584878c19dddf8f0e687fd6e7fa1ac6dd5c7a",
-                    "bytes": {"k_local_newton": 977486099, "k_local_factor": 433604545, "k_tangent_prep": 1198943790, "k_tangent_gemv": 280757367, "k_coarse_galerkin": 204851323, "k_coarse_lu": 1398513, "k_coarse_inverse": 12186833, "k_coarse_apply_inverse": 4085555, "k_mdot_partial": 25627541, "k_maxpy": 30807543, "k_prolong": 27169196, "k_coarse_ty": 20660478}}
+MEASURED_TRAFFIC = {"kernels_sha1": "a48f214f102b74f10de80c9f0240eb8ac74c2cec",
+                    "bytes": {"k_local_newton": 977616376, "k_local_factor": 433681798, "k_tangent_prep": 1199137445, "k_tangent_gemv": 280761901, "k_coarse_galerkin": 204973468, "k_coarse_lu": 1397744, "k_coarse_inverse": 12186827, "k_coarse_apply_inverse": 4089647, "k_mdot_partial": 25626506, "k_maxpy": 48708488, "k_prolong": 27171337, "k_coarse_ty": 20660858}}
 
 
 def _factor_bytes(case, elem_bytes):
