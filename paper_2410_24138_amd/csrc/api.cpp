@@ -385,6 +385,17 @@ extern "C" int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* el
     RC(h->alloc(G_MAPS, &L.start, M.nsub));
     h->dl = L;
     h->its_h.assign(M.nsub, 0);
+    {
+        const size_t need = 1024 + sizeof(int) * (size_t)M.nsub;
+        if (need > h->pin_bytes) {
+            if (h->pin) HIPCHK(hipHostFree(h->pin));
+            h->pin = nullptr;
+            h->pin_bytes = 0;
+            if (hipHostMalloc(&h->pin, need, hipHostMallocDefault) != hipSuccess)
+                return fail(h, NLS_ENOMEM, "pinned host allocation failed");
+            h->pin_bytes = need;
+        }
+    }
     // exact-tangent blocks W_i = (J_ii^{-1} B_i)[owned rows, :]
     {
         int bucket = 0;
@@ -691,6 +702,12 @@ static bool two_level(nls_handle* h) {
     return h->opt.coupling != NLS_ONE_LEVEL && h->have_coarse && h->co.n0 > 0;
 }
 
+// Regions of the pinned host buffer (see nls_handle::pin).
+static double* pin_main(nls_handle* h) { return (double*)h->pin; }
+static double* pin_coarse(nls_handle* h) { return (double*)((char*)h->pin + 256); }
+static int* pin_graph(nls_handle* h) { return (int*)((char*)h->pin + 512); }
+static int* pin_its(nls_handle* h) { return (int*)((char*)h->pin + 1024); }
+
 // The size buckets of a local kernel run concurrently: bucket 0 on s, bucket
 // b > 0 on a stream of its own that waits for s first, and s waits for them
 // all at the join (the buckets touch disjoint subdomains).
@@ -753,9 +770,10 @@ static int coarse_solve(nls_handle* h, const double* u, int* its_out, hipStream_
         HIPCHK(launch_coarse_w(h->dm, d, u, d.w, cs));
         HIPCHK(launch_coarse_q(h->dm, d, d.w, nullptr, 0, h->lds_coarse_q, cs));
         HIPCHK(launch_coarse_assemble(d, 0, cs));
-        double gn = 0.0;
-        HIPCHK(hipMemcpyAsync(&gn, d.scal, sizeof(double), hipMemcpyDeviceToHost, cs));
+        double* pc = pin_coarse(h);
+        HIPCHK(hipMemcpyAsync(pc, d.scal, sizeof(double), hipMemcpyDeviceToHost, cs));
         HIPCHK(hipStreamSynchronize(cs));
+        const double gn = pc[0];
         if (its == 0)
             tol = std::max(h->opt.inner_rtol * gn, h->opt.inner_eta * h->phib_inf * std::sqrt((double)n0));
         if (!std::isfinite(gn)) return fail(h, NLS_ENAN, "coarse residual is not finite");
@@ -777,14 +795,12 @@ static int coarse_solve(nls_handle* h, const double* u, int* its_out, hipStream_
         }
         have_lu = chord;
         HIPCHK(launch_coarse_update(d, cs));
-        double sc[3];
-        int flag = 0;
-        HIPCHK(hipMemcpyAsync(sc, d.scal, 3 * sizeof(double), hipMemcpyDeviceToHost, cs));
-        HIPCHK(hipMemcpyAsync(&flag, d.flag, sizeof(int), hipMemcpyDeviceToHost, cs));
+        HIPCHK(hipMemcpyAsync(pc, d.scal, 3 * sizeof(double), hipMemcpyDeviceToHost, cs));
+        HIPCHK(hipMemcpyAsync(pc + 4, d.flag, sizeof(int), hipMemcpyDeviceToHost, cs));
         HIPCHK(hipStreamSynchronize(cs));
-        if (flag) return fail(h, NLS_ESINGULAR, "zero pivot in the coarse matrix");
-        dprev = sc[1];
-        cmax = sc[2];
+        if (*(const int*)(pc + 4)) return fail(h, NLS_ESINGULAR, "zero pivot in the coarse matrix");
+        dprev = pc[1];
+        cmax = pc[2];
         gprev = gn;
         ++its;
     }
@@ -794,8 +810,10 @@ static int coarse_solve(nls_handle* h, const double* u, int* its_out, hipStream_
 
 static int dot_host(nls_handle* h, const double* x, const double* y, int n, double* out) {
     HIPCHK(launch_mdot(x, n, 1, y, n, h->partial, h->hn2 + 2, h->nb_dot, h->stream));
-    HIPCHK(hipMemcpyAsync(out, h->hn2 + 2, sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    return sync(h);
+    HIPCHK(hipMemcpyAsync(pin_main(h), h->hn2 + 2, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    RC(sync(h));
+    *out = pin_main(h)[0];
+    return NLS_OK;
 }
 
 static int coarse_phase(nls_handle* h, const double* u, hipStream_t cs) {
@@ -865,10 +883,13 @@ static int evaluate(nls_handle* h, const double* u, double* Fx) {
             return rc;
         }
     }
-    HIPCHK(hipMemcpyAsync(st2, h->stat2, 2 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
-    HIPCHK(hipMemcpyAsync(h->its_h.data(), h->dl.its, h->maps.nsub * sizeof(int),
+    HIPCHK(hipMemcpyAsync(pin_main(h), h->stat2, 2 * sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(pin_its(h), h->dl.its, h->maps.nsub * sizeof(int),
                           hipMemcpyDeviceToHost, h->stream));
     RC(sync(h));
+    st2[0] = ((const int*)pin_main(h))[0];
+    st2[1] = ((const int*)pin_main(h))[1];
+    std::copy(pin_its(h), pin_its(h) + h->maps.nsub, h->its_h.begin());
     if (h->st) {
         h->st->ms_inner += t.ms();
         for (int v : h->its_h) {
@@ -1305,9 +1326,10 @@ static int gmres_graph(nls_handle* h, const double* b, double* x, int* its_out) 
             } else {
                 for (int jj = j; jj < std::min(jn, j + budget); ++jj) RC(arnoldi_step(h, jj, h->gstream));
             }
-            int st[2];
-            HIPCHK(hipMemcpyAsync(st, h->gst, sizeof(st), hipMemcpyDeviceToHost, h->gstream));
+            HIPCHK(hipMemcpyAsync(pin_graph(h), h->gst, 2 * sizeof(int), hipMemcpyDeviceToHost,
+                                  h->gstream));
             HIPCHK(hipStreamSynchronize(h->gstream));
+            const int st[2] = {pin_graph(h)[0], pin_graph(h)[1]};
             if (st[0] < 0) return fail(h, NLS_ENAN, "GMRES breakdown (non-finite)");
             if (st[0] > 0) {
                 conv = st[0];

@@ -78,6 +78,12 @@ struct nls_handle {
            *ydev = nullptr, *ubuf = nullptr;
     int* stat2 = nullptr;
     int nb_dot = 0;
+    // pinned host memory for the small device-to-host reads of the driver
+    // (status words, norms, iteration counts): bytes [0, 256) for the main
+    // stream, [256, 512) the coarse stream, [512, 1024) the GMRES graph
+    // stream, from 1024 the per-subdomain inner iteration counts
+    void* pin = nullptr;
+    size_t pin_bytes = 0;
     // problem data kept on the device for nls_set_load
     const double *d_xy = nullptr, *d_coef = nullptr;
     double* d_fmid = nullptr;
@@ -145,6 +151,7 @@ struct nls_handle {
         for (auto e : gev)
             if (e) (void)hipEventDestroy(e);
         if (gstream) (void)hipStreamDestroy(gstream);
+        if (pin) (void)hipHostFree(pin);
         if (cstream) (void)hipStreamDestroy(cstream);
         for (hipStream_t q : bstream) (void)hipStreamDestroy(q);
         for (hipEvent_t e : bev) (void)hipEventDestroy(e);
