@@ -52,8 +52,8 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per dispatch measured with rocprofv3 FETCH_SIZE/WRITE_SIZE (two
 # passes, calibrated against a 256 MiB copy; profiles/hbm_traffic_*.md), valid
 # only for the kernel source they were taken with.
-MEASURED_TRAFFIC = {"kernels_sha1": "a48f214f102b74f10de80c9f0240eb8ac74c2cec",
-                    "bytes": {"k_local_newton": 977616376, "k_local_factor": 433681798, "k_tangent_prep": 1199137445, "k_tangent_gemv": 280761901, "k_coarse_galerkin": 204973468, "k_coarse_lu": 1397744, "k_coarse_inverse": 12186827, "k_coarse_apply_inverse": 4089647, "k_mdot_partial": 25626506, "k_maxpy": 48708488, "k_prolong": 27171337, "k_coarse_ty": 20660858}}
+MEASURED_TRAFFIC = {"kernels_sha1": "e95cdfc1aec6465970c92aa3aa93bcadd35eb84f",
+                    "bytes": {"k_local_newton": 980523110, "k_local_factor": 435793690, "k_tangent_prep": 1199257533, "k_tangent_gemv": 280774607, "k_coarse_galerkin": 205666488, "k_coarse_lu": 1397595, "k_coarse_inverse": 12185835, "k_coarse_apply_inverse": 4100908, "k_mdot_partial": 25620394, "k_maxpy": 48708711, "k_prolong": 27158415, "k_coarse_ty": 20666130}}
 
 
 def _factor_bytes(case, elem_bytes):

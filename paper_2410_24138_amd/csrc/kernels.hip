@@ -2558,10 +2558,6 @@ __device__ void gmres_givens_step(const GmresDev& G, int j) {
     else if (r <= G.tol[0]) G.st[0] = j + 1;
 }
 
-__global__ void k_gmres_givens(GmresDev G, int j) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    gmres_givens_step(G, j);
-}
 
 
 inline int nblocks(int n, int b = NLS_BLOCK) { return (n + b - 1) / b; }
@@ -2873,7 +2869,3 @@ hipError_t launch_any_status(const int* status, int n, int* out, hipStream_t s) 
 }
 
 
-hipError_t launch_gmres_givens(const GmresDev& G, int j, hipStream_t s) {
-    k_gmres_givens<<<1, 64, 0, s>>>(G, j);
-    return hipGetLastError();
-}

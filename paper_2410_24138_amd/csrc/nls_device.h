@@ -203,7 +203,6 @@ struct GmresDev {
     int m;
 };
 hipError_t prepare_coarse_lu(int lds_bytes, int npl);
-hipError_t launch_gmres_givens(const GmresDev& G, int j, hipStream_t s);
 // Both classical Gram-Schmidt passes of Arnoldi column j (h1 = V^T w,
 // w -= V h1, h2 = V^T w, w -= V h2), ||w||^2 into G.hn2, rotation j and
 // vnext = w / ||w||, in five launches: each kernel that consumes a
