@@ -2328,29 +2328,28 @@ __global__ void k_coarse_scatter(DevCoarse C, const double* __restrict__ src, do
 // ----------------------------------------------------------------------------
 // Vector kernels (GMRES).  partial sums per block, then a fixed-order sum.
 // ----------------------------------------------------------------------------
+// partial[b m + j] = V_j . w over block b's chunk: each wavefront takes its
+// own vectors j (wv, wv + 4, ...) over the whole chunk, four independent
+// loads per lane in flight, and reduces them itself (fixed order).
 __global__ void __launch_bounds__(NLS_BLOCK)
 k_mdot_partial(const double* __restrict__ V, int64_t ld, int m, const double* __restrict__ w,
                int n, double* __restrict__ partial) {
-    __shared__ double red[4 * 64];
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int chunk = (n + gridDim.x - 1) / gridDim.x;
     const int lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
-    for (int j0 = 0; j0 < m; j0 += 64) {
-        const int jn = min(64, m - j0);
-        for (int jj = 0; jj < jn; ++jj) {
-            const double* vj = V + (int64_t)(j0 + jj) * ld;
-            double acc = 0.0;
-            for (int t = lo + threadIdx.x; t < hi; t += blockDim.x) acc += vj[t] * w[t];
-            acc = wave_sum(acc);
-            if (lane == 0) red[wv * 64 + jj] = acc;
+    for (int j = wv; j < m; j += nw) {
+        const double* vj = V + (int64_t)j * ld;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int t = lo + lane;
+        for (; t + 192 < hi; t += 256) {
+            a0 += vj[t] * w[t];
+            a1 += vj[t + 64] * w[t + 64];
+            a2 += vj[t + 128] * w[t + 128];
+            a3 += vj[t + 192] * w[t + 192];
         }
-        __syncthreads();
-        if (threadIdx.x < jn) {
-            double s = 0.0;
-            for (int q = 0; q < (int)(blockDim.x >> 6); ++q) s += red[q * 64 + threadIdx.x];
-            partial[(int64_t)blockIdx.x * m + j0 + threadIdx.x] = s;
-        }
-        __syncthreads();
+        for (; t < hi; t += 64) a0 += vj[t] * w[t];
+        const double sum = wave_sum((a0 + a1) + (a2 + a3));
+        if (lane == 0) partial[(int64_t)blockIdx.x * m + j] = sum;
     }
 }
 
