@@ -52,8 +52,8 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per dispatch measured with rocprofv3 FETCH_SIZE/WRITE_SIZE (two
 # passes, calibrated against a 256 MiB copy; profiles/hbm_traffic_*.md), valid
 # only for the kernel source they were taken with.
-MEASURED_TRAFFIC = {"kernels_sha1": "e95cdfc1aec6465970c92aa3aa93bcadd35eb84f",
-                    "bytes": {"k_local_newton": 980523110, "k_local_factor": 435793690, "k_tangent_prep": 1199257533, "k_tangent_gemv": 280774607, "k_coarse_galerkin": 205666488, "k_coarse_lu": 1397595, "k_coarse_inverse": 12185835, "k_coarse_apply_inverse": 4100908, "k_mdot_partial": 25620394, "k_maxpy": 48708711, "k_prolong": 27158415, "k_coarse_ty": 20666130}}
+MEASURED_TRAFFIC = {"kernels_sha1": "1f4a4be35c69b5ff9ba6778a0151c5a8ac3b3db0",
+                    "bytes": {"k_local_newton": 977636081, "k_local_factor": 433396816, "k_tangent_prep": 1199131212, "k_tangent_gemv": 280771397, "k_coarse_galerkin": 204412412, "k_coarse_lu": 1397587, "k_coarse_inverse": 12185774, "k_coarse_apply_inverse": 4100870, "k_mdot_partial": 25636060, "k_maxpy": 48708288, "k_prolong": 27160217, "k_coarse_ty": 20666330}}
 
 
 def _factor_bytes(case, elem_bytes):
