@@ -2534,14 +2534,15 @@ __device__ void gmres_givens_step(const GmresDev& G, int j) {
     if (G.st[0] != 0) return;
     const int m = G.m;
     double* H = G.H;
-    for (int i = 0; i <= j; ++i) H[i * m + j] = G.h1[i] + G.h2[i];
-    H[(j + 1) * m + j] = sqrt(G.hn2[0]);
+    // the entry that rotation i leaves in row i + 1 is carried in a register
+    // into rotation i + 1 (same arithmetic as storing and reloading it)
+    double a = G.h1[0] + G.h2[0];
     for (int i = 0; i < j; ++i) {
-        const double a = H[i * m + j], b = H[(i + 1) * m + j];
-        H[(i + 1) * m + j] = -G.sn[i] * a + G.cs[i] * b;
+        const double b = G.h1[i + 1] + G.h2[i + 1];
         H[i * m + j] = G.cs[i] * a + G.sn[i] * b;
+        a = -G.sn[i] * a + G.cs[i] * b;
     }
-    const double a = H[j * m + j], b = H[(j + 1) * m + j];
+    const double b = sqrt(G.hn2[0]);
     const double den = hypot(a, b);
     const double c = den > 0.0 ? a / den : 1.0, sn = den > 0.0 ? b / den : 0.0;
     G.cs[j] = c;
