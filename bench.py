@@ -52,8 +52,8 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per dispatch measured with rocprofv3 FETCH_SIZE/WRITE_SIZE (two
 # passes, calibrated against a 256 MiB copy; profiles/hbm_traffic_*.md), valid
 # only for the kernel source they were taken with.
-MEASURED_TRAFFIC = {"kernels_sha1": "1f4a4be35c69b5ff9ba6778a0151c5a8ac3b3db0",
-                    "bytes": {"k_local_newton": 977636081, "k_local_factor": 433396816, "k_tangent_prep": 1199131212, "k_tangent_gemv": 280771397, "k_coarse_galerkin": 204412412, "k_coarse_lu": 1397587, "k_coarse_inverse": 12185774, "k_coarse_apply_inverse": 4100870, "k_mdot_partial": 25636060, "k_maxpy": 48708288, "k_prolong": 27160217, "k_coarse_ty": 20666330}}
+MEASURED_TRAFFIC = {"kernels_sha1": "b95a08ccf6cc796adf49bdfe0bcc7f713536de96",
+                    "bytes": {"k_local_newton": 977437277, "k_local_factor": 433415920, "k_tangent_prep": 1199224362, "k_tangent_gemv": 280761378, "k_coarse_galerkin": 204523324, "k_coarse_lu": 1398454, "k_coarse_inverse": 12185566, "k_coarse_apply_inverse": 4100765, "k_mdot_partial": 25635258, "k_maxpy": 48706844, "k_prolong": 27158831, "k_coarse_ty": 20665876}}
 
 
 def _factor_bytes(case, elem_bytes):
