@@ -440,7 +440,7 @@ extern "C" int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* el
     // GMRES workspace
     const int N = h->mesh.ndof();
     h->m = h->opt.gmres_restart;
-    h->nb_dot = std::min(512, std::max(1, (N + 1023) / 1024));
+    h->nb_dot = std::min(256, std::max(1, (N + 511) / 512));  // blocks of the vector reductions
     RC(h->alloc(G_MAPS, &h->V, (size_t)(h->m + 1) * N));
     RC(h->alloc(G_MAPS, &h->wv, N));
     RC(h->alloc(G_MAPS, &h->hbuf, h->m + 2));
