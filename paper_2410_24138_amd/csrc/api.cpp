@@ -421,6 +421,9 @@ extern "C" int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* el
             T.bptr = bptr; T.brow = brow; T.bslot = bslot; T.off_own = off_own;
             T.ownrow = ownrow; T.rowown = rowown; T.off_W = off_W; T.off_F = off_F;
             RC(h->alloc(G_MAPS, &T.W, (size_t)M.off_W.back()));
+            // W above 192 MiB cannot stay in MI355X's 256 MiB last-level
+            // cache between products: stream it past the cache instead
+            h->w_stream = (size_t)M.off_W.back() * sizeof(double) > ((size_t)192 << 20);
             RC(h->alloc(G_MAPS, &T.fwd, (size_t)M.off_F.back()));
             h->dt = T;
         }
@@ -1185,7 +1188,7 @@ static int tangent(nls_handle* h, const double* v, double* y, hipStream_t s = nu
         HIPCHK(hipEventRecord(h->cev[3], h->cstream));
     }
     if (h->tangent_w)
-        HIPCHK(launch_tangent_gemv(h->dp, h->dt, vloc, h->dl.z, h->max_ng, s));
+        HIPCHK(launch_tangent_gemv(h->dp, h->dt, vloc, h->dl.z, h->max_ng, h->w_stream, s));
     else
         HIPCHK(launch_tangent_local(h->dm, h->dp, h->dl, h->np, vloc, h->lds_tangent, h->npl_local, s));
     if (e0) {

@@ -1401,7 +1401,10 @@ k_tangent_prep(DevMaps P, DevLocal L, DevTangent Tg) {
 
 // z[owned rows of i] = W_i v_Gamma_i: streams W (column-major, one owned
 // row per thread) once; HBM-bound.  Grid (nsub, QS) splits each
-// subdomain's rows over QS blocks.
+// subdomain's rows over QS blocks.  STREAM: W is read with nontemporal
+// loads (for a W larger than the last-level cache, which it would only
+// thrash; a smaller W is left to stay cached between products).
+template <bool STREAM>
 __global__ void __launch_bounds__(256)
 k_tangent_gemv(DevMaps P, DevTangent Tg, const double* __restrict__ v, double* __restrict__ z) {
     extern __shared__ double vg[];
@@ -1418,7 +1421,10 @@ k_tangent_gemv(DevMaps P, DevTangent Tg, const double* __restrict__ v, double* _
         int j = 0;
         for (; j + 7 < ng; j += 8) {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) a[q] += W[(size_t)(j + q) * no + r] * vg[j + q];
+            for (int q = 0; q < 8; ++q) {
+                const double* wq = W + (size_t)(j + q) * no + r;
+                a[q] += (STREAM ? __builtin_nontemporal_load(wq) : *wq) * vg[j + q];
+            }
         }
         for (; j < ng; ++j) a[0] += W[(size_t)j * no + r] * vg[j];
         z[rowbase + Tg.ownrow[ob + r]] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
@@ -2783,12 +2789,15 @@ hipError_t launch_tangent_prep(const DevMaps& P, const DevLocal& L, const DevTan
 }
 
 hipError_t launch_tangent_gemv(const DevMaps& P, const DevTangent& Tg, const double* v, double* z,
-                               int max_ng, hipStream_t s) {
+                               int max_ng, bool stream_w, hipStream_t s) {
     // four workgroups per subdomain (eight with fewer subdomains than CUs,
     // whose patches are larger): one owned row per thread, so that enough
     // loads of W are in flight per CU
     dim3 grid(P.nsub, P.nsub < 256 ? 8 : 4);
-    k_tangent_gemv<<<grid, 256, max_ng * 8, s>>>(P, Tg, v, z);
+    if (stream_w)
+        k_tangent_gemv<true><<<grid, 256, max_ng * 8, s>>>(P, Tg, v, z);
+    else
+        k_tangent_gemv<false><<<grid, 256, max_ng * 8, s>>>(P, Tg, v, z);
     return hipGetLastError();
 }
 

@@ -172,8 +172,9 @@ int mrhs_bucket_kl(int kl, int ku);
 int mrhs_lds_bytes(int kl_bucket);
 hipError_t launch_tangent_prep(const DevMaps& P, const DevLocal& L, const DevTangent& Tg,
                                int kl_bucket, int max_ng, hipStream_t s);
+// stream_w: nontemporal loads of W (for a W larger than the last-level cache)
 hipError_t launch_tangent_gemv(const DevMaps& P, const DevTangent& Tg, const double* v, double* z,
-                               int max_ng, hipStream_t s);
+                               int max_ng, bool stream_w, hipStream_t s);
 // A0^{-1} per diagonal block from its band LU (any band up to 511 wide)
 int coarse_inverse_lds_bytes(int max_block, int max_ldu);
 hipError_t launch_coarse_inverse(const DevCoarse& C, int max_block, int max_ldu, hipStream_t s);
