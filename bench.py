@@ -52,8 +52,8 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per dispatch measured with rocprofv3 FETCH_SIZE/WRITE_SIZE (two
 # passes, calibrated against a 256 MiB copy; profiles/hbm_traffic_*.md), valid
 # only for the kernel source they were taken with.
-MEASURED_TRAFFIC = {"kernels_sha1": "b95a08ccf6cc796adf49bdfe0bcc7f713536de96",
-                    "bytes": {"k_local_newton": 977437277, "k_local_factor": 433415920, "k_tangent_prep": 1199224362, "k_tangent_gemv": 280761378, "k_coarse_galerkin": 204523324, "k_coarse_lu": 1398454, "k_coarse_inverse": 12185566, "k_coarse_apply_inverse": 4100765, "k_mdot_partial": 25635258, "k_maxpy": 48706844, "k_prolong": 27158831, "k_coarse_ty": 20665876}}
+MEASURED_TRAFFIC = {"kernels_sha1": "cab0b84f8a46e890e8fa8c8ed6552ca7001dc7ca",
+                    "bytes": {"k_local_newton": 977656090, "k_local_factor": 433445522, "k_tangent_prep": 1199041545, "k_tangent_gemv": 280757753, "k_coarse_galerkin": 204273833, "k_coarse_lu": 1399125, "k_coarse_inverse": 12186814, "k_coarse_apply_inverse": 4093713, "k_mdot_partial": 25619679, "k_maxpy": 48708400, "k_prolong": 27170183, "k_coarse_ty": 20666187}}
 
 
 def _factor_bytes(case, elem_bytes):
