@@ -516,6 +516,7 @@ extern "C" int nls_build_coarse(nls_handle* h, int kind) {
     h->lds_coarse_q = maxnc * 8;
     if (lds_gdsw > 160 * 1024 || h->lds_coarse_lu > 160 * 1024 || h->lds_coarse_q > 160 * 1024)
         return fail(h, NLS_ELIMIT, "coarse working set exceeds LDS");
+    HIPCHK(prepare_coarse_ty(h->lds_coarse_q));
     h->npl_coarse = npl_for(std::max(C.a0kl, C.a0kl + C.a0ku));
     DevCoarse d{};
     d.n0 = C.n0;
@@ -1152,7 +1153,7 @@ static int tangent(nls_handle* h, const double* v, double* y, hipStream_t s = nu
     // coarse term q = Q_0 v = Phi A0^{-1} Phi^T DF(u_0) v, as coefficients in ctmp
     auto coarse_term = [&]() -> int {
         DevCoarse& d = h->dc;
-        HIPCHK(launch_coarse_ty(d, v, s));
+        HIPCHK(launch_coarse_ty(d, v, h->lds_coarse_q, s));
         HIPCHK(launch_coarse_gather(d, s));
         if (h->coarse_inv) {
             HIPCHK(launch_coarse_apply_inverse(d, d.rhs, h->rhs2, s));

@@ -2237,18 +2237,31 @@ k_coarse_galerkin_sum(DevCoarse C) {
 
 // gblk_i = Y_i^T v on the closure of subdomain i (coarse term of the tangent);
 // Y_i is stored column by column (Y[k * nc + c]), so the lanes read along c.
+// The closure values of v are gathered into LDS once per block, so that the
+// dot products stream Y_i alone, four loads per lane in flight.
 // Grid (nsub, Q): one wavefront per coarse function, spread over Q blocks.
 __global__ void __launch_bounds__(NLS_BLOCK)
 k_coarse_ty(DevCoarse C, const double* __restrict__ v) {
+    extern __shared__ double sv[];
     const int i = blockIdx.x;
     const int cb = C.off_c[i], nc = C.off_c[i + 1] - cb;
     const int k0 = C.off_k[i], nk = C.off_k[i + 1] - k0;
     const double* y = C.ybuf + C.off_phi[i];
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) sv[c] = v[C.cnode[cb + c]];
+    __syncthreads();
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int k = wv + nw * blockIdx.y; k < nk; k += nw * gridDim.y) {
-        double acc = 0.0;
-        for (int c = lane; c < nc; c += 64) acc += y[(int64_t)k * nc + c] * v[C.cnode[cb + c]];
-        acc = wave_sum(acc);
+        const double* yk = y + (int64_t)k * nc;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int c = lane;
+        for (; c + 192 < nc; c += 256) {
+            a0 += yk[c] * sv[c];
+            a1 += yk[c + 64] * sv[c + 64];
+            a2 += yk[c + 128] * sv[c + 128];
+            a3 += yk[c + 192] * sv[c + 192];
+        }
+        for (; c < nc; c += 64) a0 += yk[c] * sv[c];
+        const double acc = wave_sum((a0 + a1) + (a2 + a3));
         if (lane == 0) C.gblk[k0 + k] = acc;
     }
 }
@@ -2725,12 +2738,14 @@ hipError_t launch_coarse_galerkin(const DevMesh& M, const DevCoarse& C, const do
     return hipGetLastError();
 }
 
-hipError_t launch_coarse_ty(const DevCoarse& C, const double* v, hipStream_t s) {
+hipError_t launch_coarse_ty(const DevCoarse& C, const double* v, int lds_bytes, hipStream_t s) {
     // up to four blocks per subdomain when there are fewer subdomains than CUs
     const dim3 grid(C.nsub, C.nsub >= 256 ? 1 : (C.nsub >= 128 ? 2 : 4));
-    k_coarse_ty<<<grid, NLS_BLOCK, 0, s>>>(C, v);
+    k_coarse_ty<<<grid, NLS_BLOCK, lds_bytes, s>>>(C, v);
     return hipGetLastError();
 }
+
+hipError_t prepare_coarse_ty(int lds_bytes) { return set_lds(k_coarse_ty, lds_bytes); }
 
 hipError_t launch_coarse_assemble(const DevCoarse& C, int with_matrix, hipStream_t s) {
     k_coarse_assemble<<<1, NLS_BLOCK, 0, s>>>(C, with_matrix);

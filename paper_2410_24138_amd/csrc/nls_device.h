@@ -156,7 +156,10 @@ hipError_t launch_coarse_q(const DevMesh& M, const DevCoarse& C, const double* w
                            const double* v, int mode, int lds_bytes, hipStream_t s);
 hipError_t launch_coarse_galerkin(const DevMesh& M, const DevCoarse& C, const double* w,
                                   int with_y, hipStream_t s);
-hipError_t launch_coarse_ty(const DevCoarse& C, const double* v, hipStream_t s);
+// lds_bytes: 8 bytes per closure node of the largest subdomain
+hipError_t launch_coarse_ty(const DevCoarse& C, const double* v, int lds_bytes, hipStream_t s);
+// sets the kernel's LDS limit (outside any stream capture)
+hipError_t prepare_coarse_ty(int lds_bytes);
 hipError_t launch_coarse_assemble(const DevCoarse& C, int with_matrix, hipStream_t s);
 // the right-hand side part of launch_coarse_assemble, spread over the grid
 hipError_t launch_coarse_gather(const DevCoarse& C, hipStream_t s);
