@@ -52,8 +52,8 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per dispatch measured with rocprofv3 FETCH_SIZE/WRITE_SIZE (two
 # passes, calibrated against a 256 MiB copy; profiles/hbm_traffic_*.md), valid
 # only for the kernel source they were taken with.
-MEASURED_TRAFFIC = {"kernels_sha1": "cab0b84f8a46e890e8fa8c8ed6552ca7001dc7ca",
-                    "bytes": {"k_local_newton": 977656090, "k_local_factor": 433445522, "k_tangent_prep": 1199041545, "k_tangent_gemv": 280757753, "k_coarse_galerkin": 204273833, "k_coarse_lu": 1399125, "k_coarse_inverse": 12186814, "k_coarse_apply_inverse": 4093713, "k_mdot_partial": 25619679, "k_maxpy": 48708400, "k_prolong": 27170183, "k_coarse_ty": 20666187}}
+MEASURED_TRAFFIC = {"kernels_sha1": "591e2d84872ea09197d973c5b24dda6e6a429715",
+                    "bytes": {"k_local_newton": 977729708, "k_local_factor": 433234534, "k_tangent_prep": 1199369532, "k_tangent_gemv": 280768814, "k_coarse_galerkin": 204335987, "k_coarse_lu": 1399538, "k_coarse_inverse": 12186836, "k_coarse_apply_inverse": 4089653, "k_mdot_partial": 25635900, "k_maxpy": 48708555, "k_prolong": 27171215, "k_coarse_ty": 20655898}}
 
 
 def _factor_bytes(case, elem_bytes):
