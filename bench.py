@@ -489,7 +489,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the solver runs on a single MI355X; "
-              "multi-GPU sharding is not part of this build", file=sys.stderr)
+              "sharding the subdomains over several GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
     import torch
     import synth
