@@ -863,8 +863,9 @@ __device__ __forceinline__ int band_lu_auto(int n, int kl, int ku, const int* __
 // ----------------------------------------------------------------------------
 // Band triangular solves with the factors of band_lu, executed by ONE
 // wavefront (threads 0..63), right-hand side b in LDS (FP64).  NPL values per
-// lane cover bands up to 64*NPL.  The factor columns of S steps are fetched
-// ahead into registers so that HBM latency is paid once per chunk.
+// lane cover bands up to 64*NPL.  The factor columns are read in chunks of S
+// steps, and the next chunk's loads are issued before the current chunk's
+// steps run, so their HBM latency overlaps those steps.
 // ----------------------------------------------------------------------------
 template <typename T, int NPL>
 __device__ __forceinline__ void band_solve_wave(int n, int kl, int ku, const T* __restrict__ Uf,
@@ -873,71 +874,99 @@ __device__ __forceinline__ void band_solve_wave(int n, int kl, int ku, const T* 
     constexpr int S = 8;
     const int lane = threadIdx.x & 63;
     const int ldu = kl + ku + 1, ldl = kl > 1 ? kl : 1;
-    for (int k0 = 0; k0 < (backward_only ? 0 : n); k0 += S) {
-        double lv[S][NPL];
-        int pv[S];
+    if (!backward_only && n > 0) {
+        T ln[S][NPL];  // columns of L and pivots of the next chunk, as loaded
+        int pn[S];
+        auto fetch_l = [&](int k0) {
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const int k = k0 + s;
-            const int lim = (k < n) ? min(kl, n - 1 - k) : 0;
-            pv[s] = (k < n) ? piv[k] : k;
+            for (int s = 0; s < S; ++s) {
+                const int k = k0 + s;
+                const int lim = (k < n) ? min(kl, n - 1 - k) : 0;
+                pn[s] = (k < n) ? piv[k] : k;
 #pragma unroll
-            for (int q = 0; q < NPL; ++q) {
-                const int j = lane + 64 * q;
-                lv[s][q] = (j < lim) ? (double)Lf[(size_t)k * ldl + j] : 0.0;
+                for (int q = 0; q < NPL; ++q) {
+                    const int j = lane + 64 * q;
+                    ln[s][q] = (j < lim) ? Lf[(size_t)k * ldl + j] : T(0);
+                }
             }
-        }
+        };
+        fetch_l(0);
+        for (int k0 = 0; k0 < n; k0 += S) {
+            double lv[S][NPL];
+            int pv[S];
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const int k = k0 + s;
-            if (k < n) {
-                if (pv[s] != k) {
-                    if (lane == 0) {
-                        const double t = b[k];
-                        b[k] = b[pv[s]];
-                        b[pv[s]] = t;
+            for (int s = 0; s < S; ++s) {
+                pv[s] = pn[s];
+#pragma unroll
+                for (int q = 0; q < NPL; ++q) lv[s][q] = (double)ln[s][q];
+            }
+            if (k0 + S < n) fetch_l(k0 + S);
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const int k = k0 + s;
+                if (k < n) {
+                    if (pv[s] != k) {
+                        if (lane == 0) {
+                            const double t = b[k];
+                            b[k] = b[pv[s]];
+                            b[pv[s]] = t;
+                        }
+                        wave_sync();
+                    }
+                    const double bk = b[k];
+                    const int lim = min(kl, n - 1 - k);
+#pragma unroll
+                    for (int q = 0; q < NPL; ++q) {
+                        const int j = lane + 64 * q;
+                        if (j < lim) b[k + 1 + j] -= lv[s][q] * bk;
                     }
                     wave_sync();
                 }
-                const double bk = b[k];
-                const int lim = min(kl, n - 1 - k);
-#pragma unroll
-                for (int q = 0; q < NPL; ++q) {
-                    const int j = lane + 64 * q;
-                    if (j < lim) b[k + 1 + j] -= lv[s][q] * bk;
-                }
-                wave_sync();
             }
         }
     }
-    for (int k0 = n - 1; k0 >= 0; k0 -= S) {
-        double uv[S][NPL];
-        double dg[S];
+    if (n > 0) {
+        T un[S][NPL];  // columns of U (above the diagonal) of the next chunk
+        T dn[S];       // and their diagonal entries, as loaded
+        auto fetch_u = [&](int k0) {
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const int k = k0 - s;
-            const int lim = (k >= 0) ? min(kl + ku, k) : 0;
-            dg[s] = (k >= 0) ? (double)Uf[(size_t)k * ldu] : 1.0;
-#pragma unroll
-            for (int q = 0; q < NPL; ++q) {
-                const int j = lane + 64 * q;
-                uv[s][q] = (j < lim) ? (double)Uf[(size_t)k * ldu + 1 + j] : 0.0;
-            }
-        }
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const int k = k0 - s;
-            if (k >= 0) {
-                if (lane == 0) b[k] = b[k] / dg[s];
-                wave_sync();
-                const double bk = b[k];
-                const int lim = min(kl + ku, k);
+            for (int s = 0; s < S; ++s) {
+                const int k = k0 - s;
+                const int lim = (k >= 0) ? min(kl + ku, k) : 0;
+                dn[s] = (k >= 0) ? Uf[(size_t)k * ldu] : T(1);
 #pragma unroll
                 for (int q = 0; q < NPL; ++q) {
                     const int j = lane + 64 * q;
-                    if (j < lim) b[k - 1 - j] -= uv[s][q] * bk;
+                    un[s][q] = (j < lim) ? Uf[(size_t)k * ldu + 1 + j] : T(0);
                 }
-                wave_sync();
+            }
+        };
+        fetch_u(n - 1);
+        for (int k0 = n - 1; k0 >= 0; k0 -= S) {
+            double uv[S][NPL];
+            double dg[S];
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                dg[s] = (double)dn[s];
+#pragma unroll
+                for (int q = 0; q < NPL; ++q) uv[s][q] = (double)un[s][q];
+            }
+            if (k0 - S >= 0) fetch_u(k0 - S);
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                const int k = k0 - s;
+                if (k >= 0) {
+                    if (lane == 0) b[k] = b[k] / dg[s];
+                    wave_sync();
+                    const double bk = b[k];
+                    const int lim = min(kl + ku, k);
+#pragma unroll
+                    for (int q = 0; q < NPL; ++q) {
+                        const int j = lane + 64 * q;
+                        if (j < lim) b[k - 1 - j] -= uv[s][q] * bk;
+                    }
+                    wave_sync();
+                }
             }
         }
     }
