@@ -52,8 +52,8 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per dispatch measured with rocprofv3 FETCH_SIZE/WRITE_SIZE (two
 # passes, calibrated against a 256 MiB copy; profiles/hbm_traffic_*.md), valid
 # only for the kernel source they were taken with.
-MEASURED_TRAFFIC = {"kernels_sha1": "591e2d84872ea09197d973c5b24dda6e6a429715",
-                    "bytes": {"k_local_newton": 977729708, "k_local_factor": 433234534, "k_tangent_prep": 1199369532, "k_tangent_gemv": 280768814, "k_coarse_galerkin": 204335987, "k_coarse_lu": 1399538, "k_coarse_inverse": 12186836, "k_coarse_apply_inverse": 4089653, "k_mdot_partial": 25635900, "k_maxpy": 48708555, "k_prolong": 27171215, "k_coarse_ty": 20655898}}
+MEASURED_TRAFFIC = {"kernels_sha1": "531fac30889f3179436beae14e04348715a67aef",
+                    "bytes": {"k_local_newton": 978015173, "k_local_factor": 433627588, "k_tangent_prep": 1199103817, "k_tangent_gemv": 280767612, "k_coarse_galerkin": 204513264, "k_coarse_lu": 1407418, "k_coarse_inverse": 12186814, "k_coarse_apply_inverse": 4089618, "k_mdot_partial": 25635973, "k_maxpy": 48708400, "k_prolong": 27170842, "k_coarse_ty": 20655853}}
 
 
 def _factor_bytes(case, elem_bytes):
