@@ -944,10 +944,10 @@ __device__ __forceinline__ void band_solve_wave(int n, int kl, int ku, const T* 
         fetch_u(n - 1);
         for (int k0 = n - 1; k0 >= 0; k0 -= S) {
             double uv[S][NPL];
-            double dg[S];
+            double rdg[S];  // reciprocals of the diagonal, off the step chain
 #pragma unroll
             for (int s = 0; s < S; ++s) {
-                dg[s] = (double)dn[s];
+                rdg[s] = 1.0 / (double)dn[s];
 #pragma unroll
                 for (int q = 0; q < NPL; ++q) uv[s][q] = (double)un[s][q];
             }
@@ -956,9 +956,10 @@ __device__ __forceinline__ void band_solve_wave(int n, int kl, int ku, const T* 
             for (int s = 0; s < S; ++s) {
                 const int k = k0 - s;
                 if (k >= 0) {
-                    if (lane == 0) b[k] = b[k] / dg[s];
-                    wave_sync();
-                    const double bk = b[k];
+                    // every lane forms x_k itself; lane 0 stores it, and no
+                    // lane writes b[k] in this step otherwise
+                    const double bk = b[k] * rdg[s];
+                    if (lane == 0) b[k] = bk;
                     const int lim = min(kl + ku, k);
 #pragma unroll
                     for (int q = 0; q < NPL; ++q) {
