@@ -52,8 +52,8 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per dispatch measured with rocprofv3 FETCH_SIZE/WRITE_SIZE (two
 # passes, calibrated against a 256 MiB copy; profiles/hbm_traffic_*.md), valid
 # only for the kernel source they were taken with.
-MEASURED_TRAFFIC = {"kernels_sha1": "531fac30889f3179436beae14e04348715a67aef",
-                    "bytes": {"k_local_newton": 978015173, "k_local_factor": 433627588, "k_tangent_prep": 1199103817, "k_tangent_gemv": 280767612, "k_coarse_galerkin": 204513264, "k_coarse_lu": 1407418, "k_coarse_inverse": 12186814, "k_coarse_apply_inverse": 4089618, "k_mdot_partial": 25635973, "k_maxpy": 48708400, "k_prolong": 27170842, "k_coarse_ty": 20655853}}
+MEASURED_TRAFFIC = {"kernels_sha1": "6842cb53b96de61b447c25d205f453e7870d657d",
+                    "bytes": {"k_local_newton": 979624183, "k_local_factor": 434428395, "k_tangent_prep": 1199293573, "k_tangent_gemv": 280761828, "k_coarse_galerkin": 211827691, "k_coarse_lu": 1406956, "k_coarse_inverse": 12186622, "k_coarse_apply_inverse": 4089522, "k_mdot_partial": 25635868, "k_maxpy": 48707194, "k_prolong": 27170961, "k_coarse_ty": 20655149}}
 
 
 def _factor_bytes(case, elem_bytes):
