@@ -31,14 +31,18 @@ Readings where the paper is silent (all are stated again where used):
     ||F_x(u_k)|| <= rtol ||F_x(u_0)||; GMRES restarted every 50 iterations,
     x_0 = 0, modified Gram-Schmidt, Givens rotations.
 
-Dense LU with partial pivoting (LAPACK getrf through SciPy) is the linear
-solver of every step; GDSW components are ordered by their smallest node
-index.  FP64 throughout.  Test infrastructure only.
+LU with partial pivoting is the linear solver of every step: in band form
+(LAPACK gbtrf/gbtrs through SciPy) for the local Jacobians, whose nonzeros
+lie in a band under the ascending node order, dense (LAPACK getrf) for the
+coarse matrix and the interior blocks of the coarse basis.  GDSW components
+are ordered by their smallest node index.  FP64 throughout.  Test
+infrastructure only.
 """
 from __future__ import annotations
 
 import numpy as np
 import scipy.linalg as sla
+import scipy.linalg.lapack as lapack
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
@@ -51,6 +55,36 @@ class LocalFailure(RuntimeError):
 
 def _stop_tol(rho0, b_inf, n, rtol, eta):
     return max(rtol * rho0, eta * b_inf * np.sqrt(n))
+
+
+def band_lu_factor(J):
+    """LU with partial pivoting of a square matrix whose nonzeros lie within
+    kl sub- and ku super-diagonals (LAPACK gbtrf; the row interchanges widen
+    the upper band of U to kl + ku, which the storage leaves room for).
+    Mathematically the same factorisation as dense getrf.  Returns the
+    factors, pivots and band widths for band_lu_solve."""
+    J = np.asarray(J, dtype=np.float64)
+    n = J.shape[0]
+    i, j = np.nonzero(J)
+    kl = int(max(np.max(i - j), 0)) if len(i) else 0
+    ku = int(max(np.max(j - i), 0)) if len(i) else 0
+    ab = np.zeros((2 * kl + ku + 1, n))
+    ab[kl + ku + i - j, j] = J[i, j]
+    lub, piv, info = lapack.dgbtrf(ab, kl, ku)
+    if info > 0:
+        raise LocalFailure(f"zero pivot at column {info - 1}")
+    return lub, piv, kl, ku
+
+
+def band_lu_solve(fac, r):
+    """Solve with the factors of band_lu_factor (LAPACK gbtrs); r is a
+    vector or an n x k array of right-hand sides."""
+    lub, piv, kl, ku = fac
+    r = np.asarray(r, dtype=np.float64)
+    x, info = lapack.dgbtrs(lub, kl, ku, r.reshape(len(r), -1), piv)
+    if info != 0:
+        raise ValueError(f"gbtrs: illegal argument {-info}")
+    return x.reshape(r.shape)
 
 
 class Schwarz:
@@ -246,7 +280,7 @@ class Schwarz:
                 raise LocalFailure(f"subdomain {i}: no convergence in "
                                    f"{its} Newton steps")
             J, _ = self.local_jacobian(i, x, tr)
-            d = sla.lu_solve(sla.lu_factor(J, check_finite=False), r)
+            d = band_lu_solve(band_lu_factor(J), r)
             x = x - d
             its += 1
             dprev = float(np.max(np.abs(d)))
@@ -257,7 +291,7 @@ class Schwarz:
     def _finish(self, i, xu, tr, out, rho_plain, start):
         x, its, hist = out
         J, B = self.local_jacobian(i, x, tr)
-        return {"x": x, "T": xu - x, "lu": sla.lu_factor(J, check_finite=False),
+        return {"x": x, "T": xu - x, "lu": band_lu_factor(J),
                 "B": B, "its": its, "rho_plain": rho_plain, "hist": hist,
                 "start": start}
 
@@ -514,7 +548,7 @@ class Schwarz:
         z = v - q if self.coupling == "hybrid" else v
         y = z.copy()
         for s, sol in zip(self.subs, st["sols"]):
-            zz = sla.lu_solve(sol["lu"], sol["B"] @ z[s["Gd"]])
+            zz = band_lu_solve(sol["lu"], sol["B"] @ z[s["Gd"]])
             y[s["owned"]] += zz[s["owned_loc"]]
         if q is not None:
             y += q
@@ -539,7 +573,7 @@ class Schwarz:
             ui = st["u"].copy()
             ui[s["Vd"]] = sol["x"]
             w = (P.jacobian(ui) @ z)[s["Vd"]]
-            zz = sla.lu_solve(sol["lu"], w)
+            zz = band_lu_solve(sol["lu"], w)
             y[s["owned"]] += zz[s["owned_loc"]]
         if q is not None:
             y += q

@@ -252,3 +252,42 @@ def test_rgdsw_elasticity_reproduces_rigid_modes_away_from_clamp():
             np.testing.assert_allclose(phi[dofs], m[dofs], atol=1e-12)
             checked += 1
     assert checked >= 2 * 3
+
+
+def test_traction_and_body_loads_are_consistent():
+    """The nodal forces of the elasticity inputs against the exact integrals
+    they stand for.  For any v in the Q1 space, sum_a f_a v(x_a) =
+    int t v ds (traction on x = lx) and int b v dA (volume force), because
+    f_a = int t phi_a ds and f_a = int b phi_a dA.  On the edge the traces
+    1 and y, in the body 1, x, y and xy, are all in that space; their exact
+    integrals are closed forms.  A lumping that put the load at the wrong
+    nodes, double-counted a segment or dropped an end would fail the first
+    moments even where the totals agree."""
+    lx, ly, t = 2.0, 1.0, (0.7, -3.0)
+    case = synth.elasticity_case(10, 6, lx, ly, [0, 5, 10], [0, 3, 6], 1, traction=t)
+    f, xy = case["nodal_force"], case["xy"]
+    fx, fy = f[0::2], f[1::2]
+    x, y = xy[:, 0], xy[:, 1]
+    assert np.all(f.reshape(-1, 2)[~np.isclose(x, lx)] == 0.0)
+    assert abs(fx.sum() - t[0] * ly) <= 1e-14
+    assert abs(fy.sum() - t[1] * ly) <= 1e-14
+    assert abs((fx * y).sum() - t[0] * ly ** 2 / 2) <= 1e-14
+    assert abs((fy * y).sum() - t[1] * ly ** 2 / 2) <= 1e-14
+    # every interior edge node carries t h, the two ends t h / 2
+    right = np.isclose(x, lx)
+    h = ly / 6
+    ends = right & (np.isclose(y, 0.0) | np.isclose(y, ly))
+    np.testing.assert_allclose(fy[right & ~ends], t[1] * h, rtol=1e-14)
+    np.testing.assert_allclose(fy[ends], t[1] * h / 2, rtol=1e-14)
+    b = (0.4, -2.5)
+    beam = synth.elasticity_case(10, 4, 5.0, 1.0, [0, 10], [0, 4], 1, traction=(0.0, 0.0),
+                                 body=b, clamp_right=True)
+    f, xy = beam["nodal_force"], beam["xy"]
+    x, y = xy[:, 0], xy[:, 1]
+    L, H = 5.0, 1.0
+    for c in (0, 1):
+        fc = f[c::2]
+        assert abs(fc.sum() - b[c] * L * H) <= 1e-13
+        assert abs((fc * x).sum() - b[c] * L ** 2 * H / 2) <= 1e-12
+        assert abs((fc * y).sum() - b[c] * L * H ** 2 / 2) <= 1e-13
+        assert abs((fc * x * y).sum() - b[c] * L ** 2 * H ** 2 / 4) <= 1e-12

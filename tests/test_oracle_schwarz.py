@@ -188,6 +188,34 @@ def test_gmres_matches_dense_solve():
     np.testing.assert_allclose(x, xd, rtol=0, atol=1e-10 * np.abs(xd).max())
 
 
+def test_band_lu_matches_lapack_dense_solve():
+    """The oracle's band LU (gbtrf/gbtrs) against numpy.linalg.solve (dense
+    LAPACK gesv): on a random banded matrix that needs row interchanges and
+    on a real local Jacobian J_ii (several right-hand sides)."""
+    from oracle.schwarz import band_lu_factor, band_lu_solve
+    rng = np.random.default_rng(7)
+    n, kl, ku = 60, 4, 3
+    A = np.zeros((n, n))
+    for k in range(-kl, ku + 1):
+        A += np.diag(rng.normal(size=n - abs(k)), k)
+    A[np.arange(n), np.arange(n)] *= 1e-3   # small diagonal: pivoting needed
+    b = rng.normal(size=(n, 3))
+    fac = band_lu_factor(A)
+    assert fac[2] == kl and fac[3] == ku
+    np.testing.assert_allclose(band_lu_solve(fac, b), np.linalg.solve(A, b),
+                               rtol=0, atol=1e-12 * np.abs(np.linalg.solve(A, b)).max())
+    P, S = _schwarz("one_level", n=20, boxes=2, overlap=2, forcing_seed=2)
+    ug, _ = global_newton(P)
+    s = S.subs[0]
+    J, B = S.local_jacobian(0, 3.0 * ug[s["Vd"]], ug[s["Gd"]])
+    rhs = B @ rng.normal(size=(B.shape[1], 2))
+    x = band_lu_solve(band_lu_factor(J), rhs)
+    ref = np.linalg.solve(J, rhs)
+    np.testing.assert_allclose(x, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+    np.testing.assert_allclose(band_lu_solve(band_lu_factor(J), rhs[:, 0]), ref[:, 0],
+                               rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
 def test_local_newton_quadratic():
     P, S = _schwarz("one_level", n=16, boxes=2, overlap=2, forcing_seed=2)
     ug, _ = global_newton(P)
@@ -226,9 +254,19 @@ def test_rgdsw_size_weights_and_constants():
         el = np.nonzero(S.part == i)[0]
         nodes = np.unique(P.conn[el])
         np.testing.assert_allclose(tot[nodes], 1.0, atol=1e-12)
-    # an edge ending at the Dirichlet boundary: weights decay towards it
+    # an edge ending at the Dirichlet boundary: the Dirichlet end (0.25, 0)
+    # enters the inverse-distance sum as a zero-valued ancestor, so at
+    # (0.25, 1/24), with the crosspoint (0.25, 0.25) at distance 5/24 and the
+    # Dirichlet node at 1/24, the only function has the weight
+    # (24/5) / (24/5 + 24) = 1/6
     g3 = int(np.nonzero(np.isclose(xy[:, 0], 0.25) & np.isclose(xy[:, 1], 1 / 24))[0][0])
-    assert 0.0 < tot[g3] < 0.2
+    w3 = Phi[g3][Phi[g3] != 0]
+    assert len(w3) == 1
+    assert abs(w3[0] - 1.0 / 6.0) <= 1e-14
+    # one node further up, distances 4/24 (crosspoint) and 2/24 (Dirichlet):
+    # d_D / (d_D + d_v) = (2/24) / (6/24) = 1/3
+    g4 = int(np.nonzero(np.isclose(xy[:, 0], 0.25) & np.isclose(xy[:, 1], 2 / 24))[0][0])
+    assert abs(tot[g4] - 1.0 / 3.0) <= 1e-14
 
 
 def test_rgdsw_fixed_point_and_linear_coarse():
