@@ -35,18 +35,19 @@ METRIC = "subdomain Newton solves/s; time-to-1e-8 per global solve, plain vs cho
 FORMS = {
     "plain": ("fp64", ()),                 # FP64, GMRES step by step from the host
     "fp64_graph": ("fp64", ("graph",)),    # FP64, graph-replayed GMRES blocks
-    "fp64_graph_chord": ("fp64", ("graph", "chord")),
-    "fp64_graph_chord_luapply": ("fp64", ("graph", "chord", "luapply")),
-    "fp64_tuned": ("fp64", ("graph", "chord", "autotune", "overlap")),
+    # graphs, the coarse Newton solve beside the local solves, autotuned
+    # LU variants and coarse apply
+    "fp64_tuned": ("fp64", ("graph", "autotune", "overlap")),
+    # as fp64_tuned with chord steps for the coarse correction (eq. 9): T_0
+    # agrees with Newton's to the coarse stopping tolerance only
+    "fp64_tuned_chord": ("fp64", ("graph", "chord", "autotune", "overlap")),
     # as fp64_tuned with the RGDSW coarse space (the paper's choice)
-    "fp64_tuned_rgdsw": ("fp64", ("graph", "chord", "autotune", "overlap", "rgdsw")),
-    # every pattern: graphs, chord coarse steps, the coarse Newton solve
-    # beside the local solves, and the autotuner choosing
-    # LU variants, the coarse apply and the local precision (FP32 LU with FP64
-    # refinement, or FP64) by measured time
-    "chosen": ("fp32_ir", ("graph", "chord", "autotune", "overlap")),
+    "fp64_tuned_rgdsw": ("fp64", ("graph", "autotune", "overlap", "rgdsw")),
+    # every pattern on a mixed-precision handle: the autotuner chooses the
+    # local precision (FP32 LU with FP64 refinement, or FP64) by measured time
+    "chosen": ("fp32_ir", ("graph", "autotune", "overlap")),
     # FP32 local LU + FP64 refinement kept throughout
-    "fp32_ir": ("fp32_ir", ("graph", "chord", "overlap")),
+    "fp32_ir": ("fp32_ir", ("graph", "overlap")),
 }
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per dispatch measured with rocprofv3 FETCH_SIZE/WRITE_SIZE (two
@@ -95,18 +96,48 @@ def cpu_baseline(case, n_sample=256, passes=2):
                       f"dense LAPACK LU, {dt:.1f} s"}
 
 
-def run_form(case, golden, form, steps, warmup, device):
-    import numpy as np
-    import torch
+def make_solver(case, form, device_index=0, **kw):
+    """The solver handle of a benchmark form (the flag sets of FORMS)."""
     from paper_2410_24138_amd import Solver, nls
     prec, extra = FORMS[form]
-    s = Solver(case, precision=prec, device=device.index or 0,
-               coarse="rgdsw" if "rgdsw" in extra else "gdsw",
-               flags=nls.FLAG_PROFILE | (nls.FLAG_GRAPH if "graph" in extra else 0)
-               | (nls.FLAG_COARSE_CHORD if "chord" in extra else 0)
-               | (nls.FLAG_COARSE_LU_APPLY if "luapply" in extra else 0)
-               | (nls.FLAG_AUTOTUNE if "autotune" in extra else 0)
-               | (nls.FLAG_OVERLAP if "overlap" in extra else 0))
+    return Solver(case, precision=prec, device=device_index,
+                  coarse="rgdsw" if "rgdsw" in extra else "gdsw",
+                  flags=nls.FLAG_PROFILE | (nls.FLAG_GRAPH if "graph" in extra else 0)
+                  | (nls.FLAG_COARSE_CHORD if "chord" in extra else 0)
+                  | (nls.FLAG_COARSE_LU_APPLY if "luapply" in extra else 0)
+                  | (nls.FLAG_AUTOTUNE if "autotune" in extra else 0)
+                  | (nls.FLAG_OVERLAP if "overlap" in extra else 0), **kw)
+
+
+def golden_for(form, name="diffusion_512x512_16x16_ov2_gdsw"):
+    """The stored oracle trace (json) and full vectors (npz: the oracle's
+    solution at the same settings and coarse space, and the brute-force
+    global Newton solution u*) that a form is checked against."""
+    import numpy as np
+    gname = name.replace("_gdsw", "_rgdsw") if "rgdsw" in FORMS[form][1] else name
+    gdir = os.path.join(ROOT, "tests", "golden")
+    golden = json.load(open(os.path.join(gdir, gname + ".json")))
+    with np.load(os.path.join(gdir, gname + ".npz")) as z:
+        u_ref = z["u"].copy()
+    with np.load(os.path.join(gdir, name + ".npz")) as z:
+        u_star = z["u_global_newton"].copy()
+    return golden, u_ref, u_star
+
+
+def parity_bar(res, form):
+    """Relative error bar against the same-settings oracle: 1e-10 when the
+    local solves ran in binary64 (all-FP64 mode), 1e-8 after refinement of
+    binary32 local solves.  A chord coarse iteration is all-FP64 but agrees
+    with the oracle's Newton T_0 to the coarse stopping tolerance only, so
+    it does not meet the 1e-10 bar and is reported beside the headline."""
+    return 1e-10 if _local_fp64(res, form) else 1e-8
+
+
+def run_form(case, form, steps, warmup, device):
+    import numpy as np
+    import torch
+    golden, u_ref, u_star = golden_for(form, case["name"])
+    s = make_solver(case, form, device.index or 0)
     N = s.N
     for _ in range(warmup):
         u = torch.zeros(N, dtype=torch.float64, device=device)
@@ -117,14 +148,11 @@ def run_form(case, golden, form, steps, warmup, device):
     stats = [s.solve_(u) for u in us]
     torch.cuda.synchronize(device)
     wall = time.perf_counter() - t0
-    idx = np.array(golden["sample_nodes"])
-    gn = np.array(golden["u_global_newton_sample"])
-    ref = np.array(golden["u_sample"])
     errs, errs_or = [], []
     for u in us:
         un = u.cpu().numpy()
-        errs.append(float(np.abs(un[idx] - gn).max() / np.abs(gn).max()))
-        errs_or.append(float(np.abs(un[idx] - ref).max() / np.abs(ref).max()))
+        errs.append(float(np.linalg.norm(un - u_star) / np.linalg.norm(u_star)))
+        errs_or.append(float(np.abs(un - u_ref).max() / np.abs(u_ref).max()))
     solves = sum(st["local_solves"] for st in stats)
     out = {
         "ms_per_solve": 1e3 * wall / steps,
@@ -135,9 +163,13 @@ def run_form(case, golden, form, steps, warmup, device):
         "inner_its_total": stats[-1]["inner_its_total"],
         "coarse_its_total": stats[-1]["coarse_its_total"],
         "phase_ms": {k: round(sum(st[k] for st in stats) / steps, 3)
-                     for k in ("ms_inner", "ms_coarse", "ms_gmres", "ms_other")},
+                     for k in ("ms_inner", "ms_coarse", "ms_gmres", "ms_other", "ms_overlap")},
+        # ||u - u*||_2 / ||u*||_2 against the global Newton solution
         "rel_err_vs_global_newton": max(errs),
+        # max_g |u_g - u_ref,g| / max |u_ref| against the oracle's solution
+        # at the same settings and coarse space (full vectors)
         "rel_err_vs_oracle_same_settings": max(errs_or),
+        "oracle_trace": golden["workload"],
         "outer_its_match_oracle": all(st["outer_its"] == golden["outer"] for st in stats),
         "converged": all(st["converged"] for st in stats),
         "kernels": {
@@ -149,6 +181,10 @@ def run_form(case, golden, form, steps, warmup, device):
         "inner_its_steps": sum(st["inner_its_total"] for st in stats),
         "tuning": s.tuning(),
     }
+    out["parity_bar"] = parity_bar(out, form)
+    out["meets_parity"] = bool(out["converged"] and out["outer_its_match_oracle"]
+                               and out["rel_err_vs_oracle_same_settings"] <= out["parity_bar"]
+                               and out["rel_err_vs_global_newton"] <= 1e-8)
     s.close()
     return out
 
@@ -476,7 +512,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--forms", default="plain,fp64_tuned,chosen,fp32_ir,fp64_tuned_rgdsw")
+    ap.add_argument("--forms",
+                    default="plain,fp64_tuned,chosen,fp32_ir,fp64_tuned_chord,fp64_tuned_rgdsw")
     ap.add_argument("--workload", default="diffusion512",
                     choices=["diffusion512", "batch", "learned", "elasticity", "beam"])
     ap.add_argument("--amp", type=float, default=10.0,
@@ -524,17 +561,17 @@ def main():
         print(json.dumps(res), flush=True)
         return
     case = synth.config2()
-    golden = json.load(open(os.path.join(ROOT, "tests", "golden", case["name"] + ".json")))
     forms = [f for f in args.forms.split(",") if f]
     res = {}
     for f in forms:
-        res[f] = run_form(case, golden, f, args.steps, args.warmup, device)
+        res[f] = run_form(case, f, args.steps, args.warmup, device)
         print(json.dumps({"form": f, **{k: v for k, v in res[f].items()
                                         if k not in ("kernels",)}}), file=sys.stderr, flush=True)
-    # the headline is the workload as named (GDSW vertex+edge coarse space);
-    # RGDSW forms are reported beside it
-    ok = {f: r for f, r in res.items() if r["converged"] and r["rel_err_vs_global_newton"] <= 1e-8
-          and "rgdsw" not in FORMS[f][1]}
+    # the headline is the workload as named (GDSW vertex+edge coarse space),
+    # among the forms that meet the parity bar (same outer iteration count as
+    # the oracle, its solution to 1e-10 in binary64 or 1e-8 in mixed mode,
+    # u* to 1e-8); RGDSW forms are reported beside it
+    ok = {f: r for f, r in res.items() if r["meets_parity"] and "rgdsw" not in FORMS[f][1]}
     best = min(ok, key=lambda f: ok[f]["ms_per_solve"]) if ok else forms[0]
     r = res[best]
     line = {

@@ -105,9 +105,12 @@ typedef struct nls_options {
 #define NLS_FLAG_GRAPH    2
 /* options.flags: the coarse iteration for T_0 (eq. (9)) takes chord steps
    with the last factorisation of A0 (from the previous evaluation or its
-   own first step), refactoring when the residual fails to halve; T_0 is
-   the same up to the coarse stopping rule.  A0 and its LU at the converged
-   coarse state are formed in every mode (exact tangent, eq. (12)). */
+   own first step), refactoring when the residual fails to halve.  This is
+   a different iteration from Newton's: both stop once ||G|| meets the
+   coarse stopping rule, so their T_0 agree to that tolerance, not to the
+   rounding level (on the 512 x 512 workload the outer solutions differ by
+   about 2e-10 relative).  A0 and its LU at the converged coarse state are
+   formed in every mode (exact tangent, eq. (12)). */
 #define NLS_FLAG_COARSE_CHORD 4
 /* options.flags: apply A0^{-1} in the tangent by band LU solves instead of
    an explicit inverse formed once per evaluation. */
@@ -147,11 +150,11 @@ typedef struct nls_stats {
     int       failed_subdomain;     /* -1, or the subdomain whose Newton failed */
     double    res0;                 /* ||F_x(u_0)||_2 */
     double    res_final;            /* ||F_x(u_final)||_2 */
-    double    ms_inner;             /* phase times (device-synchronised wall) */
-    double    ms_coarse;
-    double    ms_gmres;
-    double    ms_other;
-    double    ms_total;
+    double    ms_inner;             /* phase times (device-synchronised wall),  */
+    double    ms_coarse;            /*   the paper's schema: inner + coarse +    */
+    double    ms_gmres;             /*   gmres + other = total; coarse work run  */
+    double    ms_other;             /*   beside the local solves (NLS_FLAG_      */
+    double    ms_total;             /*   OVERLAP) is in ms_overlap, not coarse   */
     /* with NLS_FLAG_PROFILE: event-timed launches of the fused local Newton
        kernel and of the local tangent kernel */
     int       n_local_launches;
@@ -163,6 +166,8 @@ typedef struct nls_stats {
        or whose Newton iteration from it failed (then started from R_i u) */
     int64_t   guess_used;
     int64_t   guess_fallback;
+    /* coarse Newton time that ran beside the local solves (inside ms_inner) */
+    double    ms_overlap;
 } nls_stats;
 
 typedef struct nls_handle nls_handle;

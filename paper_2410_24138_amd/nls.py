@@ -97,6 +97,7 @@ class Stats(ctypes.Structure):
         ("n_local_launches", ctypes.c_int), ("ms_local_kernel", ctypes.c_double),
         ("n_tangent_launches", ctypes.c_int), ("ms_tangent_kernel", ctypes.c_double),
         ("guess_used", ctypes.c_int64), ("guess_fallback", ctypes.c_int64),
+        ("ms_overlap", ctypes.c_double),
     ]
 
     def as_dict(self):

@@ -3,13 +3,19 @@
 Calls only the FP64 CPU oracle and the seeded input generator.  Output:
 tests/golden/<workload>.json with the outer Newton trace (outer, GMRES and
 inner iteration counts, residual norms) and the solution at a fixed sample
-of nodes, plus the brute-force global Newton solution at the same nodes.
+of nodes, plus the brute-force global Newton solution at the same nodes;
+tests/golden/<workload>.npz with the full vectors: "u", the oracle's
+solution at the benchmark settings (outer rtol 1e-8, GMRES rtol 1e-6), and
+"u_global_newton", the brute-force global Newton solution.
 
     python tests/golden/make_golden.py diffusion_512x512_16x16_ov2_gdsw
 
+The RGDSW workload is the 512x512 problem with the RGDSW coarse space (its
+u_global_newton is the same discrete solution and is not stored again).
 The elasticity workload (10 load steps) stores the global Newton
 continuation solution of every step (plain definition of the result) and,
-with --schwarz, the oracle's outer Newton trace of every step.
+with --schwarz, the oracle's outer Newton trace of every step; the .npz
+holds the vectors of the last step.
 """
 import json
 import os
@@ -25,8 +31,9 @@ import synth  # noqa: E402
 from oracle import NHProblem, P1Problem, Schwarz, global_newton  # noqa: E402
 
 CASES = {
-    "diffusion_64x64_4x4_ov1": synth.config1,
-    "diffusion_512x512_16x16_ov2_gdsw": synth.config2,
+    "diffusion_64x64_4x4_ov1": (synth.config1, "gdsw"),
+    "diffusion_512x512_16x16_ov2_gdsw": (synth.config2, "gdsw"),
+    "diffusion_512x512_16x16_ov2_rgdsw": (synth.config2, "rgdsw"),
 }
 ELASTIC = {"neohooke_256x128_8x8_ov2_gdsw": synth.config3}
 N_STEPS = 10
@@ -67,28 +74,35 @@ def main_elastic(name, schwarz):
                         "coarse": st["coarse"], "converged": bool(st["converged"])})
         out["u_sample"] = u[sample].tolist()
         out["u_norm"] = float(np.linalg.norm(u))
+        np.savez(os.path.join(HERE, name + ".npz"), u=u, u_global_newton=ug)
     with open(os.path.join(HERE, name + ".json"), "w") as f:
         json.dump(out, f, indent=1)
     print(json.dumps({k: out[k] for k in out if k not in ("steps", "sample_dofs", "u_sample")}))
 
 
 def main(name):
-    case = CASES[name]()
+    make, coarse = CASES[name]
+    case = make()
     P = P1Problem(case)
     coupling = "additive" if case["two_level"] else "one_level"
     t0 = time.time()
-    S = Schwarz(P, coupling)
+    S = Schwarz(P, coupling, coarse=coarse)
     t_setup = time.time() - t0
     t0 = time.time()
     u, st = S.solve(rtol=1e-8, gmres_rtol=1e-6, gmres_restart=50,
                     gmres_maxit=1000)
     t_solve = time.time() - t0
     ug, gits = global_newton(P)
+    if coarse == "gdsw":
+        np.savez(os.path.join(HERE, name + ".npz"), u=u, u_global_newton=ug)
+    else:
+        np.savez(os.path.join(HERE, name + ".npz"), u=u)
     rng = np.random.default_rng(123)
     sample = np.sort(rng.choice(P.N, size=256, replace=False))
     out = {
         "workload": name,
         "coupling": coupling,
+        "coarse_space": coarse if case["two_level"] else "none",
         "settings": {"outer_rtol": 1e-8, "gmres_rtol": 1e-6,
                      "gmres_restart": 50, "gmres_maxit": 1000,
                      "inner_rtol": 1e-12, "inner_eta": 1e-10,

@@ -1,0 +1,107 @@
+"""Full-size parity of the benchmark workloads, in exactly the flag sets the
+benchmark times, against the full solution vectors the oracle wrote
+(tests/golden/*.npz, from tests/golden/make_golden.py):
+
+  * 512 x 512 P1 diffusion, 16 x 16 subdomains, overlap 2, two-level
+    additive coupling (eq. 10) with the GDSW coarse space, and with RGDSW
+    (option 2.2) against its own oracle run: every benchmark form.  The bar
+    is element-wise max|u - u_ref| <= 1e-10 max|u_ref| when every step runs
+    in binary64 with Newton's coarse iteration, 1e-8 after refinement of
+    binary32 LU solves or with chord steps for the coarse correction (a
+    different iteration, equal to Newton's to the coarse stopping
+    tolerance), the oracle's outer iteration count exactly, and
+    ||u - u*|| <= 1e-8 ||u*|| against the brute-force global Newton
+    solution u*;
+  * 64 x 64, 16 subdomains, one-level: the same bar;
+  * 256 x 128 Q1 Neo-Hooke, 10 load steps: outer counts of every step and
+    the final solution of the continuation.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import bench
+import synth
+from tests._lib import ensure_built
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+FORMS = ["plain", "fp64_tuned", "chosen", "fp32_ir", "fp64_tuned_chord", "fp64_tuned_rgdsw"]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    ensure_built()
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _check(u, st, rc, golden, u_ref, u_star, bar):
+    """Outer count, element-wise error against the oracle's solution at the
+    same settings, and the distance to u*: at most 1e-8, or, where the
+    oracle's own iterate at outer rtol 1e-8 is farther than that (the
+    64 x 64 one-level workload: 1.2e-8), the oracle's distance to within
+    1e-10."""
+    assert rc == 0 and st["converged"]
+    assert st["outer_its"] == golden["outer"], (st["outer_its"], golden["outer"])
+    err = np.abs(u - u_ref).max() / np.abs(u_ref).max()
+    assert err <= bar, f"max error {err:.3e} against the oracle > {bar:.0e}"
+    err_star = np.linalg.norm(u - u_star) / np.linalg.norm(u_star)
+    ref_star = golden["rel_err_vs_global_newton"]
+    assert err_star <= max(1e-8, ref_star + 1e-10), f"{err_star:.3e} against u*"
+    return err
+
+
+@pytest.mark.parametrize("form", FORMS)
+def test_config2_bench_form(form):
+    """The first solve of a handle (with the autotuner's trials where the
+    form tunes) and the second (tuned) solve, as in the benchmark's warm-up
+    and timed steps."""
+    case = synth.config2()
+    golden, u_ref, u_star = bench.golden_for(form, case["name"])
+    s = bench.make_solver(case, form, 0)
+    errs = []
+    for _ in range(2):
+        u, st, rc = s.solve()
+        bar = bench.parity_bar({"tuning": s.tuning()}, form)
+        if "chord" in bench.FORMS[form][1]:
+            bar = 1e-8  # Newton's T_0 to the coarse tolerance only (about 2e-10 here)
+        errs.append(_check(u.cpu().numpy(), st, rc, golden, u_ref, u_star, bar))
+    print(f"{form}: max rel error vs oracle {max(errs):.3e} "
+          f"(precision {s.tuning()['local_precision']})", flush=True)
+    s.close()
+
+
+def test_config1_full_vector():
+    case = synth.config1()
+    golden = json.load(open(os.path.join(HERE, "golden", case["name"] + ".json")))
+    with np.load(os.path.join(HERE, "golden", case["name"] + ".npz")) as z:
+        u_ref, u_star = z["u"].copy(), z["u_global_newton"].copy()
+    from paper_2410_24138_amd import Solver
+    s = Solver(case)
+    u, st, rc = s.solve()
+    _check(u.cpu().numpy(), st, rc, golden, u_ref, u_star, 1e-10)
+    assert st["inner_its_total"] == sum(golden["inner"])
+
+
+def test_config3_continuation_full_vector():
+    """The 10-step continuation: equal outer counts at every step and the
+    final solution against the oracle's continuation (same settings) and the
+    global Newton continuation solution."""
+    case = synth.config3()
+    golden = json.load(open(os.path.join(HERE, "golden", case["name"] + ".json")))
+    with np.load(os.path.join(HERE, "golden", case["name"] + ".npz")) as z:
+        u_ref, u_star = z["u"].copy(), z["u_global_newton"].copy()
+    from paper_2410_24138_amd import Solver
+    s = Solver(case, coupling="additive")
+    u, sts, rc = s.solve_load_steps(golden["n_steps"])
+    assert rc == 0 and all(st["converged"] for st in sts)
+    assert [st["outer_its"] for st in sts] == [st["outer"] for st in golden["steps"]]
+    un = u.cpu().numpy()
+    err = np.abs(un - u_ref).max() / np.abs(u_ref).max()
+    assert err <= 1e-10, f"{err:.3e}"
+    assert np.linalg.norm(un - u_star) <= 1e-8 * np.linalg.norm(u_star)

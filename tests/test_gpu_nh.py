@@ -123,30 +123,6 @@ def test_solve_additive(kw):
     assert np.linalg.norm(_np(uu) - u_ref) <= 1e-10 * np.linalg.norm(u_ref)
 
 
-def test_config3_load_continuation():
-    """256x128 Q1 cantilever, 8x8 seeded subdomains, overlap 2, GDSW, traction
-    ramped to (0,-4) in 10 load steps: the GPU continuation reaches the stored
-    global Newton continuation solution (plain definition of u*) to 1e-8 at
-    the sampled dofs; with the stored oracle trace, the outer iteration
-    counts of every step are equal."""
-    import json
-    import os
-    case = synth.config3()
-    golden = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)),
-                                         "golden", case["name"] + ".json")))
-    s = _solver(case, coupling="additive")
-    u, sts, rc = s.solve_load_steps(golden["n_steps"])
-    assert rc == 0 and all(st["converged"] for st in sts)
-    un = _np(u)
-    idx = np.array(golden["sample_dofs"])
-    ref = np.array(golden["steps"][-1]["u_global_newton_sample"])
-    assert np.abs(un[idx] - ref).max() <= 1e-8 * np.abs(ref).max()
-    tip = golden["steps"][-1]["tip"]
-    assert abs(un[golden["tip_dof"]] - tip) <= 1e-8 * abs(tip)
-    if "outer" in golden["steps"][0]:
-        assert [st["outer_its"] for st in sts] == [st["outer"] for st in golden["steps"]]
-
-
 def test_rgdsw_elasticity():
     case = synth.small_elasticity_case(nx=16, ny=12, boxes=(4, 3), overlap=1,
                                        traction=(0.0, -2.0), two_level=True)
