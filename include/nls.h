@@ -42,6 +42,9 @@ extern "C" {
 #define NLS_ENAN         -7   /* non-finite value in a residual */
 #define NLS_ESTATE       -8   /* call out of order (e.g. solve before set_partition) */
 #define NLS_ELIMIT       -9   /* a subdomain exceeds a kernel limit (band too wide for LDS) */
+#define NLS_EDETF       -10   /* elasticity: a deformation with det F <= 0 at a quadrature
+                                 point of a local or coarse residual (eq. (2) is defined
+                                 for det F > 0 only) */
 
 /* ---- enumerations ---------------------------------------------------- */
 #define NLS_ELEM_P1_TRI   3   /* 3-node triangles, counter-clockwise */
@@ -192,6 +195,18 @@ int nls_destroy(nls_handle* h);
 int nls_set_mesh(nls_handle* h, int elem_kind, int64_t n_nodes,
                  const double* xy, int64_t n_elems, const int32_t* conn);
 
+/* The same as nls_set_mesh for the structured mesh of [0,lx] x [0,ly] with
+   nx x ny cells: node (i,j) has index j*(nx+1) + i and coordinates
+   (i*(lx/nx), j*(ly/ny)).  NLS_ELEM_P1_TRI: cell (i,j) is split along its
+   diagonal (i,j)-(i+1,j+1) into elements 2(j nx + i) = [(i,j), (i+1,j),
+   (i+1,j+1)] and 2(j nx + i) + 1 = [(i,j), (i+1,j+1), (i,j+1)] (the
+   "regular square mesh" of Section 3 read as P1 triangles);
+   NLS_ELEM_Q1_QUAD: element j nx + i = [(i,j), (i+1,j), (i+1,j+1), (i,j+1)].
+   Errors: NLS_EINVAL (nx, ny < 1, lx, ly not positive and finite, or more
+   than 2^27 nodes or elements). */
+int nls_set_mesh_structured(nls_handle* h, int elem_kind, int32_t nx, int32_t ny,
+                            double lx, double ly);
+
 /* The nonlinear problem on that mesh.
    NLS_PROBLEM_DIFFUSION (eq. (1) generalised), P1 mesh:
      -div( kappa_e (1 + beta u^2) grad u ) = f.
@@ -231,10 +246,14 @@ int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* elem_part,
    distance weights of the crosspoints whose subdomain sets contain the
    edge's, a Dirichlet node ending the edge counting as one more ancestor
    of value 0; an edge without such crosspoints keeps its own modes.
-   Interface values are extended harmonically with DF(0) into every
-   subdomain interior.
-   Errors: NLS_ESTATE (no partition), NLS_ESINGULAR. */
-int nls_build_coarse(nls_handle* h, int kind);
+   Interface values are extended harmonically with DF(u_lin) into every
+   subdomain interior: u_lin is a host array of n_nodes * d values, or NULL
+   for u_lin = 0 (the default linearisation point; diffusion: the
+   kappa-weighted Laplacian, elasticity: linear elasticity).  The extension
+   is fixed once built (all outer iterations and load steps use it).
+   Errors: NLS_ESTATE (no partition), NLS_ESINGULAR, NLS_EINVAL (u_lin not
+   finite). */
+int nls_build_coarse(nls_handle* h, int kind, const double* u_lin);
 
 /* Nodal external forces f (n_nodes * d values, dof order) of a problem
    whose load is nodal (NLS_PROBLEM_NEOHOOKE): F(u) = f_int(u) - f on free
@@ -255,8 +274,13 @@ int nls_set_load(nls_handle* h, const double* elem_load);
    D F_x(u_k) du = F_x(u_k) by GMRES and set u_{k+1} = u_k - du.
    u: n_nodes values, read as the initial iterate and overwritten with the
    last iterate; a device pointer if u_on_device != 0, else host memory.
-   st may be NULL.  Returns NLS_OK, NLS_ENOCONV, or an error. */
-int nls_solve(nls_handle* h, double* u, int u_on_device, nls_stats* st);
+   load_factor: the external load of the problem (load samples of the
+   diffusion problem, nodal forces of elasticity) scaled by this factor for
+   this solve (1.0: as set; the set load is in place again on return).
+   st may be NULL.  Returns NLS_OK, NLS_ENOCONV, or an error (NLS_ELOCAL
+   with st->failed_subdomain, NLS_ENAN, NLS_EDETF, NLS_ESINGULAR, ...). */
+int nls_solve(nls_handle* h, double* u, int u_on_device, double load_factor,
+              nls_stats* st);
 
 /* Load stepping (continuation, Section 3 of the paper: the beam load is
    increased in steps): the external load is set to s / n_steps of its

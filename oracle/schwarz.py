@@ -97,7 +97,7 @@ class Schwarz:
 
     def __init__(self, problem: P1Problem, coupling: str = "one_level",
                  inner_rtol=1e-12, inner_eta=1e-10, inner_maxit=30,
-                 stagnation=1e-14, coarse="gdsw"):
+                 stagnation=1e-14, coarse="gdsw", coarse_lin=None):
         if coupling not in ("one_level", "additive", "hybrid"):
             raise ValueError(coupling)
         self.P = problem
@@ -114,7 +114,7 @@ class Schwarz:
             raise ValueError(coarse)
         self.coarse = coarse
         if coupling in ("additive", "hybrid"):
-            self._build_gdsw()
+            self._build_gdsw(coarse_lin)
         self.state = None
 
     # ------------------------------------------------------------------ maps
@@ -320,7 +320,8 @@ class Schwarz:
         it has two or more nodes), zero on the rest of the interface, and
         every function is extended into each subdomain interior by the
         discrete harmonic extension Phi_I = -A_II^{-1} A_IG Phi_G with
-        A = DF(u_lin), u_lin = 0.
+        A = DF(u_lin), u_lin = 0 unless the constructor's coarse_lin is
+        given.
         """
         P = self.P
         N = P.N

@@ -108,6 +108,42 @@ extern "C" int nls_set_mesh(nls_handle* h, int elem_kind, int64_t n_nodes, const
     return NLS_OK;
 }
 
+extern "C" int nls_set_mesh_structured(nls_handle* h, int elem_kind, int32_t nx, int32_t ny,
+                                       double lx, double ly) {
+    if (!h) return NLS_EINVAL;
+    if (elem_kind != NLS_ELEM_P1_TRI && elem_kind != NLS_ELEM_Q1_QUAD)
+        return fail(h, NLS_EINVAL, "element kind must be P1 triangles or Q1 quadrilaterals");
+    if (nx < 1 || ny < 1 || !(lx > 0.0) || !(ly > 0.0) || !std::isfinite(lx) || !std::isfinite(ly))
+        return fail(h, NLS_EINVAL, "need nx, ny >= 1 and positive finite lengths");
+    const int64_t nn = (int64_t)(nx + 1) * (ny + 1);
+    const int64_t ne = (int64_t)nx * ny * (elem_kind == NLS_ELEM_P1_TRI ? 2 : 1);
+    if (nn > (1 << 27) || ne > (1 << 27)) return fail(h, NLS_EINVAL, "mesh too large");
+    std::vector<double> xy(2 * (size_t)nn);
+    const double hx = lx / nx, hy = ly / ny;
+    for (int j = 0; j <= ny; ++j)
+        for (int i = 0; i <= nx; ++i) {
+            const size_t g = (size_t)j * (nx + 1) + i;
+            xy[2 * g] = (double)i * hx;
+            xy[2 * g + 1] = (double)j * hy;
+        }
+    const int nv = elem_kind == NLS_ELEM_P1_TRI ? 3 : 4;
+    std::vector<int32_t> conn((size_t)nv * ne);
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            const int32_t n00 = j * (nx + 1) + i, n10 = n00 + 1, n11 = n00 + nx + 2, n01 = n00 + nx + 1;
+            const size_t c = (size_t)j * nx + i;
+            if (nv == 3) {
+                int32_t* t = &conn[6 * c];
+                t[0] = n00; t[1] = n10; t[2] = n11;
+                t[3] = n00; t[4] = n11; t[5] = n01;
+            } else {
+                int32_t* q = &conn[4 * c];
+                q[0] = n00; q[1] = n10; q[2] = n11; q[3] = n01;
+            }
+        }
+    return nls_set_mesh(h, elem_kind, nn, xy.data(), ne, conn.data());
+}
+
 extern "C" int nls_set_problem(nls_handle* h, int kind, const double* params,
                                const double* elem_coef, const double* elem_load) {
     if (!h) return NLS_EINVAL;
@@ -482,7 +518,7 @@ static int coarse_rhs_scale(nls_handle* h) {
     return sync(h);
 }
 
-extern "C" int nls_build_coarse(nls_handle* h, int kind) {
+extern "C" int nls_build_coarse(nls_handle* h, int kind, const double* u_lin) {
     if (h) h->tuned = false;
     if (h) h->drop_graphs();
     if (!h) return NLS_EINVAL;
@@ -494,6 +530,9 @@ extern "C" int nls_build_coarse(nls_handle* h, int kind) {
     if (kind == NLS_COARSE_NONE) return NLS_OK;
     if (kind != NLS_COARSE_GDSW && kind != NLS_COARSE_RGDSW)
         return fail(h, NLS_EINVAL, "unknown coarse space kind");
+    if (u_lin)
+        for (int k = 0; k < h->mesh.ndof(); ++k)
+            if (!std::isfinite(u_lin[k])) return fail(h, NLS_EINVAL, "u_lin must be finite");
     std::string err;
     int rc = nls_build_coarse_symbolic(h->mesh, h->part_h.data(), h->maps.nsub, kind, h->co, err);
     if (rc) return fail(h, rc, err);
@@ -615,7 +654,15 @@ extern "C" int nls_build_coarse(nls_handle* h, int kind) {
     if (h->coarse_inv) RC(h->alloc(G_COARSE, &d.a0inv, (size_t)C.offI.back()));
     HIPCHK(hipMemsetAsync(d.flag, 0, sizeof(int), h->stream));
     h->dc = d;
-    HIPCHK(launch_gdsw_extend(h->dm, d, lds_gdsw, npl_for(std::max(maxikl, maxiband)), h->stream));
+    // the linearisation point of the extension (C9: u = 0 unless given)
+    double* ulin = nullptr;
+    if (u_lin) {
+        RC(h->alloc(G_COARSE, &ulin, (size_t)h->mesh.ndof()));
+        HIPCHK(hipMemcpyAsync(ulin, u_lin, sizeof(double) * h->mesh.ndof(), hipMemcpyHostToDevice,
+                              h->stream));
+    }
+    HIPCHK(launch_gdsw_extend(h->dm, d, ulin, lds_gdsw, npl_for(std::max(maxikl, maxiband)),
+                              h->stream));
     int flag = 0;
     HIPCHK(hipMemcpyAsync(&flag, d.flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
     RC(sync(h));
@@ -769,6 +816,7 @@ static int coarse_solve(nls_handle* h, const double* u, int* its_out, hipStream_
     const int n0 = d.n0;
     const bool chord = (h->opt.flags & NLS_FLAG_COARSE_CHORD) != 0;
     HIPCHK(hipMemsetAsync(d.c, 0, sizeof(double) * n0, cs));
+    HIPCHK(hipMemsetAsync(d.flag, 0, sizeof(int), cs));
     double tol = 0.0, dprev = -1.0, cmax = 0.0, gprev = 0.0;
     int its = 0;
     bool have_lu = chord && h->coarse_lu_valid;
@@ -782,7 +830,13 @@ static int coarse_solve(nls_handle* h, const double* u, int* its_out, hipStream_
         const double gn = pc[0];
         if (its == 0)
             tol = std::max(h->opt.inner_rtol * gn, h->opt.inner_eta * h->phib_inf * std::sqrt((double)n0));
-        if (!std::isfinite(gn)) return fail(h, NLS_ENAN, "coarse residual is not finite");
+        if (!std::isfinite(gn)) {
+            HIPCHK(hipMemcpyAsync(pc + 4, d.flag, sizeof(int), hipMemcpyDeviceToHost, cs));
+            HIPCHK(hipStreamSynchronize(cs));
+            if (*(const int*)(pc + 4) & 2)
+                return fail(h, NLS_EDETF, "det F <= 0 in the coarse residual");
+            return fail(h, NLS_ENAN, "coarse residual is not finite");
+        }
         if (gn <= tol) break;
         if (dprev >= 0.0 && dprev <= h->opt.stagnation * cmax) break;
         if (its == h->opt.inner_maxit) return fail(h, NLS_ELOCAL, "coarse Newton did not converge");
@@ -911,6 +965,8 @@ static int evaluate(nls_handle* h, const double* u, double* Fx) {
     if (st2[0] >= 0) {
         if (h->st) h->st->failed_subdomain = st2[0];
         if (st2[1] == 2) return fail(h, NLS_ENAN, "non-finite local residual in subdomain " + std::to_string(st2[0]));
+        if (st2[1] == 4)
+            return fail(h, NLS_EDETF, "det F <= 0 in the local residual of subdomain " + std::to_string(st2[0]));
         if (st2[1] == 3) return fail(h, NLS_ESINGULAR, "zero pivot in subdomain " + std::to_string(st2[0]));
         return fail(h, NLS_ELOCAL, "local Newton failed in subdomain " + std::to_string(st2[0]));
     }
@@ -1453,7 +1509,44 @@ static int gmres(nls_handle* h, const double* b, double* x, int* its_out) {
     return NLS_OK;
 }
 
-extern "C" int nls_solve(nls_handle* h, double* u, int u_on_device, nls_stats* st) {
+static int solve_impl(nls_handle* h, double* u, int u_on_device, nls_stats* st);
+
+// The full external load of the problem as set (nodal forces, or the load
+// samples of the diffusion problem; f = 1 when none were given), the load
+// scaled by sc on the device, and the set load again.
+static std::vector<double> full_load(const nls_handle* h, bool* had_samples) {
+    *had_samples = !h->fmid_h.empty();
+    if (h->kind == NLS_PROBLEM_NEOHOOKE) return h->fnode_h;
+    return *had_samples ? h->fmid_h : std::vector<double>(3 * (size_t)h->mesh.E, 1.0);
+}
+
+static int apply_load(nls_handle* h, const std::vector<double>& full, double sc) {
+    std::vector<double> f(full.size());
+    for (size_t j = 0; j < full.size(); ++j) f[j] = sc * full[j];
+    return h->kind == NLS_PROBLEM_NEOHOOKE ? upload_nodal_load(h, f.data()) : nls_set_load(h, f.data());
+}
+
+static int restore_load(nls_handle* h, const std::vector<double>& full, bool had_samples) {
+    if (h->kind == NLS_PROBLEM_NEOHOOKE) return upload_nodal_load(h, full.data());
+    return nls_set_load(h, had_samples ? full.data() : nullptr);
+}
+
+extern "C" int nls_solve(nls_handle* h, double* u, int u_on_device, double load_factor,
+                         nls_stats* st) {
+    if (!h || !u) return NLS_EINVAL;
+    if (!std::isfinite(load_factor)) return fail(h, NLS_EINVAL, "load_factor must be finite");
+    if (load_factor == 1.0) return solve_impl(h, u, u_on_device, st);
+    if (!h->have_part) return fail(h, NLS_ESTATE, "nls_set_partition first");
+    HIPCHK(hipSetDevice(h->opt.device));
+    bool had = false;
+    const std::vector<double> full = full_load(h, &had);
+    int rc = apply_load(h, full, load_factor);
+    if (rc == NLS_OK) rc = solve_impl(h, u, u_on_device, st);
+    const int r2 = restore_load(h, full, had);
+    return rc ? rc : r2;
+}
+
+static int solve_impl(nls_handle* h, double* u, int u_on_device, nls_stats* st) {
     if (!h || !u) return NLS_EINVAL;
     if (!h->have_part) return fail(h, NLS_ESTATE, "nls_set_partition first");
     if (h->opt.coupling != NLS_ONE_LEVEL && !h->have_coarse)
@@ -1535,24 +1628,18 @@ extern "C" int nls_solve_load_steps(nls_handle* h, double* u, int u_on_device, i
                                     nls_stats* st) {
     if (!h || !u || n_steps < 1) return NLS_EINVAL;
     if (!h->have_part) return fail(h, NLS_ESTATE, "nls_set_partition first");
-    const bool nodal = h->kind == NLS_PROBLEM_NEOHOOKE;
-    std::vector<double> full;
-    const bool had_samples = !h->fmid_h.empty();
-    if (nodal) full = h->fnode_h;
-    else full = had_samples ? h->fmid_h : std::vector<double>(3 * (size_t)h->mesh.E, 1.0);
-    std::vector<double> scaled(full.size());
+    HIPCHK(hipSetDevice(h->opt.device));
+    bool had = false;
+    const std::vector<double> full = full_load(h, &had);
     int rc = NLS_OK;
     for (int k = 1; k <= n_steps; ++k) {
-        const double sc = (double)k / (double)n_steps;
-        for (size_t j = 0; j < full.size(); ++j) scaled[j] = sc * full[j];
-        rc = nodal ? upload_nodal_load(h, scaled.data()) : nls_set_load(h, scaled.data());
+        rc = apply_load(h, full, (double)k / (double)n_steps);
         if (rc) break;
-        rc = nls_solve(h, u, u_on_device, st ? st + (k - 1) : nullptr);
+        rc = solve_impl(h, u, u_on_device, st ? st + (k - 1) : nullptr);
         if (rc) break;
     }
     // the full load again (the stored problem is unchanged)
-    int r2 = nodal ? upload_nodal_load(h, full.data())
-                   : nls_set_load(h, had_samples ? full.data() : nullptr);
+    const int r2 = restore_load(h, full, had);
     return rc ? rc : r2;
 }
 

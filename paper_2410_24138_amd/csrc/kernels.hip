@@ -246,9 +246,10 @@ __device__ __forceinline__ void nh_local_values(const DevMaps& P, int e, const d
     }
 }
 
+// detf (LDS word, or null): set to 1 when an elasticity row meets det F <= 0.
 template <bool ELAST>
 __device__ __forceinline__ void local_residual(const DevMesh& M, const DevMaps& P, int n, int rowbase,
-                               int ebase, const double* vp, double* rb) {
+                               int ebase, const double* vp, double* rb, int* detf = nullptr) {
     for (int a = threadIdx.x; a < n; a += blockDim.x) {
         const int row = rowbase + a;
         const int g = P.l2g[row];
@@ -272,6 +273,7 @@ __device__ __forceinline__ void local_residual(const DevMesh& M, const DevMaps& 
                 acc += nh_force(M, X, ue, pos, c, ok);
             }
             rb[a] = ok ? acc - M.bload[g] : __builtin_nan("");
+            if (!ok && detf) *detf = 1;
             continue;
         }
         double acc = 0.0;
@@ -1060,6 +1062,7 @@ __global__ void __launch_bounds__(NLS_BLOCK)
 k_local_newton(DevMesh M, DevMaps P, DevLocal L, NewtonParams np, const double* __restrict__ u) {
     extern __shared__ double smem[];
     __shared__ int sflag[20];
+    __shared__ int sdetf;  // a residual met det F <= 0 (elasticity)
     const int i = P.order[blockIdx.x];
     const int rowbase = P.off_n[i], n = P.off_n[i + 1] - rowbase;
     const int gbase = P.off_g[i], ng = P.off_g[i + 1] - gbase;
@@ -1074,8 +1077,9 @@ k_local_newton(DevMesh M, DevMaps P, DevLocal L, NewtonParams np, const double* 
     double* W = mult + ((kl > 1 ? kl : 1) + 1);
     for (int a = threadIdx.x; a < n; a += blockDim.x) vp[a] = u[P.l2g[rowbase + a]];
     for (int j = threadIdx.x; j < ng; j += blockDim.x) vp[n + j] = u[P.g2g[gbase + j]];
+    if (threadIdx.x == 0) sdetf = 0;
     __syncthreads();
-    local_residual<ELAST>(M, P, n, rowbase, ebase, vp, rb);
+    local_residual<ELAST>(M, P, n, rowbase, ebase, vp, rb, &sdetf);
     double ss = 0.0;
     for (int a = threadIdx.x; a < n; a += blockDim.x) ss += rb[a] * rb[a];
     const double rho_plain = sqrt(block_sum(ss, red));
@@ -1087,7 +1091,7 @@ k_local_newton(DevMesh M, DevMaps P, DevLocal L, NewtonParams np, const double* 
     if (np.xpred) {
         for (int a = threadIdx.x; a < n; a += blockDim.x) vp[a] = np.xpred[rowbase + a];
         __syncthreads();
-        local_residual<ELAST>(M, P, n, rowbase, ebase, vp, rb);
+        local_residual<ELAST>(M, P, n, rowbase, ebase, vp, rb, &sdetf);
         ss = 0.0;
         for (int a = threadIdx.x; a < n; a += blockDim.x) ss += rb[a] * rb[a];
         const double rg = sqrt(block_sum(ss, red));
@@ -1096,6 +1100,10 @@ k_local_newton(DevMesh M, DevMaps P, DevLocal L, NewtonParams np, const double* 
             rn = rg;
         } else {
             start = 2;
+            // a rejected prediction's det F does not count (the reset is
+            // ordered before the next residual by the barrier that follows
+            // the reload of R_i u)
+            if (threadIdx.x == 0) sdetf = 0;
         }
     }
     int its = 0, status = 0;
@@ -1105,7 +1113,7 @@ k_local_newton(DevMesh M, DevMaps P, DevLocal L, NewtonParams np, const double* 
             for (int a = threadIdx.x; a < n; a += blockDim.x) vp[a] = u[P.l2g[rowbase + a]];
             __syncthreads();
             if (np.xpred) {
-                local_residual<ELAST>(M, P, n, rowbase, ebase, vp, rb);
+                local_residual<ELAST>(M, P, n, rowbase, ebase, vp, rb, &sdetf);
                 rn = rho_plain;
             }
         }
@@ -1113,7 +1121,12 @@ k_local_newton(DevMesh M, DevMaps P, DevLocal L, NewtonParams np, const double* 
         status = 0;
         double dprev = -1.0;
         for (;;) {
-            if (!(rn == rn) || isinf(rn)) { status = 2; break; }
+            if (!(rn == rn) || isinf(rn)) {
+                // the norm's reduction synchronised the block, so every
+                // thread sees the flag of that residual
+                status = sdetf ? 4 : 2;
+                break;
+            }
             if (rn <= tol) break;
             if (dprev >= 0.0) {
                 double xm = 0.0;
@@ -1138,7 +1151,7 @@ k_local_newton(DevMesh M, DevMaps P, DevLocal L, NewtonParams np, const double* 
             }
             dprev = block_max(dm, red);
             ++its;
-            local_residual<ELAST>(M, P, n, rowbase, ebase, vp, rb);
+            local_residual<ELAST>(M, P, n, rowbase, ebase, vp, rb, &sdetf);
             ss = 0.0;
             for (int a = threadIdx.x; a < n; a += blockDim.x) ss += rb[a] * rb[a];
             rn = sqrt(block_sum(ss, red));
@@ -1956,11 +1969,11 @@ __device__ __forceinline__ void coarse_elem_row(const DevMesh& M, const DevCoars
     }
 }
 
-// Harmonic extension Phi_I = -A_II^{-1} A_IG Phi_G with A = DF(0) (one
-// workgroup per subdomain; setup only).
+// Harmonic extension Phi_I = -A_II^{-1} A_IG Phi_G with A = DF(u_lin), u_lin
+// = 0 by default (one workgroup per subdomain; setup only).
 template <int NPL, bool ELAST>
 __global__ void __launch_bounds__(NLS_BLOCK)
-k_gdsw_extend(DevMesh M, DevCoarse C) {
+k_gdsw_extend(DevMesh M, DevCoarse C, const double* __restrict__ ulin) {
     constexpr int D = ELAST ? 2 : 1, NV = ELAST ? 4 : 3;
     extern __shared__ double smem[];
     __shared__ int sflag[20];
@@ -1981,7 +1994,7 @@ k_gdsw_extend(DevMesh M, DevCoarse C) {
     double* red = rhs + ni;
     double* mult = red + 24;
     double* W = mult + ((kl > 1 ? kl : 1) + 1);
-    // A_II values (DF at u = 0)
+    // A_II values (DF at u_lin; at u = 0 when ulin is null)
     for (int r = threadIdx.x; r < ni; r += blockDim.x) {
         const int ca = C.inode[ib + r];
         const int js = C.iptr[ib + r], je = C.iptr[ib + r + 1];
@@ -1991,7 +2004,7 @@ k_gdsw_extend(DevMesh M, DevCoarse C) {
             const int e = eb + (code >> 2), pos = code & 3;
             double kr[4][2];
             int cn[4];
-            coarse_elem_row<ELAST>(M, C, cb, e, pos, ca % D, nullptr, kr, cn);
+            coarse_elem_row<ELAST>(M, C, cb, e, pos, ca % D, ulin, kr, cn);
 #pragma unroll
             for (int b = 0; b < NV; ++b)
 #pragma unroll
@@ -2018,7 +2031,7 @@ k_gdsw_extend(DevMesh M, DevCoarse C) {
                 const int e = eb + (code >> 2), pos = code & 3;
                 double kr[4][2];
                 int cn[4];
-                coarse_elem_row<ELAST>(M, C, cb, e, pos, ca % D, nullptr, kr, cn);
+                coarse_elem_row<ELAST>(M, C, cb, e, pos, ca % D, ulin, kr, cn);
 #pragma unroll
                 for (int b = 0; b < NV; ++b)
 #pragma unroll
@@ -2123,7 +2136,10 @@ k_coarse_q(DevMesh M, DevCoarse C, const double* __restrict__ w, const double* _
             if (ELAST && mode == 0) {
                 const int gd = C.cnode[cb + a];
                 if (C.cown[gd] == i) acc -= M.bload[gd];
-                if (!ok) acc = __builtin_nan("");
+                if (!ok) {
+                    acc = __builtin_nan("");
+                    atomicOr(C.flag, 2);  // det F <= 0
+                }
             }
         }
         q[a] = acc;
@@ -2718,13 +2734,13 @@ hipError_t launch_sub_coarse(const DevMesh& M, const DevCoarse& C, const double*
     return hipGetLastError();
 }
 
-hipError_t launch_gdsw_extend(const DevMesh& M, const DevCoarse& C, int lds_bytes, int npl,
-                              hipStream_t s) {
+hipError_t launch_gdsw_extend(const DevMesh& M, const DevCoarse& C, const double* ulin,
+                              int lds_bytes, int npl, hipStream_t s) {
     hipError_t e;
 #define NLS_GE(NPL, EL)                                                              \
     e = set_lds(k_gdsw_extend<NPL, EL>, lds_bytes);                                  \
     if (e != hipSuccess) return e;                                                   \
-    k_gdsw_extend<NPL, EL><<<C.nsub, NLS_BLOCK, lds_bytes, s>>>(M, C);
+    k_gdsw_extend<NPL, EL><<<C.nsub, NLS_BLOCK, lds_bytes, s>>>(M, C, ulin);
     if (M.kind == NLS_PROBLEM_NEOHOOKE) {
         if (npl <= 1) { NLS_GE(1, true) } else if (npl == 2) { NLS_GE(2, true) } else { NLS_GE(4, true) }
     } else {

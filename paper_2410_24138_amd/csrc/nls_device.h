@@ -47,7 +47,8 @@ struct DevLocal {
     double* T;                  // packed T_i(u) = R_i u - x*
     double* z;                  // packed scratch of the tangent
     int* its;                   // per subdomain
-    int* status;                // per subdomain: 0 ok, 1 no convergence, 2 NaN, 3 zero pivot
+    int* status;                // per subdomain: 0 ok, 1 no convergence, 2 NaN, 3 zero pivot,
+                                //   4 det F <= 0 (elasticity)
     int* start;                 // per subdomain: 0 from R_i u, 1 from the predicted start,
                                 //   2 prediction rejected or failed, then from R_i u
 };
@@ -148,8 +149,9 @@ hipError_t launch_local_factor(const DevMesh& M, const DevMaps& P, const DevLoca
 // out = v - Phi c over all dofs (hybrid tangent)
 hipError_t launch_sub_coarse(const DevMesh& M, const DevCoarse& C, const double* cvec,
                              const double* v, double* out, hipStream_t s);
-hipError_t launch_gdsw_extend(const DevMesh& M, const DevCoarse& C, int lds_bytes,
-                              int nb_per_lane, hipStream_t s);
+// ulin: linearisation point of DF (global vector), or null for u = 0
+hipError_t launch_gdsw_extend(const DevMesh& M, const DevCoarse& C, const double* ulin,
+                              int lds_bytes, int nb_per_lane, hipStream_t s);
 hipError_t launch_coarse_w(const DevMesh& M, const DevCoarse& C, const double* u,
                            double* w, hipStream_t s);
 hipError_t launch_coarse_q(const DevMesh& M, const DevCoarse& C, const double* w,

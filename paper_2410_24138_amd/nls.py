@@ -26,6 +26,7 @@ NLS_ELOCAL = -6
 NLS_ENAN = -7
 NLS_ESTATE = -8
 NLS_ELIMIT = -9
+NLS_EDETF = -10
 
 ELEM_P1_TRI = 3
 ELEM_Q1_QUAD = 4
@@ -50,6 +51,7 @@ FLAG_OVERLAP = 32
 # every symbol include/nls.h declares
 SYMBOLS = (
     "nls_default_options", "nls_create", "nls_destroy", "nls_set_mesh",
+    "nls_set_mesh_structured",
     "nls_set_problem", "nls_set_dirichlet", "nls_set_partition",
     "nls_build_coarse", "nls_solve", "nls_eval_residual",
     "nls_eval_precond_residual", "nls_apply_tangent",
@@ -143,8 +145,9 @@ def load() -> ctypes.CDLL:
         "nls_set_problem": ([P, ctypes.c_int, P, P, P], ctypes.c_int),
         "nls_set_dirichlet": ([P, i64, P, P], ctypes.c_int),
         "nls_set_partition": ([P, i32, P, i32], ctypes.c_int),
-        "nls_build_coarse": ([P, ctypes.c_int], ctypes.c_int),
-        "nls_solve": ([P, P, ctypes.c_int, ctypes.POINTER(Stats)], ctypes.c_int),
+        "nls_set_mesh_structured": ([P, ctypes.c_int, i32, i32, dbl, dbl], ctypes.c_int),
+        "nls_build_coarse": ([P, ctypes.c_int, P], ctypes.c_int),
+        "nls_solve": ([P, P, ctypes.c_int, dbl, ctypes.POINTER(Stats)], ctypes.c_int),
         "nls_eval_residual": ([P, P, P], ctypes.c_int),
         "nls_eval_precond_residual": ([P, P, P], ctypes.c_int),
         "nls_apply_tangent": ([P, P, P], ctypes.c_int),
@@ -249,12 +252,15 @@ class Solver:
     """One libnls handle set up for an input case (see synth.diffusion_case).
 
     coupling: "one_level", "additive" or "hybrid"; precision: "fp64" or "fp32_ir".
+    coarse_lin: linearisation point of the coarse basis extension (default 0);
+    structured: (nx, ny, lx, ly) to let the library generate the case's
+    structured grid (nls_set_mesh_structured) instead of passing it.
     Options not given keep the library defaults.
     """
 
     def __init__(self, case: dict, coupling: Optional[str] = None,
                  precision: str = "fp64", device: int = 0, stream=None,
-                 coarse: str = "gdsw", **opts):
+                 coarse: str = "gdsw", coarse_lin=None, structured=None, **opts):
         import torch
         self.lib = load()
         self.torch = torch
@@ -280,8 +286,14 @@ class Solver:
         elastic = case.get("kind") == "neohooke"
         self.d = 2 if elastic else 1
         self.N = self.d * len(xy)
-        self._check(self.lib.nls_set_mesh(h, ELEM_Q1_QUAD if elastic else ELEM_P1_TRI,
-                                          len(xy), _ptr(xy), len(conn), _ptr(conn)))
+        kind_e = ELEM_Q1_QUAD if elastic else ELEM_P1_TRI
+        if structured is not None:
+            # (nx, ny, lx, ly): the library generates the case's grid itself
+            nx, ny, lx, ly = structured
+            self._check(self.lib.nls_set_mesh_structured(h, kind_e, int(nx), int(ny),
+                                                         float(lx), float(ly)))
+        else:
+            self._check(self.lib.nls_set_mesh(h, kind_e, len(xy), _ptr(xy), len(conn), _ptr(conn)))
         if elastic:
             params = np.array([case["mu"], case["lam"]], dtype=np.float64)
             self._check(self.lib.nls_set_problem(h, PROBLEM_NEOHOOKE, _ptr(params), None, None))
@@ -305,7 +317,11 @@ class Solver:
                                                int(case["overlap"])))
         if coupling in ("additive", "hybrid"):
             kind = {"gdsw": COARSE_GDSW, "rgdsw": COARSE_RGDSW}[coarse]
-            self._check(self.lib.nls_build_coarse(h, kind))
+            ul = None
+            if coarse_lin is not None:
+                ul = np.ascontiguousarray(coarse_lin, dtype=np.float64)
+                assert ul.size == self.N
+            self._check(self.lib.nls_build_coarse(h, kind, None if ul is None else _ptr(ul)))
 
     def set_nodal_load(self, f):
         """Nodal forces (elasticity), n_nodes * 2 values in dof order."""
@@ -342,13 +358,15 @@ class Solver:
         return ctypes.c_void_p(t.data_ptr())
 
     # ---- entry points ------------------------------------------------------
-    def solve(self, u0=None):
-        """Outer Newton from u0 (default 0).  Returns (u tensor, stats, rc)."""
+    def solve(self, u0=None, load_factor=1.0):
+        """Outer Newton from u0 (default 0) with the external load scaled by
+        load_factor.  Returns (u tensor, stats, rc)."""
         t = self.torch
         u = t.zeros(self.N, dtype=t.float64, device=self.device) if u0 is None \
             else self._dev(u0).clone()
         st = Stats()
-        rc = self._check(self.lib.nls_solve(self.h, self._vp(u), 1, ctypes.byref(st)))
+        rc = self._check(self.lib.nls_solve(self.h, self._vp(u), 1, float(load_factor),
+                                            ctypes.byref(st)))
         return u, st.as_dict(), rc
 
     def solve_nks(self, u0=None):
@@ -377,14 +395,14 @@ class Solver:
         t = self.torch
         assert u.dtype == t.float64 and u.is_cuda and u.is_contiguous() and u.numel() == self.N
         st = Stats()
-        self._check(self.lib.nls_solve(self.h, self._vp(u), 1, ctypes.byref(st)))
+        self._check(self.lib.nls_solve(self.h, self._vp(u), 1, 1.0, ctypes.byref(st)))
         return st.as_dict()
 
     def solve_host(self, u: np.ndarray):
         """Same on a host array (updated in place)."""
         assert u.dtype == np.float64 and u.flags.c_contiguous
         st = Stats()
-        rc = self._check(self.lib.nls_solve(self.h, _ptr(u), 0, ctypes.byref(st)))
+        rc = self._check(self.lib.nls_solve(self.h, _ptr(u), 0, 1.0, ctypes.byref(st)))
         return st.as_dict(), rc
 
     def residual(self, u):

@@ -199,3 +199,40 @@ def test_tuned_streams_elasticity(coupling):
     _close(_np(s.precond_residual(u)), ref, 1e-10)
     v = np.random.default_rng(14).normal(size=P.ndof)
     _close(_np(s.tangent(v)), S.tangent(v), 1e-10)
+
+
+def test_det_f_error_code():
+    """A state that inverts elements (u_x = -2x: F_11 = -1, det F < 0) makes
+    the local residuals undefined: the solver reports NLS_EDETF (the kernel
+    finishes normally and flags the subdomain)."""
+    from paper_2410_24138_amd import NLSError
+    import paper_2410_24138_amd.nls as nls
+    case = synth.small_elasticity_case(nx=12, ny=6, boxes=(3, 2), overlap=1,
+                                       traction=(0.0, -1.0), two_level=False)
+    P = NHProblem(case)
+    u = np.zeros(P.ndof)
+    u[0::2] = -2.0 * P.xy[:, 0]
+    u[P.is_dir] = 0.0
+    s = _solver(case, coupling="one_level")
+    with pytest.raises(NLSError) as e:
+        s.precond_residual(u)
+    assert e.value.code == nls.NLS_EDETF
+
+
+def test_structured_q1_mesh_and_load_factor():
+    """nls_set_mesh_structured on Q1 gives the case's mesh (identical F and
+    solve); a solve at load_factor 0.5 equals the oracle on the half load."""
+    case = synth.small_elasticity_case(nx=16, ny=8, boxes=(4, 2), overlap=1,
+                                       traction=(0.0, -3.0), two_level=True)
+    a = _solver(case, coupling="additive")
+    b = _solver(case, coupling="additive", structured=(16, 8, 2.0, 1.0))
+    P = NHProblem(case)
+    u = _probe(P, 5)
+    np.testing.assert_array_equal(_np(a.residual(u)), _np(b.residual(u)))
+    half = dict(case)
+    half["nodal_force"] = 0.5 * case["nodal_force"]
+    S = Schwarz(NHProblem(half), "additive")
+    u_ref, st_ref = S.solve()
+    uu, st, rc = b.solve(load_factor=0.5)
+    assert rc == 0 and st["outer_its"] == st_ref["outer"]
+    assert np.linalg.norm(_np(uu) - u_ref) <= 1e-10 * np.linalg.norm(u_ref)

@@ -349,3 +349,52 @@ def test_hybrid_with_second_stream_matches_oracle(flags):
     uu, st, rc = _solver(case, coupling="hybrid", flags=f).solve()
     assert rc == 0 and st["outer_its"] == st_ref["outer"]
     assert np.linalg.norm(_np(uu) - u_ref) <= 1e-10 * np.linalg.norm(u_ref)
+
+
+def test_structured_mesh_entry_point():
+    """nls_set_mesh_structured generates the same P1 grid as the explicit
+    mesh of the case: F(u) and the solve are identical."""
+    case = synth.small_case(n=20, boxes=4, overlap=2, forcing_seed=2, two_level=True)
+    a = _solver(case)
+    b = _solver(case, structured=(20, 20, 1.0, 1.0))
+    u = np.random.default_rng(3).normal(size=len(case["xy"]))
+    np.testing.assert_array_equal(_np(a.residual(u)), _np(b.residual(u)))
+    ua, sa, _ = a.solve()
+    ub, sb, _ = b.solve()
+    np.testing.assert_array_equal(_np(ua), _np(ub))
+    assert sa["outer_its"] == sb["outer_its"]
+
+
+def test_load_factor_matches_scaled_problem():
+    """nls_solve with load_factor s solves the problem with the load samples
+    scaled by s (oracle on the scaled case), and leaves the set load in
+    place for the next solve."""
+    case = synth.small_case(n=24, boxes=4, overlap=2, forcing_seed=5, two_level=True)
+    scaled = dict(case)
+    scaled["elem_load"] = 0.4 * case["elem_load"]
+    S = Schwarz(P1Problem(scaled), "additive")
+    u_ref, st_ref = S.solve()
+    s = _solver(case)
+    u, st, rc = s.solve(load_factor=0.4)
+    assert rc == 0 and st["outer_its"] == st_ref["outer"]
+    assert np.linalg.norm(_np(u) - u_ref) <= 1e-10 * np.linalg.norm(u_ref)
+    u_full, _ = Schwarz(P1Problem(case), "additive").solve()
+    u2, _, _ = s.solve()
+    assert np.linalg.norm(_np(u2) - u_full) <= 1e-10 * np.linalg.norm(u_full)
+
+
+def test_coarse_basis_at_linearisation_point():
+    """nls_build_coarse with u_lin: the extension uses DF(u_lin); basis, F_x
+    and the solve match the oracle built at the same point."""
+    case = synth.small_case(n=24, boxes=4, overlap=2, forcing_seed=2, two_level=True)
+    P = P1Problem(case)
+    u_lin = 2.0 * np.sin(np.pi * P.xy[:, 0]) * np.sin(np.pi * P.xy[:, 1])
+    S = Schwarz(P, "additive", coarse_lin=u_lin)
+    s = _solver(case, coupling="additive", coarse_lin=u_lin)
+    _close(s.coarse_basis().toarray(), S.Phi.toarray(), 1e-12)
+    u = _probe_point(P, case)
+    _close(_np(s.precond_residual(u)), S.evaluate(u), 1e-11)
+    u_ref, st_ref = S.solve()
+    uu, st, rc = _solver(case, coupling="additive", coarse_lin=u_lin).solve()
+    assert rc == 0 and st["outer_its"] == st_ref["outer"]
+    assert np.linalg.norm(_np(uu) - u_ref) <= 1e-10 * np.linalg.norm(u_ref)

@@ -141,6 +141,28 @@ def test_gdsw_invariants():
         np.testing.assert_array_equal(Phi[nodes, k], 1.0)
 
 
+def test_gdsw_extension_at_a_linearisation_point():
+    """The energy-minimising extension with DF(u_lin) in place of DF(0):
+    interior rows are discrete harmonic for the assembled DF(u_lin) (not for
+    DF(0)), interface rows are the same indicator functions."""
+    case = synth.small_case(n=16, boxes=4, overlap=1, two_level=True, forcing_seed=3)
+    P = P1Problem(case)
+    u_lin = 2.0 * np.sin(np.pi * P.xy[:, 0]) * np.sin(np.pi * P.xy[:, 1])
+    S0 = Schwarz(P, "additive")
+    S = Schwarz(P, "additive", coarse_lin=u_lin)
+    Phi, Phi0 = S.Phi.toarray(), S0.Phi.toarray()
+    A = P.jacobian(u_lin).toarray()
+    A0 = P.jacobian(np.zeros(P.N)).toarray()
+    for (i, I, bnd) in S.interior_blocks:
+        np.testing.assert_allclose(A[I] @ Phi, 0.0, atol=1e-13)
+        assert np.abs(A0[I] @ Phi).max() > 1e-3
+    iface = np.zeros(P.N, dtype=bool)
+    for nodes, _ in S.components:
+        iface[nodes] = True
+    np.testing.assert_array_equal(Phi[iface], Phi0[iface])
+    assert np.abs(Phi - Phi0).max() > 1e-3
+
+
 def test_coarse_linear_one_step():
     """beta = 0: T_0(u) = (Phi^T A Phi)^-1 Phi^T (A u - b)."""
     P, S = _schwarz("additive", n=12, boxes=3, overlap=1, beta=0.0,
