@@ -403,6 +403,19 @@ int nls_guess_lift(nls_handle* h, const double* u_dev, const float* coef_dev,
                    double* xpred_dev);
 /* Network output in target units for n raw feature rows. */
 int nls_guess_predict(nls_handle* h, const float* X_dev, int64_t n, float* Y_dev);
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the same
+   network output as nls_guess_predict, for n <= NLS_GUESS_NOALLOC_ROWS raw
+   feature rows, computed in a fixed working area of the library (a
+   device array of 6.8 MB per GPU, held until the process ends) instead of
+   buffers it allocates.  The call allocates and frees nothing and does not
+   synchronise: it enqueues its kernels on the handle's stream and returns;
+   Y_dev is complete in stream order.  Calls on one GPU share the working
+   area, so calls that overlap in time on one GPU (other streams, other
+   threads) race; serialise them.  Errors: NLS_ELIMIT (n too large),
+   NLS_ESTATE (no network), NLS_EINVAL, NLS_EHIP. */
+#define NLS_GUESS_NOALLOC_ROWS 4096
+int nls_guess_predict_noalloc(nls_handle* h, const float* X_dev, int64_t n, float* Y_dev);
 /* Mean squared error over all outputs of the standardised batch (X_dev,
    T_dev raw, n rows <= 65536) and its gradient (NLS_GUESS_PARAMS floats,
    device; may be NULL), without changing the network. */

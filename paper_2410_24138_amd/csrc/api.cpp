@@ -19,6 +19,7 @@
 #include "handle.h"
 
 void guess_invalidate(nls_handle* h);
+int guess_scratch_setup(int device, std::string& err);
 
 // ---------------------------------------------------------------------------
 extern "C" int nls_default_options(nls_options* o) {
@@ -52,6 +53,10 @@ extern "C" int nls_create(const nls_options* opt, nls_handle** out) {
         opt->outer_maxit > NLS_MAX_OUTER || opt->inner_maxit < 1)
         return NLS_EINVAL;
     if (hipSetDevice(opt->device) != hipSuccess) return NLS_EHIP;
+    {
+        std::string err;
+        if (guess_scratch_setup(opt->device, err) != NLS_OK) return NLS_EHIP;
+    }
     auto* h = new (std::nothrow) nls_handle();
     if (!h) return NLS_ENOMEM;
     h->opt = *opt;

@@ -11,6 +11,7 @@
 // interpolant.  Targets: (v(x*) - lifting) on the grid, where v(x*) is the
 // state of eq. (4) at the converged local solution.
 #include <cmath>
+#include <mutex>
 
 #include "guess_device.h"
 #include "handle.h"
@@ -421,6 +422,67 @@ extern "C" int nls_guess_predict(nls_handle* h, const float* X, int64_t n, float
     HIPCHK(launch_gather_batch(X, nullptr, nullptr, (int)n, g->norm, g->tx, nullptr, h->stream));
     RC(forward(h, g->tx, (int)n, nullptr, g->ta, Y, true));
     return sync(h);
+}
+
+// ------------------------------------------- allocation-free inference
+// Working storage of nls_guess_predict_noalloc: a file-scope device array
+// (each GPU holds its own copy until the process ends), so that the call
+// allocates nothing.  Layout: the standardised bfloat16 inputs (rows x 320),
+// then two bfloat16 activation buffers (rows x 256) that layers 1-3 write in
+// turn.  Every call on a GPU shares that GPU's copy; nothing in it needs to
+// start at zero (each call writes what it reads).
+namespace {
+constexpr int NOALLOC_ROWS = NLS_GUESS_NOALLOC_ROWS;
+constexpr size_t SCRATCH_IN = (size_t)NOALLOC_ROWS * NLS_G_IN;      // bfloat16 elements
+constexpr size_t SCRATCH_ACT = (size_t)NOALLOC_ROWS * NLS_G_WIDTH;  // per activation buffer
+constexpr size_t SCRATCH_BYTES = (SCRATCH_IN + 2 * SCRATCH_ACT) * sizeof(uint16_t);
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void* scratch_dev[SCRATCH_MAX_DEVICES] = {};  // device address of scratch, per device
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+// Device address of this GPU's scratch array, looked up once per device
+// with that device current (called by nls_create).  In host code the name
+// scratch is not a device address; only the looked-up pointer is used.
+int guess_scratch_setup(int device, std::string& err) {
+    if (device < 0 || device >= SCRATCH_MAX_DEVICES) {
+        err = "device ordinal out of range";
+        return NLS_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (scratch_dev[device]) return NLS_OK;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+        return NLS_EHIP;
+    }
+    scratch_dev[device] = p;
+    return NLS_OK;
+}
+
+extern "C" int nls_guess_predict_noalloc(nls_handle* h, const float* X, int64_t n, float* Y) {
+    if (!h || n < 0 || (n > 0 && (!X || !Y))) return NLS_EINVAL;
+    if (n > NOALLOC_ROWS)
+        return fail(h, NLS_ELIMIT, "nls_guess_predict_noalloc takes at most " +
+                                       std::to_string(NOALLOC_ROWS) + " rows per call");
+    RC(need_model(h));
+    const int dev = h->opt.device;
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES || !scratch_dev[dev])
+        return fail(h, NLS_ESTATE, "no scratch address for this device");
+    HIPCHK(hipSetDevice(dev));
+    if (n == 0) return NLS_OK;
+    GuessState* g = h->guess;
+    uint16_t* tx = (uint16_t*)scratch_dev[dev];
+    uint16_t* a0 = tx + SCRATCH_IN;
+    uint16_t* a1 = a0 + SCRATCH_ACT;
+    uint16_t* const act[3] = {a0, a1, a0};  // layer l reads act[l-1], writes act[l]
+    HIPCHK(launch_gather_batch(X, nullptr, nullptr, (int)n, g->norm, tx, nullptr, h->stream));
+    RC(forward(h, tx, (int)n, nullptr, act, Y, true));
+    HIPCHK(hipGetLastError());
+    return NLS_OK;
 }
 
 extern "C" int nls_guess_loss_grad(nls_handle* h, const float* X, const float* T, int64_t n,

@@ -27,6 +27,7 @@ NLS_ENAN = -7
 NLS_ESTATE = -8
 NLS_ELIMIT = -9
 NLS_EDETF = -10
+NLS_GUESS_NOALLOC_ROWS = 4096
 
 ELEM_P1_TRI = 3
 ELEM_Q1_QUAD = 4
@@ -60,7 +61,8 @@ SYMBOLS = (
     "nls_inspect_coarse", "nls_set_load", "nls_guess_set_model",
     "nls_guess_get_model", "nls_guess_enable", "nls_guess_capture",
     "nls_guess_captured", "nls_guess_features", "nls_guess_lift",
-    "nls_guess_predict", "nls_guess_loss_grad", "nls_guess_train",
+    "nls_guess_predict", "nls_guess_predict_noalloc", "nls_guess_loss_grad",
+    "nls_guess_train",
     "nls_get_tuning", "nls_set_nodal_load", "nls_solve_load_steps", "nls_solve_nks",
 )
 
@@ -173,6 +175,7 @@ def load() -> ctypes.CDLL:
         "nls_guess_features": ([P, P, P], ctypes.c_int),
         "nls_guess_lift": ([P, P, P, P], ctypes.c_int),
         "nls_guess_predict": ([P, P, i64, P], ctypes.c_int),
+        "nls_guess_predict_noalloc": ([P, P, i64, P], ctypes.c_int),
         "nls_guess_loss_grad": ([P, P, P, i64, P, ctypes.POINTER(dbl)], ctypes.c_int),
         "nls_guess_train": ([P, ctypes.POINTER(TrainOpts), P, P, i64, P,
                              ctypes.POINTER(TrainStats)], ctypes.c_int),
@@ -523,6 +526,16 @@ class Solver:
         Y = self.torch.empty((X.shape[0], GUESS_OUT), dtype=self.torch.float32,
                              device=self.device)
         self._check(self.lib.nls_guess_predict(self.h, self._vp(X), X.shape[0], self._vp(Y)))
+        return Y
+
+    def guess_predict_noalloc(self, X, Y):
+        """nls_guess_predict_noalloc into the caller's Y (float32, rows x 256,
+        on the device); enqueued on the handle's stream, not synchronised."""
+        X = self._f32(X, GUESS_IN)
+        assert Y.dtype == self.torch.float32 and Y.is_cuda and Y.is_contiguous()
+        assert Y.shape == (X.shape[0], GUESS_OUT)
+        self._check(self.lib.nls_guess_predict_noalloc(self.h, self._vp(X), X.shape[0],
+                                                       self._vp(Y)))
         return Y
 
     def guess_loss_grad(self, X, T):
