@@ -48,6 +48,8 @@ FORMS = {
     "chosen": ("fp32_ir", ("graph", "autotune", "overlap")),
     # FP32 local LU + FP64 refinement kept throughout
     "fp32_ir": ("fp32_ir", ("graph", "overlap")),
+    # trial: as fp32_ir with bfloat16 operands in the LU's trailing updates
+    "bf16_ir": ("bf16_ir", ("graph", "overlap")),
 }
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per dispatch measured with rocprofv3 FETCH_SIZE/WRITE_SIZE (two
@@ -513,7 +515,8 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--forms",
-                    default="plain,fp64_tuned,chosen,fp32_ir,fp64_tuned_chord,fp64_tuned_rgdsw")
+                    default="plain,fp64_tuned,chosen,fp32_ir,bf16_ir,fp64_tuned_chord,"
+                            "fp64_tuned_rgdsw")
     ap.add_argument("--workload", default="diffusion512",
                     choices=["diffusion512", "batch", "learned", "elasticity", "beam"])
     ap.add_argument("--amp", type=float, default=10.0,

@@ -59,6 +59,12 @@ extern "C" {
 #define NLS_PREC_FP64     0   /* every step in binary64 */
 #define NLS_PREC_FP32_IR  1   /* local LU in binary32, binary64 residuals and
                                  iterative refinement of every local solve */
+#define NLS_PREC_BF16_IR  2   /* trial: as NLS_PREC_FP32_IR, with the trailing
+                                 updates A22 -= L21 U12 of the blocked LU on
+                                 bfloat16 operands (FP32 accumulation, matrix
+                                 cores); refinement up to 30 steps per solve.
+                                 Local solves whose refinement does not reach
+                                 its tolerance give inexact Newton steps */
 
 #define NLS_ONE_LEVEL     0   /* F_1(u) = sum_i P~_i T_i(u), eq. (5) with (8) */
 #define NLS_ADDITIVE      1   /* F_a(u) = F_1(u) + P_0 T_0(u), eq. (10) */

@@ -45,7 +45,9 @@ extern "C" int nls_default_options(nls_options* o) {
 extern "C" int nls_create(const nls_options* opt, nls_handle** out) {
     if (opt && (opt->lu_variant < 0 || opt->lu_variant > 3)) return NLS_EINVAL;
     if (!opt || !out) return NLS_EINVAL;
-    if (opt->precision != NLS_PREC_FP64 && opt->precision != NLS_PREC_FP32_IR) return NLS_EINVAL;
+    if (opt->precision != NLS_PREC_FP64 && opt->precision != NLS_PREC_FP32_IR &&
+        opt->precision != NLS_PREC_BF16_IR)
+        return NLS_EINVAL;
     if (opt->coupling != NLS_ONE_LEVEL && opt->coupling != NLS_ADDITIVE &&
         opt->coupling != NLS_HYBRID)
         return NLS_EINVAL;
@@ -330,7 +332,7 @@ extern "C" int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* el
     if (rc) return fail(h, rc, err);
     h->part_h.assign(elem_part, elem_part + h->mesh.E);
     const HostMaps& M = h->maps;
-    const bool mixed = h->opt.precision == NLS_PREC_FP32_IR;
+    const bool mixed = h->opt.precision != NLS_PREC_FP64;
     // kernel limits
     int maxband = 0, maxkl = 0, maxn = 0, maxng = 0;
     for (int i = 0; i < M.nsub; ++i) {
@@ -475,8 +477,8 @@ extern "C" int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* el
     np.abs_tol = h->opt.inner_eta * h->b_inf;
     np.stagnation = h->opt.stagnation;
     np.maxit = h->opt.inner_maxit;
-    np.mixed = mixed ? 1 : 0;
-    np.ir_maxit = 10;
+    np.mixed = h->opt.precision == NLS_PREC_BF16_IR ? 2 : (mixed ? 1 : 0);
+    np.ir_maxit = np.mixed == 2 ? 30 : 10;
     np.ir_rtol = 1e-10;  // a Newton step needs no more; residuals stay FP64
     np.lu_variant = var0;
     np.keep_factor = 1;
@@ -1113,13 +1115,16 @@ static int time_ms(nls_handle* h, F&& launch, float* ms) {
 // buckets in both precisions and keeps the one with the smaller total.
 static int autotune_local(nls_handle* h, const double* u) {
     const HostMaps& M = h->maps;
+    // binary32 is timed against binary64; the bfloat16 trial runs as asked,
+    // in the blocked forms that hold its matrix-core update
     const bool can_mixed = h->opt.precision == NLS_PREC_FP32_IR;
+    const bool bf16 = h->opt.precision == NLS_PREC_BF16_IR;
     const int nprec = can_mixed ? 2 : 1;
     const size_t nbk = h->bk_start.size();
     std::vector<int> var[2], ldsv[2];
     double total[2] = {0.0, 0.0};
     for (int pm = 0; pm < nprec; ++pm) {
-        const bool mixed = can_mixed && pm == 0;  // pass 0: the handle's precision
+        const bool mixed = (can_mixed && pm == 0) || bf16;  // pass 0: the handle's precision
         for (size_t b = 0; b < nbk; ++b) {
             int kmax = 0;
             for (int p = h->bk_start[b]; p < h->bk_end[b]; ++p) kmax = std::max(kmax, M.kl[M.order[p]]);
@@ -1128,6 +1133,7 @@ static int autotune_local(nls_handle* h, const double* u) {
             for (int p = h->bk_start[b]; p < h->bk_end[b]; ++p)
                 blds = std::max(blds, local_lds_bytes(M, M.order[p], mixed, 3));
             for (int v = 1; v <= 3; ++v) {
+                if (v == 3 && bf16 && kmax + 8 <= 64) continue;
                 if (v == 1 && kmax + 16 > 64) continue;
                 if (v == 2 && kmax + 8 > 64) continue;
                 int lds = 0;
@@ -1137,7 +1143,7 @@ static int autotune_local(nls_handle* h, const double* u) {
                 NewtonParams np = h->np;
                 np.xpred = nullptr;
                 np.lu_variant = v;
-                np.mixed = mixed ? 1 : 0;
+                np.mixed = bf16 ? 2 : (mixed ? 1 : 0);
                 // with the factorisation at x*, so that every subdomain's
                 // time includes at least one LU even where Newton stops at once
                 np.keep_factor = 1;
@@ -1163,7 +1169,7 @@ static int autotune_local(nls_handle* h, const double* u) {
     const int pick = (nprec == 2 && total[1] < total[0]) ? 1 : 0;
     h->bk_var = var[pick];
     h->bk_lds = ldsv[pick];
-    h->np.mixed = (can_mixed && pick == 0) ? 1 : 0;
+    h->np.mixed = bf16 ? 2 : ((can_mixed && pick == 0) ? 1 : 0);
     return NLS_OK;
 }
 
@@ -1910,6 +1916,8 @@ extern "C" int nls_get_tuning(nls_handle* h, int32_t* n_buckets, int32_t* lu_var
     if (coarse_inverse) *coarse_inverse = h->coarse_inv ? 1 : 0;
     if (coarse_ms)
         for (int k = 0; k < 3; ++k) coarse_ms[k] = h->tune_ms[k];
-    if (local_precision) *local_precision = h->np.mixed ? NLS_PREC_FP32_IR : NLS_PREC_FP64;
+    if (local_precision)
+        *local_precision = h->np.mixed == 2 ? NLS_PREC_BF16_IR
+                                            : (h->np.mixed ? NLS_PREC_FP32_IR : NLS_PREC_FP64);
     return NLS_OK;
 }

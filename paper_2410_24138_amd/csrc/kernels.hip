@@ -531,6 +531,14 @@ template <> struct Mfma<float> {
     static __device__ __forceinline__ int row(int g, int q) { return 4 * g + q; }
 };
 
+// bfloat16 operands of the trial trailing update: round to nearest even.
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ short bf16_rne(float f) {
+    unsigned u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+
 // 1/x from the hardware reciprocal and two Newton steps (a few ulp).
 __device__ __forceinline__ double recip(double x) {
     double r = __builtin_amdgcn_rcp(x);
@@ -564,11 +572,18 @@ __device__ __forceinline__ void lds_barrier() {
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
-template <typename T, int NB>
+// BF16 (T = float only): the trailing update A22 -= L21 U12 takes bfloat16
+// operands on the 16x16x16 matrix-core product with FP32 accumulation.  It
+// is a separate instantiation, not a run-time branch inside the update: with
+// both product shapes behind one branch, the wait before the accumulators
+// were read back after the FP32 product came out shorter than that product
+// needs, and the binary32 factors were wrong from run to run.
+template <typename T, int NB, bool BF16 = false>
 __device__ __forceinline__ int band_lu_blocked(int n, int kl, int ku, const int* __restrict__ rptr,
                                const int* __restrict__ cols, const double* __restrict__ vals,
                                T* W, int* sh, T* __restrict__ Uf, T* __restrict__ Lf,
                                int* __restrict__ piv, int cbase = 0, double* rhs = nullptr) {
+    static_assert(!BF16 || sizeof(T) == 4, "bfloat16 updates need binary32 factors");
     T* lt = W + (NB + kl) * (NB + kl + ku);  // L11 of the current panel, NB x NB
     int* mv = (int*)(lt + NB * NB);           // moved rows of the panel (<= 64)
     const int tid = threadIdx.x, nt = blockDim.x;
@@ -785,12 +800,29 @@ __device__ __forceinline__ int band_lu_blocked(int n, int kl, int ku, const int*
                     const int ra = r0 + li;
                     const bool aok = ra < rvalid;
                     const int sra = wrap(rb + (aok ? ra : 0), H);
+                    if constexpr (BF16) {
+                        // one 16x16x16 product: lane holds k = 4 lk .. 4 lk + 3
+                        // (k >= nbp, e.g. k >= 8 of an 8-column panel, are zero)
+                        bf16x4_t a4, b4;
 #pragma unroll
-                    for (int s4 = 0; s4 < NB / 4; ++s4) {
-                        const int k = 4 * s4 + lk;
-                        const T av = (aok && k < nbp) ? -W[sra * Wd + wrap(cb + k, Wd)] : T(0);
-                        const T bv = (cok && k < nbp) ? W[wrap(rb + k, H) * Wd + scc] : T(0);
-                        acc = Mfma<T>::step(av, bv, acc);
+                        for (int t4 = 0; t4 < 4; ++t4) {
+                            const int k = 4 * lk + t4;
+                            const bool kin = k < nbp;
+                            const int kk = kin ? k : 0;
+                            const float av = (aok && kin) ? -W[sra * Wd + wrap(cb + kk, Wd)] : 0.f;
+                            const float bv = (cok && kin) ? W[wrap(rb + kk, H) * Wd + scc] : 0.f;
+                            a4[t4] = bf16_rne(av);
+                            b4[t4] = bf16_rne(bv);
+                        }
+                        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a4, b4, acc, 0, 0, 0);
+                    } else {
+#pragma unroll
+                        for (int s4 = 0; s4 < NB / 4; ++s4) {
+                            const int k = 4 * s4 + lk;
+                            const T av = (aok && k < nbp) ? -W[sra * Wd + wrap(cb + k, Wd)] : T(0);
+                            const T bv = (cok && k < nbp) ? W[wrap(rb + k, H) * Wd + scc] : T(0);
+                            acc = Mfma<T>::step(av, bv, acc);
+                        }
                     }
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
@@ -853,8 +885,19 @@ __device__ __forceinline__ int band_lu_auto(int n, int kl, int ku, const int* __
                             const int* __restrict__ cols, const double* __restrict__ vals,
                             T* W, T* mult, int* sflag, T* __restrict__ Uf, T* __restrict__ Lf,
                             int* __restrict__ piv, int cbase = 0, int variant = 0,
-                            double* rhs = nullptr) {
+                            double* rhs = nullptr, bool bf16 = false) {
     // variant: 0 widest panel the band allows, 1 NB=16, 2 NB=8, 3 unblocked
+    // (bf16 trailing updates exist in the blocked forms only)
+    if constexpr (sizeof(T) == 4) {
+        if (bf16) {
+            if ((variant == 0 || variant == 1) && kl + 16 <= 64)
+                return band_lu_blocked<T, 16, true>(n, kl, ku, rptr, cols, vals, W, sflag, Uf, Lf,
+                                                    piv, cbase, rhs);
+            if ((variant == 0 || variant == 2) && kl + 8 <= 64)
+                return band_lu_blocked<T, 8, true>(n, kl, ku, rptr, cols, vals, W, sflag, Uf, Lf,
+                                                   piv, cbase, rhs);
+        }
+    }
     if ((variant == 0 || variant == 1) && kl + 16 <= 64)
         return band_lu_blocked<T, 16>(n, kl, ku, rptr, cols, vals, W, sflag, Uf, Lf, piv, cbase, rhs);
     if ((variant == 0 || variant == 2) && kl + 8 <= 64)
@@ -1041,7 +1084,7 @@ __device__ __forceinline__ int local_factor(const DevMaps& P, const DevLocal& L,
     if (np.mixed && !fp64)
         return band_lu_auto<float>(n, kl, ku, rptr, P.jcol, L.jval, (float*)W, (float*)mult, sflag,
                               L.Uf32 + P.off_u[i], L.Lf32 + P.off_l[i], L.piv + rowbase, 0,
-                              np.lu_variant);
+                              np.lu_variant, nullptr, np.mixed == 2);
     return band_lu_auto<double>(n, kl, ku, rptr, P.jcol, L.jval, (double*)W, (double*)mult, sflag,
                            L.Uf + P.off_u[i], L.Lf + P.off_l[i], L.piv + rowbase, 0,
                            np.lu_variant, rhs);

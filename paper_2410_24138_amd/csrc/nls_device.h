@@ -68,7 +68,8 @@ struct NewtonParams {
     double abs_tol;             // eta * ||b||_inf (times sqrt(n_i) in the kernel)
     double stagnation;
     int maxit;
-    int mixed;                  // 1: FP32 LU + FP64 iterative refinement
+    int mixed;                  // 1: FP32 LU + FP64 iterative refinement; 2: the same
+                                //   with bfloat16 operands in the LU's trailing updates
     int ir_maxit;
     double ir_rtol;
     const double* xpred;        // packed predicted starts, or null

@@ -35,6 +35,7 @@ PROBLEM_DIFFUSION = 1
 PROBLEM_NEOHOOKE = 2
 PREC_FP64 = 0
 PREC_FP32_IR = 1
+PREC_BF16_IR = 2
 ONE_LEVEL = 0
 ADDITIVE = 1
 HYBRID = 2
@@ -254,7 +255,8 @@ def default_options() -> Options:
 class Solver:
     """One libnls handle set up for an input case (see synth.diffusion_case).
 
-    coupling: "one_level", "additive" or "hybrid"; precision: "fp64" or "fp32_ir".
+    coupling: "one_level", "additive" or "hybrid"; precision: "fp64", "fp32_ir"
+    or "bf16_ir" (the trial with bfloat16 operands in the LU's trailing updates).
     coarse_lin: linearisation point of the coarse basis extension (default 0);
     structured: (nx, ny, lx, ly) to let the library generate the case's
     structured grid (nls_set_mesh_structured) instead of passing it.
@@ -276,7 +278,7 @@ class Solver:
         if coupling is None:
             coupling = "additive" if case.get("two_level") else "one_level"
         o.coupling = {"one_level": ONE_LEVEL, "additive": ADDITIVE, "hybrid": HYBRID}[coupling]
-        o.precision = {"fp64": PREC_FP64, "fp32_ir": PREC_FP32_IR}[precision]
+        o.precision = {"fp64": PREC_FP64, "fp32_ir": PREC_FP32_IR, "bf16_ir": PREC_BF16_IR}[precision]
         for k, v in opts.items():
             setattr(o, k, v)
         self.opts = o
@@ -582,4 +584,5 @@ class Solver:
         return {"lu_variant": var[:k].tolist(), "lds_bytes": lds[:k].tolist(),
                 "n_sub": cnt[:k].tolist(), "coarse_inverse": bool(ci.value),
                 "coarse_ms": cms.tolist(),
-                "local_precision": "fp32_ir" if prec.value == PREC_FP32_IR else "fp64"}
+                "local_precision": {PREC_FP32_IR: "fp32_ir", PREC_BF16_IR: "bf16_ir"}.get(
+                    prec.value, "fp64")}

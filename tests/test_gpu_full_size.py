@@ -7,7 +7,7 @@ benchmark times, against the full solution vectors the oracle wrote
     (option 2.2) against its own oracle run: every benchmark form.  The bar
     is element-wise max|u - u_ref| <= 1e-10 max|u_ref| when every step runs
     in binary64 with Newton's coarse iteration, 1e-8 after refinement of
-    binary32 LU solves or with chord steps for the coarse correction (a
+    binary32 LU solves (also with bfloat16 trailing updates) or with chord steps for the coarse correction (a
     different iteration, equal to Newton's to the coarse stopping
     tolerance), the oracle's outer iteration count exactly, and
     ||u - u*|| <= 1e-8 ||u*|| against the brute-force global Newton
@@ -29,7 +29,8 @@ from tests._lib import ensure_built
 pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-FORMS = ["plain", "fp64_tuned", "chosen", "fp32_ir", "fp64_tuned_chord", "fp64_tuned_rgdsw"]
+FORMS = ["plain", "fp64_tuned", "chosen", "fp32_ir", "bf16_ir", "fp64_tuned_chord",
+         "fp64_tuned_rgdsw"]
 
 
 @pytest.fixture(scope="module", autouse=True)

@@ -123,15 +123,38 @@ def test_solve_matches_oracle(kw, coupling):
         assert abs(a - b) <= 1
 
 
+@pytest.mark.parametrize("precision", ["fp32_ir", "bf16_ir"])
 @pytest.mark.parametrize("two_level", [False, True])
-def test_mixed_precision_matches_fp64(two_level):
+def test_mixed_precision_matches_fp64(two_level, precision):
+    """binary32 local LU (and the trial with bfloat16 operands in its
+    trailing updates), FP64 residuals and refinement: the oracle's solution
+    to 1e-8, the same outer and inner iteration counts as binary64."""
     case = synth.small_case(n=32, boxes=4, overlap=2, forcing_seed=4,
                             two_level=two_level)
     u64, st64, _ = _solver(case).solve()
-    u32, st32, rc = _solver(case, precision="fp32_ir").solve()
+    u32, st32, rc = _solver(case, precision=precision).solve()
     assert rc == 0 and st32["converged"]
+    assert st32["outer_its"] == st64["outer_its"]
+    assert st32["inner_its_total"] == st64["inner_its_total"]
     u64, u32 = _np(u64), _np(u32)
     assert np.linalg.norm(u32 - u64) <= 1e-8 * np.linalg.norm(u64)
+    S = Schwarz(P1Problem(case), "additive" if two_level else "one_level")
+    u_ref, st_ref = S.solve()
+    assert np.linalg.norm(u32 - u_ref) <= 1e-8 * np.linalg.norm(u_ref)
+
+
+def test_bf16_trial_elasticity():
+    """The bfloat16 trial on Neo-Hooke Jacobians under load (row
+    interchanges in the LU): F_x against the oracle to the mixed-mode bar."""
+    from oracle import NHProblem
+    case = synth.small_elasticity_case(nx=16, ny=8, boxes=(2, 2), overlap=2,
+                                       traction=(1.0, -4.0), two_level=True)
+    P = NHProblem(case)
+    S = Schwarz(P, "additive")
+    u_ref, st_ref = S.solve()
+    uu, st, rc = _solver(case, coupling="additive", precision="bf16_ir").solve()
+    assert rc == 0 and st["outer_its"] == st_ref["outer"]
+    assert np.linalg.norm(_np(uu) - u_ref) <= 1e-8 * np.linalg.norm(u_ref)
 
 
 def test_deterministic():
