@@ -32,9 +32,9 @@ Readings where the paper is silent (all are stated again where used):
     x_0 = 0, modified Gram-Schmidt, Givens rotations.
 
 LU with partial pivoting is the linear solver of every step: in band form
-(LAPACK gbtrf/gbtrs through SciPy) for the local Jacobians, whose nonzeros
-lie in a band under the ascending node order, dense (LAPACK getrf) for the
-coarse matrix and the interior blocks of the coarse basis.  GDSW components
+(LAPACK gbtrf/gbtrs through SciPy) for the local Jacobians and the interior
+blocks of the coarse basis, whose nonzeros lie in a band under the
+ascending node order, dense (LAPACK getrf) for the coarse matrix.  GDSW components
 are ordered by their smallest node index.  FP64 throughout.  Test
 infrastructure only.
 """
@@ -386,11 +386,13 @@ class Schwarz:
                 continue
             AII = A[I][:, I].toarray()
             rhs = -(A[I][:, bnd] @ PhiG[bnd]).toarray()
-            PhiI = sla.lu_solve(sla.lu_factor(AII, check_finite=False), rhs)
-            nzc = np.nonzero(np.any(PhiI != 0.0, axis=0))[0]
+            # only the functions with interface values next to the interior
+            # have nonzero right-hand sides (the others extend by zero)
+            nzc = np.nonzero(np.any(rhs != 0.0, axis=0))[0]
+            PhiI = band_lu_solve(band_lu_factor(AII), rhs[:, nzc])
             prow.append(np.repeat(I, len(nzc)))
             pcol.append(np.tile(nzc, len(I)))
-            pval.append(PhiI[:, nzc].ravel())
+            pval.append(PhiI.ravel())
             self.interior_blocks.append((i, I, bnd))
         self.Phi = sp.csr_matrix((np.concatenate(pval), (np.concatenate(prow),
                                   np.concatenate(pcol))), shape=(nd, n0))
