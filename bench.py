@@ -27,6 +27,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -59,43 +61,87 @@ MEASURED_TRAFFIC = {"kernels_sha1": "6842cb53b96de61b447c25d205f453e7870d657d",
                     "bytes": {"k_local_newton": 979624183, "k_local_factor": 434428395, "k_tangent_prep": 1199293573, "k_tangent_gemv": 280761828, "k_coarse_galerkin": 211827691, "k_coarse_lu": 1406956, "k_coarse_inverse": 12186622, "k_coarse_apply_inverse": 4089522, "k_mdot_partial": 25635868, "k_maxpy": 48707194, "k_prolong": 27170961, "k_coarse_ty": 20655149}}
 
 
-def _factor_bytes(case, elem_bytes):
-    """Band factor storage per subdomain: L and U, n_i (2 kl_i + ku_i + 1),
-    and U alone, n_i (kl_i + ku_i + 1)."""
+def unit_work(case, elem_bytes=8):
+    """Algorithmic work of one unit (one local Newton iteration of one
+    subdomain) per subdomain, as the hot-path table counts it: residual
+    bytes 8 (3 n_i + |Gamma_i|) (x, trace and load in, r out); Jacobian
+    bytes 8 x 7 n_i (the sparse nonzeros out, 7 per row for P1); band factor
+    bytes n_i (2 kl_i + ku_i + 1) x elem_bytes (the 3w + 1 stored diagonals);
+    band LU flops 2 n_i kl_i^2 (w = kl)."""
     from paper_2410_24138_amd import nls
     m = nls.inspect_partition(case)
-    n = m["off_v"][1:] - m["off_v"][:-1]
-    ng = m["off_g"][1:] - m["off_g"][:-1]
-    fac = (n * (2 * m["kl"] + m["ku"] + 1)).astype(float) * elem_bytes
-    facu = (n * (m["kl"] + m["ku"] + 1)).astype(float) * elem_bytes
-    return fac, n.astype(float), ng.astype(float), facu
+    n = (m["off_v"][1:] - m["off_v"][:-1]).astype(float)
+    ng = (m["off_g"][1:] - m["off_g"][:-1]).astype(float)
+    kl, ku = m["kl"].astype(float), m["ku"].astype(float)
+    return {"residual": 8.0 * (3 * n + ng), "jacobian": 8.0 * 7 * n,
+            "factor": n * (2 * kl + ku + 1) * elem_bytes, "lu_flops": 2.0 * n * kl * kl,
+            "n": n, "ng": ng, "kl": kl, "ku": ku}
 
 
-def cpu_baseline(case, n_sample=256, passes=2):
-    """The oracle's local nonlinear solves T_i(0) (the first evaluation of a
-    solve) over a sample of subdomains, repeated `passes` times (about 10 s
-    of host work at the 512x512 workload)."""
-    import numpy as np
+def _cpu_model():
+    """CPU model name, sockets, physical cores and hardware threads of this
+    host (from lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    info = {"model": None, "sockets": None, "physical_cores": None, "threads": os.cpu_count()}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        kv = {}
+        for line in out.splitlines():
+            if ":" in line:
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+        info["model"] = kv.get("Model name")
+        sockets = int(kv.get("Socket(s)", "0") or 0)
+        cps = int(kv.get("Core(s) per socket", "0") or 0)
+        info["sockets"] = sockets or None
+        info["physical_cores"] = sockets * cps or None
+        info["threads"] = int(kv.get("CPU(s)", info["threads"] or 0) or 0) or info["threads"]
+    except Exception:
+        pass
+    if info["model"] is None:
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    info["model"] = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+    return info
+
+
+def cpu_baseline(case):
+    """The oracle's full solve of the workload (outer Newton to 1e-8, the
+    benchmark's settings) on the host, timed from u = 0 to the converged
+    iterate with the set-up (maps, GDSW basis) timed apart; one BLAS thread
+    (the oracle's loops are serial Python, its local LU a LAPACK band
+    factorisation per subdomain).  Value: local nonlinear solves per second
+    of solve time, the GPU line's unit."""
+    import contextlib
     from oracle import P1Problem, Schwarz
     try:
-        from threadpoolctl import threadpool_info
-        cores = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+        from threadpoolctl import threadpool_limits
+        one_thread = threadpool_limits(limits=1)
     except Exception:
-        cores = os.cpu_count() or 1
-    S = Schwarz(P1Problem(case), "one_level")
-    idx = np.linspace(0, S.n_sub - 1, n_sample).astype(int)
-    u = np.zeros(S.P.N)
-    t0 = time.perf_counter()
-    its = 0
-    for _ in range(passes):
-        for i in idx:
-            its += S.local_solve(int(i), u)["its"]
-    dt = time.perf_counter() - t0
-    return {"value": passes * len(idx) / dt, "unit": "subdomain Newton solves/s",
-            "cores": int(cores), "kind": "oracle",
-            "sample": f"oracle local solves T_i(u=0) of {len(idx)} of the {S.n_sub} subdomains "
-                      f"(the first evaluation of a solve), {passes} passes, {its} Newton steps, "
-                      f"dense LAPACK LU, {dt:.1f} s"}
+        one_thread = contextlib.nullcontext()
+    with one_thread:
+        t0 = time.perf_counter()
+        S = Schwarz(P1Problem(case), "additive" if case.get("two_level") else "one_level")
+        t_setup = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        u, st = S.solve(rtol=1e-8, gmres_rtol=1e-6, gmres_restart=50, gmres_maxit=1000)
+        t_solve = time.perf_counter() - t0
+    solves = S.n_sub * (st["outer"] + 1)
+    cpu = _cpu_model()
+    return {"value": round(solves / t_solve, 2), "unit": "subdomain Newton solves/s",
+            "cores": 1, "kind": "oracle",
+            "time_to_1e-8_ms": round(1e3 * t_solve, 1), "setup_ms": round(1e3 * t_setup, 1),
+            "outer_its": st["outer"], "gmres_its": st["gmres"], "inner_its": st["inner"],
+            "converged": bool(st["converged"]),
+            "host": cpu,
+            "sample": f"the oracle's whole solve of {case['name']} from u = 0 to outer rtol "
+                      f"1e-8 ({solves} local nonlinear solves in {st['outer'] + 1} "
+                      f"evaluations, {sum(st['inner'])} local Newton steps, band LAPACK LU), "
+                      f"one thread on {cpu.get('model')}"}
 
 
 def make_solver(case, form, device_index=0, **kw):
@@ -459,6 +505,47 @@ def run_beam(device, forces=BEAM_FORCES, nx=320, ny=64, boxes=(20, 4)):
             "settings": opts, "runs": rows}
 
 
+def run_assembly(device, reps=50):
+    """The assembly step on its own at the 512x512 workload: nls_eval_local
+    (local residual and Jacobian rows of all 256 subdomains at x = R_i u)
+    called reps times; the kernel's duration comes from the kernel trace of
+    this run (each call synchronises, so the wall time per call includes
+    the launch).  Prints the bytes a launch moves."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2410_24138_amd import Solver
+    case = synth.config2()
+    with np.load(os.path.join(ROOT, "tests", "golden", case["name"] + ".npz")) as z:
+        u = torch.from_numpy(z["u"]).to(device)
+    s = Solver(case)
+    pat = s.local_pattern()
+    rows = len(pat["row_dof"])
+    nnz = len(pat["col"])
+    ng = len(pat["gamma_dof"])
+    r = torch.empty(rows, dtype=torch.float64, device=device)
+    jv = torch.empty(nnz, dtype=torch.float64, device=device)
+    for _ in range(3):
+        s.eval_local(u, r=r, jval=jv)
+    torch.cuda.synchronize(device)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        s.eval_local(u, r=r, jval=jv)
+    torch.cuda.synchronize(device)
+    wall_us = 1e6 * (time.perf_counter() - t0) / reps
+    for _ in range(reps):
+        s.eval_local(u, r=r, jacobian=False)
+    torch.cuda.synchronize(device)
+    s.close()
+    alg = 8.0 * (3 * rows + ng) + 8.0 * nnz
+    alg_res = 8.0 * (3 * rows + ng)
+    return {"workload": case["name"], "kernel": "k_local_assemble",
+            "rows": rows, "nnz": nnz, "gamma": ng, "reps": reps,
+            "algorithmic_bytes_per_launch": alg,
+            "algorithmic_bytes_residual_only": alg_res,
+            "wall_us_per_call_incl_launch_and_sync": round(wall_us, 2)}
+
+
 def measured_traffic(kernel):
     """Counter-measured HBM bytes of a kernel, or None if the source changed."""
     import hashlib
@@ -476,36 +563,41 @@ def _local_fp64(res, form):
 
 
 def roofline(case, res, form):
-    """Dominant kernel and its HBM roofline fraction from algorithmic bytes."""
+    """Roofline of the dominant kernel (the fused local Newton kernel, by
+    event-timed share of the solve): achieved = algorithmic bytes per launch
+    / average launch duration, the bytes being the per-unit figure (residual
+    + Jacobian + band factor, unit_work) times the units one launch
+    processes (the local Newton iterations of that evaluation, from the
+    measured counts).  Also reported: the band-LU flop rate against the
+    FP64 peak, the implementation's own bytes per launch (factors written
+    and read back, Jacobian written and read), and the counter-measured
+    HBM traffic where it was taken for this kernel source."""
     elem = 8 if _local_fp64(res, form) else 4
-    fac, n, ng, facu = _factor_bytes(case, elem)
-    kern = res["kernels"]
-    k_t, k_l = kern["tangent_local"], kern["local_newton"]
-    if k_t["ms"] >= k_l["ms"]:
-        name, k = "tangent_local", k_t
-        # per launch: every subdomain streams its band factors once (twice
-        # more per refinement sweep in mixed mode is not counted), gathers
-        # v on Gamma_i and writes z_i
-        per_launch = float(fac.sum() + 8 * (ng.sum() + n.sum()))
-    else:
-        name, k = "local_newton", k_l
-        # per launch: k_i factorizations write L and U (the forward
-        # substitution rides along) and k_i backward solves read U (the
-        # factorisation at x* for the tangent runs in its own kernel when
-        # GMRES needs it); J values written and read; u gathered, T, x* and
-        # the Gamma values written.  Averaged over subdomains with the
-        # measured totals.
-        launches = max(k["launches"], 1)
-        mean_its = res["inner_its_steps"] / (launches * len(n))
-        jac = 8 * 2 * 7 * n + 8 * 2 * n  # ~7 nonzeros per row, written and read; residual
-        per_sub = mean_its * (fac + jac + facu) + 8 * (n + 2 * ng + 2 * n)
-        per_launch = float(per_sub.sum())
-    avg_s = k["ms"] / max(k["launches"], 1) / 1e3
+    w = unit_work(case, elem)
+    k = res["kernels"]["local_newton"]
+    launches = max(k["launches"], 1)
+    units_per_launch = res["inner_its_steps"] / launches
+    per_unit = float(np.mean(w["residual"] + w["jacobian"] + w["factor"]))
+    per_launch = units_per_launch * per_unit
+    flops = units_per_launch * float(np.mean(w["lu_flops"]))
+    avg_s = k["ms"] / launches / 1e3
     achieved = per_launch / avg_s / 1e9
-    traffic = measured_traffic("k_" + name) if _local_fp64(res, form) else None
-    return {"kernel": name, "bound": "hbm", "achieved": round(achieved, 1),
+    # implementation: per step L and U written, U read by the backward
+    # solve, J written and read, vectors
+    n, ng, kl, ku = w["n"], w["ng"], w["kl"], w["ku"]
+    fac = n * (2 * kl + ku + 1) * elem
+    facu = n * (kl + ku + 1) * elem
+    impl = units_per_launch * float(np.mean(fac + facu + 8 * 2 * 7 * n + 8 * 2 * n))
+    traffic = measured_traffic("k_local_newton") if _local_fp64(res, form) else None
+    return {"kernel": "k_local_newton", "bound": "hbm", "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic, "bytes_per_launch": per_launch,
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": round(per_launch),
+            "bytes_per_unit": round(per_unit), "units_per_launch": round(units_per_launch, 2),
+            "implementation_bytes_per_launch": round(impl),
+            "traffic_over_algorithmic": round(traffic / per_launch, 3) if traffic else None,
+            "lu_flops_per_launch": round(flops), "lu_tflops": round(flops / avg_s / 1e12, 3),
+            "lu_flop_frac_fp64": round(flops / avg_s / 78.6e12, 5),
             "avg_launch_us": round(avg_s * 1e6, 2), "launches": k["launches"]}
 
 
@@ -518,7 +610,8 @@ def main():
                     default="plain,fp64_tuned,chosen,fp32_ir,bf16_ir,fp64_tuned_chord,"
                             "fp64_tuned_rgdsw")
     ap.add_argument("--workload", default="diffusion512",
-                    choices=["diffusion512", "batch", "learned", "elasticity", "beam"])
+                    choices=["diffusion512", "batch", "learned", "elasticity", "beam",
+                             "assembly"])
     ap.add_argument("--amp", type=float, default=10.0,
                     help="forcing amplitude of the learned workload")
     ap.add_argument("--train-seeds", type=int, default=130)
@@ -548,6 +641,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize(device)
         del src, dst
+    if args.workload == "assembly":
+        print(json.dumps(run_assembly(device)), flush=True)
+        return
     if args.workload == "batch":
         print(json.dumps(run_batch(args.steps, args.warmup, device)), flush=True)
         return

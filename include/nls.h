@@ -326,6 +326,27 @@ int nls_eval_precond_residual(nls_handle* h, const double* u_dev,
    (eqs. (6), (7), (12)).  Errors: NLS_ESTATE if no state is kept. */
 int nls_apply_tangent(nls_handle* h, const double* v_dev, double* y_dev);
 
+/* Standalone local assembly (eqs. (3)-(4) at the first local iterate
+   x = R_i u): for every subdomain the local residual R_i F(u) (at x = R_i u
+   it equals the rows of F(u) at V_i, assembled from the patch elements
+   only) into r_dev, sum_i |V_i| values in packed order, and, if jval_dev is
+   not NULL, the values of the local Jacobian rows [J_ii | B_i] = R_i DF(u)
+   restricted to the patch, in the CSR pattern of nls_get_local_pattern.
+   Device pointers.  The same element kernels as the local Newton solves,
+   without the factorisation: the assembly step on its own. */
+int nls_eval_local(nls_handle* h, const double* u_dev, double* r_dev, double* jval_dev);
+
+/* Row layout of the local problems and the CSR pattern of [J_ii | B_i]
+   (host arrays).  Call with off_v == NULL to get counts[0] = sum_i |V_i|
+   (packed rows), counts[1] = nonzeros, counts[2] = sum_i |Gamma_i|; then
+   off_v (n_sub + 1): the rows of subdomain i are [off_v[i], off_v[i+1]);
+   row_dof (counts[0]): global dof of each packed row; off_g (n_sub + 1) and
+   gamma_dof (counts[2]): the Gamma_i dofs; rowptr (counts[0] + 1) and col
+   (counts[1]): patch-local columns, c < n_i the c-th row of the subdomain,
+   c >= n_i its (c - n_i)-th Gamma_i dof.  Any output may be NULL. */
+int nls_get_local_pattern(nls_handle* h, int64_t* counts, int32_t* off_v, int32_t* row_dof,
+                          int32_t* off_g, int32_t* gamma_dof, int64_t* rowptr, int32_t* col);
+
 /* Local Newton iteration counts of the last evaluation, n_sub ints (host). */
 int nls_get_inner_iterations(nls_handle* h, int32_t* its_host);
 

@@ -1827,6 +1827,43 @@ extern "C" int nls_apply_tangent(nls_handle* h, const double* v, double* y) {
     return sync(h);
 }
 
+extern "C" int nls_eval_local(nls_handle* h, const double* u, double* r, double* jval) {
+    if (!h || !u || !r) return NLS_EINVAL;
+    if (!h->have_part) return fail(h, NLS_ESTATE, "nls_set_partition first");
+    HIPCHK(hipSetDevice(h->opt.device));
+    const HostMaps& M = h->maps;
+    int maxn = 0, maxp = 0;
+    for (int i = 0; i < M.nsub; ++i) {
+        const int n = M.off_n[i + 1] - M.off_n[i], ng = M.off_g[i + 1] - M.off_g[i];
+        maxn = std::max(maxn, n);
+        maxp = std::max(maxp, n + ng);
+    }
+    if (maxp * 8 > 160 * 1024) return fail(h, NLS_ELIMIT, "patch values exceed LDS");
+    HIPCHK(launch_local_assemble(h->dm, h->dp, u, r, jval, maxn, maxp * 8, h->stream));
+    return sync(h);
+}
+
+extern "C" int nls_get_local_pattern(nls_handle* h, int64_t* counts, int32_t* off_v,
+                                     int32_t* row_dof, int32_t* off_g, int32_t* gamma_dof,
+                                     int64_t* rowptr, int32_t* col) {
+    if (!h) return NLS_EINVAL;
+    if (!h->have_part) return fail(h, NLS_ESTATE, "nls_set_partition first");
+    const HostMaps& M = h->maps;
+    const int64_t nrows = M.off_n.back(), nnz = M.jcol.size(), ngam = M.off_g.back();
+    if (counts) {
+        counts[0] = nrows;
+        counts[1] = nnz;
+        counts[2] = ngam;
+    }
+    if (off_v) std::copy(M.off_n.begin(), M.off_n.end(), off_v);
+    if (row_dof) std::copy(M.l2g.begin(), M.l2g.end(), row_dof);
+    if (off_g) std::copy(M.off_g.begin(), M.off_g.end(), off_g);
+    if (gamma_dof) std::copy(M.g2g.begin(), M.g2g.end(), gamma_dof);
+    if (rowptr) std::copy(M.jptr.begin(), M.jptr.begin() + nrows + 1, rowptr);
+    if (col) std::copy(M.jcol.begin(), M.jcol.end(), col);
+    return NLS_OK;
+}
+
 extern "C" int nls_get_inner_iterations(nls_handle* h, int32_t* its) {
     if (!h || !its) return NLS_EINVAL;
     if (!h->have_part) return fail(h, NLS_ESTATE, "nls_set_partition first");

@@ -354,6 +354,103 @@ __device__ __forceinline__ void local_jacobian(const DevMesh& M, const DevMaps& 
 }
 
 // ----------------------------------------------------------------------------
+// Residual and Jacobian rows of one local problem in one pass (the
+// standalone assembly of eqs. (3)-(4) at the patch values vp): rows
+// [a0, a1) of subdomain i, one row per thread, the row's CSR slots
+// accumulated in registers and written once.  r[a] = R_i F(v)[a]; jval
+// (may be null) the values of [J_ii | B_i] in the fixed CSR slots.  Rows
+// with more slots than MS (unstructured meshes of high valence) add into
+// jval in place.
+// ----------------------------------------------------------------------------
+template <bool ELAST>
+__device__ __forceinline__ void assemble_rows(const DevMesh& M, const DevMaps& P, int n, int rowbase,
+                                              int ebase, const double* vp, int a0, int a1,
+                                              double* __restrict__ r, double* __restrict__ jval) {
+    constexpr int MS = ELAST ? 18 : 10;
+    for (int a = a0 + threadIdx.x; a < a1; a += blockDim.x) {
+        const int row = rowbase + a;
+        const int g = P.l2g[row];
+        const int js = P.jptr[row], je = P.jptr[row + 1];
+        const bool inreg = jval && je - js <= MS;
+        int cl[MS];
+        double acc[MS];
+#pragma unroll
+        for (int t = 0; t < MS; ++t) {
+            cl[t] = (inreg && js + t < je) ? P.jcol[js + t] : -1;
+            acc[t] = 0.0;
+        }
+        if (jval && !inreg)
+            for (int s = js; s < je; ++s) jval[s] = 0.0;
+        auto add = [&](int col, double K) {
+            if (!jval) return;
+            if (inreg) {
+#pragma unroll
+                for (int t = 0; t < MS; ++t) acc[t] += (cl[t] == col) ? K : 0.0;
+            } else {
+                for (int t = js; t < je; ++t)
+                    if (P.jcol[t] == col) { jval[t] += K; break; }
+            }
+        };
+        double res;
+        if (M.dflag[g]) {
+            res = vp[a] - M.dval[g];
+            if (jval) add(a, 1.0);
+        } else if (ELAST) {
+            const int c = a & 1;
+            double f = 0.0;
+            bool ok = true;
+            for (int k = P.rinc_ptr[row]; k < P.rinc_ptr[row + 1]; ++k) {
+                const int code = P.rinc[k];
+                const int e = ebase + (code >> 2), pos = code & 3;
+                double X[4][2], ue[4][2];
+                int nd[4];
+                nh_coords(M, P.pe_gid[e], X);
+                nh_local_values(P, e, vp, nd, ue);
+                f += nh_force(M, X, ue, pos, c, ok);
+                if (jval) {
+                    double kr[4][2];
+                    nh_stiff_row(M, X, ue, pos, c, kr);
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+#pragma unroll
+                        for (int kk = 0; kk < 2; ++kk) add(2 * nd[b] + kk, kr[b][kk]);
+                }
+            }
+            res = ok ? f - M.bload[g] : __builtin_nan("");
+        } else {
+            double f = 0.0;
+            for (int k = P.rinc_ptr[row]; k < P.rinc_ptr[row + 1]; ++k) {
+                const int code = P.rinc[k];
+                const int e = ebase + (code >> 2), pos = code & 3;
+                const int nd[3] = {P.pe_conn[3 * e], P.pe_conn[3 * e + 1], P.pe_conn[3 * e + 2]};
+                const double uu[3] = {vp[nd[0]], vp[nd[1]], vp[nd[2]]};
+                const int ge = P.pe_gid[e];
+                const double U = uu[0] + uu[1] + uu[2];
+                const double m = (U * U + uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2]) * (1.0 / 12.0);
+                double gr[3];
+                g_row(M.G6 + 6 * (size_t)ge, pos, gr[0], gr[1], gr[2]);
+                const double sg = gr[0] * uu[0] + gr[1] * uu[1] + gr[2] * uu[2];
+                const double kap = M.kappa[ge];
+                const double coef = kap * (1.0 + M.beta * m);
+                f += coef * sg;
+                if (jval) {
+                    const double rk = M.beta * kap * sg * (1.0 / 6.0);
+#pragma unroll
+                    for (int cc = 0; cc < 3; ++cc) add(nd[cc], coef * gr[cc] + rk * (U + uu[cc]));
+                }
+            }
+            res = f - M.bload[g];
+        }
+        r[a] = res;
+        if (jval && inreg) {
+#pragma unroll
+            for (int t = 0; t < MS; ++t)
+                if (js + t < je) jval[js + t] = acc[t];
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
 // Band LU with partial pivoting of an n x n matrix with kl sub- and ku
 // superdiagonals, rows given in CSR (columns >= n are ignored).  The whole
 // workgroup cooperates.  Results:
@@ -1222,6 +1319,36 @@ k_local_newton(DevMesh M, DevMaps P, DevLocal L, NewtonParams np, const double* 
 }
 
 // ----------------------------------------------------------------------------
+// ----------------------------------------------------------------------------
+// Standalone local assembly (A1-A3) at x = R_i u for every subdomain: Q
+// blocks per subdomain, block q stages the patch values of subdomain i in
+// LDS and assembles rows [256 q, 256 (q + 1)).  r: packed local residuals;
+// jval (or null): packed CSR values of [J_ii | B_i].  XCD-aware order:
+// workgroups go to the eight XCDs in turn (block b to XCD b mod 8), so the
+// Q blocks of subdomain i are placed at b = 8 j + (i mod 8) with consecutive
+// j: they run together in the L2 of one XCD, which then serves the element
+// data the neighbouring rows share.
+// ----------------------------------------------------------------------------
+template <bool ELAST>
+__global__ void __launch_bounds__(256)
+k_local_assemble(DevMesh M, DevMaps P, const double* __restrict__ u, double* __restrict__ r,
+                 double* __restrict__ jval, int Q) {
+    extern __shared__ double smem[];
+    const int x = blockIdx.x & 7, j = blockIdx.x >> 3;
+    const int i = x + 8 * (j / Q);
+    if (i >= P.nsub) return;
+    const int rowbase = P.off_n[i], n = P.off_n[i + 1] - rowbase;
+    const int a0 = (j % Q) * blockDim.x;
+    if (a0 >= n) return;
+    const int gbase = P.off_g[i], ng = P.off_g[i + 1] - gbase;
+    double* vp = smem;
+    for (int a = threadIdx.x; a < n; a += blockDim.x) vp[a] = u[P.l2g[rowbase + a]];
+    for (int j = threadIdx.x; j < ng; j += blockDim.x) vp[n + j] = u[P.g2g[gbase + j]];
+    __syncthreads();
+    assemble_rows<ELAST>(M, P, n, rowbase, P.off_e[i], vp, a0, min(n, a0 + (int)blockDim.x),
+                         r + rowbase, jval);
+}
+
 // Multi right-hand-side band solve X = J^{-1} R with the FP64 factors of
 // band_lu: one right-hand side per lane (column c = blockIdx.y*256 + tid).
 // Each lane keeps its forward window (KL+1 rows) and its backward window of
@@ -2716,6 +2843,25 @@ hipError_t launch_local_newton(const DevMesh& M, const DevMaps& P, const DevLoca
         if (npl <= 1) { NLS_LN(1, false) } else if (npl == 2) { NLS_LN(2, false) } else { NLS_LN(4, false) }
     }
 #undef NLS_LN
+    return hipGetLastError();
+}
+
+hipError_t launch_local_assemble(const DevMesh& M, const DevMaps& P, const double* u, double* r,
+                                 double* jval, int max_rows, int lds_bytes, hipStream_t s) {
+    // blocks per subdomain, and 8 XCD slots each holding ceil(nsub / 8)
+    // subdomains' worth of blocks
+    const int Q = (max_rows + 255) / 256;
+    const int grid = 8 * Q * ((P.nsub + 7) / 8);
+    hipError_t e;
+    if (M.kind == NLS_PROBLEM_NEOHOOKE) {
+        e = set_lds(k_local_assemble<true>, lds_bytes);
+        if (e != hipSuccess) return e;
+        k_local_assemble<true><<<grid, 256, lds_bytes, s>>>(M, P, u, r, jval, Q);
+    } else {
+        e = set_lds(k_local_assemble<false>, lds_bytes);
+        if (e != hipSuccess) return e;
+        k_local_assemble<false><<<grid, 256, lds_bytes, s>>>(M, P, u, r, jval, Q);
+    }
     return hipGetLastError();
 }
 

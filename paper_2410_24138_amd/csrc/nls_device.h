@@ -128,6 +128,11 @@ hipError_t launch_global_residual(const DevMesh& M, const double* u, double* F,
 hipError_t launch_local_newton(const DevMesh& M, const DevMaps& P, const DevLocal& L,
                                const NewtonParams& np, const double* u, int nblk, int lds_bytes,
                                int nb_per_lane, hipStream_t s);
+// Standalone local assembly at x = R_i u: packed residuals r and CSR values
+// jval (may be null) of every subdomain; max_rows = largest |V_i| rows,
+// lds_bytes = 8 (|V_i| + |Gamma_i|) of the largest patch.
+hipError_t launch_local_assemble(const DevMesh& M, const DevMaps& P, const double* u, double* r,
+                                 double* jval, int max_rows, int lds_bytes, hipStream_t s);
 hipError_t launch_prolong(const DevMesh& M, const DevMaps& P, const double* T,
                           const DevCoarse* C, const double* cvec, double* out,
                           const double* addv, hipStream_t s);

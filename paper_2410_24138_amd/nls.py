@@ -58,6 +58,7 @@ SYMBOLS = (
     "nls_build_coarse", "nls_solve", "nls_eval_residual",
     "nls_eval_precond_residual", "nls_apply_tangent",
     "nls_get_inner_iterations", "nls_get_sizes", "nls_get_coarse_basis",
+    "nls_eval_local", "nls_get_local_pattern",
     "nls_strerror", "nls_last_error", "nls_inspect_partition",
     "nls_inspect_coarse", "nls_set_load", "nls_guess_set_model",
     "nls_guess_get_model", "nls_guess_enable", "nls_guess_capture",
@@ -155,6 +156,8 @@ def load() -> ctypes.CDLL:
         "nls_eval_precond_residual": ([P, P, P], ctypes.c_int),
         "nls_apply_tangent": ([P, P, P], ctypes.c_int),
         "nls_get_inner_iterations": ([P, P], ctypes.c_int),
+        "nls_eval_local": ([P, P, P, P], ctypes.c_int),
+        "nls_get_local_pattern": ([P, P, P, P, P, P, P, P], ctypes.c_int),
         "nls_get_sizes": ([P, P, P, P], ctypes.c_int),
         "nls_get_coarse_basis": ([P, ctypes.POINTER(i64), P, P, P], ctypes.c_int),
         "nls_strerror": ([ctypes.c_int], ctypes.c_char_p),
@@ -428,6 +431,39 @@ class Solver:
         y = self.torch.empty_like(v)
         self._check(self.lib.nls_apply_tangent(self.h, self._vp(v), self._vp(y)))
         return y
+
+    def local_pattern(self):
+        """Packed row layout of the local problems and the CSR pattern of
+        [J_ii | B_i] (numpy arrays, see nls_get_local_pattern)."""
+        cnt = np.zeros(3, np.int64)
+        self._check(self.lib.nls_get_local_pattern(self.h, _ptr(cnt), None, None, None, None,
+                                                   None, None))
+        ns = int(self.case["n_sub"])
+        out = {"off_v": np.zeros(ns + 1, np.int32), "row_dof": np.zeros(cnt[0], np.int32),
+               "off_g": np.zeros(ns + 1, np.int32), "gamma_dof": np.zeros(cnt[2], np.int32),
+               "rowptr": np.zeros(cnt[0] + 1, np.int64), "col": np.zeros(cnt[1], np.int32)}
+        self._check(self.lib.nls_get_local_pattern(
+            self.h, _ptr(cnt), _ptr(out["off_v"]), _ptr(out["row_dof"]), _ptr(out["off_g"]),
+            _ptr(out["gamma_dof"]), _ptr(out["rowptr"]), _ptr(out["col"])))
+        return out
+
+    def eval_local(self, u, jacobian=True, r=None, jval=None):
+        """Standalone local assembly at x = R_i u: packed local residuals and
+        (if jacobian) the CSR values of [J_ii | B_i].  Output tensors may be
+        passed in (float64, on the device) to avoid allocation."""
+        t = self.torch
+        u = self._dev(u)
+        if r is None or (jacobian and jval is None):
+            cnt = np.zeros(3, np.int64)
+            self._check(self.lib.nls_get_local_pattern(self.h, _ptr(cnt), None, None, None,
+                                                       None, None, None))
+            if r is None:
+                r = t.empty(int(cnt[0]), dtype=t.float64, device=self.device)
+            if jacobian and jval is None:
+                jval = t.empty(int(cnt[1]), dtype=t.float64, device=self.device)
+        self._check(self.lib.nls_eval_local(self.h, self._vp(u), self._vp(r),
+                                            self._vp(jval) if jacobian else None))
+        return r, jval
 
     def inner_iterations(self):
         n_sub, _, _ = self.sizes()

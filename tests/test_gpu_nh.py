@@ -236,3 +236,30 @@ def test_structured_q1_mesh_and_load_factor():
     uu, st, rc = b.solve(load_factor=0.5)
     assert rc == 0 and st["outer_its"] == st_ref["outer"]
     assert np.linalg.norm(_np(uu) - u_ref) <= 1e-10 * np.linalg.norm(u_ref)
+
+
+def test_standalone_local_assembly_elasticity():
+    """nls_eval_local on Neo-Hooke (2 dofs per node, 2x2 Gauss): residual
+    and [J_ii | B_i] rows against the oracle, by global dof."""
+    from tests.test_gpu_parity import _local_parts
+    case = synth.small_elasticity_case(nx=12, ny=8, boxes=(3, 2), overlap=2,
+                                       traction=(0.5, -2.0), two_level=False)
+    P = NHProblem(case)
+    S = Schwarz(P, "one_level")
+    u = _probe(P, 4)
+    s = _solver(case, coupling="one_level")
+    for i, (vd, r, J) in enumerate(_local_parts(s, u)):
+        sub = S.subs[i]
+        ro = S.local_residual(i, u[sub["Vd"]], u[sub["Gd"]])
+        Jo, Bo = S.local_jacobian(i, u[sub["Vd"]], u[sub["Gd"]])
+        pos = {int(g): k for k, g in enumerate(sub["Vd"])}
+        order = np.array([pos[int(g)] for g in vd])
+        assert np.abs(r - ro[order]).max() <= 1e-12 * np.abs(ro).max()
+        cols = np.concatenate([sub["Vd"], sub["Gd"]])
+        Jfull = np.concatenate([Jo, Bo], axis=1)
+        jscale = np.abs(Jfull).max()
+        for a in range(len(sub["Vd"])):
+            for c in np.nonzero(Jfull[a])[0]:
+                key = (int(sub["Vd"][a]), int(cols[c]))
+                assert abs(J.get(key, 0.0) - Jfull[a, c]) <= 1e-12 * jscale, key
+        assert len(J) >= np.count_nonzero(Jfull)

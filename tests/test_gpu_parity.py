@@ -421,3 +421,56 @@ def test_coarse_basis_at_linearisation_point():
     uu, st, rc = _solver(case, coupling="additive", coarse_lin=u_lin).solve()
     assert rc == 0 and st["outer_its"] == st_ref["outer"]
     assert np.linalg.norm(_np(uu) - u_ref) <= 1e-10 * np.linalg.norm(u_ref)
+
+
+def _local_parts(s, u):
+    """GPU standalone assembly mapped to global dof ids: per subdomain the
+    residual rows and the Jacobian rows as {(row dof, col dof): value}."""
+    pat = s.local_pattern()
+    r, jv = s.eval_local(u)
+    r, jv = _np(r), _np(jv)
+    out = []
+    for i in range(len(pat["off_v"]) - 1):
+        a0, a1 = pat["off_v"][i], pat["off_v"][i + 1]
+        vd = pat["row_dof"][a0:a1]
+        gd = pat["gamma_dof"][pat["off_g"][i]:pat["off_g"][i + 1]]
+        colmap = np.concatenate([vd, gd])
+        J = {}
+        for a in range(a1 - a0):
+            for t in range(pat["rowptr"][a0 + a], pat["rowptr"][a0 + a + 1]):
+                J[(int(vd[a]), int(colmap[pat["col"][t]]))] = jv[t]
+        out.append((vd, r[a0:a1], J))
+    return out
+
+
+@pytest.mark.parametrize("kw", [dict(n=16, boxes=4, overlap=2, forcing_seed=3, coef_seed=2),
+                                dict(n=13, boxes=3, overlap=1, uneven=True)])
+def test_standalone_local_assembly(kw):
+    """nls_eval_local (A1-A3 on their own): the local residual R_i F(u) and
+    the rows [J_ii | B_i] of every subdomain at x = R_i u against the
+    oracle's local residual and Jacobian (patch elements only), mapped by
+    global dof."""
+    case = synth.small_case(**kw)
+    P = P1Problem(case)
+    S = Schwarz(P, "one_level")
+    u = _probe_point(P, case)
+    s = _solver(case)
+    for i, (vd, r, J) in enumerate(_local_parts(s, u)):
+        sub = S.subs[i]
+        ro = S.local_residual(i, u[sub["Vd"]], u[sub["Gd"]])
+        Jo, Bo = S.local_jacobian(i, u[sub["Vd"]], u[sub["Gd"]])
+        pos = {int(g): k for k, g in enumerate(sub["Vd"])}
+        order = np.array([pos[int(g)] for g in vd])
+        scale = max(np.abs(ro).max(), 1e-300)
+        assert np.abs(r - ro[order]).max() <= 1e-13 * scale
+        cols = np.concatenate([sub["Vd"], sub["Gd"]])
+        Jfull = np.concatenate([Jo, Bo], axis=1)
+        jscale = np.abs(Jfull).max()
+        dense = {}
+        for a in range(len(sub["Vd"])):
+            for c in np.nonzero(Jfull[a])[0]:
+                dense[(int(sub["Vd"][a]), int(cols[c]))] = Jfull[a, c]
+        for key, v in dense.items():
+            assert abs(J.get(key, 0.0) - v) <= 1e-13 * jscale, key
+        for key, v in J.items():
+            assert abs(dense.get(key, 0.0) - v) <= 1e-13 * jscale, key
