@@ -288,6 +288,22 @@ int nls_set_load(nls_handle* h, const double* elem_load);
 int nls_solve(nls_handle* h, double* u, int u_on_device, double load_factor,
               nls_stats* st);
 
+/* A batch of independent problems, one handle each (hs[k], n distinct
+   handles, each set up completely): every handle runs nls_solve (outer
+   Newton, eq. (13), with its own stopping rule, GMRES and local and coarse
+   solves) on its own iterate us[k] (device pointer if u_on_device[k],
+   u_on_device may be NULL for host arrays), at the same time as the others:
+   one host thread per handle (at most 32 at once, taking the handles in
+   order), so the kernels of handles on different streams run on the device
+   together; handles sharing a stream run in that stream's order.  Results
+   are those of solving each problem alone.  codes[k] receives each
+   instance's return code and sts[k] (or NULL) its statistics.  Returns
+   NLS_OK if every instance converged, the first negative code in index
+   order if any failed, else NLS_ENOCONV.  NLS_EINVAL on null or repeated
+   handles. */
+int nls_solve_batch(nls_handle* const* hs, int n, double* const* us,
+                    const int* u_on_device, nls_stats* sts, int* codes);
+
 /* Load stepping (continuation, Section 3 of the paper: the beam load is
    increased in steps): the external load is set to s / n_steps of its
    full value (nodal forces, or the load samples of the diffusion problem)

@@ -13,8 +13,10 @@
 //   Newton   u <- u - du (eq. 13).
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <memory>
 #include <numeric>
+#include <thread>
 
 #include "handle.h"
 
@@ -1631,6 +1633,48 @@ static int solve_impl(nls_handle* h, double* u, int u_on_device, nls_stats* st) 
         if (!std::isfinite(S->res_final)) return finish(fail(h, NLS_ENAN, "F_x is not finite"));
     }
     return finish(S->converged ? NLS_OK : NLS_ENOCONV);
+}
+
+// Independent solves (a batch of problems, each with its own handle): every
+// handle runs its own outer Newton iteration (eq. 13) with its own stopping
+// rule and status, driven by a host thread of its own (at most
+// NLS_BATCH_THREADS at a time, taking handles in order), so that the work of
+// handles on different streams runs on the device at the same time.
+#define NLS_BATCH_THREADS 32
+extern "C" int nls_solve_batch(nls_handle* const* hs, int n, double* const* us,
+                               const int* u_on_device, nls_stats* sts, int* codes) {
+    if (!hs || !us || !codes || n < 1) return NLS_EINVAL;
+    for (int k = 0; k < n; ++k)
+        if (!hs[k] || !us[k]) return NLS_EINVAL;
+    {
+        std::vector<nls_handle*> v(hs, hs + n);
+        std::sort(v.begin(), v.end());
+        if (std::adjacent_find(v.begin(), v.end()) != v.end()) return NLS_EINVAL;
+    }
+    std::atomic<int> next{0};
+    auto work = [&]() {
+        for (;;) {
+            const int k = next.fetch_add(1);
+            if (k >= n) break;
+            codes[k] = nls_solve(hs[k], us[k], u_on_device ? u_on_device[k] : 0, 1.0,
+                                 sts ? sts + k : nullptr);
+        }
+    };
+    std::vector<std::thread> pool;
+    const int nw = std::min(n, NLS_BATCH_THREADS);
+    try {
+        for (int w = 1; w < nw; ++w) pool.emplace_back(work);
+    } catch (...) {
+        // fewer threads: the ones started and this one take the rest
+    }
+    work();
+    for (auto& t : pool) t.join();
+    int rc = NLS_OK;
+    for (int k = 0; k < n; ++k) {
+        if (codes[k] < 0) return codes[k];
+        if (codes[k] > 0) rc = NLS_ENOCONV;
+    }
+    return rc;
 }
 
 // Load stepping (continuation): the load at s / n_steps of its full value,

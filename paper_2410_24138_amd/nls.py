@@ -66,6 +66,7 @@ SYMBOLS = (
     "nls_guess_predict", "nls_guess_predict_noalloc", "nls_guess_loss_grad",
     "nls_guess_train",
     "nls_get_tuning", "nls_set_nodal_load", "nls_solve_load_steps", "nls_solve_nks",
+    "nls_solve_batch",
 )
 
 GUESS_PARAMS = 279552
@@ -170,6 +171,7 @@ def load() -> ctypes.CDLL:
         "nls_solve_load_steps": ([P, P, ctypes.c_int, ctypes.c_int, ctypes.POINTER(Stats)],
                                  ctypes.c_int),
         "nls_solve_nks": ([P, P, ctypes.c_int, ctypes.POINTER(Stats)], ctypes.c_int),
+        "nls_solve_batch": ([P, ctypes.c_int, P, P, P, P], ctypes.c_int),
         "nls_get_tuning": ([P, P, P, P, P, P, P, P], ctypes.c_int),
         "nls_guess_set_model": ([P, P, i64, P], ctypes.c_int),
         "nls_guess_get_model": ([P, P, P], ctypes.c_int),
@@ -247,6 +249,31 @@ def inspect_coarse(case: dict):
     if rc:
         raise NLSError(rc, lib.nls_strerror(rc).decode())
     return [nodes[off[k]:off[k + 1]] for k in range(cnt[0])]
+
+
+def solve_batch(solvers, us=None):
+    """nls_solve_batch over Solver objects (distinct handles; give each its
+    own stream to let them run together).  us: float64 device tensors (the
+    initial iterates, overwritten), default zeros.  Returns (us, per-instance
+    stats, per-instance codes, rc)."""
+    import torch
+    lib = load()
+    n = len(solvers)
+    if us is None:
+        us = [torch.zeros(s.N, dtype=torch.float64, device=s.device) for s in solvers]
+    for s, u in zip(solvers, us):
+        assert u.dtype == torch.float64 and u.is_cuda and u.is_contiguous() and u.numel() == s.N
+    hs = (ctypes.c_void_p * n)(*[s.h.value for s in solvers])
+    ups = (ctypes.c_void_p * n)(*[u.data_ptr() for u in us])
+    dev = (ctypes.c_int * n)(*([1] * n))
+    sts = (Stats * n)()
+    codes = (ctypes.c_int * n)()
+    for s in solvers:
+        torch.cuda.current_stream(s.device).synchronize()
+    rc = lib.nls_solve_batch(hs, n, ups, dev, sts, codes)
+    if rc == NLS_EINVAL:
+        raise NLSError(rc, "nls_solve_batch: null or repeated handles")
+    return us, [st.as_dict() for st in sts], list(codes), rc
 
 
 def default_options() -> Options:
