@@ -214,3 +214,118 @@ def test_predictor_solve_reaches_plain_solution():
     u1, st1 = S.solve(predictor=pred)
     assert st1["converged"] and st1["outer"] == st0["outer"]
     assert np.linalg.norm(u1 - u0) <= 1e-10 * np.linalg.norm(u0)
+
+
+# ------------------------------------------------------------- elasticity
+def _nh_schwarz(**kw):
+    from oracle import NHProblem
+    case = synth.small_elasticity_case(**kw)
+    return Schwarz(NHProblem(case), "one_level")
+
+
+def test_q1_inverse_map_recovers_reference_coordinates():
+    """Newton's inverse of the bilinear element map on random convex
+    quadrilaterals: x(xi, eta) of known (xi, eta) maps back to them."""
+    rng = np.random.default_rng(5)
+    base = np.array([[0.0, 0.0], [1.0, 0.0], [1.0, 1.0], [0.0, 1.0]])
+    quads = base[None] * rng.uniform(0.5, 2.0, size=(6, 1, 2)) \
+        + rng.uniform(-0.15, 0.15, size=(6, 4, 2))
+    ref = rng.uniform(0.0, 1.0, size=(10, 2))
+    for q in quads:
+        N = G.q1_shape(ref[:, 0], ref[:, 1])
+        p = N @ q
+        xi, eta = G.q1_local(p, q[None])
+        np.testing.assert_allclose(xi[:, 0], ref[:, 0], atol=1e-13)
+        np.testing.assert_allclose(eta[:, 0], ref[:, 1], atol=1e-13)
+
+
+def test_nh_sampling_exact_for_bilinear_fields():
+    """On rectangles the Q1 interpolant reproduces a + bx + cy + dxy, so
+    every sample (trace, load and grid) of such a field is exact, each
+    sample point lies in its element, and the weights sum to 1."""
+    S = _nh_schwarz(nx=12, ny=8, boxes=(3, 2), overlap=2, traction=(0.0, -1.0))
+    xy = S.P.xy
+    fx = lambda p: 0.3 + 1.7 * p[:, 0] - 2.2 * p[:, 1] + 0.5 * p[:, 0] * p[:, 1]  # noqa: E731
+    fy = lambda p: -1.1 + 0.4 * p[:, 0] + 0.9 * p[:, 1] - 0.7 * p[:, 0] * p[:, 1]  # noqa: E731
+    u = np.empty(2 * len(xy))
+    u[0::2], u[1::2] = fx(xy), fy(xy)
+    for i in range(S.n_sub):
+        geo = G.PatchGeometryNH(S, i)
+        assert geo.eligible and geo.samp_inside.min() >= -1e-12
+        np.testing.assert_allclose(geo.samp_w.sum(axis=1), 1.0, atol=1e-14)
+        rec = (geo.samp_w[:, :, None] * xy[geo.samp_nodes]).sum(axis=1)
+        np.testing.assert_allclose(rec, geo.sample_pts, atol=1e-13)
+        pts = geo.sample_pts
+        T = G.NH_TRACE
+        np.testing.assert_allclose(geo.trace(u), np.concatenate([fx(pts[:T]), fy(pts[:T])]),
+                                   atol=1e-13)
+        L = slice(T, T + G.NH_LOAD)
+        np.testing.assert_allclose(geo.load(u), np.concatenate([fx(pts[L]), fy(pts[L])]),
+                                   atol=1e-13)
+        np.testing.assert_allclose(geo.grid_sample(u, 1), fy(geo.grid_pts), atol=1e-13)
+
+
+def test_nh_lift_and_target_on_bilinear_states():
+    """For a bilinear displacement the Coons lifting of its trace (8 samples
+    per side) is the field itself, so lift(u, 0) = u on the free V dofs and
+    the target of x* = R_i u vanishes."""
+    S = _nh_schwarz(nx=16, ny=8, boxes=(2, 2), overlap=1, traction=(0.0, -1.0))
+    P = S.P
+    xy = P.xy
+    u = np.empty(P.ndof)
+    u[0::2] = 0.1 - 0.3 * xy[:, 0] + 0.2 * xy[:, 1] + 0.05 * xy[:, 0] * xy[:, 1]
+    u[1::2] = -0.2 + 0.1 * xy[:, 0] - 0.4 * xy[:, 0] * xy[:, 1]
+    for i in range(S.n_sub):
+        s = S.subs[i]
+        geo = G.PatchGeometryNH(S, i)
+        x = geo.lift(u, np.zeros(G.N_OUT), s["dirV"], P.dir_value[s["Vd"]])
+        free = ~s["dirV"]
+        np.testing.assert_allclose(x[free], u[s["Vd"]][free], atol=1e-13)
+        np.testing.assert_array_equal(x[s["dirV"]], P.dir_value[s["Vd"]][s["dirV"]])
+        np.testing.assert_allclose(geo.target(u, u[s["Vd"]]), 0.0, atol=1e-13)
+        # bilinear coefficients are reproduced by the reference-grid interpolant
+        xi, eta = geo._grid_unit()
+        c = 0.7 - 0.2 * xi + 1.3 * eta + 0.4 * xi * eta
+        coef = np.concatenate([c, -c])
+        y = geo.lift(np.zeros(P.ndof), coef, np.zeros(len(x), bool), np.zeros(len(x)))
+        ref = 0.7 - 0.2 * geo.xi + 1.3 * geo.eta + 0.4 * geo.xi * geo.eta
+        np.testing.assert_allclose(y[0::2], ref, atol=1e-13)
+        np.testing.assert_allclose(y[1::2], -ref, atol=1e-13)
+
+
+def test_nh_load_features_sample_the_loaded_edge():
+    """Load features: zero for boxes away from the loaded edge; on the edge
+    the interpolant of the lumped traction t h (t h / 2 at the two end
+    nodes), so t h wherever the sample lies between two interior nodes."""
+    t = (0.0, -3.0)
+    S = _nh_schwarz(nx=12, ny=6, boxes=(3, 2), overlap=1, traction=t)
+    f = G.nodal_load(S.P)
+    h = 1.0 / 6
+    touched = 0
+    for i in range(S.n_sub):
+        geo = G.PatchGeometryNH(S, i)
+        ld = geo.load(f)
+        if geo.x1 < 2.0 - 1e-12:
+            np.testing.assert_array_equal(ld, 0.0)
+            continue
+        touched += 1
+        y = geo.sample_pts[G.NH_TRACE:G.NH_TRACE + G.NH_LOAD, 1]
+        mid = (y >= h - 1e-12) & (y <= 1.0 - h + 1e-12)
+        np.testing.assert_allclose(ld[:G.NH_LOAD][mid], t[0] * h, atol=1e-14)
+        np.testing.assert_allclose(ld[G.NH_LOAD:][mid], t[1] * h, rtol=1e-13)
+    assert touched == 2
+
+
+def test_nh_predictor_solve_reaches_plain_solution():
+    """Elasticity: an untrained network only changes the starts; the local
+    solutions and the outer iteration are those of the plain method."""
+    from oracle import NHProblem
+    case = synth.small_elasticity_case(nx=16, ny=8, boxes=(2, 2), overlap=1,
+                                       traction=(0.0, -2.0), two_level=True)
+    S = Schwarz(NHProblem(case), "additive")
+    u0, st0 = S.solve()
+    normz = (np.zeros(G.N_IN), np.ones(G.N_IN), np.zeros(G.N_OUT), np.full(G.N_OUT, 1e-4))
+    pred = G.Predictor(S, synth.mlp_init(9), normz)
+    u1, st1 = S.solve(predictor=pred)
+    assert st1["converged"] and st1["outer"] == st0["outer"]
+    assert np.linalg.norm(u1 - u0) <= 1e-10 * np.linalg.norm(u0)
