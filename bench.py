@@ -405,6 +405,104 @@ def run_learned(device, amp, train_seeds, eval_seeds, epochs, batch=256, capacit
     }
 
 
+def run_learned_nh(device, train_runs=40, epochs=30, batch=256, capacity=100_000,
+                   n_load_steps=10, held_out=(6000, 6001, 6002)):
+    """Learned initial guess on the 256x128 Q1 Neo-Hooke cantilever (8x8
+    seeded cuts, overlap 2, GDSW, 10 load steps): (features, target) pairs
+    captured from the solver's own converged local solves on training runs
+    with cut seeds 5400.. and right-edge traction tau_max ~ U(2, 6), the
+    network trained on the GPU, then the continuation solved with and
+    without it: the 256x128 workload itself (cut seed 3, tau_max = 4) and
+    held-out cut seeds with tau_max ~ U(2, 6).  Every continuation is timed
+    from u = 0; solutions with and without the network are compared."""
+    import torch
+    import synth
+    from paper_2410_24138_amd import Solver
+
+    def case_for(seed, tau):
+        cx, cy = synth.seeded_cuts(seed, 256, 128)
+        return synth.elasticity_case(256, 128, 2.0, 1.0, cx, cy, 2, traction=(0.0, -tau),
+                                     name=f"neohooke_256x128_cuts{seed}_tau{tau:.2f}")
+
+    rng = np.random.default_rng(5400)
+    Xs, Ts = [], []
+    n = 0
+    t0 = time.perf_counter()
+    runs = 0
+    for k in range(train_runs):
+        tau = float(rng.uniform(2.0, 6.0))
+        s = Solver(case_for(5400 + k, tau))
+        s.guess_capture(capacity - n)
+        s.solve_load_steps(n_load_steps)
+        X, T = s.guess_captured()
+        Xs.append(X.cpu())
+        Ts.append(T.cpu())
+        n += X.shape[0]
+        runs += 1
+        s.close()
+        if n >= capacity:
+            break
+    t_capture = time.perf_counter() - t0
+    X = torch.cat(Xs).to(device)
+    T = torch.cat(Ts).to(device)
+    del Xs, Ts
+    trainer = Solver(synth.config3())
+    trainer.guess_set_model(synth.mlp_init(1))
+    order = synth.epoch_orders(2, n, epochs)
+    tr = trainer.guess_train(X, T, epochs=epochs, batch=batch, lr=1e-3, order=order, cosine=True)
+    params, norm = trainer.guess_get_model()
+    trainer.close()
+    del X, T
+    evals = [("neohooke_256x128_8x8_ov2_gdsw", synth.config3())]
+    for sd in held_out:
+        evals.append((f"cuts{sd}", case_for(sd, float(np.random.default_rng(sd).uniform(2, 6)))))
+    rows = []
+    for name, case in evals:
+        s = Solver(case)
+        s.guess_set_model(params, norm)
+        out = {}
+        for mode in ("plain", "learned"):
+            s.guess_enable(mode == "learned")
+            s.solve_load_steps(n_load_steps)  # warm-up
+            torch.cuda.synchronize(device)
+            t1 = time.perf_counter()
+            u, sts, rc = s.solve_load_steps(n_load_steps)
+            torch.cuda.synchronize(device)
+            out[mode] = {"ms": 1e3 * (time.perf_counter() - t1), "u": u, "sts": sts, "rc": rc}
+        s.close()
+        up, ul = out["plain"]["u"], out["learned"]["u"]
+        sp, sl = out["plain"]["sts"], out["learned"]["sts"]
+        rows.append({
+            "case": name,
+            "ms_plain": round(out["plain"]["ms"], 2), "ms_learned": round(out["learned"]["ms"], 2),
+            "inner_plain": sum(st["inner_its_total"] for st in sp),
+            "inner_learned": sum(st["inner_its_total"] for st in sl),
+            "outer_plain": [st["outer_its"] for st in sp],
+            "outer_learned": [st["outer_its"] for st in sl],
+            "used": sum(st["guess_used"] for st in sl),
+            "fallback": sum(st["guess_fallback"] for st in sl),
+            "solves": sum(st["local_solves"] for st in sl),
+            "converged": out["plain"]["rc"] == 0 and out["learned"]["rc"] == 0,
+            "rel_diff": float(torch.linalg.norm(ul - up) / torch.linalg.norm(up))})
+    ip = sum(r["inner_plain"] for r in rows)
+    il = sum(r["inner_learned"] for r in rows)
+    return {
+        "metric": "time per 10-step continuation with and without the learned initial guess",
+        "workload": "neohooke_256x128_8x8_ov2_gdsw (+ held-out cuts)",
+        "train": {"runs": runs, "cut_seeds": f"5400..{5400 + runs - 1}", "tau_max": "U(2,6)",
+                  "samples": int(n), "capture_s": round(t_capture, 2), "epochs": epochs,
+                  "batch": batch, "steps": tr["steps"], "train_ms": round(tr["ms"], 1),
+                  "loss_first_epoch": tr["epoch_loss"][0], "loss_last_epoch": tr["final_loss"]},
+        "inner_its_plain": ip, "inner_its_learned": il,
+        "inner_its_saved_frac": round(1 - il / ip, 4) if ip else None,
+        "outer_its_equal": all(r["outer_plain"] == r["outer_learned"] for r in rows),
+        "all_converged": all(r["converged"] for r in rows),
+        "max_rel_diff_learned_vs_plain": max(r["rel_diff"] for r in rows),
+        "speedup_config3": round(rows[0]["ms_plain"] / rows[0]["ms_learned"], 4),
+        "per_case": rows,
+    }
+
+
 def run_elasticity(forms, steps, warmup, device, n_load_steps=10):
     """Compressible Neo-Hooke cantilever, 256x128 Q1 cells on [0,2]x[0,1]
     (66,306 dofs), 8x8 subdomains at seeded cuts, overlap 2, GDSW with
@@ -625,8 +723,8 @@ def main():
                     default="plain,fp64_tuned,chosen,fp32_ir,bf16_ir,fp64_tuned_chord,"
                             "fp64_tuned_rgdsw")
     ap.add_argument("--workload", default="diffusion512",
-                    choices=["diffusion512", "batch", "learned", "elasticity", "beam",
-                             "assembly"])
+                    choices=["diffusion512", "batch", "learned", "learned_nh", "elasticity",
+                             "beam", "assembly"])
     ap.add_argument("--amp", type=float, default=10.0,
                     help="forcing amplitude of the learned workload")
     ap.add_argument("--train-seeds", type=int, default=130)
@@ -656,6 +754,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize(device)
         del src, dst
+    if args.workload == "learned_nh":
+        print(json.dumps(run_learned_nh(device, epochs=args.epochs)), flush=True)
+        return
     if args.workload == "assembly":
         print(json.dumps(run_assembly(device)), flush=True)
         return

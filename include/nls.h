@@ -397,7 +397,12 @@ int nls_get_tuning(nls_handle* h, int32_t* n_buckets, int32_t* lu_variant,
    to ||R_i F(u)||_2, and restarts from R_i u if Newton from the prediction
    fails, so T_i(u) is the same up to the stopping tolerance.
 
-   Features of subdomain i (320): u at 64 points of the perimeter of the
+   Within nls_solve, an evaluation whose predictions the judge took for
+   fewer than 1 in 20 subdomains makes the next two evaluations start from
+   R_i u without consulting the network (guess_used + guess_fallback then
+   count only the evaluations that consulted it).
+
+   Features of subdomain i (320), diffusion: u at 64 points of the perimeter of the
    patch box (16 per side at t = j/16, counter-clockwise from the lower-left
    corner), then the nodal load (mean of the edge-midpoint samples of f
    around each node) at the 16 x 16 reference nodes (x0 + p W/15,
@@ -410,7 +415,17 @@ int nls_get_tuning(nls_handle* h, int32_t* n_buckets, int32_t* lu_variant,
 
    Network: affine layers 320 -> 256 -> 256 -> 256 -> 256, GELU (exact erf)
    after the first three; parameters flat float32 W1 b1 W2 b2 W3 b3 W4 b4
-   (W_l row-major [out][in]), 279552 values.  Products in bfloat16 on the
+   (W_l row-major [out][in]), 279552 values.
+
+   Elasticity (Q1, two components; the same sizes, per component x then y):
+   inputs u_x, u_y at 32 perimeter points (8 per side), then the external
+   nodal forces f_x, f_y (zero on Dirichlet dofs) at 128 points
+   (x1, y0 + j H/127) on the right side of the box (the loaded edge of the
+   cantilever); outputs and targets on the 16 x 8 reference nodes
+   (x0 + p W/15, y0 + q H/7), index q*16 + p, per component; samples are
+   bilinear (Q1) interpolants in the quadrilateral containing the point;
+   x_pred per component = Coons of its 32 trace samples + bilinear
+   interpolant of its 128 coefficients, Dirichlet dofs exact.  Products in bfloat16 on the
    matrix cores with FP32 accumulation; FP32 master weights.  norm: 1152
    floats [x_mean(320) x_dev(320) y_mean(256) y_dev(256)]; the network maps
    (x - x_mean)/x_dev to (y - y_mean)/y_dev.  Arrays named _dev below are

@@ -756,6 +756,7 @@ extern "C" int nls_set_load(nls_handle* h, const double* elem_load) {
 bool guess_enabled(const nls_handle* h);
 int guess_prepare(nls_handle* h, const double* u, const double** xpred);
 int guess_after_local(nls_handle* h, const double* u);
+void guess_new_solve(nls_handle* h);
 
 // ------------------------------------------------------------ evaluation
 static bool two_level(nls_handle* h) {
@@ -1571,6 +1572,7 @@ static int solve_impl(nls_handle* h, double* u, int u_on_device, nls_stats* st) 
     std::memset(S, 0, sizeof(*S));
     S->failed_subdomain = -1;
     h->st = S;
+    guess_new_solve(h);
     h->coarse_lu_valid = false;  // chord steps reuse factorisations within one solve only
     h->coarse_inv_valid = false;
     const int N = h->mesh.ndof();

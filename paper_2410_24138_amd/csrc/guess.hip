@@ -37,39 +37,126 @@ __device__ __forceinline__ double sample(const DevGuessTables& T, int i, int k, 
 }
 
 // Side function s (0 bottom, 1 right, 2 top, 3 left) at parameter t: linear
-// between the 16 samples of the side; the last interval ends at the first
+// between the NS samples of the side; the last interval ends at the first
 // sample of the next side (the corner).
+template <int NS>
 __device__ __forceinline__ double side(const double* tr, int sd, double t) {
-    const double pos = t * NLS_G_SIDE;
+    const double pos = t * NS;
     int j = (int)floor(pos);
-    j = j < 0 ? 0 : (j > NLS_G_SIDE - 1 ? NLS_G_SIDE - 1 : j);
+    j = j < 0 ? 0 : (j > NS - 1 ? NS - 1 : j);
     const double w = pos - j;
-    const int nx = (j < NLS_G_SIDE - 1) ? sd * NLS_G_SIDE + j + 1 : ((sd + 1) & 3) * NLS_G_SIDE;
-    return (1.0 - w) * tr[sd * NLS_G_SIDE + j] + w * tr[nx];
+    const int nx = (j < NS - 1) ? sd * NS + j + 1 : ((sd + 1) & 3) * NS;
+    return (1.0 - w) * tr[sd * NS + j] + w * tr[nx];
 }
 
-// Transfinite (Coons) interpolant of the sampled perimeter at unit (xi, eta).
+// Transfinite (Coons) interpolant of the sampled perimeter (NS samples per
+// side) at unit (xi, eta).
+template <int NS = NLS_G_SIDE>
 __device__ __forceinline__ double coons(const double* tr, double xi, double eta) {
-    const double g0 = side(tr, 0, xi), g1 = side(tr, 1, eta);
-    const double g2 = side(tr, 2, 1.0 - xi), g3 = side(tr, 3, 1.0 - eta);
-    const double c00 = tr[0], c10 = tr[NLS_G_SIDE], c11 = tr[2 * NLS_G_SIDE],
-                 c01 = tr[3 * NLS_G_SIDE];
+    const double g0 = side<NS>(tr, 0, xi), g1 = side<NS>(tr, 1, eta);
+    const double g2 = side<NS>(tr, 2, 1.0 - xi), g3 = side<NS>(tr, 3, 1.0 - eta);
+    const double c00 = tr[0], c10 = tr[NS], c11 = tr[2 * NS], c01 = tr[3 * NS];
     return (1.0 - eta) * g0 + eta * g2 + (1.0 - xi) * g3 + xi * g1 -
            ((1.0 - xi) * (1.0 - eta) * c00 + xi * (1.0 - eta) * c10 + xi * eta * c11 +
             (1.0 - xi) * eta * c01);
 }
 
-// Bilinear interpolant of the 16 x 16 reference-node values c[q*16 + p].
+// Bilinear interpolant of the GX x GY reference-node values c[q*GX + p].
+template <int GX = NLS_G_GRID, int GY = NLS_G_GRID>
 __device__ __forceinline__ double bilinear(const float* c, double xi, double eta) {
-    const double px = xi * (NLS_G_GRID - 1), py = eta * (NLS_G_GRID - 1);
+    const double px = xi * (GX - 1), py = eta * (GY - 1);
     int p0 = (int)floor(px), q0 = (int)floor(py);
-    p0 = p0 < 0 ? 0 : (p0 > NLS_G_GRID - 2 ? NLS_G_GRID - 2 : p0);
-    q0 = q0 < 0 ? 0 : (q0 > NLS_G_GRID - 2 ? NLS_G_GRID - 2 : q0);
+    p0 = p0 < 0 ? 0 : (p0 > GX - 2 ? GX - 2 : p0);
+    q0 = q0 < 0 ? 0 : (q0 > GY - 2 ? GY - 2 : q0);
     const double a = px - p0, b = py - q0;
-    const float* r0 = c + q0 * NLS_G_GRID + p0;
-    const float* r1 = r0 + NLS_G_GRID;
+    const float* r0 = c + q0 * GX + p0;
+    const float* r1 = r0 + GX;
     return (1.0 - a) * (1.0 - b) * r0[0] + a * (1.0 - b) * r0[1] + (1.0 - a) * b * r1[0] +
            a * b * r1[1];
+}
+
+// ------------------------------------------------- elasticity (Q1, d = 2)
+// Component c of the dof field f (node-major, two per node) at sample k.
+__device__ __forceinline__ double sample_e(const DevGuessTables& T, int i, int k,
+                                           const double* f, int c) {
+    const size_t b = ((size_t)i * NLS_GE_NSAMP + k) * 4;
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v += T.sw[b + q] * f[2 * T.snode[b + q] + c];
+    return v;
+}
+
+// Features: u_x, u_y at the 32 perimeter points, then f_x, f_y (external
+// nodal forces) at the 128 points on the right side of the box.
+__global__ void __launch_bounds__(NLS_G_IN)
+k_guess_features_e(DevGuessTables T, const double* __restrict__ u, const double* __restrict__ fload,
+                   const float* __restrict__ xm, const float* __restrict__ xs,
+                   float* __restrict__ xraw, uint16_t* __restrict__ xbf) {
+    const int i = blockIdx.x, k = threadIdx.x;
+    double v;
+    if (k < 2 * NLS_GE_TRACE) {
+        v = sample_e(T, i, k % NLS_GE_TRACE, u, k / NLS_GE_TRACE);
+    } else {
+        const int kk = k - 2 * NLS_GE_TRACE;
+        v = sample_e(T, i, NLS_GE_TRACE + kk % NLS_GE_LOAD, fload, kk / NLS_GE_LOAD);
+    }
+    const size_t o = (size_t)i * NLS_G_IN + k;
+    if (xraw) xraw[o] = (float)v;
+    if (xbf) xbf[o] = f2bf((float)((v - (double)xm[k]) / (double)xs[k]));
+}
+
+// x_pred on the V dofs: per component Coons of its 32 trace samples +
+// bilinear interpolant of its 128 coefficients; Dirichlet dofs exact.
+__global__ void __launch_bounds__(256)
+k_guess_lift_e(DevMaps P, DevGuessTables T, DevMesh M, const double* __restrict__ xy,
+               const double* __restrict__ u, const float* __restrict__ coef,
+               double* __restrict__ xpred) {
+    __shared__ double tr[2 * NLS_GE_TRACE];
+    __shared__ float cf[NLS_G_OUT];
+    const int i = blockIdx.x;
+    if (threadIdx.x < 2 * NLS_GE_TRACE)
+        tr[threadIdx.x] = sample_e(T, i, threadIdx.x % NLS_GE_TRACE, u, threadIdx.x / NLS_GE_TRACE);
+    for (int k = threadIdx.x; k < NLS_G_OUT; k += blockDim.x) cf[k] = coef[(size_t)i * NLS_G_OUT + k];
+    __syncthreads();
+    const double x0 = T.box[4 * i], y0 = T.box[4 * i + 1];
+    const double W = T.box[4 * i + 2] - x0, H = T.box[4 * i + 3] - y0;
+    const int rb = P.off_n[i], n = P.off_n[i + 1] - rb;
+    for (int a = threadIdx.x; a < n; a += blockDim.x) {
+        const int dof = P.l2g[rb + a], g = dof >> 1, c = dof & 1;
+        double v;
+        if (M.dflag[dof]) {
+            v = M.dval[dof];
+        } else {
+            const double xi = (xy[2 * g] - x0) / W, eta = (xy[2 * g + 1] - y0) / H;
+            v = coons<NLS_GE_SIDE>(tr + c * NLS_GE_TRACE, xi, eta) +
+                bilinear<NLS_GE_GX, NLS_GE_GY>(cf + c * NLS_GE_NGRID, xi, eta);
+        }
+        xpred[rb + a] = v;
+    }
+}
+
+// Training target: per component (v(x*) - Coons) at the 16 x 8 reference
+// nodes, v(x*) = x* on the V dofs and u elsewhere.
+__global__ void __launch_bounds__(NLS_G_OUT)
+k_guess_target_e(DevGuessTables T, const double* __restrict__ u, const double* __restrict__ xstar,
+                 float* __restrict__ traw) {
+    __shared__ double tr[2 * NLS_GE_TRACE];
+    const int i = blockIdx.x, k = threadIdx.x;
+    if (k < 2 * NLS_GE_TRACE) tr[k] = sample_e(T, i, k % NLS_GE_TRACE, u, k / NLS_GE_TRACE);
+    __syncthreads();
+    const int c = k / NLS_GE_NGRID, q = k % NLS_GE_NGRID;
+    const size_t b = ((size_t)i * NLS_GE_NSAMP + NLS_GE_TRACE + NLS_GE_LOAD + q) * 4;
+    const size_t bl = ((size_t)i * NLS_GE_NGRID + q) * 4;
+    double v = 0.0;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int loc = T.sloc[bl + t];
+        v += T.sw[b + t] * (loc >= 0 ? xstar[loc + c] : u[2 * T.snode[b + t] + c]);
+    }
+    const int p = q % NLS_GE_GX, qq = q / NLS_GE_GX;
+    const double xi = (double)p / (NLS_GE_GX - 1), eta = (double)qq / (NLS_GE_GY - 1);
+    traw[(size_t)i * NLS_G_OUT + k] =
+        (float)(v - coons<NLS_GE_SIDE>(tr + c * NLS_GE_TRACE, xi, eta));
 }
 
 // f^_g = mean of the edge-midpoint load samples over the (element, edge)
@@ -412,7 +499,10 @@ hipError_t launch_guess_features(const DevGuessTables& T, int nrows, const doubl
                                  const double* fhat, const float* xm, const float* xs,
                                  float* xraw, uint16_t* xbf, hipStream_t s) {
     if (nrows <= 0) return hipSuccess;
-    k_guess_features<<<nrows, NLS_G_IN, 0, s>>>(T, u, fhat, xm, xs, xraw, xbf);
+    if (T.elast)
+        k_guess_features_e<<<nrows, NLS_G_IN, 0, s>>>(T, u, fhat, xm, xs, xraw, xbf);
+    else
+        k_guess_features<<<nrows, NLS_G_IN, 0, s>>>(T, u, fhat, xm, xs, xraw, xbf);
     return hipGetLastError();
 }
 
@@ -420,14 +510,20 @@ hipError_t launch_guess_lift(const DevMaps& P, const DevGuessTables& T, const De
                              const double* xy, const double* u, const float* coef,
                              double* xpred, hipStream_t s) {
     if (T.nsub <= 0) return hipSuccess;
-    k_guess_lift<<<T.nsub, 256, 0, s>>>(P, T, M, xy, u, coef, xpred);
+    if (T.elast)
+        k_guess_lift_e<<<T.nsub, 256, 0, s>>>(P, T, M, xy, u, coef, xpred);
+    else
+        k_guess_lift<<<T.nsub, 256, 0, s>>>(P, T, M, xy, u, coef, xpred);
     return hipGetLastError();
 }
 
 hipError_t launch_guess_target(const DevGuessTables& T, int nrows, const double* u,
                                const double* xstar, float* traw, hipStream_t s) {
     if (nrows <= 0) return hipSuccess;
-    k_guess_target<<<nrows, NLS_G_NGRID, 0, s>>>(T, u, xstar, traw);
+    if (T.elast)
+        k_guess_target_e<<<nrows, NLS_G_OUT, 0, s>>>(T, u, xstar, traw);
+    else
+        k_guess_target<<<nrows, NLS_G_NGRID, 0, s>>>(T, u, xstar, traw);
     return hipGetLastError();
 }
 

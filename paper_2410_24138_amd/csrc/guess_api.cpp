@@ -44,6 +44,11 @@ struct GuessState {
     float* y = nullptr;
     double* xpred = nullptr;
     bool enabled = false;
+    // within a solve: evaluations left without inference after one whose
+    // predictions the judge took for fewer than 1 in 20 subdomains, and
+    // whether the current evaluation consulted the network
+    int skip = 0;
+    bool consulted = false;
     // captured training pairs
     float *cx = nullptr, *ct = nullptr;
     int64_t cap = 0, count = 0;
@@ -87,8 +92,9 @@ static int ensure_tables(nls_handle* h) {
     GuessState* g = state(h);
     if (g->tables) return NLS_OK;
     if (!h->have_part) return fail(h, NLS_ESTATE, "nls_set_partition first");
-    if (h->mesh.d != 1 || h->kind != NLS_PROBLEM_DIFFUSION)
-        return fail(h, NLS_EINVAL, "the learned guess is built for the scalar diffusion problem");
+    const bool elast = h->kind == NLS_PROBLEM_NEOHOOKE;
+    if (elast ? (h->mesh.d != 2 || h->mesh.nv != 4) : (h->mesh.d != 1 || h->mesh.nv != 3))
+        return fail(h, NLS_EINVAL, "the learned guess needs P1 diffusion or Q1 elasticity");
     HostGuess hg;
     std::string err;
     int rc = nls_build_guess_tables(h->mesh, h->maps, hg, err);
@@ -100,17 +106,19 @@ static int ensure_tables(nls_handle* h) {
     RC(galloc(h, GuessState::B_TABLES, &sloc, hg.sloc.size()));
     RC(galloc(h, GuessState::B_TABLES, &sw, hg.sw.size()));
     RC(galloc(h, GuessState::B_TABLES, &box, hg.box.size()));
-    RC(galloc(h, GuessState::B_TABLES, &g->fhat, (size_t)h->mesh.N));
+    if (!elast) RC(galloc(h, GuessState::B_TABLES, &g->fhat, (size_t)h->mesh.N));
     HIPCHK(hipMemcpyAsync(snode, hg.snode.data(), hg.snode.size() * sizeof(int), hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipMemcpyAsync(sloc, hg.sloc.data(), hg.sloc.size() * sizeof(int), hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipMemcpyAsync(sw, hg.sw.data(), hg.sw.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipMemcpyAsync(box, hg.box.data(), hg.box.size() * sizeof(double), hipMemcpyHostToDevice, h->stream));
     g->T.nsub = h->maps.nsub;
+    g->T.elast = elast ? 1 : 0;
     g->T.box = box;
     g->T.snode = snode;
     g->T.sw = sw;
     g->T.sloc = sloc;
-    HIPCHK(launch_nodal_load(h->dm, h->fmid_h.empty() ? nullptr : h->d_fmid, g->fhat, h->stream));
+    if (!elast)
+        HIPCHK(launch_nodal_load(h->dm, h->fmid_h.empty() ? nullptr : h->d_fmid, g->fhat, h->stream));
     RC(sync(h));
     g->tables = true;
     return NLS_OK;
@@ -130,7 +138,7 @@ void guess_invalidate(nls_handle* h) {
 
 int guess_refresh_load(nls_handle* h) {
     GuessState* g = h->guess;
-    if (!g || !g->tables) return NLS_OK;
+    if (!g || !g->tables || g->T.elast) return NLS_OK;
     HIPCHK(launch_nodal_load(h->dm, h->fmid_h.empty() ? nullptr : h->d_fmid, g->fhat, h->stream));
     return NLS_OK;
 }
@@ -248,12 +256,38 @@ static int need_model(nls_handle* h) {
     return NLS_OK;
 }
 
+// The nodal load field the features sample: f^ (diffusion), or the external
+// nodal forces with Dirichlet dofs zeroed (elasticity), kept current by the
+// load setters.
+static const double* load_field(const nls_handle* h) {
+    return h->guess->T.elast ? h->dm.bload : h->guess->fhat;
+}
+
 // ------------------------------------------------------- evaluate hooks
 bool guess_enabled(const nls_handle* h) { return h->guess && h->guess->enabled; }
+
+// Inference gating restarts with every solve.
+void guess_new_solve(nls_handle* h) {
+    if (h->guess) {
+        h->guess->skip = 0;
+        h->guess->consulted = false;
+    }
+}
+
+// Evaluations a solve runs without inference after one whose predictions
+// were almost all rejected (the start is then R_i u, as without a network).
+#define NLS_GUESS_SKIP 2
 
 // Predicted starts of every subdomain at u (packed like the V rows).
 int guess_prepare(nls_handle* h, const double* u, const double** xpred) {
     GuessState* g = h->guess;
+    g->consulted = false;
+    if (h->st && g->skip > 0) {
+        --g->skip;
+        *xpred = nullptr;
+        return NLS_OK;
+    }
+    g->consulted = true;
     RC(ensure_tables(h));
     const int ns = h->maps.nsub;
     if (g->inf_rows < ns) {
@@ -265,7 +299,7 @@ int guess_prepare(nls_handle* h, const double* u, const double** xpred) {
         RC(galloc(h, GuessState::B_INFER, &g->xpred, (size_t)h->maps.off_n.back()));
         g->inf_rows = ns;
     }
-    HIPCHK(launch_guess_features(g->T, ns, u, g->fhat, g->norm, g->norm + NLS_G_IN, nullptr,
+    HIPCHK(launch_guess_features(g->T, ns, u, load_field(h), g->norm, g->norm + NLS_G_IN, nullptr,
                                  g->xin, h->stream));
     uint16_t* acts[3] = {g->a0, g->a1, g->a0};
     RC(forward(h, g->xin, ns, nullptr, acts, g->y, true));
@@ -283,19 +317,20 @@ int guess_after_local(nls_handle* h, const double* u) {
     if (g->cap > 0 && g->count < g->cap) {
         RC(ensure_tables(h));
         const int rows = (int)std::min<int64_t>(ns, g->cap - g->count);
-        HIPCHK(launch_guess_features(g->T, rows, u, g->fhat, nullptr, nullptr,
+        HIPCHK(launch_guess_features(g->T, rows, u, load_field(h), nullptr, nullptr,
                                      g->cx + g->count * NLS_G_IN, nullptr, h->stream));
         HIPCHK(launch_guess_target(g->T, rows, u, h->dl.xstar, g->ct + g->count * NLS_G_OUT,
                                    h->stream));
         g->count += rows;
     }
-    if (g->enabled && h->st && g->counts) {
+    if (g->enabled && h->st && g->counts && g->consulted) {
         int c[2] = {0, 0};
         HIPCHK(launch_count_starts(h->dl.start, ns, g->counts, h->stream));
         HIPCHK(hipMemcpyAsync(c, g->counts, sizeof(c), hipMemcpyDeviceToHost, h->stream));
         RC(sync(h));
         h->st->guess_used += c[0];
         h->st->guess_fallback += c[1];
+        if (20 * c[0] < ns) g->skip = NLS_GUESS_SKIP;
     }
     return NLS_OK;
 }
@@ -399,7 +434,7 @@ extern "C" int nls_guess_features(nls_handle* h, const double* u, float* X) {
     HIPCHK(hipSetDevice(h->opt.device));
     RC(ensure_tables(h));
     GuessState* g = h->guess;
-    HIPCHK(launch_guess_features(g->T, h->maps.nsub, u, g->fhat, nullptr, nullptr, X, nullptr, h->stream));
+    HIPCHK(launch_guess_features(g->T, h->maps.nsub, u, load_field(h), nullptr, nullptr, X, nullptr, h->stream));
     return sync(h);
 }
 

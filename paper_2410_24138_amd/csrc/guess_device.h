@@ -30,12 +30,25 @@
 #define NLS_G_OFF_W4 213760
 #define NLS_G_OFF_B4 279296
 
+// Elasticity (two dofs per node, Q1): 8 perimeter samples per side (32),
+// 128 load samples on the right side of the box, a 16 x 8 reference grid;
+// inputs and outputs per component (x then y).
+#define NLS_GE_SIDE 8
+#define NLS_GE_TRACE 32
+#define NLS_GE_LOAD 128
+#define NLS_GE_GX 16
+#define NLS_GE_GY 8
+#define NLS_GE_NGRID 128
+#define NLS_GE_NSAMP 288
+
 struct DevGuessTables {
     int nsub;
+    int elast;           // 0: scalar P1 layout, 1: elasticity Q1 layout
     const double* box;   // 4 per subdomain: x0, y0, x1, y1
-    const int* snode;    // nsub x 320 x 3: element nodes of each sample
-    const double* sw;    // nsub x 320 x 3: barycentric weights
-    const int* sloc;     // nsub x 256 x 3: packed V row of a grid-sample node, or -1
+    const int* snode;    // nsub x 320 x 3 (elasticity: nsub x 288 x 4): element nodes
+    const double* sw;    // interpolation weights, same layout
+    const int* sloc;     // nsub x 256 x 3 (elasticity: nsub x 128 x 4): packed V row of
+                         //   a grid-sample node (of its x dof), or -1
 };
 
 enum GemmEpilogue {

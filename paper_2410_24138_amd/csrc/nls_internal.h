@@ -145,11 +145,15 @@ struct HostCoarse {
 // mesh element containing the point (its three nodes and barycentric
 // weights); for the grid nodes also the packed V row of each node in the
 // subdomain, or -1.
+// Elasticity (Q1): 288 samples (32 perimeter, 128 on the right side of the
+// box, 16 x 8 reference nodes) of four nodes each; sloc holds the packed V
+// row of the node's x dof.
 struct HostGuess {
+    int nper = 3, nsamp = 320, ngrid = 256;  // nodes per sample, samples, grid nodes
     std::vector<double> box;       // 4 per subdomain: x0, y0, x1, y1
-    std::vector<int> snode;        // nsub x 320 x 3
-    std::vector<double> sw;        // nsub x 320 x 3
-    std::vector<int> sloc;         // nsub x 256 x 3
+    std::vector<int> snode;        // nsub x nsamp x nper
+    std::vector<double> sw;        // nsub x nsamp x nper
+    std::vector<int> sloc;         // nsub x ngrid x nper
 };
 
 // Most coarse functions nonzero at one interface dof: RGDSW elasticity on an

@@ -742,8 +742,8 @@ BucketGrid build_buckets(const HostMesh& m) {
     std::vector<int> lo(4 * (size_t)m.E);
     for (int e = 0; e < m.E; ++e) {
         double ex0 = 1e300, ex1 = -1e300, ey0 = 1e300, ey1 = -1e300;
-        for (int k = 0; k < 3; ++k) {
-            const int v = m.conn[3 * e + k];
+        for (int k = 0; k < m.nv; ++k) {
+            const int v = m.conn[m.nv * e + k];
             ex0 = std::min(ex0, m.xy[2 * v]);
             ex1 = std::max(ex1, m.xy[2 * v]);
             ey0 = std::min(ey0, m.xy[2 * v + 1]);
@@ -769,8 +769,47 @@ BucketGrid build_buckets(const HostMesh& m) {
     return g;
 }
 
-// Element containing (px, py) and its barycentric weights.
-int locate(const HostMesh& m, const BucketGrid& g, double px, double py, double w[3]) {
+// Reference coordinates of (px, py) in quadrilateral e: Newton's method on
+// the bilinear element map x(xi, eta) = p from the centre (corners counter-
+// clockwise at (0,0), (1,0), (1,1), (0,1)); the bilinear weights of the
+// corners into w, and min(xi, 1 - xi, eta, 1 - eta) returned.
+double q1_weights(const HostMesh& m, int e, double px, double py, double w[4]) {
+    double X[4], Y[4];
+    for (int k = 0; k < 4; ++k) {
+        X[k] = m.xy[2 * m.conn[4 * e + k]];
+        Y[k] = m.xy[2 * m.conn[4 * e + k] + 1];
+    }
+    double xi = 0.5, eta = 0.5;
+    for (int it = 0; it < 30; ++it) {
+        const double N[4] = {(1 - xi) * (1 - eta), xi * (1 - eta), xi * eta, (1 - xi) * eta};
+        const double dxi[4] = {-(1 - eta), 1 - eta, eta, -eta};
+        const double deta[4] = {-(1 - xi), -xi, xi, 1 - xi};
+        double rx = -px, ry = -py, a = 0, b = 0, c = 0, d = 0;
+        for (int k = 0; k < 4; ++k) {
+            rx += N[k] * X[k];
+            ry += N[k] * Y[k];
+            a += dxi[k] * X[k];
+            b += deta[k] * X[k];
+            c += dxi[k] * Y[k];
+            d += deta[k] * Y[k];
+        }
+        const double det = a * d - b * c;
+        const double sx = (d * rx - b * ry) / det, sy = (-c * rx + a * ry) / det;
+        xi -= sx;
+        eta -= sy;
+        if (std::max(std::abs(sx), std::abs(sy)) < 1e-15) break;
+    }
+    w[0] = (1 - xi) * (1 - eta);
+    w[1] = xi * (1 - eta);
+    w[2] = xi * eta;
+    w[3] = (1 - xi) * eta;
+    return std::min(std::min(xi, 1 - xi), std::min(eta, 1 - eta));
+}
+
+// Element containing (px, py) and its interpolation weights: barycentric
+// (P1, w[3] = 0) or bilinear (Q1); the element whose weights are largest at
+// their smallest wins, ties to the lower element id.
+int locate(const HostMesh& m, const BucketGrid& g, double px, double py, double w[4]) {
     const int ci = std::min(g.nx - 1, std::max(0, (int)std::floor((px - g.x0) / g.hx)));
     const int cj = std::min(g.ny - 1, std::max(0, (int)std::floor((py - g.y0) / g.hy)));
     int best = -1;
@@ -785,15 +824,18 @@ int locate(const HostMesh& m, const BucketGrid& g, double px, double py, double 
                 const size_t b = (size_t)j * g.nx + i;
                 for (int k = g.ptr[b]; k < g.ptr[b + 1]; ++k) {
                     const int e = g.elems[k];
-                    double lam[3];
-                    barycentric(m, e, px, py, lam);
-                    const double mn = std::min(lam[0], std::min(lam[1], lam[2]));
+                    double lam[4] = {0.0, 0.0, 0.0, 0.0};
+                    double mn;
+                    if (m.nv == 4) {
+                        mn = q1_weights(m, e, px, py, lam);
+                    } else {
+                        barycentric(m, e, px, py, lam);
+                        mn = std::min(lam[0], std::min(lam[1], lam[2]));
+                    }
                     if (mn > bmin || (mn == bmin && e < best)) {
                         bmin = mn;
                         best = e;
-                        w[0] = lam[0];
-                        w[1] = lam[1];
-                        w[2] = lam[2];
+                        for (int v = 0; v < 4; ++v) w[v] = lam[v];
                     }
                 }
             }
@@ -804,6 +846,79 @@ int locate(const HostMesh& m, const BucketGrid& g, double px, double py, double 
 }
 }  // namespace
 
+// Elasticity (Q1, two dofs per node): 32 perimeter points (8 per side), 128
+// points on the right side of the box, the 16 x 8 reference nodes; four
+// nodes and bilinear weights per sample; for the reference nodes the packed
+// V row of each element node's x dof in the subdomain, or -1.
+static int build_guess_tables_q1(const HostMesh& m, const HostMaps& M, const BucketGrid& grid,
+                                 HostGuess& out, std::string& err) {
+    constexpr int NS = 8, NT = 32, NL = 128, GX = 16, GY = 8, NSAMP = 288;
+    const int nsub = M.nsub;
+    out.nper = 4;
+    out.nsamp = NSAMP;
+    out.ngrid = GX * GY;
+    out.box.assign(4 * (size_t)nsub, 0.0);
+    out.snode.assign((size_t)nsub * NSAMP * 4, 0);
+    out.sw.assign((size_t)nsub * NSAMP * 4, 0.0);
+    out.sloc.assign((size_t)nsub * GX * GY * 4, -1);
+    std::vector<int> rowof(m.N, -1);
+    for (int i = 0; i < nsub; ++i) {
+        double x0 = 1e300, x1 = -1e300, y0 = 1e300, y1 = -1e300;
+        auto take = [&](int dof) {
+            const int g = dof / 2;
+            x0 = std::min(x0, m.xy[2 * g]);
+            x1 = std::max(x1, m.xy[2 * g]);
+            y0 = std::min(y0, m.xy[2 * g + 1]);
+            y1 = std::max(y1, m.xy[2 * g + 1]);
+        };
+        for (int r = M.off_n[i]; r < M.off_n[i + 1]; ++r) take(M.l2g[r]);
+        for (int r = M.off_g[i]; r < M.off_g[i + 1]; ++r) take(M.g2g[r]);
+        const double W = x1 - x0, H = y1 - y0;
+        if (!(W > 0.0) || !(H > 0.0)) {
+            err = "subdomain " + std::to_string(i) + " has a degenerate patch box";
+            return NLS_EPARTITION;
+        }
+        double* bx = &out.box[4 * (size_t)i];
+        bx[0] = x0;
+        bx[1] = y0;
+        bx[2] = x1;
+        bx[3] = y1;
+        for (int r = M.off_n[i]; r < M.off_n[i + 1]; ++r)
+            if (M.l2g[r] % 2 == 0) rowof[M.l2g[r] / 2] = r;
+        for (int k = 0; k < NSAMP; ++k) {
+            double px, py;
+            if (k < NT) {
+                const int sd = k / NS;
+                const double t = (double)(k % NS) / NS;
+                if (sd == 0) { px = x0 + t * W; py = y0; }
+                else if (sd == 1) { px = x1; py = y0 + t * H; }
+                else if (sd == 2) { px = x1 - t * W; py = y1; }
+                else { px = x0; py = y1 - t * H; }
+            } else if (k < NT + NL) {
+                px = x1;
+                py = y0 + ((double)(k - NT) / (NL - 1)) * H;
+            } else {
+                const int q = (k - NT - NL) / GX, p = (k - NT - NL) % GX;
+                px = x0 + ((double)p / (GX - 1)) * W;
+                py = y0 + ((double)q / (GY - 1)) * H;
+            }
+            double w[4];
+            const int e = locate(m, grid, px, py, w);
+            const size_t o = ((size_t)i * NSAMP + k) * 4;
+            for (int v = 0; v < 4; ++v) {
+                const int g = m.conn[4 * e + v];
+                out.snode[o + v] = g;
+                out.sw[o + v] = w[v];
+                if (k >= NT + NL)
+                    out.sloc[((size_t)i * GX * GY + (k - NT - NL)) * 4 + v] = rowof[g];
+            }
+        }
+        for (int r = M.off_n[i]; r < M.off_n[i + 1]; ++r)
+            if (M.l2g[r] % 2 == 0) rowof[M.l2g[r] / 2] = -1;
+    }
+    return NLS_OK;
+}
+
 int nls_build_guess_tables(const HostMesh& m, const HostMaps& M, HostGuess& out,
                            std::string& err) {
     constexpr int NS = 16, NT = 64, NG = 16, NIN = 320;
@@ -813,6 +928,10 @@ int nls_build_guess_tables(const HostMesh& m, const HostMaps& M, HostGuess& out,
         return NLS_EINVAL;
     }
     const BucketGrid grid = build_buckets(m);
+    if (m.nv == 4) return build_guess_tables_q1(m, M, grid, out, err);
+    out.nper = 3;
+    out.nsamp = NIN;
+    out.ngrid = NG * NG;
     out.box.assign(4 * (size_t)nsub, 0.0);
     out.snode.assign((size_t)nsub * NIN * 3, 0);
     out.sw.assign((size_t)nsub * NIN * 3, 0.0);
@@ -851,7 +970,7 @@ int nls_build_guess_tables(const HostMesh& m, const HostMaps& M, HostGuess& out,
                 px = x0 + ((double)p / (NG - 1)) * W;
                 py = y0 + ((double)q / (NG - 1)) * H;
             }
-            double w[3];
+            double w[4];
             const int e = locate(m, grid, px, py, w);
             const size_t o = ((size_t)i * NIN + k) * 3;
             for (int v = 0; v < 3; ++v) {

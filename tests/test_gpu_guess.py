@@ -187,7 +187,8 @@ def test_learned_start_keeps_the_solution():
     uu, st, rc = s.solve()
     assert rc == 0 and st["outer_its"] == st_ref["outer"]
     assert np.linalg.norm(_np(uu) - u_ref) <= 1e-10 * np.linalg.norm(u_ref)
-    assert st["guess_used"] + st["guess_fallback"] == st["local_solves"]
+    # evaluations after one with almost no accepted predictions skip inference
+    assert 0 < st["guess_used"] + st["guess_fallback"] <= st["local_solves"]
 
 
 def _strong_case(seed, n=32):
