@@ -230,9 +230,12 @@ def run_form(case, form, steps, warmup, device):
         "tuning": s.tuning(),
     }
     out["parity_bar"] = parity_bar(out, form)
+    # distance to u*: 1e-8, or the oracle's own distance at outer rtol 1e-8
+    # where that is larger (64x64 one-level: 1.2e-8)
+    star_bar = max(1e-8, golden.get("rel_err_vs_global_newton", 0.0) + 1e-10)
     out["meets_parity"] = bool(out["converged"] and out["outer_its_match_oracle"]
                                and out["rel_err_vs_oracle_same_settings"] <= out["parity_bar"]
-                               and out["rel_err_vs_global_newton"] <= 1e-8)
+                               and out["rel_err_vs_global_newton"] <= star_bar)
     s.close()
     return out
 
@@ -527,13 +530,22 @@ def run_elasticity(forms, steps, warmup, device, n_load_steps=10):
                    | (nls.FLAG_COARSE_CHORD if "chord" in extra else 0)
                    | (nls.FLAG_AUTOTUNE if "autotune" in extra else 0)
                    | (nls.FLAG_OVERLAP if "overlap" in extra else 0))
-        for _ in range(warmup):
-            s.solve_load_steps(n_load_steps)
-        torch.cuda.synchronize(device)
-        t0 = time.perf_counter()
-        outs = [s.solve_load_steps(n_load_steps) for _ in range(steps)]
-        torch.cuda.synchronize(device)
-        wall = (time.perf_counter() - t0) / steps
+        from paper_2410_24138_amd import NLSError
+        try:
+            for _ in range(warmup):
+                s.solve_load_steps(n_load_steps)
+            torch.cuda.synchronize(device)
+            t0 = time.perf_counter()
+            outs = [s.solve_load_steps(n_load_steps) for _ in range(steps)]
+            torch.cuda.synchronize(device)
+            wall = (time.perf_counter() - t0) / steps
+        except NLSError as e:
+            # reported, not hidden: the form does not reach the solution
+            res[f] = {"converged": False, "error": str(e), "code": int(e.code),
+                      "rel_err_vs_global_newton": None, "ms_per_continuation": None}
+            s.close()
+            print(json.dumps({"form": f, **res[f]}), file=sys.stderr, flush=True)
+            continue
         u, sts, rc = outs[-1]
         un = u.cpu().numpy()
         solves = sum(st["local_solves"] for st in sts)
@@ -723,8 +735,8 @@ def main():
                     default="plain,fp64_tuned,chosen,fp32_ir,bf16_ir,fp64_tuned_chord,"
                             "fp64_tuned_rgdsw")
     ap.add_argument("--workload", default="diffusion512",
-                    choices=["diffusion512", "batch", "learned", "learned_nh", "elasticity",
-                             "beam", "assembly"])
+                    choices=["diffusion512", "diffusion64", "batch", "learned", "learned_nh",
+                             "elasticity", "beam", "assembly"])
     ap.add_argument("--amp", type=float, default=10.0,
                     help="forcing amplitude of the learned workload")
     ap.add_argument("--train-seeds", type=int, default=130)
@@ -775,8 +787,11 @@ def main():
                           list(range(6000, 6010)), args.epochs)
         print(json.dumps(res), flush=True)
         return
-    case = synth.config2()
+    small = args.workload == "diffusion64"
+    case = synth.config1() if small else synth.config2()
     forms = [f for f in args.forms.split(",") if f]
+    if small:  # one level: no coarse space, so no chord or RGDSW forms
+        forms = [f for f in forms if "chord" not in f and "rgdsw" not in f]
     res = {}
     for f in forms:
         res[f] = run_form(case, f, args.steps, args.warmup, device)
@@ -802,8 +817,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if _local_fp64(r, best) else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": case["name"], "grid": "512x512 P1", "nodes": len(case["xy"]),
-                   "subdomains": 256, "overlap": 2, "coarse": "GDSW vertex+edge",
+        "config": {"workload": case["name"],
+                   "grid": "64x64 P1" if small else "512x512 P1", "nodes": len(case["xy"]),
+                   "subdomains": int(case["n_sub"]), "overlap": int(case["overlap"]),
+                   "coarse": "none (one level)" if small else "GDSW vertex+edge",
                    "form": best, "outer_rtol": 1e-8, "parallelism": "1 GPU"},
         "time_to_1e-8_ms": {f: round(res[f]["ms_per_solve"], 3) for f in res},
         "forms": {f: {k: v for k, v in res[f].items()} for f in res},
