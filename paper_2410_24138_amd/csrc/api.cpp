@@ -306,7 +306,7 @@ static int upload_problem(nls_handle* h) {
 // patch values, residual/step (and refinement vectors in mixed mode),
 // reduction scratch, multipliers, and the band window of the factorisation
 // (FP64 in every mode: the factorisation at the converged state is FP64).
-static int local_lds_bytes(const HostMaps& M, int i, bool mixed, int v) {
+static int local_lds_key(const HostMaps& M, int i, bool mixed, int v) {
     const int n = M.off_n[i + 1] - M.off_n[i], ng = M.off_g[i + 1] - M.off_g[i];
     const int dbl = (n + ng) + n + (mixed ? 2 * n : 0) + 24 + std::max(M.kl[i], 1) + 1;
     int w = band_window_doubles_v(M.kl[i], M.ku[i], v);
@@ -315,6 +315,28 @@ static int local_lds_bytes(const HostMaps& M, int i, bool mixed, int v) {
 }
 
 static int npl_for(int band) { return band <= 64 ? 1 : (band <= 128 ? 2 : 4); }
+
+// LDS bytes that stage 64 steps of FP64 factor entries for the band solves:
+// two buffers of 64 columns, each column in slot order (NPL + 1 slots of 64
+// entries) with its pivot or reciprocal diagonal.
+static int solve_stage_bytes(int kl, int ku) {
+    const int slots = npl_for(std::max(kl, kl + ku)) + 1;
+    return 2 * 64 * (slots * 64 * 8 + 8);
+}
+
+// LDS bytes of a launch: the working set above, with the window region
+// grown (up to the 160 KB of a compute unit, less 1 KB for the kernels'
+// static LDS) so that it also holds the band solves' staging buffers.  The
+// kernel is limited to one workgroup per compute unit by its registers, so
+// the extra LDS costs no occupancy.
+static const int kLdsGrowCap = 159 * 1024;
+static int local_lds_bytes(const HostMaps& M, int i, bool mixed, int v) {
+    const int key = local_lds_key(M, i, mixed, v);
+    const int n = M.off_n[i + 1] - M.off_n[i], ng = M.off_g[i + 1] - M.off_g[i];
+    const int base = ((n + ng) + n + (mixed ? 2 * n : 0) + 24 + std::max(M.kl[i], 1) + 1) * 8;
+    const int want = base + solve_stage_bytes(M.kl[i], M.ku[i]);
+    return std::max(key, std::min(want, kLdsGrowCap));
+}
 
 extern "C" int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* elem_part,
                                  int32_t overlap) {
@@ -347,14 +369,14 @@ extern "C" int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* el
         return fail(h, NLS_ELIMIT, "local band too wide (kl <= 127, kl+ku <= 256)");
     int lds = 0;
     const int var0 = h->opt.lu_variant;
-    for (int i = 0; i < M.nsub; ++i) lds = std::max(lds, local_lds_bytes(M, i, mixed, var0));
+    for (int i = 0; i < M.nsub; ++i) lds = std::max(lds, local_lds_key(M, i, mixed, var0));
     if (lds > 160 * 1024) return fail(h, NLS_ELIMIT, "subdomain too large for the LDS working set");
     h->lds_local = lds;
     // launch order: largest LDS first; size buckets of equal occupancy (WGs
     // per CU allowed by LDS), one launch each
     std::vector<int> sub_lds(M.nsub), sub_band(M.nsub);
     for (int i = 0; i < M.nsub; ++i) {
-        sub_lds[i] = local_lds_bytes(M, i, mixed, var0);
+        sub_lds[i] = local_lds_key(M, i, mixed, var0);
         sub_band[i] = std::max(M.kl[i], M.kl[i] + M.ku[i]);
     }
     std::vector<int> lorder(M.nsub);
@@ -371,14 +393,19 @@ extern "C" int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* el
             band = std::max(band, sub_band[lorder[q]]);
             ++q;
         }
+        int blds = 0;
+        for (int t = p; t < q; ++t) blds = std::max(blds, local_lds_bytes(M, lorder[t], mixed, var0));
         h->bk_start.push_back(p);
         h->bk_end.push_back(q);
-        h->bk_lds.push_back(sub_lds[lorder[p]]);
+        h->bk_lds.push_back(blds);
         h->bk_npl.push_back(npl_for(band));
         h->bk_var.push_back(var0);
         p = q;
     }
-    h->lds_tangent = (maxn + (mixed ? 2 * maxn : 0) + 24) * 8;
+    int stage = 0;
+    for (int i = 0; i < M.nsub; ++i) stage = std::max(stage, solve_stage_bytes(M.kl[i], M.ku[i]));
+    const int tan_min = (maxn + (mixed ? 2 * maxn : 0) + 24) * 8;
+    h->lds_tangent = std::max(tan_min, std::min(tan_min + stage, kLdsGrowCap));
     h->npl_local = npl_for(std::max(maxkl, maxband));
     // tables
     DevMaps d{};

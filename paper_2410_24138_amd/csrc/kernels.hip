@@ -294,73 +294,14 @@ __device__ __forceinline__ void local_residual(const DevMesh& M, const DevMaps& 
     }
 }
 
-// Jacobian rows [J_ii | B_i] into the CSR values jval (slots fixed at setup).
-template <bool ELAST>
-__device__ __forceinline__ void local_jacobian(const DevMesh& M, const DevMaps& P, int n, int rowbase,
-                               int ebase, const double* vp, double* __restrict__ jval) {
-    for (int a = threadIdx.x; a < n; a += blockDim.x) {
-        const int row = rowbase + a;
-        const int g = P.l2g[row];
-        const int js = P.jptr[row], je = P.jptr[row + 1];
-        for (int s = js; s < je; ++s) jval[s] = 0.0;
-        if (M.dflag[g]) {
-            for (int s = js; s < je; ++s)
-                if (P.jcol[s] == a) jval[s] = 1.0;
-            continue;
-        }
-        if (ELAST) {
-            const int c = a & 1;
-            for (int k = P.rinc_ptr[row]; k < P.rinc_ptr[row + 1]; ++k) {
-                const int code = P.rinc[k];
-                const int e = ebase + (code >> 2), pos = code & 3;
-                double X[4][2], ue[4][2], kr[4][2];
-                int nd[4];
-                nh_coords(M, P.pe_gid[e], X);
-                nh_local_values(P, e, vp, nd, ue);
-                nh_stiff_row(M, X, ue, pos, c, kr);
-#pragma unroll
-                for (int b = 0; b < 4; ++b)
-#pragma unroll
-                    for (int kk = 0; kk < 2; ++kk) {
-                        const int col = 2 * nd[b] + kk;
-                        for (int t = js; t < je; ++t)
-                            if (P.jcol[t] == col) { jval[t] += kr[b][kk]; break; }
-                    }
-            }
-            continue;
-        }
-        for (int k = P.rinc_ptr[row]; k < P.rinc_ptr[row + 1]; ++k) {
-            const int code = P.rinc[k];
-            const int e = ebase + (code >> 2), pos = code & 3;
-            const int nd[3] = {P.pe_conn[3 * e], P.pe_conn[3 * e + 1], P.pe_conn[3 * e + 2]};
-            const double uu[3] = {vp[nd[0]], vp[nd[1]], vp[nd[2]]};
-            const int ge = P.pe_gid[e];
-            const double U = uu[0] + uu[1] + uu[2];
-            const double m = (U * U + uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2]) * (1.0 / 12.0);
-            double gr[3];
-            g_row(M.G6 + 6 * (size_t)ge, pos, gr[0], gr[1], gr[2]);
-            const double s = gr[0] * uu[0] + gr[1] * uu[1] + gr[2] * uu[2];
-            const double kap = M.kappa[ge];
-            const double coef = kap * (1.0 + M.beta * m);
-            const double rk = M.beta * kap * s * (1.0 / 6.0);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const double K = coef * gr[c] + rk * (U + uu[c]);
-                for (int t = js; t < je; ++t)
-                    if (P.jcol[t] == nd[c]) { jval[t] += K; break; }
-            }
-        }
-    }
-}
-
 // ----------------------------------------------------------------------------
 // Residual and Jacobian rows of one local problem in one pass (the
 // standalone assembly of eqs. (3)-(4) at the patch values vp): rows
 // [a0, a1) of subdomain i, one row per thread, the row's CSR slots
-// accumulated in registers and written once.  r[a] = R_i F(v)[a]; jval
-// (may be null) the values of [J_ii | B_i] in the fixed CSR slots.  Rows
-// with more slots than MS (unstructured meshes of high valence) add into
-// jval in place.
+// accumulated in registers and written once.  r[a] = R_i F(v)[a] (r may be
+// null: no residual); jval (may be null) the values of [J_ii | B_i] in the
+// fixed CSR slots.  Rows with more slots than MS (unstructured meshes of
+// high valence) add into jval in place.
 // ----------------------------------------------------------------------------
 template <bool ELAST>
 __device__ __forceinline__ void assemble_rows(const DevMesh& M, const DevMaps& P, int n, int rowbase,
@@ -374,9 +315,13 @@ __device__ __forceinline__ void assemble_rows(const DevMesh& M, const DevMaps& P
         const bool inreg = jval && je - js <= MS;
         int cl[MS];
         double acc[MS];
+        // slot columns: loads from in-row addresses (a row has at least its
+        // diagonal slot), selected afterwards, so that they are all in flight
 #pragma unroll
         for (int t = 0; t < MS; ++t) {
-            cl[t] = (inreg && js + t < je) ? P.jcol[js + t] : -1;
+            const bool in = inreg && js + t < je;
+            const int c = P.jcol[in ? js + t : js];
+            cl[t] = in ? c : -1;
             acc[t] = 0.0;
         }
         if (jval && !inreg)
@@ -406,7 +351,7 @@ __device__ __forceinline__ void assemble_rows(const DevMesh& M, const DevMaps& P
                 int nd[4];
                 nh_coords(M, P.pe_gid[e], X);
                 nh_local_values(P, e, vp, nd, ue);
-                f += nh_force(M, X, ue, pos, c, ok);
+                if (r) f += nh_force(M, X, ue, pos, c, ok);
                 if (jval) {
                     double kr[4][2];
                     nh_stiff_row(M, X, ue, pos, c, kr);
@@ -441,13 +386,21 @@ __device__ __forceinline__ void assemble_rows(const DevMesh& M, const DevMaps& P
             }
             res = f - M.bload[g];
         }
-        r[a] = res;
+        if (r) r[a] = res;
         if (jval && inreg) {
 #pragma unroll
             for (int t = 0; t < MS; ++t)
                 if (js + t < je) jval[js + t] = acc[t];
         }
     }
+}
+
+// Jacobian rows [J_ii | B_i] of the whole local problem into the CSR values
+// jval (slots fixed at setup), accumulated in registers row by row.
+template <bool ELAST>
+__device__ __forceinline__ void local_jacobian(const DevMesh& M, const DevMaps& P, int n, int rowbase,
+                                               int ebase, const double* vp, double* __restrict__ jval) {
+    assemble_rows<ELAST>(M, P, n, rowbase, ebase, vp, 0, n, nullptr, jval);
 }
 
 // ----------------------------------------------------------------------------
@@ -681,7 +634,7 @@ __device__ __forceinline__ int band_lu_blocked(int n, int kl, int ku, const int*
                                T* W, int* sh, T* __restrict__ Uf, T* __restrict__ Lf,
                                int* __restrict__ piv, int cbase = 0, double* rhs = nullptr) {
     static_assert(!BF16 || sizeof(T) == 4, "bfloat16 updates need binary32 factors");
-    T* lt = W + (NB + kl) * (NB + kl + ku);  // L11 of the current panel, NB x NB
+    T* lt = W + (NB + kl) * (NB + kl + ku);  // L11 of the current panel by columns, NB x NB
     int* mv = (int*)(lt + NB * NB);           // moved rows of the panel (<= 64)
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wv = tid >> 6;
@@ -747,13 +700,22 @@ __device__ __forceinline__ int band_lu_blocked(int n, int kl, int ku, const int*
             T p[NB];
             const bool have = lane < rvalid;
             const int sr = wrap(rb + (lane < H ? lane : 0), H);
+            // loads from in-window addresses, then selects: no branch and
+            // no wait between the loads
 #pragma unroll
-            for (int c = 0; c < NB; ++c) p[c] = have ? W[sr * Wd + wrap(cb + c, Wd)] : T(0);
+            for (int c = 0; c < NB; ++c) {
+                const T w = W[sr * Wd + wrap(cb + c, Wd)];
+                p[c] = have ? w : T(0);
+            }
             int pos = lane, sing = 0;
             bool used = false;
             // right-hand side (forward substitution fused with the
             // factorisation): each row carries its entry through the steps
-            double pb = (rhs && have) ? rhs[k0 + lane] : 0.0;
+            double pb = 0.0;
+            if (rhs) {
+                const double w = rhs[have ? k0 + lane : k0];
+                pb = have ? w : 0.0;
+            }
             // The steps hold no stores (the multipliers and interchanges are
             // stored after the loop) and no branch but the one around the
             // pivot search.
@@ -809,7 +771,7 @@ __device__ __forceinline__ int band_lu_blocked(int n, int kl, int ku, const int*
                 for (int c = 0; c < NB; ++c) W[sp * Wd + wrap(cb + c, Wd)] = p[c];
                 if (pos < NB) {
 #pragma unroll
-                    for (int c = 0; c < NB; ++c) lt[pos * NB + c] = p[c];
+                    for (int c = 0; c < NB; ++c) lt[c * NB + pos] = p[c];
                 }
             }
             // rows that changed position: (new position << 8) | old position
@@ -863,11 +825,17 @@ __device__ __forceinline__ int band_lu_blocked(int n, int kl, int ku, const int*
             const int sc = wrap(cb + NB + t, Wd);
             T x[NB];
 #pragma unroll
-            for (int j = 0; j < NB; ++j) x[j] = (j < nbp) ? W[wrap(rb + j, H) * Wd + sc] : T(0);
+            for (int j = 0; j < NB; ++j) {
+                const T w = W[wrap(rb + j, H) * Wd + sc];
+                x[j] = (j < nbp) ? w : T(0);
+            }
+            // column j of L11 is contiguous: its loads do not depend on x
+            // and are issued ahead of the updates that use them
 #pragma unroll
             for (int j = 0; j < NB; ++j) {
+                const T xj = x[j];
 #pragma unroll
-                for (int r = j + 1; r < NB; ++r) x[r] -= lt[r * NB + j] * x[j];
+                for (int r = j + 1; r < NB; ++r) x[r] -= lt[j * NB + r] * xj;
             }
 #pragma unroll
             for (int j = 0; j < NB; ++j)
@@ -888,10 +856,15 @@ __device__ __forceinline__ int band_lu_blocked(int n, int kl, int ku, const int*
                     const bool cok = cc < NB + ntr;
                     const int scc = wrap(cb + (cok ? cc : 0), Wd);
                     typename Mfma<T>::acc_t acc;
+                    // every load reads an in-window address (rows and
+                    // columns clamped) and is selected afterwards, so the
+                    // loads of a tile are issued together
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         const int rr = r0 + Mfma<T>::row(lk, q);
-                        acc[q] = (cok && rr < rvalid) ? W[wrap(rb + rr, H) * Wd + scc] : T(0);
+                        const bool ok = cok && rr < rvalid;
+                        const T w = W[wrap(rb + (ok ? rr : 0), H) * Wd + scc];
+                        acc[q] = ok ? w : T(0);
                     }
                     // A = -L21 (rows r0 + li, k = 4 s + lk), B = U12 (rows k, column cc)
                     const int ra = r0 + li;
@@ -906,8 +879,10 @@ __device__ __forceinline__ int band_lu_blocked(int n, int kl, int ku, const int*
                             const int k = 4 * lk + t4;
                             const bool kin = k < nbp;
                             const int kk = kin ? k : 0;
-                            const float av = (aok && kin) ? -W[sra * Wd + wrap(cb + kk, Wd)] : 0.f;
-                            const float bv = (cok && kin) ? W[wrap(rb + kk, H) * Wd + scc] : 0.f;
+                            const float wa = W[sra * Wd + wrap(cb + kk, Wd)];
+                            const float wb = W[wrap(rb + kk, H) * Wd + scc];
+                            const float av = (aok && kin) ? -wa : 0.f;
+                            const float bv = (cok && kin) ? wb : 0.f;
                             a4[t4] = bf16_rne(av);
                             b4[t4] = bf16_rne(bv);
                         }
@@ -916,8 +891,10 @@ __device__ __forceinline__ int band_lu_blocked(int n, int kl, int ku, const int*
 #pragma unroll
                         for (int s4 = 0; s4 < NB / 4; ++s4) {
                             const int k = 4 * s4 + lk;
-                            const T av = (aok && k < nbp) ? -W[sra * Wd + wrap(cb + k, Wd)] : T(0);
-                            const T bv = (cok && k < nbp) ? W[wrap(rb + k, H) * Wd + scc] : T(0);
+                            const T wa = W[sra * Wd + wrap(cb + k, Wd)];
+                            const T wb = W[wrap(rb + k, H) * Wd + scc];
+                            const T av = (aok && k < nbp) ? -wa : T(0);
+                            const T bv = (cok && k < nbp) ? wb : T(0);
                             acc = Mfma<T>::step(av, bv, acc);
                         }
                     }
@@ -1115,21 +1092,305 @@ __device__ __forceinline__ void band_solve_wave(int n, int kl, int ku, const T* 
     }
 }
 
-template <int NPL>
-__device__ __forceinline__ void band_solve_any(bool f32, int n, int kl, int ku, const double* Ud,
-                               const double* Ld, const float* Us, const float* Ls,
-                               const int* piv, double* b, bool backward_only = false) {
-    if (f32) band_solve_wave<float, NPL>(n, kl, ku, Us, Ls, piv, b, backward_only);
-    else band_solve_wave<double, NPL>(n, kl, ku, Ud, Ld, piv, b, backward_only);
+// ----------------------------------------------------------------------------
+// Band triangular solves with the factors of band_lu for one right-hand side
+// b (LDS, FP64), carried out by the whole workgroup.  Wavefront 0 runs the
+// substitution steps with the rows of b that a step can touch in registers:
+// R = NPL + 1 slots of 64 rows (the kl + ku <= 64 NPL rows next to step k lie
+// in blocks k / 64 -+ 0..R-1), slot 0 holding the block of row k.  A step
+// broadcasts the finished entry with v_readlane, keeps it in slot 0 and
+// updates every slot with one FMA; when the step leaves a block, the block
+// goes to b and the slots move by one, the last one taking the next block
+// from b.  The other wavefronts stage the next G steps' factor entries into
+// one half of an LDS double buffer while wavefront 0 reads the other half,
+// already in slot order (entry (q, l) of a column is the factor entry of the
+// row that lane l of slot q holds, zero outside the band) with the pivots or
+// the reciprocals of the diagonal beside them, so that a step reads one entry
+// per slot and applies no masks.  The workgroup synchronises every G steps.
+// Same arithmetic, in the same order, as the one-wavefront solve above.  All
+// threads of the workgroup call it.
+// ----------------------------------------------------------------------------
+template <typename T, int NPL>
+__host__ __device__ __forceinline__ int band_stage_col_bytes() {
+    return (NPL + 1) * 64 * (int)sizeof(T) + 8;  // slot entries + pivot or 1/d
+}
+template <typename T, int NPL>
+__device__ __forceinline__ int band_stage_cols(int stage_bytes) {
+    const int g = stage_bytes / (2 * band_stage_col_bytes<T, NPL>());
+    return g >= 64 ? 64 : (g & ~7);
+}
+
+// The rows of b next to a substitution step: R blocks of 64 rows, block q in
+// slot q.  Named members, not an array: every access is by a compile-time
+// slot, or by a chain of selects on a uniform one, so the slots stay in
+// registers.
+template <int R>
+struct BandRing {
+    static_assert(R >= 2 && R <= 5, "1 to 4 values per lane");
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0, s4 = 0.0;
+    // row (q, lane l), q and l uniform: every slot is read at lane l and
+    // the scalars are selected, so that no slot is indexed at run time
+    __device__ __forceinline__ double lane_value(int q, int l) const {
+        double v = rdlane(s0, l);
+        const double v1 = rdlane(s1, l);
+        v = q == 1 ? v1 : v;
+        if constexpr (R > 2) { const double v2 = rdlane(s2, l); v = q == 2 ? v2 : v; }
+        if constexpr (R > 3) { const double v3 = rdlane(s3, l); v = q == 3 ? v3 : v; }
+        if constexpr (R > 4) { const double v4 = rdlane(s4, l); v = q == 4 ? v4 : v; }
+        return v;
+    }
+    // row (q, lane of mine) := v
+    __device__ __forceinline__ void put(int q, bool mine, double v) {
+        s0 = (q == 0 && mine) ? v : s0;
+        s1 = (q == 1 && mine) ? v : s1;
+        if constexpr (R > 2) s2 = (q == 2 && mine) ? v : s2;
+        if constexpr (R > 3) s3 = (q == 3 && mine) ? v : s3;
+        if constexpr (R > 4) s4 = (q == 4 && mine) ? v : s4;
+    }
+    // slot q -= c[q] x
+    template <typename C>
+    __device__ __forceinline__ void axpy(const C& c, double x) {
+        s0 -= c[0] * x;
+        s1 -= c[1] * x;
+        if constexpr (R > 2) s2 -= c[2] * x;
+        if constexpr (R > 3) s3 -= c[3] * x;
+        if constexpr (R > 4) s4 -= c[4] * x;
+    }
+    // slots move down by one; the last one takes v
+    __device__ __forceinline__ void shift(double v) {
+        s0 = s1;
+        if constexpr (R > 2) { s1 = s2; } else { s1 = v; }
+        if constexpr (R > 3) { s2 = s3; } else if constexpr (R > 2) { s2 = v; }
+        if constexpr (R > 4) { s3 = s4; s4 = v; } else if constexpr (R > 3) { s3 = v; }
+    }
+    __device__ __forceinline__ void set(int q, double v) {
+        if (q == 0) s0 = v;
+        if (q == 1) s1 = v;
+        if constexpr (R > 2) { if (q == 2) s2 = v; }
+        if constexpr (R > 3) { if (q == 3) s3 = v; }
+        if constexpr (R > 4) { if (q == 4) s4 = v; }
+    }
+};
+
+template <typename T, int NPL>
+__device__ __forceinline__ void band_solve_staged(int n, int kl, int ku, const T* __restrict__ Uf,
+                                                  const T* __restrict__ Lf,
+                                                  const int* __restrict__ piv, double* b,
+                                                  void* stage, int G, bool backward_only) {
+    constexpr int R = NPL + 1, S = 4, CB = 8, PER = R * 64;
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63;
+    const int ldu = kl + ku + 1, ldl = kl > 1 ? kl : 1, bw = kl + ku;
+    const int t0 = nt > 64 ? 64 : 0;  // first thread of the staging waves
+    // buffer h: G columns of PER entries, then G pivots or reciprocals
+    T* sE[2] = {(T*)stage, (T*)stage + G * PER};
+    double* sD[2] = {(double*)((T*)stage + 2 * G * PER), (double*)((T*)stage + 2 * G * PER) + G};
+    BandRing<R> ring;
+    // rows of block B (zeros outside 0..n-1)
+    auto block = [&](int B) {
+        const int r = 64 * B + lane;
+        const bool in = B >= 0 && r < n;
+        const double v = b[in ? r : 0];
+        return in ? v : 0.0;
+    };
+    auto flush = [&](int B) {  // slot 0 holds the finished rows of block B
+        const int r = 64 * B + lane;
+        if (B >= 0 && r < n) b[r] = ring.s0;
+    };
+    // entry e of buffer h for the columns [c0, c0 + cnt): column c0 + e / PER,
+    // slot (e % PER) / 64, lane e % 64; the value is val(k, slot, lane) or 0
+    auto stage_entries = [&](T* E, int c0, int cnt, int first, auto val) {
+        if (tid < first) return;
+        const int step = nt - first, tot = cnt * PER;
+        for (int e0 = tid - first; e0 < tot; e0 += CB * step) {
+            T v[CB];
+            bool ok[CB];
+#pragma unroll
+            for (int u = 0; u < CB; ++u) {
+                const int e = min(e0 + u * step, tot - 1);
+                const int c = e / PER, rem = e - c * PER;
+                v[u] = val(c0 + c, rem >> 6, rem & 63, ok[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < CB; ++u) {
+                const int e = e0 + u * step;
+                if (e < tot) E[e] = ok[u] ? v[u] : T(0);
+            }
+        }
+    };
+    if (n <= 0) return;
+    if (!backward_only) {
+        // forward: slot q holds block k / 64 + q; entry (q, l) of column k is
+        // the multiplier of row 64 (k / 64 + q) + l at step k
+        auto stage_l = [&](int h, int c0, int first) {
+            const int cnt = min(c0 + G, n) - c0;
+            stage_entries(sE[h], c0, cnt, first, [&](int k, int q, int l, bool& ok) {
+                const int j = 64 * ((k >> 6) + q) + l - k - 1;
+                ok = j >= 0 && j < min(kl, n - 1 - k);
+                return Lf[(size_t)k * ldl + (ok ? j : 0)];
+            });
+            if (tid >= first)
+                for (int c = tid - first; c < cnt; c += nt - first)
+                    ((int*)sD[h])[c] = piv[c0 + c];
+        };
+        stage_l(0, 0, 0);
+        __syncthreads();
+        if (tid < 64) {
+#pragma unroll
+            for (int q = 0; q < R; ++q) ring.set(q, block(q));
+        }
+        for (int c0 = 0, h = 0; c0 < n; c0 += G, h ^= 1) {
+            const int c1 = min(c0 + G, n);
+            if (c1 < n) stage_l(h ^ 1, c1, t0);
+            if (tid < 64) {
+                const T* E = sE[h];
+                const int* pvs = (const int*)sD[h];
+                T ln[S][R];
+                int pn[S];
+                auto fetch = [&](int k) {
+#pragma unroll
+                    for (int t = 0; t < S; ++t) {
+                        const int ck = min(k + t, c1 - 1) - c0;
+                        pn[t] = pvs[ck];
+#pragma unroll
+                        for (int q = 0; q < R; ++q) ln[t][q] = E[ck * PER + q * 64 + lane];
+                    }
+                };
+                fetch(c0);
+                for (int k0 = c0; k0 < c1; k0 += S) {
+                    double lv[S][R];
+                    int pv[S];
+#pragma unroll
+                    for (int t = 0; t < S; ++t) {
+                        pv[t] = pn[t];
+#pragma unroll
+                        for (int q = 0; q < R; ++q) lv[t][q] = (double)ln[t][q];
+                    }
+                    if (k0 + S < c1) fetch(k0 + S);
+#pragma unroll
+                    for (int t = 0; t < S; ++t) {
+                        const int k = k0 + t;
+                        if (k < c1) {
+                            const int lk = k & 63;
+                            // entering block k / 64: the finished block leaves
+                            if (lk == 0 && k > 0) {
+                                flush((k >> 6) - 1);
+                                ring.shift(block((k >> 6) + R - 1));
+                            }
+                            const int p = __builtin_amdgcn_readfirstlane(pv[t]);
+                            const double bk = rdlane(ring.s0, lk);
+                            double x = bk;
+                            if (p != k) {
+                                // interchange rows k and p: row p takes b_k
+                                const int qp = (p >> 6) - (k >> 6), lp = p & 63;
+                                x = ring.lane_value(qp, lp);
+                                ring.put(qp, lane == lp, bk);
+                            }
+                            ring.axpy(lv[t], x);  // zero at row k itself
+                            ring.s0 = lane == lk ? x : ring.s0;
+                        }
+                    }
+                }
+                if (c1 == n) flush((n - 1) >> 6);
+            }
+            __syncthreads();
+        }
+    }
+    // backward: U x = b from the last column down; slot q holds block
+    // k / 64 - q; entry (q, l) of column k is U(row, k) for the row
+    // 64 (k / 64 - q) + l above the diagonal, and the reciprocal of U(k, k)
+    // sits beside the column
+    auto stage_u = [&](int h, int c1, int first) {
+        const int c0 = max(c1 - G, 0), cnt = c1 - c0;
+        stage_entries(sE[h], c0, cnt, first, [&](int k, int q, int l, bool& ok) {
+            const int off = k - 64 * ((k >> 6) - q) - l;
+            ok = off >= 1 && off <= min(bw, k);
+            return Uf[(size_t)k * ldu + (ok ? off : 0)];
+        });
+        if (tid >= first)
+            for (int c = tid - first; c < cnt; c += nt - first)
+                sD[h][c] = 1.0 / (double)Uf[(size_t)(c0 + c) * ldu];
+    };
+    stage_u(0, n, 0);
+    __syncthreads();
+    if (tid < 64) {
+        const int Btop = (n - 1) >> 6;
+#pragma unroll
+        for (int q = 0; q < R; ++q) ring.set(q, block(Btop - q));
+    }
+    for (int c1 = n, h = 0; c1 > 0; c1 -= G, h ^= 1) {
+        const int c0 = max(c1 - G, 0);
+        if (c0 > 0) stage_u(h ^ 1, c0, t0);
+        if (tid < 64) {
+            const T* E = sE[h];
+            const double* D = sD[h];
+            T un[S][R];
+            double dn[S];
+            auto fetch = [&](int k) {
+#pragma unroll
+                for (int t = 0; t < S; ++t) {
+                    const int ck = max(k - t, c0) - c0;
+                    dn[t] = D[ck];
+#pragma unroll
+                    for (int q = 0; q < R; ++q) un[t][q] = E[ck * PER + q * 64 + lane];
+                }
+            };
+            fetch(c1 - 1);
+            for (int k0 = c1 - 1; k0 >= c0; k0 -= S) {
+                double uv[S][R], rdg[S];
+#pragma unroll
+                for (int t = 0; t < S; ++t) {
+                    rdg[t] = dn[t];
+#pragma unroll
+                    for (int q = 0; q < R; ++q) uv[t][q] = (double)un[t][q];
+                }
+                if (k0 - S >= c0) fetch(k0 - S);
+#pragma unroll
+                for (int t = 0; t < S; ++t) {
+                    const int k = k0 - t;
+                    if (k >= c0) {
+                        const int lk = k & 63;
+                        const double xk = rdlane(ring.s0, lk) * rdg[t];
+                        ring.axpy(uv[t], xk);  // zero at row k itself
+                        ring.s0 = lane == lk ? xk : ring.s0;
+                        // block k / 64 is finished: to b, and the slots move
+                        if (lk == 0) {
+                            flush(k >> 6);
+                            if (k > 0) ring.shift(block((k >> 6) - R));
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// The workgroup's band solve: staged when the stage holds 8 or more steps,
+// otherwise the one-wavefront solve.  All threads call it; b is complete for
+// every thread on return.
+template <typename T, int NPL>
+__device__ __forceinline__ void band_solve_group(int n, int kl, int ku, const T* __restrict__ Uf,
+                                                 const T* __restrict__ Lf, const int* __restrict__ piv,
+                                                 double* b, void* stage, int stage_bytes,
+                                                 bool backward_only) {
+    const int G = stage ? band_stage_cols<T, NPL>(stage_bytes) : 0;
+    if (G >= 8) {
+        band_solve_staged<T, NPL>(n, kl, ku, Uf, Lf, piv, b, stage, G, backward_only);
+    } else {
+        if (threadIdx.x < 64) band_solve_wave<T, NPL>(n, kl, ku, Uf, Lf, piv, b, backward_only);
+        __syncthreads();
+    }
 }
 
 // Solve J d = rb in place (rb in LDS).  FP64 factors: one band solve.  FP32
 // factors: iterative refinement with FP64 residuals r0 - J d computed from
 // the FP64 CSR values (columns < n), until ||res|| <= ir_rtol ||r0||.
+// stage (LDS, stage_bytes; may be null): staging space of the band solves.
 template <int NPL>
 __device__ __forceinline__ void local_linear_solve(const DevMaps& P, const DevLocal& L, const NewtonParams& np,
                                    int i, int n, int rowbase, double* rb, double* r0,
-                                   double* dl, double* red, bool forward_done = false) {
+                                   double* dl, double* red, bool forward_done = false,
+                                   void* stage = nullptr, int stage_bytes = 0) {
     const int kl = P.kl[i], ku = P.ku[i];
     const double* Ud = L.Uf + P.off_u[i];
     const double* Ld = L.Lf + P.off_l[i];
@@ -1137,8 +1398,7 @@ __device__ __forceinline__ void local_linear_solve(const DevMaps& P, const DevLo
     const float* Ls = np.mixed ? L.Lf32 + P.off_l[i] : nullptr;
     const int* piv = L.piv + rowbase;
     if (!np.mixed) {
-        if (threadIdx.x < 64) band_solve_any<NPL>(false, n, kl, ku, Ud, Ld, Us, Ls, piv, rb, forward_done);
-        __syncthreads();
+        band_solve_group<double, NPL>(n, kl, ku, Ud, Ld, piv, rb, stage, stage_bytes, forward_done);
         return;
     }
     double nr0 = 0.0;
@@ -1149,8 +1409,7 @@ __device__ __forceinline__ void local_linear_solve(const DevMaps& P, const DevLo
     }
     nr0 = sqrt(block_sum(nr0, red));
     for (int it = 0;; ++it) {
-        if (threadIdx.x < 64) band_solve_any<NPL>(true, n, kl, ku, Ud, Ld, Us, Ls, piv, rb);
-        __syncthreads();
+        band_solve_group<float, NPL>(n, kl, ku, Us, Ls, piv, rb, stage, stage_bytes, false);
         double rr = 0.0;
         for (int a = threadIdx.x; a < n; a += blockDim.x) dl[a] += rb[a];
         __syncthreads();
@@ -1199,7 +1458,8 @@ __device__ __forceinline__ int local_factor(const DevMaps& P, const DevLocal& L,
 // ----------------------------------------------------------------------------
 template <int NPL, bool ELAST>
 __global__ void __launch_bounds__(NLS_BLOCK)
-k_local_newton(DevMesh M, DevMaps P, DevLocal L, NewtonParams np, const double* __restrict__ u) {
+k_local_newton(DevMesh M, DevMaps P, DevLocal L, NewtonParams np, const double* __restrict__ u,
+               int lds_bytes) {
     extern __shared__ double smem[];
     __shared__ int sflag[20];
     __shared__ int sdetf;  // a residual met det F <= 0 (elasticity)
@@ -1283,7 +1543,10 @@ k_local_newton(DevMesh M, DevMaps P, DevLocal L, NewtonParams np, const double* 
                 status = 3;
                 break;
             }
-            local_linear_solve<NPL>(P, L, np, i, n, rowbase, rb, r0, dl, red, !np.mixed);
+            // the factorisation window is free during the solve: it holds
+            // the staged factor columns
+            local_linear_solve<NPL>(P, L, np, i, n, rowbase, rb, r0, dl, red, !np.mixed, W,
+                                    lds_bytes - (int)((char*)W - (char*)smem));
             double dm = 0.0;
             for (int a = threadIdx.x; a < n; a += blockDim.x) {
                 vp[a] -= rb[a];
@@ -1802,7 +2065,7 @@ k_coarse_apply_inverse(DevCoarse C, const double* __restrict__ x, double* __rest
 template <int NPL>
 __global__ void __launch_bounds__(NLS_BLOCK)
 k_tangent_local(DevMesh M, DevMaps P, DevLocal L, NewtonParams np, const double* __restrict__ v,
-                int restrict_rhs) {
+                int restrict_rhs, int lds_bytes) {
     extern __shared__ double smem[];
     const int i = P.order[blockIdx.x];
     const int rowbase = P.off_n[i], n = P.off_n[i + 1] - rowbase;
@@ -1825,7 +2088,9 @@ k_tangent_local(DevMesh M, DevMaps P, DevLocal L, NewtonParams np, const double*
         rb[a] = acc;
     }
     __syncthreads();
-    local_linear_solve<NPL>(P, L, np, i, n, rowbase, rb, r0, dl, red);
+    double* stage = red + 24;
+    local_linear_solve<NPL>(P, L, np, i, n, rowbase, rb, r0, dl, red, false, stage,
+                            lds_bytes - (int)((char*)stage - (char*)smem));
     for (int a = threadIdx.x; a < n; a += blockDim.x) L.z[rowbase + a] = rb[a];
 }
 
@@ -2836,7 +3101,7 @@ hipError_t launch_local_newton(const DevMesh& M, const DevMaps& P, const DevLoca
 #define NLS_LN(NPL, EL)                                                              \
     e = set_lds(k_local_newton<NPL, EL>, lds_bytes);                                 \
     if (e != hipSuccess) return e;                                                   \
-    k_local_newton<NPL, EL><<<nblk, NLS_BLOCK, lds_bytes, s>>>(M, P, L, np, u);
+    k_local_newton<NPL, EL><<<nblk, NLS_BLOCK, lds_bytes, s>>>(M, P, L, np, u, lds_bytes);
     if (M.kind == NLS_PROBLEM_NEOHOOKE) {
         if (npl <= 1) { NLS_LN(1, true) } else if (npl == 2) { NLS_LN(2, true) } else { NLS_LN(4, true) }
     } else {
@@ -2872,7 +3137,7 @@ hipError_t launch_tangent_local(const DevMesh& M, const DevMaps& P, const DevLoc
 #define NLS_TL(NPL)                                                                  \
     e = set_lds(k_tangent_local<NPL>, lds_bytes);                                    \
     if (e != hipSuccess) return e;                                                   \
-    k_tangent_local<NPL><<<P.nsub, NLS_BLOCK, lds_bytes, s>>>(M, P, L, np, v, restrict_rhs);
+    k_tangent_local<NPL><<<P.nsub, NLS_BLOCK, lds_bytes, s>>>(M, P, L, np, v, restrict_rhs, lds_bytes);
     if (npl <= 1) { NLS_TL(1) } else if (npl == 2) { NLS_TL(2) } else { NLS_TL(4) }
 #undef NLS_TL
     return hipGetLastError();
