@@ -636,6 +636,11 @@ __device__ __forceinline__ int band_lu_blocked(int n, int kl, int ku, const int*
     static_assert(!BF16 || sizeof(T) == 4, "bfloat16 updates need binary32 factors");
     T* lt = W + (NB + kl) * (NB + kl + ku);  // L11 of the current panel by columns, NB x NB
     int* mv = (int*)(lt + NB * NB);           // moved rows of the panel (<= 64)
+    // multipliers of the panel's steps, staged by wavefront 0 at the row's
+    // position after the step (NB + position - step - 1), copied out by the
+    // whole workgroup with the U rows
+    constexpr int LSW = 64 + NB;
+    T* ls = (T*)(mv + 64);
     const int tid = threadIdx.x, nt = blockDim.x;
     const int lane = tid & 63, wv = tid >> 6;
     const int H = NB + kl, Wd = NB + kl + ku;
@@ -721,7 +726,6 @@ __device__ __forceinline__ int band_lu_blocked(int n, int kl, int ku, const int*
             // pivot search.
             int dsel = lane;        // lane j: the pivot position of step j
             int posj[NB];           // position of this row after step j
-            unsigned below_mask = 0u;
 #pragma unroll
             for (int j = 0; j < NB; ++j) {
                 // a step past the last column (j >= nbp, last panel only)
@@ -752,7 +756,6 @@ __device__ __forceinline__ int band_lu_blocked(int n, int kl, int ku, const int*
                 sing |= (act && pivv == T(0)) ? 1 : 0;
                 const T inv = pivv != T(0) ? recip(pivv) : T(0);
                 const bool below = cand && lane != pl;
-                below_mask |= below ? (1u << j) : 0u;
                 // l = 0 leaves the rows that are not below the pivot as they are
                 const T l = below ? p[j] * inv : T(0);
                 p[j] = below ? l : p[j];
@@ -761,9 +764,10 @@ __device__ __forceinline__ int band_lu_blocked(int n, int kl, int ku, const int*
                 if (rhs) pb -= (double)l * rdlane(pb, plr);
             }
             if (lane < nbp) piv[k0 + lane] = k0 + dsel;
+            // every lane writes its slot (positions are distinct); the rows
+            // not below a step's pivot fall outside the copied range
 #pragma unroll
-            for (int j = 0; j < NB; ++j)
-                if ((below_mask >> j) & 1u) Lf[(size_t)(k0 + j) * ldl + (posj[j] - j - 1)] = p[j];
+            for (int j = 0; j < NB; ++j) ls[j * LSW + NB + posj[j] - j - 1] = p[j];
             if (rhs && have) rhs[k0 + pos] = pb;
             if (have) {
                 const int sp = wrap(rb + pos, H);
@@ -849,54 +853,59 @@ __device__ __forceinline__ int band_lu_blocked(int n, int kl, int ku, const int*
             if (nr2 > 0 && ntr > 0) {
                 const int tr = (nr2 + 15) >> 4, tc = (ntr + 15) >> 4;
                 const int li = lane & 15, lk = lane >> 4;
-                for (int t = wv; t < tr * tc; t += nt >> 6) {
-                    const int r0 = NB + 16 * (t / tc), c0 = NB + 16 * (t % tc);
+                // tile t = rt tc + ct, t = wv, wv + 4, ..: (rt, ct) advanced
+                // without divisions.  Loads are unconditional, from clamped
+                // in-window addresses: rows >= rvalid and columns >= ntr give
+                // outputs that are not stored (selecting after the load lets
+                // the compiler move each load under a branch of its own), and
+                // with trailing columns the panel is full (nbp = NB)
+                const int nw = nt >> 6;
+                int rt = wv / tc, ct = wv - (wv / tc) * tc;
+                for (int t = wv; t < tr * tc; t += nw) {
+                    const int r0 = NB + 16 * rt, c0 = NB + 16 * ct;
+                    ct += nw;
+                    while (ct >= tc) {
+                        ct -= tc;
+                        ++rt;
+                    }
                     // C: lane holds rows r0 + row(lk, q), column c0 + li
                     const int cc = c0 + li;
                     const bool cok = cc < NB + ntr;
                     const int scc = wrap(cb + (cok ? cc : 0), Wd);
                     typename Mfma<T>::acc_t acc;
-                    // every load reads an in-window address (rows and
-                    // columns clamped) and is selected afterwards, so the
-                    // loads of a tile are issued together
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         const int rr = r0 + Mfma<T>::row(lk, q);
-                        const bool ok = cok && rr < rvalid;
-                        const T w = W[wrap(rb + (ok ? rr : 0), H) * Wd + scc];
-                        acc[q] = ok ? w : T(0);
+                        acc[q] = W[wrap(rb + (rr < rvalid ? rr : 0), H) * Wd + scc];
                     }
                     // A = -L21 (rows r0 + li, k = 4 s + lk), B = U12 (rows k, column cc)
                     const int ra = r0 + li;
-                    const bool aok = ra < rvalid;
-                    const int sra = wrap(rb + (aok ? ra : 0), H);
+                    const int sra = wrap(rb + (ra < rvalid ? ra : 0), H);
                     if constexpr (BF16) {
                         // one 16x16x16 product: lane holds k = 4 lk .. 4 lk + 3
-                        // (k >= nbp, e.g. k >= 8 of an 8-column panel, are zero)
+                        // (k >= NB, i.e. k >= 8 of an 8-column panel, are zero)
                         bf16x4_t a4, b4;
 #pragma unroll
                         for (int t4 = 0; t4 < 4; ++t4) {
                             const int k = 4 * lk + t4;
-                            const bool kin = k < nbp;
+                            const bool kin = k < NB;
                             const int kk = kin ? k : 0;
                             const float wa = W[sra * Wd + wrap(cb + kk, Wd)];
                             const float wb = W[wrap(rb + kk, H) * Wd + scc];
-                            const float av = (aok && kin) ? -wa : 0.f;
-                            const float bv = (cok && kin) ? wb : 0.f;
-                            a4[t4] = bf16_rne(av);
-                            b4[t4] = bf16_rne(bv);
+                            a4[t4] = bf16_rne(kin ? -wa : 0.f);
+                            b4[t4] = bf16_rne(kin ? wb : 0.f);
                         }
                         acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a4, b4, acc, 0, 0, 0);
                     } else {
+                        T av[NB / 4], bv[NB / 4];
 #pragma unroll
                         for (int s4 = 0; s4 < NB / 4; ++s4) {
                             const int k = 4 * s4 + lk;
-                            const T wa = W[sra * Wd + wrap(cb + k, Wd)];
-                            const T wb = W[wrap(rb + k, H) * Wd + scc];
-                            const T av = (aok && k < nbp) ? -wa : T(0);
-                            const T bv = (cok && k < nbp) ? wb : T(0);
-                            acc = Mfma<T>::step(av, bv, acc);
+                            av[s4] = -W[sra * Wd + wrap(cb + k, Wd)];
+                            bv[s4] = W[wrap(rb + k, H) * Wd + scc];
                         }
+#pragma unroll
+                        for (int s4 = 0; s4 < NB / 4; ++s4) acc = Mfma<T>::step(av[s4], bv[s4], acc);
                     }
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
@@ -912,12 +921,28 @@ __device__ __forceinline__ int band_lu_blocked(int n, int kl, int ku, const int*
                 if (r < nbp && o >= 0 && o < ldu && k0 + c < n)
                     Uf[(size_t)(k0 + c) * ldu + o] = W[wrap(rb + r, H) * Wd + wrap(cb + c, Wd)];
             }
+            // multipliers of step j: Lf[(k0 + j) ldl + i], i < min(kl, n - 1 - k0 - j),
+            // the steps spread over the wavefronts
+            for (int j = wv; j < nbp; j += nt >> 6) {
+                const int lim = min(kl, n - 1 - (k0 + j));
+                for (int i = lane; i < lim; i += 64) Lf[(size_t)(k0 + j) * ldl + i] = ls[j * LSW + NB + i];
+            }
         }
         lds_barrier();
         // ---- slide by NB: rows k0.. and columns k0.. leave the window
-        for (int i = tid; i < NB * Wd; i += nt) {
-            const int q = i / Wd, c = i - q * Wd;
-            W[wrap(rb + q, H) * Wd + c] = T(0);
+        {
+            // (row q, column c) of thread tid + m nt, advanced without divisions
+            const int dq = nt / Wd, dc = nt - dq * Wd;
+            int q = tid / Wd, c = tid - q * Wd;
+            while (q < NB) {
+                W[wrap(rb + q, H) * Wd + c] = T(0);
+                c += dc;
+                q += dq;
+                if (c >= Wd) {
+                    c -= Wd;
+                    ++q;
+                }
+            }
         }
         for (int i = tid; i < H * NB; i += nt) {
             const int r = i / NB, q = i - r * NB;

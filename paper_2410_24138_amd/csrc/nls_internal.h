@@ -9,19 +9,20 @@
 
 // Band-window size of the LU kernels (ring buffers): blocked panels of NB
 // columns need (NB+kl) x (NB+kl+ku); the unblocked form (kl+1) x (kl+ku+1).
-// Blocked variants: (NB + kl) x (NB + kl + ku) window, NB x NB L11, and 64
-// ints (32 doubles) for the panel's moved-row list.
+// Blocked variants: (NB + kl) x (NB + kl + ku) window, NB x NB L11, 64 ints
+// (32 doubles) for the panel's moved-row list and NB x (64 + NB) staged
+// multipliers.
 inline int band_window_doubles(int kl, int ku) {
-    if (kl + 16 <= 64) return (16 + kl) * (16 + kl + ku) + 16 * 16 + 32;
-    if (kl + 8 <= 64) return (8 + kl) * (8 + kl + ku) + 8 * 8 + 32;
+    if (kl + 16 <= 64) return (16 + kl) * (16 + kl + ku) + 16 * 16 + 32 + 16 * 80;
+    if (kl + 8 <= 64) return (8 + kl) * (8 + kl + ku) + 8 * 8 + 32 + 8 * 72;
     return (kl + 1) * (kl + ku + 1);
 }
 // Window of a forced LU variant: 1 blocked NB=16, 2 blocked NB=8,
 // 3 unblocked, 0 the automatic choice above; -1 if the variant cannot hold kl.
 inline int band_window_doubles_v(int kl, int ku, int v) {
     if (v == 0) return band_window_doubles(kl, ku);
-    if (v == 1) return kl + 16 <= 64 ? (16 + kl) * (16 + kl + ku) + 16 * 16 + 32 : -1;
-    if (v == 2) return kl + 8 <= 64 ? (8 + kl) * (8 + kl + ku) + 8 * 8 + 32 : -1;
+    if (v == 1) return kl + 16 <= 64 ? (16 + kl) * (16 + kl + ku) + 16 * 16 + 32 + 16 * 80 : -1;
+    if (v == 2) return kl + 8 <= 64 ? (8 + kl) * (8 + kl + ku) + 8 * 8 + 32 + 8 * 72 : -1;
     return (kl + 1) * (kl + ku + 1);
 }
 // LDS of the fused local Newton kernel, in doubles:
