@@ -57,8 +57,8 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per dispatch measured with rocprofv3 FETCH_SIZE/WRITE_SIZE (two
 # passes, calibrated against a 256 MiB copy; profiles/hbm_traffic_*.md), valid
 # only for the kernel source they were taken with.
-MEASURED_TRAFFIC = {"kernels_sha1": "6842cb53b96de61b447c25d205f453e7870d657d",
-                    "bytes": {"k_local_newton": 979624183, "k_local_factor": 434428395, "k_tangent_prep": 1199293573, "k_tangent_gemv": 280761828, "k_coarse_galerkin": 211827691, "k_coarse_lu": 1406956, "k_coarse_inverse": 12186622, "k_coarse_apply_inverse": 4089522, "k_mdot_partial": 25635868, "k_maxpy": 48707194, "k_prolong": 27170961, "k_coarse_ty": 20655149}}
+MEASURED_TRAFFIC = {"kernels_sha1": "42ce754612e712771963480d3fc17c2b43d5f2f4",
+                    "bytes": {"k_local_newton": 1730232065, "k_local_factor": 397367411, "k_tangent_prep": 1199040796, "k_tangent_gemv": 280761218, "k_coarse_galerkin": 107920901, "k_coarse_galerkin_sum": 99517818, "k_coarse_lu": 1787328, "k_coarse_inverse": 12185800, "k_coarse_apply_inverse": 4100887, "k_mdot_partial": 25692412, "k_maxpy": 48709363, "k_prolong": 27325717, "k_coarse_ty": 20647838, "k_coarse_q": 80426020}}
 
 
 def unit_work(case, elem_bytes=8):
