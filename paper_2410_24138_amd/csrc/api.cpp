@@ -497,6 +497,35 @@ extern "C" int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* el
             // cache between products: stream it past the cache instead
             h->w_stream = (size_t)M.off_W.back() * sizeof(double) > ((size_t)192 << 20);
             RC(h->alloc(G_MAPS, &T.fwd, (size_t)M.off_F.back()));
+            // the blocked solve holds the window of 16 + kl rows in four
+            // row tiles and the backward strip of 16 + kl + ku rows in its
+            // LDS ring
+            int max_kl = 0, max_kw = 0;
+            for (int i = 0; i < M.nsub; ++i) {
+                max_kl = std::max(max_kl, M.kl[i]);
+                max_kw = std::max(max_kw, M.kl[i] + M.ku[i]);
+            }
+            h->tangent_nblk = 0;
+            h->tangent_nkk = 0;
+            if (max_kl <= 48 && max_kw <= 112 && !(h->opt.flags & NLS_FLAG_TANGENT_SWEEP)) {
+                std::vector<int> off_blk(1, 0), blk_sub;
+                for (int i = 0; i < M.nsub; ++i) {
+                    const int nb = (M.off_n[i + 1] - M.off_n[i] + 15) / 16;
+                    for (int b = 0; b < nb; ++b) blk_sub.push_back(i);
+                    off_blk.push_back(off_blk.back() + nb);
+                }
+                const size_t nblk = blk_sub.size();
+                int *d_off_blk, *d_blk_sub;
+                RC(h->upload(G_MAPS, &d_off_blk, off_blk));
+                RC(h->upload(G_MAPS, &d_blk_sub, blk_sub));
+                T.off_blk = d_off_blk;
+                T.blk_sub = d_blk_sub;
+                RC(h->alloc(G_MAPS, &T.tsig, nblk * 64));
+                RC(h->alloc(G_MAPS, &T.tG, nblk * 1024));
+                RC(h->alloc(G_MAPS, &T.tUi, nblk * 256));
+                h->tangent_nblk = (int)nblk;
+                h->tangent_nkk = (max_kw + 3) / 4;
+            }
             h->dt = T;
         }
     }
@@ -1085,8 +1114,12 @@ static int prepare_tangent(nls_handle* h) {
     }
     if (h->tangent_w) {
         Timer tp;
-        const hipError_t e = launch_tangent_prep(h->dp, h->dl, h->dt, h->tangent_bucket, h->max_ng,
-                                                 h->stream);
+        const hipError_t e =
+            h->tangent_nblk > 0
+                ? launch_tangent_blocked(h->dp, h->dl, h->dt, h->tangent_nblk, h->tangent_nkk,
+                                         h->max_ng, h->stream)
+                : launch_tangent_prep(h->dp, h->dl, h->dt, h->tangent_bucket, h->max_ng,
+                                      h->stream);
         if (e != hipSuccess) return bail(fail(h, NLS_EHIP, hipGetErrorString(e)));
         const int rc = sync(h);
         if (rc) return bail(rc);

@@ -52,6 +52,7 @@ struct nls_handle {
     bool tangent_w = false;       // W_i = J^{-1} B on owned rows (else per-apply solves)
     bool w_stream = false;        // W read with nontemporal loads (too large to stay cached)
     int tangent_bucket = 0, max_ng = 0;
+    int tangent_nblk = 0, tangent_nkk = 0;  // > 0: W_i by the blocked matrix-core solve
     bool coarse_inv = false;      // explicit A0^{-1} for the tangent
     bool coarse_lu_valid = false; // a factorisation of A0 is held (chord steps)
     bool coarse_inv_valid = false; // a0inv is the inverse of that factorisation

@@ -1900,6 +1900,306 @@ k_tangent_prep(DevMaps P, DevLocal L, DevTangent Tg) {
                             valid, col, Tg.fwd + Tg.off_F[i], ng, rowown, smem, sint, put);
 }
 
+// ----------------------------------------------------------------------------
+// W_i = J_ii^{-1} B_i on the matrix cores.  The band LU's forward elimination
+// (an interchange, then multipliers below the pivot, at every step) is taken
+// 16 steps at a time: the steps of block b (rows from k0 = 16 b) act on the
+// window of R = 16 + kl rows from k0 only, and their product is
+// L_b^{-1} P_b, with P_b a permutation of the window and L_b unit lower
+// triangular, the identity right of its first 16 columns.  With X' = P_b X
+// on the window, X <- [0; X'_2] + G_b X'_1 with G_b = [L11^{-1}; -L21 L11^{-1}]
+// ((16 + kl) x 16), a product on 16x16x4 FP64 matrix-core steps.  The
+// backward substitution goes up in the same blocks: X_1 <- U11^{-1}
+// (Y_1 - U12 X_2), U12 the 16 x (kl + ku) band strip right of the diagonal
+// block.  k_tangent_blocks forms, one wavefront per block of every
+// subdomain, sigma_b (P_b as a gather: position p of X' holds window row
+// sigma_b(p)), G_b and U11^{-1}, stored in the operand order of the
+// matrix-core steps; k_tangent_mfma runs both sweeps, one wavefront per 16
+// columns of B_i, with its window of X in LDS.  Same operator as the
+// per-lane sweeps above, with the rounding of a blocked elimination.
+// ----------------------------------------------------------------------------
+constexpr int TB_RT = 4;              // row tiles of G_b (16 + kl <= 64)
+constexpr int TB_G = TB_RT * 4 * 64;  // doubles of G_b per block
+constexpr int TB_U = 4 * 64;          // doubles of U11^{-1} per block
+constexpr int TB_RING = 128;          // window rows in LDS (>= 16 + kl + ku)
+
+__global__ void __launch_bounds__(64) k_tangent_blocks(DevMaps P, DevLocal L, DevTangent Tg) {
+    __shared__ double Lb[64 * 17];
+    __shared__ double Ub[16 * 17];
+    const int gb = blockIdx.x;
+    const int i = Tg.blk_sub[gb];
+    const int k0 = (gb - Tg.off_blk[i]) * 16;
+    const int rowbase = P.off_n[i], n = P.off_n[i + 1] - rowbase;
+    const int kl = P.kl[i], kw = kl + P.ku[i];
+    const int ldu = kw + 1, ldl = kl > 1 ? kl : 1;
+    const double* __restrict__ Lf = L.Lf + P.off_l[i];
+    const double* __restrict__ Uf = L.Uf + P.off_u[i];
+    const int lane = threadIdx.x;
+    const int ns = min(16, n - k0);  // steps of this block; past n the identity
+    // every load first: lane s < ns holds the pivot offset of step s, lane q
+    // the multipliers of each step s for window position q
+    const int pv = lane < ns ? L.piv[rowbase + k0 + lane] - k0 : lane;
+    double lv[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+        const int j = lane - s - 1;
+        const bool ok = s < ns && j >= 0 && j < kl && k0 + s + 1 + j < n;
+        const double v = Lf[ok ? (size_t)(k0 + s) * ldl + j : 0];
+        lv[s] = ok ? v : 0.0;
+    }
+    double uv[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int r = (lane + 64 * e) >> 4, c = (lane + 64 * e) & 15;
+        const bool ok = c < ns && r <= c && c - r <= kw;
+        const double v = Uf[ok ? (size_t)(k0 + c) * ldu + (c - r) : 0];
+        uv[e] = ok ? v : (r == c ? 1.0 : 0.0);  // rows and columns past n: identity
+    }
+    for (int e = lane; e < 64 * 17; e += 64) Lb[e] = 0.0;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) Ub[((lane + 64 * e) >> 4) * 17 + ((lane + 64 * e) & 15)] = uv[e];
+    // sigma_b: the interchanges of the block applied to the window positions
+    int ident = lane;
+#pragma unroll
+    for (int s = 0; s < 16; ++s)
+        if (s < ns) {
+            const int d = __builtin_amdgcn_readlane(pv, s);
+            const int va = __builtin_amdgcn_readlane(ident, s);
+            const int vc = __builtin_amdgcn_readlane(ident, d);
+            if (lane == s) ident = vc;
+            if (lane == d) ident = va;
+        }
+    Tg.tsig[(size_t)gb * 64 + lane] = ident;
+    // L_b: step s's multiplier for the row at position q after that step's
+    // interchange belongs to the row's position after the whole block, m_s(q);
+    // m runs backward from the identity (after the last step).  Lanes without
+    // a multiplier store the zero of L_b at their position.
+    __syncthreads();
+    int m = lane;
+#pragma unroll
+    for (int s = 15; s >= 0; --s)
+        if (s < ns) {
+            Lb[m * 17 + s] = lv[s];
+            const int d = __builtin_amdgcn_readlane(pv, s);
+            const int va = __builtin_amdgcn_readlane(m, s);
+            const int vc = __builtin_amdgcn_readlane(m, d);
+            if (lane == s) m = vc;
+            if (lane == d) m = va;
+        }
+    __syncthreads();
+    // G_b = L_b^{-1}[:, 0:16]: lane (c, g) substitutes e_c through L11 (unit
+    // diagonal; entries on and above it are not read), then forms rows
+    // 16 + g + 4 t of -L21 L11^{-1}.  G_b[p][c] is lane (p & 15) + 16 (c & 3)
+    // of k-step c >> 2 of row tile p >> 4.
+    const int c = lane & 15, g = lane >> 4, kk = c >> 2, lc = 16 * (c & 3);
+    double x[16];
+#pragma unroll
+    for (int p = 0; p < 16; ++p) x[p] = (p == c) ? 1.0 : 0.0;
+#pragma unroll
+    for (int s = 0; s < 15; ++s)
+#pragma unroll
+        for (int p = s + 1; p < 16; ++p) x[p] = fma(-Lb[p * 17 + s], x[s], x[p]);
+    double* __restrict__ G = Tg.tG + (size_t)gb * TB_G;
+#pragma unroll
+    for (int p = 0; p < 16; ++p)
+        if ((p & 3) == g) G[kk * 64 + p + lc] = x[p];
+#pragma unroll
+    for (int t = 0; t < 12; ++t) {
+        const int p = 16 + g + 4 * t;
+        double a = 0.0;
+#pragma unroll
+        for (int s = 0; s < 16; ++s) a = fma(Lb[p * 17 + s], x[s], a);
+        G[((p >> 4) * 4 + kk) * 64 + (p & 15) + lc] = -a;
+    }
+    // U11^{-1} by columns (back substitution with e_c); entry [r][c] is lane
+    // r + 16 (c & 3) of k-step c >> 2
+    double y[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) y[r] = (r == c) ? 1.0 : 0.0;
+#pragma unroll
+    for (int jj = 15; jj >= 0; --jj) {
+        y[jj] = y[jj] / Ub[jj * 17 + jj];
+#pragma unroll
+        for (int r = 0; r < jj; ++r) y[r] = fma(-Ub[r * 17 + jj], y[jj], y[r]);
+    }
+    double* __restrict__ Ui = Tg.tUi + (size_t)gb * TB_U;
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+        if ((r & 3) == g) Ui[kk * 64 + r + lc] = y[r];
+}
+
+// One wavefront per (subdomain, 16 columns of B_i).  Forward: the window
+// rows [k0, k0 + R) sit in an LDS ring; rows entering it are filled from the
+// column's (row, value) list of B_i; each block gathers X' = P_b X from the
+// ring by sigma_b, forms [0; X'_2] + G_b X'_1 (up to four row tiles of 16),
+// writes rows k0 .. k0 + 15 (final) to the scratch Y and keeps the rest in
+// the ring.  Backward: the solved rows above the block's strip sit in the
+// ring; each block forms Y_1 - U12 X_2 (U12 read from the band factor, NKK
+// k-steps of 4 columns at most), then U11^{-1} times it (the FP64 result
+// layout, rows g + 4 q in lane (c, g), is already the operand layout of the
+// next product), and writes the owned rows to W.  The operands of the next
+// block are loaded while the current one computes.
+template <int NKK>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NKK <= 18 ? 3 : 2)))
+k_tangent_mfma(DevMaps P, DevLocal L, DevTangent Tg) {
+    typedef Mfma<double>::acc_t acc_t;
+    __shared__ double ring[TB_RING * 16];
+    constexpr int RM = TB_RING - 1;
+    const int i = P.order[blockIdx.x];
+    const int rowbase = P.off_n[i], n = P.off_n[i + 1] - rowbase;
+    const int gbase = P.off_g[i], ng = P.off_g[i + 1] - gbase;
+    const int tile = blockIdx.y;
+    if (tile * 16 >= ng) return;  // uniform over the wavefront
+    const int kl = P.kl[i], kw = kl + P.ku[i], ldu = kw + 1, R = 16 + kl;
+    const int rtn = (R + 15) >> 4, nkk = (kw + 3) >> 2;
+    const int lane = threadIdx.x, c = lane & 15, h = lane >> 4;
+    const int col = tile * 16 + c;
+    const bool cv = col < ng;
+    const int nb = (n + 15) >> 4, b0 = Tg.off_blk[i];
+    int re[NLS_MAX_BCOL];
+    double ve[NLS_MAX_BCOL];
+    {
+        const int pb = cv ? Tg.bptr[gbase + col] : 0, pe = cv ? Tg.bptr[gbase + col + 1] : 0;
+#pragma unroll
+        for (int q = 0; q < NLS_MAX_BCOL; ++q) {
+            re[q] = (pb + q < pe) ? Tg.brow[pb + q] : -1;
+            ve[q] = (pb + q < pe) ? L.jval[Tg.bslot[pb + q]] : 0.0;
+        }
+    }
+    // rows [lo, lo + 16) of B_i's column into the ring (rows past n: zero)
+    auto fill16 = [&](int lo) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = lo + h + 4 * q;
+            double v = 0.0;
+#pragma unroll
+            for (int e = 0; e < NLS_MAX_BCOL; ++e) v = (re[e] == r) ? ve[e] : v;
+            ring[(r & RM) * 16 + c] = v;
+        }
+    };
+    double* __restrict__ Y = Tg.fwd + Tg.off_F[i] + (size_t)tile * nb * 256;
+    const int* __restrict__ sig = Tg.tsig + (size_t)b0 * 64;
+    const double* __restrict__ Gs = Tg.tG + (size_t)b0 * TB_G;
+    for (int lo = 0; lo < R; lo += 16) fill16(lo);
+    // operands of block b + 1 are loaded once block b's products have
+    // been issued (into the registers those products read)
+    int sg = sig[lane];
+    double ga[TB_RT * 4];
+#pragma unroll
+    for (int e = 0; e < TB_RT * 4; ++e) ga[e] = Gs[e * 64 + lane];
+    for (int b = 0; b < nb; ++b) {
+        const int k0 = b * 16;
+        if (b > 0) fill16(k0 + kl);
+        double bo[4];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            const int sp = __shfl(sg, 4 * kk + h);
+            bo[kk] = ring[((k0 + sp) & RM) * 16 + c];
+        }
+        acc_t acc[TB_RT];
+        acc[0] = acc_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int rt = 1; rt < TB_RT; ++rt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int p = 16 * rt + h + 4 * q;
+                const int sp = __shfl(sg, p);
+                const double v = ring[((k0 + sp) & RM) * 16 + c];
+                acc[rt][q] = p < R ? v : 0.0;
+            }
+#pragma unroll
+        for (int rt = 0; rt < TB_RT; ++rt)
+            if (rt < rtn) {
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk)
+                    acc[rt] = Mfma<double>::step(ga[rt * 4 + kk], bo[kk], acc[rt]);
+            }
+        if (b + 1 < nb) {
+            sg = sig[(b + 1) * 64 + lane];
+#pragma unroll
+            for (int e = 0; e < TB_RT * 4; ++e) ga[e] = Gs[(size_t)(b + 1) * TB_G + e * 64 + lane];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Y[(size_t)(k0 + h + 4 * q) * 16 + c] = acc[0][q];
+#pragma unroll
+        for (int rt = 1; rt < TB_RT; ++rt)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int p = 16 * rt + h + 4 * q;
+                if (p < R) ring[((k0 + p) & RM) * 16 + c] = acc[rt][q];
+            }
+    }
+    __syncthreads();
+    for (int e = lane; e < TB_RING * 16; e += 64) ring[e] = 0.0;
+    __syncthreads();
+    const double* __restrict__ Uf = L.Uf + P.off_u[i];
+    const double* __restrict__ Us = Tg.tUi + (size_t)b0 * TB_U;
+    double* __restrict__ W = Tg.W + Tg.off_W[i];
+    const int* __restrict__ rowown = Tg.rowown + rowbase;
+    const int nown = Tg.off_own[i + 1] - Tg.off_own[i];
+    // A[r][j] = -U[k0 + r][k0 + 16 + j] (r = c, j = 4 kk + h): column
+    // k0 + 16 + j of the band factor, t = 16 + j - r above its diagonal
+    // (NKK >= nkk k-steps; those past nkk have A = 0).  With them: Y_1,
+    // U11^{-1} and the owned-row index of each result row.  The loads take
+    // clamped in-range addresses and are masked where they are used; those
+    // of block b - 1 are issued once block b's strip products have been.
+    double ua[NKK], yn[4], un[4];
+    int on[4];
+    auto load_blk = [&](int b) {
+        const int k0 = b * 16;
+#pragma unroll
+        for (int kk = 0; kk < NKK; ++kk) {
+            const int j = 4 * kk + h, cu = min(k0 + 16 + j, n - 1), t = min(16 + j - c, kw);
+            ua[kk] = Uf[(size_t)cu * ldu + t];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = k0 + h + 4 * q;
+            yn[q] = Y[(size_t)r * 16 + c];
+            on[q] = rowown[min(r, n - 1)];
+        }
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) un[kk] = Us[(size_t)b * TB_U + kk * 64 + lane];
+    };
+    load_blk(nb - 1);
+    for (int b = nb - 1; b >= 0; --b) {
+        const int k0 = b * 16;
+        double uc[4];
+        int oc[4];
+        acc_t acc0, acc1 = acc_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            acc0[q] = yn[q];
+            uc[q] = un[q];
+            oc[q] = (cv && k0 + h + 4 * q < n) ? on[q] : -1;
+        }
+#pragma unroll
+        for (int kk = 0; kk < NKK; kk += 2) {
+#pragma unroll
+            for (int d = 0; d < 2; ++d) {
+                if (kk + d >= NKK) break;
+                const int j = 4 * (kk + d) + h;
+                const bool ok = kk + d < nkk && k0 + 16 + j < n && 16 + j - c <= kw;
+                const double a = ok ? -ua[kk + d] : 0.0;
+                const double xb = ring[((k0 + 16 + j) & RM) * 16 + c];
+                if (d == 0)
+                    acc0 = Mfma<double>::step(a, xb, acc0);
+                else
+                    acc1 = Mfma<double>::step(a, xb, acc1);
+            }
+        }
+        if (b > 0) load_blk(b - 1);
+        acc_t xo = acc_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) xo = Mfma<double>::step(uc[kk], acc0[kk] + acc1[kk], xo);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            ring[((k0 + h + 4 * q) & RM) * 16 + c] = xo[q];
+            if (oc[q] >= 0) W[(size_t)col * nown + oc[q]] = xo[q];
+        }
+    }
+}
+
 // z[owned rows of i] = W_i v_Gamma_i: streams W (column-major, one owned
 // row per thread) once; HBM-bound.  Grid (nsub, QS) splits each
 // subdomain's rows over QS blocks.  STREAM: W is read with nontemporal
@@ -3326,6 +3626,23 @@ hipError_t launch_tangent_prep(const DevMaps& P, const DevLocal& L, const DevTan
     NLS_MR_BUCKETS(NLS_TP)
 #undef NLS_TP
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_tangent_blocked(const DevMaps& P, const DevLocal& L, const DevTangent& Tg,
+                                  int nblk, int nkk, int max_ng, hipStream_t s) {
+    if (nblk <= 0 || nkk < 1 || nkk > 28) return hipErrorInvalidValue;
+    k_tangent_blocks<<<nblk, 64, 0, s>>>(P, L, Tg);
+    dim3 grid(P.nsub, (max_ng + 15) / 16);
+    // nkk: k-steps of 4 band columns in the backward strip
+    if (nkk <= 12)
+        k_tangent_mfma<12><<<grid, 64, 0, s>>>(P, L, Tg);
+    else if (nkk <= 18)
+        k_tangent_mfma<18><<<grid, 64, 0, s>>>(P, L, Tg);
+    else if (nkk <= 24)
+        k_tangent_mfma<24><<<grid, 64, 0, s>>>(P, L, Tg);
+    else
+        k_tangent_mfma<28><<<grid, 64, 0, s>>>(P, L, Tg);
+    return hipGetLastError();
 }
 
 hipError_t launch_tangent_gemv(const DevMaps& P, const DevTangent& Tg, const double* v, double* z,

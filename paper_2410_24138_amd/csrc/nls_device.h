@@ -60,7 +60,12 @@ struct DevTangent {
     const int *off_own, *ownrow, *rowown;
     const int64_t *off_W, *off_F;
     double* W;                        // sum |owned_i| |Gamma_i|
-    double* fwd;                      // sum n_i |Gamma_i| (forward-sweep scratch)
+    double* fwd;                      // sum ceil16(n_i) ceil16(|Gamma_i|) (forward-sweep scratch)
+    // blocked solve on the matrix cores: blocks of 16 rows, off_blk[i] the
+    // first block of subdomain i, blk_sub the subdomain of each block
+    const int *off_blk, *blk_sub;
+    int* tsig;                        // 64 per block: sigma_b
+    double *tG, *tUi;                 // per block: G_b, U11^{-1} in operand order
 };
 
 struct NewtonParams {
@@ -183,6 +188,10 @@ int mrhs_bucket_kl(int kl, int ku);
 int mrhs_lds_bytes(int kl_bucket);
 hipError_t launch_tangent_prep(const DevMaps& P, const DevLocal& L, const DevTangent& Tg,
                                int kl_bucket, int max_ng, hipStream_t s);
+// the same W_i by the blocked solve on the matrix cores (kl <= 48,
+// kl + ku <= 112): nblk blocks in all, nkk = ceil(max (kl + ku) / 4)
+hipError_t launch_tangent_blocked(const DevMaps& P, const DevLocal& L, const DevTangent& Tg,
+                                  int nblk, int nkk, int max_ng, hipStream_t s);
 // stream_w: nontemporal loads of W (for a W larger than the last-level cache)
 hipError_t launch_tangent_gemv(const DevMaps& P, const DevTangent& Tg, const double* v, double* z,
                                int max_ng, bool stream_w, hipStream_t s);

@@ -231,7 +231,7 @@ int nls_build_maps(const HostMesh& m, const int* part, int nsub, int overlap,
             }
         M.off_own.push_back((int)M.ownrow.size());
         M.off_W.push_back(M.off_W.back() + (int64_t)no * ng);
-        M.off_F.push_back(M.off_F.back() + (int64_t)n * ng);
+        M.off_F.push_back(M.off_F.back() + (int64_t)((n + 15) / 16 * 16) * ((ng + 15) / 16 * 16));
     }
 
     // factor storage and launch order

@@ -49,6 +49,7 @@ FLAG_COARSE_CHORD = 4
 FLAG_COARSE_LU_APPLY = 8
 FLAG_AUTOTUNE = 16
 FLAG_OVERLAP = 32
+FLAG_TANGENT_SWEEP = 64
 
 # every symbol include/nls.h declares
 SYMBOLS = (
