@@ -57,8 +57,8 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per dispatch measured with rocprofv3 FETCH_SIZE/WRITE_SIZE (two
 # passes, calibrated against a 256 MiB copy; profiles/hbm_traffic_*.md), valid
 # only for the kernel source they were taken with.
-MEASURED_TRAFFIC = {"kernels_sha1": "42ce754612e712771963480d3fc17c2b43d5f2f4",
-                    "bytes": {"k_local_newton": 1730232065, "k_local_factor": 397367411, "k_tangent_prep": 1199040796, "k_tangent_gemv": 280761218, "k_coarse_galerkin": 107920901, "k_coarse_galerkin_sum": 99517818, "k_coarse_lu": 1787328, "k_coarse_inverse": 12185800, "k_coarse_apply_inverse": 4100887, "k_mdot_partial": 25692412, "k_maxpy": 48709363, "k_prolong": 27325717, "k_coarse_ty": 20647838, "k_coarse_q": 80426020}}
+MEASURED_TRAFFIC = {"kernels_sha1": "c34c4ab9ecb62eb9a202b4d9d49c41a61fba626c",
+                    "bytes": {"k_local_newton": 1726935778, "k_local_factor": 397330638, "k_tangent_blocks": 359830512, "k_tangent_mfma": 3170894673, "k_tangent_gemv": 280759503, "k_coarse_galerkin": 108151384, "k_coarse_galerkin_sum": 97708774, "k_coarse_lu": 1786430, "k_coarse_inverse": 12186811, "k_coarse_apply_inverse": 4093712, "k_mdot_partial": 25692619, "k_maxpy": 48708378, "k_prolong": 27325029, "k_coarse_ty": 20659157, "k_coarse_q": 80461750}}
 
 
 def unit_work(case, elem_bytes=8):
