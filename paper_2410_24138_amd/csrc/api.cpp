@@ -617,6 +617,10 @@ extern "C" int nls_build_coarse(nls_handle* h, int kind, const double* u_lin) {
     int maxb = 0;
     for (size_t b = 0; b + 1 < C.boff.size(); ++b) maxb = std::max(maxb, C.boff[b + 1] - C.boff[b]);
     h->lds_coarse_lu = (maxb + std::max(C.a0kl, 1) + 1 + band_window_doubles(C.a0kl, C.a0ku)) * 8;
+    // room for the solve's staged factor columns beyond the LU's window
+    h->lds_coarse_lu = std::max(h->lds_coarse_lu,
+                                std::min(h->lds_coarse_lu + solve_stage_bytes(C.a0kl, C.a0ku),
+                                         kLdsGrowCap));
     h->lds_coarse_q = maxnc * 8;
     if (lds_gdsw > 160 * 1024 || h->lds_coarse_lu > 160 * 1024 || h->lds_coarse_q > 160 * 1024)
         return fail(h, NLS_ELIMIT, "coarse working set exceeds LDS");

@@ -3099,9 +3099,12 @@ k_coarse_assemble(DevCoarse C, int with_matrix) {
 
 // One workgroup per diagonal block of A0 (independent problems give one
 // block each): (factor and) solve A0 d = rhs in place (band order).
+// A factorisation carries the right-hand side along (its forward
+// substitution), so only the backward substitution remains; the solves run
+// on the whole workgroup with the LU's window (free by then) as staging.
 template <int NPL>
 __global__ void __launch_bounds__(NLS_BLOCK)
-k_coarse_lu(DevCoarse C, int factor) {
+k_coarse_lu(DevCoarse C, int factor, int lds_bytes) {
     extern __shared__ double smem[];
     __shared__ int sflag[20];
     const int b = blockIdx.x;
@@ -3109,18 +3112,20 @@ k_coarse_lu(DevCoarse C, int factor) {
     double* x = smem;
     double* mult = x + n;
     double* W = mult + ((kl > 1 ? kl : 1) + 1);
+    const int stage_bytes = lds_bytes - (int)((W - smem) * sizeof(double));
     double* U = C.a0U + C.offU[b];
     double* L = C.a0L + C.offL[b];
     int* piv = C.a0piv + off;
-    if (factor) {
-        if (band_lu_auto<double>(n, kl, ku, C.a0ptr + off, C.a0col, C.a0val, W, mult, sflag, U, L,
-                                 piv, off)) {
-            if (threadIdx.x == 0) atomicOr(C.flag, 2);
-        }
-    }
     for (int k = threadIdx.x; k < n; k += blockDim.x) x[k] = C.rhs[off + k];
     __syncthreads();
-    if (threadIdx.x < 64) band_solve_wave<double, NPL>(n, kl, ku, U, L, piv, x);
+    if (factor) {
+        if (band_lu_auto<double>(n, kl, ku, C.a0ptr + off, C.a0col, C.a0val, W, mult, sflag, U, L,
+                                 piv, off, 0, x)) {
+            if (threadIdx.x == 0) atomicOr(C.flag, 2);
+        }
+        __syncthreads();
+    }
+    band_solve_group<double, NPL>(n, kl, ku, U, L, piv, x, W, stage_bytes, factor != 0);
     __syncthreads();
     for (int k = threadIdx.x; k < n; k += blockDim.x) C.rhs[off + k] = x[k];
 }
@@ -3582,7 +3587,7 @@ hipError_t launch_coarse_lu(const DevCoarse& C, int factor, int lds_bytes, int n
 #define NLS_CL(NPL)                                                                  \
     e = set_lds(k_coarse_lu<NPL>, lds_bytes);                                        \
     if (e != hipSuccess) return e;                                                   \
-    k_coarse_lu<NPL><<<C.nblk, NLS_BLOCK, lds_bytes, s>>>(C, factor);
+    k_coarse_lu<NPL><<<C.nblk, NLS_BLOCK, lds_bytes, s>>>(C, factor, lds_bytes);
     if (npl <= 1) { NLS_CL(1) } else if (npl == 2) { NLS_CL(2) } else { NLS_CL(4) }
 #undef NLS_CL
     return hipGetLastError();
