@@ -2961,6 +2961,86 @@ k_coarse_galerkin(DevMesh M, DevCoarse C, const double* __restrict__ w, int with
         }
         return;
     }
+    // rows accumulated in registers where the subdomain meets at most
+    // GAL_K coarse functions (the general loop below otherwise)
+    constexpr int GAL_K = 40;
+    if (nk <= GAL_K) {
+        for (int a = a0 + threadIdx.x; a < a1; a += blockDim.x) {
+            double acc[GAL_K];
+#pragma unroll
+            for (int l = 0; l < GAL_K; ++l) acc[l] = 0.0;
+            const int t0 = C.ctype[cb + a] == 2 ? 0 : C.cinc_ptr[cb + a];
+            const int t1 = C.ctype[cb + a] == 2 ? 0 : C.cinc_ptr[cb + a + 1];
+            for (int t = t0; t < t1; ++t) {
+                const int code = C.cinc[t];
+                const int e = eb + (code >> 2), pos = code & 3;
+                const int ge = C.ne_gid[e];
+                double uu[3];
+                int cn[3];
+                for (int c = 0; c < 3; ++c) {
+                    cn[c] = C.ne_conn[3 * e + c];
+                    uu[c] = w[C.cnode[cb + cn[c]]];
+                }
+                const double U = uu[0] + uu[1] + uu[2];
+                const double m = (U * U + uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2]) * (1.0 / 12.0);
+                double gr[3];
+                g_row(M.G6 + 6 * (size_t)ge, pos, gr[0], gr[1], gr[2]);
+                const double s = gr[0] * uu[0] + gr[1] * uu[1] + gr[2] * uu[2];
+                const double kap = M.kappa[ge];
+                const double coef = kap * (1.0 + M.beta * m);
+                const double rk = M.beta * kap * s * (1.0 / 6.0);
+                for (int c = 0; c < 3; ++c) {
+                    const double K = coef * gr[c] + rk * (U + uu[c]);
+                    const double* pr = ph + (int64_t)cn[c] * nk;
+#pragma unroll
+                    for (int l = 0; l < GAL_K; ++l)
+                        if (l < nk) acc[l] += K * pr[l];
+                }
+            }
+            double* zr = z + (int64_t)a * nk;
+#pragma unroll
+            for (int l = 0; l < GAL_K; ++l)
+                if (l < nk) zr[l] = acc[l];
+        }
+        if (with_y) {
+            double* y = C.ybuf + C.off_phi[i];
+            for (int c = a0 + threadIdx.x; c < a1; c += blockDim.x) {
+                double acc[GAL_K];
+#pragma unroll
+                for (int l = 0; l < GAL_K; ++l) acc[l] = 0.0;
+                for (int t = C.cinc_ptr[cb + c]; t < C.cinc_ptr[cb + c + 1]; ++t) {
+                    const int code = C.cinc[t];
+                    const int e = eb + (code >> 2), pc = code & 3;
+                    const int ge = C.ne_gid[e];
+                    double uu[3];
+                    int cn[3];
+                    for (int a = 0; a < 3; ++a) {
+                        cn[a] = C.ne_conn[3 * e + a];
+                        uu[a] = w[C.cnode[cb + cn[a]]];
+                    }
+                    const double U = uu[0] + uu[1] + uu[2];
+                    const double m = (U * U + uu[0] * uu[0] + uu[1] * uu[1] + uu[2] * uu[2]) * (1.0 / 12.0);
+                    const double kap = M.kappa[ge];
+                    const double coef = kap * (1.0 + M.beta * m);
+                    for (int a = 0; a < 3; ++a) {
+                        double gr[3];
+                        g_row(M.G6 + 6 * (size_t)ge, a, gr[0], gr[1], gr[2]);
+                        const double sa = gr[0] * uu[0] + gr[1] * uu[1] + gr[2] * uu[2];
+                        // K_T[a][pc]
+                        const double K = coef * gr[pc] + M.beta * kap * sa * (U + uu[pc]) * (1.0 / 6.0);
+                        const double* pr = ph + (int64_t)cn[a] * nk;
+#pragma unroll
+                        for (int l = 0; l < GAL_K; ++l)
+                            if (l < nk) acc[l] += K * pr[l];
+                    }
+                }
+#pragma unroll
+                for (int l = 0; l < GAL_K; ++l)
+                    if (l < nk) y[(int64_t)l * nc + c] = acc[l];
+            }
+        }
+        return;
+    }
     for (int a = a0 + threadIdx.x; a < a1; a += blockDim.x) {
         double* zr = z + (int64_t)a * nk;
         for (int l = 0; l < nk; ++l) zr[l] = 0.0;
