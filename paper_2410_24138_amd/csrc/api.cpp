@@ -550,7 +550,8 @@ extern "C" int nls_set_partition(nls_handle* h, int32_t n_sub, const int32_t* el
     RC(h->alloc(G_MAPS, &h->hbuf, h->m + 2));
     RC(h->alloc(G_MAPS, &h->hbuf2, h->m + 2));
     RC(h->alloc(G_MAPS, &h->hn2, 4));
-    RC(h->alloc(G_MAPS, &h->partial, (size_t)h->nb_dot * (h->m + 2)));
+    // nb x (m + 1) partial sums, nb norm partials, and a second nb x (m + 1)
+    RC(h->alloc(G_MAPS, &h->partial, (size_t)h->nb_dot * (2 * (h->m + 1) + 1)));
     RC(h->alloc(G_MAPS, &h->Fx, N));
     RC(h->alloc(G_MAPS, &h->du, N));
     RC(h->alloc(G_MAPS, &h->tmp, N));
@@ -1375,7 +1376,7 @@ static int arnoldi_step(nls_handle* h, int j, hipStream_t s) {
     // norm partial sums after the (m + 1) nb dot-product partials
     double* pnorm = h->partial + (int64_t)h->nb_dot * (h->m + 1);
     HIPCHK(launch_arnoldi_gs(h->V, ld, j + 1, h->wv, N, h->partial, pnorm, h->hbuf, h->hbuf2,
-                             gmres_dev(h), j, vn, h->nb_dot, s));
+                             gmres_dev(h), j, vn, h->nb_dot, s, pnorm + h->nb_dot));
     return NLS_OK;
 }
 

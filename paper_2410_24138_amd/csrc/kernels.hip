@@ -3326,17 +3326,41 @@ __device__ __forceinline__ void block_totals(const double* __restrict__ partial,
     __syncthreads();
 }
 
-// h = totals of partial (nb x m); w -= V h (one element per thread)
+// h = totals of partial; w -= V h on this block's chunk (the chunks of
+// k_mdot_partial with gridDim.x blocks), then the chunk's partial dot
+// products of the updated w with V into partial2: the update and the next
+// k_mdot_partial in one launch, with the same operations per element and
+// per partial sum as two separate launches
 __global__ void __launch_bounds__(NLS_BLOCK)
-k_maxpy_totals(const double* __restrict__ V, int64_t ld, int m, const double* __restrict__ partial,
-               int nb, double* __restrict__ hout, double* __restrict__ w, int n) {
+k_maxpy_mdot_totals(const double* __restrict__ V, int64_t ld, int m,
+                    const double* __restrict__ partial, int nb, double* __restrict__ hout,
+                    double* __restrict__ w, int n, double* __restrict__ partial2) {
     extern __shared__ double hs[];
     block_totals(partial, nb, m, hs, hout);
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n) return;
-    double acc = 0.0;
-    for (int j = 0; j < m; ++j) acc += hs[j] * V[(int64_t)j * ld + t];
-    w[t] -= acc;
+    const int chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int lo = blockIdx.x * chunk, hi = min(n, lo + chunk);
+    for (int t = lo + threadIdx.x; t < hi; t += blockDim.x) {
+        double acc = 0.0;
+        for (int j = 0; j < m; ++j) acc += hs[j] * V[(int64_t)j * ld + t];
+        w[t] -= acc;
+    }
+    __threadfence_block();
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int j = wv; j < m; j += nw) {
+        const double* vj = V + (int64_t)j * ld;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int t = lo + lane;
+        for (; t + 192 < hi; t += 256) {
+            a0 += vj[t] * w[t];
+            a1 += vj[t + 64] * w[t + 64];
+            a2 += vj[t + 128] * w[t + 128];
+            a3 += vj[t + 192] * w[t + 192];
+        }
+        for (; t < hi; t += 64) a0 += vj[t] * w[t];
+        const double sum = wave_sum((a0 + a1) + (a2 + a3));
+        if (lane == 0) partial2[(int64_t)blockIdx.x * m + j] = sum;
+    }
 }
 
 // h = totals of partial; w -= V h and partial sums of ||w||^2 into pnorm
@@ -3774,12 +3798,11 @@ hipError_t launch_maxpy(const double* V, int64_t ld, int m, const double* h, dou
 
 hipError_t launch_arnoldi_gs(const double* V, int64_t ld, int m, double* w, int n, double* partial,
                              double* pnorm, double* h1, double* h2, const GmresDev& G, int j,
-                             double* vnext, int nb, hipStream_t s) {
+                             double* vnext, int nb, hipStream_t s, double* partial2) {
     const int lds = m * (int)sizeof(double);
     k_mdot_partial<<<nb, NLS_BLOCK, 0, s>>>(V, ld, m, w, n, partial);
-    k_maxpy_totals<<<nblocks(n), NLS_BLOCK, lds, s>>>(V, ld, m, partial, nb, h1, w, n);
-    k_mdot_partial<<<nb, NLS_BLOCK, 0, s>>>(V, ld, m, w, n, partial);
-    k_maxpy_norm_totals<<<nb, NLS_BLOCK, lds, s>>>(V, ld, m, partial, nb, h2, w, n, pnorm);
+    k_maxpy_mdot_totals<<<nb, NLS_BLOCK, lds, s>>>(V, ld, m, partial, nb, h1, w, n, partial2);
+    k_maxpy_norm_totals<<<nb, NLS_BLOCK, lds, s>>>(V, ld, m, partial2, nb, h2, w, n, pnorm);
     k_scale_givens_totals<<<nblocks(n), NLS_BLOCK, 0, s>>>(w, vnext, n, pnorm, nb, G, j);
     return hipGetLastError();
 }

@@ -226,10 +226,11 @@ struct GmresDev {
 hipError_t prepare_coarse_lu(int lds_bytes, int npl);
 // Both classical Gram-Schmidt passes of Arnoldi column j (h1 = V^T w,
 // w -= V h1, h2 = V^T w, w -= V h2), ||w||^2 into G.hn2, rotation j and
-// vnext = w / ||w||, in five launches: each kernel that consumes a
+// vnext = w / ||w||, in four launches: each kernel that consumes a
 // reduction adds up its nb partial sums itself (same fixed order in every
-// block), so no final-sum launches are needed.  pnorm: nb doubles apart
-// from partial (nb x m).
+// block), so no final-sum launches are needed, and the first update of w
+// computes the second pass's partial sums for its own chunk.  pnorm: nb
+// doubles, partial and partial2: nb x m each, all disjoint.
 hipError_t launch_arnoldi_gs(const double* V, int64_t ld, int m, double* w, int n, double* partial,
                              double* pnorm, double* h1, double* h2, const GmresDev& G, int j,
-                             double* vnext, int nb, hipStream_t s);
+                             double* vnext, int nb, hipStream_t s, double* partial2);
