@@ -57,8 +57,8 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per dispatch measured with rocprofv3 FETCH_SIZE/WRITE_SIZE (two
 # passes, calibrated against a 256 MiB copy; profiles/hbm_traffic_*.md), valid
 # only for the kernel source they were taken with.
-MEASURED_TRAFFIC = {"kernels_sha1": "c34c4ab9ecb62eb9a202b4d9d49c41a61fba626c",
-                    "bytes": {"k_local_newton": 1726935778, "k_local_factor": 397330638, "k_tangent_blocks": 359830512, "k_tangent_mfma": 3170894673, "k_tangent_gemv": 280759503, "k_coarse_galerkin": 108151384, "k_coarse_galerkin_sum": 97708774, "k_coarse_lu": 1786430, "k_coarse_inverse": 12186811, "k_coarse_apply_inverse": 4093712, "k_mdot_partial": 25692619, "k_maxpy": 48708378, "k_prolong": 27325029, "k_coarse_ty": 20659157, "k_coarse_q": 80461750}}
+MEASURED_TRAFFIC = {"kernels_sha1": "6ad6a804e0f948a424d45248ff283d4bd51b5ac2",
+                    "bytes": {"k_local_newton": 1726521682, "k_local_factor": 397353958, "k_tangent_blocks": 359826500, "k_tangent_mfma": 3209288928, "k_tangent_gemv": 280776295, "k_coarse_galerkin": 84180956, "k_coarse_galerkin_sum": 96889209, "k_coarse_lu": 1514470, "k_coarse_inverse": 12186850, "k_coarse_apply_inverse": 4089640, "k_mdot_partial": 23556806, "k_maxpy_mdot_totals": 31400194, "k_prolong": 27324149, "k_coarse_ty": 20656108, "k_coarse_q": 80388331}}
 
 
 def unit_work(case, elem_bytes=8):
