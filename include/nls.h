@@ -147,8 +147,9 @@ typedef struct nls_options {
 /* options.flags: build the exact tangent's local blocks W_i = J_ii^{-1} B_i
    (eqs. 6, 7) by per-lane band sweeps, one right-hand side per lane, instead
    of the blocked solve on the matrix cores (the default where kl <= 48 and
-   kl + ku <= 112 in every subdomain).  Both apply the same factors; they
-   differ in rounding only. */
+   kl + ku <= 112 in every subdomain), and the explicit A0^{-1} by a band
+   solve step by step instead of the same blocked solve.  Both forms apply
+   the same factors; they differ in rounding only. */
 #define NLS_FLAG_TANGENT_SWEEP 64
 
 /* ---- statistics of the last solve ------------------------------------ */

@@ -722,6 +722,39 @@ extern "C" int nls_build_coarse(nls_handle* h, int kind, const double* u_lin) {
     h->coarse_lu_valid = false;
     h->coarse_inv_valid = false;
     if (h->coarse_inv) RC(h->alloc(G_COARSE, &d.a0inv, (size_t)C.offI.back()));
+    // A0^{-1} by the blocked solve on the matrix cores where every diagonal
+    // block's band allows it (kl <= 48, kl + ku <= 112)
+    d.inv_nblk = 0;
+    d.inv_nkk = 0;
+    if (h->coarse_inv && !(h->opt.flags & NLS_FLAG_TANGENT_SWEEP)) {
+        bool fits = true;
+        int nkk = 1;
+        for (size_t b = 0; b < C.bkl.size(); ++b) {
+            fits = fits && C.bkl[b] <= 48 && C.bkl[b] + C.bku[b] <= 112;
+            nkk = std::max(nkk, (C.bkl[b] + C.bku[b] + 3) / 4);
+        }
+        if (fits) {
+            std::vector<int> off(1, 0);
+            std::vector<int64_t> offY(1, 0);
+            for (size_t b = 0; b + 1 < C.boff.size(); ++b) {
+                const int nbk = (C.boff[b + 1] - C.boff[b] + 15) / 16;
+                off.push_back(off.back() + nbk);
+                offY.push_back(offY.back() + (int64_t)nbk * nbk * 256);
+            }
+            int* d_off;
+            int64_t* d_offY;
+            RC(h->upload(G_COARSE, &d_off, off));
+            RC(h->upload(G_COARSE, &d_offY, offY));
+            d.inv_off = d_off;
+            d.inv_offY = d_offY;
+            RC(h->alloc(G_COARSE, &d.inv_sig, (size_t)off.back() * 64));
+            RC(h->alloc(G_COARSE, &d.inv_G, (size_t)off.back() * 1024));
+            RC(h->alloc(G_COARSE, &d.inv_Ui, (size_t)off.back() * 256));
+            RC(h->alloc(G_COARSE, &d.inv_Y, (size_t)offY.back()));
+            d.inv_nblk = off.back();
+            d.inv_nkk = nkk;
+        }
+    }
     HIPCHK(hipMemsetAsync(d.flag, 0, sizeof(int), h->stream));
     h->dc = d;
     // the linearisation point of the extension (C9: u = 0 unless given)

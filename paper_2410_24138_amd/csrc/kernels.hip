@@ -1923,22 +1923,24 @@ constexpr int TB_G = TB_RT * 4 * 64;  // doubles of G_b per block
 constexpr int TB_U = 4 * 64;          // doubles of U11^{-1} per block
 constexpr int TB_RING = 128;          // window rows in LDS (>= 16 + kl + ku)
 
-__global__ void __launch_bounds__(64) k_tangent_blocks(DevMaps P, DevLocal L, DevTangent Tg) {
+// sigma_b, G_b and U11^{-1} of the 16-row block at row k0 of one band
+// problem (n rows, band factors Lf, Uf and pivots piv of band_lu, local
+// indices), by one wavefront; stored at sg (64 ints), G (TB_G doubles) and
+// Ui (TB_U doubles) in the operand order of the matrix-core steps.
+__device__ __forceinline__ void tb_block_pieces(int n, int kl, int ku, const double* __restrict__ Lf,
+                                                const double* __restrict__ Uf,
+                                                const int* __restrict__ piv, int k0,
+                                                int* __restrict__ sg, double* __restrict__ G,
+                                                double* __restrict__ Ui) {
     __shared__ double Lb[64 * 17];
     __shared__ double Ub[16 * 17];
-    const int gb = blockIdx.x;
-    const int i = Tg.blk_sub[gb];
-    const int k0 = (gb - Tg.off_blk[i]) * 16;
-    const int rowbase = P.off_n[i], n = P.off_n[i + 1] - rowbase;
-    const int kl = P.kl[i], kw = kl + P.ku[i];
+    const int kw = kl + ku;
     const int ldu = kw + 1, ldl = kl > 1 ? kl : 1;
-    const double* __restrict__ Lf = L.Lf + P.off_l[i];
-    const double* __restrict__ Uf = L.Uf + P.off_u[i];
     const int lane = threadIdx.x;
     const int ns = min(16, n - k0);  // steps of this block; past n the identity
     // every load first: lane s < ns holds the pivot offset of step s, lane q
     // the multipliers of each step s for window position q
-    const int pv = lane < ns ? L.piv[rowbase + k0 + lane] - k0 : lane;
+    const int pv = lane < ns ? piv[k0 + lane] - k0 : lane;
     double lv[16];
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
@@ -1969,7 +1971,7 @@ __global__ void __launch_bounds__(64) k_tangent_blocks(DevMaps P, DevLocal L, De
             if (lane == s) ident = vc;
             if (lane == d) ident = va;
         }
-    Tg.tsig[(size_t)gb * 64 + lane] = ident;
+    sg[lane] = ident;
     // L_b: step s's multiplier for the row at position q after that step's
     // interchange belongs to the row's position after the whole block, m_s(q);
     // m runs backward from the identity (after the last step).  Lanes without
@@ -1999,7 +2001,6 @@ __global__ void __launch_bounds__(64) k_tangent_blocks(DevMaps P, DevLocal L, De
     for (int s = 0; s < 15; ++s)
 #pragma unroll
         for (int p = s + 1; p < 16; ++p) x[p] = fma(-Lb[p * 17 + s], x[s], x[p]);
-    double* __restrict__ G = Tg.tG + (size_t)gb * TB_G;
 #pragma unroll
     for (int p = 0; p < 16; ++p)
         if ((p & 3) == g) G[kk * 64 + p + lc] = x[p];
@@ -2022,67 +2023,56 @@ __global__ void __launch_bounds__(64) k_tangent_blocks(DevMaps P, DevLocal L, De
 #pragma unroll
         for (int r = 0; r < jj; ++r) y[r] = fma(-Ub[r * 17 + jj], y[jj], y[r]);
     }
-    double* __restrict__ Ui = Tg.tUi + (size_t)gb * TB_U;
 #pragma unroll
     for (int r = 0; r < 16; ++r)
         if ((r & 3) == g) Ui[kk * 64 + r + lc] = y[r];
 }
 
-// One wavefront per (subdomain, 16 columns of B_i).  Forward: the window
-// rows [k0, k0 + R) sit in an LDS ring; rows entering it are filled from the
-// column's (row, value) list of B_i; each block gathers X' = P_b X from the
-// ring by sigma_b, forms [0; X'_2] + G_b X'_1 (up to four row tiles of 16),
-// writes rows k0 .. k0 + 15 (final) to the scratch Y and keeps the rest in
-// the ring.  Backward: the solved rows above the block's strip sit in the
-// ring; each block forms Y_1 - U12 X_2 (U12 read from the band factor, NKK
-// k-steps of 4 columns at most), then U11^{-1} times it (the FP64 result
-// layout, rows g + 4 q in lane (c, g), is already the operand layout of the
-// next product), and writes the owned rows to W.  The operands of the next
-// block are loaded while the current one computes.
-template <int NKK>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NKK <= 18 ? 3 : 2)))
-k_tangent_mfma(DevMaps P, DevLocal L, DevTangent Tg) {
-    typedef Mfma<double>::acc_t acc_t;
-    __shared__ double ring[TB_RING * 16];
-    constexpr int RM = TB_RING - 1;
-    const int i = P.order[blockIdx.x];
+__global__ void __launch_bounds__(64) k_tangent_blocks(DevMaps P, DevLocal L, DevTangent Tg) {
+    const int gb = blockIdx.x;
+    const int i = Tg.blk_sub[gb];
     const int rowbase = P.off_n[i], n = P.off_n[i + 1] - rowbase;
-    const int gbase = P.off_g[i], ng = P.off_g[i + 1] - gbase;
-    const int tile = blockIdx.y;
-    if (tile * 16 >= ng) return;  // uniform over the wavefront
-    const int kl = P.kl[i], kw = kl + P.ku[i], ldu = kw + 1, R = 16 + kl;
+    tb_block_pieces(n, P.kl[i], P.ku[i], L.Lf + P.off_l[i], L.Uf + P.off_u[i], L.piv + rowbase,
+                    (gb - Tg.off_blk[i]) * 16, Tg.tsig + (size_t)gb * 64,
+                    Tg.tG + (size_t)gb * TB_G, Tg.tUi + (size_t)gb * TB_U);
+}
+
+// Both sweeps of the blocked solve for the 16 columns of one wavefront, on
+// one band problem (n rows, band widths kl, ku, U by columns in Uf; sig, Gs,
+// Us its blocks' pieces; Y a scratch of ceil(n / 16) 16 x 16 tiles).
+// bval(r): entry r of this lane's right-hand-side column (zero past n).
+// oidx(r): the output index of row r (read one block ahead; r < n), ook(r):
+// whether row r is written, put(o, v): the write.  Forward: the window rows
+// [k0, k0 + R) sit in an LDS ring; rows entering it are filled by bval; each
+// block gathers X' = P_b X from the ring by sigma_b, forms [0; X'_2] +
+// G_b X'_1 (up to four row tiles of 16), writes rows k0 .. k0 + 15 (final)
+// to Y and keeps the rest in the ring.  Backward: the solved rows above the
+// block's strip sit in the ring; each block forms Y_1 - U12 X_2 (U12 read
+// from the band factor, NKK k-steps of 4 columns at most), then U11^{-1}
+// times it (the FP64 result layout, rows g + 4 q in lane (c, g), is already
+// the operand layout of the next product), and hands the rows to put.  The
+// operands of the next block are loaded once the current block's products
+// have been issued.
+template <int NKK, class BVal, class OIdx, class OOk, class Put>
+__device__ __forceinline__ void tb_sweeps(int n, int kl, int ku, const double* __restrict__ Uf,
+                                          const int* __restrict__ sig,
+                                          const double* __restrict__ Gs,
+                                          const double* __restrict__ Us, double* __restrict__ Y,
+                                          double* ring, BVal bval, OIdx oidx, OOk ook, Put put) {
+    typedef Mfma<double>::acc_t acc_t;
+    constexpr int RM = TB_RING - 1;
+    const int kw = kl + ku, ldu = kw + 1, R = 16 + kl;
     const int rtn = (R + 15) >> 4, nkk = (kw + 3) >> 2;
-    const int lane = threadIdx.x, c = lane & 15, h = lane >> 4;
-    const int col = tile * 16 + c;
-    const bool cv = col < ng;
-    const int nb = (n + 15) >> 4, b0 = Tg.off_blk[i];
-    int re[NLS_MAX_BCOL];
-    double ve[NLS_MAX_BCOL];
-    {
-        const int pb = cv ? Tg.bptr[gbase + col] : 0, pe = cv ? Tg.bptr[gbase + col + 1] : 0;
-#pragma unroll
-        for (int q = 0; q < NLS_MAX_BCOL; ++q) {
-            re[q] = (pb + q < pe) ? Tg.brow[pb + q] : -1;
-            ve[q] = (pb + q < pe) ? L.jval[Tg.bslot[pb + q]] : 0.0;
-        }
-    }
-    // rows [lo, lo + 16) of B_i's column into the ring (rows past n: zero)
+    const int lane = threadIdx.x & 63, c = lane & 15, h = lane >> 4;
+    const int nb = (n + 15) >> 4;
     auto fill16 = [&](int lo) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int r = lo + h + 4 * q;
-            double v = 0.0;
-#pragma unroll
-            for (int e = 0; e < NLS_MAX_BCOL; ++e) v = (re[e] == r) ? ve[e] : v;
-            ring[(r & RM) * 16 + c] = v;
+            ring[(r & RM) * 16 + c] = bval(r);
         }
     };
-    double* __restrict__ Y = Tg.fwd + Tg.off_F[i] + (size_t)tile * nb * 256;
-    const int* __restrict__ sig = Tg.tsig + (size_t)b0 * 64;
-    const double* __restrict__ Gs = Tg.tG + (size_t)b0 * TB_G;
     for (int lo = 0; lo < R; lo += 16) fill16(lo);
-    // operands of block b + 1 are loaded once block b's products have
-    // been issued (into the registers those products read)
     int sg = sig[lane];
     double ga[TB_RT * 4];
 #pragma unroll
@@ -2132,15 +2122,10 @@ k_tangent_mfma(DevMaps P, DevLocal L, DevTangent Tg) {
     __syncthreads();
     for (int e = lane; e < TB_RING * 16; e += 64) ring[e] = 0.0;
     __syncthreads();
-    const double* __restrict__ Uf = L.Uf + P.off_u[i];
-    const double* __restrict__ Us = Tg.tUi + (size_t)b0 * TB_U;
-    double* __restrict__ W = Tg.W + Tg.off_W[i];
-    const int* __restrict__ rowown = Tg.rowown + rowbase;
-    const int nown = Tg.off_own[i + 1] - Tg.off_own[i];
     // A[r][j] = -U[k0 + r][k0 + 16 + j] (r = c, j = 4 kk + h): column
     // k0 + 16 + j of the band factor, t = 16 + j - r above its diagonal
     // (NKK >= nkk k-steps; those past nkk have A = 0).  With them: Y_1,
-    // U11^{-1} and the owned-row index of each result row.  The loads take
+    // U11^{-1} and the output index of each result row.  The loads take
     // clamped in-range addresses and are masked where they are used; those
     // of block b - 1 are issued once block b's strip products have been.
     double ua[NKK], yn[4], un[4];
@@ -2156,7 +2141,7 @@ k_tangent_mfma(DevMaps P, DevLocal L, DevTangent Tg) {
         for (int q = 0; q < 4; ++q) {
             const int r = k0 + h + 4 * q;
             yn[q] = Y[(size_t)r * 16 + c];
-            on[q] = rowown[min(r, n - 1)];
+            on[q] = oidx(min(r, n - 1));
         }
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) un[kk] = Us[(size_t)b * TB_U + kk * 64 + lane];
@@ -2169,9 +2154,10 @@ k_tangent_mfma(DevMaps P, DevLocal L, DevTangent Tg) {
         acc_t acc0, acc1 = acc_t{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
+            const int r = k0 + h + 4 * q;
             acc0[q] = yn[q];
             uc[q] = un[q];
-            oc[q] = (cv && k0 + h + 4 * q < n) ? on[q] : -1;
+            oc[q] = (r < n && ook(r)) ? on[q] : -1;
         }
 #pragma unroll
         for (int kk = 0; kk < NKK; kk += 2) {
@@ -2195,9 +2181,83 @@ k_tangent_mfma(DevMaps P, DevLocal L, DevTangent Tg) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             ring[((k0 + h + 4 * q) & RM) * 16 + c] = xo[q];
-            if (oc[q] >= 0) W[(size_t)col * nown + oc[q]] = xo[q];
+            if (oc[q] >= 0) put(oc[q], xo[q]);
         }
     }
+}
+
+// W_i: one wavefront per (subdomain, 16 columns of B_i), the columns given
+// by their (row, value) lists; the owned rows of the result go to W.
+template <int NKK>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NKK <= 18 ? 3 : 2)))
+k_tangent_mfma(DevMaps P, DevLocal L, DevTangent Tg) {
+    __shared__ double ring[TB_RING * 16];
+    const int i = P.order[blockIdx.x];
+    const int rowbase = P.off_n[i], n = P.off_n[i + 1] - rowbase;
+    const int gbase = P.off_g[i], ng = P.off_g[i + 1] - gbase;
+    const int tile = blockIdx.y;
+    if (tile * 16 >= ng) return;  // uniform over the wavefront
+    const int c = threadIdx.x & 15;
+    const int col = tile * 16 + c;
+    const bool cv = col < ng;
+    const int nb = (n + 15) >> 4, b0 = Tg.off_blk[i];
+    int re[NLS_MAX_BCOL];
+    double ve[NLS_MAX_BCOL];
+    {
+        const int pb = cv ? Tg.bptr[gbase + col] : 0, pe = cv ? Tg.bptr[gbase + col + 1] : 0;
+#pragma unroll
+        for (int q = 0; q < NLS_MAX_BCOL; ++q) {
+            re[q] = (pb + q < pe) ? Tg.brow[pb + q] : -1;
+            ve[q] = (pb + q < pe) ? L.jval[Tg.bslot[pb + q]] : 0.0;
+        }
+    }
+    auto bval = [&](int r) {
+        double v = 0.0;
+#pragma unroll
+        for (int e = 0; e < NLS_MAX_BCOL; ++e) v = (re[e] == r) ? ve[e] : v;
+        return v;
+    };
+    const int* __restrict__ rowown = Tg.rowown + rowbase;
+    double* __restrict__ W = Tg.W + Tg.off_W[i];
+    const int nown = Tg.off_own[i + 1] - Tg.off_own[i];
+    tb_sweeps<NKK>(n, P.kl[i], P.ku[i], L.Uf + P.off_u[i], Tg.tsig + (size_t)b0 * 64,
+                   Tg.tG + (size_t)b0 * TB_G, Tg.tUi + (size_t)b0 * TB_U,
+                   Tg.fwd + Tg.off_F[i] + (size_t)tile * nb * 256, ring, bval,
+                   [&](int r) { return rowown[r]; }, [&](int) { return cv; },
+                   [&](int o, double v) { W[(size_t)col * nown + o] = v; });
+}
+
+
+// A0^{-1} by the same blocked solve: the pieces of every 16-row block of
+// the diagonal blocks of A0, then one wavefront per 16 identity columns,
+// the rows of the result into the row-major inverse.
+__global__ void __launch_bounds__(64) k_coarse_inv_blocks(DevCoarse C) {
+    const int gb = blockIdx.x;
+    int b = 0;
+    while (b + 1 < C.nblk && C.inv_off[b + 1] <= gb) ++b;
+    const int off = C.boff[b], n = C.boff[b + 1] - off;
+    tb_block_pieces(n, C.bkl[b], C.bku[b], C.a0L + C.offL[b], C.a0U + C.offU[b], C.a0piv + off,
+                    (gb - C.inv_off[b]) * 16, C.inv_sig + (size_t)gb * 64,
+                    C.inv_G + (size_t)gb * TB_G, C.inv_Ui + (size_t)gb * TB_U);
+}
+
+template <int NKK>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(NKK <= 18 ? 3 : 2)))
+k_coarse_inv_mfma(DevCoarse C) {
+    __shared__ double ring[TB_RING * 16];
+    const int b = blockIdx.x, tile = blockIdx.y;
+    const int off = C.boff[b], n = C.boff[b + 1] - off;
+    if (tile * 16 >= n) return;  // uniform over the wavefront
+    const int col = tile * 16 + (threadIdx.x & 15);
+    const bool cv = col < n;
+    const int nb = (n + 15) >> 4, b0 = C.inv_off[b];
+    double* __restrict__ Ainv = C.a0inv + C.offI[b];
+    tb_sweeps<NKK>(n, C.bkl[b], C.bku[b], C.a0U + C.offU[b], C.inv_sig + (size_t)b0 * 64,
+                   C.inv_G + (size_t)b0 * TB_G, C.inv_Ui + (size_t)b0 * TB_U,
+                   C.inv_Y + C.inv_offY[b] + (size_t)tile * nb * 256, ring,
+                   [&](int r) { return (cv && r == col) ? 1.0 : 0.0; }, [&](int r) { return r; },
+                   [&](int) { return cv; },
+                   [&](int o, double v) { Ainv[(size_t)o * n + col] = v; });
 }
 
 // z[owned rows of i] = W_i v_Gamma_i: streams W (column-major, one owned
@@ -3768,6 +3828,19 @@ hipError_t launch_tangent_gemv(const DevMaps& P, const DevTangent& Tg, const dou
 }
 
 hipError_t launch_coarse_inverse(const DevCoarse& C, int max_block, int max_ldu, hipStream_t s) {
+    if (C.inv_nblk > 0) {
+        k_coarse_inv_blocks<<<C.inv_nblk, 64, 0, s>>>(C);
+        const dim3 grid(C.nblk, (max_block + 15) / 16);
+        if (C.inv_nkk <= 12)
+            k_coarse_inv_mfma<12><<<grid, 64, 0, s>>>(C);
+        else if (C.inv_nkk <= 18)
+            k_coarse_inv_mfma<18><<<grid, 64, 0, s>>>(C);
+        else if (C.inv_nkk <= 24)
+            k_coarse_inv_mfma<24><<<grid, 64, 0, s>>>(C);
+        else
+            k_coarse_inv_mfma<28><<<grid, 64, 0, s>>>(C);
+        return hipGetLastError();
+    }
     if (max_ldu > INV_MAXW) return hipErrorInvalidValue;
     const dim3 nb((max_block + INV_CB - 1) / INV_CB, C.nblk);
     const int lds = coarse_inverse_lds_bytes(max_block, max_ldu);

@@ -117,6 +117,14 @@ struct DevCoarse {
     int* a0piv;
     double* rhs;                // n0, band order
     double* a0inv;              // n0 x n0 inverse of A0 (band order, row-major)
+    // A0^{-1} by the blocked solve on the matrix cores (inv_nblk > 0): the
+    // 16-row blocks of the diagonal blocks (inv_off[b]: the first of block
+    // b), their pieces, and the forward scratch (inv_offY[b] into inv_Y)
+    const int* inv_off;
+    const int64_t* inv_offY;
+    int inv_nblk, inv_nkk;
+    int* inv_sig;
+    double *inv_G, *inv_Ui, *inv_Y;
     double* c;                  // n0, coarse iterate (coarse id order)
     double* w;                  // N: u - Phi c
     double* scal;               // device scalars: [0] ||G||, [1] max|dc|, [2] max|c|
