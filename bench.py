@@ -57,8 +57,8 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per dispatch measured with rocprofv3 FETCH_SIZE/WRITE_SIZE (two
 # passes, calibrated against a 256 MiB copy; profiles/hbm_traffic_*.md), valid
 # only for the kernel source they were taken with.
-MEASURED_TRAFFIC = {"kernels_sha1": "6ad6a804e0f948a424d45248ff283d4bd51b5ac2",
-                    "bytes": {"k_local_newton": 1726521682, "k_local_factor": 397353958, "k_tangent_blocks": 359826500, "k_tangent_mfma": 3209288928, "k_tangent_gemv": 280776295, "k_coarse_galerkin": 84180956, "k_coarse_galerkin_sum": 96889209, "k_coarse_lu": 1514470, "k_coarse_inverse": 12186850, "k_coarse_apply_inverse": 4089640, "k_mdot_partial": 23556806, "k_maxpy_mdot_totals": 31400194, "k_prolong": 27324149, "k_coarse_ty": 20656108, "k_coarse_q": 80388331}}
+MEASURED_TRAFFIC = {"kernels_sha1": "8892c97675b19b76544a439f752dce2444bfa839",
+                    "bytes": {"k_local_newton": 1728210265, "k_local_factor": 397415490, "k_tangent_blocks": 359826586, "k_tangent_mfma": 3121291397, "k_tangent_gemv": 280760292, "k_coarse_galerkin": 84045018, "k_coarse_galerkin_sum": 96665211, "k_coarse_lu": 1519457, "k_coarse_inv_blocks": 1150761, "k_coarse_inv_mfma": 20875800, "k_coarse_apply_inverse": 4101905, "k_mdot_partial": 23552427, "k_maxpy_mdot_totals": 31341072, "k_prolong": 27326065, "k_coarse_ty": 20663199, "k_coarse_q": 80450638}}
 
 
 def unit_work(case, elem_bytes=8):
