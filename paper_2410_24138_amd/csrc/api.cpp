@@ -688,7 +688,7 @@ extern "C" int nls_build_coarse(nls_handle* h, int kind, const double* u_lin) {
     d.off_c = off_c; d.cnode = cnode; d.ctype = ctype; d.off_k = off_k; d.klist = klist;
     d.cfun = cfun; d.cval = cval; d.off_ne = off_ne; d.ne_conn = ne_conn; d.ne_gid = ne_gid;
     d.cinc_ptr = cinc_ptr; d.cinc = cinc; d.iidx = iidx; d.off_ni = off_ni; d.inode = inode;
-    d.iptr = iptr; d.icol = icol; d.ikl = ikl; d.iku = iku; d.perm = perm; d.a0ptr = a0ptr;
+    d.iptr = iptr; d.icol = icol; d.ikl = ikl; d.iku = iku; d.perm = perm; d.a0ptr = a0ptr; d.nnz0 = C.a0ptr.back();
     d.a0col = a0col; d.a0src_ptr = a0src_ptr; d.a0src = a0src; d.gsrc_ptr = gsrc_ptr;
     d.gsrc = gsrc; d.cpos = cpos; d.cown = cown; d.off_phi = off_phi; d.off_iu = off_iu;
     d.off_il = off_il; d.off_kk = off_kk;

@@ -3212,26 +3212,46 @@ k_coarse_ty(DevCoarse C, const double* __restrict__ v) {
     }
 }
 
+// sum over t in [t0, t1) of val[src[t]], in that order: the first 16
+// indices and values are loaded before any is added, so the loads overlap
+// instead of each waiting for the one before
+__device__ __forceinline__ double sum_pieces(const double* __restrict__ val,
+                                             const int* __restrict__ src, int t0, int t1) {
+    constexpr int GM = 16;
+    if (t1 <= t0) return 0.0;
+    int ix[GM];
+#pragma unroll
+    for (int q = 0; q < GM; ++q) ix[q] = src[min(t0 + q, t1 - 1)];
+    double v[GM];
+#pragma unroll
+    for (int q = 0; q < GM; ++q) v[q] = val[ix[q]];
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < GM; ++q)
+        if (t0 + q < t1) acc += v[q];
+    for (int t = t0 + GM; t < t1; ++t) acc += val[src[t]];
+    return acc;
+}
+
 // Deterministic assembly: rhs (band order) from the gblk pieces, and, if
 // with_matrix, the CSR values of A0 from the Galerkin blocks.  Also writes
 // ||rhs||_2 to scal[0] (single block).
+// Block 0 forms rhs and its norm; with_matrix, blocks 1.. form the CSR
+// values, one entry per thread.
 __global__ void __launch_bounds__(NLS_BLOCK)
 k_coarse_assemble(DevCoarse C, int with_matrix) {
     __shared__ double red[24];
+    if (blockIdx.x > 0) {
+        const int s = (blockIdx.x - 1) * blockDim.x + threadIdx.x;
+        if (with_matrix && s < C.a0ptr[C.n0])
+            C.a0val[s] = sum_pieces(C.ablk, C.a0src, C.a0src_ptr[s], C.a0src_ptr[s + 1]);
+        return;
+    }
     double ss = 0.0;
     for (int k = threadIdx.x; k < C.n0; k += blockDim.x) {
-        double acc = 0.0;
-        for (int t = C.gsrc_ptr[k]; t < C.gsrc_ptr[k + 1]; ++t) acc += C.gblk[C.gsrc[t]];
+        const double acc = sum_pieces(C.gblk, C.gsrc, C.gsrc_ptr[k], C.gsrc_ptr[k + 1]);
         C.rhs[C.perm[k]] = acc;
         ss += acc * acc;
-    }
-    if (with_matrix) {
-        const int nnz = C.a0ptr[C.n0];
-        for (int s = threadIdx.x; s < nnz; s += blockDim.x) {
-            double acc = 0.0;
-            for (int t = C.a0src_ptr[s]; t < C.a0src_ptr[s + 1]; ++t) acc += C.ablk[C.a0src[t]];
-            C.a0val[s] = acc;
-        }
     }
     ss = block_sum(ss, red);
     if (threadIdx.x == 0) C.scal[0] = sqrt(ss);
@@ -3475,9 +3495,7 @@ k_scale_givens_totals(const double* __restrict__ x, double* __restrict__ y, int 
 __global__ void k_coarse_gather(DevCoarse C) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= C.n0) return;
-    double acc = 0.0;
-    for (int t = C.gsrc_ptr[k]; t < C.gsrc_ptr[k + 1]; ++t) acc += C.gblk[C.gsrc[t]];
-    C.rhs[C.perm[k]] = acc;
+    C.rhs[C.perm[k]] = sum_pieces(C.gblk, C.gsrc, C.gsrc_ptr[k], C.gsrc_ptr[k + 1]);
 }
 
 __global__ void k_scale_by(const double* __restrict__ x, const double* __restrict__ dsq,
@@ -3742,7 +3760,8 @@ hipError_t launch_coarse_ty(const DevCoarse& C, const double* v, int lds_bytes, 
 hipError_t prepare_coarse_ty(int lds_bytes) { return set_lds(k_coarse_ty, lds_bytes); }
 
 hipError_t launch_coarse_assemble(const DevCoarse& C, int with_matrix, hipStream_t s) {
-    k_coarse_assemble<<<1, NLS_BLOCK, 0, s>>>(C, with_matrix);
+    const int nnz = with_matrix ? C.nnz0 : 0;
+    k_coarse_assemble<<<1 + (nnz + NLS_BLOCK - 1) / NLS_BLOCK, NLS_BLOCK, 0, s>>>(C, with_matrix);
     return hipGetLastError();
 }
 

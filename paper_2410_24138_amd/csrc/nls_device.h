@@ -98,6 +98,7 @@ struct DevCoarse {
     const int64_t *off_phi, *off_iu, *off_il, *off_kk;
     const int *perm, *a0ptr, *a0col, *a0src_ptr, *a0src, *gsrc_ptr, *gsrc, *cpos, *cown;
     int a0kl, a0ku;
+    int nnz0;                   // entries of A0's CSR pattern
     int nblk;                   // diagonal blocks of A0 (connected components)
     const int *boff, *bkl, *bku, *rblk;
     const int64_t *offU, *offL, *offI;
