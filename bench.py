@@ -57,8 +57,8 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per dispatch measured with rocprofv3 FETCH_SIZE/WRITE_SIZE (two
 # passes, calibrated against a 256 MiB copy; profiles/hbm_traffic_*.md), valid
 # only for the kernel source they were taken with.
-MEASURED_TRAFFIC = {"kernels_sha1": "8892c97675b19b76544a439f752dce2444bfa839",
-                    "bytes": {"k_local_newton": 1728210265, "k_local_factor": 397415490, "k_tangent_blocks": 359826586, "k_tangent_mfma": 3121291397, "k_tangent_gemv": 280760292, "k_coarse_galerkin": 84045018, "k_coarse_galerkin_sum": 96665211, "k_coarse_lu": 1519457, "k_coarse_inv_blocks": 1150761, "k_coarse_inv_mfma": 20875800, "k_coarse_apply_inverse": 4101905, "k_mdot_partial": 23552427, "k_maxpy_mdot_totals": 31341072, "k_prolong": 27326065, "k_coarse_ty": 20663199, "k_coarse_q": 80450638}}
+MEASURED_TRAFFIC = {"kernels_sha1": "1b8d4f8c1ba10a1092991d3e2d9452176e14f1b7",
+                    "bytes": {"k_local_newton": 1729753495, "k_local_factor": 397416786, "k_tangent_blocks": 359828439, "k_tangent_mfma": 3106679445, "k_tangent_gemv": 280765810, "k_coarse_galerkin": 84064600, "k_coarse_galerkin_sum": 97875451, "k_coarse_lu": 1517538, "k_coarse_inv_blocks": 1150762, "k_coarse_inv_mfma": 20875817, "k_coarse_apply_inverse": 4101910, "k_mdot_partial": 23556716, "k_maxpy_mdot_totals": 31341962, "k_prolong": 27326741, "k_coarse_ty": 20663292, "k_coarse_q": 80454912}}
 
 
 def unit_work(case, elem_bytes=8):
