@@ -92,6 +92,23 @@ def test_precond_residual_and_tangent(kw, coupling):
         _close(_np(s.tangent(v)), S.tangent(v), 1e-11)
 
 
+@pytest.mark.parametrize("coupling", ["one_level", "additive", "hybrid"])
+def test_tangent_with_subdomains_under_one_block(coupling):
+    """Subdomains of 9 rows (fewer than one 16-row block of the blocked
+    tangent solve, kl = ku = 4): F_x and the tangent against the oracle."""
+    kw = dict(n=6, boxes=3, overlap=1, forcing_seed=2)
+    case = synth.small_case(two_level=(coupling != "one_level"), **kw)
+    P = P1Problem(case)
+    S = Schwarz(P, coupling)
+    s = _solver(case, coupling=coupling)
+    u = _probe_point(P, case)
+    _close(_np(s.precond_residual(u)), S.evaluate(u), 1e-11)
+    rng = np.random.default_rng(4)
+    for _ in range(2):
+        v = rng.normal(size=P.N)
+        _close(_np(s.tangent(v)), S.tangent(v), 1e-11)
+
+
 @pytest.mark.parametrize("kw", [dict(n=16, boxes=4, overlap=1),
                                 dict(n=13, boxes=3, overlap=2, uneven=True, coef_seed=2),
                                 dict(n=24, boxes=3, overlap=2, forcing_seed=9)])
